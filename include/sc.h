@@ -1,0 +1,249 @@
+/*
+ * sc.h -- C ABI of the MI355X (gfx950) SuperCaustics rendering library.
+ *
+ * The library renders the outputs that the SuperCaustics paper defines for
+ * scenes with transparent objects (arXiv 2107.11008):
+ *   - a spectral image with refraction, dispersion, specular reflection and
+ *     caustics (Abstract; Sec. I; caustic softness, Fig. 4);
+ *   - depth, the distance from the camera to the surface seen in a pixel,
+ *     raw and normalised over a 10 m range (Sec. III-D-1);
+ *   - world- and camera-space surface normals (Sec. III-D-2);
+ *   - the object mask: the object each pixel sees first, and whether it is
+ *     transparent (Sec. III-D-3, pixel-perfect labels);
+ *   - a caustic map on a receiver plane (the photon side of the caustic
+ *     ground truth of Sec. III-D-6).
+ * The paper obtains these from a game engine's hardware ray tracing; here
+ * every step runs in hand-written HIP kernels: a BVH8 builder, a wavefront
+ * path tracer (ray generation, closest- and any-hit traversal, material
+ * sort and compaction, dielectric and diffuse shading), photon tracing with
+ * fixed-point atomics into the caustic map, the ground-truth writer and the
+ * film resolve.
+ *
+ * Conventions
+ *   - Every call returns sc_status: 0 on success, a negative SC_E* code on
+ *     failure; sc_last_error() returns a thread-local message for the last
+ *     failure.  No C++ exception crosses this boundary.
+ *   - Buffers named "device" are device pointers owned by the caller; they
+ *     must stay valid until the stream has passed the call (and, for the
+ *     scene arrays, for the lifetime of the sc_bvh built from them).
+ *     Arrays named "host" are read during the call only.
+ *   - All kernels run on the context's stream.  Calls return after
+ *     enqueueing, except sc_build_bvh (sizes its allocations), calls that
+ *     fill host statistics, and sc_sync/sc_get_counters.  Argument errors
+ *     are reported synchronously; device faults surface at sc_sync.
+ *   - Units are metres, the world is right-handed with +z up.  Object id 0
+ *     means "no hit"; every triangle belongs to an object id >= 1.
+ *   - Floating point: IEEE binary32, no contraction, correctly rounded
+ *     division and square root.  Given the same inputs and seeds the
+ *     traced paths are bit-identical to the CPU oracle of the repository.
+ */
+#ifndef SC_H
+#define SC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SC_ABI_VERSION 1u
+
+typedef int32_t sc_status;
+#define SC_OK 0
+#define SC_EINVAL (-1)        /* invalid argument (null, size, range) */
+#define SC_ENOMEM (-2)        /* device allocation failed */
+#define SC_EDEVICE (-3)       /* HIP runtime error */
+#define SC_EUNSUPPORTED (-4)  /* valid but unsupported request */
+
+typedef struct sc_ctx sc_ctx;
+typedef struct sc_bvh sc_bvh;
+
+/* Materials: one per object id.  DIFFUSE is Lambertian (two-sided);
+ * DIELECTRIC is smooth glass in air with n(lambda) = cauchy_a +
+ * cauchy_b / lambda_um^2 (dispersion, Abstract); EMISSIVE emits radiance
+ * `le` from its front face (counter-clockwise winding). */
+#define SC_MAT_DIFFUSE 0u
+#define SC_MAT_DIELECTRIC 1u
+#define SC_MAT_EMISSIVE 2u
+#define SC_ALBEDO_CONST 0u    /* rho_a */
+#define SC_ALBEDO_CHECKER 1u  /* 1 m squares on x,y: rho_a where floor(x)+floor(y) is even, else rho_b */
+#define SC_ALBEDO_TEXTURE 2u  /* the scene texture, nearest texel over its rectangle */
+
+typedef struct {
+    uint32_t type, albedo_mode;
+    float rho_a, rho_b;
+    float cauchy_a, cauchy_b;
+    float le;
+    float pad;
+} sc_material; /* 32 bytes */
+
+typedef struct {
+    const float* V;          /* device [nv][3] vertex positions */
+    const uint32_t* I;       /* device [nt][3] vertex indices */
+    const float* VN;         /* device [nv][3] unit vertex normals, or NULL for flat shading */
+    const uint32_t* tri_obj; /* device [nt] object id of each triangle, 1..n_mat-1 */
+    uint32_t nv, nt;
+    const sc_material* mat;  /* host [n_mat]; index = object id, row 0 unused */
+    uint32_t n_mat;
+    const float* point_lights; /* host [n_pl][4]: x, y, z, intensity (W/sr, flat spectrum) */
+    uint32_t n_pl;
+    const uint32_t* targets_obj; /* host [n_tg] object ids that photons are aimed at */
+    const float* targets_sphere; /* host [n_tg][4]: bounding sphere cx, cy, cz, r */
+    uint32_t n_tg;
+    const float* tex;          /* device [tex_h][tex_w] grey albedo, or NULL */
+    uint32_t tex_w, tex_h;
+    float tex_x0, tex_y0, tex_ext_u, tex_ext_v; /* texture rectangle on x,y */
+    uint32_t recv_obj;         /* receiver object of the caustic map, 0 = none */
+    uint32_t recv_wc, recv_hc; /* caustic-map cells along x and y */
+    float recv_x0, recv_y0, recv_ext_u, recv_ext_v; /* receiver rectangle on x,y */
+} sc_scene;
+
+typedef struct {
+    uint32_t width;     /* 4 or 8 (children per node); 0 = 8 */
+    uint32_t leaf_max;  /* triangles per leaf, 1..8; 0 = 4 */
+} sc_bvh_opts;
+
+typedef struct {
+    uint32_t width, leaf_max;
+    uint32_t n_nodes, depth;   /* wide nodes and levels below the root */
+    uint64_t node_bytes, tri_bytes;
+    uint32_t max_stack;        /* traversal stack entries a ray can need */
+} sc_bvh_info;
+
+/* Pinhole camera: the ray through film point (sx, sy) in [-1,1]^2 (row 0
+ * at the top) has direction fwd + sx*right + sy*up, normalised; right and
+ * up already carry tan(vfov/2) and the aspect ratio. */
+typedef struct {
+    float eye[3], fwd[3], right[3], up[3];
+    uint32_t w, h;
+} sc_camera;
+
+/* Wavelength sampling.  FIXED: k = 1 or 3 slots with wavelengths nm[]
+ * (channel order R, G, B when k = 3); every (pixel, sample) traces k paths;
+ * the caustic map has k channels.  UNIFORM: one path per (pixel, sample)
+ * with lambda uniform in [lo, hi]; Gaussian sensor curves (40 nm wide at
+ * 650/550/450 nm, mean 1 over [lo, hi]) map it to RGB; the caustic map
+ * has `bins` spectral bins. */
+#define SC_WL_FIXED 0u
+#define SC_WL_UNIFORM 1u
+typedef struct {
+    uint32_t mode, k;
+    float nm[4];
+    float lo, hi;
+    uint32_t bins;
+} sc_wavelengths;
+
+/* Outputs of sc_render, each a device array or NULL (not written):
+ *   rgb        [h][w][3] f32  linear radiance, mean over samples
+ *   obj        [h][w]    u32  object id of the first surface (0 = miss)
+ *   trans      [h][w]    u8   1 if that object is DIELECTRIC
+ *   tri        [h][w]    u32  triangle index (0xffffffff = miss)
+ *   depth      [h][w]    f32  distance along the unit ray (+inf = miss)
+ *   depthn     [h][w]    f32  min(depth / 10 m, 1)
+ *   normal     [h][w][3] f32  world-space shading normal facing the camera
+ *   normal_cam [h][w][3] f32  the same in camera space (x right, y up, z back)
+ *   albedo     [h][w]    f32  diffuse albedo (glass 1, emitter 0, miss 0)
+ * The last seven come from the ray through the pixel centre. */
+typedef struct {
+    float* rgb;
+    uint32_t* obj;
+    uint8_t* trans;
+    uint32_t* tri;
+    float* depth;
+    float* depthn;
+    float* normal;
+    float* normal_cam;
+    float* albedo;
+} sc_aov;
+
+/* Photon outcome statistics (host struct filled by sc_trace_photons when
+ * requested; the call then synchronises). */
+#define SC_PH_DEPOSITED 0
+#define SC_PH_OUTSIDE 1
+#define SC_PH_DIRECT 2
+#define SC_PH_ELSEWHERE 3
+#define SC_PH_ESCAPED 4
+#define SC_PH_ABSORBED 5
+#define SC_PH_TRUNCATED 6
+#define SC_PH_LOST 7
+#define SC_PH_EMIT_DEAD 8
+typedef struct {
+    double flux[9];
+    uint64_t count[9];
+    uint64_t segments;
+} sc_photon_stats;
+
+/* Cumulative counters of a context (sc_get_counters synchronises). */
+typedef struct {
+    uint64_t rays_closest;    /* closest-hit queries (camera, ground truth, photons) */
+    uint64_t rays_shadow;     /* any-hit queries */
+    uint64_t node_visits;     /* wide nodes fetched by closest-hit traversal (visit counting on) */
+    uint64_t tri_tests;       /* triangles tested by closest-hit traversal (visit counting on) */
+    uint64_t closest_launches;/* closest-hit kernel launches timed (profiling on) */
+    double closest_ms;        /* their summed duration from HIP events (profiling on) */
+    uint64_t closest_rays_timed; /* rays processed by the timed launches */
+} sc_counters;
+
+#define SC_OPT_COUNT_VISITS 1 /* 0/1: closest-hit traversal counts node and triangle visits */
+#define SC_OPT_PROFILE 2      /* 0/1: time every closest-hit launch with HIP events */
+#define SC_OPT_QUEUE_CAP 3    /* paths per wavefront chunk (default 1<<23) */
+
+uint32_t sc_abi_version(void);
+const char* sc_last_error(void);
+
+/* Context on HIP device `device` using stream `hip_stream` (a hipStream_t,
+ * NULL = the null stream).  The context owns its work buffers. */
+sc_status sc_create(int device, void* hip_stream, sc_ctx** out);
+sc_status sc_destroy(sc_ctx* ctx);
+sc_status sc_set_stream(sc_ctx* ctx, void* hip_stream);
+sc_status sc_set_option(sc_ctx* ctx, int32_t option, int64_t value);
+sc_status sc_sync(sc_ctx* ctx);
+sc_status sc_get_counters(sc_ctx* ctx, sc_counters* out);
+sc_status sc_reset_counters(sc_ctx* ctx);
+
+/* Build the wide BVH of a scene on the GPU (Morton codes, bitonic sort,
+ * radix-tree hierarchy, bottom-up bounds, greedy collapse to `width`
+ * children) and prepare its light and material tables.  The handle
+ * references the scene's device arrays.  Synchronises.  EINVAL on null
+ * pointers, nt == 0, an object id outside [1, n_mat) or an unknown
+ * material; EUNSUPPORTED if the tree is too deep for the traversal stack. */
+sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* scene, const sc_bvh_opts* opts, sc_bvh** out);
+sc_status sc_bvh_get_info(const sc_bvh* bvh, sc_bvh_info* out);
+sc_status sc_bvh_free(sc_bvh* bvh);
+
+/* Closest hit of n rays (device O, D: [n][3], D unit length): the
+ * lexicographic minimum of (t, triangle index) over all triangles with
+ * t > 0 under the watertight test of Woop et al. (JCGT 2013).  Outputs
+ * device t, prim (0xffffffff and +inf on a miss), barycentrics u, v of
+ * vertices 1 and 2 (u, v may be NULL). */
+sc_status sc_trace_rays(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D,
+                        float* t, uint32_t* prim, float* u, float* v);
+/* Any hit with 0 < t < tmax[i], ignoring triangle excl[i] (excl may be
+ * NULL); occluded[i] = 0/1.  All device arrays. */
+sc_status sc_occluded(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D,
+                      const float* tmax, const uint32_t* excl, uint8_t* occluded);
+
+/* Photon pass (the caustic side of the ground truth, Sec. III-D-6):
+ * n_photons photons from the lights aimed at the photon target spheres,
+ * carried through dielectrics (Cauchy IOR, Fresnel, total internal
+ * reflection) and stored on the receiver at the first diffuse hit after at
+ * least one dielectric event.  caustic_map: device f32 [recv_hc][recv_wc][C]
+ * (C = k for FIXED, bins for UNIFORM) holding flux per cell; overwritten.
+ * count_map: device u32 of the same shape with deposits per cell, or NULL.
+ * stats: host, or NULL (non-NULL synchronises).  EINVAL if the scene has
+ * no receiver, max_depth == 0 or the wavelength setting is invalid. */
+sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, uint32_t max_depth,
+                           const sc_wavelengths* wl, uint64_t seed, float* caustic_map, uint32_t* count_map,
+                           sc_photon_stats* stats);
+
+/* Render spp samples per pixel with at most max_depth surface hits per
+ * path.  caustic_map: device map from sc_trace_photons with the same
+ * wavelength setting, or NULL (caustic gather off).  EINVAL on spp == 0,
+ * max_depth == 0, w*h == 0, an invalid wavelength setting or a NULL out. */
+sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
+                    const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, const sc_aov* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

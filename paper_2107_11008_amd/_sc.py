@@ -1,0 +1,310 @@
+"""ctypes binding of libsc.so (include/sc.h).
+
+Argument marshalling only: every step of the rendering path runs in the
+library's HIP kernels.  Device memory comes from PyTorch tensors on the
+current ROCm device and kernels run on PyTorch's current stream.  If the
+library is missing this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsc.so")
+_lib = None
+
+SC_OPT_COUNT_VISITS = 1
+SC_OPT_PROFILE = 2
+SC_OPT_QUEUE_CAP = 3
+
+
+class ScError(RuntimeError):
+    pass
+
+
+class Material(C.Structure):
+    _fields_ = [("type", C.c_uint32), ("albedo_mode", C.c_uint32), ("rho_a", C.c_float), ("rho_b", C.c_float),
+                ("cauchy_a", C.c_float), ("cauchy_b", C.c_float), ("le", C.c_float), ("pad", C.c_float)]
+
+
+class Scene(C.Structure):
+    _fields_ = [("V", C.c_void_p), ("I", C.c_void_p), ("VN", C.c_void_p), ("tri_obj", C.c_void_p),
+                ("nv", C.c_uint32), ("nt", C.c_uint32),
+                ("mat", C.c_void_p), ("n_mat", C.c_uint32),
+                ("point_lights", C.c_void_p), ("n_pl", C.c_uint32),
+                ("targets_obj", C.c_void_p), ("targets_sphere", C.c_void_p), ("n_tg", C.c_uint32),
+                ("tex", C.c_void_p), ("tex_w", C.c_uint32), ("tex_h", C.c_uint32),
+                ("tex_x0", C.c_float), ("tex_y0", C.c_float), ("tex_ext_u", C.c_float), ("tex_ext_v", C.c_float),
+                ("recv_obj", C.c_uint32), ("recv_wc", C.c_uint32), ("recv_hc", C.c_uint32),
+                ("recv_x0", C.c_float), ("recv_y0", C.c_float), ("recv_ext_u", C.c_float), ("recv_ext_v", C.c_float)]
+
+
+class BvhOpts(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("leaf_max", C.c_uint32)]
+
+
+class BvhInfo(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("leaf_max", C.c_uint32), ("n_nodes", C.c_uint32), ("depth", C.c_uint32),
+                ("node_bytes", C.c_uint64), ("tri_bytes", C.c_uint64), ("max_stack", C.c_uint32)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("fwd", C.c_float * 3), ("right", C.c_float * 3), ("up", C.c_float * 3),
+                ("w", C.c_uint32), ("h", C.c_uint32)]
+
+
+class Wavelengths(C.Structure):
+    _fields_ = [("mode", C.c_uint32), ("k", C.c_uint32), ("nm", C.c_float * 4), ("lo", C.c_float),
+                ("hi", C.c_float), ("bins", C.c_uint32)]
+
+
+class Aov(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("obj", C.c_void_p), ("trans", C.c_void_p), ("tri", C.c_void_p),
+                ("depth", C.c_void_p), ("depthn", C.c_void_p), ("normal", C.c_void_p),
+                ("normal_cam", C.c_void_p), ("albedo", C.c_void_p)]
+
+
+class PhotonStats(C.Structure):
+    _fields_ = [("flux", C.c_double * 9), ("count", C.c_uint64 * 9), ("segments", C.c_uint64)]
+
+
+class Counters(C.Structure):
+    _fields_ = [("rays_closest", C.c_uint64), ("rays_shadow", C.c_uint64), ("node_visits", C.c_uint64),
+                ("tri_tests", C.c_uint64), ("closest_launches", C.c_uint64), ("closest_ms", C.c_double),
+                ("closest_rays_timed", C.c_uint64)]
+
+
+PH_OUTCOMES = ("deposited", "outside", "direct", "elsewhere", "escaped", "absorbed", "truncated", "lost",
+               "emit_dead")
+
+EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set_stream", "sc_set_option",
+           "sc_sync", "sc_get_counters", "sc_reset_counters", "sc_build_bvh", "sc_bvh_get_info", "sc_bvh_free",
+           "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render"]
+
+
+def load(path: str = LIB_PATH):
+    """Load libsc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ScError(f"{path} is missing: build it with paper_2107_11008_amd/build.py (no CPU fallback exists)")
+    L = C.CDLL(path)
+    vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32
+    L.sc_abi_version.restype = u32
+    L.sc_last_error.restype = C.c_char_p
+    L.sc_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+    L.sc_destroy.argtypes = [vp]
+    L.sc_set_stream.argtypes = [vp, vp]
+    L.sc_set_option.argtypes = [vp, i32, C.c_int64]
+    L.sc_sync.argtypes = [vp]
+    L.sc_get_counters.argtypes = [vp, C.POINTER(Counters)]
+    L.sc_reset_counters.argtypes = [vp]
+    L.sc_build_bvh.argtypes = [vp, C.POINTER(Scene), C.POINTER(BvhOpts), C.POINTER(vp)]
+    L.sc_bvh_get_info.argtypes = [vp, C.POINTER(BvhInfo)]
+    L.sc_bvh_free.argtypes = [vp]
+    L.sc_trace_rays.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp]
+    L.sc_occluded.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
+    L.sc_trace_photons.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, vp, vp, C.POINTER(PhotonStats)]
+    L.sc_render.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, C.POINTER(Aov)]
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if name not in ("sc_abi_version", "sc_last_error"):
+            fn.restype = i32
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = load().sc_last_error().decode(errors="replace")
+        raise ScError(f"{what} failed ({rc}): {msg}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA (ROCm) tensors"
+    return t.data_ptr()
+
+
+def _dev(a: np.ndarray, device) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def camera_struct(cam) -> Camera:
+    c = Camera()
+    c.eye[:] = [float(x) for x in cam.eye]
+    c.fwd[:] = [float(x) for x in cam.fwd]
+    c.right[:] = [float(x) for x in cam.right]
+    c.up[:] = [float(x) for x in cam.up]
+    c.w, c.h = int(cam.w), int(cam.h)
+    return c
+
+
+def wavelengths_struct(wl) -> Wavelengths:
+    w = Wavelengths()
+    w.mode, w.k = int(wl.mode), int(wl.k)
+    nm = list(wl.nm) + [0.0] * (4 - len(wl.nm))
+    w.nm[:] = [float(x) for x in nm[:4]]
+    w.lo, w.hi, w.bins = float(wl.lo), float(wl.hi), int(wl.bins)
+    return w
+
+
+class Context:
+    """A library context bound to a device and PyTorch's current stream."""
+
+    def __init__(self, device: int = 0):
+        L = load()
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = C.c_void_p()
+        _check(L.sc_create(device, C.c_void_p(stream), C.byref(h)), "sc_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().sc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, opt: int, value: int):
+        _check(load().sc_set_option(self.h, opt, int(value)), "sc_set_option")
+
+    def sync(self):
+        _check(load().sc_sync(self.h), "sc_sync")
+
+    def counters(self) -> dict:
+        c = Counters()
+        _check(load().sc_get_counters(self.h, C.byref(c)), "sc_get_counters")
+        return {k: getattr(c, k) for k, _ in Counters._fields_}
+
+    def reset_counters(self):
+        _check(load().sc_reset_counters(self.h), "sc_reset_counters")
+
+    # ------------------------------------------------------------ entry points
+    def build_bvh(self, scene, width: int = 8, leaf_max: int = 4) -> "Bvh":
+        return Bvh(self, scene, width, leaf_max)
+
+    def trace_rays(self, bvh: "Bvh", O: torch.Tensor, D: torch.Tensor):
+        n = O.shape[0]
+        t = torch.empty(n, dtype=torch.float32, device=self.device)
+        prim = torch.empty(n, dtype=torch.int32, device=self.device)
+        u = torch.empty(n, dtype=torch.float32, device=self.device)
+        v = torch.empty(n, dtype=torch.float32, device=self.device)
+        _check(load().sc_trace_rays(self.h, bvh.h, n, _ptr(O), _ptr(D), _ptr(t), _ptr(prim), _ptr(u), _ptr(v)),
+               "sc_trace_rays")
+        return t, prim, u, v
+
+    def occluded(self, bvh: "Bvh", O, D, tmax, excl=None):
+        n = O.shape[0]
+        occ = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(load().sc_occluded(self.h, bvh.h, n, _ptr(O), _ptr(D), _ptr(tmax), _ptr(excl), _ptr(occ)),
+               "sc_occluded")
+        return occ
+
+    def trace_photons(self, bvh: "Bvh", n_photons: int, max_depth: int, wl, seed: int, counts: bool = False,
+                      stats: bool = False, out: Optional[torch.Tensor] = None):
+        r = bvh.scene.receiver
+        shape = (r.hc, r.wc, wl.channels)
+        cmap = out if out is not None else torch.empty(shape, dtype=torch.float32, device=self.device)
+        cnt = torch.empty(shape, dtype=torch.int32, device=self.device) if counts else None
+        st = PhotonStats() if stats else None
+        w = wavelengths_struct(wl)
+        _check(load().sc_trace_photons(self.h, bvh.h, int(n_photons), int(max_depth), C.byref(w), int(seed),
+                                       _ptr(cmap), _ptr(cnt), C.byref(st) if st is not None else None),
+               "sc_trace_photons")
+        res = {"map": cmap}
+        if counts:
+            res["count"] = cnt
+        if stats:
+            res["stats"] = {k: (st.flux[i], st.count[i]) for i, k in enumerate(PH_OUTCOMES)}
+            res["stats"]["segments"] = st.segments
+        return res
+
+    def render(self, bvh: "Bvh", cam, spp: int, max_depth: int, wl, seed: int,
+               caustic_map: Optional[torch.Tensor] = None, outputs=("rgb", "obj", "trans", "tri", "depth", "depthn",
+                                                                      "normal", "normal_cam", "albedo"),
+               out: Optional[dict] = None):
+        H, W = cam.h, cam.w
+        shapes = dict(rgb=((H, W, 3), torch.float32), obj=((H, W), torch.int32), trans=((H, W), torch.uint8),
+                      tri=((H, W), torch.int32), depth=((H, W), torch.float32), depthn=((H, W), torch.float32),
+                      normal=((H, W, 3), torch.float32), normal_cam=((H, W, 3), torch.float32),
+                      albedo=((H, W), torch.float32))
+        res = {} if out is None else dict(out)
+        a = Aov()
+        for k in outputs:
+            if k not in res:
+                shp, dt = shapes[k]
+                res[k] = torch.empty(shp, dtype=dt, device=self.device)
+            setattr(a, k, _ptr(res[k]))
+        cs = camera_struct(cam)
+        w = wavelengths_struct(wl)
+        _check(load().sc_render(self.h, bvh.h, C.byref(cs), int(spp), int(max_depth), C.byref(w), int(seed),
+                                _ptr(caustic_map), C.byref(a)), "sc_render")
+        return res
+
+
+class Bvh:
+    """Scene uploaded to the device plus its wide BVH and tables."""
+
+    def __init__(self, ctx: Context, scene, width: int = 8, leaf_max: int = 4):
+        self.ctx = ctx
+        self.scene = scene
+        dev = ctx.device
+        self.V = _dev(scene.V, dev)
+        self.I = _dev(scene.I.view(np.int32), dev)
+        self.VN = _dev(scene.VN, dev) if scene.VN is not None else None
+        self.tri_obj = _dev(scene.tri_obj.view(np.int32), dev)
+        self.tex = _dev(scene.tex, dev) if scene.tex is not None else None
+        self._mat = np.ascontiguousarray(scene.materials)
+        self._pl = np.ascontiguousarray(scene.point_lights, dtype=np.float32)
+        self._tgo = np.ascontiguousarray(scene.targets_obj, dtype=np.uint32)
+        self._tgs = np.ascontiguousarray(scene.targets_sphere, dtype=np.float32)
+        s = Scene()
+        s.V, s.I, s.VN, s.tri_obj = _ptr(self.V), _ptr(self.I), _ptr(self.VN), _ptr(self.tri_obj)
+        s.nv, s.nt = scene.nv, scene.nt
+        s.mat, s.n_mat = self._mat.ctypes.data, len(self._mat)
+        s.point_lights, s.n_pl = (self._pl.ctypes.data if len(self._pl) else None), len(self._pl)
+        s.targets_obj = self._tgo.ctypes.data if len(self._tgo) else None
+        s.targets_sphere = self._tgs.ctypes.data if len(self._tgs) else None
+        s.n_tg = len(self._tgo)
+        if self.tex is not None:
+            s.tex, s.tex_h, s.tex_w = _ptr(self.tex), scene.tex.shape[0], scene.tex.shape[1]
+            s.tex_x0, s.tex_y0, s.tex_ext_u, s.tex_ext_v = scene.tex_rect
+        r = scene.receiver
+        if r is not None:
+            s.recv_obj, s.recv_wc, s.recv_hc = r.obj, r.wc, r.hc
+            s.recv_x0, s.recv_y0, s.recv_ext_u, s.recv_ext_v = r.x0, r.y0, r.ext_u, r.ext_v
+        self._s = s
+        opts = BvhOpts(width, leaf_max)
+        h = C.c_void_p()
+        _check(load().sc_build_bvh(ctx.h, C.byref(s), C.byref(opts), C.byref(h)), "sc_build_bvh")
+        self.h = h
+
+    def info(self) -> dict:
+        i = BvhInfo()
+        _check(load().sc_bvh_get_info(self.h, C.byref(i)), "sc_bvh_get_info")
+        return {k: getattr(i, k) for k, _ in BvhInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().sc_bvh_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

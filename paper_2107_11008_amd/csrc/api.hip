@@ -1,0 +1,321 @@
+// api.hip -- the C ABI (include/sc.h): argument checks, handles, scene
+// tables, and dispatch to the GPU passes.
+#pragma clang fp contract(off)
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sc_internal.h"
+#include "sc_kernels.h"
+
+struct sc_ctx {
+    scl::Ctx c;
+};
+struct sc_bvh {
+    scl::Bvh b;
+};
+
+namespace scl {
+
+static thread_local std::string g_err;
+
+sc_status set_error(sc_status code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+}  // namespace scl
+
+using scl::set_error;
+
+namespace {
+
+sc_status check_wavelengths(const sc_wavelengths* wl) {
+    if (!wl) return set_error(SC_EINVAL, "wavelengths is NULL");
+    if (wl->mode == SC_WL_FIXED) {
+        if (!(wl->k == 1 || wl->k == 3)) return set_error(SC_EINVAL, "fixed wavelengths need k = 1 or 3");
+        for (uint32_t i = 0; i < wl->k; ++i)
+            if (!(wl->nm[i] > 0.0f) || !isfinite(wl->nm[i])) return set_error(SC_EINVAL, "wavelength must be > 0");
+    } else if (wl->mode == SC_WL_UNIFORM) {
+        if (wl->bins == 0 || wl->bins > 256) return set_error(SC_EINVAL, "uniform wavelengths need 1..256 bins");
+        if (!(wl->hi > wl->lo) || !(wl->lo > 0.0f) || !isfinite(wl->hi))
+            return set_error(SC_EINVAL, "uniform wavelengths need 0 < lo < hi");
+    } else {
+        return set_error(SC_EINVAL, "unknown wavelength mode");
+    }
+    return SC_OK;
+}
+
+sc_status upload(scl::DevBuf& buf, const void* host, size_t bytes, hipStream_t st) {
+    SC_TRY(buf.alloc(bytes));
+    if (bytes) SC_HIP(hipMemcpyAsync(buf.p, host, bytes, hipMemcpyHostToDevice, st));
+    return SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t sc_abi_version(void) { return SC_ABI_VERSION; }
+
+const char* sc_last_error(void) { return scl::g_err.c_str(); }
+
+sc_status sc_create(int device, void* hip_stream, sc_ctx** out) {
+    if (!out) return set_error(SC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return set_error(SC_EDEVICE, "no HIP device");
+    if (device < 0 || device >= n) return set_error(SC_EINVAL, "device index out of range");
+    SC_HIP(hipSetDevice(device));
+    sc_ctx* x = new (std::nothrow) sc_ctx();
+    if (!x) return set_error(SC_ENOMEM, "host allocation failed");
+    x->c.device = device;
+    x->c.stream = static_cast<hipStream_t>(hip_stream);
+    sc_status s = scl::ctx_init(&x->c);
+    if (s != SC_OK) {
+        delete x;
+        return s;
+    }
+    *out = x;
+    return SC_OK;
+}
+
+sc_status sc_destroy(sc_ctx* ctx) {
+    if (!ctx) return set_error(SC_EINVAL, "ctx is NULL");
+    (void)hipStreamSynchronize(ctx->c.stream);
+    scl::ctx_release(&ctx->c);
+    delete ctx;
+    return SC_OK;
+}
+
+sc_status sc_set_stream(sc_ctx* ctx, void* hip_stream) {
+    if (!ctx) return set_error(SC_EINVAL, "ctx is NULL");
+    SC_HIP(hipStreamSynchronize(ctx->c.stream));
+    ctx->c.stream = static_cast<hipStream_t>(hip_stream);
+    return SC_OK;
+}
+
+sc_status sc_set_option(sc_ctx* ctx, int32_t option, int64_t value) {
+    if (!ctx) return set_error(SC_EINVAL, "ctx is NULL");
+    switch (option) {
+        case SC_OPT_COUNT_VISITS: ctx->c.count_visits = value != 0; return SC_OK;
+        case SC_OPT_PROFILE: ctx->c.profile = value != 0; return SC_OK;
+        case SC_OPT_QUEUE_CAP:
+            if (value < 1024 || value > (int64_t)1 << 30) return set_error(SC_EINVAL, "queue cap out of range");
+            ctx->c.queue_cap = (uint64_t)value;
+            return SC_OK;
+        default: return set_error(SC_EINVAL, "unknown option");
+    }
+}
+
+sc_status sc_sync(sc_ctx* ctx) {
+    if (!ctx) return set_error(SC_EINVAL, "ctx is NULL");
+    SC_HIP(hipStreamSynchronize(ctx->c.stream));
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+sc_status sc_get_counters(sc_ctx* ctx, sc_counters* out) {
+    if (!ctx || !out) return set_error(SC_EINVAL, "ctx or out is NULL");
+    return scl::ctx_counters(&ctx->c, out);
+}
+
+sc_status sc_reset_counters(sc_ctx* ctx) {
+    if (!ctx) return set_error(SC_EINVAL, "ctx is NULL");
+    return scl::ctx_reset_counters(&ctx->c);
+}
+
+sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* sc, const sc_bvh_opts* opts, sc_bvh** out) {
+    if (!ctx || !sc || !out) return set_error(SC_EINVAL, "ctx, scene or out is NULL");
+    *out = nullptr;
+    if (!sc->V || !sc->I || !sc->tri_obj || !sc->mat) return set_error(SC_EINVAL, "scene arrays V, I, tri_obj, mat are required");
+    if (sc->nt == 0 || sc->nv == 0) return set_error(SC_EINVAL, "scene has no triangles");
+    if (sc->nt > (1u << 28) - 1) return set_error(SC_EUNSUPPORTED, "more than 2^28 - 1 triangles");
+    if (sc->n_mat < 2) return set_error(SC_EINVAL, "n_mat must be >= 2 (row 0 is unused)");
+    for (uint32_t i = 1; i < sc->n_mat; ++i) {
+        const sc_material& m = sc->mat[i];
+        if (m.type > SC_MAT_EMISSIVE) return set_error(SC_EINVAL, "unknown material type");
+        if (m.type == SC_MAT_DIFFUSE && m.albedo_mode > SC_ALBEDO_TEXTURE) return set_error(SC_EINVAL, "unknown albedo mode");
+        if (m.type == SC_MAT_DIFFUSE && m.albedo_mode == SC_ALBEDO_TEXTURE && !sc->tex)
+            return set_error(SC_EINVAL, "texture albedo without a texture");
+    }
+    if (sc->n_pl && !sc->point_lights) return set_error(SC_EINVAL, "point_lights is NULL");
+    if (sc->n_tg && (!sc->targets_obj || !sc->targets_sphere)) return set_error(SC_EINVAL, "photon targets are NULL");
+    if (sc->recv_obj) {
+        if (sc->recv_obj >= sc->n_mat) return set_error(SC_EINVAL, "receiver object out of range");
+        if (sc->recv_wc == 0 || sc->recv_hc == 0 || !(sc->recv_ext_u > 0.0f) || !(sc->recv_ext_v > 0.0f))
+            return set_error(SC_EINVAL, "receiver needs cells and a positive extent");
+    }
+    if (sc->tex && (sc->tex_w == 0 || sc->tex_h == 0 || !(sc->tex_ext_u > 0.0f) || !(sc->tex_ext_v > 0.0f)))
+        return set_error(SC_EINVAL, "texture needs a size and a positive extent");
+    uint32_t width = opts && opts->width ? opts->width : 8u;
+    uint32_t leaf_max = opts && opts->leaf_max ? opts->leaf_max : 4u;
+    if (!(width == 4 || width == 8)) return set_error(SC_EINVAL, "width must be 4 or 8");
+    if (leaf_max < 1 || leaf_max > 8) return set_error(SC_EINVAL, "leaf_max must be 1..8");
+
+    scl::Ctx* c = &ctx->c;
+    hipStream_t st = c->stream;
+    sc_bvh* h = new (std::nothrow) sc_bvh();
+    if (!h) return set_error(SC_ENOMEM, "host allocation failed");
+    scl::Bvh* b = &h->b;
+    b->ctx = c;
+    b->scene_in = *sc;
+    sc_status s = scl::build_wide_bvh(c, b, width, leaf_max);
+    if (s == SC_OK && b->max_stack > (uint32_t)kMaxStack)
+        s = set_error(SC_EUNSUPPORTED, "BVH depth " + std::to_string(b->depth) + " needs a traversal stack of " +
+                                           std::to_string(b->max_stack) + " > " + std::to_string(kMaxStack));
+    // emissive triangles: areas in double, cumulative distribution rounded to float
+    std::vector<uint32_t> emit_prim;
+    std::vector<float> emit_cdf;
+    double a_tot = 0.0;
+    float max_power = 0.0f;
+    if (s == SC_OK) {
+        bool any_emit = false;
+        for (uint32_t i = 1; i < sc->n_mat; ++i) any_emit = any_emit || sc->mat[i].type == SC_MAT_EMISSIVE;
+        if (any_emit) {
+            std::vector<uint32_t> tobj(sc->nt), I(3 * (size_t)sc->nt);
+            std::vector<float> V(3 * (size_t)sc->nv);
+            if (hipMemcpy(tobj.data(), sc->tri_obj, 4 * (size_t)sc->nt, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(I.data(), sc->I, 12 * (size_t)sc->nt, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(V.data(), sc->V, 12 * (size_t)sc->nv, hipMemcpyDeviceToHost) != hipSuccess) {
+                s = set_error(SC_EDEVICE, "reading the scene back failed");
+            } else {
+                std::vector<double> area;
+                for (uint32_t i = 0; i < sc->nt; ++i) {
+                    if (sc->mat[tobj[i]].type != SC_MAT_EMISSIVE) continue;
+                    double a[3], bb[3], cc[3];
+                    for (int j = 0; j < 3; ++j) {
+                        a[j] = V[3 * (size_t)I[3 * (size_t)i] + j];
+                        bb[j] = V[3 * (size_t)I[3 * (size_t)i + 1] + j];
+                        cc[j] = V[3 * (size_t)I[3 * (size_t)i + 2] + j];
+                    }
+                    const double e1[3] = {bb[0] - a[0], bb[1] - a[1], bb[2] - a[2]};
+                    const double e2[3] = {cc[0] - a[0], cc[1] - a[1], cc[2] - a[2]};
+                    const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+                    const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+                    const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+                    area.push_back(0.5 * sqrt(cx * cx + cy * cy + cz * cz));
+                    a_tot += area.back();
+                    emit_prim.push_back(i);
+                }
+                double cum = 0.0;
+                for (size_t j = 0; j < area.size(); ++j) {
+                    cum += area[j];
+                    emit_cdf.push_back((float)(cum / a_tot));
+                }
+                if (!emit_cdf.empty()) emit_cdf.back() = 1.0f;
+            }
+        }
+    }
+    if (s == SC_OK) {
+        const float atf = (float)a_tot;
+        for (uint32_t i = 0; i < sc->n_pl; ++i) max_power = std::max(max_power, sc->point_lights[4 * (size_t)i + 3]);
+        if (!emit_prim.empty())
+            for (uint32_t i = 1; i < sc->n_mat; ++i)
+                if (sc->mat[i].type == SC_MAT_EMISSIVE) max_power = std::max(max_power, sc->mat[i].le * atf);
+        b->max_power = max_power;
+        std::vector<float> tg(4 * (size_t)sc->n_tg);
+        for (uint32_t i = 0; i < 4 * sc->n_tg; ++i) tg[i] = sc->targets_sphere[i];
+        if ((s = upload(b->mat, sc->mat, sizeof(sc_material) * sc->n_mat, st)) == SC_OK &&
+            (s = upload(b->pl, sc->point_lights, 16 * (size_t)sc->n_pl, st)) == SC_OK &&
+            (s = upload(b->tg, tg.data(), 16 * (size_t)sc->n_tg, st)) == SC_OK &&
+            (s = upload(b->emit_prim, emit_prim.data(), 4 * emit_prim.size(), st)) == SC_OK &&
+            (s = upload(b->emit_cdf, emit_cdf.data(), 4 * emit_cdf.size(), st)) == SC_OK) {
+            if (hipStreamSynchronize(st) != hipSuccess) s = set_error(SC_EDEVICE, "upload failed");
+        }
+    }
+    if (s != SC_OK) {
+        delete h;
+        return s;
+    }
+    DevScene& D = b->scene;
+    D.V = sc->V; D.I = sc->I; D.VN = sc->VN; D.tri_obj = sc->tri_obj; D.nt = sc->nt;
+    D.mat = b->mat.as<sc_material>(); D.n_mat = sc->n_mat;
+    D.pl = b->pl.as<float>(); D.n_pl = sc->n_pl;
+    D.tg = b->tg.as<float>(); D.n_tg = sc->n_tg;
+    D.tex = sc->tex; D.tex_w = sc->tex_w; D.tex_h = sc->tex_h; D.tex_x0 = sc->tex_x0; D.tex_y0 = sc->tex_y0;
+    D.tex_sx = sc->tex ? (float)sc->tex_w / sc->tex_ext_u : 0.0f;
+    D.tex_sy = sc->tex ? (float)sc->tex_h / sc->tex_ext_v : 0.0f;
+    D.recv_obj = sc->recv_obj; D.recv_wc = sc->recv_wc; D.recv_hc = sc->recv_hc;
+    D.recv_x0 = sc->recv_x0; D.recv_y0 = sc->recv_y0;
+    D.cell_sx = sc->recv_obj ? (float)sc->recv_wc / sc->recv_ext_u : 0.0f;
+    D.cell_sy = sc->recv_obj ? (float)sc->recv_hc / sc->recv_ext_v : 0.0f;
+    D.inv_cell_area = sc->recv_obj ? (float)(((double)sc->recv_wc * (double)sc->recv_hc) /
+                                             ((double)sc->recv_ext_u * (double)sc->recv_ext_v))
+                                   : 0.0f;
+    D.emit_prim = b->emit_prim.as<uint32_t>(); D.emit_cdf = b->emit_cdf.as<float>();
+    D.n_emit = (uint32_t)emit_prim.size(); D.a_tot = (float)a_tot;
+    D.n_entries = sc->n_pl + (emit_prim.empty() ? 0u : 1u);
+    D.nodes = b->nodes.as<BNode>(); D.tris = b->tris.as<float4>(); D.n_nodes = b->n_nodes;
+    *out = h;
+    return SC_OK;
+}
+
+sc_status sc_bvh_get_info(const sc_bvh* bvh, sc_bvh_info* out) {
+    if (!bvh || !out) return set_error(SC_EINVAL, "bvh or out is NULL");
+    const scl::Bvh& b = bvh->b;
+    out->width = b.width;
+    out->leaf_max = b.leaf_max;
+    out->n_nodes = b.n_nodes;
+    out->depth = b.depth;
+    out->node_bytes = (uint64_t)b.n_nodes * sizeof(BNode);
+    out->tri_bytes = (uint64_t)b.scene.nt * 48u;
+    out->max_stack = b.max_stack;
+    return SC_OK;
+}
+
+sc_status sc_bvh_free(sc_bvh* bvh) {
+    if (!bvh) return set_error(SC_EINVAL, "bvh is NULL");
+    (void)hipStreamSynchronize(bvh->b.ctx->stream);
+    delete bvh;
+    return SC_OK;
+}
+
+sc_status sc_trace_rays(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D, float* t,
+                        uint32_t* prim, float* u, float* v) {
+    if (!ctx || !bvh) return set_error(SC_EINVAL, "ctx or bvh is NULL");
+    if (n == 0) return SC_OK;
+    if (!O || !D || !t || !prim) return set_error(SC_EINVAL, "O, D, t and prim are required");
+    return scl::trace_rays(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n, O, D, t, prim, u, v);
+}
+
+sc_status sc_occluded(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D, const float* tmax,
+                      const uint32_t* excl, uint8_t* occ) {
+    if (!ctx || !bvh) return set_error(SC_EINVAL, "ctx or bvh is NULL");
+    if (n == 0) return SC_OK;
+    if (!O || !D || !tmax || !occ) return set_error(SC_EINVAL, "O, D, tmax and occluded are required");
+    return scl::occluded(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n, O, D, tmax, excl, occ);
+}
+
+sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, uint32_t max_depth,
+                           const sc_wavelengths* wl, uint64_t seed, float* caustic_map, uint32_t* count_map,
+                           sc_photon_stats* stats) {
+    if (!ctx || !bvh || !caustic_map) return set_error(SC_EINVAL, "ctx, bvh or caustic_map is NULL");
+    SC_TRY(check_wavelengths(wl));
+    if (max_depth == 0) return set_error(SC_EINVAL, "max_depth must be >= 1");
+    if (!bvh->b.scene.recv_obj) return set_error(SC_EINVAL, "the scene has no caustic receiver");
+    if (n_photons > (1ull << 40)) return set_error(SC_EINVAL, "n_photons too large");
+    if (stats) memset(stats, 0, sizeof(*stats));
+    return scl::trace_photons(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n_photons, max_depth, *wl, seed, caustic_map,
+                              count_map, stats);
+}
+
+sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
+                    const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, const sc_aov* out) {
+    if (!ctx || !bvh || !cam || !out) return set_error(SC_EINVAL, "ctx, bvh, camera or out is NULL");
+    SC_TRY(check_wavelengths(wl));
+    if (spp == 0) return set_error(SC_EINVAL, "spp must be >= 1");
+    if (max_depth == 0) return set_error(SC_EINVAL, "max_depth must be >= 1");
+    if (cam->w == 0 || cam->h == 0) return set_error(SC_EINVAL, "camera has no pixels");
+    if ((uint64_t)cam->w * cam->h > (1ull << 28)) return set_error(SC_EUNSUPPORTED, "image too large");
+    if (caustic_map && !bvh->b.scene.recv_obj) return set_error(SC_EINVAL, "caustic map given but no receiver");
+    return scl::render(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), *cam, spp, max_depth, *wl, seed, caustic_map, *out);
+}
+
+}  // extern "C"

@@ -1,0 +1,438 @@
+// bvh.hip -- GPU construction of the wide BVH.
+//
+// 1. per-triangle bounds and centroids, centroid bounds of the scene;
+// 2. 64-bit keys (30-bit Morton code of the centroid, triangle index);
+// 3. bitonic sort of the keys (LDS for short strides, global otherwise);
+// 4. binary radix tree over the sorted keys (Karras, "Maximizing
+//    parallelism in the construction of BVHs, octrees, and k-d trees",
+//    HPG 2012), internal node i spanning a contiguous key range;
+// 5. bottom-up bounds with one atomic arrival flag per internal node;
+// 6. greedy collapse, one level of wide nodes per launch: a wide node opens
+//    its largest-area non-leaf child until it holds 8 children; ranges of
+//    at most leaf_max triangles become leaves;
+// 7. triangles gathered in key order for the leaves.
+#pragma clang fp contract(off)
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sc_internal.h"
+
+namespace {
+
+__device__ __forceinline__ uint32_t ordered(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float unordered(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__global__ void k_validate(const uint32_t* __restrict__ I, const uint32_t* __restrict__ tri_obj, uint32_t nt,
+                           uint32_t nv, uint32_t n_mat, uint32_t* err) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
+        const uint32_t o = tri_obj[i];
+        if (o == 0 || o >= n_mat) atomicOr(err, 1u);
+        if (I[3 * (size_t)i] >= nv || I[3 * (size_t)i + 1] >= nv || I[3 * (size_t)i + 2] >= nv) atomicOr(err, 2u);
+    }
+}
+
+// bounds [nt][6] (lo xyz, hi xyz) and centroid bounds (ordered uints)
+__global__ void k_tri_bounds(const float* __restrict__ V, const uint32_t* __restrict__ I, uint32_t nt,
+                             float* __restrict__ bounds, uint32_t* __restrict__ cb) {
+    float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
+        const uint32_t* idx = I + 3 * (size_t)i;
+        float lo[3], hi[3];
+        bool finite = true;
+        for (int k = 0; k < 3; ++k) {
+            const float a = V[3 * (size_t)idx[0] + k], b = V[3 * (size_t)idx[1] + k], c = V[3 * (size_t)idx[2] + k];
+            finite = finite && isfinite(a) && isfinite(b) && isfinite(c);
+            lo[k] = fminf(a, fminf(b, c));
+            hi[k] = fmaxf(a, fmaxf(b, c));
+        }
+        if (!finite) {
+            // a triangle with a non-finite vertex can never be hit: empty box
+            for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+        }
+        for (int k = 0; k < 3; ++k) {
+            bounds[6 * (size_t)i + k] = lo[k];
+            bounds[6 * (size_t)i + 3 + k] = hi[k];
+            if (finite) {
+                const float c = 0.5f * lo[k] + 0.5f * hi[k];
+                clo[k] = fminf(clo[k], c);
+                chi[k] = fmaxf(chi[k], c);
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        for (int off = 32; off > 0; off >>= 1) {
+            clo[k] = fminf(clo[k], __shfl_xor(clo[k], off));
+            chi[k] = fmaxf(chi[k], __shfl_xor(chi[k], off));
+        }
+    }
+    if (__lane_id() == 0) {
+        for (int k = 0; k < 3; ++k) {
+            atomicMin(&cb[k], ordered(clo[k]));
+            atomicMax(&cb[3 + k], ordered(chi[k]));
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__global__ void k_morton(const float* __restrict__ bounds, uint32_t nt, uint32_t n_pad, const uint32_t* __restrict__ cb,
+                         unsigned long long* __restrict__ keys) {
+    float lo[3], inv[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = unordered(cb[k]);
+        const float ext = unordered(cb[3 + k]) - lo[k];
+        inv[k] = ext > 0.0f ? 1023.0f / ext : 0.0f;
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += gridDim.x * blockDim.x) {
+        if (i >= nt) {
+            keys[i] = ~0ull;
+            continue;
+        }
+        uint32_t q[3];
+        for (int k = 0; k < 3; ++k) {
+            const float l = bounds[6 * (size_t)i + k], h = bounds[6 * (size_t)i + 3 + k];
+            float c = 0.5f * l + 0.5f * h;
+            float f = isfinite(c) ? (c - lo[k]) * inv[k] : 0.0f;
+            f = fminf(fmaxf(f, 0.0f), 1023.0f);
+            q[k] = (uint32_t)f;
+        }
+        const uint32_t m = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+        keys[i] = ((unsigned long long)m << 32) | (unsigned long long)i;
+    }
+}
+
+// Bitonic sort.  Element pairs (i, i ^ j) are ordered ascending when
+// (i & k) == 0.  Strides below kLocal run in LDS.
+constexpr int kLocal = 2048;  // elements per block in LDS (1024 threads x 2)
+
+__global__ __launch_bounds__(1024) void k_bitonic_local(unsigned long long* keys, uint32_t k_begin, uint32_t k_end) {
+    __shared__ unsigned long long s[kLocal];
+    const uint32_t base = blockIdx.x * kLocal;
+    s[threadIdx.x] = keys[base + threadIdx.x];
+    s[threadIdx.x + 1024] = keys[base + threadIdx.x + 1024];
+    __syncthreads();
+    for (uint32_t k = k_begin; k <= k_end; k <<= 1) {
+        const uint32_t jstart = (k <= (uint32_t)kLocal) ? (k >> 1) : (uint32_t)(kLocal >> 1);
+        for (uint32_t j = jstart; j > 0; j >>= 1) {
+            const uint32_t t = threadIdx.x;
+            const uint32_t i = 2 * t - (t & (j - 1));   // lower index of the pair
+            const uint32_t l = i + j;
+            const bool up = ((base + i) & k) == 0;
+            const unsigned long long a = s[i], b = s[l];
+            if ((a > b) == up) { s[i] = b; s[l] = a; }
+            __syncthreads();
+        }
+    }
+    keys[base + threadIdx.x] = s[threadIdx.x];
+    keys[base + threadIdx.x + 1024] = s[threadIdx.x + 1024];
+}
+
+__global__ void k_bitonic_global(unsigned long long* keys, uint32_t n, uint32_t k, uint32_t j) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n / 2; t += gridDim.x * blockDim.x) {
+        const uint32_t i = 2 * t - (t & (j - 1));
+        const uint32_t l = i + j;
+        const bool up = (i & k) == 0;
+        const unsigned long long a = keys[i], b = keys[l];
+        if ((a > b) == up) { keys[i] = b; keys[l] = a; }
+    }
+}
+
+__device__ __forceinline__ int delta(const unsigned long long* keys, uint32_t n, int i, int j) {
+    if (j < 0 || j >= (int)n) return -1;
+    return __clzll(keys[i] ^ keys[j]);
+}
+
+// Radix tree: internal nodes 0..n-2; child encoding: value < n-1 internal,
+// value >= n-1 is leaf (value - (n-1)) = sorted position.
+__global__ void k_radix_tree(const unsigned long long* __restrict__ keys, uint32_t n, int32_t* __restrict__ left,
+                             int32_t* __restrict__ right, int32_t* __restrict__ parent, uint32_t* __restrict__ rlo,
+                             uint32_t* __restrict__ rhi) {
+    for (uint32_t ii = blockIdx.x * blockDim.x + threadIdx.x; ii + 1 < n; ii += gridDim.x * blockDim.x) {
+        const int i = (int)ii;
+        const int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+        const int dmin = delta(keys, n, i, i - d);
+        int lmax = 2;
+        while (delta(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+        int l = 0;
+        for (int t = lmax >> 1; t >= 1; t >>= 1)
+            if (delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+        const int j = i + l * d;
+        const int dnode = delta(keys, n, i, j);
+        int s = 0;
+        int t = l;
+        do {
+            t = (t + 1) >> 1;
+            if (delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
+        } while (t > 1);
+        const int gamma = i + s * d + (d < 0 ? -1 : 0);
+        const int lo = i < j ? i : j, hi = i < j ? j : i;
+        const int lc = (lo == gamma) ? (int)(n - 1) + gamma : gamma;
+        const int rc = (hi == gamma + 1) ? (int)(n - 1) + gamma + 1 : gamma + 1;
+        left[i] = lc;
+        right[i] = rc;
+        parent[lc] = i;
+        parent[rc] = i;
+        rlo[i] = (uint32_t)lo;
+        rhi[i] = (uint32_t)hi;
+    }
+}
+
+// bottom-up bounds: node boxes nb[(2n-1)][6], leaves at n-1+pos
+__global__ void k_refit(const unsigned long long* __restrict__ keys, const float* __restrict__ tb, uint32_t n,
+                        const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                        const int32_t* __restrict__ parent, float* nb, uint32_t* flags) {
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const uint32_t prim = (uint32_t)(keys[p] & 0xffffffffull);
+        const uint32_t leaf = n - 1 + p;
+        for (int k = 0; k < 6; ++k) nb[6 * (size_t)leaf + k] = tb[6 * (size_t)prim + k];
+        if (n == 1) continue;
+        __threadfence();
+        int node = parent[leaf];
+        while (node >= 0) {
+            if (atomicAdd(&flags[node], 1u) == 0) break;   // first arrival: the sibling finishes
+            __threadfence();
+            const int a = left[node], b = right[node];
+            for (int k = 0; k < 3; ++k) {
+                // the fence above orders these reads after the sibling's writes
+                const volatile float* vb = nb;
+                const float la = vb[6 * (size_t)a + k];
+                const float lb = vb[6 * (size_t)b + k];
+                const float ha = vb[6 * (size_t)a + 3 + k];
+                const float hb = vb[6 * (size_t)b + 3 + k];
+                nb[6 * (size_t)node + k] = fminf(la, lb);
+                nb[6 * (size_t)node + 3 + k] = fmaxf(ha, hb);
+            }
+            __threadfence();
+            node = node == 0 ? -1 : parent[node];
+        }
+    }
+}
+
+__device__ __forceinline__ float half_area(const float* b) {
+    const float ex = b[3] - b[0], ey = b[4] - b[1], ez = b[5] - b[2];
+    if (!(ex >= 0.0f) || !(ey >= 0.0f) || !(ez >= 0.0f)) return 0.0f;
+    return ex * ey + ey * ez + ez * ex;
+}
+
+// One level of the collapse.  work[i] = (bvh2 node, wide node index).
+__global__ void k_collapse(uint32_t n, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                           const uint32_t* __restrict__ rlo, const uint32_t* __restrict__ rhi,
+                           const float* __restrict__ nb, uint32_t leaf_max, uint32_t width,
+                           const uint2* __restrict__ work, const uint32_t* __restrict__ n_work, uint2* next_work,
+                           uint32_t* n_next, uint32_t* n_nodes, BNode* nodes) {
+    const uint32_t nw = *n_work;
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) {
+        const uint2 item = work[w];
+        int32_t set[8];
+        int cnt = 0;
+        const int32_t root = (int32_t)item.x;
+        auto range_of = [&](int32_t c, uint32_t& lo, uint32_t& cn) {
+            if (c >= (int32_t)(n - 1)) { lo = (uint32_t)c - (n - 1); cn = 1; }
+            else { lo = rlo[c]; cn = rhi[c] - rlo[c] + 1; }
+        };
+        if (root >= (int32_t)(n - 1)) {
+            set[cnt++] = root;   // a single-triangle tree
+        } else {
+            set[cnt++] = left[root];
+            set[cnt++] = right[root];
+        }
+        while (cnt < (int)width) {
+            int best = -1;
+            float ba = -1.0f;
+            for (int c = 0; c < cnt; ++c) {
+                uint32_t lo, cn;
+                range_of(set[c], lo, cn);
+                if (cn <= leaf_max) continue;
+                const float a = half_area(nb + 6 * (size_t)set[c]);
+                if (a > ba) { ba = a; best = c; }
+            }
+            if (best < 0) break;
+            const int32_t c = set[best];
+            set[best] = left[c];
+            set[cnt++] = right[c];
+        }
+        BNode node;
+        for (int c = 0; c < 8; ++c) {
+            if (c < cnt) {
+                const float* b = nb + 6 * (size_t)set[c];
+                node.lox[c] = b[0]; node.loy[c] = b[1]; node.loz[c] = b[2];
+                node.hix[c] = b[3]; node.hiy[c] = b[4]; node.hiz[c] = b[5];
+                uint32_t lo, cn;
+                range_of(set[c], lo, cn);
+                if (cn <= leaf_max) {
+                    node.child[c] = SC_LEAF_BIT | ((cn - 1) << 28) | lo;
+                } else {
+                    const uint32_t idx = atomicAdd(n_nodes, 1u);
+                    const uint32_t q = atomicAdd(n_next, 1u);
+                    next_work[q] = make_uint2((uint32_t)set[c], idx);
+                    node.child[c] = idx;
+                }
+            } else {
+                node.lox[c] = INFINITY; node.loy[c] = INFINITY; node.loz[c] = INFINITY;
+                node.hix[c] = -INFINITY; node.hiy[c] = -INFINITY; node.hiz[c] = -INFINITY;
+                node.child[c] = SC_CHILD_EMPTY;
+            }
+            node.pad[c] = 0;
+        }
+        nodes[item.y] = node;
+    }
+}
+
+__global__ void k_gather_tris(const unsigned long long* __restrict__ keys, uint32_t n, const float* __restrict__ V,
+                              const uint32_t* __restrict__ I, float4* __restrict__ tris) {
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+        const uint32_t prim = (uint32_t)(keys[p] & 0xffffffffull);
+        const uint32_t* idx = I + 3 * (size_t)prim;
+        const float* a = V + 3 * (size_t)idx[0];
+        const float* b = V + 3 * (size_t)idx[1];
+        const float* c = V + 3 * (size_t)idx[2];
+        tris[3 * (size_t)p + 0] = make_float4(a[0], a[1], a[2], __uint_as_float(prim));
+        tris[3 * (size_t)p + 1] = make_float4(b[0], b[1], b[2], 0.0f);
+        tris[3 * (size_t)p + 2] = make_float4(c[0], c[1], c[2], 0.0f);
+    }
+}
+
+__global__ void k_init_u32(uint32_t* p, uint32_t n, uint32_t v) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_init_i32(int32_t* p, uint32_t n, int32_t v) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+inline uint32_t grid_for(size_t n, uint32_t bs, uint32_t cap = 65536) {
+    size_t g = (n + bs - 1) / bs;
+    if (g < 1) g = 1;
+    return (uint32_t)(g > cap ? cap : g);
+}
+
+}  // namespace
+
+namespace scl {
+
+// Builds nodes/tris into the handle.  Returns SC_OK or an error code with
+// the message set.
+sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
+    hipStream_t st = ctx->stream;
+    const uint32_t n = b->scene.nt;
+    uint32_t n_pad = 1;
+    while (n_pad < n) n_pad <<= 1;
+    if (n_pad < (uint32_t)kLocal) n_pad = kLocal;
+
+    DevBuf err_d, bounds, cb, keys, left, right, parent, rlo, rhi, nb, flags, work_a, work_b, counters;
+    SC_TRY(err_d.alloc(sizeof(uint32_t)));
+    SC_TRY(bounds.alloc(sizeof(float) * 6 * (size_t)n));
+    SC_TRY(cb.alloc(sizeof(uint32_t) * 6));
+    SC_TRY(keys.alloc(sizeof(unsigned long long) * (size_t)n_pad));
+    SC_TRY(left.alloc(sizeof(int32_t) * (size_t)(n > 1 ? n - 1 : 1)));
+    SC_TRY(right.alloc(sizeof(int32_t) * (size_t)(n > 1 ? n - 1 : 1)));
+    SC_TRY(parent.alloc(sizeof(int32_t) * (size_t)(2 * n)));
+    SC_TRY(rlo.alloc(sizeof(uint32_t) * (size_t)(n > 1 ? n - 1 : 1)));
+    SC_TRY(rhi.alloc(sizeof(uint32_t) * (size_t)(n > 1 ? n - 1 : 1)));
+    SC_TRY(nb.alloc(sizeof(float) * 6 * (size_t)(2 * n)));
+    SC_TRY(flags.alloc(sizeof(uint32_t) * (size_t)(n > 1 ? n - 1 : 1)));
+    SC_TRY(work_a.alloc(sizeof(uint2) * (size_t)n));
+    SC_TRY(work_b.alloc(sizeof(uint2) * (size_t)n));
+    SC_TRY(counters.alloc(sizeof(uint32_t) * 4));
+
+    const uint32_t bs = 256;
+    hipLaunchKernelGGL(k_init_u32, dim3(1), dim3(64), 0, st, err_d.as<uint32_t>(), 1u, 0u);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(n, bs)), dim3(bs), 0, st, b->scene_in.I, b->scene_in.tri_obj, n,
+                       b->scene_in.nv, b->scene_in.n_mat, err_d.as<uint32_t>());
+    uint32_t err_h = 0;
+    SC_HIP(hipMemcpyAsync(&err_h, err_d.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    SC_HIP(hipStreamSynchronize(st));
+    if (err_h & 1u) return set_error(SC_EINVAL, "tri_obj holds an object id outside [1, n_mat)");
+    if (err_h & 2u) return set_error(SC_EINVAL, "I holds a vertex index >= nv");
+
+    uint32_t cb_init[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
+    SC_HIP(hipMemcpyAsync(cb.p, cb_init, sizeof(cb_init), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_tri_bounds, dim3(grid_for(n, bs, 4096)), dim3(bs), 0, st, b->scene_in.V, b->scene_in.I, n,
+                       bounds.as<float>(), cb.as<uint32_t>());
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n_pad, bs)), dim3(bs), 0, st, bounds.as<float>(), n, n_pad,
+                       cb.as<uint32_t>(), keys.as<unsigned long long>());
+    // bitonic sort
+    const uint32_t nblk = n_pad / kLocal;
+    hipLaunchKernelGGL(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys.as<unsigned long long>(), 2u,
+                       (uint32_t)kLocal);
+    for (uint32_t k = 2 * kLocal; k <= n_pad; k <<= 1) {
+        for (uint32_t j = k >> 1; j >= (uint32_t)kLocal; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic_global, dim3(grid_for(n_pad / 2, bs)), dim3(bs), 0, st,
+                               keys.as<unsigned long long>(), n_pad, k, j);
+        hipLaunchKernelGGL(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys.as<unsigned long long>(), k, k);
+    }
+    // radix tree + bounds
+    hipLaunchKernelGGL(k_init_i32, dim3(grid_for(2 * n, bs)), dim3(bs), 0, st, parent.as<int32_t>(), 2 * n, -1);
+    if (n > 1) {
+        hipLaunchKernelGGL(k_init_u32, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, flags.as<uint32_t>(), n - 1, 0u);
+        hipLaunchKernelGGL(k_radix_tree, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(), n,
+                           left.as<int32_t>(), right.as<int32_t>(), parent.as<int32_t>(), rlo.as<uint32_t>(),
+                           rhi.as<uint32_t>());
+    }
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(),
+                       bounds.as<float>(), n, left.as<int32_t>(), right.as<int32_t>(), parent.as<int32_t>(),
+                       nb.as<float>(), flags.as<uint32_t>());
+
+    // collapse: level by level
+    const uint32_t max_nodes = n > 1 ? n : 1;
+    DevBuf nodes_tmp;
+    SC_TRY(nodes_tmp.alloc(sizeof(BNode) * (size_t)max_nodes));
+    uint32_t init_cnt[4] = {1u, 0u, 1u, 0u};   // [0] work count, [1] next count, [2] nodes allocated
+    SC_HIP(hipMemcpyAsync(counters.p, init_cnt, sizeof(init_cnt), hipMemcpyHostToDevice, st));
+    const uint2 root = make_uint2(n > 1 ? 0u : 0u, 0u);
+    uint2 root_item = root;
+    if (n == 1) root_item.x = 0;   // leaf index n-1+0 = 0 when n == 1
+    SC_HIP(hipMemcpyAsync(work_a.p, &root_item, sizeof(uint2), hipMemcpyHostToDevice, st));
+    uint32_t depth = 0;
+    uint32_t cur_count = 1;
+    DevBuf* wa = &work_a;
+    DevBuf* wb = &work_b;
+    while (cur_count > 0) {
+        uint32_t zero = 0;
+        SC_HIP(hipMemcpyAsync(counters.as<uint32_t>() + 1, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_collapse, dim3(grid_for(cur_count, 128)), dim3(128), 0, st, n, left.as<int32_t>(),
+                           right.as<int32_t>(), rlo.as<uint32_t>(), rhi.as<uint32_t>(), nb.as<float>(), leaf_max,
+                           width, wa->as<uint2>(), counters.as<uint32_t>(), wb->as<uint2>(),
+                           counters.as<uint32_t>() + 1, counters.as<uint32_t>() + 2, nodes_tmp.as<BNode>());
+        uint32_t h[3];
+        SC_HIP(hipMemcpyAsync(h, counters.p, sizeof(h), hipMemcpyDeviceToHost, st));
+        SC_HIP(hipStreamSynchronize(st));
+        cur_count = h[1];
+        SC_HIP(hipMemcpyAsync(counters.p, &cur_count, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        DevBuf* t = wa;
+        wa = wb;
+        wb = t;
+        ++depth;
+        if (depth > 4096) return set_error(SC_EDEVICE, "BVH collapse did not terminate");
+    }
+    uint32_t n_nodes = 0;
+    SC_HIP(hipMemcpyAsync(&n_nodes, counters.as<uint32_t>() + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    SC_HIP(hipStreamSynchronize(st));
+
+    SC_TRY(b->nodes.alloc(sizeof(BNode) * (size_t)n_nodes));
+    SC_HIP(hipMemcpyAsync(b->nodes.p, nodes_tmp.p, sizeof(BNode) * (size_t)n_nodes, hipMemcpyDeviceToDevice, st));
+    SC_TRY(b->tris.alloc(sizeof(float4) * 3 * (size_t)n));
+    hipLaunchKernelGGL(k_gather_tris, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(), n,
+                       b->scene_in.V, b->scene_in.I, b->tris.as<float4>());
+    SC_HIP(hipGetLastError());
+    SC_HIP(hipStreamSynchronize(st));
+    b->n_nodes = n_nodes;
+    b->depth = depth;
+    b->width = width;
+    b->leaf_max = leaf_max;
+    b->max_stack = (width - 1) * depth + 1;
+    return SC_OK;
+}
+
+}  // namespace scl

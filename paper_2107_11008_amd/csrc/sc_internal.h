@@ -1,0 +1,102 @@
+// sc_internal.h -- host-side objects of the library (context, BVH handle,
+// device buffers, error reporting).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sc_types.h"
+
+namespace scl {
+
+sc_status set_error(sc_status code, const std::string& msg);
+
+// RAII device allocation
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    sc_status alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return set_error(SC_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+        }
+        bytes = n;
+        return SC_OK;
+    }
+    // grow-only
+    sc_status ensure(size_t n) {
+        if (n <= bytes && p) return SC_OK;
+        return alloc(n);
+    }
+    template <class T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+#define SC_TRY(expr)                      \
+    do {                                  \
+        sc_status _s = (expr);            \
+        if (_s != SC_OK) return _s;       \
+    } while (0)
+
+#define SC_HIP(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t _e = (expr);                                                                    \
+        if (_e != hipSuccess)                                                                      \
+            return ::scl::set_error(SC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool count_visits = false;
+    bool profile = false;
+    uint64_t queue_cap = 1ull << 23;
+    uint64_t photon_cap = 1ull << 22;
+    DevBuf counters;   // DevCounters
+    DevBuf work;       // per-launch work counters of the traversal kernels
+    uint32_t work_slot = 0;
+    DevBuf path;       // PathState arrays
+    size_t path_n = 0;
+    DevBuf queues;     // five queues + counts
+    size_t queue_n = 0;
+    DevBuf photon;     // PhotonState arrays
+    size_t photon_n = 0;
+    DevBuf acc64;      // fixed-point caustic accumulator
+    DevBuf sensor;     // sensor curve table
+    DevBuf aos;        // SoA copies for sc_trace_rays / sc_occluded
+    size_t aos_n = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    double closest_ms = 0.0;
+    uint64_t closest_launches = 0;
+};
+
+struct Bvh {
+    Ctx* ctx = nullptr;
+    sc_scene scene_in{};          // copy of the caller's description (pointers borrowed)
+    DevScene scene{};             // device view
+    DevBuf nodes, tris, mat, pl, tg, emit_prim, emit_cdf;
+    uint32_t n_nodes = 0, depth = 0, width = 8, leaf_max = 4, max_stack = 0;
+    // strongest light power (point intensity or emitted radiance x area)
+    float max_power = 0.0f;
+};
+
+sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max);
+
+}  // namespace scl

@@ -1,0 +1,42 @@
+// sc_kernels.h -- ray buffer views used by the traversal kernels and the
+// entry points of the wavefront passes.
+#pragma once
+#include <stdint.h>
+
+#include "sc_internal.h"
+#include "sc_types.h"
+
+// maximum traversal stack entries per ray (LDS part plus scratch spill)
+constexpr int kMaxStack = 160;
+
+struct RaySoA {
+    float *ox, *oy, *oz, *dx, *dy, *dz;
+};
+struct HitSoA {
+    float* t;
+    uint32_t* prim;
+    float *u, *v;
+};
+struct ShadowSoA {
+    float *ox, *oy, *oz, *dx, *dy, *dz;
+    float* tmax;
+    uint32_t* excl;
+    float* contrib;
+};
+
+namespace scl {
+
+sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t max_depth, const sc_wavelengths& wl,
+                 uint64_t seed, const float* cmap, const sc_aov& out);
+sc_status trace_photons(Ctx* c, Bvh* b, uint64_t n_photons, uint32_t max_depth, const sc_wavelengths& wl,
+                        uint64_t seed, float* map, uint32_t* count_map, sc_photon_stats* stats);
+sc_status trace_rays(Ctx* c, Bvh* b, uint32_t n, const float* O, const float* D, float* t, uint32_t* prim, float* u,
+                     float* v);
+sc_status occluded(Ctx* c, Bvh* b, uint32_t n, const float* O, const float* D, const float* tmax,
+                   const uint32_t* excl, uint8_t* occ);
+sc_status ctx_counters(Ctx* c, sc_counters* out);
+sc_status ctx_reset_counters(Ctx* c);
+sc_status ctx_init(Ctx* c);
+void ctx_release(Ctx* c);
+
+}  // namespace scl

@@ -1,0 +1,309 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Bar (from the method's outputs): triangle id, object id, mask and depth
+bit-exact; the traced paths are bit-identical, so radiance is bit-exact
+when both sides gather from the same caustic map, and within 1e-4
+relative (99.9% of pixels, mean within 1e-5) with each side's own map;
+caustic-map cells within 1e-5 relative (floor 1e-3 of the largest cell),
+per-cell photon counts exact.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2107_11008_amd as sc
+    return sc.Context(0)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _bits(x):
+    return np.ascontiguousarray(x).view(np.uint32)
+
+
+def _rays(rng, n, center, spread, targets=None):
+    O = (center + rng.normal(size=(n, 3)) * spread).astype(np.float32)
+    if targets is None:
+        D = rng.normal(size=(n, 3))
+    else:
+        D = targets[rng.integers(0, len(targets), size=n)] - O
+    D = (D / np.linalg.norm(D, axis=1, keepdims=True)).astype(np.float32)
+    return O, D
+
+
+def _scene_c2_small(seed=2000, scale=0.03):
+    c = sg.config2(seed=seed, tri_scale=scale, w=64, h=64)
+    return c
+
+
+@pytest.mark.parametrize("which", ["c1", "c2s", "soup"])
+@pytest.mark.parametrize("n", [1, 63, 65, 5000])
+def test_closest_hit_bitexact(ctx, which, n):
+    rng = np.random.default_rng(n)
+    if which == "c1":
+        scene = sg.config1()["scene"]
+        center, spread = np.array([0, 0, 1.5]), 3.0
+    elif which == "c2s":
+        scene = _scene_c2_small()["scene"]
+        center, spread = np.array([0, 0, 0.2]), 0.8
+    else:
+        b = sg.SceneBuilder()
+        V = rng.uniform(-1, 1, size=(600, 3))
+        b.add(sg.Mesh(V, np.arange(600).reshape(200, 3), np.tile([0, 0, 1.0], (600, 1))),
+              dict(type=sg.MAT_DIFFUSE, rho_a=0.5))
+        scene = b.build(None)
+        center, spread = np.zeros(3), 2.0
+    V = scene.V.astype(np.float64)
+    I = scene.I
+    targets = np.concatenate([V, 0.5 * (V[I[:, 0]] + V[I[:, 1]])])
+    O1, D1 = _rays(rng, n // 2 + 1, center, spread)
+    O2, D2 = _rays(rng, n - n // 2 - 1, center, spread, targets)
+    O, D = np.concatenate([O1, O2])[:n], np.concatenate([D1, D2])[:n]
+    osc = oracle.OracleScene(scene)
+    to, po, uo, vo = oracle.closest(osc, O, D)
+    bvh = ctx.build_bvh(scene)
+    t, p, u, v = [x.cpu().numpy() for x in ctx.trace_rays(bvh, _t(O), _t(D))]
+    assert np.array_equal(p.view(np.uint32), po)
+    assert np.array_equal(_bits(t), _bits(to))
+    assert np.array_equal(_bits(u), _bits(uo))
+    assert np.array_equal(_bits(v), _bits(vo))
+
+
+@pytest.mark.parametrize("width,leaf", [(8, 4), (4, 1), (8, 8), (4, 3)])
+def test_bvh_shape_does_not_change_hits(ctx, width, leaf):
+    """Width and leaf size change only the traversal, never the result."""
+    c = _scene_c2_small(scale=0.05)
+    scene = c["scene"]
+    rng = np.random.default_rng(5)
+    O, D = _rays(rng, 4000, np.array([0, 0, 0.2]), 0.8)
+    ref = oracle.closest(oracle.OracleScene(scene), O, D)
+    bvh = ctx.build_bvh(scene, width=width, leaf_max=leaf)
+    info = bvh.info()
+    assert info["width"] == width and info["leaf_max"] == leaf
+    t, p, u, v = [x.cpu().numpy() for x in ctx.trace_rays(bvh, _t(O), _t(D))]
+    assert np.array_equal(p.view(np.uint32), ref[1])
+    assert np.array_equal(_bits(t), _bits(ref[0]))
+
+
+def test_any_hit_exact(ctx):
+    c = sg.config1()
+    scene = c["scene"]
+    rng = np.random.default_rng(9)
+    O, D = _rays(rng, 7000, np.array([0, 0, 1.5]), 2.5)
+    tmax = rng.uniform(0.05, 8.0, size=len(O)).astype(np.float32)
+    osc = oracle.OracleScene(scene)
+    t, p, _, _ = oracle.closest(osc, O, D)
+    excl = np.where(rng.uniform(size=len(O)) < 0.5, p, 0xFFFFFFFF).astype(np.uint32)
+    ref = oracle.any_hit(osc, O, D, tmax, excl)
+    bvh = ctx.build_bvh(scene)
+    occ = ctx.occluded(bvh, _t(O), _t(D), _t(tmax), _t(excl.view(np.int32))).cpu().numpy().astype(bool)
+    assert np.array_equal(occ, ref)
+
+
+def _oracle_aov(scene, cam, wl, spp=1, depth=1, seed=1, cmap=None, pixels=None):
+    return oracle.render(oracle.OracleScene(scene), cam, spp, depth, wl, seed, caustic_map=cmap, pixels=pixels,
+                         want_tie=True)
+
+
+AOV_KEYS = ("obj", "trans", "tri", "depth", "depthn", "normal", "normal_cam", "albedo")
+
+
+def _cmp_aov(g, o, mask=None):
+    for k in AOV_KEYS:
+        gv = g[k].cpu().numpy()
+        ov = o[k]
+        if k in ("obj", "tri"):
+            gv = gv.view(np.uint32)
+        if mask is not None:
+            gv, ov = gv[mask], ov[mask]
+        if gv.dtype == np.float32:
+            assert np.array_equal(_bits(gv), _bits(ov)), k
+        else:
+            assert np.array_equal(gv, ov), k
+
+
+def test_ground_truth_c1_bitexact(ctx):
+    c = sg.config1()
+    o = _oracle_aov(c["scene"], c["camera"], c["wavelengths"])
+    bvh = ctx.build_bvh(c["scene"])
+    g = ctx.render(bvh, c["camera"], 1, 1, c["wavelengths"], 1, outputs=AOV_KEYS)
+    assert o["tie"].sum() == 0
+    _cmp_aov(g, o)
+
+
+def _photon_cmp(g_map, g_cnt, o_map64, o_cnt):
+    o32 = o_map64.astype(np.float32)
+    assert np.array_equal(g_cnt.view(np.uint32), o_cnt)
+    floor = 1e-3 * float(np.abs(o_map64).max())
+    err = np.abs(g_map.astype(np.float64) - o_map64)
+    assert np.all(err <= 1e-5 * np.maximum(np.abs(o_map64), floor))
+    return o32
+
+
+def test_photons_c1(ctx):
+    c = sg.config1()
+    scene, wl = c["scene"], c["wavelengths"]
+    osc = oracle.OracleScene(scene)
+    om, msum, ocnt, ost = oracle.trace_photons(osc, c["n_photons"], c["max_depth"], wl, c["photon_seed"])
+    bvh = ctx.build_bvh(scene)
+    r = ctx.trace_photons(bvh, c["n_photons"], c["max_depth"], wl, c["photon_seed"], counts=True, stats=True)
+    _photon_cmp(r["map"].cpu().numpy(), r["count"].cpu().numpy(), msum, ocnt)
+    for k in oracle.PH_OUTCOMES:
+        assert r["stats"][k][1] == ost[k][1], k
+        assert abs(r["stats"][k][0] - ost[k][0]) <= 1e-9 * max(1.0, ost[k][0]), k
+    assert r["stats"]["segments"] == ost["segments"]
+
+
+def test_radiance_c1_same_map_bitexact(ctx):
+    """With the oracle's caustic map fed to both sides every path is traced
+    identically, so the image is bit-exact."""
+    c = sg.config1()
+    scene, wl = c["scene"], c["wavelengths"]
+    osc = oracle.OracleScene(scene)
+    om, _, _, _ = oracle.trace_photons(osc, c["n_photons"], c["max_depth"], wl, c["photon_seed"])
+    o = oracle.render(osc, c["camera"], c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=om)
+    bvh = ctx.build_bvh(scene)
+    g = ctx.render(bvh, c["camera"], c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=_t(om))
+    assert np.array_equal(_bits(g["rgb"].cpu().numpy()), _bits(o["rgb"]))
+    _cmp_aov(g, o)
+
+
+def _radiance_ok(g, o):
+    g = g.astype(np.float64)
+    o = o.astype(np.float64)
+    for ch in range(3):
+        gc, oc = g[..., ch], o[..., ch]
+        floor = 1e-3 * oc.mean()
+        ok = np.abs(gc - oc) <= 1e-4 * np.maximum(np.abs(oc), floor)
+        assert ok.mean() >= 0.999, (ch, ok.mean())
+        assert abs(gc.mean() - oc.mean()) <= 1e-5 * oc.mean(), ch
+
+
+def test_radiance_c1_own_maps(ctx):
+    """Each side gathers from its own photon map."""
+    c = sg.config1()
+    scene, wl = c["scene"], c["wavelengths"]
+    osc = oracle.OracleScene(scene)
+    om, _, _, _ = oracle.trace_photons(osc, c["n_photons"], c["max_depth"], wl, c["photon_seed"])
+    o = oracle.render(osc, c["camera"], c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=om)
+    bvh = ctx.build_bvh(scene)
+    gm = ctx.trace_photons(bvh, c["n_photons"], c["max_depth"], wl, c["photon_seed"])["map"]
+    g = ctx.render(bvh, c["camera"], c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=gm)
+    _radiance_ok(g["rgb"].cpu().numpy(), o["rgb"])
+
+
+@pytest.mark.parametrize("spp,cap", [(3, None), (5, 4096)])
+def test_radiance_c2_small_spectral(ctx, spp, cap):
+    """Spectral sampling, area light, texture, several objects; with a tiny
+    queue capacity the image is processed in many sample chunks and must
+    not change."""
+    c = _scene_c2_small()
+    scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
+    osc = oracle.OracleScene(scene)
+    n_ph = 1 << 15
+    om, msum, ocnt, _ = oracle.trace_photons(osc, n_ph, c["max_depth"], wl, c["photon_seed"])
+    o = oracle.render(osc, cam, spp, c["max_depth"], wl, c["render_seed"], caustic_map=om)
+    if cap:
+        ctx.set_option(3, cap)
+    try:
+        bvh = ctx.build_bvh(scene)
+        r = ctx.trace_photons(bvh, n_ph, c["max_depth"], wl, c["photon_seed"], counts=True)
+        _photon_cmp(r["map"].cpu().numpy(), r["count"].cpu().numpy(), msum, ocnt)
+        g = ctx.render(bvh, cam, spp, c["max_depth"], wl, c["render_seed"], caustic_map=_t(om))
+    finally:
+        ctx.set_option(3, 1 << 23)
+    assert np.array_equal(_bits(g["rgb"].cpu().numpy()), _bits(o["rgb"]))
+    _cmp_aov(g, o)
+
+
+def test_determinism(ctx):
+    c = sg.config1()
+    bvh = ctx.build_bvh(c["scene"])
+    a = ctx.trace_photons(bvh, 1 << 14, 8, c["wavelengths"], 3)["map"].cpu().numpy()
+    b = ctx.trace_photons(bvh, 1 << 14, 8, c["wavelengths"], 3)["map"].cpu().numpy()
+    assert np.array_equal(_bits(a), _bits(b))
+    g1 = ctx.render(bvh, c["camera"], 2, 8, c["wavelengths"], 5, caustic_map=torch.from_numpy(a).cuda())
+    g2 = ctx.render(bvh, c["camera"], 2, 8, c["wavelengths"], 5, caustic_map=torch.from_numpy(a).cuda())
+    assert np.array_equal(_bits(g1["rgb"].cpu().numpy()), _bits(g2["rgb"].cpu().numpy()))
+
+
+def test_single_triangle_and_degenerate(ctx):
+    """One triangle, plus degenerate and non-finite triangles that never hit."""
+    b = sg.SceneBuilder()
+    V = np.array([[-1, -1, 0], [1, -1, 0], [0, 1, 0]], np.float64)
+    b.add(sg.Mesh(V, np.array([[0, 1, 2]]), np.tile([0, 0, 1.0], (3, 1))), dict(type=sg.MAT_DIFFUSE, rho_a=0.5))
+    one = b.build(None)
+    b2 = sg.SceneBuilder()
+    b2.add(sg.Mesh(V, np.array([[0, 1, 2]]), np.tile([0, 0, 1.0], (3, 1))), dict(type=sg.MAT_DIFFUSE, rho_a=0.5))
+    Vd = np.array([[0, 0, 0.5], [0, 0, 0.5], [0.1, 0, 0.5], [np.nan, 0, 1], [0, 1, 1], [1, 0, 1]], np.float64)
+    b2.add(sg.Mesh(Vd, np.array([[0, 1, 2], [3, 4, 5]]), np.tile([0, 0, 1.0], (6, 1))),
+           dict(type=sg.MAT_DIFFUSE, rho_a=0.5))
+    bad = b2.build(None)
+    rng = np.random.default_rng(1)
+    O = np.tile(np.array([0, 0, 3], np.float32), (500, 1))
+    D = np.concatenate([rng.uniform(-0.3, 0.3, size=(500, 2)), -np.ones((500, 1))], 1)
+    D = (D / np.linalg.norm(D, axis=1, keepdims=True)).astype(np.float32)
+    for scene in (one, bad):
+        ref = oracle.closest(oracle.OracleScene(scene), O, D)
+        bvh = ctx.build_bvh(scene)
+        t, p, u, v = [x.cpu().numpy() for x in ctx.trace_rays(bvh, _t(O), _t(D))]
+        assert np.array_equal(p.view(np.uint32), ref[1])
+        assert np.array_equal(_bits(t), _bits(ref[0]))
+        assert (ref[1] != 0xFFFFFFFF).sum() > 100
+
+
+def test_invalid_arguments_raise(ctx):
+    import paper_2107_11008_amd as sc
+    c = sg.config1()
+    bvh = ctx.build_bvh(c["scene"])
+    with pytest.raises(sc.ScError):
+        ctx.render(bvh, c["camera"], 0, 8, c["wavelengths"], 1)
+    with pytest.raises(sc.ScError):
+        ctx.render(bvh, c["camera"], 1, 0, c["wavelengths"], 1)
+    bad = sg.Wavelengths(sg.WL_FIXED, 2, (500.0, 600.0))
+    with pytest.raises(sc.ScError):
+        ctx.render(bvh, c["camera"], 1, 1, bad, 1)
+    s = c["scene"]
+    s2 = sg.Scene(V=s.V, I=s.I, VN=s.VN, tri_obj=np.full_like(s.tri_obj, 9), materials=s.materials,
+                  point_lights=s.point_lights, targets_obj=s.targets_obj, targets_sphere=s.targets_sphere,
+                  receiver=s.receiver)
+    with pytest.raises(sc.ScError):
+        ctx.build_bvh(s2)
+
+
+def test_c2_full_size_sampled_pixels(ctx):
+    """The full 512x512, 16 spp medium scene in the launch configuration the
+    benchmark times, checked on a seeded sample of pixels the oracle
+    renders one by one (gathering from the same caustic map)."""
+    c = sg.config2()
+    scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
+    bvh = ctx.build_bvh(scene)
+    gm = ctx.trace_photons(bvh, c["n_photons"], c["max_depth"], wl, c["photon_seed"])["map"]
+    g = ctx.render(bvh, cam, c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=gm)
+    rng = np.random.default_rng(11)
+    pix = np.sort(rng.choice(cam.w * cam.h, size=96, replace=False)).astype(np.uint32)
+    osc = oracle.OracleScene(scene)
+    o = oracle.render(osc, cam, c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=gm.cpu().numpy(),
+                      pixels=pix)
+    m = np.zeros(cam.w * cam.h, bool)
+    m[pix] = True
+    m = m.reshape(cam.h, cam.w)
+    assert np.array_equal(_bits(g["rgb"].cpu().numpy()[m]), _bits(o["rgb"][m]))
+    _cmp_aov(g, o, mask=m)
+    # full-size ground truth: every pixel
+    ogt = oracle.render(osc, cam, 1, 1, wl, 1, pixels=np.arange(0, cam.w * cam.h, 7, dtype=np.uint32))
+    m2 = np.zeros(cam.w * cam.h, bool)
+    m2[::7] = True
+    _cmp_aov(g, ogt, mask=m2.reshape(cam.h, cam.w))
