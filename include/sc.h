@@ -210,6 +210,15 @@ sc_status sc_reset_counters(sc_ctx* ctx);
 sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* scene, const sc_bvh_opts* opts, sc_bvh** out);
 sc_status sc_bvh_get_info(const sc_bvh* bvh, sc_bvh_info* out);
 sc_status sc_bvh_free(sc_bvh* bvh);
+/* Copy the built structure to host memory for inspection (synchronises):
+ * nodes_host receives node_bytes bytes (256-byte nodes: child boxes as
+ * lo_x[8], hi_x[8], lo_y[8], hi_y[8], lo_z[8], hi_z[8], then child[8];
+ * child 0xffffffff = empty, bit 31 set = leaf of (bits 28..30) + 1
+ * triangles starting at bits 0..27, else a node index); tris_host receives
+ * tri_bytes bytes (per leaf-ordered triangle three float4: vertex 0 with
+ * the triangle index in .w as bits, vertex 1, vertex 2).  Either may be
+ * NULL. */
+sc_status sc_bvh_export(const sc_bvh* bvh, void* nodes_host, void* tris_host);
 
 /* Closest hit of n rays (device O, D: [n][3], D unit length): the
  * lexicographic minimum of (t, triangle index) over all triangles with

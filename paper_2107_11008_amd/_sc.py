@@ -79,11 +79,14 @@ class Counters(C.Structure):
                 ("closest_rays_timed", C.c_uint64)]
 
 
+NODE_DTYPE = np.dtype([("lox", "<f4", 8), ("hix", "<f4", 8), ("loy", "<f4", 8), ("hiy", "<f4", 8),
+                       ("loz", "<f4", 8), ("hiz", "<f4", 8), ("child", "<u4", 8), ("pad", "<u4", 8)])
+
 PH_OUTCOMES = ("deposited", "outside", "direct", "elsewhere", "escaped", "absorbed", "truncated", "lost",
                "emit_dead")
 
 EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set_stream", "sc_set_option",
-           "sc_sync", "sc_get_counters", "sc_reset_counters", "sc_build_bvh", "sc_bvh_get_info", "sc_bvh_free",
+           "sc_sync", "sc_get_counters", "sc_reset_counters", "sc_build_bvh", "sc_bvh_get_info", "sc_bvh_free", "sc_bvh_export",
            "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render"]
 
 
@@ -108,6 +111,7 @@ def load(path: str = LIB_PATH):
     L.sc_build_bvh.argtypes = [vp, C.POINTER(Scene), C.POINTER(BvhOpts), C.POINTER(vp)]
     L.sc_bvh_get_info.argtypes = [vp, C.POINTER(BvhInfo)]
     L.sc_bvh_free.argtypes = [vp]
+    L.sc_bvh_export.argtypes = [vp, vp, vp]
     L.sc_trace_rays.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp]
     L.sc_occluded.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
     L.sc_trace_photons.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, vp, vp, C.POINTER(PhotonStats)]
@@ -297,6 +301,15 @@ class Bvh:
         i = BvhInfo()
         _check(load().sc_bvh_get_info(self.h, C.byref(i)), "sc_bvh_get_info")
         return {k: getattr(i, k) for k, _ in BvhInfo._fields_}
+
+    def export(self):
+        """Host copies of the wide nodes (structured array) and the
+        leaf-ordered triangles ([nt, 3, 4] float32, index bits in [:, 0, 3])."""
+        inf = self.info()
+        nodes = np.zeros(inf["n_nodes"], dtype=NODE_DTYPE)
+        tris = np.zeros((self.scene.nt, 3, 4), dtype=np.float32)
+        _check(load().sc_bvh_export(self.h, nodes.ctypes.data, tris.ctypes.data), "sc_bvh_export")
+        return nodes, tris
 
     def close(self):
         if getattr(self, "h", None):

@@ -270,6 +270,15 @@ sc_status sc_bvh_get_info(const sc_bvh* bvh, sc_bvh_info* out) {
     return SC_OK;
 }
 
+sc_status sc_bvh_export(const sc_bvh* bvh, void* nodes_host, void* tris_host) {
+    if (!bvh) return set_error(SC_EINVAL, "bvh is NULL");
+    const scl::Bvh& b = bvh->b;
+    SC_HIP(hipStreamSynchronize(b.ctx->stream));
+    if (nodes_host) SC_HIP(hipMemcpy(nodes_host, b.nodes.p, sizeof(BNode) * (size_t)b.n_nodes, hipMemcpyDeviceToHost));
+    if (tris_host) SC_HIP(hipMemcpy(tris_host, b.tris.p, 48 * (size_t)b.scene.nt, hipMemcpyDeviceToHost));
+    return SC_OK;
+}
+
 sc_status sc_bvh_free(sc_bvh* bvh) {
     if (!bvh) return set_error(SC_EINVAL, "bvh is NULL");
     (void)hipStreamSynchronize(bvh->b.ctx->stream);

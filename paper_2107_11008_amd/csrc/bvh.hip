@@ -14,6 +14,7 @@
 #pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "sc_internal.h"
 
@@ -321,11 +322,25 @@ inline uint32_t grid_for(size_t n, uint32_t bs, uint32_t cap = 65536) {
 
 namespace scl {
 
+static bool debug_sync() {
+    static const bool on = getenv("SC_DEBUG_SYNC") != nullptr;
+    return on;
+}
+
+#define SC_LAUNCH(...)                                                                   \
+    do {                                                                                 \
+        hipLaunchKernelGGL(__VA_ARGS__);                                                 \
+        hipError_t _le = hipGetLastError();                                              \
+        if (_le == hipSuccess && debug_sync()) _le = hipStreamSynchronize(st);           \
+        if (_le != hipSuccess)                                                           \
+            return set_error(SC_EDEVICE, std::string("launch failed: ") + hipGetErrorString(_le)); \
+    } while (0)
+
 // Builds nodes/tris into the handle.  Returns SC_OK or an error code with
 // the message set.
 sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
     hipStream_t st = ctx->stream;
-    const uint32_t n = b->scene.nt;
+    const uint32_t n = b->scene_in.nt;
     uint32_t n_pad = 1;
     while (n_pad < n) n_pad <<= 1;
     if (n_pad < (uint32_t)kLocal) n_pad = kLocal;
@@ -347,8 +362,8 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
     SC_TRY(counters.alloc(sizeof(uint32_t) * 4));
 
     const uint32_t bs = 256;
-    hipLaunchKernelGGL(k_init_u32, dim3(1), dim3(64), 0, st, err_d.as<uint32_t>(), 1u, 0u);
-    hipLaunchKernelGGL(k_validate, dim3(grid_for(n, bs)), dim3(bs), 0, st, b->scene_in.I, b->scene_in.tri_obj, n,
+    SC_LAUNCH(k_init_u32, dim3(1), dim3(64), 0, st, err_d.as<uint32_t>(), 1u, 0u);
+    SC_LAUNCH(k_validate, dim3(grid_for(n, bs)), dim3(bs), 0, st, b->scene_in.I, b->scene_in.tri_obj, n,
                        b->scene_in.nv, b->scene_in.n_mat, err_d.as<uint32_t>());
     uint32_t err_h = 0;
     SC_HIP(hipMemcpyAsync(&err_h, err_d.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -358,29 +373,29 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
 
     uint32_t cb_init[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
     SC_HIP(hipMemcpyAsync(cb.p, cb_init, sizeof(cb_init), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_tri_bounds, dim3(grid_for(n, bs, 4096)), dim3(bs), 0, st, b->scene_in.V, b->scene_in.I, n,
+    SC_LAUNCH(k_tri_bounds, dim3(grid_for(n, bs, 4096)), dim3(bs), 0, st, b->scene_in.V, b->scene_in.I, n,
                        bounds.as<float>(), cb.as<uint32_t>());
-    hipLaunchKernelGGL(k_morton, dim3(grid_for(n_pad, bs)), dim3(bs), 0, st, bounds.as<float>(), n, n_pad,
+    SC_LAUNCH(k_morton, dim3(grid_for(n_pad, bs)), dim3(bs), 0, st, bounds.as<float>(), n, n_pad,
                        cb.as<uint32_t>(), keys.as<unsigned long long>());
     // bitonic sort
     const uint32_t nblk = n_pad / kLocal;
-    hipLaunchKernelGGL(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys.as<unsigned long long>(), 2u,
+    SC_LAUNCH(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys.as<unsigned long long>(), 2u,
                        (uint32_t)kLocal);
     for (uint32_t k = 2 * kLocal; k <= n_pad; k <<= 1) {
         for (uint32_t j = k >> 1; j >= (uint32_t)kLocal; j >>= 1)
-            hipLaunchKernelGGL(k_bitonic_global, dim3(grid_for(n_pad / 2, bs)), dim3(bs), 0, st,
+            SC_LAUNCH(k_bitonic_global, dim3(grid_for(n_pad / 2, bs)), dim3(bs), 0, st,
                                keys.as<unsigned long long>(), n_pad, k, j);
-        hipLaunchKernelGGL(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys.as<unsigned long long>(), k, k);
+        SC_LAUNCH(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys.as<unsigned long long>(), k, k);
     }
     // radix tree + bounds
-    hipLaunchKernelGGL(k_init_i32, dim3(grid_for(2 * n, bs)), dim3(bs), 0, st, parent.as<int32_t>(), 2 * n, -1);
+    SC_LAUNCH(k_init_i32, dim3(grid_for(2 * n, bs)), dim3(bs), 0, st, parent.as<int32_t>(), 2 * n, -1);
     if (n > 1) {
-        hipLaunchKernelGGL(k_init_u32, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, flags.as<uint32_t>(), n - 1, 0u);
-        hipLaunchKernelGGL(k_radix_tree, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(), n,
+        SC_LAUNCH(k_init_u32, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, flags.as<uint32_t>(), n - 1, 0u);
+        SC_LAUNCH(k_radix_tree, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(), n,
                            left.as<int32_t>(), right.as<int32_t>(), parent.as<int32_t>(), rlo.as<uint32_t>(),
                            rhi.as<uint32_t>());
     }
-    hipLaunchKernelGGL(k_refit, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(),
+    SC_LAUNCH(k_refit, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(),
                        bounds.as<float>(), n, left.as<int32_t>(), right.as<int32_t>(), parent.as<int32_t>(),
                        nb.as<float>(), flags.as<uint32_t>());
 
@@ -401,7 +416,7 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
     while (cur_count > 0) {
         uint32_t zero = 0;
         SC_HIP(hipMemcpyAsync(counters.as<uint32_t>() + 1, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_collapse, dim3(grid_for(cur_count, 128)), dim3(128), 0, st, n, left.as<int32_t>(),
+        SC_LAUNCH(k_collapse, dim3(grid_for(cur_count, 128)), dim3(128), 0, st, n, left.as<int32_t>(),
                            right.as<int32_t>(), rlo.as<uint32_t>(), rhi.as<uint32_t>(), nb.as<float>(), leaf_max,
                            width, wa->as<uint2>(), counters.as<uint32_t>(), wb->as<uint2>(),
                            counters.as<uint32_t>() + 1, counters.as<uint32_t>() + 2, nodes_tmp.as<BNode>());
@@ -423,7 +438,7 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
     SC_TRY(b->nodes.alloc(sizeof(BNode) * (size_t)n_nodes));
     SC_HIP(hipMemcpyAsync(b->nodes.p, nodes_tmp.p, sizeof(BNode) * (size_t)n_nodes, hipMemcpyDeviceToDevice, st));
     SC_TRY(b->tris.alloc(sizeof(float4) * 3 * (size_t)n));
-    hipLaunchKernelGGL(k_gather_tris, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(), n,
+    SC_LAUNCH(k_gather_tris, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(), n,
                        b->scene_in.V, b->scene_in.I, b->tris.as<float4>());
     SC_HIP(hipGetLastError());
     SC_HIP(hipStreamSynchronize(st));

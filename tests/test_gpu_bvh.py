@@ -1,0 +1,70 @@
+"""Structural invariants of the GPU-built wide BVH: every triangle sits in
+exactly one leaf, leaf triangles are the scene's own vertices, and every
+child box contains everything below it."""
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_tree(scene, nodes, tris, width, leaf_max):
+    nt = scene.nt
+    prim = tris[:, 0, 3].view(np.uint32)
+    assert np.array_equal(np.sort(prim), np.arange(nt, dtype=np.uint32))
+    V = scene.V[scene.I[prim]]                       # [nt,3,3] in leaf order
+    assert np.array_equal(tris[:, :, :3], V)
+    seen = np.zeros(nt, np.int64)
+    stack = [(0, None)]
+    visited = 0
+    while stack:
+        idx, box = stack.pop()
+        nd = nodes[idx]
+        visited += 1
+        nch = 0
+        for c in range(8):
+            ch = int(nd["child"][c])
+            if ch == 0xFFFFFFFF:
+                assert nd["lox"][c] == np.inf and nd["hix"][c] == -np.inf
+                continue
+            nch += 1
+            lo = np.array([nd["lox"][c], nd["loy"][c], nd["loz"][c]])
+            hi = np.array([nd["hix"][c], nd["hiy"][c], nd["hiz"][c]])
+            if box is not None:
+                assert np.all(lo >= box[0]) and np.all(hi <= box[1])
+            if ch & 0x80000000:
+                first = ch & 0x0FFFFFFF
+                cnt = ((ch >> 28) & 7) + 1
+                assert cnt <= leaf_max
+                seg = tris[first:first + cnt, :, :3].reshape(-1, 3)
+                assert np.all(seg >= lo) and np.all(seg <= hi)
+                seen[first:first + cnt] += 1
+            else:
+                assert ch < len(nodes)
+                stack.append((ch, (lo, hi)))
+        assert nch <= width
+    assert np.all(seen == 1)
+    assert visited == len(nodes)
+
+
+@pytest.mark.parametrize("which,width,leaf", [("c1", 8, 4), ("c1", 4, 1), ("c2s", 8, 4), ("c2s", 4, 8),
+                                              ("one", 8, 4), ("two", 8, 1)])
+def test_bvh_structure(which, width, leaf):
+    import paper_2107_11008_amd as sc
+    ctx = sc.Context(0)
+    if which == "c1":
+        scene = sg.config1()["scene"]
+    elif which == "c2s":
+        scene = sg.config2(tri_scale=0.05, w=32, h=32)["scene"]
+    else:
+        b = sg.SceneBuilder()
+        V = np.array([[-1, -1, 0], [1, -1, 0], [0, 1, 0], [0, 0, 1]], np.float64)
+        I = np.array([[0, 1, 2]]) if which == "one" else np.array([[0, 1, 2], [0, 1, 3]])
+        b.add(sg.Mesh(V, I, np.tile([0, 0, 1.0], (4, 1))), dict(type=sg.MAT_DIFFUSE, rho_a=0.5))
+        scene = b.build(None)
+    bvh = ctx.build_bvh(scene, width=width, leaf_max=leaf)
+    nodes, tris = bvh.export()
+    info = bvh.info()
+    assert info["max_stack"] == (width - 1) * info["depth"] + 1
+    _check_tree(scene, nodes, tris, width, leaf)
