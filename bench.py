@@ -1,0 +1,221 @@
+"""Benchmark of the rendering hot path on one MI355X.
+
+One step = the whole path over the medium workload (512x512, 16 spp
+spectral 380-720 nm, depth 12, 2^22 caustic photons, eight glass objects of
+~198k triangles on a textured plane with an area light): GPU BVH build,
+photon pass into the caustic map, ground-truth pass (pixel-centre rays)
+and the spectral path-traced image gathering the caustic map.
+
+value = traced ray segments per second over the timed steps (camera and
+ground-truth closest hits + shadow any hits + photon closest hits), in
+Mrays/s.  The JSON line also carries the roofline of the dominant kernel
+(closest-hit traversal, bound by HBM bandwidth; algorithmic bytes per ray
+= 24 B ray + 4 B queue entry + 16 B hit + node visits x 256 B + triangle
+tests x 48 B, the visit counts taken from a counting pass of the same
+kernel) and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s; 1080p frames/s at relMSE≤0.01 vs 1024spp, denoised vs plain"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_closest_c2_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2107_11008_amd", "csrc", "trace.hip")
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    for f in ("trace.hip", "sc_device.h", "sc_kernels.h", "sc_types.h"):
+        with open(os.path.join(ROOT, "paper_2107_11008_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_per_launch():
+    """HBM bytes per closest-hit launch from the committed rocprofv3 counter
+    summary, or None when absent or taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != _src_hash():
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(cfg, rays_per_step, step_s):
+    """The oracle (single-threaded C) on a bounded sample of the workload:
+    every 2nd pixel of every 2nd row (1/4 of the pixels) at full spp and
+    depth, and the first 1/8 of the photons (about 10 s of one core)."""
+    import numpy as np
+
+    import oracle
+    scene, wl, cam = cfg["scene"], cfg["wavelengths"], cfg["camera"]
+    t0 = time.perf_counter()
+    osc = oracle.OracleScene(scene)
+    t_bvh = time.perf_counter() - t0
+    n_ph = cfg["n_photons"]
+    p1 = n_ph // 8
+    t0 = time.perf_counter()
+    m, msum, cnt, st = oracle.trace_photons(osc, n_ph, cfg["max_depth"], wl, cfg["photon_seed"], p0=0, p1=p1)
+    t_ph = time.perf_counter() - t0
+    ys, xs = np.meshgrid(np.arange(0, cam.h, 2), np.arange(0, cam.w, 2), indexing="ij")
+    pix = (ys * cam.w + xs).ravel().astype(np.uint32)
+    t0 = time.perf_counter()
+    out = oracle.render(osc, cam, cfg["spp"], cfg["max_depth"], wl, cfg["render_seed"], caustic_map=m, pixels=pix)
+    t_r = time.perf_counter() - t0
+    rays = st["segments"] + out["segments"]
+    secs = t_ph + t_r
+    return {"value": round(rays / secs / 1e6, 4), "unit": "Mrays/s", "cores": 1, "kind": "oracle",
+            "sample": f"1/4 of the pixels (every 2nd row and column, {len(pix)} px at {cfg['spp']} spp) and "
+                      f"photons [0, {p1}) of {n_ph}; {rays} ray segments in {secs:.2f} s (oracle BVH build "
+                      f"{t_bvh:.2f} s not counted); full step would take ~{rays_per_step / (rays / secs):.0f} s "
+                      f"on one core vs {step_s * 1e3:.1f} ms on the GPU"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration for rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU sharding is described in the design notes, not run)"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2107_11008_amd as sc
+    import scenegen as sg
+
+    cfg = sg.config2()
+    scene, wl, cam = cfg["scene"], cfg["wavelengths"], cfg["camera"]
+    ctx = sc.Context(0)
+    stream = torch.cuda.current_stream()
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    outs = {}
+
+    def step():
+        bvh = ctx.build_bvh(scene)
+        ph = ctx.trace_photons(bvh, cfg["n_photons"], cfg["max_depth"], wl, cfg["photon_seed"],
+                               out=outs.get("map"))
+        outs["map"] = ph["map"]
+        r = ctx.render(bvh, cam, cfg["spp"], cfg["max_depth"], wl, cfg["render_seed"], caustic_map=ph["map"],
+                       out=outs.get("img"))
+        outs["img"] = r
+        return bvh
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # visit counts of the traversal kernel (same kernel, counting variant), untimed
+    ctx.reset_counters()
+    ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 1)
+    bvh = step()
+    cnt = ctx.counters()
+    ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 0)
+    nodes_per_ray = cnt["node_visits"] / cnt["rays_closest"]
+    tris_per_ray = cnt["tri_tests"] / cnt["rays_closest"]
+    rays_per_step = cnt["rays_closest"] + cnt["rays_shadow"]
+    info = bvh.info()
+    del bvh
+
+    # timed region
+    ctx.reset_counters()
+    ctx.set_option(sc._sc.SC_OPT_PROFILE, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c = ctx.counters()
+    ctx.set_option(sc._sc.SC_OPT_PROFILE, 0)
+
+    secs = t1 - t0
+    rays = c["rays_closest"] + c["rays_shadow"]
+    value = rays / secs / 1e6
+    bytes_per_ray = 24 + 4 + 16 + nodes_per_ray * 256 + tris_per_ray * 48
+    launches = c["closest_launches"]
+    avg_ms = c["closest_ms"] / max(launches, 1)
+    alg_bytes_per_launch = bytes_per_ray * c["rays_closest"] / max(launches, 1)
+    achieved = alg_bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic_per_launch()
+
+    # breakdown of one step (separately, untimed for the headline)
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    bvh = ctx.build_bvh(scene)
+    torch.cuda.synchronize()
+    tb1 = time.perf_counter()
+    ph = ctx.trace_photons(bvh, cfg["n_photons"], cfg["max_depth"], wl, cfg["photon_seed"], out=outs["map"])
+    torch.cuda.synchronize()
+    tb2 = time.perf_counter()
+    ctx.render(bvh, cam, cfg["spp"], cfg["max_depth"], wl, cfg["render_seed"], caustic_map=ph["map"],
+               out=outs["img"])
+    torch.cuda.synchronize()
+    tb3 = time.perf_counter()
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(secs / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "medium glass scene: 512x512, 16 spp, wavelengths uniform 380-720 nm, max depth 12, "
+                               "2^22 caustic photons into a 1024x1024x16 map, 8 procedural glass objects "
+                               f"({scene.nt} triangles) on a textured plane, one area light; step = BVH build + "
+                               "photon pass + ground truth + image",
+                   "triangles": scene.nt, "width": cam.w, "height": cam.h, "spp": cfg["spp"],
+                   "max_depth": cfg["max_depth"], "photons": cfg["n_photons"]},
+        "rays_per_step": rays_per_step,
+        "breakdown_ms": {"bvh_build": round((tb1 - tb0) * 1e3, 3), "photons": round((tb2 - tb1) * 1e3, 3),
+                         "render": round((tb3 - tb2) * 1e3, 3)},
+        "bvh": {"nodes": info["n_nodes"], "depth": info["depth"], "node_bytes": info["node_bytes"],
+                "tri_bytes": info["tri_bytes"]},
+        "roofline": {"bound": "hbm", "kernel": "k_closest (closest-hit traversal)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "avg_launch_ms": round(avg_ms, 5), "launches": launches,
+                     "alg_bytes_per_launch": round(alg_bytes_per_launch),
+                     "bytes_per_ray": round(bytes_per_ray, 1), "nodes_per_ray": round(nodes_per_ray, 3),
+                     "tris_per_ray": round(tris_per_ray, 3),
+                     "kernel_Mrays_s": round(c["rays_closest"] / (c["closest_ms"] * 1e-3) / 1e6, 1)},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, rays_per_step, secs / args.steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
