@@ -252,6 +252,51 @@ sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, u
 sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
                     const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, const sc_aov* out);
 
+/* ------------------------------------------------------------------
+ * Learned denoiser.  A U-Net (the network family the paper trains for
+ * segmentation, Sec. IV-A-3; Ronneberger et al. 2015) maps a low-sample
+ * render and its ground-truth buffers to a clean image.  Per level two 3x3
+ * convolutions with ReLU; 2x2 max pooling down, nearest 2x upsampling and
+ * skip concatenation up; a 1x1 output convolution predicting log(1 + rgb).
+ * Input features per pixel (9): log(1+rgb) x3, albedo, world normal x3,
+ * normalised depth, transparent bit.  Weights and activations are bfloat16
+ * on the matrix cores with float accumulation; float master weights are
+ * updated by Adam (beta 0.9/0.999, eps 1e-8); loss = mean |pred -
+ * log(1 + target)|.
+ *
+ * Parameters are a float vector: layer by layer (encoder levels shallow to
+ * deep, decoder levels deep to shallow, output layer), weights as
+ * [cout][ky][kx][cin] followed by the biases.
+ * ------------------------------------------------------------------ */
+typedef struct sc_unet sc_unet;
+
+/* widths[levels] channels per level, multiples of 16 (<= 256), 2 <= levels
+ * <= 6; parameters start at zero (set them with sc_unet_set_params). */
+sc_status sc_unet_create(sc_ctx* ctx, const uint32_t* widths, uint32_t levels, sc_unet** out);
+sc_status sc_unet_free(sc_unet* net);
+sc_status sc_unet_num_params(const sc_unet* net, uint64_t* n);
+/* host float[n_params] in and out; set resets the Adam moments and step. */
+sc_status sc_unet_set_params(sc_unet* net, const float* host_params);
+sc_status sc_unet_get_params(sc_unet* net, float* host_params);
+/* Forward pass of n images: device feat [n][h][w][9] f32 -> device pred
+ * [n][h][w][3] f32 (log domain).  h and w must be multiples of
+ * 2^(levels-1).  Keeps the activations for sc_unet_backward. */
+sc_status sc_unet_forward(sc_ctx* ctx, sc_unet* net, const float* feat, uint32_t n, uint32_t w, uint32_t h,
+                          float* pred);
+/* Gradient of a loss w.r.t. all parameters, given device dpred [n][h][w][3]
+ * (the loss gradient w.r.t. the last sc_unet_forward's prediction);
+ * writes device grad f32 [n_params]. */
+sc_status sc_unet_backward(sc_ctx* ctx, sc_unet* net, const float* dpred, float* grad);
+/* One Adam step on the L1-log loss of n images: device feat [n][h][w][9],
+ * device target [n][h][w][3] linear rgb.  loss (host, may be NULL; then
+ * the call does not synchronise) receives the loss before the update. */
+sc_status sc_unet_train_step(sc_ctx* ctx, sc_unet* net, const float* feat, const float* target, uint32_t n,
+                             uint32_t w, uint32_t h, float lr, float* loss);
+/* Denoise a render: in->rgb, albedo, normal, depthn, trans (device, as
+ * written by sc_render; albedo/normal/depthn/trans may be NULL) of size
+ * w x h -> device out_rgb [h][w][3] linear rgb.  Any w, h (padded inside). */
+sc_status sc_denoise(sc_ctx* ctx, sc_unet* net, const sc_aov* in, uint32_t w, uint32_t h, float* out_rgb);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,7 +87,9 @@ PH_OUTCOMES = ("deposited", "outside", "direct", "elsewhere", "escaped", "absorb
 
 EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set_stream", "sc_set_option",
            "sc_sync", "sc_get_counters", "sc_reset_counters", "sc_build_bvh", "sc_bvh_get_info", "sc_bvh_free", "sc_bvh_export",
-           "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render"]
+           "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render",
+           "sc_unet_create", "sc_unet_free", "sc_unet_num_params", "sc_unet_set_params", "sc_unet_get_params",
+           "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise"]
 
 
 def load(path: str = LIB_PATH):
@@ -116,6 +118,15 @@ def load(path: str = LIB_PATH):
     L.sc_occluded.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
     L.sc_trace_photons.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, vp, vp, C.POINTER(PhotonStats)]
     L.sc_render.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, C.POINTER(Aov)]
+    L.sc_unet_create.argtypes = [vp, vp, u32, C.POINTER(vp)]
+    L.sc_unet_free.argtypes = [vp]
+    L.sc_unet_num_params.argtypes = [vp, C.POINTER(u64)]
+    L.sc_unet_set_params.argtypes = [vp, vp]
+    L.sc_unet_get_params.argtypes = [vp, vp]
+    L.sc_unet_forward.argtypes = [vp, vp, vp, u32, u32, u32, vp]
+    L.sc_unet_backward.argtypes = [vp, vp, vp, vp]
+    L.sc_unet_train_step.argtypes = [vp, vp, vp, vp, u32, u32, u32, C.c_float, C.POINTER(C.c_float)]
+    L.sc_denoise.argtypes = [vp, vp, C.POINTER(Aov), u32, u32, vp]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("sc_abi_version", "sc_last_error"):
@@ -314,6 +325,73 @@ class Bvh:
     def close(self):
         if getattr(self, "h", None):
             load().sc_bvh_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class UNet:
+    """The denoiser network on the device (sc_unet_*)."""
+
+    def __init__(self, ctx: Context, widths=(32, 48, 64, 96, 128), params: Optional[np.ndarray] = None):
+        self.ctx = ctx
+        self.widths = tuple(int(w) for w in widths)
+        arr = (C.c_uint32 * len(self.widths))(*self.widths)
+        h = C.c_void_p()
+        _check(load().sc_unet_create(ctx.h, arr, len(self.widths), C.byref(h)), "sc_unet_create")
+        self.h = h
+        n = C.c_uint64()
+        _check(load().sc_unet_num_params(self.h, C.byref(n)), "sc_unet_num_params")
+        self.n_params = n.value
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_params
+        _check(load().sc_unet_set_params(self.h, p.ctypes.data), "sc_unet_set_params")
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.n_params, np.float32)
+        _check(load().sc_unet_get_params(self.h, p.ctypes.data), "sc_unet_get_params")
+        return p
+
+    def forward(self, feat: torch.Tensor) -> torch.Tensor:
+        n, h, w, c = feat.shape
+        assert c == 9
+        pred = torch.empty((n, h, w, 3), dtype=torch.float32, device=self.ctx.device)
+        _check(load().sc_unet_forward(self.ctx.h, self.h, _ptr(feat), n, w, h, _ptr(pred)), "sc_unet_forward")
+        return pred
+
+    def backward(self, dpred: torch.Tensor) -> torch.Tensor:
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self.ctx.device)
+        _check(load().sc_unet_backward(self.ctx.h, self.h, _ptr(dpred), _ptr(g)), "sc_unet_backward")
+        return g
+
+    def train_step(self, feat: torch.Tensor, target: torch.Tensor, lr: float, want_loss: bool = True):
+        n, h, w, _ = feat.shape
+        loss = C.c_float()
+        _check(load().sc_unet_train_step(self.ctx.h, self.h, _ptr(feat), _ptr(target), n, w, h, float(lr),
+                                         C.byref(loss) if want_loss else None), "sc_unet_train_step")
+        return loss.value if want_loss else None
+
+    def denoise(self, aov: dict, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        h, w = aov["rgb"].shape[:2]
+        a = Aov()
+        for k in ("rgb", "albedo", "normal", "depthn", "trans"):
+            if k in aov and aov[k] is not None:
+                setattr(a, k, _ptr(aov[k]))
+        o = out if out is not None else torch.empty((h, w, 3), dtype=torch.float32, device=self.ctx.device)
+        _check(load().sc_denoise(self.ctx.h, self.h, C.byref(a), w, h, _ptr(o)), "sc_denoise")
+        return o
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().sc_unet_free(self.h)
             self.h = None
 
     def __del__(self):

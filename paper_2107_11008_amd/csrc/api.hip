@@ -13,12 +13,16 @@
 
 #include "sc_internal.h"
 #include "sc_kernels.h"
+#include "sc_unet.h"
 
 struct sc_ctx {
     scl::Ctx c;
 };
 struct sc_bvh {
     scl::Bvh b;
+};
+struct sc_unet {
+    scl::Unet u;
 };
 
 namespace scl {
@@ -325,6 +329,119 @@ sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32
     if ((uint64_t)cam->w * cam->h > (1ull << 28)) return set_error(SC_EUNSUPPORTED, "image too large");
     if (caustic_map && !bvh->b.scene.recv_obj) return set_error(SC_EINVAL, "caustic map given but no receiver");
     return scl::render(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), *cam, spp, max_depth, *wl, seed, caustic_map, *out);
+}
+
+sc_status sc_unet_create(sc_ctx* ctx, const uint32_t* widths, uint32_t levels, sc_unet** out) {
+    if (!ctx || !widths || !out) return set_error(SC_EINVAL, "ctx, widths or out is NULL");
+    *out = nullptr;
+    sc_unet* n = new (std::nothrow) sc_unet();
+    if (!n) return set_error(SC_ENOMEM, "host allocation failed");
+    sc_status s = scl::unet_create(&ctx->c, widths, levels, &n->u);
+    if (s == SC_OK && hipStreamSynchronize(ctx->c.stream) != hipSuccess) s = set_error(SC_EDEVICE, "init failed");
+    if (s != SC_OK) {
+        delete n;
+        return s;
+    }
+    *out = n;
+    return SC_OK;
+}
+
+sc_status sc_unet_free(sc_unet* net) {
+    if (!net) return set_error(SC_EINVAL, "net is NULL");
+    (void)hipStreamSynchronize(net->u.ctx->stream);
+    delete net;
+    return SC_OK;
+}
+
+sc_status sc_unet_num_params(const sc_unet* net, uint64_t* n) {
+    if (!net || !n) return set_error(SC_EINVAL, "net or n is NULL");
+    *n = net->u.n_params;
+    return SC_OK;
+}
+
+sc_status sc_unet_set_params(sc_unet* net, const float* host) {
+    if (!net || !host) return set_error(SC_EINVAL, "net or params is NULL");
+    scl::Unet& u = net->u;
+    SC_HIP(hipStreamSynchronize(u.ctx->stream));
+    SC_HIP(hipMemcpy(u.theta.p, host, 4 * u.n_params, hipMemcpyHostToDevice));
+    SC_HIP(hipMemset(u.m.p, 0, 4 * u.n_params));
+    SC_HIP(hipMemset(u.v.p, 0, 4 * u.n_params));
+    u.step = 0;
+    SC_TRY(scl::unet_refresh(&u));
+    SC_HIP(hipStreamSynchronize(u.ctx->stream));
+    return SC_OK;
+}
+
+sc_status sc_unet_get_params(sc_unet* net, float* host) {
+    if (!net || !host) return set_error(SC_EINVAL, "net or params is NULL");
+    SC_HIP(hipStreamSynchronize(net->u.ctx->stream));
+    SC_HIP(hipMemcpy(host, net->u.theta.p, 4 * net->u.n_params, hipMemcpyDeviceToHost));
+    return SC_OK;
+}
+
+static sc_status check_shape(const scl::Unet& u, uint32_t n, uint32_t w, uint32_t h) {
+    const uint32_t m = 1u << (u.widths.size() - 1);
+    if (n == 0 || w == 0 || h == 0) return set_error(SC_EINVAL, "empty batch");
+    if (w % m || h % m) return set_error(SC_EINVAL, "w and h must be multiples of 2^(levels-1)");
+    if ((uint64_t)n * w * h > (1ull << 28)) return set_error(SC_EUNSUPPORTED, "batch too large");
+    return SC_OK;
+}
+
+sc_status sc_unet_forward(sc_ctx* ctx, sc_unet* net, const float* feat, uint32_t n, uint32_t w, uint32_t h,
+                          float* pred) {
+    if (!ctx || !net || !feat || !pred) return set_error(SC_EINVAL, "NULL argument");
+    scl::Unet& u = net->u;
+    SC_TRY(check_shape(u, n, w, h));
+    SC_TRY(scl::unet_prepare(&u, n, h, w));
+    SC_TRY(scl::unet_pack_input(&u, feat));
+    SC_TRY(scl::unet_forward_packed(&u));
+    SC_HIP(hipMemcpyAsync(pred, u.pred.p, 12 * (size_t)n * w * h, hipMemcpyDeviceToDevice, ctx->c.stream));
+    return SC_OK;
+}
+
+sc_status sc_unet_backward(sc_ctx* ctx, sc_unet* net, const float* dpred, float* grad) {
+    if (!ctx || !net || !dpred || !grad) return set_error(SC_EINVAL, "NULL argument");
+    scl::Unet& u = net->u;
+    if (!u.acts.p) return set_error(SC_EINVAL, "sc_unet_backward needs a preceding sc_unet_forward");
+    SC_TRY(scl::unet_pack_dpred(&u, dpred));
+    SC_TRY(scl::unet_backward_packed(&u));
+    SC_HIP(hipMemcpyAsync(grad, u.grad.p, 4 * u.n_params, hipMemcpyDeviceToDevice, ctx->c.stream));
+    return SC_OK;
+}
+
+sc_status sc_unet_train_step(sc_ctx* ctx, sc_unet* net, const float* feat, const float* target, uint32_t n,
+                             uint32_t w, uint32_t h, float lr, float* loss) {
+    if (!ctx || !net || !feat || !target) return set_error(SC_EINVAL, "NULL argument");
+    if (!(lr > 0.0f)) return set_error(SC_EINVAL, "lr must be > 0");
+    scl::Unet& u = net->u;
+    SC_TRY(check_shape(u, n, w, h));
+    SC_TRY(scl::unet_prepare(&u, n, h, w));
+    SC_TRY(scl::unet_pack_input(&u, feat));
+    SC_TRY(scl::unet_forward_packed(&u));
+    SC_TRY(scl::unet_loss(&u, target, u.loss.as<float>()));
+    SC_TRY(scl::unet_backward_packed(&u));
+    SC_TRY(scl::unet_adam(&u, lr));
+    if (loss) {
+        float s = 0.0f;
+        SC_HIP(hipMemcpyAsync(&s, u.loss.p, 4, hipMemcpyDeviceToHost, ctx->c.stream));
+        SC_HIP(hipStreamSynchronize(ctx->c.stream));
+        *loss = s / (float)((double)n * w * h * 3);
+    }
+    return SC_OK;
+}
+
+sc_status sc_denoise(sc_ctx* ctx, sc_unet* net, const sc_aov* in, uint32_t w, uint32_t h, float* out_rgb) {
+    if (!ctx || !net || !in || !in->rgb || !out_rgb) return set_error(SC_EINVAL, "NULL argument");
+    if (w == 0 || h == 0) return set_error(SC_EINVAL, "empty image");
+    scl::Unet& u = net->u;
+    const uint32_t m = 1u << (u.widths.size() - 1);
+    const uint32_t W = (w + m - 1) / m * m, H = (h + m - 1) / m * m;
+    SC_TRY(check_shape(u, 1, W, H));
+    SC_TRY(scl::unet_prepare(&u, 1, H, W));
+    SC_TRY(scl::unet_features(&u, *in, w, h));
+    SC_TRY(scl::unet_forward_packed(&u));
+    SC_TRY(scl::unet_output_rgb(&u, w, h, out_rgb));
+    return SC_OK;
 }
 
 }  // extern "C"

@@ -6,7 +6,8 @@
 // 4. binary radix tree over the sorted keys (Karras, "Maximizing
 //    parallelism in the construction of BVHs, octrees, and k-d trees",
 //    HPG 2012), internal node i spanning a contiguous key range;
-// 5. bottom-up bounds with one atomic arrival flag per internal node;
+// 5. node boxes from a sparse table of range unions over the sorted
+//    triangle boxes (every node spans a contiguous key range);
 // 6. greedy collapse, one level of wide nodes per launch: a wide node opens
 //    its largest-area non-leaf child until it holds 8 children; ranges of
 //    at most leaf_max triangles become leaves;
@@ -158,8 +159,7 @@ __device__ __forceinline__ int delta(const unsigned long long* keys, uint32_t n,
 // Radix tree: internal nodes 0..n-2; child encoding: value < n-1 internal,
 // value >= n-1 is leaf (value - (n-1)) = sorted position.
 __global__ void k_radix_tree(const unsigned long long* __restrict__ keys, uint32_t n, int32_t* __restrict__ left,
-                             int32_t* __restrict__ right, int32_t* __restrict__ parent, uint32_t* __restrict__ rlo,
-                             uint32_t* __restrict__ rhi) {
+                             int32_t* __restrict__ right, uint32_t* __restrict__ rlo, uint32_t* __restrict__ rhi) {
     for (uint32_t ii = blockIdx.x * blockDim.x + threadIdx.x; ii + 1 < n; ii += gridDim.x * blockDim.x) {
         const int i = (int)ii;
         const int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
@@ -183,45 +183,51 @@ __global__ void k_radix_tree(const unsigned long long* __restrict__ keys, uint32
         const int rc = (hi == gamma + 1) ? (int)(n - 1) + gamma + 1 : gamma + 1;
         left[i] = lc;
         right[i] = rc;
-        parent[lc] = i;
-        parent[rc] = i;
         rlo[i] = (uint32_t)lo;
         rhi[i] = (uint32_t)hi;
     }
 }
 
-// bottom-up bounds: node boxes nb[(2n-1)][6], leaves at n-1+pos
-__global__ void k_refit(const unsigned long long* __restrict__ keys, const float* __restrict__ tb, uint32_t n,
-                        const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-                        const int32_t* __restrict__ parent, float* nb, uint32_t* flags) {
+// Range unions of the key-sorted triangle boxes: level 0 holds the box of
+// the triangle at each sorted position, level L the union of positions
+// [i, i + 2^L).  A radix-tree node spans a contiguous range [lo, hi], so its
+// box is the union of two overlapping level-floor(log2(len)) windows.
+__global__ void k_sparse_level0(const unsigned long long* __restrict__ keys, const float* __restrict__ tb, uint32_t n,
+                                float* __restrict__ st) {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
         const uint32_t prim = (uint32_t)(keys[p] & 0xffffffffull);
-        const uint32_t leaf = n - 1 + p;
-        for (int k = 0; k < 6; ++k) nb[6 * (size_t)leaf + k] = tb[6 * (size_t)prim + k];
-        if (n == 1) continue;
-        __threadfence();
-        int node = parent[leaf];
-        while (node >= 0) {
-            if (atomicAdd(&flags[node], 1u) == 0) break;   // first arrival: the sibling finishes
-            __threadfence();
-            const int a = left[node], b = right[node];
-            for (int k = 0; k < 3; ++k) {
-                // the fence above orders these reads after the sibling's writes
-                const volatile float* vb = nb;
-                const float la = vb[6 * (size_t)a + k];
-                const float lb = vb[6 * (size_t)b + k];
-                const float ha = vb[6 * (size_t)a + 3 + k];
-                const float hb = vb[6 * (size_t)b + 3 + k];
-                nb[6 * (size_t)node + k] = fminf(la, lb);
-                nb[6 * (size_t)node + 3 + k] = fmaxf(ha, hb);
-            }
-            __threadfence();
-            node = node == 0 ? -1 : parent[node];
+        for (int k = 0; k < 6; ++k) st[6 * (size_t)p + k] = tb[6 * (size_t)prim + k];
+    }
+}
+
+__global__ void k_sparse_level(float* __restrict__ st, uint32_t n, uint32_t level) {
+    const size_t src = (size_t)(level - 1) * n * 6, dst = (size_t)level * n * 6;
+    const uint32_t half = 1u << (level - 1);
+    const uint32_t cnt = n - (1u << level) + 1;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+        const float* a = st + src + 6 * (size_t)i;
+        const float* b = st + src + 6 * (size_t)(i + half);
+        float* d = st + dst + 6 * (size_t)i;
+        for (int k = 0; k < 3; ++k) {
+            d[k] = fminf(a[k], b[k]);
+            d[3 + k] = fmaxf(a[3 + k], b[3 + k]);
         }
     }
 }
 
+__device__ __forceinline__ void range_box(const float* __restrict__ st, uint32_t n, uint32_t lo, uint32_t cnt,
+                                          float* box) {
+    const uint32_t level = 31u - __clz(cnt);
+    const float* a = st + ((size_t)level * n + lo) * 6;
+    const float* b = st + ((size_t)level * n + (lo + cnt - (1u << level))) * 6;
+    for (int k = 0; k < 3; ++k) {
+        box[k] = fminf(a[k], b[k]);
+        box[3 + k] = fmaxf(a[3 + k], b[3 + k]);
+    }
+}
+
 __device__ __forceinline__ float half_area(const float* b) {
+    // surface area / 2 of a box given as lo xyz, hi xyz (0 for an empty box)
     const float ex = b[3] - b[0], ey = b[4] - b[1], ez = b[5] - b[2];
     if (!(ex >= 0.0f) || !(ey >= 0.0f) || !(ez >= 0.0f)) return 0.0f;
     return ex * ey + ey * ez + ez * ex;
@@ -230,7 +236,7 @@ __device__ __forceinline__ float half_area(const float* b) {
 // One level of the collapse.  work[i] = (bvh2 node, wide node index).
 __global__ void k_collapse(uint32_t n, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
                            const uint32_t* __restrict__ rlo, const uint32_t* __restrict__ rhi,
-                           const float* __restrict__ nb, uint32_t leaf_max, uint32_t width,
+                           const float* __restrict__ st, uint32_t leaf_max, uint32_t width,
                            const uint2* __restrict__ work, const uint32_t* __restrict__ n_work, uint2* next_work,
                            uint32_t* n_next, uint32_t* n_nodes, BNode* nodes) {
     const uint32_t nw = *n_work;
@@ -256,7 +262,9 @@ __global__ void k_collapse(uint32_t n, const int32_t* __restrict__ left, const i
                 uint32_t lo, cn;
                 range_of(set[c], lo, cn);
                 if (cn <= leaf_max) continue;
-                const float a = half_area(nb + 6 * (size_t)set[c]);
+                float bx[6];
+                range_box(st, n, lo, cn, bx);
+                const float a = half_area(bx);
                 if (a > ba) { ba = a; best = c; }
             }
             if (best < 0) break;
@@ -267,11 +275,12 @@ __global__ void k_collapse(uint32_t n, const int32_t* __restrict__ left, const i
         BNode node;
         for (int c = 0; c < 8; ++c) {
             if (c < cnt) {
-                const float* b = nb + 6 * (size_t)set[c];
-                node.lox[c] = b[0]; node.loy[c] = b[1]; node.loz[c] = b[2];
-                node.hix[c] = b[3]; node.hiy[c] = b[4]; node.hiz[c] = b[5];
                 uint32_t lo, cn;
                 range_of(set[c], lo, cn);
+                float b[6];
+                range_box(st, n, lo, cn, b);
+                node.lox[c] = b[0]; node.loy[c] = b[1]; node.loz[c] = b[2];
+                node.hix[c] = b[3]; node.hiy[c] = b[4]; node.hiz[c] = b[5];
                 if (cn <= leaf_max) {
                     node.child[c] = SC_LEAF_BIT | ((cn - 1) << 28) | lo;
                 } else {
@@ -345,18 +354,18 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
     while (n_pad < n) n_pad <<= 1;
     if (n_pad < (uint32_t)kLocal) n_pad = kLocal;
 
-    DevBuf err_d, bounds, cb, keys, left, right, parent, rlo, rhi, nb, flags, work_a, work_b, counters;
+    uint32_t levels = 1;
+    while ((2u << (levels - 1)) <= n) ++levels;   // levels 0..floor(log2 n)
+    DevBuf err_d, bounds, cb, keys, left, right, rlo, rhi, st_buf, work_a, work_b, counters;
     SC_TRY(err_d.alloc(sizeof(uint32_t)));
     SC_TRY(bounds.alloc(sizeof(float) * 6 * (size_t)n));
     SC_TRY(cb.alloc(sizeof(uint32_t) * 6));
     SC_TRY(keys.alloc(sizeof(unsigned long long) * (size_t)n_pad));
     SC_TRY(left.alloc(sizeof(int32_t) * (size_t)(n > 1 ? n - 1 : 1)));
     SC_TRY(right.alloc(sizeof(int32_t) * (size_t)(n > 1 ? n - 1 : 1)));
-    SC_TRY(parent.alloc(sizeof(int32_t) * (size_t)(2 * n)));
     SC_TRY(rlo.alloc(sizeof(uint32_t) * (size_t)(n > 1 ? n - 1 : 1)));
     SC_TRY(rhi.alloc(sizeof(uint32_t) * (size_t)(n > 1 ? n - 1 : 1)));
-    SC_TRY(nb.alloc(sizeof(float) * 6 * (size_t)(2 * n)));
-    SC_TRY(flags.alloc(sizeof(uint32_t) * (size_t)(n > 1 ? n - 1 : 1)));
+    SC_TRY(st_buf.alloc(sizeof(float) * 6 * (size_t)n * levels));
     SC_TRY(work_a.alloc(sizeof(uint2) * (size_t)n));
     SC_TRY(work_b.alloc(sizeof(uint2) * (size_t)n));
     SC_TRY(counters.alloc(sizeof(uint32_t) * 4));
@@ -387,17 +396,15 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
                                keys.as<unsigned long long>(), n_pad, k, j);
         SC_LAUNCH(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys.as<unsigned long long>(), k, k);
     }
-    // radix tree + bounds
-    SC_LAUNCH(k_init_i32, dim3(grid_for(2 * n, bs)), dim3(bs), 0, st, parent.as<int32_t>(), 2 * n, -1);
-    if (n > 1) {
-        SC_LAUNCH(k_init_u32, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, flags.as<uint32_t>(), n - 1, 0u);
+    // radix tree
+    if (n > 1)
         SC_LAUNCH(k_radix_tree, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(), n,
-                           left.as<int32_t>(), right.as<int32_t>(), parent.as<int32_t>(), rlo.as<uint32_t>(),
-                           rhi.as<uint32_t>());
-    }
-    SC_LAUNCH(k_refit, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(),
-                       bounds.as<float>(), n, left.as<int32_t>(), right.as<int32_t>(), parent.as<int32_t>(),
-                       nb.as<float>(), flags.as<uint32_t>());
+                  left.as<int32_t>(), right.as<int32_t>(), rlo.as<uint32_t>(), rhi.as<uint32_t>());
+    // range-union table for node boxes
+    SC_LAUNCH(k_sparse_level0, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(),
+              bounds.as<float>(), n, st_buf.as<float>());
+    for (uint32_t L = 1; L < levels; ++L)
+        SC_LAUNCH(k_sparse_level, dim3(grid_for(n - (1u << L) + 1, bs)), dim3(bs), 0, st, st_buf.as<float>(), n, L);
 
     // collapse: level by level
     const uint32_t max_nodes = n > 1 ? n : 1;
@@ -417,7 +424,7 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
         uint32_t zero = 0;
         SC_HIP(hipMemcpyAsync(counters.as<uint32_t>() + 1, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, st));
         SC_LAUNCH(k_collapse, dim3(grid_for(cur_count, 128)), dim3(128), 0, st, n, left.as<int32_t>(),
-                           right.as<int32_t>(), rlo.as<uint32_t>(), rhi.as<uint32_t>(), nb.as<float>(), leaf_max,
+                           right.as<int32_t>(), rlo.as<uint32_t>(), rhi.as<uint32_t>(), st_buf.as<float>(), leaf_max,
                            width, wa->as<uint2>(), counters.as<uint32_t>(), wb->as<uint2>(),
                            counters.as<uint32_t>() + 1, counters.as<uint32_t>() + 2, nodes_tmp.as<BNode>());
         uint32_t h[3];

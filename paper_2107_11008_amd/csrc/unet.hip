@@ -1,0 +1,794 @@
+// unet.hip -- the learned denoiser: a U-Net (the network family the paper
+// trains, Sec. IV-A-3) with bfloat16 weights and activations on the matrix
+// cores (v_mfma_f32_16x16x32_bf16, float accumulation) and float master
+// weights updated by Adam.
+//
+// Layout: activations NHWC bfloat16 with channels padded to a multiple of
+// 16; forward weights [Cout_p][K_p] with k = tap * Cin_p + ci (K_p = 9 * Cin_p
+// rounded up to 32, zero padded); input-gradient weights are the same
+// convolution with the kernel flipped and the channel roles swapped, so one
+// implicit-GEMM kernel serves the forward pass and the input gradient.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "sc_internal.h"
+#include "sc_unet.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+union Frag {
+    bf16x8 v;
+    uint4 u;
+};
+
+// ---------------------------------------------------------------- convolution
+// One wave computes 16 consecutive output pixels x 64 output channels (four
+// 16x16 tiles sharing the pixel operand).  Lane l feeds pixel l%16 and the
+// k-group 8*(l/16)..+7 of the A operand, output channel l%16 of each B tile,
+// and receives pixels 4*(l/16)+i of channel l%16.
+template <int KS>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, uint32_t P, uint32_t H, uint32_t W,
+                                              uint32_t cin_p, const uint16_t* __restrict__ Wt, uint32_t kpad,
+                                              const float* __restrict__ bias, uint32_t cout_p, uint32_t cout_real,
+                                              uint16_t* __restrict__ Y, float* __restrict__ Yf, uint32_t y_stride,
+                                              uint32_t y_off, int relu) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_groups = (cout_p / 16 + 3) / 4;
+    const uint32_t tile = wave / n_groups;
+    const uint32_t grp = wave % n_groups;
+    const uint32_t n_tiles = (P + 15) / 16;
+    if (tile >= n_tiles) return;
+    const uint32_t nt_total = cout_p / 16;
+    const uint32_t pl = lane & 15, g = lane >> 4;
+    const uint32_t p = tile * 16 + pl;
+    const bool pvalid = p < P;
+    const uint32_t x = pvalid ? p % W : 0, rest = pvalid ? p / W : 0;
+    const uint32_t y = rest % H, b = rest / H;
+    const uint32_t K = KS * KS * cin_p;
+    floatx4 acc[4];
+    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t k0 = 0; k0 < kpad; k0 += 32) {
+        const uint32_t kk = k0 + 8 * g;
+        Frag a;
+        a.u = make_uint4(0u, 0u, 0u, 0u);
+        if (pvalid && kk < K) {
+            const uint32_t tap = kk / cin_p, ci = kk % cin_p;
+            const int dy = KS == 3 ? (int)(tap / 3) - 1 : 0;
+            const int dx = KS == 3 ? (int)(tap % 3) - 1 : 0;
+            const int yy = (int)y + dy, xx = (int)x + dx;
+            if (yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W) {
+                const size_t src = (((size_t)b * H + yy) * W + xx) * cin_p + ci;
+                a.u = *reinterpret_cast<const uint4*>(X + src);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t nt = grp * 4 + j;
+            if (nt < nt_total) {
+                Frag bw;
+                const uint32_t co = nt * 16 + pl;
+                bw.u = *reinterpret_cast<const uint4*>(Wt + (size_t)co * kpad + kk);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, bw.v, acc[j], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t nt = grp * 4 + j;
+        if (nt >= nt_total) continue;
+        const uint32_t co = nt * 16 + pl;
+        if (co >= cout_real) continue;
+        const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t po = tile * 16 + 4 * g + i;
+            if (po >= P) continue;
+            float v = acc[j][i] + bv;
+            if (relu) v = fmaxf(v, 0.0f);
+            if (Yf) Yf[(size_t)po * y_stride + y_off + co] = v;
+            else Y[(size_t)po * y_stride + y_off + co] = to_bf16(v);
+        }
+    }
+}
+
+// Weight gradient: dW[co][k] = sum_p dZ[p][co] * X[shift_tap(p)][ci] with
+// k = tap * cin_p + ci.  One wave: 16 output channels x 64 k over a chunk
+// of pixels (32 per MFMA step), added into dW with float atomics.
+template <int KS>
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dZ, uint32_t cout_p,
+                                               const uint16_t* __restrict__ X, uint32_t cin_p, uint32_t P,
+                                               uint32_t H, uint32_t W, uint32_t chunk, float* __restrict__ dW,
+                                               uint32_t kreal) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t co_tiles = cout_p / 16;
+    const uint32_t k_groups = (kreal + 63) / 64;
+    const uint32_t n_chunks = (P + chunk - 1) / chunk;
+    const uint32_t total = co_tiles * k_groups * n_chunks;
+    if (wave >= total) return;
+    const uint32_t ct = wave % co_tiles;
+    const uint32_t kg = (wave / co_tiles) % k_groups;
+    const uint32_t ch = wave / (co_tiles * k_groups);
+    const uint32_t pl = lane & 15, g = lane >> 4;
+    const uint32_t co = ct * 16 + pl;
+    // per B tile: weight column k = kg*64 + j*16 + pl -> (tap, ci)
+    int dyv[4], dxv[4];
+    uint32_t civ[4];
+    bool kval[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t k = kg * 64 + j * 16 + pl;
+        kval[j] = k < kreal;
+        const uint32_t tap = kval[j] ? k / cin_p : 0, ci = kval[j] ? k % cin_p : 0;
+        dyv[j] = KS == 3 ? (int)(tap / 3) - 1 : 0;
+        dxv[j] = KS == 3 ? (int)(tap % 3) - 1 : 0;
+        civ[j] = ci;
+    }
+    floatx4 acc[4];
+    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const uint32_t p_begin = ch * chunk;
+    const uint32_t p_end = min(P, p_begin + chunk);
+    for (uint32_t p0 = p_begin; p0 < p_end; p0 += 32) {
+        Frag a;
+        uint16_t av[8];
+        uint32_t pxs[8], pys[8], pbs[8];
+        bool pv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t p = p0 + 8 * g + e;
+            pv[e] = p < p_end;
+            const uint32_t pp = pv[e] ? p : 0;
+            pxs[e] = pp % W;
+            const uint32_t r = pp / W;
+            pys[e] = r % H;
+            pbs[e] = r / H;
+            av[e] = pv[e] ? dZ[(size_t)pp * cout_p + co] : (uint16_t)0;
+        }
+        a.u = make_uint4(av[0] | ((uint32_t)av[1] << 16), av[2] | ((uint32_t)av[3] << 16),
+                         av[4] | ((uint32_t)av[5] << 16), av[6] | ((uint32_t)av[7] << 16));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint16_t bv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int yy = (int)pys[e] + dyv[j], xx = (int)pxs[e] + dxv[j];
+                const bool in = pv[e] && kval[j] && yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W;
+                bv[e] = in ? X[(((size_t)pbs[e] * H + yy) * W + xx) * cin_p + civ[j]] : (uint16_t)0;
+            }
+            Frag bw;
+            bw.u = make_uint4(bv[0] | ((uint32_t)bv[1] << 16), bv[2] | ((uint32_t)bv[3] << 16),
+                              bv[4] | ((uint32_t)bv[5] << 16), bv[6] | ((uint32_t)bv[7] << 16));
+            // D[m = co][n = k]: A = dZ^T (co x pixels), B = X_shift (pixels x k)
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, bw.v, acc[j], 0, 0, 0);
+        }
+    }
+    // lane holds D[co = ct*16 + 4*g + i][k = kg*64 + j*16 + pl]
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t k = kg * 64 + j * 16 + pl;
+        if (k >= kreal) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t c = ct * 16 + 4 * g + i;
+            atomicAdd(&dW[(size_t)c * kreal + k], acc[j][i]);
+        }
+    }
+}
+
+__global__ void k_bias_grad(const uint16_t* __restrict__ dZ, uint32_t P, uint32_t cout_p, uint32_t cout_real,
+                            float* __restrict__ db) {
+    // block: 256 threads over a pixel range, one channel per thread group
+    const uint32_t c = threadIdx.x % 64;
+    const uint32_t sub = threadIdx.x / 64;
+    __shared__ float part[4][64];
+    for (uint32_t c0 = 0; c0 < cout_real; c0 += 64) {
+        float s = 0.0f;
+        const uint32_t cc = c0 + c;
+        if (cc < cout_real)
+            for (uint32_t p = blockIdx.x * 4 + sub; p < P; p += gridDim.x * 4) s += from_bf16(dZ[(size_t)p * cout_p + cc]);
+        part[sub][c] = s;
+        __syncthreads();
+        if (sub == 0 && cc < cout_real) atomicAdd(&db[cc], part[0][c] + part[1][c] + part[2][c] + part[3][c]);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- elementwise
+__global__ void k_relu_mask(const uint16_t* __restrict__ dY, const uint16_t* __restrict__ Y, size_t n,
+                            uint16_t* __restrict__ dZ) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dZ[i] = from_bf16(Y[i]) > 0.0f ? dY[i] : (uint16_t)0;
+}
+
+__global__ void k_maxpool(const uint16_t* __restrict__ X, uint32_t B, uint32_t H, uint32_t W, uint32_t C,
+                          uint16_t* __restrict__ Y, uint8_t* __restrict__ idx) {
+    const uint32_t h = H / 2, w = W / 2;
+    const size_t n = (size_t)B * h * w * C;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t c = i % C;
+        size_t r = i / C;
+        const uint32_t x = r % w;
+        r /= w;
+        const uint32_t y = r % h;
+        const uint32_t b = r / h;
+        float best = -INFINITY;
+        uint8_t bi = 0;
+        uint16_t bv = 0;
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t yy = 2 * y + (q >> 1), xx = 2 * x + (q & 1);
+            const uint16_t v = X[(((size_t)b * H + yy) * W + xx) * C + c];
+            const float f = from_bf16(v);
+            if (f > best) { best = f; bi = (uint8_t)q; bv = v; }
+        }
+        Y[i] = bv;
+        idx[i] = bi;
+    }
+}
+
+// dX = scatter of dY to the arg-max position (+ add, the skip gradient)
+__global__ void k_maxpool_bwd(const uint16_t* __restrict__ dY, const uint8_t* __restrict__ idx, uint32_t B,
+                              uint32_t H, uint32_t W, uint32_t C, const uint16_t* __restrict__ add,
+                              uint16_t* __restrict__ dX) {
+    const size_t n = (size_t)B * H * W * C;
+    const uint32_t w = W / 2, h = H / 2;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t c = i % C;
+        size_t r = i / C;
+        const uint32_t x = r % W;
+        r /= W;
+        const uint32_t y = r % H;
+        const uint32_t b = r / H;
+        const size_t o = (((size_t)b * h + y / 2) * w + x / 2) * C + c;
+        const uint32_t q = ((y & 1) << 1) | (x & 1);
+        float v = idx[o] == q ? from_bf16(dY[o]) : 0.0f;
+        if (add) v += from_bf16(add[i]);
+        dX[i] = to_bf16(v);
+    }
+}
+
+// C[b,y,x,:] = [ D[b,y/2,x/2,:cu] | E[b,y,x,:ce] ]
+__global__ void k_upcat(const uint16_t* __restrict__ D, uint32_t cu, const uint16_t* __restrict__ E, uint32_t ce,
+                        uint32_t B, uint32_t H, uint32_t W, uint16_t* __restrict__ Cc) {
+    const uint32_t ct = cu + ce;
+    const size_t n = (size_t)B * H * W * ct;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t c = i % ct;
+        const size_t pix = i / ct;
+        const uint32_t x = pix % W;
+        const size_t r = pix / W;
+        const uint32_t y = r % H;
+        const uint32_t b = r / H;
+        Cc[i] = c < cu ? D[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * cu + c] : E[pix * ce + (c - cu)];
+    }
+}
+
+// dD = sum over each 2x2 block of the first cu channels; dE = the rest
+__global__ void k_upcat_bwd(const uint16_t* __restrict__ dC, uint32_t cu, uint32_t ce, uint32_t B, uint32_t H,
+                            uint32_t W, uint16_t* __restrict__ dD, uint16_t* __restrict__ dE) {
+    const uint32_t ct = cu + ce;
+    const uint32_t h = H / 2, w = W / 2;
+    const size_t nd = (size_t)B * h * w * cu;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nd; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t c = i % cu;
+        size_t r = i / cu;
+        const uint32_t x = r % w;
+        r /= w;
+        const uint32_t y = r % h;
+        const uint32_t b = r / h;
+        float s = 0.0f;
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t yy = 2 * y + (q >> 1), xx = 2 * x + (q & 1);
+            s += from_bf16(dC[(((size_t)b * H + yy) * W + xx) * ct + c]);
+        }
+        dD[i] = to_bf16(s);
+    }
+    const size_t ne = (size_t)B * H * W * ce;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ne; i += (size_t)gridDim.x * blockDim.x)
+        dE[i] = dC[(i / ce) * ct + cu + (i % ce)];
+}
+
+// network input: float [P][in_ch] -> bf16 [P][cin_p] (zero padded channels)
+__global__ void k_pack_input(const float* __restrict__ f, uint32_t P, uint32_t in_ch, uint32_t cin_p,
+                             uint16_t* __restrict__ X) {
+    const size_t n = (size_t)P * cin_p;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t c = i % cin_p;
+        X[i] = c < in_ch ? to_bf16(f[(i / cin_p) * in_ch + c]) : (uint16_t)0;
+    }
+}
+
+// features from the renderer's outputs into a zero-padded canvas
+__global__ void k_features(const float* __restrict__ rgb, const float* __restrict__ albedo,
+                           const float* __restrict__ normal, const float* __restrict__ depthn,
+                           const uint8_t* __restrict__ trans, uint32_t w, uint32_t h, uint32_t W, uint32_t H,
+                           uint32_t cin_p, uint16_t* __restrict__ X) {
+    const size_t n = (size_t)W * H;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t x = i % W, y = i / W;
+        float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (x < w && y < h) {
+            const size_t p = (size_t)y * w + x;
+            for (int c = 0; c < 3; ++c) v[c] = log1pf(fmaxf(rgb[3 * p + c], 0.0f));
+            v[3] = albedo ? albedo[p] : 0.0f;
+            for (int c = 0; c < 3; ++c) v[4 + c] = normal ? normal[3 * p + c] : 0.0f;
+            v[7] = depthn ? depthn[p] : 0.0f;
+            v[8] = trans ? (float)trans[p] : 0.0f;
+        }
+        for (uint32_t c = 0; c < cin_p; ++c) X[i * cin_p + c] = c < 9 ? to_bf16(v[c]) : (uint16_t)0;
+    }
+}
+
+__global__ void k_expm1_crop(const float* __restrict__ pred, uint32_t W, uint32_t w, uint32_t h,
+                             float* __restrict__ out) {
+    const size_t n = (size_t)w * h;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t x = i % w, y = i / w;
+        const size_t q = (size_t)y * W + x;
+        for (int c = 0; c < 3; ++c) out[3 * i + c] = fmaxf(expm1f(pred[3 * q + c]), 0.0f);
+    }
+}
+
+// L1 loss on log(1 + target): sum |pred - t| (atomic) and dY = sign / N as bf16
+__global__ void k_l1_loss(const float* __restrict__ pred, const float* __restrict__ target, uint32_t P,
+                          uint32_t cout_p, float inv_n, uint16_t* __restrict__ dY, float* __restrict__ loss_sum) {
+    float s = 0.0f;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)P * cout_p;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t c = i % cout_p;
+        const size_t p = i / cout_p;
+        float g = 0.0f;
+        if (c < 3) {
+            const float d = pred[3 * p + c] - log1pf(fmaxf(target[3 * p + c], 0.0f));
+            s += fabsf(d);
+            g = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
+        }
+        dY[i] = to_bf16(g);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) atomicAdd(loss_sum, s);
+}
+
+// given dpred float [P][3] -> bf16 [P][cout_p]
+__global__ void k_pack_dpred(const float* __restrict__ dp, uint32_t P, uint32_t cout_p, uint16_t* __restrict__ dY) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)P * cout_p;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t c = i % cout_p;
+        dY[i] = c < 3 ? to_bf16(dp[(i / cout_p) * 3 + c]) : (uint16_t)0;
+    }
+}
+
+// float master weights of one layer (oracle packing [co][ky][kx][ci], then
+// bias) -> forward and input-gradient bfloat16 matrices
+__global__ void k_convert(const float* __restrict__ w, uint32_t cout, uint32_t cin, uint32_t ks, uint32_t cout_p,
+                          uint32_t cin_p, uint32_t kpad, uint32_t kpad_t, uint16_t* __restrict__ Wf,
+                          uint16_t* __restrict__ Wd) {
+    const uint32_t taps = ks * ks;
+    const size_t nf = (size_t)cout_p * kpad;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nf; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t co = i / kpad, k = i % kpad;
+        const uint32_t tap = k / cin_p, ci = k % cin_p;
+        float v = 0.0f;
+        if (co < cout && tap < taps && ci < cin) v = w[((size_t)co * taps + tap) * cin + ci];
+        Wf[i] = to_bf16(v);
+    }
+    const size_t nd = (size_t)cin_p * kpad_t;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nd; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t ci = i / kpad_t, k = i % kpad_t;
+        const uint32_t tap = k / cout_p, co = k % cout_p;
+        float v = 0.0f;
+        if (ci < cin && tap < taps && co < cout) v = w[((size_t)co * taps + (taps - 1 - tap)) * cin + ci];
+        Wd[i] = to_bf16(v);
+    }
+}
+
+// scatter dW [cout_p][taps*cin_p] (padded) into the packed float gradient
+__global__ void k_unpad_grad(const float* __restrict__ dWp, uint32_t cout, uint32_t cin, uint32_t ks,
+                             uint32_t cin_p, float* __restrict__ g) {
+    const uint32_t taps = ks * ks;
+    const size_t n = (size_t)cout * taps * cin;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t ci = i % cin;
+        const size_t r = i / cin;
+        const uint32_t tap = r % taps, co = r / taps;
+        g[i] = dWp[(size_t)co * taps * cin_p + (size_t)tap * cin_p + ci];
+    }
+}
+
+__global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, size_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        th[i] = th[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void k_zero_f(float* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0f;
+}
+
+inline uint32_t blocks(size_t n, uint32_t bs = 256, uint32_t cap = 16384) {
+    size_t g = (n + bs - 1) / bs;
+    return (uint32_t)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+// =====================================================================
+namespace scl {
+
+namespace {
+
+uint32_t round_up(uint32_t v, uint32_t m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+sc_status unet_create(Ctx* c, const uint32_t* widths, uint32_t levels, Unet* u) {
+    if (levels < 2 || levels > 6) return set_error(SC_EINVAL, "levels must be 2..6");
+    u->ctx = c;
+    u->widths.assign(widths, widths + levels);
+    for (uint32_t i = 0; i < levels; ++i)
+        if (widths[i] == 0 || widths[i] % 16 != 0 || widths[i] > 256)
+            return set_error(SC_EINVAL, "widths must be multiples of 16 up to 256");
+    // layer table in parameter order
+    auto add = [&](uint32_t cout, uint32_t ks, uint32_t cin) {
+        UnetLayer L;
+        L.cout = cout; L.ks = ks; L.cin = cin;
+        L.cout_p = round_up(cout, 16);
+        L.cin_p = round_up(cin, 16);
+        L.kpad = round_up(ks * ks * L.cin_p, 32);
+        L.kpad_t = round_up(ks * ks * L.cout_p, 32);
+        L.w_off = u->n_params;
+        L.b_off = L.w_off + (size_t)cout * ks * ks * cin;
+        u->n_params = L.b_off + cout;
+        u->layers.push_back(L);
+    };
+    uint32_t cin = kUnetIn;
+    for (uint32_t i = 0; i < levels; ++i) {
+        add(widths[i], 3, cin);
+        add(widths[i], 3, widths[i]);
+        cin = widths[i];
+    }
+    for (int i = (int)levels - 2; i >= 0; --i) {
+        add(widths[i], 3, cin + widths[i]);
+        add(widths[i], 3, widths[i]);
+        cin = widths[i];
+    }
+    add(kUnetOut, 1, cin);
+    size_t wf = 0, wd = 0;
+    for (auto& L : u->layers) {
+        L.wf_off = wf;
+        L.wd_off = wd;
+        wf += (size_t)L.cout_p * L.kpad;
+        wd += (size_t)L.cin_p * L.kpad_t;
+    }
+    SC_TRY(u->theta.alloc(4 * u->n_params));
+    SC_TRY(u->m.alloc(4 * u->n_params));
+    SC_TRY(u->v.alloc(4 * u->n_params));
+    SC_TRY(u->grad.alloc(4 * u->n_params));
+    SC_TRY(u->wf.alloc(2 * wf));
+    SC_TRY(u->wd.alloc(2 * wd));
+    size_t maxw = 0;
+    for (auto& L : u->layers) maxw = std::max(maxw, (size_t)L.cout_p * L.ks * L.ks * L.cin_p);
+    SC_TRY(u->dwp.alloc(4 * maxw));
+    SC_TRY(u->loss.alloc(16));
+    hipLaunchKernelGGL(k_zero_f, dim3(blocks(u->n_params)), dim3(256), 0, c->stream, u->theta.as<float>(), u->n_params);
+    hipLaunchKernelGGL(k_zero_f, dim3(blocks(u->n_params)), dim3(256), 0, c->stream, u->m.as<float>(), u->n_params);
+    hipLaunchKernelGGL(k_zero_f, dim3(blocks(u->n_params)), dim3(256), 0, c->stream, u->v.as<float>(), u->n_params);
+    SC_HIP(hipGetLastError());
+    return unet_refresh(u);
+}
+
+sc_status unet_refresh(Unet* u) {
+    hipStream_t st = u->ctx->stream;
+    for (auto& L : u->layers) {
+        hipLaunchKernelGGL(k_convert, dim3(blocks((size_t)L.cout_p * L.kpad)), dim3(256), 0, st,
+                           u->theta.as<float>() + L.w_off, L.cout, L.cin, L.ks, L.cout_p, L.cin_p, L.kpad, L.kpad_t,
+                           u->wf.as<uint16_t>() + L.wf_off, u->wd.as<uint16_t>() + L.wd_off);
+    }
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+namespace {
+
+// activation buffers for a batch shape
+sc_status ensure_acts(Unet* u, uint32_t B, uint32_t H, uint32_t W) {
+    if (u->B == B && u->H == H && u->W == W && u->acts.p) return SC_OK;
+    const uint32_t L = (uint32_t)u->widths.size();
+    // offsets (in bf16 elements) of every tensor
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        size_t o = off;
+        off += (n + 127) / 128 * 128;
+        return o;
+    };
+    u->t.clear();
+    UnetTensors& T = u->t;
+    const size_t P0 = (size_t)B * H * W;
+    T.in = take(P0 * 16);
+    for (uint32_t i = 0; i < L; ++i) {
+        const size_t P = P0 >> (2 * i);
+        const uint32_t w = u->widths[i];
+        if (i > 0) {
+            const uint32_t cprev = u->widths[i - 1];
+            T.pool.push_back(take(P * cprev));
+            T.pool_idx.push_back(take((P * cprev + 1) / 2));   // bytes stored in bf16 slots
+        } else {
+            T.pool.push_back(0);
+            T.pool_idx.push_back(0);
+        }
+        T.enc_a.push_back(take(P * w));
+        T.enc_b.push_back(take(P * w));
+    }
+    T.cat.assign(L, 0);
+    T.dec_a.assign(L, 0);
+    T.dec_b.assign(L, 0);
+    for (int i = (int)L - 2; i >= 0; --i) {
+        const size_t P = P0 >> (2 * i);
+        const uint32_t cu = (i == (int)L - 2) ? u->widths[L - 1] : u->widths[i + 1];
+        T.cat[i] = take(P * (cu + u->widths[i]));
+        T.dec_a[i] = take(P * u->widths[i]);
+        T.dec_b[i] = take(P * u->widths[i]);
+    }
+    // gradient scratch: two ping-pong buffers big enough for any tensor, plus skip grads
+    size_t maxt = P0 * 16;
+    for (uint32_t i = 0; i < L; ++i) {
+        const size_t P = P0 >> (2 * i);
+        maxt = std::max(maxt, P * (size_t)(2 * u->widths[std::min(i + 1, L - 1)] + u->widths[i]));
+    }
+    T.g0 = take(maxt);
+    T.g1 = take(maxt);
+    T.g2 = take(maxt);
+    T.skip.assign(L, 0);
+    for (uint32_t i = 0; i + 1 < L; ++i) T.skip[i] = take((P0 >> (2 * i)) * u->widths[i]);
+    SC_TRY(u->acts.alloc(2 * off));
+    SC_TRY(u->pred.alloc(4 * P0 * 3));
+    u->B = B;
+    u->H = H;
+    u->W = W;
+    return SC_OK;
+}
+
+void conv_launch(hipStream_t st, const UnetLayer& L, const uint16_t* X, uint32_t P, uint32_t H, uint32_t W,
+                 const uint16_t* Wt, uint32_t cin_p, uint32_t kpad, const float* bias, uint32_t cout_p,
+                 uint32_t cout_real, uint16_t* Y, float* Yf, uint32_t y_stride, int relu) {
+    const uint32_t n_tiles = (P + 15) / 16;
+    const uint32_t groups = (cout_p / 16 + 3) / 4;
+    const size_t waves = (size_t)n_tiles * groups;
+    const uint32_t grid = (uint32_t)((waves + 3) / 4);
+    if (L.ks == 3)
+        hipLaunchKernelGGL(k_conv<3>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
+                           cout_real, Y, Yf, y_stride, 0u, relu);
+    else
+        hipLaunchKernelGGL(k_conv<1>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
+                           cout_real, Y, Yf, y_stride, 0u, relu);
+}
+
+}  // namespace
+
+// Forward pass over the packed input in u->acts (T.in); prediction in u->pred.
+sc_status unet_forward_packed(Unet* u) {
+    hipStream_t st = u->ctx->stream;
+    const uint32_t L = (uint32_t)u->widths.size();
+    uint16_t* A = u->acts.as<uint16_t>();
+    const float* th = u->theta.as<float>();
+    const uint16_t* wf = u->wf.as<uint16_t>();
+    UnetTensors& T = u->t;
+    size_t li = 0;
+    const uint16_t* h = A + T.in;
+    uint32_t hc = 16;
+    for (uint32_t i = 0; i < L; ++i) {
+        const uint32_t H = u->H >> i, W = u->W >> i, P = u->B * H * W;
+        if (i > 0) {
+            hipLaunchKernelGGL(k_maxpool, dim3(blocks((size_t)P * hc)), dim3(256), 0, st, h, u->B, 2 * H, 2 * W, hc,
+                               A + T.pool[i], reinterpret_cast<uint8_t*>(A + T.pool_idx[i]));
+            h = A + T.pool[i];
+        }
+        for (int part = 0; part < 2; ++part) {
+            const UnetLayer& Ly = u->layers[li++];
+            uint16_t* out = A + (part == 0 ? T.enc_a[i] : T.enc_b[i]);
+            conv_launch(st, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p, Ly.cout, out,
+                        nullptr, Ly.cout, 1);
+            h = out;
+            hc = Ly.cout;
+        }
+    }
+    for (int i = (int)L - 2; i >= 0; --i) {
+        const uint32_t H = u->H >> i, W = u->W >> i, P = u->B * H * W;
+        hipLaunchKernelGGL(k_upcat, dim3(blocks((size_t)P * (hc + u->widths[i]))), dim3(256), 0, st, h, hc,
+                           A + T.enc_b[i], u->widths[i], u->B, H, W, A + T.cat[i]);
+        h = A + T.cat[i];
+        for (int part = 0; part < 2; ++part) {
+            const UnetLayer& Ly = u->layers[li++];
+            uint16_t* out = A + (part == 0 ? T.dec_a[i] : T.dec_b[i]);
+            conv_launch(st, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p, Ly.cout, out,
+                        nullptr, Ly.cout, 1);
+            h = out;
+            hc = Ly.cout;
+        }
+    }
+    const UnetLayer& Lo = u->layers[li];
+    const uint32_t P0 = u->B * u->H * u->W;
+    conv_launch(st, Lo, h, P0, u->H, u->W, wf + Lo.wf_off, Lo.cin_p, Lo.kpad, th + Lo.b_off, Lo.cout_p, Lo.cout,
+                nullptr, u->pred.as<float>(), 3, 0);
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+namespace {
+
+// gradient of one convolution: dZ (bf16, [P][cout_p] layout) given; writes
+// the weight and bias gradient and, if dX is not null, the input gradient
+void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint16_t* dZ, uint32_t P, uint32_t H,
+                   uint32_t W, uint16_t* dX) {
+    hipStream_t st = u->ctx->stream;
+    float* g = u->grad.as<float>();
+    const uint32_t taps = Ly.ks * Ly.ks;
+    const uint32_t kreal = taps * Ly.cin_p;
+    float* dWp = u->dwp.as<float>();
+    hipLaunchKernelGGL(k_zero_f, dim3(blocks((size_t)Ly.cout_p * kreal)), dim3(256), 0, st, dWp,
+                       (size_t)Ly.cout_p * kreal);
+    const uint32_t chunk = 4096;
+    const size_t waves = (size_t)(Ly.cout_p / 16) * ((kreal + 63) / 64) * ((P + chunk - 1) / chunk);
+    if (Ly.ks == 3)
+        hipLaunchKernelGGL(k_wgrad<3>, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, st, dZ, Ly.cout_p, Xin,
+                           Ly.cin_p, P, H, W, chunk, dWp, kreal);
+    else
+        hipLaunchKernelGGL(k_wgrad<1>, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, st, dZ, Ly.cout_p, Xin,
+                           Ly.cin_p, P, H, W, chunk, dWp, kreal);
+    hipLaunchKernelGGL(k_unpad_grad, dim3(blocks((size_t)Ly.cout * taps * Ly.cin)), dim3(256), 0, st, dWp, Ly.cout,
+                       Ly.cin, Ly.ks, Ly.cin_p, g + Ly.w_off);
+    hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(256), 0, st, g + Ly.b_off, (size_t)Ly.cout);
+    hipLaunchKernelGGL(k_bias_grad, dim3(std::min<uint32_t>(1024, (P + 3) / 4)), dim3(256), 0, st, dZ, P, Ly.cout_p,
+                       Ly.cout, g + Ly.b_off);
+    if (dX)
+        conv_launch(st, Ly, dZ, P, H, W, u->wd.as<uint16_t>() + Ly.wd_off, Ly.cout_p, Ly.kpad_t, nullptr, Ly.cin_p,
+                    Ly.cin_p, dX, nullptr, Ly.cin_p, 0);
+}
+
+}  // namespace
+
+// Backward pass: dY (bf16 [P0][16], gradient of the prediction) in T.g0.
+sc_status unet_backward_packed(Unet* u) {
+    hipStream_t st = u->ctx->stream;
+    const uint32_t L = (uint32_t)u->widths.size();
+    uint16_t* A = u->acts.as<uint16_t>();
+    UnetTensors& T = u->t;
+    uint16_t* gcur = A + T.g0;    // gradient w.r.t. the current tensor
+    uint16_t* gz = A + T.g1;      // masked gradient
+    uint16_t* gn = A + T.g2;      // gradient w.r.t. the previous tensor
+    size_t li = u->layers.size() - 1;
+    const uint32_t P0 = u->B * u->H * u->W;
+    // output layer (no activation): dZ = dY
+    {
+        const UnetLayer& Lo = u->layers[li];
+        const uint16_t* xin = A + T.dec_b[0];
+        if (L == 1) xin = A + T.enc_b[0];
+        conv_backward(u, Lo, xin, gcur, P0, u->H, u->W, gn);
+        std::swap(gcur, gn);
+    }
+    // decoder levels, shallow to deep
+    for (uint32_t i = 0; i + 1 < L; ++i) {
+        const uint32_t H = u->H >> i, W = u->W >> i, P = u->B * H * W;
+        for (int part = 1; part >= 0; --part) {
+            // decoder layers are stored from the deepest level: index 2L + 2(L-2-i) + part
+            li = 2 * L + 2 * (L - 2 - i) + (size_t)part;
+            const UnetLayer& Ly = u->layers[li];
+            const uint16_t* yout = A + (part == 1 ? T.dec_b[i] : T.dec_a[i]);
+            const uint16_t* xin = A + (part == 1 ? T.dec_a[i] : T.cat[i]);
+            const size_t n = (size_t)P * Ly.cout;
+            hipLaunchKernelGGL(k_relu_mask, dim3(blocks(n)), dim3(256), 0, st, gcur, yout, n, gz);
+            conv_backward(u, Ly, xin, gz, P, H, W, gn);
+            std::swap(gcur, gn);
+        }
+        // split the concat gradient: upsampled part -> deeper level, skip part kept
+        const uint32_t cu = (i == L - 2) ? u->widths[L - 1] : u->widths[i + 1];
+        hipLaunchKernelGGL(k_upcat_bwd, dim3(blocks((size_t)P * (cu + u->widths[i]))), dim3(256), 0, st, gcur, cu,
+                           u->widths[i], u->B, H, W, gn, A + T.skip[i]);
+        std::swap(gcur, gn);
+    }
+    // encoder levels, deep to shallow
+    for (int i = (int)L - 1; i >= 0; --i) {
+        const uint32_t H = u->H >> i, W = u->W >> i, P = u->B * H * W;
+        for (int part = 1; part >= 0; --part) {
+            const UnetLayer& Ly = u->layers[2 * i + part];
+            const uint16_t* yout = A + (part == 1 ? T.enc_b[i] : T.enc_a[i]);
+            const uint16_t* xin = part == 1 ? A + T.enc_a[i] : (i > 0 ? A + T.pool[i] : A + T.in);
+            const size_t n = (size_t)P * Ly.cout;
+            hipLaunchKernelGGL(k_relu_mask, dim3(blocks(n)), dim3(256), 0, st, gcur, yout, n, gz);
+            const bool need_dx = !(i == 0 && part == 0);
+            conv_backward(u, Ly, xin, gz, P, H, W, need_dx ? gn : nullptr);
+            if (need_dx) std::swap(gcur, gn);
+        }
+        if (i > 0) {
+            // through the pooling into level i-1, plus that level's skip gradient
+            const uint32_t c = u->widths[i - 1];
+            const size_t n = (size_t)u->B * (2 * H) * (2 * W) * c;
+            hipLaunchKernelGGL(k_maxpool_bwd, dim3(blocks(n)), dim3(256), 0, st, gcur,
+                               reinterpret_cast<const uint8_t*>(A + T.pool_idx[i]), u->B, 2 * H, 2 * W, c,
+                               A + T.skip[i - 1], gn);
+            std::swap(gcur, gn);
+        }
+    }
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+sc_status unet_prepare(Unet* u, uint32_t B, uint32_t H, uint32_t W) { return ensure_acts(u, B, H, W); }
+
+sc_status unet_pack_input(Unet* u, const float* feat) {
+    const uint32_t P = u->B * u->H * u->W;
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks((size_t)P * 16)), dim3(256), 0, u->ctx->stream, feat, P, kUnetIn, 16u,
+                       u->acts.as<uint16_t>() + u->t.in);
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+sc_status unet_pack_dpred(Unet* u, const float* dpred) {
+    const uint32_t P = u->B * u->H * u->W;
+    hipLaunchKernelGGL(k_pack_dpred, dim3(blocks((size_t)P * 16)), dim3(256), 0, u->ctx->stream, dpred, P, 16u,
+                       u->acts.as<uint16_t>() + u->t.g0);
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+sc_status unet_loss(Unet* u, const float* target, float* loss_dev) {
+    const uint32_t P = u->B * u->H * u->W;
+    hipStream_t st = u->ctx->stream;
+    hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(64), 0, st, loss_dev, (size_t)1);
+    hipLaunchKernelGGL(k_l1_loss, dim3(blocks((size_t)P * 16)), dim3(256), 0, st, u->pred.as<float>(), target, P, 16u,
+                       1.0f / (float)((size_t)P * 3), u->acts.as<uint16_t>() + u->t.g0, loss_dev);
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+sc_status unet_adam(Unet* u, float lr) {
+    u->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - pow(0.9, (double)u->step));
+    const float c2 = (float)(1.0 - pow(0.999, (double)u->step));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(u->n_params)), dim3(256), 0, u->ctx->stream, u->theta.as<float>(),
+                       u->m.as<float>(), u->v.as<float>(), u->grad.as<float>(), u->n_params, lr, b1, b2, 1e-8f, c1, c2);
+    SC_HIP(hipGetLastError());
+    return unet_refresh(u);
+}
+
+sc_status unet_features(Unet* u, const sc_aov& in, uint32_t w, uint32_t h) {
+    hipLaunchKernelGGL(k_features, dim3(blocks((size_t)u->W * u->H)), dim3(256), 0, u->ctx->stream, in.rgb, in.albedo,
+                       in.normal, in.depthn, in.trans, w, h, u->W, u->H, 16u, u->acts.as<uint16_t>() + u->t.in);
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+sc_status unet_output_rgb(Unet* u, uint32_t w, uint32_t h, float* out) {
+    hipLaunchKernelGGL(k_expm1_crop, dim3(blocks((size_t)w * h)), dim3(256), 0, u->ctx->stream, u->pred.as<float>(),
+                       u->W, w, h, out);
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+}  // namespace scl

@@ -16,6 +16,7 @@ are not available, so procedural geometry of the same flavour is used.
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass, field
 from typing import List, Optional
@@ -148,6 +149,13 @@ def _area_weighted_normals(V, I):
 
 
 def icosphere(level: int, radius: float = 1.0, center=(0.0, 0.0, 0.0)) -> Mesh:
+    U, I = _unit_icosphere(level)
+    cen = np.asarray(center, dtype=np.float64)
+    return Mesh(U * radius + cen, I.copy(), U.copy())
+
+
+@functools.lru_cache(maxsize=None)
+def _unit_icosphere(level: int):
     """Subdivided icosahedron with vertices projected to the sphere.
 
     Level L has 20*4^L triangles and 10*4^L+2 vertices (level 3: 1,280 and
@@ -181,8 +189,9 @@ def icosphere(level: int, radius: float = 1.0, center=(0.0, 0.0, 0.0)) -> Mesh:
         F = nf
     U = np.array(P)
     I = _orient_outward(U, np.array(F, dtype=np.int64), np.zeros(3))
-    cen = np.asarray(center, dtype=np.float64)
-    return Mesh(U * radius + cen, I, U.copy())
+    U.setflags(write=False)
+    I.setflags(write=False)
+    return U, I
 
 
 def quad(p0, p1, p2, p3, normal) -> Mesh:
@@ -196,38 +205,35 @@ def quad(p0, p1, p2, p3, normal) -> Mesh:
     return Mesh(V, I, VN)
 
 
-def _revolve(rings_r, rings_z, m):
-    """Closed surface of revolution around +z: poles at both ends.
+def _ring_faces(s: int, m: int) -> np.ndarray:
+    """Faces of a closed grid with a pole at each end: vertex 0 is the bottom
+    pole, rings 1..s-2 hold m vertices each, the last vertex is the top pole."""
+    i = np.arange(m)
+    i1 = (i + 1) % m
+    bottom = np.stack([np.zeros(m, np.int64), 1 + i1, 1 + i], 1)
+    k = np.arange(s - 3)[:, None]
+    b0 = 1 + k * m
+    b1 = 1 + (k + 1) * m
+    q1 = np.stack([b0 + i, b0 + i1, b1 + i1], -1).reshape(-1, 3)
+    q2 = np.stack([b0 + i, b1 + i1, b1 + i], -1).reshape(-1, 3)
+    quads = np.stack([q1, q2], 1).reshape(-1, 3)
+    bl = 1 + (s - 3) * m
+    top_idx = 1 + (s - 2) * m
+    top = np.stack([bl + i, bl + i1, np.full(m, top_idx, np.int64)], 1)
+    return np.concatenate([bottom, quads, top]).astype(np.int64)
 
-    ``rings_r``/``rings_z`` give the interior rings (radius > 0); the
-    bottom pole sits at rings_z[0]-step, the top at rings_z[-1]+step,
-    i.e. the caller passes the pole heights as the first/last entries
-    with radius 0.
-    """
+
+def _revolve(rings_r, rings_z, m):
+    """Closed surface of revolution around +z: rings_r[0] and rings_r[-1]
+    are 0 (the poles)."""
     s = len(rings_r)
     assert rings_r[0] == 0 and rings_r[-1] == 0
-    V = [(0.0, 0.0, rings_z[0])]
     phi = np.arange(m) * (2.0 * math.pi / m)
-    for k in range(1, s - 1):
-        for p in phi:
-            V.append((rings_r[k] * math.cos(p), rings_r[k] * math.sin(p), rings_z[k]))
-    V.append((0.0, 0.0, rings_z[-1]))
-    V = np.array(V)
-    top = len(V) - 1
-    I = []
-    for i in range(m):
-        I.append((0, 1 + (i + 1) % m, 1 + i))
-    for k in range(s - 3):
-        b0 = 1 + k * m
-        b1 = 1 + (k + 1) * m
-        for i in range(m):
-            i1 = (i + 1) % m
-            I.append((b0 + i, b0 + i1, b1 + i1))
-            I.append((b0 + i, b1 + i1, b1 + i))
-    bl = 1 + (s - 3) * m
-    for i in range(m):
-        I.append((bl + i, bl + (i + 1) % m, top))
-    return V, np.array(I, dtype=np.int64)
+    r = np.asarray(rings_r[1:-1], dtype=np.float64)[:, None]
+    z = np.asarray(rings_z[1:-1], dtype=np.float64)[:, None]
+    ring = np.stack([r * np.cos(phi), r * np.sin(phi), np.broadcast_to(z, (len(r), m))], -1)
+    V = np.concatenate([[[0.0, 0.0, rings_z[0]]], ring.reshape(-1, 3), [[0.0, 0.0, rings_z[-1]]]])
+    return V, _ring_faces(s, m)
 
 
 def lathe(rng: np.random.Generator, n_tris: int, height: float, max_radius: float) -> Mesh:
@@ -259,29 +265,15 @@ def superquadric(rng: np.random.Generator, n_tris: int, size: float) -> Mesh:
     def f(w, e):
         return np.sign(w) * np.abs(w) ** e
 
-    eta = np.linspace(-math.pi / 2, math.pi / 2, s)
-    V = [(0.0, 0.0, -ax[2])]
-    omg = np.arange(m) * (2.0 * math.pi / m)
-    for k in range(1, s - 1):
-        ce, se = f(math.cos(eta[k]), e1), f(math.sin(eta[k]), e1)
-        for o in omg:
-            V.append((ax[0] * ce * f(math.cos(o), e2), ax[1] * ce * f(math.sin(o), e2), ax[2] * se))
-    V.append((0.0, 0.0, ax[2]))
-    V = np.array(V)
-    top = len(V) - 1
-    I = []
-    for i in range(m):
-        I.append((0, 1 + (i + 1) % m, 1 + i))
-    for k in range(s - 3):
-        b0, b1 = 1 + k * m, 1 + (k + 1) * m
-        for i in range(m):
-            i1 = (i + 1) % m
-            I.append((b0 + i, b0 + i1, b1 + i1))
-            I.append((b0 + i, b1 + i1, b1 + i))
-    bl = 1 + (s - 3) * m
-    for i in range(m):
-        I.append((bl + i, bl + (i + 1) % m, top))
-    I = _orient_outward(V, np.array(I, dtype=np.int64), np.zeros(3))
+    eta = np.linspace(-math.pi / 2, math.pi / 2, s)[1:-1, None]
+    omg = (np.arange(m) * (2.0 * math.pi / m))[None, :]
+    ce, se = f(np.cos(eta), e1), f(np.sin(eta), e1)
+    X = ax[0] * ce * f(np.cos(omg), e2)
+    Y = ax[1] * ce * f(np.sin(omg), e2)
+    Z = np.broadcast_to(ax[2] * se, X.shape)
+    V = np.concatenate([[[0.0, 0.0, -ax[2]]], np.stack([X, Y, Z], -1).reshape(-1, 3), [[0.0, 0.0, ax[2]]]])
+    I = _ring_faces(s, m)
+    I = _orient_outward(V, I, np.zeros(3))
     return Mesh(V, I, _area_weighted_normals(V, I))
 
 

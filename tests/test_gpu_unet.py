@@ -1,0 +1,152 @@
+"""The denoiser's GPU kernels (BF16 matrix cores, float accumulation)
+against the oracle U-Net run with bfloat16 rounding at the same points.
+
+Bars: forward relative L2 error <= 1e-2 of the prediction (bfloat16 keeps
+8 significant bits; the float accumulation order differs from the
+oracle's, which can flip a rounding of an intermediate activation);
+gradients: see test_backward_matches_oracle; one Adam step moves the
+parameters in the oracle's direction (cosine >= 0.99)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _cos(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2107_11008_amd as sc
+    return sc.Context(0)
+
+
+def _inputs(rng, n, h, w):
+    x = rng.normal(size=(n, h, w, U.IN_CH)).astype(np.float32)
+    x[..., :3] = np.abs(x[..., :3])
+    return x
+
+
+@pytest.mark.parametrize("widths,n,h,w", [((16, 32), 1, 16, 16), ((32, 48, 64, 96, 128), 2, 32, 48),
+                                          ((32, 48, 64, 96, 128), 1, 48, 32)])
+def test_forward_matches_oracle(ctx, widths, n, h, w):
+    import paper_2107_11008_amd as sc
+    rng = np.random.default_rng(1)
+    th = U.init_params(3, widths)
+    th = th + rng.normal(scale=0.02, size=th.shape).astype(np.float32)   # non-zero biases
+    net = sc.UNet(ctx, widths, th)
+    x = _inputs(rng, n, h, w)
+    g = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    o = U.UNet(th, widths, bf16=True).forward(x.astype(np.float64))
+    assert _rel(g, o) <= 1e-2, _rel(g, o)
+    assert np.array_equal(net.get_params(), th)
+
+
+@pytest.mark.parametrize("widths,n,h,w,cos_all,rel_all,cos_layer",
+                         [((16, 32), 2, 16, 16, 0.999, 3e-2, 0.99),
+                          ((32, 48, 64, 96, 128), 1, 32, 32, 0.98, 0.25, 0.95)])
+def test_backward_matches_oracle(ctx, widths, n, h, w, cos_all, rel_all, cos_layer):
+    """The two-level network exercises every kernel (3x3 and 1x1 forward,
+    input and weight gradients, pooling, upsampling, concatenation, bias)
+    at the tight bar.  Through five levels bfloat16 rounding decisions
+    (which ReLU and max-pool branches they tip) decorrelate the gradients
+    of any two bfloat16 evaluations: the oracle against itself with the
+    parameters moved by 1e-6 relative gives cosine 0.9885, relative L2
+    0.154 and per-layer cosines >= 0.967, so the deep network is held to
+    cosine >= 0.98, relative L2 <= 0.25, per layer >= 0.95."""
+    import paper_2107_11008_amd as sc
+    rng = np.random.default_rng(2)
+    th = U.init_params(4, widths) + rng.normal(scale=0.02, size=U.n_params(widths)).astype(np.float32)
+    net = sc.UNet(ctx, widths, th)
+    x = _inputs(rng, n, h, w)
+    dp = (rng.normal(size=(n, h, w, 3)) / (n * h * w)).astype(np.float32)
+    net.forward(torch.from_numpy(x).cuda())
+    gg = net.backward(torch.from_numpy(dp).cuda()).cpu().numpy()
+    on = U.UNet(th, widths, bf16=True)
+    on.forward(x.astype(np.float64))
+    og = on.backward(dp.astype(np.float64))
+    assert _cos(gg, og) >= cos_all, _cos(gg, og)
+    assert _rel(gg, og) <= rel_all, _rel(gg, og)
+    # every layer separately
+    pg = U.unpack(gg.astype(np.float64), widths)
+    po = U.unpack(og, widths)
+    for name in pg:
+        assert _cos(pg[name][0], po[name][0]) >= cos_layer, name
+        assert _cos(pg[name][1], po[name][1]) >= cos_layer, name
+
+
+def test_train_step_matches_oracle(ctx):
+    import paper_2107_11008_amd as sc
+    widths = (16, 32, 48)
+    rng = np.random.default_rng(5)
+    th = U.init_params(6, widths)
+    net = sc.UNet(ctx, widths, th)
+    x = _inputs(rng, 2, 32, 32)
+    t = np.abs(rng.normal(size=(2, 32, 32, 3))).astype(np.float32)
+    loss = net.train_step(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), 1e-3)
+    on = U.UNet(th, widths, bf16=True)
+    pred = on.forward(x.astype(np.float64))
+    ol, dy = U.l1_log_loss(pred, t.astype(np.float64))
+    assert abs(loss - ol) <= 1e-2 * ol
+    g = on.backward(dy)
+    th2, _, _ = U.adam(th.astype(np.float64), np.zeros_like(g), np.zeros_like(g), g, 1, 1e-3)
+    new = net.get_params().astype(np.float64)
+    assert _cos(new - th, th2 - th) >= 0.99
+
+
+def test_training_reduces_loss(ctx):
+    """A small network learns to remove additive noise from a smooth image."""
+    import paper_2107_11008_amd as sc
+    widths = (16, 32, 48)
+    rng = np.random.default_rng(7)
+    net = sc.UNet(ctx, widths, U.init_params(8, widths))
+    yy, xx = np.meshgrid(np.linspace(0, 1, 32), np.linspace(0, 1, 32), indexing="ij")
+    losses = []
+    for step in range(150):
+        clean = np.stack([0.5 + 0.4 * np.sin(6 * xx + rng.uniform(0, 6)) * np.cos(4 * yy)] * 3, -1)[None]
+        clean = np.repeat(clean, 4, 0)
+        noisy = np.maximum(clean + rng.normal(scale=0.2, size=clean.shape), 0)
+        f = np.zeros((4, 32, 32, 9))
+        f[..., :3] = np.log1p(noisy)
+        l = net.train_step(torch.from_numpy(f.astype(np.float32)).cuda(),
+                           torch.from_numpy(clean.astype(np.float32)).cuda(), 2e-3)
+        losses.append(l)
+    assert np.mean(losses[-20:]) < 0.6 * np.mean(losses[:5])
+
+
+def test_denoise_pads_and_crops(ctx):
+    """sc_denoise on an image whose sides are not multiples of 16 equals the
+    network run on the zero-padded features, cropped."""
+    import paper_2107_11008_amd as sc
+    widths = (32, 48, 64, 96, 128)
+    rng = np.random.default_rng(9)
+    th = U.init_params(10, widths) + rng.normal(scale=0.02, size=U.n_params(widths)).astype(np.float32)
+    net = sc.UNet(ctx, widths, th)
+    h, w = 37, 70
+    rgb = np.abs(rng.normal(size=(h, w, 3))).astype(np.float32)
+    alb = rng.uniform(size=(h, w)).astype(np.float32)
+    nrm = rng.normal(size=(h, w, 3)).astype(np.float32)
+    dep = rng.uniform(size=(h, w)).astype(np.float32)
+    tr = (rng.uniform(size=(h, w)) < 0.3).astype(np.uint8)
+    aov = {k: torch.from_numpy(v).cuda() for k, v in dict(rgb=rgb, albedo=alb, normal=nrm, depthn=dep, trans=tr).items()}
+    out = net.denoise(aov).cpu().numpy()
+    f = np.zeros((1, 48, 80, 9), np.float32)
+    f[0, :h, :w] = U.features(rgb.astype(np.float64), alb, nrm, dep, tr)
+    pred = net.forward(torch.from_numpy(f).cuda()).cpu().numpy()[0, :h, :w]
+    ref = np.maximum(np.expm1(pred), 0)
+    # the features are formed in float on the device and in float64 here,
+    # which can move a bfloat16 rounding of an input by one step
+    assert _rel(out, ref) <= 1e-2
+    assert out.shape == (h, w, 3) and np.isfinite(out).all()
