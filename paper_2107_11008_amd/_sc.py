@@ -7,8 +7,11 @@ library is missing this module raises; there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -17,6 +20,22 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsc.so")
 _lib = None
+
+# Live handles, released before the HIP runtime and PyTorch shut down: this
+# hook is registered after torch's, so it runs first.
+_live = {"unet": weakref.WeakSet(), "bvh": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+
+
+def _release_all():
+    for kind in ("unet", "bvh", "ctx"):
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+atexit.register(_release_all)
 
 SC_OPT_COUNT_VISITS = 1
 SC_OPT_PROFILE = 2
@@ -182,6 +201,7 @@ class Context:
         h = C.c_void_p()
         _check(L.sc_create(device, C.c_void_p(stream), C.byref(h)), "sc_create")
         self.h = h
+        _live["ctx"].add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -189,6 +209,8 @@ class Context:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -307,6 +329,7 @@ class Bvh:
         h = C.c_void_p()
         _check(load().sc_build_bvh(ctx.h, C.byref(s), C.byref(opts), C.byref(h)), "sc_build_bvh")
         self.h = h
+        _live["bvh"].add(self)
 
     def info(self) -> dict:
         i = BvhInfo()
@@ -328,6 +351,8 @@ class Bvh:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -344,6 +369,7 @@ class UNet:
         h = C.c_void_p()
         _check(load().sc_unet_create(ctx.h, arr, len(self.widths), C.byref(h)), "sc_unet_create")
         self.h = h
+        _live["unet"].add(self)
         n = C.c_uint64()
         _check(load().sc_unet_num_params(self.h, C.byref(n)), "sc_unet_num_params")
         self.n_params = n.value
@@ -395,6 +421,8 @@ class UNet:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
