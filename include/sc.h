@@ -253,6 +253,46 @@ sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32
                     const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, const sc_aov* out);
 
 /* ------------------------------------------------------------------
+ * Batched form: many scenes of uneven size rendered by persistent kernels
+ * whose waves pull work items (64*m photons or pixels of one scene) from a
+ * global counter; each lane follows its photon or its pixel's paths to the
+ * end with the same per-path code as sc_trace_photons / sc_render, so every
+ * output equals the one-scene result bit for bit.  The batch (clears,
+ * photon pass, map conversion, rendering) is captured once in a hipGraph.
+ * The paper's dataset is many such scenes (Sec. IV-A-2).
+ * ------------------------------------------------------------------ */
+typedef struct sc_batch sc_batch;
+
+typedef struct {
+    const sc_bvh* bvh;        /* scene and its BVH (built by sc_build_bvh) */
+    sc_camera cam;
+    uint32_t spp, max_depth;
+    sc_wavelengths wl;
+    uint64_t seed;            /* camera paths */
+    uint64_t photon_seed;
+    uint64_t n_photons;       /* 0: no photon pass; caustic_map (if not NULL) is then only gathered */
+    float* caustic_map;       /* device [hc][wc][C], written by the photon pass; NULL with n_photons > 0
+                                 = held by the batch */
+    sc_aov out;               /* device outputs as in sc_render (NULL fields are skipped) */
+} sc_batch_item;
+
+typedef struct {
+    uint32_t block_size;      /* threads per block: 64, 128 or 256 */
+    uint32_t blocks_per_cu;   /* persistent blocks per compute unit, 1..32 */
+    uint32_t px_per_item;     /* pixels or photons per work item: a multiple of 64, <= 4096 */
+    uint32_t use_graph;       /* 1: capture in a hipGraph at creation, replay at every run */
+} sc_tune;
+
+/* Prepare a batch (the items' device buffers must outlive it).  tune NULL
+ * = {128, 8, 64, 1}.  EINVAL on an invalid item or tuning value. */
+sc_status sc_batch_create(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune* tune, sc_batch** out);
+/* Run every photon pass and render of the batch (one graph launch). */
+sc_status sc_batch_run(sc_ctx* ctx, sc_batch* batch);
+sc_status sc_batch_free(sc_batch* batch);
+/* create + run + free; synchronises. */
+sc_status sc_render_batch(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune* tune);
+
+/* ------------------------------------------------------------------
  * Learned denoiser.  A U-Net (the network family the paper trains for
  * segmentation, Sec. IV-A-3; Ronneberger et al. 2015) maps a low-sample
  * render and its ground-truth buffers to a clean image.  Per level two 3x3

@@ -23,11 +23,11 @@ _lib = None
 
 # Live handles, released before the HIP runtime and PyTorch shut down: this
 # hook is registered after torch's, so it runs first.
-_live = {"unet": weakref.WeakSet(), "bvh": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+_live = {"batch": weakref.WeakSet(), "unet": weakref.WeakSet(), "bvh": weakref.WeakSet(), "ctx": weakref.WeakSet()}
 
 
 def _release_all():
-    for kind in ("unet", "bvh", "ctx"):
+    for kind in ("batch", "unet", "bvh", "ctx"):
         for obj in list(_live[kind]):
             try:
                 obj.close()
@@ -88,6 +88,17 @@ class Aov(C.Structure):
                 ("normal_cam", C.c_void_p), ("albedo", C.c_void_p)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("bvh", C.c_void_p), ("cam", Camera), ("spp", C.c_uint32), ("max_depth", C.c_uint32),
+                ("wl", Wavelengths), ("seed", C.c_uint64), ("photon_seed", C.c_uint64), ("n_photons", C.c_uint64),
+                ("caustic_map", C.c_void_p), ("out", Aov)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("block_size", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("px_per_item", C.c_uint32),
+                ("use_graph", C.c_uint32)]
+
+
 class PhotonStats(C.Structure):
     _fields_ = [("flux", C.c_double * 9), ("count", C.c_uint64 * 9), ("segments", C.c_uint64)]
 
@@ -108,7 +119,8 @@ EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set
            "sc_sync", "sc_get_counters", "sc_reset_counters", "sc_build_bvh", "sc_bvh_get_info", "sc_bvh_free", "sc_bvh_export",
            "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render",
            "sc_unet_create", "sc_unet_free", "sc_unet_num_params", "sc_unet_set_params", "sc_unet_get_params",
-           "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise"]
+           "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise",
+           "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch"]
 
 
 def load(path: str = LIB_PATH):
@@ -137,6 +149,10 @@ def load(path: str = LIB_PATH):
     L.sc_occluded.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
     L.sc_trace_photons.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, vp, vp, C.POINTER(PhotonStats)]
     L.sc_render.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, C.POINTER(Aov)]
+    L.sc_batch_create.argtypes = [vp, u32, vp, C.POINTER(Tune), C.POINTER(vp)]
+    L.sc_batch_run.argtypes = [vp, vp]
+    L.sc_batch_free.argtypes = [vp]
+    L.sc_render_batch.argtypes = [vp, u32, vp, C.POINTER(Tune)]
     L.sc_unet_create.argtypes = [vp, vp, u32, C.POINTER(vp)]
     L.sc_unet_free.argtypes = [vp]
     L.sc_unet_num_params.argtypes = [vp, C.POINTER(u64)]
@@ -418,6 +434,75 @@ class UNet:
     def close(self):
         if getattr(self, "h", None):
             load().sc_unet_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many scenes rendered by the persistent, graph-captured batch kernels.
+
+    items: list of dicts with keys bvh, cam, spp, max_depth, wl, seed,
+    photon_seed, n_photons and optionally caustic_map (tensor) and outputs
+    (names as in Context.render).  Output tensors are allocated here and
+    returned by outputs()."""
+
+    _SHAPES = dict(rgb=(3, torch.float32), obj=(None, torch.int32), trans=(None, torch.uint8),
+                   tri=(None, torch.int32), depth=(None, torch.float32), depthn=(None, torch.float32),
+                   normal=(3, torch.float32), normal_cam=(3, torch.float32), albedo=(None, torch.float32))
+
+    def __init__(self, ctx: Context, items, tune: Optional[dict] = None):
+        self.ctx = ctx
+        self.items = items
+        arr = (BatchItem * len(items))()
+        self._outs = []
+        self._keep = []
+        for i, it in enumerate(items):
+            a = arr[i]
+            a.bvh = it["bvh"].h
+            a.cam = camera_struct(it["cam"])
+            a.spp, a.max_depth = int(it["spp"]), int(it["max_depth"])
+            a.wl = wavelengths_struct(it["wl"])
+            a.seed, a.photon_seed, a.n_photons = int(it["seed"]), int(it.get("photon_seed", 0)), int(it.get("n_photons", 0))
+            cm = it.get("caustic_map")
+            if cm is None and a.n_photons:
+                r = it["bvh"].scene.receiver
+                cm = torch.empty((r.hc, r.wc, it["wl"].channels), dtype=torch.float32, device=ctx.device)
+            a.caustic_map = _ptr(cm)
+            H, W = it["cam"].h, it["cam"].w
+            outs = {"caustic_map": cm}
+            for k in it.get("outputs", ("rgb", "obj", "trans", "tri", "depth", "depthn", "normal", "normal_cam",
+                                        "albedo")):
+                c, dt = self._SHAPES[k]
+                outs[k] = torch.empty((H, W) if c is None else (H, W, c), dtype=dt, device=ctx.device)
+                setattr(a.out, k, _ptr(outs[k]))
+            self._outs.append(outs)
+        self._arr = arr
+        t = None
+        if tune is not None:
+            t = Tune(int(tune["block_size"]), int(tune["blocks_per_cu"]), int(tune["px_per_item"]),
+                     int(tune.get("use_graph", 1)))
+        h = C.c_void_p()
+        _check(load().sc_batch_create(ctx.h, len(items), C.cast(arr, C.c_void_p), C.byref(t) if t else None,
+                                      C.byref(h)), "sc_batch_create")
+        self.h = h
+        _live["batch"].add(self)
+
+    def run(self):
+        _check(load().sc_batch_run(self.ctx.h, self.h), "sc_batch_run")
+
+    def outputs(self):
+        return self._outs
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().sc_batch_free(self.h)
             self.h = None
 
     def __del__(self):

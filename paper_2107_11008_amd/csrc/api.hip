@@ -14,15 +14,13 @@
 #include "sc_internal.h"
 #include "sc_kernels.h"
 #include "sc_unet.h"
+#include "sc_batch.h"
 
-struct sc_ctx {
-    scl::Ctx c;
-};
-struct sc_bvh {
-    scl::Bvh b;
-};
 struct sc_unet {
     scl::Unet u;
+};
+struct sc_batch {
+    scl::Batch bt;
 };
 
 namespace scl {
@@ -329,6 +327,61 @@ sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32
     if ((uint64_t)cam->w * cam->h > (1ull << 28)) return set_error(SC_EUNSUPPORTED, "image too large");
     if (caustic_map && !bvh->b.scene.recv_obj) return set_error(SC_EINVAL, "caustic map given but no receiver");
     return scl::render(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), *cam, spp, max_depth, *wl, seed, caustic_map, *out);
+}
+
+sc_status sc_batch_create(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune* tune, sc_batch** out) {
+    if (!ctx || !items || !out) return set_error(SC_EINVAL, "ctx, items or out is NULL");
+    *out = nullptr;
+    if (n == 0) return set_error(SC_EINVAL, "empty batch");
+    sc_tune t = tune ? *tune : sc_tune{128, 8, 64, 1};
+    if (!(t.block_size == 64 || t.block_size == 128 || t.block_size == 256))
+        return set_error(SC_EINVAL, "block_size must be 64, 128 or 256");
+    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return set_error(SC_EINVAL, "blocks_per_cu must be 1..32");
+    if (t.px_per_item < 64 || t.px_per_item > 4096 || t.px_per_item % 64)
+        return set_error(SC_EINVAL, "px_per_item must be a multiple of 64 up to 4096");
+    for (uint32_t i = 0; i < n; ++i) {
+        const sc_batch_item& it = items[i];
+        const std::string where = "batch item " + std::to_string(i) + ": ";
+        if (!it.bvh) return set_error(SC_EINVAL, where + "bvh is NULL");
+        SC_TRY(check_wavelengths(&it.wl));
+        if (it.spp == 0 || it.max_depth == 0) return set_error(SC_EINVAL, where + "spp and max_depth must be >= 1");
+        if (it.cam.w == 0 || it.cam.h == 0) return set_error(SC_EINVAL, where + "camera has no pixels");
+        if ((uint64_t)it.cam.w * it.cam.h > (1ull << 28)) return set_error(SC_EUNSUPPORTED, where + "image too large");
+        if ((it.n_photons || it.caustic_map) && !it.bvh->b.scene.recv_obj)
+            return set_error(SC_EINVAL, where + "caustics need a receiver");
+        if (it.bvh->b.ctx != &ctx->c) return set_error(SC_EINVAL, where + "bvh belongs to another context");
+    }
+    sc_batch* b = new (std::nothrow) sc_batch();
+    if (!b) return set_error(SC_ENOMEM, "host allocation failed");
+    sc_status s = scl::batch_create(&ctx->c, n, items, t, &b->bt);
+    if (s != SC_OK) {
+        delete b;
+        return s;
+    }
+    *out = b;
+    return SC_OK;
+}
+
+sc_status sc_batch_run(sc_ctx* ctx, sc_batch* batch) {
+    if (!ctx || !batch) return set_error(SC_EINVAL, "ctx or batch is NULL");
+    if (batch->bt.ctx != &ctx->c) return set_error(SC_EINVAL, "batch belongs to another context");
+    return scl::batch_run(&batch->bt);
+}
+
+sc_status sc_batch_free(sc_batch* batch) {
+    if (!batch) return set_error(SC_EINVAL, "batch is NULL");
+    (void)hipStreamSynchronize(batch->bt.ctx->stream);
+    delete batch;
+    return SC_OK;
+}
+
+sc_status sc_render_batch(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune* tune) {
+    sc_batch* b = nullptr;
+    SC_TRY(sc_batch_create(ctx, n, items, tune, &b));
+    sc_status s = sc_batch_run(ctx, b);
+    if (s == SC_OK && hipStreamSynchronize(ctx->c.stream) != hipSuccess) s = set_error(SC_EDEVICE, "batch failed");
+    sc_batch_free(b);
+    return s;
 }
 
 sc_status sc_unet_create(sc_ctx* ctx, const uint32_t* widths, uint32_t levels, sc_unet** out) {

@@ -79,7 +79,9 @@ struct Ctx {
     DevBuf photon;     // PhotonState arrays
     size_t photon_n = 0;
     DevBuf acc64;      // fixed-point caustic accumulator
-    DevBuf sensor;     // sensor curve table
+    DevBuf sensor;     // sensor curve table of the range [sensor_lo, sensor_hi]
+    float sensor_lo = -1.0f, sensor_hi = -1.0f;
+    uint32_t sensor_n = 0;
     DevBuf aos;        // SoA copies for sc_trace_rays / sc_occluded
     size_t aos_n = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -100,3 +102,10 @@ struct Bvh {
 sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max);
 
 }  // namespace scl
+
+struct sc_ctx {
+    scl::Ctx c;
+};
+struct sc_bvh {
+    scl::Bvh b;
+};

@@ -3,6 +3,8 @@
 #pragma once
 #include <stdint.h>
 
+#include <vector>
+
 #include "sc_internal.h"
 #include "sc_types.h"
 
@@ -34,6 +36,9 @@ sc_status trace_rays(Ctx* c, Bvh* b, uint32_t n, const float* O, const float* D,
                      float* v);
 sc_status occluded(Ctx* c, Bvh* b, uint32_t n, const float* O, const float* D, const float* tmax,
                    const uint32_t* excl, uint8_t* occ);
+uint32_t sensor_table(const sc_wavelengths& wl, std::vector<float>& tab);
+WaveDev wave_view(const sc_wavelengths& wl, const float* tab_dev, uint32_t n_tab);
+double photon_scale(const Bvh* b, uint64_t n_photons, const sc_wavelengths& wl);
 sc_status ctx_counters(Ctx* c, sc_counters* out);
 sc_status ctx_reset_counters(Ctx* c);
 sc_status ctx_init(Ctx* c);

@@ -1,0 +1,532 @@
+// sc_path.h -- per-ray and per-path device functions shared by the
+// wavefront kernels (one stage per launch, queues between stages) and the
+// persistent batched kernels (one lane follows a path to its end).  Both
+// call exactly these functions, so their results are bit-identical.
+#pragma once
+#pragma clang fp contract(off)
+
+#include "sc_device.h"
+
+namespace scd {
+
+constexpr int kLdsStack = 16;
+constexpr int kStackMax = 160;   // maximum traversal stack entries per ray
+
+// ---------------------------------------------------------------- traversal
+__device__ __forceinline__ float safe_inv(float d) {
+    const float a = fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d;
+    return 1.0f / a;
+}
+
+// search bound: a node is visited if its entry distance is within a
+// relative margin of the best hit, so equal-distance triangles with a
+// smaller index in other nodes are still found
+__device__ __forceinline__ float search_limit(float t) { return t + t * 9.765625e-04f; }
+
+// traversal stack: the first kLdsStack entries of each lane in LDS, deeper
+// entries in a private (scratch) array
+struct Spill {
+    uint2 e[kStackMax - kLdsStack];
+};
+
+template <int BS>
+__device__ __forceinline__ void push(uint2 (*lds)[BS], Spill& s, int& sp, uint2 e) {
+    if (sp < kLdsStack) lds[sp][threadIdx.x] = e;
+    else s.e[sp - kLdsStack] = e;
+    ++sp;
+}
+template <int BS>
+__device__ __forceinline__ uint2 pop(uint2 (*lds)[BS], Spill& s, int& sp) {
+    --sp;
+    return sp < kLdsStack ? lds[sp][threadIdx.x] : s.e[sp - kLdsStack];
+}
+
+__device__ __forceinline__ void cswap(uint32_t& ka, uint32_t& va, uint32_t& kb, uint32_t& vb) {
+    const bool sw = kb < ka;
+    const uint32_t k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+    const uint32_t v0 = sw ? vb : va, v1 = sw ? va : vb;
+    ka = k0; kb = k1; va = v0; vb = v1;
+}
+
+// Batcher's odd-even merge sort of 8 (key, value) pairs, ascending keys
+__device__ __forceinline__ void sort8(uint32_t* k, uint32_t* v) {
+#define SC_CS(a, b) cswap(k[a], v[a], k[b], v[b])
+    SC_CS(0, 1); SC_CS(2, 3); SC_CS(4, 5); SC_CS(6, 7);
+    SC_CS(0, 2); SC_CS(1, 3); SC_CS(4, 6); SC_CS(5, 7);
+    SC_CS(1, 2); SC_CS(5, 6);
+    SC_CS(0, 4); SC_CS(1, 5); SC_CS(2, 6); SC_CS(3, 7);
+    SC_CS(2, 4); SC_CS(3, 5);
+    SC_CS(1, 2); SC_CS(3, 4); SC_CS(5, 6);
+#undef SC_CS
+}
+
+struct NodeTest {
+    uint32_t key[8];
+    uint32_t ref[8];
+};
+
+// Box tests of the 8 children against (o, inv); near/far planes chosen by
+// the sign of each direction component.  key = entry distance bits, or
+// 0xffffffff when the child is missed or lies beyond tlim.
+__device__ __forceinline__ void test_node(const BNode* __restrict__ nd, F3 o, F3 inv, float tlim, NodeTest& r) {
+    const float4* q = reinterpret_cast<const float4*>(nd);
+    // q[0..1] lox, q[2..3] hix, q[4..5] loy, q[6..7] hiy, q[8..9] loz, q[10..11] hiz, q[12..13] child
+    const bool px = inv.x >= 0.0f, py = inv.y >= 0.0f, pz = inv.z >= 0.0f;
+    const float4 nx0 = q[px ? 0 : 2], nx1 = q[px ? 1 : 3], fx0 = q[px ? 2 : 0], fx1 = q[px ? 3 : 1];
+    const float4 ny0 = q[py ? 4 : 6], ny1 = q[py ? 5 : 7], fy0 = q[py ? 6 : 4], fy1 = q[py ? 7 : 5];
+    const float4 nz0 = q[pz ? 8 : 10], nz1 = q[pz ? 9 : 11], fz0 = q[pz ? 10 : 8], fz1 = q[pz ? 11 : 9];
+    const uint4 c0 = reinterpret_cast<const uint4*>(nd)[12];
+    const uint4 c1 = reinterpret_cast<const uint4*>(nd)[13];
+    const float nx[8] = {nx0.x, nx0.y, nx0.z, nx0.w, nx1.x, nx1.y, nx1.z, nx1.w};
+    const float fx[8] = {fx0.x, fx0.y, fx0.z, fx0.w, fx1.x, fx1.y, fx1.z, fx1.w};
+    const float ny[8] = {ny0.x, ny0.y, ny0.z, ny0.w, ny1.x, ny1.y, ny1.z, ny1.w};
+    const float fy[8] = {fy0.x, fy0.y, fy0.z, fy0.w, fy1.x, fy1.y, fy1.z, fy1.w};
+    const float nz[8] = {nz0.x, nz0.y, nz0.z, nz0.w, nz1.x, nz1.y, nz1.z, nz1.w};
+    const float fz[8] = {fz0.x, fz0.y, fz0.z, fz0.w, fz1.x, fz1.y, fz1.z, fz1.w};
+    const uint32_t ch[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float tnx = (nx[c] - o.x) * inv.x, tfx = (fx[c] - o.x) * inv.x;
+        const float tny = (ny[c] - o.y) * inv.y, tfy = (fy[c] - o.y) * inv.y;
+        const float tnz = (nz[c] - o.z) * inv.z, tfz = (fz[c] - o.z) * inv.z;
+        const float tn = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
+        const float tf = fminf(fminf(tfx, tfy), tfz);
+        const bool hit = (tn <= tf + fabsf(tf) * 9.765625e-04f) && (tn <= tlim);
+        r.key[c] = hit ? __float_as_uint(tn) : 0xffffffffu;
+        r.ref[c] = ch[c];
+    }
+}
+
+__device__ __forceinline__ F3 perm(const RayPre& r, float4 p) { return permute(r, F3{p.x, p.y, p.z}); }
+
+struct HitRec {
+    float t, u, v;
+    uint32_t prim;
+};
+
+struct VisitCount {
+    unsigned long long nodes = 0, tris = 0;
+};
+
+// Closest hit: lexicographic minimum of (t, triangle) over the scene.
+template <int BS, bool COUNT>
+__device__ __forceinline__ HitRec trace_closest(const DevScene& S, F3 o, F3 d, uint2 (*lds)[BS], Spill& st,
+                                                VisitCount& vc) {
+    const RayPre rp = ray_prepare(o, d);
+    const F3 inv{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
+    float tb = INFINITY, bV = 0.0f, bW = 0.0f, brcp = 0.0f;
+    uint32_t pb = 0xffffffffu;
+    int sp = 0;
+    uint32_t ref = 0;   // root node
+    bool have = true;
+    while (have) {
+        if (!(ref & SC_LEAF_BIT)) {
+            NodeTest nt;
+            test_node(S.nodes + ref, o, inv, search_limit(tb), nt);
+            if (COUNT) ++vc.nodes;
+            sort8(nt.key, nt.ref);
+            if (nt.key[0] != 0xffffffffu) {
+#pragma unroll
+                for (int c = 7; c >= 1; --c)
+                    if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, sp, make_uint2(nt.ref[c], nt.key[c]));
+                ref = nt.ref[0];
+                continue;
+            }
+        } else {
+            const uint32_t first = ref & SC_LEAF_FIRST_MASK;
+            const uint32_t cnt = ((ref >> 28) & 7u) + 1u;
+            if (COUNT) vc.tris += cnt;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const float4* tp = S.tris + 3 * (size_t)(first + k);
+                const float4 a = tp[0], b = tp[1], c = tp[2];
+                const uint32_t prim = __float_as_uint(a.w);
+                TriHit h;
+                if (tri_test(rp, perm(rp, a), perm(rp, b), perm(rp, c), h)) {
+                    if (h.t < tb || (h.t == tb && prim < pb)) {
+                        tb = h.t; pb = prim; bV = h.V; bW = h.W; brcp = h.rcp;
+                    }
+                }
+            }
+        }
+        // next entry from the stack that is still within reach
+        have = false;
+        while (sp > 0) {
+            const uint2 e = pop<BS>(lds, st, sp);
+            if (__uint_as_float(e.y) <= search_limit(tb)) {
+                ref = e.x;
+                have = true;
+                break;
+            }
+        }
+    }
+    return HitRec{tb, bV * brcp, bW * brcp, pb};
+}
+
+// Any hit with 0 < t < tmax, skipping triangle excl.
+template <int BS>
+__device__ __forceinline__ bool trace_any(const DevScene& S, F3 o, F3 d, float tmax, uint32_t excl, uint2 (*lds)[BS],
+                                          Spill& st) {
+    const RayPre rp = ray_prepare(o, d);
+    const F3 inv{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
+    const float tlim = search_limit(tmax);
+    int sp = 0;
+    uint32_t ref = 0;
+    for (;;) {
+        if (!(ref & SC_LEAF_BIT)) {
+            NodeTest nt;
+            test_node(S.nodes + ref, o, inv, tlim, nt);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, sp, make_uint2(nt.ref[c], nt.key[c]));
+        } else {
+            const uint32_t first = ref & SC_LEAF_FIRST_MASK;
+            const uint32_t cnt = ((ref >> 28) & 7u) + 1u;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const float4* tp = S.tris + 3 * (size_t)(first + k);
+                const float4 a = tp[0], b = tp[1], c = tp[2];
+                if (__float_as_uint(a.w) == excl) continue;
+                TriHit h;
+                if (tri_test(rp, perm(rp, a), perm(rp, b), perm(rp, c), h) && h.t < tmax) return true;
+            }
+        }
+        if (sp == 0) return false;
+        ref = pop<BS>(lds, st, sp).x;
+    }
+}
+
+// ---------------------------------------------------------------- camera paths
+struct CamPath {
+    F3 o, d;
+    float T, L, lam;
+    uint32_t flags;   // bit 0: a diffuse vertex was seen
+};
+
+struct ShadowReq {
+    F3 o, d;
+    float tmax, contrib;
+    uint32_t excl;
+    bool shoot;
+};
+
+// ray through the jittered film point; wavelength of the slot (fixed) or
+// drawn uniformly (spectral); throughput 1, radiance 0
+__device__ __forceinline__ CamPath camera_start(const sc_camera& cam, const WaveDev& wl, uint64_t seed, uint32_t pix,
+                                                uint32_t sample, uint32_t slot) {
+    CamPath P;
+    const uint32_t x = pix % cam.w, y = pix / cam.w;
+    const U4 r = rng_camera(seed, pix, sample, 0, 0, slot);
+    P.lam = wl.mode == SC_WL_FIXED ? wl.nm[slot] : lambda_from(wl, unit(r.c));
+    camera_ray(cam, x, y, unit(r.a), unit(r.b), P.o, P.d);
+    P.T = 1.0f;
+    P.L = 0.0f;
+    P.flags = 0u;
+    return P;
+}
+
+// emitter hit: its front-face radiance counts only before any diffuse vertex
+__device__ __forceinline__ void camera_emission(const DevScene& S, const HitRec& h, CamPath& P) {
+    if (P.flags & 1u) return;
+    const sc_material m = S.mat[S.tri_obj[h.prim]];
+    F3 p0, p1, p2;
+    tri_vertices(S, h.prim, p0, p1, p2);
+    const F3 Ng = normalize(cross(p1 - p0, p2 - p0));
+    if (dot(P.d, Ng) < 0.0f) P.L = P.L + P.T * m.le;
+}
+
+// dielectric hit: reflect or refract; false if the path ends here
+__device__ __forceinline__ bool camera_dielectric(const DevScene& S, uint64_t seed, uint32_t pix, uint32_t sample,
+                                                  uint32_t slot, uint32_t depth, uint32_t max_depth, const HitRec& h,
+                                                  CamPath& P) {
+    const Frame f = hit_frame(S, h.prim, h.u, h.v, P.d);
+    const sc_material m = S.mat[S.tri_obj[h.prim]];
+    const U4 r = rng_camera(seed, pix, sample, depth, 1, slot);
+    F3 nd;
+    bool refl;
+    if (!dielectric(f, P.d, P.lam, m.cauchy_a, m.cauchy_b, unit(r.c), nd, refl)) return false;
+    P.o = offset_ray(f.P, refl ? f.Nf : neg(f.Nf));
+    P.d = nd;
+    return depth < max_depth;
+}
+
+// diffuse hit: caustic gather added to L, one light sample prepared as a
+// shadow ray (its contribution is added if unoccluded), cosine-weighted
+// bounce; false if the path ends here
+__device__ __forceinline__ bool camera_diffuse(const DevScene& S, const WaveDev& wl, const float* __restrict__ cmap,
+                                               uint64_t seed, uint32_t pix, uint32_t sample, uint32_t slot,
+                                               uint32_t depth, uint32_t max_depth, const HitRec& h, CamPath& P,
+                                               ShadowReq& sr) {
+    const uint32_t obj = S.tri_obj[h.prim];
+    const Frame f = hit_frame(S, h.prim, h.u, h.v, P.d);
+    const sc_material m = S.mat[obj];
+    const float rho = albedo(S, m, f.P);
+    const float T = P.T;
+    P.flags = P.flags | 1u;
+    const F3 os = offset_ray(f.P, f.Nf);
+    sr.shoot = false;
+    // caustic gather
+    if (cmap && S.recv_obj && obj == S.recv_obj) {
+        const int64_t cell = receiver_cell(S, f.P);
+        if (cell >= 0) {
+            const uint32_t b = wl.mode == SC_WL_FIXED ? slot : spectral_bin(wl, P.lam);
+            const float E = cmap[(size_t)cell * wl.channels + b] * S.inv_cell_area;
+            const float g = ((T * rho) * kInvPi) * E;
+            P.L = P.L + g;
+        }
+    }
+    // next event estimation
+    if (S.n_entries > 0) {
+        const U4 r = rng_camera(seed, pix, sample, depth, 2, slot);
+        const uint32_t e = pick_entry(S.n_entries, unit(r.c));
+        if (e < S.n_pl) {
+            const float* lp = S.pl + 4 * (size_t)e;
+            const F3 w = F3{lp[0], lp[1], lp[2]} - os;
+            const float r2 = dot(w, w);
+            const float dist = sqrtf(r2);
+            const F3 om = w * (1.0f / dist);
+            const float cosx = dot(f.Nf, om);
+            if (cosx > 0.0f) {
+                float contrib = ((((T * rho) * kInvPi) * lp[3]) * cosx) / r2;
+                contrib = contrib * (float)S.n_entries;
+                sr = ShadowReq{os, om, dist, contrib, 0xffffffffu, true};
+            }
+        } else {
+            const uint32_t k = cdf_first_above(S.emit_cdf, S.n_emit, unit(r.d));
+            const uint32_t lprim = S.emit_prim[k];
+            F3 Nl;
+            const F3 y = light_point(S, lprim, unit(r.a), unit(r.b), Nl);
+            const F3 w = y - os;
+            const float r2 = dot(w, w);
+            const float dist = sqrtf(r2);
+            const F3 om = w * (1.0f / dist);
+            const float cosx = dot(f.Nf, om);
+            const float cosl = -dot(Nl, om);
+            if (cosx > 0.0f && cosl > 0.0f) {
+                const float le = S.mat[S.tri_obj[lprim]].le;
+                float contrib = ((((((T * rho) * kInvPi) * le) * cosx) * cosl) / r2) * S.a_tot;
+                contrib = contrib * (float)S.n_entries;
+                sr = ShadowReq{os, om, dist * 0.9999f, contrib, lprim, true};
+            }
+        }
+    }
+    // cosine-weighted bounce
+    if (depth < max_depth) {
+        const U4 r = rng_camera(seed, pix, sample, depth, 1, slot);
+        const float u0 = unit(r.a), u1 = unit(r.b);
+        const float rr = sqrtf(u0);
+        float sp, cp;
+        sincos_turn(u1, sp, cp);
+        const float x = rr * cp, y = rr * sp;
+        const float z = sqrtf(fmaxf(0.0f, 1.0f - u0));
+        F3 t1, t2;
+        basis(f.Nf, t1, t2);
+        P.d = normalize((t1 * x + t2 * y) + f.Nf * z);
+        P.o = os;
+        P.T = T * rho;
+        return true;
+    }
+    return false;
+}
+
+// film: samples added in sample order (then slot order)
+__device__ __forceinline__ void film_add(const WaveDev& wl, uint32_t K, uint32_t slot, float L, float lam, float* acc) {
+    if (wl.mode == SC_WL_FIXED) {
+        if (K == 3) {
+            acc[slot] = acc[slot] + L;
+        } else {
+            acc[0] = acc[0] + L; acc[1] = acc[1] + L; acc[2] = acc[2] + L;
+        }
+    } else {
+        acc[0] = acc[0] + sensor(wl, 0, lam) * L;
+        acc[1] = acc[1] + sensor(wl, 1, lam) * L;
+        acc[2] = acc[2] + sensor(wl, 2, lam) * L;
+    }
+}
+
+// ground truth of the pixel-centre ray
+__device__ __forceinline__ void aov_write(const DevScene& S, const sc_camera& cam, uint32_t pix, F3 d, const HitRec& h,
+                                          const sc_aov& out) {
+    const F3 Rh = normalize(F3{cam.right[0], cam.right[1], cam.right[2]});
+    const F3 Uh = normalize(F3{cam.up[0], cam.up[1], cam.up[2]});
+    const F3 Fh = normalize(F3{cam.fwd[0], cam.fwd[1], cam.fwd[2]});
+    uint32_t obj = 0;
+    float dep = INFINITY, depn = 1.0f, alb = 0.0f;
+    F3 N{0.0f, 0.0f, 0.0f}, Nc{0.0f, 0.0f, 0.0f};
+    uint8_t trans = 0;
+    if (h.prim != 0xffffffffu) {
+        obj = S.tri_obj[h.prim];
+        const sc_material m = S.mat[obj];
+        const Frame f = hit_frame(S, h.prim, h.u, h.v, d);
+        dep = h.t;
+        depn = fminf(h.t / 10.0f, 1.0f);
+        N = f.Ns;
+        Nc = F3{dot(N, Rh), dot(N, Uh), -dot(N, Fh)};
+        alb = m.type == SC_MAT_DIFFUSE ? albedo(S, m, f.P) : (m.type == SC_MAT_DIELECTRIC ? 1.0f : 0.0f);
+        trans = m.type == SC_MAT_DIELECTRIC ? 1 : 0;
+    }
+    if (out.obj) out.obj[pix] = obj;
+    if (out.trans) out.trans[pix] = trans;
+    if (out.tri) out.tri[pix] = h.prim;
+    if (out.depth) out.depth[pix] = dep;
+    if (out.depthn) out.depthn[pix] = depn;
+    if (out.normal) store3(out.normal, pix, N);
+    if (out.normal_cam) store3(out.normal_cam, pix, Nc);
+    if (out.albedo) out.albedo[pix] = alb;
+}
+
+// ---------------------------------------------------------------- photons
+struct PhotonPath {
+    F3 o, d;
+    float phi, lam;
+    uint32_t slot, spec;
+};
+
+// 1 - cos(theta) of the cone subtended by a sphere of squared radius rr at
+// squared distance dist2, without cancellation
+__device__ __forceinline__ float cap_height(float rr, float dist2) {
+    const float q = rr / dist2;
+    return q >= 1.0f ? 2.0f : q / (1.0f + sqrtf(1.0f - q));
+}
+
+// Photon p of a pass of n_total: light point, cone towards a target sphere
+// picked by solid angle, direction uniform in the cone, flux = light power
+// x total solid angle x light entries / (photons in its slot x cones that
+// contain the direction).  False if the photon leaves an area light's back.
+__device__ __forceinline__ bool photon_emit(const DevScene& S, const WaveDev& wl, uint64_t seed, uint64_t n_total,
+                                            uint64_t p, PhotonPath& ph) {
+    const U4 r0 = rng_photon(seed, p, 0, 0);
+    uint32_t slot;
+    float lam, nslot;
+    if (wl.mode == SC_WL_FIXED) {
+        slot = (uint32_t)(p % wl.k);
+        lam = wl.nm[slot];
+        const uint64_t cnt = n_total / wl.k + ((p % wl.k) < (n_total % wl.k) ? 1u : 0u);
+        nslot = (float)cnt;
+    } else {
+        lam = lambda_from(wl, unit(r0.d));
+        slot = spectral_bin(wl, lam);
+        nslot = (float)n_total / (float)wl.bins;
+    }
+    const U4 r2 = rng_photon(seed, p, 0, 2);
+    const uint32_t e = pick_entry(S.n_entries, unit(r2.c));
+    F3 y, Nl{0.0f, 0.0f, 0.0f};
+    float power;
+    bool area = false;
+    if (e < S.n_pl) {
+        const float* lp = S.pl + 4 * (size_t)e;
+        y = F3{lp[0], lp[1], lp[2]};
+        power = lp[3];
+    } else {
+        const uint32_t k = cdf_first_above(S.emit_cdf, S.n_emit, unit(r2.d));
+        const uint32_t lprim = S.emit_prim[k];
+        y = light_point(S, lprim, unit(r2.a), unit(r2.b), Nl);
+        power = S.mat[S.tri_obj[lprim]].le * S.a_tot;
+        area = true;
+    }
+    float osum = 0.0f;
+    for (uint32_t k = 0; k < S.n_tg; ++k) {
+        const float* sp = S.tg + 4 * (size_t)k;
+        const F3 dk = F3{sp[0], sp[1], sp[2]} - y;
+        osum = osum + kTwoPi * cap_height(sp[3] * sp[3], dot(dk, dk));
+    }
+    const float target = unit(r0.a) * osum;
+    uint32_t kk = S.n_tg - 1;
+    float cum = 0.0f;
+    for (uint32_t k = 0; k < S.n_tg; ++k) {
+        const float* sp = S.tg + 4 * (size_t)k;
+        const F3 dk = F3{sp[0], sp[1], sp[2]} - y;
+        cum = cum + kTwoPi * cap_height(sp[3] * sp[3], dot(dk, dk));
+        if (cum > target) {
+            kk = k;
+            break;
+        }
+    }
+    const float* spk = S.tg + 4 * (size_t)kk;
+    const F3 dkk = F3{spk[0], spk[1], spk[2]} - y;
+    const float d2k = dot(dkk, dkk);
+    const float hk = cap_height(spk[3] * spk[3], d2k);
+    const F3 axis = dkk * (1.0f / sqrtf(d2k));
+    const float g = unit(r0.b) * hk;
+    const float cost = 1.0f - g;
+    const float sint = sqrtf(fmaxf(0.0f, g * (2.0f - g)));
+    float sp_, cp_;
+    sincos_turn(unit(r0.c), sp_, cp_);
+    F3 t1, t2;
+    basis(axis, t1, t2);
+    const F3 om = normalize((t1 * (cp_ * sint) + t2 * (sp_ * sint)) + axis * cost);
+    uint32_t m = 1;
+    for (uint32_t k = 0; k < S.n_tg; ++k) {
+        if (k == kk) continue;
+        const float* sp = S.tg + 4 * (size_t)k;
+        const F3 dk = F3{sp[0], sp[1], sp[2]} - y;
+        const float dist2 = dot(dk, dk);
+        const float q = (sp[3] * sp[3]) / dist2;
+        const F3 ax = dk * (1.0f / sqrtf(dist2));
+        const F3 cr = cross(om, ax);
+        if (q >= 1.0f || (dot(om, ax) > 0.0f && dot(cr, cr) <= q)) ++m;
+    }
+    bool alive = true;
+    if (area) {
+        const float cy = dot(Nl, om);
+        if (!(cy > 0.0f)) alive = false;
+        ph.phi = (((power * cy) * osum) * (float)S.n_entries) / (nslot * (float)m);
+        ph.o = offset_ray(y, Nl);
+    } else {
+        ph.phi = ((power * osum) * (float)S.n_entries) / (nslot * (float)m);
+        ph.o = y;
+    }
+    ph.d = om;
+    ph.lam = lam;
+    ph.slot = slot;
+    ph.spec = 0u;
+    return alive;
+}
+
+// One photon interaction.  Returns true if the photon continues; sets
+// outcome (SC_PH_*) when it ends, and cell_ch >= 0 for a deposit.
+__device__ __forceinline__ bool photon_event(const DevScene& S, const WaveDev& wl, uint64_t seed, uint64_t p,
+                                             uint32_t depth, uint32_t max_depth, const HitRec& h, PhotonPath& ph,
+                                             int& outcome, int64_t& cell_ch) {
+    cell_ch = -1;
+    if (h.prim == 0xffffffffu) {
+        outcome = SC_PH_ESCAPED;
+        return false;
+    }
+    const uint32_t obj = S.tri_obj[h.prim];
+    const sc_material m = S.mat[obj];
+    const Frame f = hit_frame(S, h.prim, h.u, h.v, ph.d);
+    if (m.type == SC_MAT_EMISSIVE) {
+        outcome = SC_PH_ABSORBED;
+        return false;
+    }
+    if (m.type == SC_MAT_DIELECTRIC) {
+        const U4 r = rng_photon(seed, p, depth, 1);
+        F3 nd;
+        bool refl;
+        if (!dielectric(f, ph.d, ph.lam, m.cauchy_a, m.cauchy_b, unit(r.c), nd, refl)) {
+            outcome = SC_PH_LOST;
+            return false;
+        }
+        ph.o = offset_ray(f.P, refl ? f.Nf : neg(f.Nf));
+        ph.d = nd;
+        ph.spec = ph.spec + 1u;
+        if (depth < max_depth) return true;
+        outcome = SC_PH_TRUNCATED;
+        return false;
+    }
+    if (ph.spec == 0u) {
+        outcome = SC_PH_DIRECT;
+    } else if (obj != S.recv_obj) {
+        outcome = SC_PH_ELSEWHERE;
+    } else {
+        const int64_t cell = receiver_cell(S, f.P);
+        if (cell < 0) {
+            outcome = SC_PH_OUTSIDE;
+        } else {
+            outcome = SC_PH_DEPOSITED;
+            cell_ch = cell * (int64_t)wl.channels + (int64_t)ph.slot;
+        }
+    }
+    return false;
+}
+
+}  // namespace scd

@@ -17,13 +17,14 @@
 #include "sc_device.h"
 #include "sc_internal.h"
 #include "sc_kernels.h"
+#include "sc_path.h"
 
 using namespace scd;
 
 namespace {
 
 constexpr int kTraceBS = 128;
-constexpr int kLdsStack = 16;
+static_assert(kStackMax == kMaxStack, "stack bound shared with the host check");
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -52,90 +53,6 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-__device__ __forceinline__ float safe_inv(float d) {
-    const float a = fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d;
-    return 1.0f / a;
-}
-
-// search bound: a node is visited if its entry distance is within a
-// relative margin of the best hit, so equal-distance triangles with a
-// smaller index in other nodes are still found
-__device__ __forceinline__ float search_limit(float t) { return t + t * 9.765625e-04f; }
-
-// traversal stack: the first kLdsStack entries of each lane in LDS, deeper
-// entries in a private (scratch) array
-struct Spill {
-    uint2 e[kMaxStack - kLdsStack];
-};
-
-__device__ __forceinline__ void push(uint2 (*lds)[kTraceBS], Spill& s, int& sp, uint2 e) {
-    if (sp < kLdsStack) lds[sp][threadIdx.x] = e;
-    else s.e[sp - kLdsStack] = e;
-    ++sp;
-}
-__device__ __forceinline__ uint2 pop(uint2 (*lds)[kTraceBS], Spill& s, int& sp) {
-    --sp;
-    return sp < kLdsStack ? lds[sp][threadIdx.x] : s.e[sp - kLdsStack];
-}
-
-__device__ __forceinline__ void cswap(uint32_t& ka, uint32_t& va, uint32_t& kb, uint32_t& vb) {
-    const bool sw = kb < ka;
-    const uint32_t k0 = sw ? kb : ka, k1 = sw ? ka : kb;
-    const uint32_t v0 = sw ? vb : va, v1 = sw ? va : vb;
-    ka = k0; kb = k1; va = v0; vb = v1;
-}
-
-// Batcher's odd-even merge sort of 8 (key, value) pairs, ascending keys
-__device__ __forceinline__ void sort8(uint32_t* k, uint32_t* v) {
-#define CS(a, b) cswap(k[a], v[a], k[b], v[b])
-    CS(0, 1); CS(2, 3); CS(4, 5); CS(6, 7);
-    CS(0, 2); CS(1, 3); CS(4, 6); CS(5, 7);
-    CS(1, 2); CS(5, 6);
-    CS(0, 4); CS(1, 5); CS(2, 6); CS(3, 7);
-    CS(2, 4); CS(3, 5);
-    CS(1, 2); CS(3, 4); CS(5, 6);
-#undef CS
-}
-
-struct NodeTest {
-    uint32_t key[8];
-    uint32_t ref[8];
-};
-
-// Box tests of the 8 children against (o, inv); near/far planes chosen by
-// the sign of each direction component.  key = entry distance bits, or
-// 0xffffffff when the child is missed or lies beyond tlim.
-__device__ __forceinline__ void test_node(const BNode* __restrict__ nd, F3 o, F3 inv, float tlim, NodeTest& r) {
-    const float4* q = reinterpret_cast<const float4*>(nd);
-    // q[0..1] lox, q[2..3] hix, q[4..5] loy, q[6..7] hiy, q[8..9] loz, q[10..11] hiz, q[12..13] child
-    const bool px = inv.x >= 0.0f, py = inv.y >= 0.0f, pz = inv.z >= 0.0f;
-    float4 nx0 = q[px ? 0 : 2], nx1 = q[px ? 1 : 3], fx0 = q[px ? 2 : 0], fx1 = q[px ? 3 : 1];
-    float4 ny0 = q[py ? 4 : 6], ny1 = q[py ? 5 : 7], fy0 = q[py ? 6 : 4], fy1 = q[py ? 7 : 5];
-    float4 nz0 = q[pz ? 8 : 10], nz1 = q[pz ? 9 : 11], fz0 = q[pz ? 10 : 8], fz1 = q[pz ? 11 : 9];
-    const uint4 c0 = reinterpret_cast<const uint4*>(nd)[12];
-    const uint4 c1 = reinterpret_cast<const uint4*>(nd)[13];
-    const float nx[8] = {nx0.x, nx0.y, nx0.z, nx0.w, nx1.x, nx1.y, nx1.z, nx1.w};
-    const float fx[8] = {fx0.x, fx0.y, fx0.z, fx0.w, fx1.x, fx1.y, fx1.z, fx1.w};
-    const float ny[8] = {ny0.x, ny0.y, ny0.z, ny0.w, ny1.x, ny1.y, ny1.z, ny1.w};
-    const float fy[8] = {fy0.x, fy0.y, fy0.z, fy0.w, fy1.x, fy1.y, fy1.z, fy1.w};
-    const float nz[8] = {nz0.x, nz0.y, nz0.z, nz0.w, nz1.x, nz1.y, nz1.z, nz1.w};
-    const float fz[8] = {fz0.x, fz0.y, fz0.z, fz0.w, fz1.x, fz1.y, fz1.z, fz1.w};
-    const uint32_t ch[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const float tnx = (nx[c] - o.x) * inv.x, tfx = (fx[c] - o.x) * inv.x;
-        const float tny = (ny[c] - o.y) * inv.y, tfy = (fy[c] - o.y) * inv.y;
-        const float tnz = (nz[c] - o.z) * inv.z, tfz = (fz[c] - o.z) * inv.z;
-        const float tn = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
-        const float tf = fminf(fminf(tfx, tfy), tfz);
-        const bool hit = (tn <= tf + fabsf(tf) * 9.765625e-04f) && (tn <= tlim);
-        r.key[c] = hit ? __float_as_uint(tn) : 0xffffffffu;
-        r.ref[c] = ch[c];
-    }
-}
-
-__device__ __forceinline__ F3 perm(const RayPre& r, float4 p) { return permute(r, F3{p.x, p.y, p.z}); }
-
 // ------------------------------------------------------------------ closest hit
 template <bool COUNT>
 __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitSoA H, const uint32_t* __restrict__ queue,
@@ -143,9 +60,9 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
                                                       uint32_t* __restrict__ work, DevCounters* __restrict__ C) {
     __shared__ uint2 lds[kLdsStack][kTraceBS];
     Spill st;
-    int sp = 0;
     const uint32_t n = count ? *count : n_static;
-    unsigned long long c_nodes = 0, c_tris = 0, c_rays = 0;
+    VisitCount vc;
+    unsigned long long c_rays = 0;
     for (;;) {
         uint32_t base = 0;
         if (lane_id() == 0) base = atomicAdd(work, 64u);
@@ -156,64 +73,19 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
             const uint32_t pid = queue ? queue[i] : i;
             const F3 o{R.ox[pid], R.oy[pid], R.oz[pid]};
             const F3 d{R.dx[pid], R.dy[pid], R.dz[pid]};
-            const RayPre rp = ray_prepare(o, d);
-            const F3 inv{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
-            float tb = INFINITY, bV = 0.0f, bW = 0.0f, brcp = 0.0f;
-            uint32_t pb = 0xffffffffu;
-            sp = 0;
-            uint32_t ref = 0;   // root node
-            bool have = true;
-            while (have) {
-                if (!(ref & SC_LEAF_BIT)) {
-                    NodeTest nt;
-                    test_node(S.nodes + ref, o, inv, search_limit(tb), nt);
-                    if (COUNT) ++c_nodes;
-                    sort8(nt.key, nt.ref);
-                    if (nt.key[0] != 0xffffffffu) {
-#pragma unroll
-                        for (int c = 7; c >= 1; --c)
-                            if (nt.key[c] != 0xffffffffu) push(lds, st, sp, make_uint2(nt.ref[c], nt.key[c]));
-                        ref = nt.ref[0];
-                        continue;
-                    }
-                } else {
-                    const uint32_t first = ref & SC_LEAF_FIRST_MASK;
-                    const uint32_t cnt = ((ref >> 28) & 7u) + 1u;
-                    if (COUNT) c_tris += cnt;
-                    for (uint32_t k = 0; k < cnt; ++k) {
-                        const float4* tp = S.tris + 3 * (size_t)(first + k);
-                        const float4 a = tp[0], b = tp[1], c = tp[2];
-                        const uint32_t prim = __float_as_uint(a.w);
-                        TriHit h;
-                        if (tri_test(rp, perm(rp, a), perm(rp, b), perm(rp, c), h)) {
-                            if (h.t < tb || (h.t == tb && prim < pb)) {
-                                tb = h.t; pb = prim; bV = h.V; bW = h.W; brcp = h.rcp;
-                            }
-                        }
-                    }
-                }
-                // next entry from the stack that is still within reach
-                have = false;
-                while (sp > 0) {
-                    const uint2 e = pop(lds, st, sp);
-                    if (__uint_as_float(e.y) <= search_limit(tb)) {
-                        ref = e.x;
-                        have = true;
-                        break;
-                    }
-                }
-            }
-            H.t[pid] = tb;
-            H.prim[pid] = pb;
-            if (H.u) H.u[pid] = bV * brcp;
-            if (H.v) H.v[pid] = bW * brcp;
+            const HitRec h = trace_closest<kTraceBS, COUNT>(S, o, d, lds, st, vc);
+            H.t[pid] = h.t;
+            H.prim[pid] = h.prim;
+            if (H.u) H.u[pid] = h.u;
+            if (H.v) H.v[pid] = h.v;
             ++c_rays;
         }
     }
     c_rays = wave_sum_u64(c_rays);
+    unsigned long long c_nodes = 0, c_tris = 0;
     if (COUNT) {
-        c_nodes = wave_sum_u64(c_nodes);
-        c_tris = wave_sum_u64(c_tris);
+        c_nodes = wave_sum_u64(vc.nodes);
+        c_tris = wave_sum_u64(vc.tris);
     }
     if (lane_id() == 0) {
         atomicAdd(&C->rays_closest, c_rays);
@@ -233,7 +105,6 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
                                                      float* __restrict__ L, DevCounters* __restrict__ C) {
     __shared__ uint2 lds[kLdsStack][kTraceBS];
     Spill st;
-    int sp = 0;
     const uint32_t n = count ? *count : n_static;
     unsigned long long c_rays = 0;
     for (;;) {
@@ -246,42 +117,8 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
             const uint32_t pid = queue ? queue[i] : i;
             const F3 o{R.ox[pid], R.oy[pid], R.oz[pid]};
             const F3 d{R.dx[pid], R.dy[pid], R.dz[pid]};
-            const float tmax = R.tmax[pid];
             const uint32_t excl = R.excl ? R.excl[pid] : 0xffffffffu;
-            const RayPre rp = ray_prepare(o, d);
-            const F3 inv{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
-            const float tlim = search_limit(tmax);
-            bool occluded = false;
-            sp = 0;
-            uint32_t ref = 0;
-            bool have = true;
-            while (have && !occluded) {
-                if (!(ref & SC_LEAF_BIT)) {
-                    NodeTest nt;
-                    test_node(S.nodes + ref, o, inv, tlim, nt);
-#pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (nt.key[c] != 0xffffffffu) push(lds, st, sp, make_uint2(nt.ref[c], nt.key[c]));
-                } else {
-                    const uint32_t first = ref & SC_LEAF_FIRST_MASK;
-                    const uint32_t cnt = ((ref >> 28) & 7u) + 1u;
-                    for (uint32_t k = 0; k < cnt; ++k) {
-                        const float4* tp = S.tris + 3 * (size_t)(first + k);
-                        const float4 a = tp[0], b = tp[1], c = tp[2];
-                        if (__float_as_uint(a.w) == excl) continue;
-                        TriHit h;
-                        if (tri_test(rp, perm(rp, a), perm(rp, b), perm(rp, c), h) && h.t < tmax) {
-                            occluded = true;
-                            break;
-                        }
-                    }
-                }
-                have = false;
-                if (!occluded && sp > 0) {
-                    ref = pop(lds, st, sp).x;
-                    have = true;
-                }
-            }
+            const bool occluded = trace_any<kTraceBS>(S, o, d, R.tmax[pid], excl, lds, st);
             if (occ_out) occ_out[pid] = occluded ? 1 : 0;
             if (L && !occluded) L[pid] = L[pid] + R.contrib[pid];
             ++c_rays;
@@ -301,10 +138,7 @@ __global__ void k_zero_u64(unsigned long long* p, size_t n) {
 __global__ void k_zero_f32(float* p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0f;
 }
-__global__ void k_set_count(uint32_t* counts, uint32_t idx, uint32_t v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) counts[idx] = v;
-}
-// counts[dst] = counts[src]; counts[src2..] zeroed
+// counts[0] = counts[1]; counts[1..4] = 0
 __global__ void k_rotate_counts(uint32_t* counts) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         counts[0] = counts[1];
@@ -351,21 +185,34 @@ __device__ __forceinline__ void pid_decode(const CamInfo& ci, uint32_t pid, uint
     sample = ci.s0 + rest / ci.hw;
 }
 
+__device__ __forceinline__ CamPath load_path(const PathState& P, uint32_t pid) {
+    CamPath c;
+    c.o = F3{P.ox[pid], P.oy[pid], P.oz[pid]};
+    c.d = F3{P.dx[pid], P.dy[pid], P.dz[pid]};
+    c.T = P.T[pid];
+    c.L = P.L[pid];
+    c.lam = P.lambda[pid];
+    c.flags = P.flags[pid];
+    return c;
+}
+__device__ __forceinline__ void store_ray(const PathState& P, uint32_t pid, const CamPath& c) {
+    P.ox[pid] = c.o.x; P.oy[pid] = c.o.y; P.oz[pid] = c.o.z;
+    P.dx[pid] = c.d.x; P.dy[pid] = c.d.y; P.dz[pid] = c.d.z;
+}
+__device__ __forceinline__ HitRec load_hit(const PathState& P, uint32_t pid) {
+    return HitRec{P.t[pid], P.u[pid], P.v[pid], P.prim[pid]};
+}
+
 __global__ void k_raygen(CamInfo ci, WaveDev wl, PathState P, uint32_t n, uint32_t* queue, uint32_t* counts) {
     for (uint32_t pid = blockIdx.x * blockDim.x + threadIdx.x; pid < n; pid += gridDim.x * blockDim.x) {
         uint32_t pix, sample, slot;
         pid_decode(ci, pid, pix, sample, slot);
-        const uint32_t x = pix % ci.cam.w, y = pix / ci.cam.w;
-        const U4 r = rng_camera(ci.seed, pix, sample, 0, 0, slot);
-        const float lam = wl.mode == SC_WL_FIXED ? wl.nm[slot] : lambda_from(wl, unit(r.c));
-        F3 o, d;
-        camera_ray(ci.cam, x, y, unit(r.a), unit(r.b), o, d);
-        P.ox[pid] = o.x; P.oy[pid] = o.y; P.oz[pid] = o.z;
-        P.dx[pid] = d.x; P.dy[pid] = d.y; P.dz[pid] = d.z;
-        P.T[pid] = 1.0f;
-        P.L[pid] = 0.0f;
-        P.lambda[pid] = lam;
-        P.flags[pid] = 0u;
+        const CamPath c = camera_start(ci.cam, wl, ci.seed, pix, sample, slot);
+        store_ray(P, pid, c);
+        P.T[pid] = c.T;
+        P.L[pid] = c.L;
+        P.lambda[pid] = c.lam;
+        P.flags[pid] = c.flags;
         queue[pid] = pid;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) counts[0] = n;
@@ -385,16 +232,12 @@ __global__ void k_classify(DevScene S, PathState P, const uint32_t* __restrict__
             pid = queue[i];
             const uint32_t prim = P.prim[pid];
             if (prim != 0xffffffffu) {
-                const sc_material m = S.mat[S.tri_obj[prim]];
-                if (m.type == SC_MAT_EMISSIVE) {
-                    if (!(P.flags[pid] & 1u)) {
-                        F3 p0, p1, p2;
-                        tri_vertices(S, prim, p0, p1, p2);
-                        const F3 Ng = normalize(cross(p1 - p0, p2 - p0));
-                        const F3 d{P.dx[pid], P.dy[pid], P.dz[pid]};
-                        if (dot(d, Ng) < 0.0f) P.L[pid] = P.L[pid] + P.T[pid] * m.le;
-                    }
-                } else if (m.type == SC_MAT_DIELECTRIC) {
+                const uint32_t type = S.mat[S.tri_obj[prim]].type;
+                if (type == SC_MAT_EMISSIVE) {
+                    CamPath c = load_path(P, pid);
+                    camera_emission(S, load_hit(P, pid), c);
+                    P.L[pid] = c.L;
+                } else if (type == SC_MAT_DIELECTRIC) {
                     to_diel = true;
                 } else {
                     to_diff = true;
@@ -418,19 +261,9 @@ __global__ void k_shade_dielectric(DevScene S, CamInfo ci, PathState P, uint32_t
             pid = q[i];
             uint32_t pix, sample, slot;
             pid_decode(ci, pid, pix, sample, slot);
-            const uint32_t prim = P.prim[pid];
-            const F3 d{P.dx[pid], P.dy[pid], P.dz[pid]};
-            const Frame f = hit_frame(S, prim, P.u[pid], P.v[pid], d);
-            const sc_material m = S.mat[S.tri_obj[prim]];
-            const U4 r = rng_camera(ci.seed, pix, sample, depth, 1, slot);
-            F3 nd;
-            bool refl;
-            if (dielectric(f, d, P.lambda[pid], m.cauchy_a, m.cauchy_b, unit(r.c), nd, refl)) {
-                const F3 o = offset_ray(f.P, refl ? f.Nf : neg(f.Nf));
-                P.ox[pid] = o.x; P.oy[pid] = o.y; P.oz[pid] = o.z;
-                P.dx[pid] = nd.x; P.dy[pid] = nd.y; P.dz[pid] = nd.z;
-                cont = depth < ci.max_depth;
-            }
+            CamPath c = load_path(P, pid);
+            cont = camera_dielectric(S, ci.seed, pix, sample, slot, depth, ci.max_depth, load_hit(P, pid), c);
+            if (cont) store_ray(P, pid, c);
         }
         wave_push(cont, pid, q_next, counts + 1);
     }
@@ -443,101 +276,31 @@ __global__ void k_shade_diffuse(DevScene S, CamInfo ci, WaveDev wl, PathState P,
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
         const uint32_t i = base + threadIdx.x;
-        bool cont = false, shoot = false;
+        bool cont = false;
+        ShadowReq sr;
+        sr.shoot = false;
         uint32_t pid = 0;
         if (i < n) {
             pid = q[i];
             uint32_t pix, sample, slot;
             pid_decode(ci, pid, pix, sample, slot);
-            const uint32_t prim = P.prim[pid];
-            const uint32_t obj = S.tri_obj[prim];
-            const F3 d{P.dx[pid], P.dy[pid], P.dz[pid]};
-            const Frame f = hit_frame(S, prim, P.u[pid], P.v[pid], d);
-            const sc_material m = S.mat[obj];
-            const float rho = albedo(S, m, f.P);
-            const float T = P.T[pid];
-            const float lam = P.lambda[pid];
-            float L = P.L[pid];
-            P.flags[pid] = P.flags[pid] | 1u;
-            const F3 os = offset_ray(f.P, f.Nf);
-            // caustic gather
-            if (cmap && S.recv_obj && obj == S.recv_obj) {
-                const int64_t cell = receiver_cell(S, f.P);
-                if (cell >= 0) {
-                    const uint32_t b = wl.mode == SC_WL_FIXED ? slot : spectral_bin(wl, lam);
-                    const float E = cmap[(size_t)cell * wl.channels + b] * S.inv_cell_area;
-                    const float g = ((T * rho) * kInvPi) * E;
-                    L = L + g;
-                }
+            CamPath c = load_path(P, pid);
+            cont = camera_diffuse(S, wl, cmap, ci.seed, pix, sample, slot, depth, ci.max_depth, load_hit(P, pid), c, sr);
+            P.L[pid] = c.L;
+            P.flags[pid] = c.flags;
+            if (sr.shoot) {
+                P.sox[pid] = sr.o.x; P.soy[pid] = sr.o.y; P.soz[pid] = sr.o.z;
+                P.sdx[pid] = sr.d.x; P.sdy[pid] = sr.d.y; P.sdz[pid] = sr.d.z;
+                P.stmax[pid] = sr.tmax;
+                P.sexcl[pid] = sr.excl;
+                P.scontrib[pid] = sr.contrib;
             }
-            P.L[pid] = L;
-            // next event estimation
-            if (S.n_entries > 0) {
-                const U4 r = rng_camera(ci.seed, pix, sample, depth, 2, slot);
-                const uint32_t e = pick_entry(S.n_entries, unit(r.c));
-                float contrib = 0.0f, tmax = 0.0f;
-                uint32_t excl = 0xffffffffu;
-                F3 om{0.0f, 0.0f, 0.0f};
-                if (e < S.n_pl) {
-                    const float* lp = S.pl + 4 * (size_t)e;
-                    const F3 w = F3{lp[0], lp[1], lp[2]} - os;
-                    const float r2 = dot(w, w);
-                    const float dist = sqrtf(r2);
-                    om = w * (1.0f / dist);
-                    const float cosx = dot(f.Nf, om);
-                    if (cosx > 0.0f) {
-                        contrib = ((((T * rho) * kInvPi) * lp[3]) * cosx) / r2;
-                        contrib = contrib * (float)S.n_entries;
-                        tmax = dist;
-                        shoot = true;
-                    }
-                } else {
-                    const uint32_t k = cdf_first_above(S.emit_cdf, S.n_emit, unit(r.d));
-                    const uint32_t lprim = S.emit_prim[k];
-                    F3 Nl;
-                    const F3 y = light_point(S, lprim, unit(r.a), unit(r.b), Nl);
-                    const F3 w = y - os;
-                    const float r2 = dot(w, w);
-                    const float dist = sqrtf(r2);
-                    om = w * (1.0f / dist);
-                    const float cosx = dot(f.Nf, om);
-                    const float cosl = -dot(Nl, om);
-                    if (cosx > 0.0f && cosl > 0.0f) {
-                        const float le = S.mat[S.tri_obj[lprim]].le;
-                        contrib = ((((((T * rho) * kInvPi) * le) * cosx) * cosl) / r2) * S.a_tot;
-                        contrib = contrib * (float)S.n_entries;
-                        tmax = dist * 0.9999f;
-                        excl = lprim;
-                        shoot = true;
-                    }
-                }
-                if (shoot) {
-                    P.sox[pid] = os.x; P.soy[pid] = os.y; P.soz[pid] = os.z;
-                    P.sdx[pid] = om.x; P.sdy[pid] = om.y; P.sdz[pid] = om.z;
-                    P.stmax[pid] = tmax;
-                    P.sexcl[pid] = excl;
-                    P.scontrib[pid] = contrib;
-                }
-            }
-            // cosine-weighted bounce
-            if (depth < ci.max_depth) {
-                const U4 r = rng_camera(ci.seed, pix, sample, depth, 1, slot);
-                const float u0 = unit(r.a), u1 = unit(r.b);
-                const float rr = sqrtf(u0);
-                float sp, cp;
-                sincos_turn(u1, sp, cp);
-                const float x = rr * cp, y = rr * sp;
-                const float z = sqrtf(fmaxf(0.0f, 1.0f - u0));
-                F3 t1, t2;
-                basis(f.Nf, t1, t2);
-                const F3 nd = normalize((t1 * x + t2 * y) + f.Nf * z);
-                P.ox[pid] = os.x; P.oy[pid] = os.y; P.oz[pid] = os.z;
-                P.dx[pid] = nd.x; P.dy[pid] = nd.y; P.dz[pid] = nd.z;
-                P.T[pid] = T * rho;
-                cont = true;
+            if (cont) {
+                store_ray(P, pid, c);
+                P.T[pid] = c.T;
             }
         }
-        wave_push(shoot, pid, q_shadow, counts + 4);
+        wave_push(sr.shoot, pid, q_shadow, counts + 4);
         wave_push(cont, pid, q_next, counts + 1);
     }
 }
@@ -546,29 +309,14 @@ __global__ void k_shade_diffuse(DevScene S, CamInfo ci, WaveDev wl, PathState P,
 __global__ void k_film_accumulate(CamInfo ci, WaveDev wl, const float* __restrict__ L, const float* __restrict__ lambda,
                                   uint32_t n_samples, float* __restrict__ rgb) {
     for (uint32_t pix = blockIdx.x * blockDim.x + threadIdx.x; pix < ci.hw; pix += gridDim.x * blockDim.x) {
-        float a0 = rgb[3 * (size_t)pix], a1 = rgb[3 * (size_t)pix + 1], a2 = rgb[3 * (size_t)pix + 2];
+        float acc[3] = {rgb[3 * (size_t)pix], rgb[3 * (size_t)pix + 1], rgb[3 * (size_t)pix + 2]};
         for (uint32_t s = 0; s < n_samples; ++s) {
             const size_t base = ((size_t)s * ci.hw + pix) * ci.K;
-            if (wl.mode == SC_WL_FIXED) {
-                if (ci.K == 3) {
-                    a0 = a0 + L[base];
-                    a1 = a1 + L[base + 1];
-                    a2 = a2 + L[base + 2];
-                } else {
-                    const float v = L[base];
-                    a0 = a0 + v; a1 = a1 + v; a2 = a2 + v;
-                }
-            } else {
-                const float v = L[base];
-                const float lam = lambda[base];
-                a0 = a0 + sensor(wl, 0, lam) * v;
-                a1 = a1 + sensor(wl, 1, lam) * v;
-                a2 = a2 + sensor(wl, 2, lam) * v;
-            }
+            for (uint32_t slot = 0; slot < ci.K; ++slot) film_add(wl, ci.K, slot, L[base + slot], lambda[base + slot], acc);
         }
-        rgb[3 * (size_t)pix] = a0;
-        rgb[3 * (size_t)pix + 1] = a1;
-        rgb[3 * (size_t)pix + 2] = a2;
+        rgb[3 * (size_t)pix] = acc[0];
+        rgb[3 * (size_t)pix + 1] = acc[1];
+        rgb[3 * (size_t)pix + 2] = acc[2];
     }
 }
 
@@ -590,36 +338,9 @@ __global__ void k_aov_raygen(sc_camera cam, RaySoA R) {
 
 __global__ void k_aov_write(DevScene S, sc_camera cam, RaySoA R, HitSoA H, sc_aov out) {
     const uint32_t hw = cam.w * cam.h;
-    const F3 Rh = normalize(F3{cam.right[0], cam.right[1], cam.right[2]});
-    const F3 Uh = normalize(F3{cam.up[0], cam.up[1], cam.up[2]});
-    const F3 Fh = normalize(F3{cam.fwd[0], cam.fwd[1], cam.fwd[2]});
     for (uint32_t pix = blockIdx.x * blockDim.x + threadIdx.x; pix < hw; pix += gridDim.x * blockDim.x) {
-        const uint32_t prim = H.prim[pix];
-        uint32_t obj = 0;
-        float dep = INFINITY, depn = 1.0f, alb = 0.0f;
-        F3 N{0.0f, 0.0f, 0.0f}, Nc{0.0f, 0.0f, 0.0f};
-        uint8_t trans = 0;
-        if (prim != 0xffffffffu) {
-            obj = S.tri_obj[prim];
-            const sc_material m = S.mat[obj];
-            const F3 d{R.dx[pix], R.dy[pix], R.dz[pix]};
-            const float t = H.t[pix];
-            const Frame f = hit_frame(S, prim, H.u[pix], H.v[pix], d);
-            dep = t;
-            depn = fminf(t / 10.0f, 1.0f);
-            N = f.Ns;
-            Nc = F3{dot(N, Rh), dot(N, Uh), -dot(N, Fh)};
-            alb = m.type == SC_MAT_DIFFUSE ? albedo(S, m, f.P) : (m.type == SC_MAT_DIELECTRIC ? 1.0f : 0.0f);
-            trans = m.type == SC_MAT_DIELECTRIC ? 1 : 0;
-        }
-        if (out.obj) out.obj[pix] = obj;
-        if (out.trans) out.trans[pix] = trans;
-        if (out.tri) out.tri[pix] = prim;
-        if (out.depth) out.depth[pix] = dep;
-        if (out.depthn) out.depthn[pix] = depn;
-        if (out.normal) store3(out.normal, pix, N);
-        if (out.normal_cam) store3(out.normal_cam, pix, Nc);
-        if (out.albedo) out.albedo[pix] = alb;
+        const F3 d{R.dx[pix], R.dy[pix], R.dz[pix]};
+        aov_write(S, cam, pix, d, HitRec{H.t[pix], H.u[pix], H.v[pix], H.prim[pix]}, out);
     }
 }
 
@@ -639,13 +360,6 @@ __device__ __forceinline__ void ph_stat(DevCounters* C, const PhInfo& pi, int ou
     atomicAdd(&C->ph_flux[outcome], (double)phi);
 }
 
-// 1 - cos(theta) of the cone subtended by a sphere of squared radius rr at
-// squared distance dist2, without cancellation
-__device__ __forceinline__ float cap_height(float rr, float dist2) {
-    const float q = rr / dist2;
-    return q >= 1.0f ? 2.0f : q / (1.0f + sqrtf(1.0f - q));
-}
-
 __global__ void k_photon_emit(DevScene S, WaveDev wl, PhInfo pi, uint32_t n, PhotonState Ph, uint32_t* queue,
                               uint32_t* counts, DevCounters* C) {
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -653,101 +367,17 @@ __global__ void k_photon_emit(DevScene S, WaveDev wl, PhInfo pi, uint32_t n, Pho
         const uint32_t i = base + threadIdx.x;
         bool alive = false;
         if (i < n) {
-            const uint64_t p = pi.p0 + i;
-            const U4 r0 = rng_photon(pi.seed, p, 0, 0);
-            uint32_t slot;
-            float lam, nslot;
-            if (wl.mode == SC_WL_FIXED) {
-                slot = (uint32_t)(p % wl.k);
-                lam = wl.nm[slot];
-                const uint64_t cnt = pi.n_total / wl.k + ((p % wl.k) < (pi.n_total % wl.k) ? 1u : 0u);
-                nslot = (float)cnt;
-            } else {
-                lam = lambda_from(wl, unit(r0.d));
-                slot = spectral_bin(wl, lam);
-                nslot = (float)pi.n_total / (float)wl.bins;
-            }
-            const U4 r2 = rng_photon(pi.seed, p, 0, 2);
-            const uint32_t e = pick_entry(S.n_entries, unit(r2.c));
-            F3 y, Nl{0.0f, 0.0f, 0.0f};
-            float power;
-            bool area = false;
-            if (e < S.n_pl) {
-                const float* lp = S.pl + 4 * (size_t)e;
-                y = F3{lp[0], lp[1], lp[2]};
-                power = lp[3];
-            } else {
-                const uint32_t k = cdf_first_above(S.emit_cdf, S.n_emit, unit(r2.d));
-                const uint32_t lprim = S.emit_prim[k];
-                y = light_point(S, lprim, unit(r2.a), unit(r2.b), Nl);
-                power = S.mat[S.tri_obj[lprim]].le * S.a_tot;
-                area = true;
-            }
-            // cone per target, picked in proportion to its solid angle
-            float osum = 0.0f;
-            for (uint32_t k = 0; k < S.n_tg; ++k) {
-                const float* sp = S.tg + 4 * (size_t)k;
-                const F3 dk = F3{sp[0], sp[1], sp[2]} - y;
-                osum = osum + kTwoPi * cap_height(sp[3] * sp[3], dot(dk, dk));
-            }
-            const float target = unit(r0.a) * osum;
-            uint32_t kk = S.n_tg - 1;
-            float cum = 0.0f;
-            for (uint32_t k = 0; k < S.n_tg; ++k) {
-                const float* sp = S.tg + 4 * (size_t)k;
-                const F3 dk = F3{sp[0], sp[1], sp[2]} - y;
-                cum = cum + kTwoPi * cap_height(sp[3] * sp[3], dot(dk, dk));
-                if (cum > target) {
-                    kk = k;
-                    break;
-                }
-            }
-            const float* spk = S.tg + 4 * (size_t)kk;
-            const F3 dkk = F3{spk[0], spk[1], spk[2]} - y;
-            const float d2k = dot(dkk, dkk);
-            const float hk = cap_height(spk[3] * spk[3], d2k);
-            const F3 axis = dkk * (1.0f / sqrtf(d2k));
-            const float g = unit(r0.b) * hk;
-            const float cost = 1.0f - g;
-            const float sint = sqrtf(fmaxf(0.0f, g * (2.0f - g)));
-            float sp_, cp_;
-            sincos_turn(unit(r0.c), sp_, cp_);
-            F3 t1, t2;
-            basis(axis, t1, t2);
-            const F3 om = normalize((t1 * (cp_ * sint) + t2 * (sp_ * sint)) + axis * cost);
-            uint32_t m = 1;
-            for (uint32_t k = 0; k < S.n_tg; ++k) {
-                if (k == kk) continue;
-                const float* sp = S.tg + 4 * (size_t)k;
-                const F3 dk = F3{sp[0], sp[1], sp[2]} - y;
-                const float dist2 = dot(dk, dk);
-                const float q = (sp[3] * sp[3]) / dist2;
-                const F3 ax = dk * (1.0f / sqrtf(dist2));
-                const F3 cr = cross(om, ax);
-                if (q >= 1.0f || (dot(om, ax) > 0.0f && dot(cr, cr) <= q)) ++m;
-            }
-            float phi;
-            F3 o;
-            bool dead = false;
-            if (area) {
-                const float cy = dot(Nl, om);
-                if (!(cy > 0.0f)) dead = true;
-                phi = (((power * cy) * osum) * (float)S.n_entries) / (nslot * (float)m);
-                o = offset_ray(y, Nl);
-            } else {
-                phi = ((power * osum) * (float)S.n_entries) / (nslot * (float)m);
-                o = y;
-            }
-            if (dead) {
+            PhotonPath ph;
+            alive = photon_emit(S, wl, pi.seed, pi.n_total, pi.p0 + i, ph);
+            if (!alive) {
                 if (pi.stats) atomicAdd(&C->ph_count[SC_PH_EMIT_DEAD], 1ull);
             } else {
-                Ph.ox[i] = o.x; Ph.oy[i] = o.y; Ph.oz[i] = o.z;
-                Ph.dx[i] = om.x; Ph.dy[i] = om.y; Ph.dz[i] = om.z;
-                Ph.phi[i] = phi;
-                Ph.lambda[i] = lam;
-                Ph.slot[i] = slot;
-                Ph.spec[i] = 0u;
-                alive = true;
+                Ph.ox[i] = ph.o.x; Ph.oy[i] = ph.o.y; Ph.oz[i] = ph.o.z;
+                Ph.dx[i] = ph.d.x; Ph.dy[i] = ph.d.y; Ph.dz[i] = ph.d.z;
+                Ph.phi[i] = ph.phi;
+                Ph.lambda[i] = ph.lam;
+                Ph.slot[i] = ph.slot;
+                Ph.spec[i] = ph.spec;
             }
         }
         wave_push(alive, i, queue, counts + 0);
@@ -787,46 +417,27 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
         unsigned long long q = 0;
         if (i < n) {
             id = queue[i];
-            const uint32_t prim = Ph.prim[id];
-            const float phi = Ph.phi[id];
-            if (prim == 0xffffffffu) {
-                ph_stat(C, pi, SC_PH_ESCAPED, phi);
-            } else {
-                const uint32_t obj = S.tri_obj[prim];
-                const sc_material m = S.mat[obj];
-                const F3 d{Ph.dx[id], Ph.dy[id], Ph.dz[id]};
-                const Frame f = hit_frame(S, prim, Ph.u[id], Ph.v[id], d);
-                if (m.type == SC_MAT_EMISSIVE) {
-                    ph_stat(C, pi, SC_PH_ABSORBED, phi);
-                } else if (m.type == SC_MAT_DIELECTRIC) {
-                    const U4 r = rng_photon(pi.seed, pi.p0 + id, depth, 1);
-                    F3 nd;
-                    bool refl;
-                    if (!dielectric(f, d, Ph.lambda[id], m.cauchy_a, m.cauchy_b, unit(r.c), nd, refl)) {
-                        ph_stat(C, pi, SC_PH_LOST, phi);
-                    } else {
-                        const F3 o = offset_ray(f.P, refl ? f.Nf : neg(f.Nf));
-                        Ph.ox[id] = o.x; Ph.oy[id] = o.y; Ph.oz[id] = o.z;
-                        Ph.dx[id] = nd.x; Ph.dy[id] = nd.y; Ph.dz[id] = nd.z;
-                        Ph.spec[id] = Ph.spec[id] + 1u;
-                        if (depth < pi.max_depth) cont = true;
-                        else ph_stat(C, pi, SC_PH_TRUNCATED, phi);
-                    }
-                } else if (Ph.spec[id] == 0u) {
-                    ph_stat(C, pi, SC_PH_DIRECT, phi);
-                } else if (obj != S.recv_obj) {
-                    ph_stat(C, pi, SC_PH_ELSEWHERE, phi);
-                } else {
-                    const int64_t cell = receiver_cell(S, f.P);
-                    if (cell < 0) {
-                        ph_stat(C, pi, SC_PH_OUTSIDE, phi);
-                    } else {
-                        dep = true;
-                        cell_ch = (uint32_t)cell * wl.channels + Ph.slot[id];
-                        q = __double2ull_rn((double)phi * pi.scale);
-                        ph_stat(C, pi, SC_PH_DEPOSITED, phi);
-                    }
-                }
+            PhotonPath ph;
+            ph.o = F3{Ph.ox[id], Ph.oy[id], Ph.oz[id]};
+            ph.d = F3{Ph.dx[id], Ph.dy[id], Ph.dz[id]};
+            ph.phi = Ph.phi[id];
+            ph.lam = Ph.lambda[id];
+            ph.slot = Ph.slot[id];
+            ph.spec = Ph.spec[id];
+            int outcome = -1;
+            int64_t cc = -1;
+            cont = photon_event(S, wl, pi.seed, pi.p0 + id, depth, pi.max_depth,
+                                HitRec{Ph.t[id], Ph.u[id], Ph.v[id], Ph.prim[id]}, ph, outcome, cc);
+            if (cont) {
+                Ph.ox[id] = ph.o.x; Ph.oy[id] = ph.o.y; Ph.oz[id] = ph.o.z;
+                Ph.dx[id] = ph.d.x; Ph.dy[id] = ph.d.y; Ph.dz[id] = ph.d.z;
+                Ph.spec[id] = ph.spec;
+            }
+            if (!cont) ph_stat(C, pi, outcome, ph.phi);
+            if (cc >= 0) {
+                dep = true;
+                cell_ch = (uint32_t)cc;
+                q = __double2ull_rn((double)ph.phi * pi.scale);
             }
         }
         deposit(dep, cell_ch, q, acc, cnt_map);
@@ -969,41 +580,74 @@ void launch_anyhit(Ctx* c, const DevScene& S, ShadowSoA R, const uint32_t* queue
                        work, occ, L, c->counters.as<DevCounters>());
 }
 
+}  // namespace
+
 // Sensor curves (Gaussians, 40 nm, at 650/550/450 nm, mean 1 over the
-// range) tabulated every 0.25 nm in double, uploaded as float.
-sc_status make_wave(Ctx* c, const sc_wavelengths& wl, WaveDev& w) {
+// range) tabulated every 0.25 nm in double, rounded to float.
+uint32_t sensor_table(const sc_wavelengths& wl, std::vector<float>& tab) {
+    const uint32_t n = (uint32_t)((double)(wl.hi - wl.lo) * 4.0 + 0.5) + 1;
+    tab.assign(3 * (size_t)n, 0.0f);
+    const double mu[3] = {650.0, 550.0, 450.0};
+    std::vector<double> g(n);
+    for (int ch = 0; ch < 3; ++ch) {
+        for (uint32_t i = 0; i < n; ++i) {
+            const double lam = (double)wl.lo + 0.25 * (double)i;
+            const double x = (lam - mu[ch]) / 40.0;
+            g[i] = exp(-0.5 * x * x);
+        }
+        double sum = 0.0;
+        for (uint32_t i = 0; i + 1 < n; ++i) sum += 0.5 * (g[i] + g[i + 1]) * 0.25;
+        const double mean = sum / ((double)(n - 1) * 0.25);
+        for (uint32_t i = 0; i < n; ++i) tab[(size_t)ch * n + i] = (float)(g[i] / mean);
+    }
+    return n;
+}
+
+// device view of a wavelength setting; tab_dev receives the sensor table
+// (uniform mode) when not NULL
+WaveDev wave_view(const sc_wavelengths& wl, const float* tab_dev, uint32_t n_tab) {
+    WaveDev w;
     w.mode = wl.mode;
     w.k = wl.k;
     for (int i = 0; i < 4; ++i) w.nm[i] = wl.nm[i];
     w.lo = wl.lo;
     w.hi = wl.hi;
     w.bins = wl.bins;
-    w.tab = nullptr;
-    w.n_tab = 0;
-    w.bin_scale = 0.0f;
+    w.tab = tab_dev;
+    w.n_tab = n_tab;
+    w.bin_scale = wl.mode == SC_WL_UNIFORM ? (float)wl.bins / (wl.hi - wl.lo) : 0.0f;
     w.channels = wl.mode == SC_WL_FIXED ? wl.k : wl.bins;
-    if (wl.mode == SC_WL_UNIFORM) {
-        w.bin_scale = (float)wl.bins / (wl.hi - wl.lo);
-        const uint32_t n = (uint32_t)((double)(wl.hi - wl.lo) * 4.0 + 0.5) + 1;
-        std::vector<float> tab(3 * (size_t)n);
-        const double mu[3] = {650.0, 550.0, 450.0};
-        std::vector<double> g(n);
-        for (int ch = 0; ch < 3; ++ch) {
-            for (uint32_t i = 0; i < n; ++i) {
-                const double lam = (double)wl.lo + 0.25 * (double)i;
-                const double x = (lam - mu[ch]) / 40.0;
-                g[i] = exp(-0.5 * x * x);
-            }
-            double sum = 0.0;
-            for (uint32_t i = 0; i + 1 < n; ++i) sum += 0.5 * (g[i] + g[i + 1]) * 0.25;
-            const double mean = sum / ((double)(n - 1) * 0.25);
-            for (uint32_t i = 0; i < n; ++i) tab[(size_t)ch * n + i] = (float)(g[i] / mean);
-        }
+    return w;
+}
+
+double photon_scale(const Bvh* b, uint64_t N, const sc_wavelengths& wl) {
+    const DevScene& S = b->scene;
+    double nslot_min = wl.mode == SC_WL_FIXED ? (double)(N / wl.k) : (double)N / (double)wl.bins;
+    if (nslot_min < 1.0) nslot_min = 1.0;
+    const double bound = (double)b->max_power * (double)S.n_entries * 4.0 * M_PI * (double)S.n_tg / nslot_min;
+    if (!(bound > 0.0) || N == 0) return 1.0;
+    const double room = ldexp(1.0, 62) / ((double)N * bound);
+    return ldexp(1.0, (int)floor(log2(room)));
+}
+
+namespace {
+
+sc_status make_wave(Ctx* c, const sc_wavelengths& wl, WaveDev& w) {
+    w = wave_view(wl, nullptr, 0);
+    if (wl.mode == SC_WL_UNIFORM && c->sensor.p && c->sensor_lo == wl.lo && c->sensor_hi == wl.hi) {
+        w.tab = c->sensor.as<float>();   // table of this range already on the device
+        w.n_tab = c->sensor_n;
+    } else if (wl.mode == SC_WL_UNIFORM) {
+        std::vector<float> tab;
+        const uint32_t n = sensor_table(wl, tab);
         SC_TRY(c->sensor.ensure(tab.size() * sizeof(float)));
         SC_HIP(hipMemcpyAsync(c->sensor.p, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
         SC_HIP(hipStreamSynchronize(c->stream));   // tab is a host temporary
         w.tab = c->sensor.as<float>();
         w.n_tab = n;
+        c->sensor_lo = wl.lo;
+        c->sensor_hi = wl.hi;
+        c->sensor_n = n;
     }
     return SC_OK;
 }
@@ -1145,14 +789,9 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
     }
     double scale = 1.0;
     if (N > 0 && S.n_tg > 0 && S.n_entries > 0) {
-        // bound on one photon's flux: strongest light, all entries, every
-        // cone a full sphere, smallest slot
-        double nslot_min = wl.mode == SC_WL_FIXED ? (double)(N / wl.k) : (double)N / (double)wl.bins;
-        if (nslot_min < 1.0) nslot_min = 1.0;
-        const double bound = (double)b->max_power * (double)S.n_entries * 4.0 * M_PI * (double)S.n_tg / nslot_min;
-        const double room = ldexp(1.0, 62) / ((double)N * bound);
-        const int e = (int)floor(log2(room));
-        scale = ldexp(1.0, e);
+        // fixed-point scale from a bound on one photon's flux (strongest
+        // light, all entries, every cone a full sphere, smallest slot)
+        scale = photon_scale(b, N, wl);
         const size_t chunk = std::min<uint64_t>(N, c->photon_cap);
         if (c->photon_n < chunk || !c->photon.p) {
             SC_TRY(c->photon.alloc(photon_bytes(chunk)));
