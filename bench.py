@@ -151,6 +151,19 @@ def denoise_fps(ctx):
     return res
 
 
+def batch_compare(ctx):
+    """The batched form: 64 scenes of 1e3-5e5 triangles (log-uniform) at
+    256^2-1024^2 pixels, 8 spp, depth 12, 2^18 photons each, rendered by the
+    autotuned persistent graph launch vs one scene after another."""
+    import scenegen as sg
+    from paper_2107_11008_amd import autotune as A
+    cfgs = [sg.config4_item(j) for j in range(64)]
+    best = A.autotune(ctx, cfgs)
+    res = A.compare(ctx, cfgs, best)
+    res["tuning"] = {k: best[k] for k in ("width", "block_size", "blocks_per_cu", "px_per_item")}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +171,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-denoise", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -284,6 +298,8 @@ def main():
     }
     if not args.no_denoise:
         line["denoise_1080p"] = denoise_fps(ctx)
+    if not args.no_batch:
+        line["batch_64"] = batch_compare(ctx)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, rays_per_step, secs / args.steps)
     print(json.dumps(line), flush=True)
