@@ -253,6 +253,30 @@ sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32
                     const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, const sc_aov* out);
 
 /* ------------------------------------------------------------------
+ * Ground-truth passes over sc_render's buffers (Sec. III-D).  Each is a
+ * plain per-pixel definition; device arrays [h][w].
+ * ------------------------------------------------------------------ */
+/* Local / non-local caustic mask (Sec. III-D-6): the luminance (Rec. 709:
+ * (0.2126 R + 0.7152 G) + 0.0722 B) of a render with the caustic gather
+ * minus that of the same render without it (same seeds, so the paths are
+ * identical apart from the gathered light); mask = 0 if the difference is
+ * <= threshold, 1 (local: the pixel's first surface is transparent, trans
+ * may be NULL = never) or 2 (non-local) otherwise. */
+sc_status sc_caustic_mask(sc_ctx* ctx, const float* rgb_with, const float* rgb_without, const uint8_t* trans,
+                          uint32_t w, uint32_t h, float threshold, uint8_t* mask);
+/* Outlines (Sec. III-D-4): out = 1 for a pixel of an object (obj != 0) whose
+ * window of Chebyshev radius `thickness` (1..64, clipped at the image
+ * border) contains another id; a band `thickness` pixels wide inside every
+ * object edge. */
+sc_status sc_outline(sc_ctx* ctx, const uint32_t* obj, uint32_t w, uint32_t h, uint32_t thickness, uint8_t* out);
+/* Occlusion boundaries (Sec. III-D-5, depth discontinuities): out = 1 for a
+ * pixel with finite depth d that has an 8-neighbour q with depth(q) - d >
+ * rel_jump * d (the near side of the jump; a miss counts as infinitely
+ * far). */
+sc_status sc_occlusion_boundary(sc_ctx* ctx, const float* depth, uint32_t w, uint32_t h, float rel_jump,
+                                uint8_t* out);
+
+/* ------------------------------------------------------------------
  * Batched form: many scenes of uneven size rendered by persistent kernels
  * whose waves pull work items (64*m photons or pixels of one scene) from a
  * global counter; each lane follows its photon or its pixel's paths to the

@@ -120,7 +120,8 @@ EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set
            "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render",
            "sc_unet_create", "sc_unet_free", "sc_unet_num_params", "sc_unet_set_params", "sc_unet_get_params",
            "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise",
-           "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch"]
+           "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch",
+           "sc_caustic_mask", "sc_outline", "sc_occlusion_boundary"]
 
 
 def load(path: str = LIB_PATH):
@@ -149,6 +150,9 @@ def load(path: str = LIB_PATH):
     L.sc_occluded.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
     L.sc_trace_photons.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, vp, vp, C.POINTER(PhotonStats)]
     L.sc_render.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, C.POINTER(Aov)]
+    L.sc_caustic_mask.argtypes = [vp, vp, vp, vp, u32, u32, C.c_float, vp]
+    L.sc_outline.argtypes = [vp, vp, u32, u32, u32, vp]
+    L.sc_occlusion_boundary.argtypes = [vp, vp, u32, u32, C.c_float, vp]
     L.sc_batch_create.argtypes = [vp, u32, vp, C.POINTER(Tune), C.POINTER(vp)]
     L.sc_batch_run.argtypes = [vp, vp]
     L.sc_batch_free.argtypes = [vp]
@@ -309,6 +313,44 @@ class Context:
         return res
 
 
+def _gt_methods():
+    def caustic_mask(self, rgb_with, rgb_without, trans=None, threshold: float = 0.0):
+        h, w = rgb_with.shape[:2]
+        m = torch.empty((h, w), dtype=torch.uint8, device=self.device)
+        _check(load().sc_caustic_mask(self.h, _ptr(rgb_with), _ptr(rgb_without), _ptr(trans), w, h,
+                                      float(threshold), _ptr(m)), "sc_caustic_mask")
+        return m
+
+    def render_caustic_mask(self, bvh, cam, spp, max_depth, wl, seed, caustic_map, rel: float = 0.05):
+        """Renders with and without the caustic gather (same seeds) and
+        thresholds the luminance difference at rel x the mean luminance of
+        the render with caustics."""
+        a = self.render(bvh, cam, spp, max_depth, wl, seed, caustic_map=caustic_map, outputs=("rgb", "trans"))
+        b = self.render(bvh, cam, spp, max_depth, wl, seed, caustic_map=None, outputs=("rgb",))
+        lum = (0.2126 * a["rgb"][..., 0].double() + 0.7152 * a["rgb"][..., 1].double()
+               + 0.0722 * a["rgb"][..., 2].double())
+        thr = float(rel * float(lum.mean()))
+        return self.caustic_mask(a["rgb"], b["rgb"], a["trans"], thr), a, b, thr
+
+    def outline(self, obj, thickness: int = 1):
+        h, w = obj.shape
+        o = torch.empty((h, w), dtype=torch.uint8, device=self.device)
+        _check(load().sc_outline(self.h, _ptr(obj), w, h, int(thickness), _ptr(o)), "sc_outline")
+        return o
+
+    def occlusion_boundary(self, depth, rel_jump: float = 0.1):
+        h, w = depth.shape
+        o = torch.empty((h, w), dtype=torch.uint8, device=self.device)
+        _check(load().sc_occlusion_boundary(self.h, _ptr(depth), w, h, float(rel_jump), _ptr(o)),
+               "sc_occlusion_boundary")
+        return o
+
+    Context.caustic_mask = caustic_mask
+    Context.render_caustic_mask = render_caustic_mask
+    Context.outline = outline
+    Context.occlusion_boundary = occlusion_boundary
+
+
 class Bvh:
     """Scene uploaded to the device plus its wide BVH and tables."""
 
@@ -443,6 +485,9 @@ class UNet:
             self.close()
         except Exception:
             pass
+
+
+_gt_methods()
 
 
 class Batch:
