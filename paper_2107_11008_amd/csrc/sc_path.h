@@ -136,14 +136,25 @@ __device__ __forceinline__ HitRec trace_closest(const DevScene& S, F3 o, F3 d, u
             const uint32_t first = ref & SC_LEAF_FIRST_MASK;
             const uint32_t cnt = ((ref >> 28) & 7u) + 1u;
             if (COUNT) vc.tris += cnt;
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const float4* tp = S.tris + 3 * (size_t)(first + k);
-                const float4 a = tp[0], b = tp[1], c = tp[2];
-                const uint32_t prim = __float_as_uint(a.w);
-                TriHit h;
-                if (tri_test(rp, perm(rp, a), perm(rp, b), perm(rp, c), h)) {
-                    if (h.t < tb || (h.t == tb && prim < pb)) {
-                        tb = h.t; pb = prim; bV = h.V; bW = h.W; brcp = h.rcp;
+            // triangles in groups of 4, all loads of a group issued before
+            // its tests (indexes clamped to the leaf, extra tests skipped)
+            for (uint32_t k0 = 0; k0 < cnt; k0 += 4) {
+                float4 ta[4], tb4[4], tc[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t k = min(k0 + (uint32_t)j, cnt - 1u);
+                    const float4* tp = S.tris + 3 * (size_t)(first + k);
+                    ta[j] = tp[0]; tb4[j] = tp[1]; tc[j] = tp[2];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (k0 + (uint32_t)j >= cnt) break;
+                    const uint32_t prim = __float_as_uint(ta[j].w);
+                    TriHit h;
+                    if (tri_test(rp, perm(rp, ta[j]), perm(rp, tb4[j]), perm(rp, tc[j]), h)) {
+                        if (h.t < tb || (h.t == tb && prim < pb)) {
+                            tb = h.t; pb = prim; bV = h.V; bW = h.W; brcp = h.rcp;
+                        }
                     }
                 }
             }
@@ -181,12 +192,21 @@ __device__ __forceinline__ bool trace_any(const DevScene& S, F3 o, F3 d, float t
         } else {
             const uint32_t first = ref & SC_LEAF_FIRST_MASK;
             const uint32_t cnt = ((ref >> 28) & 7u) + 1u;
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const float4* tp = S.tris + 3 * (size_t)(first + k);
-                const float4 a = tp[0], b = tp[1], c = tp[2];
-                if (__float_as_uint(a.w) == excl) continue;
-                TriHit h;
-                if (tri_test(rp, perm(rp, a), perm(rp, b), perm(rp, c), h) && h.t < tmax) return true;
+            for (uint32_t k0 = 0; k0 < cnt; k0 += 4) {
+                float4 ta[4], tb4[4], tc[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t k = min(k0 + (uint32_t)j, cnt - 1u);
+                    const float4* tp = S.tris + 3 * (size_t)(first + k);
+                    ta[j] = tp[0]; tb4[j] = tp[1]; tc[j] = tp[2];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (k0 + (uint32_t)j >= cnt) break;
+                    if (__float_as_uint(ta[j].w) == excl) continue;
+                    TriHit h;
+                    if (tri_test(rp, perm(rp, ta[j]), perm(rp, tb4[j]), perm(rp, tc[j]), h) && h.t < tmax) return true;
+                }
             }
         }
         if (sp == 0) return false;

@@ -53,6 +53,18 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// Ray chunks of 64 for a wave: the first by the wave's index in the grid,
+// the rest from the launch's atomic counter (offset by the statically
+// assigned chunks), so a launch with few rays costs no atomics.
+__device__ __forceinline__ uint32_t wave_first_chunk() {
+    return (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
+}
+__device__ __forceinline__ uint32_t wave_next_chunk(uint32_t* work) {
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(work, 64u);
+    return __shfl(base, 0) + gridDim.x * blockDim.x;
+}
+
 // ------------------------------------------------------------------ closest hit
 template <bool COUNT>
 __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitSoA H, const uint32_t* __restrict__ queue,
@@ -63,10 +75,8 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
     const uint32_t n = count ? *count : n_static;
     VisitCount vc;
     unsigned long long c_rays = 0;
+    uint32_t base = wave_first_chunk();
     for (;;) {
-        uint32_t base = 0;
-        if (lane_id() == 0) base = atomicAdd(work, 64u);
-        base = __shfl(base, 0);
         if (base >= n) break;
         const uint32_t i = base + lane_id();
         if (i < n) {
@@ -80,6 +90,7 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
             if (H.v) H.v[pid] = h.v;
             ++c_rays;
         }
+        base = wave_next_chunk(work);
     }
     c_rays = wave_sum_u64(c_rays);
     unsigned long long c_nodes = 0, c_tris = 0;
@@ -87,7 +98,7 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
         c_nodes = wave_sum_u64(vc.nodes);
         c_tris = wave_sum_u64(vc.tris);
     }
-    if (lane_id() == 0) {
+    if (lane_id() == 0 && c_rays) {
         atomicAdd(&C->rays_closest, c_rays);
         if (COUNT) {
             atomicAdd(&C->node_visits, c_nodes);
@@ -107,10 +118,8 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
     Spill st;
     const uint32_t n = count ? *count : n_static;
     unsigned long long c_rays = 0;
+    uint32_t base = wave_first_chunk();
     for (;;) {
-        uint32_t base = 0;
-        if (lane_id() == 0) base = atomicAdd(work, 64u);
-        base = __shfl(base, 0);
         if (base >= n) break;
         const uint32_t i = base + lane_id();
         if (i < n) {
@@ -123,9 +132,10 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
             if (L && !occluded) L[pid] = L[pid] + R.contrib[pid];
             ++c_rays;
         }
+        base = wave_next_chunk(work);
     }
     c_rays = wave_sum_u64(c_rays);
-    if (lane_id() == 0) atomicAdd(&C->rays_shadow, c_rays);
+    if (lane_id() == 0 && c_rays) atomicAdd(&C->rays_shadow, c_rays);
 }
 
 // ------------------------------------------------------------------ helpers
