@@ -108,69 +108,95 @@ struct VisitCount {
     unsigned long long nodes = 0, tris = 0;
 };
 
-// Closest hit: lexicographic minimum of (t, triangle) over the scene.
+// Closest hit: lexicographic minimum of (t, triangle) over the scene,
+// as a resumable traversal: trav_step advances one ray by one node visit or
+// one leaf and returns true when the ray is finished (trav_result is then
+// final).  Any visiting order gives the same result: boxes are tested
+// conservatively and hits are compared by (t, triangle).
+struct TravState {
+    RayPre rp;
+    F3 o, inv;
+    float tb, bV, bW, brcp;
+    uint32_t pb, ref;
+    int sp;
+};
+
+__device__ __forceinline__ void trav_init(TravState& t, F3 o, F3 d) {
+    t.rp = ray_prepare(o, d);
+    t.o = o;
+    t.inv = F3{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
+    t.tb = INFINITY;
+    t.bV = 0.0f; t.bW = 0.0f; t.brcp = 0.0f;
+    t.pb = 0xffffffffu;
+    t.ref = 0;   // root node
+    t.sp = 0;
+}
+
 template <int BS, bool COUNT>
-__device__ __forceinline__ HitRec trace_closest(const DevScene& S, F3 o, F3 d, uint2 (*lds)[BS], Spill& st,
-                                                VisitCount& vc) {
-    const RayPre rp = ray_prepare(o, d);
-    const F3 inv{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
-    float tb = INFINITY, bV = 0.0f, bW = 0.0f, brcp = 0.0f;
-    uint32_t pb = 0xffffffffu;
-    int sp = 0;
-    uint32_t ref = 0;   // root node
-    bool have = true;
-    while (have) {
-        if (!(ref & SC_LEAF_BIT)) {
-            NodeTest nt;
-            test_node(S.nodes + ref, o, inv, search_limit(tb), nt);
-            if (COUNT) ++vc.nodes;
-            sort8(nt.key, nt.ref);
-            if (nt.key[0] != 0xffffffffu) {
+__device__ __forceinline__ bool trav_step(const DevScene& S, TravState& t, uint2 (*lds)[BS], Spill& st,
+                                          VisitCount& vc) {
+    if (!(t.ref & SC_LEAF_BIT)) {
+        NodeTest nt;
+        test_node(S.nodes + t.ref, t.o, t.inv, search_limit(t.tb), nt);
+        if (COUNT) ++vc.nodes;
+        sort8(nt.key, nt.ref);
+        if (nt.key[0] != 0xffffffffu) {
 #pragma unroll
-                for (int c = 7; c >= 1; --c)
-                    if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, sp, make_uint2(nt.ref[c], nt.key[c]));
-                ref = nt.ref[0];
-                continue;
+            for (int c = 7; c >= 1; --c)
+                if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, t.sp, make_uint2(nt.ref[c], nt.key[c]));
+            t.ref = nt.ref[0];
+            return false;
+        }
+    } else {
+        const uint32_t first = t.ref & SC_LEAF_FIRST_MASK;
+        const uint32_t cnt = ((t.ref >> 28) & 7u) + 1u;
+        if (COUNT) vc.tris += cnt;
+        // triangles in groups of 4, all loads of a group issued before
+        // its tests (indexes clamped to the leaf, extra tests skipped)
+        for (uint32_t k0 = 0; k0 < cnt; k0 += 4) {
+            float4 ta[4], tb4[4], tc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t k = min(k0 + (uint32_t)j, cnt - 1u);
+                const float4* tp = S.tris + 3 * (size_t)(first + k);
+                ta[j] = tp[0]; tb4[j] = tp[1]; tc[j] = tp[2];
             }
-        } else {
-            const uint32_t first = ref & SC_LEAF_FIRST_MASK;
-            const uint32_t cnt = ((ref >> 28) & 7u) + 1u;
-            if (COUNT) vc.tris += cnt;
-            // triangles in groups of 4, all loads of a group issued before
-            // its tests (indexes clamped to the leaf, extra tests skipped)
-            for (uint32_t k0 = 0; k0 < cnt; k0 += 4) {
-                float4 ta[4], tb4[4], tc[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t k = min(k0 + (uint32_t)j, cnt - 1u);
-                    const float4* tp = S.tris + 3 * (size_t)(first + k);
-                    ta[j] = tp[0]; tb4[j] = tp[1]; tc[j] = tp[2];
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (k0 + (uint32_t)j >= cnt) break;
-                    const uint32_t prim = __float_as_uint(ta[j].w);
-                    TriHit h;
-                    if (tri_test(rp, perm(rp, ta[j]), perm(rp, tb4[j]), perm(rp, tc[j]), h)) {
-                        if (h.t < tb || (h.t == tb && prim < pb)) {
-                            tb = h.t; pb = prim; bV = h.V; bW = h.W; brcp = h.rcp;
-                        }
+            for (int j = 0; j < 4; ++j) {
+                if (k0 + (uint32_t)j >= cnt) break;
+                const uint32_t prim = __float_as_uint(ta[j].w);
+                TriHit h;
+                if (tri_test(t.rp, perm(t.rp, ta[j]), perm(t.rp, tb4[j]), perm(t.rp, tc[j]), h)) {
+                    if (h.t < t.tb || (h.t == t.tb && prim < t.pb)) {
+                        t.tb = h.t; t.pb = prim; t.bV = h.V; t.bW = h.W; t.brcp = h.rcp;
                     }
                 }
             }
         }
-        // next entry from the stack that is still within reach
-        have = false;
-        while (sp > 0) {
-            const uint2 e = pop<BS>(lds, st, sp);
-            if (__uint_as_float(e.y) <= search_limit(tb)) {
-                ref = e.x;
-                have = true;
-                break;
-            }
+    }
+    // next entry from the stack that is still within reach
+    while (t.sp > 0) {
+        const uint2 e = pop<BS>(lds, st, t.sp);
+        if (__uint_as_float(e.y) <= search_limit(t.tb)) {
+            t.ref = e.x;
+            return false;
         }
     }
-    return HitRec{tb, bV * brcp, bW * brcp, pb};
+    return true;
+}
+
+__device__ __forceinline__ HitRec trav_result(const TravState& t) {
+    return HitRec{t.tb, t.bV * t.brcp, t.bW * t.brcp, t.pb};
+}
+
+template <int BS, bool COUNT>
+__device__ __forceinline__ HitRec trace_closest(const DevScene& S, F3 o, F3 d, uint2 (*lds)[BS], Spill& st,
+                                                VisitCount& vc) {
+    TravState t;
+    trav_init(t, o, d);
+    while (!trav_step<BS, COUNT>(S, t, lds, st, vc)) {
+    }
+    return trav_result(t);
 }
 
 // Any hit with 0 < t < tmax, skipping triangle excl.

@@ -66,6 +66,14 @@ __device__ __forceinline__ uint32_t wave_next_chunk(uint32_t* work) {
 }
 
 // ------------------------------------------------------------------ closest hit
+constexpr uint32_t kRefill = 16;   // idle lanes that trigger a refill
+
+// Persistent lanes: each wave owns a batch of rays [next, end) (the first
+// by its index in the grid, the rest from the launch's atomic counter); a
+// lane whose ray is finished takes the next ray of the batch once at least
+// kRefill lanes of the wave are idle, while the others keep traversing, so
+// a wave does not idle behind its slowest ray.  Batch size: 64 to 256 rays,
+// smaller for small launches so that the rays spread over the whole grid.
 template <bool COUNT>
 __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitSoA H, const uint32_t* __restrict__ queue,
                                                       const uint32_t* __restrict__ count, uint32_t n_static,
@@ -73,24 +81,48 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
     __shared__ uint2 lds[kLdsStack][kTraceBS];
     Spill st;
     const uint32_t n = count ? *count : n_static;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t per_wave = n / (4u * waves);
+    const uint32_t batch = per_wave >= 256u ? 256u : (per_wave >= 128u ? 128u : 64u);
+    uint32_t next = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * batch;
+    uint32_t end = next < n ? min(next + batch, n) : next;
     VisitCount vc;
     unsigned long long c_rays = 0;
-    uint32_t base = wave_first_chunk();
+    TravState t;
+    uint32_t pid = 0;
+    bool active = false, drained = next >= n;
     for (;;) {
-        if (base >= n) break;
-        const uint32_t i = base + lane_id();
-        if (i < n) {
-            const uint32_t pid = queue ? queue[i] : i;
-            const F3 o{R.ox[pid], R.oy[pid], R.oz[pid]};
-            const F3 d{R.dx[pid], R.dy[pid], R.dz[pid]};
-            const HitRec h = trace_closest<kTraceBS, COUNT>(S, o, d, lds, st, vc);
+        const unsigned long long idle = __ballot(!active);
+        const uint32_t n_idle = (uint32_t)__popcll(idle);
+        if (n_idle >= kRefill) {
+            if (next >= end && !drained) {
+                uint32_t base = 0;
+                if (lane_id() == 0) base = atomicAdd(work, batch);
+                base = __shfl(base, 0) + waves * batch;
+                next = base;
+                end = base < n ? min(base + batch, n) : base;
+                drained = base >= n;
+            }
+            if (!active) {
+                const uint32_t i = next + lanes_below(idle);
+                if (i < end) {
+                    pid = queue ? queue[i] : i;
+                    trav_init(t, F3{R.ox[pid], R.oy[pid], R.oz[pid]}, F3{R.dx[pid], R.dy[pid], R.dz[pid]});
+                    active = true;
+                }
+            }
+            next = min(next + n_idle, end);
+        }
+        if (__ballot(active) == 0ull) break;
+        if (active && trav_step<kTraceBS, COUNT>(S, t, lds, st, vc)) {
+            const HitRec h = trav_result(t);
             H.t[pid] = h.t;
             H.prim[pid] = h.prim;
             if (H.u) H.u[pid] = h.u;
             if (H.v) H.v[pid] = h.v;
             ++c_rays;
+            active = false;
         }
-        base = wave_next_chunk(work);
     }
     c_rays = wave_sum_u64(c_rays);
     unsigned long long c_nodes = 0, c_tris = 0;
