@@ -168,52 +168,48 @@ sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* sc, const sc_bvh_opts* opts,
     scl::Bvh* b = &h->b;
     b->ctx = c;
     b->scene_in = *sc;
-    sc_status s = scl::build_wide_bvh(c, b, width, leaf_max);
+    std::vector<float> tg(4 * (size_t)sc->n_tg);
+    for (uint32_t i = 0; i < 4 * sc->n_tg; ++i) tg[i] = sc->targets_sphere[i];
+    sc_status s = SC_OK;
+    if ((s = upload(b->mat, sc->mat, sizeof(sc_material) * sc->n_mat, st)) == SC_OK &&
+        (s = upload(b->pl, sc->point_lights, 16 * (size_t)sc->n_pl, st)) == SC_OK)
+        s = upload(b->tg, tg.data(), 16 * (size_t)sc->n_tg, st);
+    // emissive triangles in index order with their vertices, from the builder
+    std::vector<uint32_t> emit_prim;
+    std::vector<float> emit_v;
+    if (s == SC_OK) s = scl::build_wide_bvh(c, b, width, leaf_max, emit_prim, emit_v);
     if (s == SC_OK && b->max_stack > (uint32_t)kMaxStack)
         s = set_error(SC_EUNSUPPORTED, "BVH depth " + std::to_string(b->depth) + " needs a traversal stack of " +
                                            std::to_string(b->max_stack) + " > " + std::to_string(kMaxStack));
-    // emissive triangles: areas in double, cumulative distribution rounded to float
-    std::vector<uint32_t> emit_prim;
+    // emitter areas in double, cumulative distribution rounded to float
     std::vector<float> emit_cdf;
     double a_tot = 0.0;
     float max_power = 0.0f;
     if (s == SC_OK) {
-        bool any_emit = false;
-        for (uint32_t i = 1; i < sc->n_mat; ++i) any_emit = any_emit || sc->mat[i].type == SC_MAT_EMISSIVE;
-        if (any_emit) {
-            std::vector<uint32_t> tobj(sc->nt), I(3 * (size_t)sc->nt);
-            std::vector<float> V(3 * (size_t)sc->nv);
-            if (hipMemcpy(tobj.data(), sc->tri_obj, 4 * (size_t)sc->nt, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(I.data(), sc->I, 12 * (size_t)sc->nt, hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(V.data(), sc->V, 12 * (size_t)sc->nv, hipMemcpyDeviceToHost) != hipSuccess) {
-                s = set_error(SC_EDEVICE, "reading the scene back failed");
-            } else {
-                std::vector<double> area;
-                for (uint32_t i = 0; i < sc->nt; ++i) {
-                    if (sc->mat[tobj[i]].type != SC_MAT_EMISSIVE) continue;
-                    double a[3], bb[3], cc[3];
-                    for (int j = 0; j < 3; ++j) {
-                        a[j] = V[3 * (size_t)I[3 * (size_t)i] + j];
-                        bb[j] = V[3 * (size_t)I[3 * (size_t)i + 1] + j];
-                        cc[j] = V[3 * (size_t)I[3 * (size_t)i + 2] + j];
-                    }
-                    const double e1[3] = {bb[0] - a[0], bb[1] - a[1], bb[2] - a[2]};
-                    const double e2[3] = {cc[0] - a[0], cc[1] - a[1], cc[2] - a[2]};
-                    const double cx = e1[1] * e2[2] - e1[2] * e2[1];
-                    const double cy = e1[2] * e2[0] - e1[0] * e2[2];
-                    const double cz = e1[0] * e2[1] - e1[1] * e2[0];
-                    area.push_back(0.5 * sqrt(cx * cx + cy * cy + cz * cz));
-                    a_tot += area.back();
-                    emit_prim.push_back(i);
-                }
-                double cum = 0.0;
-                for (size_t j = 0; j < area.size(); ++j) {
-                    cum += area[j];
-                    emit_cdf.push_back((float)(cum / a_tot));
-                }
-                if (!emit_cdf.empty()) emit_cdf.back() = 1.0f;
+        std::vector<double> area;
+        area.reserve(emit_prim.size());
+        for (size_t k = 0; k < emit_prim.size(); ++k) {
+            const float* tv = emit_v.data() + 9 * k;
+            double a[3], bb[3], cc[3];
+            for (int j = 0; j < 3; ++j) {
+                a[j] = tv[j];
+                bb[j] = tv[3 + j];
+                cc[j] = tv[6 + j];
             }
+            const double e1[3] = {bb[0] - a[0], bb[1] - a[1], bb[2] - a[2]};
+            const double e2[3] = {cc[0] - a[0], cc[1] - a[1], cc[2] - a[2]};
+            const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+            const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+            const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+            area.push_back(0.5 * sqrt(cx * cx + cy * cy + cz * cz));
+            a_tot += area.back();
         }
+        double cum = 0.0;
+        for (size_t j = 0; j < area.size(); ++j) {
+            cum += area[j];
+            emit_cdf.push_back((float)(cum / a_tot));
+        }
+        if (!emit_cdf.empty()) emit_cdf.back() = 1.0f;
     }
     if (s == SC_OK) {
         const float atf = (float)a_tot;
@@ -222,12 +218,7 @@ sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* sc, const sc_bvh_opts* opts,
             for (uint32_t i = 1; i < sc->n_mat; ++i)
                 if (sc->mat[i].type == SC_MAT_EMISSIVE) max_power = std::max(max_power, sc->mat[i].le * atf);
         b->max_power = max_power;
-        std::vector<float> tg(4 * (size_t)sc->n_tg);
-        for (uint32_t i = 0; i < 4 * sc->n_tg; ++i) tg[i] = sc->targets_sphere[i];
-        if ((s = upload(b->mat, sc->mat, sizeof(sc_material) * sc->n_mat, st)) == SC_OK &&
-            (s = upload(b->pl, sc->point_lights, 16 * (size_t)sc->n_pl, st)) == SC_OK &&
-            (s = upload(b->tg, tg.data(), 16 * (size_t)sc->n_tg, st)) == SC_OK &&
-            (s = upload(b->emit_prim, emit_prim.data(), 4 * emit_prim.size(), st)) == SC_OK &&
+        if ((s = upload(b->emit_prim, emit_prim.data(), 4 * emit_prim.size(), st)) == SC_OK &&
             (s = upload(b->emit_cdf, emit_cdf.data(), 4 * emit_cdf.size(), st)) == SC_OK) {
             if (hipStreamSynchronize(st) != hipSuccess) s = set_error(SC_EDEVICE, "upload failed");
         }

@@ -38,16 +38,21 @@ __global__ void k_validate(const uint32_t* __restrict__ I, const uint32_t* __res
     }
 }
 
-// bounds [nt][6] (lo xyz, hi xyz) and centroid bounds (ordered uints)
-__global__ void k_tri_bounds(const float* __restrict__ V, const uint32_t* __restrict__ I, uint32_t nt,
-                             float* __restrict__ bounds, uint32_t* __restrict__ cb) {
+// bounds [nt][6] (lo xyz, hi xyz) and centroid bounds (ordered uints).
+// Vertex indices are clamped to the vertex array so that invalid input
+// (reported by k_validate) reads nothing out of bounds.  One atomic per
+// block for the centroid bounds.
+__global__ __launch_bounds__(256) void k_tri_bounds(const float* __restrict__ V, const uint32_t* __restrict__ I,
+                                                    uint32_t nt, uint32_t nv, float* __restrict__ bounds,
+                                                    uint32_t* __restrict__ cb) {
     float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
         const uint32_t* idx = I + 3 * (size_t)i;
+        const uint32_t i0 = min(idx[0], nv - 1), i1 = min(idx[1], nv - 1), i2 = min(idx[2], nv - 1);
         float lo[3], hi[3];
         bool finite = true;
         for (int k = 0; k < 3; ++k) {
-            const float a = V[3 * (size_t)idx[0] + k], b = V[3 * (size_t)idx[1] + k], c = V[3 * (size_t)idx[2] + k];
+            const float a = V[3 * (size_t)i0 + k], b = V[3 * (size_t)i1 + k], c = V[3 * (size_t)i2 + k];
             finite = finite && isfinite(a) && isfinite(b) && isfinite(c);
             lo[k] = fminf(a, fminf(b, c));
             hi[k] = fmaxf(a, fmaxf(b, c));
@@ -66,17 +71,108 @@ __global__ void k_tri_bounds(const float* __restrict__ V, const uint32_t* __rest
             }
         }
     }
+    __shared__ float red[4][6];
     for (int k = 0; k < 3; ++k) {
         for (int off = 32; off > 0; off >>= 1) {
             clo[k] = fminf(clo[k], __shfl_xor(clo[k], off));
             chi[k] = fmaxf(chi[k], __shfl_xor(chi[k], off));
         }
     }
-    if (__lane_id() == 0) {
+    const uint32_t w = threadIdx.x >> 6;
+    if (__lane_id() == 0)
+        for (int k = 0; k < 3; ++k) { red[w][k] = clo[k]; red[w][3 + k] = chi[k]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t v = 1; v < (blockDim.x >> 6); ++v)
+            for (int k = 0; k < 3; ++k) {
+                clo[k] = fminf(clo[k], red[v][k]);
+                chi[k] = fmaxf(chi[k], red[v][3 + k]);
+            }
         for (int k = 0; k < 3; ++k) {
             atomicMin(&cb[k], ordered(clo[k]));
             atomicMax(&cb[3 + k], ordered(chi[k]));
         }
+    }
+}
+
+// Emissive triangles, compacted in index order: per segment of 256
+// triangles a count, one scan over the segments, then each segment writes
+// its emitters (index and the 9 vertex coordinates) at its offset.
+__device__ __forceinline__ bool is_emitter(const uint32_t* __restrict__ tri_obj, const sc_material* __restrict__ mat,
+                                           uint32_t n_mat, uint32_t i, uint32_t nt) {
+    if (i >= nt) return false;
+    const uint32_t o = tri_obj[i];
+    return o >= 1 && o < n_mat && mat[o].type == SC_MAT_EMISSIVE;
+}
+
+__global__ __launch_bounds__(256) void k_emit_count(const uint32_t* __restrict__ tri_obj,
+                                                    const sc_material* __restrict__ mat, uint32_t n_mat, uint32_t nt,
+                                                    uint32_t* __restrict__ seg_cnt) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    const int c = __syncthreads_count(is_emitter(tri_obj, mat, n_mat, i, nt));
+    if (threadIdx.x == 0) seg_cnt[blockIdx.x] = (uint32_t)c;
+}
+
+// exclusive scan of nseg counts by one block of 1024 threads; total in *total
+__global__ __launch_bounds__(1024) void k_emit_scan(const uint32_t* __restrict__ seg_cnt, uint32_t nseg,
+                                                    uint32_t* __restrict__ seg_off, uint32_t* __restrict__ total) {
+    __shared__ uint32_t part[1024];
+    const uint32_t per = (nseg + 1023u) / 1024u;
+    const uint32_t b0 = threadIdx.x * per, b1 = min(b0 + per, nseg);
+    uint32_t sum = 0;
+    for (uint32_t j = b0; j < b1; ++j) sum += seg_cnt[j];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024u; off <<= 1) {
+        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;   // exclusive prefix of this thread's range
+    for (uint32_t j = b0; j < b1; ++j) {
+        seg_off[j] = run;
+        run += seg_cnt[j];
+    }
+    if (threadIdx.x == 1023) *total = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_emit_gather(const uint32_t* __restrict__ tri_obj,
+                                                     const sc_material* __restrict__ mat, uint32_t n_mat,
+                                                     uint32_t nt, const uint32_t* __restrict__ I,
+                                                     const float* __restrict__ V, uint32_t nv,
+                                                     const uint32_t* __restrict__ seg_off,
+                                                     uint32_t* __restrict__ out_prim, float* __restrict__ out_v) {
+    __shared__ uint32_t wcnt[4];
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    const bool e = is_emitter(tri_obj, mat, n_mat, i, nt);
+    const unsigned long long m = __ballot(e);
+    const uint32_t w = threadIdx.x >> 6;
+    if (__lane_id() == 0) wcnt[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t base = seg_off[blockIdx.x];
+    for (uint32_t v = 0; v < w; ++v) base += wcnt[v];
+    if (e) {
+        const uint32_t k = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        out_prim[k] = i;
+        for (int j = 0; j < 3; ++j) {
+            const uint32_t vi = min(I[3 * (size_t)i + j], nv - 1);
+            for (int c = 0; c < 3; ++c) out_v[9 * (size_t)k + 3 * j + c] = V[3 * (size_t)vi + c];
+        }
+    }
+}
+
+// Builder start state: error flags, node and emitter counts and the
+// per-level work counts cleared, the root (radix-tree node 0, or the single
+// leaf when n == 1) as the one work item of level 0, empty centroid bounds.
+__global__ void k_build_init(uint32_t* meta, uint32_t n_meta, uint2* work0, uint32_t* cb) {
+    for (uint32_t i = threadIdx.x; i < n_meta; i += blockDim.x) meta[i] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        meta[1] = 1u;          // nodes allocated: the root
+        meta[8] = 1u;          // level 0 work: the root
+        work0[0] = make_uint2(0u, 0u);
+        for (int k = 0; k < 3; ++k) { cb[k] = 0xffffffffu; cb[3 + k] = 0u; }
     }
 }
 
@@ -301,13 +397,13 @@ __global__ void k_collapse(uint32_t n, const int32_t* __restrict__ left, const i
 }
 
 __global__ void k_gather_tris(const unsigned long long* __restrict__ keys, uint32_t n, const float* __restrict__ V,
-                              const uint32_t* __restrict__ I, float4* __restrict__ tris) {
+                              uint32_t nv, const uint32_t* __restrict__ I, float4* __restrict__ tris) {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
         const uint32_t prim = (uint32_t)(keys[p] & 0xffffffffull);
         const uint32_t* idx = I + 3 * (size_t)prim;
-        const float* a = V + 3 * (size_t)idx[0];
-        const float* b = V + 3 * (size_t)idx[1];
-        const float* c = V + 3 * (size_t)idx[2];
+        const float* a = V + 3 * (size_t)min(idx[0], nv - 1);
+        const float* b = V + 3 * (size_t)min(idx[1], nv - 1);
+        const float* c = V + 3 * (size_t)min(idx[2], nv - 1);
         tris[3 * (size_t)p + 0] = make_float4(a[0], a[1], a[2], __uint_as_float(prim));
         tris[3 * (size_t)p + 1] = make_float4(b[0], b[1], b[2], 0.0f);
         tris[3 * (size_t)p + 2] = make_float4(c[0], c[1], c[2], 0.0f);
@@ -345,108 +441,111 @@ static bool debug_sync() {
             return set_error(SC_EDEVICE, std::string("launch failed: ") + hipGetErrorString(_le)); \
     } while (0)
 
-// Builds nodes/tris into the handle.  Returns SC_OK or an error code with
-// the message set.
-sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max) {
+constexpr uint32_t kMaxLevels = 64;   // wide levels (the radix tree is at most 62 deep)
+constexpr uint32_t kMeta = 8 + kMaxLevels + 1;
+constexpr uint32_t kLevelBatch = 4;  // collapse levels launched between host checks
+
+sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max, std::vector<uint32_t>& emit_prim,
+                         std::vector<float>& emit_v) {
     hipStream_t st = ctx->stream;
-    const uint32_t n = b->scene_in.nt;
+    const sc_scene& sc = b->scene_in;
+    const uint32_t n = sc.nt;
     uint32_t n_pad = 1;
     while (n_pad < n) n_pad <<= 1;
     if (n_pad < (uint32_t)kLocal) n_pad = kLocal;
-
     uint32_t levels = 1;
     while ((2u << (levels - 1)) <= n) ++levels;   // levels 0..floor(log2 n)
-    DevBuf err_d, bounds, cb, keys, left, right, rlo, rhi, st_buf, work_a, work_b, counters;
-    SC_TRY(err_d.alloc(sizeof(uint32_t)));
-    SC_TRY(bounds.alloc(sizeof(float) * 6 * (size_t)n));
-    SC_TRY(cb.alloc(sizeof(uint32_t) * 6));
-    SC_TRY(keys.alloc(sizeof(unsigned long long) * (size_t)n_pad));
-    SC_TRY(left.alloc(sizeof(int32_t) * (size_t)(n > 1 ? n - 1 : 1)));
-    SC_TRY(right.alloc(sizeof(int32_t) * (size_t)(n > 1 ? n - 1 : 1)));
-    SC_TRY(rlo.alloc(sizeof(uint32_t) * (size_t)(n > 1 ? n - 1 : 1)));
-    SC_TRY(rhi.alloc(sizeof(uint32_t) * (size_t)(n > 1 ? n - 1 : 1)));
-    SC_TRY(st_buf.alloc(sizeof(float) * 6 * (size_t)n * levels));
-    SC_TRY(work_a.alloc(sizeof(uint2) * (size_t)n));
-    SC_TRY(work_b.alloc(sizeof(uint2) * (size_t)n));
-    SC_TRY(counters.alloc(sizeof(uint32_t) * 4));
+    const uint32_t nseg = (n + 255u) / 256u;
+    const size_t ni = n > 1 ? n - 1 : 1;
+
+    // temporaries, carved from one grow-only buffer of the context
+    uint32_t *meta, *cb, *rlo, *rhi, *seg_cnt, *seg_off, *e_prim;
+    float *bounds, *st_buf, *e_v;
+    unsigned long long* keys;
+    int32_t *left, *right;
+    uint2 *work_a, *work_b;
+    BNode* nodes_tmp;
+    auto carve = [&](char* base) {
+        Carver c{base};
+        meta = c.take<uint32_t>(kMeta);
+        cb = c.take<uint32_t>(6);
+        bounds = c.take<float>(6 * (size_t)n);
+        keys = c.take<unsigned long long>(n_pad);
+        left = c.take<int32_t>(ni);
+        right = c.take<int32_t>(ni);
+        rlo = c.take<uint32_t>(ni);
+        rhi = c.take<uint32_t>(ni);
+        st_buf = c.take<float>(6 * (size_t)n * levels);
+        work_a = c.take<uint2>(n);
+        work_b = c.take<uint2>(n);
+        nodes_tmp = c.take<BNode>(n);
+        seg_cnt = c.take<uint32_t>(nseg);
+        seg_off = c.take<uint32_t>(nseg);
+        e_prim = c.take<uint32_t>(n);
+        e_v = c.take<float>(9 * (size_t)n);
+        return c.off;
+    };
+    SC_TRY(ctx->bvh_tmp.ensure(carve(nullptr) + 256));
+    carve(static_cast<char*>(ctx->bvh_tmp.p));
 
     const uint32_t bs = 256;
-    SC_LAUNCH(k_init_u32, dim3(1), dim3(64), 0, st, err_d.as<uint32_t>(), 1u, 0u);
-    SC_LAUNCH(k_validate, dim3(grid_for(n, bs)), dim3(bs), 0, st, b->scene_in.I, b->scene_in.tri_obj, n,
-                       b->scene_in.nv, b->scene_in.n_mat, err_d.as<uint32_t>());
-    uint32_t err_h = 0;
-    SC_HIP(hipMemcpyAsync(&err_h, err_d.p, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    SC_HIP(hipStreamSynchronize(st));
-    if (err_h & 1u) return set_error(SC_EINVAL, "tri_obj holds an object id outside [1, n_mat)");
-    if (err_h & 2u) return set_error(SC_EINVAL, "I holds a vertex index >= nv");
-
-    uint32_t cb_init[6] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
-    SC_HIP(hipMemcpyAsync(cb.p, cb_init, sizeof(cb_init), hipMemcpyHostToDevice, st));
-    SC_LAUNCH(k_tri_bounds, dim3(grid_for(n, bs, 4096)), dim3(bs), 0, st, b->scene_in.V, b->scene_in.I, n,
-                       bounds.as<float>(), cb.as<uint32_t>());
-    SC_LAUNCH(k_morton, dim3(grid_for(n_pad, bs)), dim3(bs), 0, st, bounds.as<float>(), n, n_pad,
-                       cb.as<uint32_t>(), keys.as<unsigned long long>());
+    const sc_material* mat_d = b->mat.as<sc_material>();
+    SC_LAUNCH(k_build_init, dim3(1), dim3(256), 0, st, meta, kMeta, work_a, cb);
+    SC_LAUNCH(k_validate, dim3(grid_for(n, bs)), dim3(bs), 0, st, sc.I, sc.tri_obj, n, sc.nv, sc.n_mat, meta);
+    SC_LAUNCH(k_tri_bounds, dim3(grid_for(n, bs, 512)), dim3(bs), 0, st, sc.V, sc.I, n, sc.nv, bounds, cb);
+    SC_LAUNCH(k_emit_count, dim3(nseg), dim3(256), 0, st, sc.tri_obj, mat_d, sc.n_mat, n, seg_cnt);
+    SC_LAUNCH(k_emit_scan, dim3(1), dim3(1024), 0, st, seg_cnt, nseg, seg_off, meta + 2);
+    SC_LAUNCH(k_emit_gather, dim3(nseg), dim3(256), 0, st, sc.tri_obj, mat_d, sc.n_mat, n, sc.I, sc.V, sc.nv, seg_off,
+              e_prim, e_v);
+    SC_LAUNCH(k_morton, dim3(grid_for(n_pad, bs)), dim3(bs), 0, st, bounds, n, n_pad, cb, keys);
     // bitonic sort
     const uint32_t nblk = n_pad / kLocal;
-    SC_LAUNCH(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys.as<unsigned long long>(), 2u,
-                       (uint32_t)kLocal);
+    SC_LAUNCH(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys, 2u, (uint32_t)kLocal);
     for (uint32_t k = 2 * kLocal; k <= n_pad; k <<= 1) {
         for (uint32_t j = k >> 1; j >= (uint32_t)kLocal; j >>= 1)
-            SC_LAUNCH(k_bitonic_global, dim3(grid_for(n_pad / 2, bs)), dim3(bs), 0, st,
-                               keys.as<unsigned long long>(), n_pad, k, j);
-        SC_LAUNCH(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys.as<unsigned long long>(), k, k);
+            SC_LAUNCH(k_bitonic_global, dim3(grid_for(n_pad / 2, bs)), dim3(bs), 0, st, keys, n_pad, k, j);
+        SC_LAUNCH(k_bitonic_local, dim3(nblk), dim3(1024), 0, st, keys, k, k);
     }
     // radix tree
-    if (n > 1)
-        SC_LAUNCH(k_radix_tree, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(), n,
-                  left.as<int32_t>(), right.as<int32_t>(), rlo.as<uint32_t>(), rhi.as<uint32_t>());
+    if (n > 1) SC_LAUNCH(k_radix_tree, dim3(grid_for(n - 1, bs)), dim3(bs), 0, st, keys, n, left, right, rlo, rhi);
     // range-union table for node boxes
-    SC_LAUNCH(k_sparse_level0, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(),
-              bounds.as<float>(), n, st_buf.as<float>());
+    SC_LAUNCH(k_sparse_level0, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys, bounds, n, st_buf);
     for (uint32_t L = 1; L < levels; ++L)
-        SC_LAUNCH(k_sparse_level, dim3(grid_for(n - (1u << L) + 1, bs)), dim3(bs), 0, st, st_buf.as<float>(), n, L);
+        SC_LAUNCH(k_sparse_level, dim3(grid_for(n - (1u << L) + 1, bs)), dim3(bs), 0, st, st_buf, n, L);
 
-    // collapse: level by level
-    const uint32_t max_nodes = n > 1 ? n : 1;
-    DevBuf nodes_tmp;
-    SC_TRY(nodes_tmp.alloc(sizeof(BNode) * (size_t)max_nodes));
-    uint32_t init_cnt[4] = {1u, 0u, 1u, 0u};   // [0] work count, [1] next count, [2] nodes allocated
-    SC_HIP(hipMemcpyAsync(counters.p, init_cnt, sizeof(init_cnt), hipMemcpyHostToDevice, st));
-    const uint2 root = make_uint2(n > 1 ? 0u : 0u, 0u);
-    uint2 root_item = root;
-    if (n == 1) root_item.x = 0;   // leaf index n-1+0 = 0 when n == 1
-    SC_HIP(hipMemcpyAsync(work_a.p, &root_item, sizeof(uint2), hipMemcpyHostToDevice, st));
+    // collapse, one wide level per launch; level L reads its work count
+    // from meta[8 + L] and appends the next level's items to meta[9 + L],
+    // so the host checks for the end only every kLevelBatch levels
+    uint32_t h[kMeta];
     uint32_t depth = 0;
-    uint32_t cur_count = 1;
-    DevBuf* wa = &work_a;
-    DevBuf* wb = &work_b;
-    while (cur_count > 0) {
-        uint32_t zero = 0;
-        SC_HIP(hipMemcpyAsync(counters.as<uint32_t>() + 1, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        SC_LAUNCH(k_collapse, dim3(grid_for(cur_count, 128)), dim3(128), 0, st, n, left.as<int32_t>(),
-                           right.as<int32_t>(), rlo.as<uint32_t>(), rhi.as<uint32_t>(), st_buf.as<float>(), leaf_max,
-                           width, wa->as<uint2>(), counters.as<uint32_t>(), wb->as<uint2>(),
-                           counters.as<uint32_t>() + 1, counters.as<uint32_t>() + 2, nodes_tmp.as<BNode>());
-        uint32_t h[3];
-        SC_HIP(hipMemcpyAsync(h, counters.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    for (uint32_t L0 = 0;; L0 += kLevelBatch) {
+        if (L0 + kLevelBatch > kMaxLevels) return set_error(SC_EDEVICE, "BVH collapse did not terminate");
+        for (uint32_t L = L0; L < L0 + kLevelBatch; ++L) {
+            const uint2* wa = (L & 1u) ? work_b : work_a;
+            uint2* wb = (L & 1u) ? work_a : work_b;
+            SC_LAUNCH(k_collapse, dim3(grid_for(n, 128, 512)), dim3(128), 0, st, n, left, right, rlo, rhi, st_buf,
+                      leaf_max, width, wa, meta + 8 + L, wb, meta + 9 + L, meta + 1, nodes_tmp);
+        }
+        SC_HIP(hipMemcpyAsync(h, meta, sizeof(h), hipMemcpyDeviceToHost, st));
         SC_HIP(hipStreamSynchronize(st));
-        cur_count = h[1];
-        SC_HIP(hipMemcpyAsync(counters.p, &cur_count, sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        DevBuf* t = wa;
-        wa = wb;
-        wb = t;
-        ++depth;
-        if (depth > 4096) return set_error(SC_EDEVICE, "BVH collapse did not terminate");
+        if (h[0] & 1u) return set_error(SC_EINVAL, "tri_obj holds an object id outside [1, n_mat)");
+        if (h[0] & 2u) return set_error(SC_EINVAL, "I holds a vertex index >= nv");
+        if (h[8 + L0 + kLevelBatch] == 0) break;
     }
-    uint32_t n_nodes = 0;
-    SC_HIP(hipMemcpyAsync(&n_nodes, counters.as<uint32_t>() + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    SC_HIP(hipStreamSynchronize(st));
+    while (depth < kMaxLevels && h[8 + depth] > 0) ++depth;
+    const uint32_t n_nodes = h[1];
+    const uint32_t n_emit = h[2];
 
     SC_TRY(b->nodes.alloc(sizeof(BNode) * (size_t)n_nodes));
-    SC_HIP(hipMemcpyAsync(b->nodes.p, nodes_tmp.p, sizeof(BNode) * (size_t)n_nodes, hipMemcpyDeviceToDevice, st));
+    SC_HIP(hipMemcpyAsync(b->nodes.p, nodes_tmp, sizeof(BNode) * (size_t)n_nodes, hipMemcpyDeviceToDevice, st));
     SC_TRY(b->tris.alloc(sizeof(float4) * 3 * (size_t)n));
-    SC_LAUNCH(k_gather_tris, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys.as<unsigned long long>(), n,
-                       b->scene_in.V, b->scene_in.I, b->tris.as<float4>());
+    SC_LAUNCH(k_gather_tris, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys, n, sc.V, sc.nv, sc.I, b->tris.as<float4>());
+    emit_prim.resize(n_emit);
+    emit_v.resize(9 * (size_t)n_emit);
+    if (n_emit) {
+        SC_HIP(hipMemcpyAsync(emit_prim.data(), e_prim, 4 * (size_t)n_emit, hipMemcpyDeviceToHost, st));
+        SC_HIP(hipMemcpyAsync(emit_v.data(), e_v, 36 * (size_t)n_emit, hipMemcpyDeviceToHost, st));
+    }
     SC_HIP(hipGetLastError());
     SC_HIP(hipStreamSynchronize(st));
     b->n_nodes = n_nodes;

@@ -49,6 +49,20 @@ struct DevBuf {
     }
 };
 
+// Sub-allocation of one device buffer into 256-byte aligned arrays
+// (base == nullptr only measures: off is then the bytes needed).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = reinterpret_cast<T*>(base + off);
+        off += sizeof(T) * n;
+        return p;
+    }
+};
+
 #define SC_TRY(expr)                      \
     do {                                  \
         sc_status _s = (expr);            \
@@ -83,6 +97,7 @@ struct Ctx {
     float sensor_lo = -1.0f, sensor_hi = -1.0f;
     uint32_t sensor_n = 0;
     DevBuf aos;        // SoA copies for sc_trace_rays / sc_occluded
+    DevBuf bvh_tmp;    // temporaries of the BVH builder (grow-only, reused)
     size_t aos_n = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     double closest_ms = 0.0;
@@ -99,7 +114,11 @@ struct Bvh {
     float max_power = 0.0f;
 };
 
-sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max);
+// Builds b->nodes and b->tris for b->scene_in (b->mat must already hold the
+// materials on the device).  Also returns the emissive triangles in index
+// order with their vertices (9 floats each).  Synchronises the stream.
+sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max, std::vector<uint32_t>& emit_prim,
+                         std::vector<float>& emit_v);
 
 }  // namespace scl
 

@@ -511,18 +511,6 @@ namespace {
 constexpr uint32_t kWorkSlots = 4096;
 
 // carve n-element arrays out of one allocation, 256-byte aligned
-struct Carver {
-    char* base;
-    size_t off = 0;
-    template <class T>
-    T* take(size_t n) {
-        off = (off + 255) & ~(size_t)255;
-        T* p = reinterpret_cast<T*>(base + off);
-        off += sizeof(T) * n;
-        return p;
-    }
-};
-
 size_t path_bytes(size_t n) { return 25 * (n * 4 + 256); }
 size_t photon_bytes(size_t n) { return 16 * (n * 4 + 256); }
 
