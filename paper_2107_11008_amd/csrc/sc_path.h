@@ -199,45 +199,74 @@ __device__ __forceinline__ HitRec trace_closest(const DevScene& S, F3 o, F3 d, u
     return trav_result(t);
 }
 
-// Any hit with 0 < t < tmax, skipping triangle excl.
+// Any hit: is there a triangle other than excl with 0 < t < tmax?  As a
+// resumable traversal: any_step advances by one node visit or one leaf and
+// returns true when the answer (AnyState::hit) is known.
+struct AnyState {
+    RayPre rp;
+    F3 o, inv;
+    float tmax, tlim;
+    uint32_t excl, ref;
+    int sp;
+    bool hit;
+};
+
+__device__ __forceinline__ void any_init(AnyState& t, F3 o, F3 d, float tmax, uint32_t excl) {
+    t.rp = ray_prepare(o, d);
+    t.o = o;
+    t.inv = F3{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
+    t.tmax = tmax;
+    t.tlim = search_limit(tmax);
+    t.excl = excl;
+    t.ref = 0;
+    t.sp = 0;
+    t.hit = false;
+}
+
 template <int BS>
-__device__ __forceinline__ bool trace_any(const DevScene& S, F3 o, F3 d, float tmax, uint32_t excl, uint2 (*lds)[BS],
-                                          Spill& st) {
-    const RayPre rp = ray_prepare(o, d);
-    const F3 inv{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
-    const float tlim = search_limit(tmax);
-    int sp = 0;
-    uint32_t ref = 0;
-    for (;;) {
-        if (!(ref & SC_LEAF_BIT)) {
-            NodeTest nt;
-            test_node(S.nodes + ref, o, inv, tlim, nt);
+__device__ __forceinline__ bool any_step(const DevScene& S, AnyState& t, uint2 (*lds)[BS], Spill& st) {
+    if (!(t.ref & SC_LEAF_BIT)) {
+        NodeTest nt;
+        test_node(S.nodes + t.ref, t.o, t.inv, t.tlim, nt);
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, sp, make_uint2(nt.ref[c], nt.key[c]));
-        } else {
-            const uint32_t first = ref & SC_LEAF_FIRST_MASK;
-            const uint32_t cnt = ((ref >> 28) & 7u) + 1u;
-            for (uint32_t k0 = 0; k0 < cnt; k0 += 4) {
-                float4 ta[4], tb4[4], tc[4];
+        for (int c = 0; c < 8; ++c)
+            if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, t.sp, make_uint2(nt.ref[c], nt.key[c]));
+    } else {
+        const uint32_t first = t.ref & SC_LEAF_FIRST_MASK;
+        const uint32_t cnt = ((t.ref >> 28) & 7u) + 1u;
+        for (uint32_t k0 = 0; k0 < cnt; k0 += 4) {
+            float4 ta[4], tb4[4], tc[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t k = min(k0 + (uint32_t)j, cnt - 1u);
-                    const float4* tp = S.tris + 3 * (size_t)(first + k);
-                    ta[j] = tp[0]; tb4[j] = tp[1]; tc[j] = tp[2];
-                }
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t k = min(k0 + (uint32_t)j, cnt - 1u);
+                const float4* tp = S.tris + 3 * (size_t)(first + k);
+                ta[j] = tp[0]; tb4[j] = tp[1]; tc[j] = tp[2];
+            }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (k0 + (uint32_t)j >= cnt) break;
-                    if (__float_as_uint(ta[j].w) == excl) continue;
-                    TriHit h;
-                    if (tri_test(rp, perm(rp, ta[j]), perm(rp, tb4[j]), perm(rp, tc[j]), h) && h.t < tmax) return true;
+            for (int j = 0; j < 4; ++j) {
+                if (k0 + (uint32_t)j >= cnt) break;
+                if (__float_as_uint(ta[j].w) == t.excl) continue;
+                TriHit h;
+                if (tri_test(t.rp, perm(t.rp, ta[j]), perm(t.rp, tb4[j]), perm(t.rp, tc[j]), h) && h.t < t.tmax) {
+                    t.hit = true;
+                    return true;
                 }
             }
         }
-        if (sp == 0) return false;
-        ref = pop<BS>(lds, st, sp).x;
     }
+    if (t.sp == 0) return true;
+    t.ref = pop<BS>(lds, st, t.sp).x;
+    return false;
+}
+
+template <int BS>
+__device__ __forceinline__ bool trace_any(const DevScene& S, F3 o, F3 d, float tmax, uint32_t excl, uint2 (*lds)[BS],
+                                          Spill& st) {
+    AnyState t;
+    any_init(t, o, d, tmax, excl);
+    while (!any_step<BS>(S, t, lds, st)) {
+    }
+    return t.hit;
 }
 
 // ---------------------------------------------------------------- camera paths

@@ -94,8 +94,11 @@ struct Queues {
     uint32_t* diffuse;
     uint32_t* dielectric;
     uint32_t* shadow;
-    uint32_t* counts;  // [0] cur [1] next [2] diffuse [3] dielectric [4] shadow
+    uint32_t* counts;  // QC_CUR, QC_NEXT, QC_DIFF, QC_DIEL, QC_SHADOW: one 256-byte line each
 };
+// queue counters, each on its own cache line so that appends to different
+// queues do not contend for one line
+constexpr uint32_t QC_CUR = 0, QC_NEXT = 64, QC_DIFF = 128, QC_DIEL = 192, QC_SHADOW = 256, QC_WORDS = 320;
 
 // counters incremented by kernels
 struct DevCounters {

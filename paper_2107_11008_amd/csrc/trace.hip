@@ -7,9 +7,10 @@
 //              shade dielectric | shade diffuse (+ shadow ray) ->
 //              any hit (shadow) ] x depth -> film
 // Queue appends use one atomic per wave (ballot + mbcnt prefix).
-// Traversal kernels fetch 64 rays per wave from a per-launch atomic
-// counter, keep the traversal stack in LDS (spilling to scratch only for
-// deep trees) and visit the children of a wide node front to back.
+// Traversal kernels keep every lane busy: a wave takes batches of rays and
+// refills the lanes whose ray is finished while the others go on; the
+// traversal stack lives in LDS (spilling to scratch only for deep trees) and
+// the children of a wide node are visited front to back.
 #pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,16 +33,28 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Append `val` to queue q for lanes with pred; one atomic per wave.  Every
-// lane of the wave must call this.
-__device__ __forceinline__ void wave_push(bool pred, uint32_t val, uint32_t* q, uint32_t* cnt) {
+// Append `val` to queue q for threads with pred; one atomic per block.
+// Every thread of the block must call this (block size a multiple of 64,
+// at most 1024).
+__device__ __forceinline__ void block_push(bool pred, uint32_t val, uint32_t* q, uint32_t* cnt) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_base;
     const unsigned long long m = __ballot(pred);
-    if (m == 0ull) return;
-    const uint32_t leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
-    base = __shfl(base, (int)leader);
-    if (pred) q[base + lanes_below(m)] = val;
+    const uint32_t w = threadIdx.x >> 6;
+    if (lane_id() == 0) s_w[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (uint32_t k = 0; k < (blockDim.x >> 6); ++k) {
+            const uint32_t c = s_w[k];
+            s_w[k] = tot;
+            tot += c;
+        }
+        s_base = tot ? atomicAdd(cnt, tot) : 0u;
+    }
+    __syncthreads();
+    if (pred) q[s_base + s_w[w] + lanes_below(m)] = val;
+    __syncthreads();   // s_w and s_base are reused by the next call
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -53,65 +66,71 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// Ray chunks of 64 for a wave: the first by the wave's index in the grid,
-// the rest from the launch's atomic counter (offset by the statically
-// assigned chunks), so a launch with few rays costs no atomics.
-__device__ __forceinline__ uint32_t wave_first_chunk() {
-    return (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
-}
-__device__ __forceinline__ uint32_t wave_next_chunk(uint32_t* work) {
-    uint32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(work, 64u);
-    return __shfl(base, 0) + gridDim.x * blockDim.x;
-}
-
-// ------------------------------------------------------------------ closest hit
+// ------------------------------------------------------------------ ray feed
 constexpr uint32_t kRefill = 16;   // idle lanes that trigger a refill
 
-// Persistent lanes: each wave owns a batch of rays [next, end) (the first
-// by its index in the grid, the rest from the launch's atomic counter); a
+// Persistent lanes: each wave owns a batch of rays [next, end) of the
+// launch's list (the first batch by the wave's index in the grid, the rest
+// from the launch's atomic counter, so small launches cost no atomics); a
 // lane whose ray is finished takes the next ray of the batch once at least
-// kRefill lanes of the wave are idle, while the others keep traversing, so
-// a wave does not idle behind its slowest ray.  Batch size: 64 to 256 rays,
-// smaller for small launches so that the rays spread over the whole grid.
+// kRefill lanes of the wave are idle while the others go on, so a wave does
+// not idle behind its slowest ray.  Batches are 64 to 256 rays, smaller for
+// small launches so that the rays spread over the whole grid.  All members
+// are wave-uniform.
+struct RayFeed {
+    uint32_t n, waves, batch, next, end;
+    bool drained;
+
+    __device__ __forceinline__ void init(uint32_t n_rays) {
+        n = n_rays;
+        waves = gridDim.x * (blockDim.x >> 6);
+        const uint32_t per_wave = n / (4u * waves);
+        batch = per_wave >= 256u ? 256u : (per_wave >= 128u ? 128u : 64u);
+        next = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * batch;
+        end = next < n ? min(next + batch, n) : next;
+        drained = next >= n;
+    }
+
+    // Called by every lane of the wave; returns the list index of the new
+    // ray for an idle lane that receives one, else 0xffffffff.
+    __device__ __forceinline__ uint32_t take(bool idle_lane, uint32_t* work) {
+        const unsigned long long idle = __ballot(idle_lane);
+        const uint32_t n_idle = (uint32_t)__popcll(idle);
+        if (n_idle < kRefill) return 0xffffffffu;
+        if (next >= end && !drained) {
+            uint32_t base = 0;
+            if (lane_id() == 0) base = atomicAdd(work, batch);
+            base = __shfl(base, 0) + waves * batch;
+            next = base;
+            end = base < n ? min(base + batch, n) : base;
+            drained = base >= n;
+        }
+        const uint32_t i = next + lanes_below(idle);
+        next = min(next + n_idle, end);
+        return (idle_lane && i < end) ? i : 0xffffffffu;
+    }
+};
+
+// ------------------------------------------------------------------ closest hit
 template <bool COUNT>
 __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitSoA H, const uint32_t* __restrict__ queue,
                                                       const uint32_t* __restrict__ count, uint32_t n_static,
                                                       uint32_t* __restrict__ work, DevCounters* __restrict__ C) {
     __shared__ uint2 lds[kLdsStack][kTraceBS];
     Spill st;
-    const uint32_t n = count ? *count : n_static;
-    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-    const uint32_t per_wave = n / (4u * waves);
-    const uint32_t batch = per_wave >= 256u ? 256u : (per_wave >= 128u ? 128u : 64u);
-    uint32_t next = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * batch;
-    uint32_t end = next < n ? min(next + batch, n) : next;
+    RayFeed feed;
+    feed.init(count ? *count : n_static);
     VisitCount vc;
     unsigned long long c_rays = 0;
     TravState t;
     uint32_t pid = 0;
-    bool active = false, drained = next >= n;
+    bool active = false;
     for (;;) {
-        const unsigned long long idle = __ballot(!active);
-        const uint32_t n_idle = (uint32_t)__popcll(idle);
-        if (n_idle >= kRefill) {
-            if (next >= end && !drained) {
-                uint32_t base = 0;
-                if (lane_id() == 0) base = atomicAdd(work, batch);
-                base = __shfl(base, 0) + waves * batch;
-                next = base;
-                end = base < n ? min(base + batch, n) : base;
-                drained = base >= n;
-            }
-            if (!active) {
-                const uint32_t i = next + lanes_below(idle);
-                if (i < end) {
-                    pid = queue ? queue[i] : i;
-                    trav_init(t, F3{R.ox[pid], R.oy[pid], R.oz[pid]}, F3{R.dx[pid], R.dy[pid], R.dz[pid]});
-                    active = true;
-                }
-            }
-            next = min(next + n_idle, end);
+        const uint32_t i = feed.take(!active, work);
+        if (i != 0xffffffffu) {
+            pid = queue ? queue[i] : i;
+            trav_init(t, F3{R.ox[pid], R.oy[pid], R.oz[pid]}, F3{R.dx[pid], R.dy[pid], R.dz[pid]});
+            active = true;
         }
         if (__ballot(active) == 0ull) break;
         if (active && trav_step<kTraceBS, COUNT>(S, t, lds, st, vc)) {
@@ -140,8 +159,11 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
 }
 
 // ------------------------------------------------------------------ any hit
-// Occlusion of segments (0, tmax) skipping triangle excl; for shadow rays of
-// camera paths, an unoccluded segment adds its stored contribution to L.
+// Shadow / occlusion rays.  These end at their first hit, so a wave's rays
+// take similar times and plain chunks of 64 suffice: the first chunk by the
+// wave's index in the grid, the rest from the launch's atomic counter.  For
+// shadow rays of camera paths, an unoccluded segment adds its stored
+// contribution to L.
 __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, const uint32_t* __restrict__ queue,
                                                      const uint32_t* __restrict__ count, uint32_t n_static,
                                                      uint32_t* __restrict__ work, uint8_t* __restrict__ occ_out,
@@ -150,9 +172,8 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
     Spill st;
     const uint32_t n = count ? *count : n_static;
     unsigned long long c_rays = 0;
-    uint32_t base = wave_first_chunk();
-    for (;;) {
-        if (base >= n) break;
+    uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
+    while (base < n) {
         const uint32_t i = base + lane_id();
         if (i < n) {
             const uint32_t pid = queue ? queue[i] : i;
@@ -164,7 +185,9 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
             if (L && !occluded) L[pid] = L[pid] + R.contrib[pid];
             ++c_rays;
         }
-        base = wave_next_chunk(work);
+        uint32_t next = 0;
+        if (lane_id() == 0) next = atomicAdd(work, 64u);
+        base = __shfl(next, 0) + gridDim.x * blockDim.x;
     }
     c_rays = wave_sum_u64(c_rays);
     if (lane_id() == 0 && c_rays) atomicAdd(&C->rays_shadow, c_rays);
@@ -180,14 +203,14 @@ __global__ void k_zero_u64(unsigned long long* p, size_t n) {
 __global__ void k_zero_f32(float* p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0f;
 }
-// counts[0] = counts[1]; counts[1..4] = 0
+// next queue becomes the current one; the others are emptied
 __global__ void k_rotate_counts(uint32_t* counts) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        counts[0] = counts[1];
-        counts[1] = 0u;
-        counts[2] = 0u;
-        counts[3] = 0u;
-        counts[4] = 0u;
+        counts[QC_CUR] = counts[QC_NEXT];
+        counts[QC_NEXT] = 0u;
+        counts[QC_DIFF] = 0u;
+        counts[QC_DIEL] = 0u;
+        counts[QC_SHADOW] = 0u;
     }
 }
 
@@ -257,14 +280,14 @@ __global__ void k_raygen(CamInfo ci, WaveDev wl, PathState P, uint32_t n, uint32
         P.flags[pid] = c.flags;
         queue[pid] = pid;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) counts[0] = n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) counts[QC_CUR] = n;
 }
 
 // Sort hits by material: emitters and misses end here, dielectric and
 // diffuse hits go to their own queues.
 __global__ void k_classify(DevScene S, PathState P, const uint32_t* __restrict__ queue, uint32_t* counts,
                            uint32_t* q_diffuse, uint32_t* q_dielectric, uint32_t cap) {
-    const uint32_t n = counts[0];
+    const uint32_t n = counts[QC_CUR];
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
         const uint32_t i = base + threadIdx.x;
@@ -286,14 +309,14 @@ __global__ void k_classify(DevScene S, PathState P, const uint32_t* __restrict__
                 }
             }
         }
-        wave_push(to_diel, pid, q_dielectric, counts + 3);
-        wave_push(to_diff, pid, q_diffuse, counts + 2);
+        block_push(to_diel, pid, q_dielectric, counts + QC_DIEL);
+        block_push(to_diff, pid, q_diffuse, counts + QC_DIFF);
     }
 }
 
 __global__ void k_shade_dielectric(DevScene S, CamInfo ci, PathState P, uint32_t depth, const uint32_t* __restrict__ q,
                                    uint32_t* counts, uint32_t* q_next) {
-    const uint32_t n = counts[3];
+    const uint32_t n = counts[QC_DIEL];
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
         const uint32_t i = base + threadIdx.x;
@@ -307,14 +330,14 @@ __global__ void k_shade_dielectric(DevScene S, CamInfo ci, PathState P, uint32_t
             cont = camera_dielectric(S, ci.seed, pix, sample, slot, depth, ci.max_depth, load_hit(P, pid), c);
             if (cont) store_ray(P, pid, c);
         }
-        wave_push(cont, pid, q_next, counts + 1);
+        block_push(cont, pid, q_next, counts + QC_NEXT);
     }
 }
 
 __global__ void k_shade_diffuse(DevScene S, CamInfo ci, WaveDev wl, PathState P, uint32_t depth,
                                 const float* __restrict__ cmap, const uint32_t* __restrict__ q, uint32_t* counts,
                                 uint32_t* q_next, uint32_t* q_shadow) {
-    const uint32_t n = counts[2];
+    const uint32_t n = counts[QC_DIFF];
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
         const uint32_t i = base + threadIdx.x;
@@ -342,8 +365,8 @@ __global__ void k_shade_diffuse(DevScene S, CamInfo ci, WaveDev wl, PathState P,
                 P.T[pid] = c.T;
             }
         }
-        wave_push(sr.shoot, pid, q_shadow, counts + 4);
-        wave_push(cont, pid, q_next, counts + 1);
+        block_push(sr.shoot, pid, q_shadow, counts + QC_SHADOW);
+        block_push(cont, pid, q_next, counts + QC_NEXT);
     }
 }
 
@@ -422,7 +445,7 @@ __global__ void k_photon_emit(DevScene S, WaveDev wl, PhInfo pi, uint32_t n, Pho
                 Ph.spec[i] = ph.spec;
             }
         }
-        wave_push(alive, i, queue, counts + 0);
+        block_push(alive, i, queue, counts + QC_CUR);
     }
 }
 
@@ -450,7 +473,7 @@ __device__ __forceinline__ void deposit(bool want, uint32_t cell, unsigned long 
 __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth, PhotonState Ph,
                                const uint32_t* __restrict__ queue, uint32_t* counts, uint32_t* q_next,
                                unsigned long long* acc, uint32_t* cnt_map, DevCounters* C) {
-    const uint32_t n = counts[0];
+    const uint32_t n = counts[QC_CUR];
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
         const uint32_t i = base + threadIdx.x;
@@ -483,7 +506,7 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
             }
         }
         deposit(dep, cell_ch, q, acc, cnt_map);
-        wave_push(cont, id, q_next, counts + 1);
+        block_push(cont, id, q_next, counts + QC_NEXT);
     }
 }
 
@@ -543,13 +566,13 @@ Queues carve_queues(void* p, size_t n) {
     Carver c{static_cast<char*>(p)};
     Queues q;
     q.cur = c.take<uint32_t>(n); q.next = c.take<uint32_t>(n); q.diffuse = c.take<uint32_t>(n);
-    q.dielectric = c.take<uint32_t>(n); q.shadow = c.take<uint32_t>(n); q.counts = c.take<uint32_t>(8);
+    q.dielectric = c.take<uint32_t>(n); q.shadow = c.take<uint32_t>(n); q.counts = c.take<uint32_t>(QC_WORDS);
     return q;
 }
 
 sc_status ensure_queues(Ctx* c, size_t n) {
     if (c->queue_n >= n && c->queues.p) return SC_OK;
-    SC_TRY(c->queues.alloc(5 * (n * 4 + 256) + 512));
+    SC_TRY(c->queues.alloc(5 * (n * 4 + 256) + 4 * QC_WORDS + 512));
     c->queue_n = n;
     return SC_OK;
 }
@@ -770,19 +793,19 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
             const uint32_t ns = (uint32_t)std::min<size_t>(chunk, spp - s0);
             const uint32_t n = (uint32_t)(ns * per_sample);
             CamInfo ci{cam, seed, s0, (uint32_t)hw, K, max_depth};
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, q.counts, 8u);
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, q.counts, QC_WORDS);
             hipLaunchKernelGGL(k_raygen, dim3(grid_for(n, bs)), dim3(bs), 0, st, ci, wd, P, n, q.cur, q.counts);
             uint32_t* cur = q.cur;
             uint32_t* nxt = q.next;
             for (uint32_t depth = 1; depth <= max_depth; ++depth) {
-                launch_closest(c, S, R, H, cur, q.counts + 0, 0u, n);
+                launch_closest(c, S, R, H, cur, q.counts + QC_CUR, 0u, n);
                 hipLaunchKernelGGL(k_classify, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, P, cur, q.counts, q.diffuse,
                                    q.dielectric, n);
                 hipLaunchKernelGGL(k_shade_dielectric, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, P, depth,
                                    q.dielectric, q.counts, nxt);
                 hipLaunchKernelGGL(k_shade_diffuse, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, wd, P, depth, cmap,
                                    q.diffuse, q.counts, nxt, q.shadow);
-                launch_anyhit(c, S, SR, q.shadow, q.counts + 4, 0u, n, nullptr, P.L);
+                launch_anyhit(c, S, SR, q.shadow, q.counts + QC_SHADOW, 0u, n, nullptr, P.L);
                 hipLaunchKernelGGL(k_rotate_counts, dim3(1), dim3(64), 0, st, q.counts);
                 std::swap(cur, nxt);
             }
@@ -836,13 +859,13 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
         for (uint64_t p0 = 0; p0 < N; p0 += chunk) {
             const uint32_t n = (uint32_t)std::min<uint64_t>(chunk, N - p0);
             PhInfo pi{seed, N, p0, max_depth, scale, stats ? 1 : 0};
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, q.counts, 8u);
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, q.counts, QC_WORDS);
             hipLaunchKernelGGL(k_photon_emit, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, wd, pi, n, Ph, q.cur, q.counts,
                                c->counters.as<DevCounters>());
             uint32_t* cur = q.cur;
             uint32_t* nxt = q.next;
             for (uint32_t depth = 1; depth <= max_depth; ++depth) {
-                launch_closest(c, S, R, H, cur, q.counts + 0, 0u, n);
+                launch_closest(c, S, R, H, cur, q.counts + QC_CUR, 0u, n);
                 hipLaunchKernelGGL(k_photon_event, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, wd, pi, depth, Ph, cur,
                                    q.counts, nxt, c->acc64.as<unsigned long long>(), count_map,
                                    c->counters.as<DevCounters>());
