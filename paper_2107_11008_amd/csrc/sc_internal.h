@@ -88,8 +88,9 @@ struct Ctx {
     uint32_t work_slot = 0;
     DevBuf path;       // PathState arrays
     size_t path_n = 0;
-    DevBuf queues;     // five queues + counts
+    DevBuf queues;     // five queues
     size_t queue_n = 0;
+    DevBuf qcounts;    // queue counter frames, one per bounce depth
     DevBuf photon;     // PhotonState arrays
     size_t photon_n = 0;
     DevBuf acc64;      // fixed-point caustic accumulator

@@ -94,11 +94,15 @@ struct Queues {
     uint32_t* diffuse;
     uint32_t* dielectric;
     uint32_t* shadow;
-    uint32_t* counts;  // QC_CUR, QC_NEXT, QC_DIFF, QC_DIEL, QC_SHADOW: one 256-byte line each
+    uint32_t* counts;  // one frame of counters per bounce depth (see QC_*)
 };
-// queue counters, each on its own cache line so that appends to different
-// queues do not contend for one line
-constexpr uint32_t QC_CUR = 0, QC_NEXT = 64, QC_DIFF = 128, QC_DIEL = 192, QC_SHADOW = 256, QC_WORDS = 320;
+// Queue counters: one frame of QC_FRAME words per bounce depth, each counter
+// on its own cache line so that appends to different queues do not contend
+// for one line.  Frame d holds the length of the depth-d queue (QC_CUR) and
+// of the diffuse, dielectric and shadow queues made at depth d; appends to
+// the next depth's queue go to frame d + 1 (QC_NEXT from frame d), so the
+// frames never need to be rotated between launches.
+constexpr uint32_t QC_CUR = 0, QC_DIFF = 64, QC_DIEL = 128, QC_SHADOW = 192, QC_FRAME = 256, QC_NEXT = QC_FRAME;
 
 // counters incremented by kernels
 struct DevCounters {

@@ -79,9 +79,10 @@ constexpr uint32_t kRefill = 16;   // idle lanes that trigger a refill
 // are wave-uniform.
 struct RayFeed {
     uint32_t n, waves, batch, next, end;
+    uint32_t* counter;
     bool drained;
 
-    __device__ __forceinline__ void init(uint32_t n_rays) {
+    __device__ __forceinline__ void init(uint32_t n_rays, uint32_t* work) {
         n = n_rays;
         waves = gridDim.x * (blockDim.x >> 6);
         const uint32_t per_wave = n / (4u * waves);
@@ -89,17 +90,18 @@ struct RayFeed {
         next = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * batch;
         end = next < n ? min(next + batch, n) : next;
         drained = next >= n;
+        counter = work;
     }
 
     // Called by every lane of the wave; returns the list index of the new
     // ray for an idle lane that receives one, else 0xffffffff.
-    __device__ __forceinline__ uint32_t take(bool idle_lane, uint32_t* work) {
+    __device__ __forceinline__ uint32_t take(bool idle_lane) {
         const unsigned long long idle = __ballot(idle_lane);
         const uint32_t n_idle = (uint32_t)__popcll(idle);
         if (n_idle < kRefill) return 0xffffffffu;
         if (next >= end && !drained) {
             uint32_t base = 0;
-            if (lane_id() == 0) base = atomicAdd(work, batch);
+            if (lane_id() == 0) base = atomicAdd(counter, batch);
             base = __shfl(base, 0) + waves * batch;
             next = base;
             end = base < n ? min(base + batch, n) : base;
@@ -118,15 +120,15 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
                                                       uint32_t* __restrict__ work, DevCounters* __restrict__ C) {
     __shared__ uint2 lds[kLdsStack][kTraceBS];
     Spill st;
+    const uint32_t n = count ? *count : n_static;
     RayFeed feed;
-    feed.init(count ? *count : n_static);
+    feed.init(n, work);
     VisitCount vc;
-    unsigned long long c_rays = 0;
     TravState t;
     uint32_t pid = 0;
     bool active = false;
     for (;;) {
-        const uint32_t i = feed.take(!active, work);
+        const uint32_t i = feed.take(!active);
         if (i != 0xffffffffu) {
             pid = queue ? queue[i] : i;
             trav_init(t, F3{R.ox[pid], R.oy[pid], R.oz[pid]}, F3{R.dx[pid], R.dy[pid], R.dz[pid]});
@@ -139,19 +141,14 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
             H.prim[pid] = h.prim;
             if (H.u) H.u[pid] = h.u;
             if (H.v) H.v[pid] = h.v;
-            ++c_rays;
             active = false;
         }
     }
-    c_rays = wave_sum_u64(c_rays);
-    unsigned long long c_nodes = 0, c_tris = 0;
+    // every ray of the list is traced exactly once
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(&C->rays_closest, (unsigned long long)n);
     if (COUNT) {
-        c_nodes = wave_sum_u64(vc.nodes);
-        c_tris = wave_sum_u64(vc.tris);
-    }
-    if (lane_id() == 0 && c_rays) {
-        atomicAdd(&C->rays_closest, c_rays);
-        if (COUNT) {
+        const unsigned long long c_nodes = wave_sum_u64(vc.nodes), c_tris = wave_sum_u64(vc.tris);
+        if (lane_id() == 0 && c_nodes) {
             atomicAdd(&C->node_visits, c_nodes);
             atomicAdd(&C->tri_tests, c_tris);
         }
@@ -171,7 +168,6 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
     __shared__ uint2 lds[kLdsStack][kTraceBS];
     Spill st;
     const uint32_t n = count ? *count : n_static;
-    unsigned long long c_rays = 0;
     uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
     while (base < n) {
         const uint32_t i = base + lane_id();
@@ -183,14 +179,12 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
             const bool occluded = trace_any<kTraceBS>(S, o, d, R.tmax[pid], excl, lds, st);
             if (occ_out) occ_out[pid] = occluded ? 1 : 0;
             if (L && !occluded) L[pid] = L[pid] + R.contrib[pid];
-            ++c_rays;
         }
         uint32_t next = 0;
         if (lane_id() == 0) next = atomicAdd(work, 64u);
         base = __shfl(next, 0) + gridDim.x * blockDim.x;
     }
-    c_rays = wave_sum_u64(c_rays);
-    if (lane_id() == 0 && c_rays) atomicAdd(&C->rays_shadow, c_rays);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(&C->rays_shadow, (unsigned long long)n);
 }
 
 // ------------------------------------------------------------------ helpers
@@ -202,16 +196,6 @@ __global__ void k_zero_u64(unsigned long long* p, size_t n) {
 }
 __global__ void k_zero_f32(float* p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0f;
-}
-// next queue becomes the current one; the others are emptied
-__global__ void k_rotate_counts(uint32_t* counts) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        counts[QC_CUR] = counts[QC_NEXT];
-        counts[QC_NEXT] = 0u;
-        counts[QC_DIFF] = 0u;
-        counts[QC_DIEL] = 0u;
-        counts[QC_SHADOW] = 0u;
-    }
 }
 
 // AoS [n][3] rays to the SoA buffers
@@ -531,7 +515,8 @@ namespace scl {
 
 namespace {
 
-constexpr uint32_t kWorkSlots = 4096;
+constexpr uint32_t kWorkSlots = 256;     // traversal launches between clears
+constexpr uint32_t kWorkStride = 64;     // words per launch: one counter on its own line
 
 // carve n-element arrays out of one allocation, 256-byte aligned
 size_t path_bytes(size_t n) { return 25 * (n * 4 + 256); }
@@ -566,13 +551,13 @@ Queues carve_queues(void* p, size_t n) {
     Carver c{static_cast<char*>(p)};
     Queues q;
     q.cur = c.take<uint32_t>(n); q.next = c.take<uint32_t>(n); q.diffuse = c.take<uint32_t>(n);
-    q.dielectric = c.take<uint32_t>(n); q.shadow = c.take<uint32_t>(n); q.counts = c.take<uint32_t>(QC_WORDS);
+    q.dielectric = c.take<uint32_t>(n); q.shadow = c.take<uint32_t>(n); q.counts = nullptr;
     return q;
 }
 
 sc_status ensure_queues(Ctx* c, size_t n) {
     if (c->queue_n >= n && c->queues.p) return SC_OK;
-    SC_TRY(c->queues.alloc(5 * (n * 4 + 256) + 4 * QC_WORDS + 512));
+    SC_TRY(c->queues.alloc(5 * (n * 4 + 256) + 512));
     c->queue_n = n;
     return SC_OK;
 }
@@ -586,14 +571,16 @@ sc_status ensure_path(Ctx* c, size_t n) {
 
 uint32_t* next_work_slot(Ctx* c) {
     if (c->work_slot >= kWorkSlots) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(16), dim3(256), 0, c->stream, c->work.as<uint32_t>(), kWorkSlots);
+        hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, c->stream, c->work.as<uint32_t>(),
+                           kWorkSlots * kWorkStride);
         c->work_slot = 0;
     }
-    return c->work.as<uint32_t>() + (c->work_slot++);
+    return c->work.as<uint32_t>() + (size_t)(c->work_slot++) * kWorkStride;
 }
 
 void reset_work(Ctx* c) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(16), dim3(256), 0, c->stream, c->work.as<uint32_t>(), kWorkSlots);
+    hipLaunchKernelGGL(k_zero_u32, dim3(64), dim3(256), 0, c->stream, c->work.as<uint32_t>(),
+                       kWorkSlots * kWorkStride);
     c->work_slot = 0;
 }
 
@@ -709,9 +696,9 @@ sc_status make_wave(Ctx* c, const sc_wavelengths& wl, WaveDev& w) {
 
 sc_status ctx_init(Ctx* c) {
     SC_TRY(c->counters.alloc(sizeof(DevCounters)));
-    SC_TRY(c->work.alloc(sizeof(uint32_t) * kWorkSlots));
+    SC_TRY(c->work.alloc(sizeof(uint32_t) * kWorkSlots * kWorkStride));
     SC_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(DevCounters), c->stream));
-    SC_HIP(hipMemsetAsync(c->work.p, 0, sizeof(uint32_t) * kWorkSlots, c->stream));
+    SC_HIP(hipMemsetAsync(c->work.p, 0, sizeof(uint32_t) * kWorkSlots * kWorkStride, c->stream));
     SC_HIP(hipStreamSynchronize(c->stream));
     return SC_OK;
 }
@@ -774,6 +761,9 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
     SC_TRY(ensure_queues(c, n_max));
     PathState P = carve_path(c->path.p, n_max);
     Queues q = carve_queues(c->queues.p, n_max);
+    const uint32_t frame_words = (max_depth + 2) * QC_FRAME;
+    SC_TRY(c->qcounts.ensure(4 * (size_t)frame_words));
+    q.counts = c->qcounts.as<uint32_t>();
     reset_work(c);
 
     const bool want_aov = out.obj || out.trans || out.tri || out.depth || out.depthn || out.normal || out.normal_cam ||
@@ -793,20 +783,20 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
             const uint32_t ns = (uint32_t)std::min<size_t>(chunk, spp - s0);
             const uint32_t n = (uint32_t)(ns * per_sample);
             CamInfo ci{cam, seed, s0, (uint32_t)hw, K, max_depth};
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, q.counts, QC_WORDS);
+            hipLaunchKernelGGL(k_zero_u32, dim3(32), dim3(256), 0, st, q.counts, frame_words);
             hipLaunchKernelGGL(k_raygen, dim3(grid_for(n, bs)), dim3(bs), 0, st, ci, wd, P, n, q.cur, q.counts);
             uint32_t* cur = q.cur;
             uint32_t* nxt = q.next;
             for (uint32_t depth = 1; depth <= max_depth; ++depth) {
-                launch_closest(c, S, R, H, cur, q.counts + QC_CUR, 0u, n);
-                hipLaunchKernelGGL(k_classify, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, P, cur, q.counts, q.diffuse,
+                uint32_t* fc = q.counts + (size_t)(depth - 1) * QC_FRAME;
+                launch_closest(c, S, R, H, cur, fc + QC_CUR, 0u, n);
+                hipLaunchKernelGGL(k_classify, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, P, cur, fc, q.diffuse,
                                    q.dielectric, n);
                 hipLaunchKernelGGL(k_shade_dielectric, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, P, depth,
-                                   q.dielectric, q.counts, nxt);
+                                   q.dielectric, fc, nxt);
                 hipLaunchKernelGGL(k_shade_diffuse, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, wd, P, depth, cmap,
-                                   q.diffuse, q.counts, nxt, q.shadow);
-                launch_anyhit(c, S, SR, q.shadow, q.counts + QC_SHADOW, 0u, n, nullptr, P.L);
-                hipLaunchKernelGGL(k_rotate_counts, dim3(1), dim3(64), 0, st, q.counts);
+                                   q.diffuse, fc, nxt, q.shadow);
+                launch_anyhit(c, S, SR, q.shadow, fc + QC_SHADOW, 0u, n, nullptr, P.L);
                 std::swap(cur, nxt);
             }
             hipLaunchKernelGGL(k_film_accumulate, dim3(grid_for(hw, bs)), dim3(bs), 0, st, ci, wd, P.L, P.lambda, ns,
@@ -853,23 +843,26 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
         SC_TRY(ensure_queues(c, chunk));
         PhotonState Ph = carve_photon(c->photon.p, chunk);
         Queues q = carve_queues(c->queues.p, chunk);
+        const uint32_t frame_words = (max_depth + 2) * QC_FRAME;
+        SC_TRY(c->qcounts.ensure(4 * (size_t)frame_words));
+        q.counts = c->qcounts.as<uint32_t>();
         reset_work(c);
         const RaySoA R{Ph.ox, Ph.oy, Ph.oz, Ph.dx, Ph.dy, Ph.dz};
         const HitSoA H{Ph.t, Ph.prim, Ph.u, Ph.v};
         for (uint64_t p0 = 0; p0 < N; p0 += chunk) {
             const uint32_t n = (uint32_t)std::min<uint64_t>(chunk, N - p0);
             PhInfo pi{seed, N, p0, max_depth, scale, stats ? 1 : 0};
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, q.counts, QC_WORDS);
+            hipLaunchKernelGGL(k_zero_u32, dim3(32), dim3(256), 0, st, q.counts, frame_words);
             hipLaunchKernelGGL(k_photon_emit, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, wd, pi, n, Ph, q.cur, q.counts,
                                c->counters.as<DevCounters>());
             uint32_t* cur = q.cur;
             uint32_t* nxt = q.next;
             for (uint32_t depth = 1; depth <= max_depth; ++depth) {
-                launch_closest(c, S, R, H, cur, q.counts + QC_CUR, 0u, n);
+                uint32_t* fc = q.counts + (size_t)(depth - 1) * QC_FRAME;
+                launch_closest(c, S, R, H, cur, fc + QC_CUR, 0u, n);
                 hipLaunchKernelGGL(k_photon_event, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, wd, pi, depth, Ph, cur,
-                                   q.counts, nxt, c->acc64.as<unsigned long long>(), count_map,
+                                   fc, nxt, c->acc64.as<unsigned long long>(), count_map,
                                    c->counters.as<DevCounters>());
-                hipLaunchKernelGGL(k_rotate_counts, dim3(1), dim3(64), 0, st, q.counts);
                 std::swap(cur, nxt);
             }
         }
