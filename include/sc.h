@@ -208,6 +208,16 @@ sc_status sc_reset_counters(sc_ctx* ctx);
  * pointers, nt == 0, an object id outside [1, n_mat) or an unknown
  * material; EUNSUPPORTED if the tree is too deep for the traversal stack. */
 sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* scene, const sc_bvh_opts* opts, sc_bvh** out);
+/* Rebuild an existing handle for `scene` (the same scene with moved
+ * vertices, or another one) with the options it was built with, as
+ * sc_build_bvh would, reusing the handle's device memory where it is large
+ * enough: the per-frame rebuild of dynamic geometry.  Work already enqueued
+ * on the context's stream that reads the old tree finishes first (stream
+ * order).  Synchronises.  EINVAL on null pointers, a handle of another
+ * context or an invalid scene (as sc_build_bvh); after any failure the
+ * handle holds no tree and tracing calls on it fail with EINVAL until a
+ * rebuild succeeds. */
+sc_status sc_bvh_rebuild(sc_ctx* ctx, sc_bvh* bvh, const sc_scene* scene);
 sc_status sc_bvh_get_info(const sc_bvh* bvh, sc_bvh_info* out);
 sc_status sc_bvh_free(sc_bvh* bvh);
 /* Copy the built structure to host memory for inspection (synchronises):

@@ -116,7 +116,8 @@ PH_OUTCOMES = ("deposited", "outside", "direct", "elsewhere", "escaped", "absorb
                "emit_dead")
 
 EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set_stream", "sc_set_option",
-           "sc_sync", "sc_get_counters", "sc_reset_counters", "sc_build_bvh", "sc_bvh_get_info", "sc_bvh_free", "sc_bvh_export",
+           "sc_sync", "sc_get_counters", "sc_reset_counters", "sc_build_bvh", "sc_bvh_rebuild", "sc_bvh_get_info",
+           "sc_bvh_free", "sc_bvh_export",
            "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render",
            "sc_unet_create", "sc_unet_free", "sc_unet_num_params", "sc_unet_set_params", "sc_unet_get_params",
            "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise",
@@ -143,6 +144,7 @@ def load(path: str = LIB_PATH):
     L.sc_get_counters.argtypes = [vp, C.POINTER(Counters)]
     L.sc_reset_counters.argtypes = [vp]
     L.sc_build_bvh.argtypes = [vp, C.POINTER(Scene), C.POINTER(BvhOpts), C.POINTER(vp)]
+    L.sc_bvh_rebuild.argtypes = [vp, vp, C.POINTER(Scene)]
     L.sc_bvh_get_info.argtypes = [vp, C.POINTER(BvhInfo)]
     L.sc_bvh_free.argtypes = [vp]
     L.sc_bvh_export.argtypes = [vp, vp, vp]
@@ -251,7 +253,18 @@ class Context:
         _check(load().sc_reset_counters(self.h), "sc_reset_counters")
 
     # ------------------------------------------------------------ entry points
-    def build_bvh(self, scene, width: int = 8, leaf_max: int = 4) -> "Bvh":
+    def upload_scene(self, scene) -> "SceneDev":
+        """Copy a host scene (scenegen.Scene) to the device once; the result
+        can be passed to build_bvh any number of times."""
+        return SceneDev(self, scene)
+
+    def build_bvh(self, scene, width: int = 8, leaf_max: int = 4, out: Optional["Bvh"] = None) -> "Bvh":
+        """Wide BVH of a scene (host scenegen.Scene, uploaded on the fly, or
+        a SceneDev).  With out=, that handle is rebuilt in place (same
+        width and leaf size) and returned."""
+        if out is not None:
+            out.rebuild(scene)
+            return out
         return Bvh(self, scene, width, leaf_max)
 
     def trace_rays(self, bvh: "Bvh", O: torch.Tensor, D: torch.Tensor):
@@ -351,11 +364,12 @@ def _gt_methods():
     Context.occlusion_boundary = occlusion_boundary
 
 
-class Bvh:
-    """Scene uploaded to the device plus its wide BVH and tables."""
+class SceneDev:
+    """A scene's arrays on the device and the sc_scene describing them."""
 
-    def __init__(self, ctx: Context, scene, width: int = 8, leaf_max: int = 4):
-        self.ctx = ctx
+    def __init__(self, ctx: Context, scene):
+        if isinstance(scene, SceneDev):
+            scene = scene.scene
         self.scene = scene
         dev = ctx.device
         self.V = _dev(scene.V, dev)
@@ -382,12 +396,34 @@ class Bvh:
         if r is not None:
             s.recv_obj, s.recv_wc, s.recv_hc = r.obj, r.wc, r.hc
             s.recv_x0, s.recv_y0, s.recv_ext_u, s.recv_ext_v = r.x0, r.y0, r.ext_u, r.ext_v
-        self._s = s
+        self.s = s
+
+    # the scene's attributes (nt, nv, V, ...) as on the host scene
+    def __getattr__(self, name):
+        return getattr(self.__dict__["scene"], name)
+
+
+class Bvh:
+    """A scene on the device plus its wide BVH and tables.  Holds the
+    SceneDev it was built from (the tree references its arrays)."""
+
+    def __init__(self, ctx: Context, scene, width: int = 8, leaf_max: int = 4):
+        self.ctx = ctx
+        self.dev = scene if isinstance(scene, SceneDev) else SceneDev(ctx, scene)
+        self.scene = self.dev.scene
         opts = BvhOpts(width, leaf_max)
         h = C.c_void_p()
-        _check(load().sc_build_bvh(ctx.h, C.byref(s), C.byref(opts), C.byref(h)), "sc_build_bvh")
+        _check(load().sc_build_bvh(ctx.h, C.byref(self.dev.s), C.byref(opts), C.byref(h)), "sc_build_bvh")
         self.h = h
         _live["bvh"].add(self)
+
+    def rebuild(self, scene):
+        """Rebuild this handle's tree for scene (host scene or SceneDev),
+        reusing its device memory."""
+        dev = scene if isinstance(scene, SceneDev) else SceneDev(self.ctx, scene)
+        _check(load().sc_bvh_rebuild(self.ctx.h, self.h, C.byref(dev.s)), "sc_bvh_rebuild")
+        self.dev = dev
+        self.scene = dev.scene
 
     def info(self) -> dict:
         i = BvhInfo()

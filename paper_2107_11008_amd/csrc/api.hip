@@ -55,7 +55,7 @@ sc_status check_wavelengths(const sc_wavelengths* wl) {
 }
 
 sc_status upload(scl::DevBuf& buf, const void* host, size_t bytes, hipStream_t st) {
-    SC_TRY(buf.alloc(bytes));
+    SC_TRY(buf.ensure(bytes));
     if (bytes) SC_HIP(hipMemcpyAsync(buf.p, host, bytes, hipMemcpyHostToDevice, st));
     return SC_OK;
 }
@@ -133,9 +133,15 @@ sc_status sc_reset_counters(sc_ctx* ctx) {
     return scl::ctx_reset_counters(&ctx->c);
 }
 
-sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* sc, const sc_bvh_opts* opts, sc_bvh** out) {
-    if (!ctx || !sc || !out) return set_error(SC_EINVAL, "ctx, scene or out is NULL");
-    *out = nullptr;
+namespace {
+
+// a handle whose last rebuild failed holds no usable tree
+sc_status check_built(const sc_bvh* bvh) {
+    if (bvh->b.n_nodes == 0) return set_error(SC_EINVAL, "bvh holds no tree (its last rebuild failed)");
+    return SC_OK;
+}
+
+sc_status check_scene(const sc_scene* sc) {
     if (!sc->V || !sc->I || !sc->tri_obj || !sc->mat) return set_error(SC_EINVAL, "scene arrays V, I, tri_obj, mat are required");
     if (sc->nt == 0 || sc->nv == 0) return set_error(SC_EINVAL, "scene has no triangles");
     if (sc->nt > (1u << 28) - 1) return set_error(SC_EUNSUPPORTED, "more than 2^28 - 1 triangles");
@@ -156,18 +162,16 @@ sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* sc, const sc_bvh_opts* opts,
     }
     if (sc->tex && (sc->tex_w == 0 || sc->tex_h == 0 || !(sc->tex_ext_u > 0.0f) || !(sc->tex_ext_v > 0.0f)))
         return set_error(SC_EINVAL, "texture needs a size and a positive extent");
-    uint32_t width = opts && opts->width ? opts->width : 8u;
-    uint32_t leaf_max = opts && opts->leaf_max ? opts->leaf_max : 4u;
-    if (!(width == 4 || width == 8)) return set_error(SC_EINVAL, "width must be 4 or 8");
-    if (leaf_max < 1 || leaf_max > 8) return set_error(SC_EINVAL, "leaf_max must be 1..8");
+    return SC_OK;
+}
 
-    scl::Ctx* c = &ctx->c;
+// (Re)builds b for scene sc: BVH, light and material tables, device view.
+// Device buffers of b are reused when large enough.
+sc_status build_into(scl::Ctx* c, scl::Bvh* b, const sc_scene* sc, uint32_t width, uint32_t leaf_max) {
     hipStream_t st = c->stream;
-    sc_bvh* h = new (std::nothrow) sc_bvh();
-    if (!h) return set_error(SC_ENOMEM, "host allocation failed");
-    scl::Bvh* b = &h->b;
     b->ctx = c;
     b->scene_in = *sc;
+    b->scene = DevScene{};
     std::vector<float> tg(4 * (size_t)sc->n_tg);
     for (uint32_t i = 0; i < 4 * sc->n_tg; ++i) tg[i] = sc->targets_sphere[i];
     sc_status s = SC_OK;
@@ -223,10 +227,7 @@ sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* sc, const sc_bvh_opts* opts,
             if (hipStreamSynchronize(st) != hipSuccess) s = set_error(SC_EDEVICE, "upload failed");
         }
     }
-    if (s != SC_OK) {
-        delete h;
-        return s;
-    }
+    if (s != SC_OK) return s;
     DevScene& D = b->scene;
     D.V = sc->V; D.I = sc->I; D.VN = sc->VN; D.tri_obj = sc->tri_obj; D.nt = sc->nt;
     D.mat = b->mat.as<sc_material>(); D.n_mat = sc->n_mat;
@@ -246,8 +247,37 @@ sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* sc, const sc_bvh_opts* opts,
     D.n_emit = (uint32_t)emit_prim.size(); D.a_tot = (float)a_tot;
     D.n_entries = sc->n_pl + (emit_prim.empty() ? 0u : 1u);
     D.nodes = b->nodes.as<BNode>(); D.tris = b->tris.as<float4>(); D.n_nodes = b->n_nodes;
+    return SC_OK;
+}
+
+}  // namespace
+
+sc_status sc_build_bvh(sc_ctx* ctx, const sc_scene* sc, const sc_bvh_opts* opts, sc_bvh** out) {
+    if (!ctx || !sc || !out) return set_error(SC_EINVAL, "ctx, scene or out is NULL");
+    *out = nullptr;
+    SC_TRY(check_scene(sc));
+    uint32_t width = opts && opts->width ? opts->width : 8u;
+    uint32_t leaf_max = opts && opts->leaf_max ? opts->leaf_max : 4u;
+    if (!(width == 4 || width == 8)) return set_error(SC_EINVAL, "width must be 4 or 8");
+    if (leaf_max < 1 || leaf_max > 8) return set_error(SC_EINVAL, "leaf_max must be 1..8");
+    sc_bvh* h = new (std::nothrow) sc_bvh();
+    if (!h) return set_error(SC_ENOMEM, "host allocation failed");
+    const sc_status s = build_into(&ctx->c, &h->b, sc, width, leaf_max);
+    if (s != SC_OK) {
+        delete h;
+        return s;
+    }
     *out = h;
     return SC_OK;
+}
+
+sc_status sc_bvh_rebuild(sc_ctx* ctx, sc_bvh* bvh, const sc_scene* sc) {
+    if (!ctx || !bvh || !sc) return set_error(SC_EINVAL, "ctx, bvh or scene is NULL");
+    if (bvh->b.ctx != &ctx->c) return set_error(SC_EINVAL, "bvh was built on another context");
+    SC_TRY(check_scene(sc));
+    const sc_status s = build_into(&ctx->c, &bvh->b, sc, bvh->b.width, bvh->b.leaf_max);
+    if (s != SC_OK) bvh->b.n_nodes = 0;   // unusable until rebuilt
+    return s;
 }
 
 sc_status sc_bvh_get_info(const sc_bvh* bvh, sc_bvh_info* out) {
@@ -282,6 +312,7 @@ sc_status sc_bvh_free(sc_bvh* bvh) {
 sc_status sc_trace_rays(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D, float* t,
                         uint32_t* prim, float* u, float* v) {
     if (!ctx || !bvh) return set_error(SC_EINVAL, "ctx or bvh is NULL");
+    SC_TRY(check_built(bvh));
     if (n == 0) return SC_OK;
     if (!O || !D || !t || !prim) return set_error(SC_EINVAL, "O, D, t and prim are required");
     return scl::trace_rays(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n, O, D, t, prim, u, v);
@@ -290,6 +321,7 @@ sc_status sc_trace_rays(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float*
 sc_status sc_occluded(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D, const float* tmax,
                       const uint32_t* excl, uint8_t* occ) {
     if (!ctx || !bvh) return set_error(SC_EINVAL, "ctx or bvh is NULL");
+    SC_TRY(check_built(bvh));
     if (n == 0) return SC_OK;
     if (!O || !D || !tmax || !occ) return set_error(SC_EINVAL, "O, D, tmax and occluded are required");
     return scl::occluded(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n, O, D, tmax, excl, occ);
@@ -299,6 +331,7 @@ sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, u
                            const sc_wavelengths* wl, uint64_t seed, float* caustic_map, uint32_t* count_map,
                            sc_photon_stats* stats) {
     if (!ctx || !bvh || !caustic_map) return set_error(SC_EINVAL, "ctx, bvh or caustic_map is NULL");
+    SC_TRY(check_built(bvh));
     SC_TRY(check_wavelengths(wl));
     if (max_depth == 0) return set_error(SC_EINVAL, "max_depth must be >= 1");
     if (!bvh->b.scene.recv_obj) return set_error(SC_EINVAL, "the scene has no caustic receiver");
@@ -311,6 +344,7 @@ sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, u
 sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
                     const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, const sc_aov* out) {
     if (!ctx || !bvh || !cam || !out) return set_error(SC_EINVAL, "ctx, bvh, camera or out is NULL");
+    SC_TRY(check_built(bvh));
     SC_TRY(check_wavelengths(wl));
     if (spp == 0) return set_error(SC_EINVAL, "spp must be >= 1");
     if (max_depth == 0) return set_error(SC_EINVAL, "max_depth must be >= 1");
@@ -334,6 +368,7 @@ sc_status sc_batch_create(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, c
         const sc_batch_item& it = items[i];
         const std::string where = "batch item " + std::to_string(i) + ": ";
         if (!it.bvh) return set_error(SC_EINVAL, where + "bvh is NULL");
+        SC_TRY(check_built(it.bvh));
         SC_TRY(check_wavelengths(&it.wl));
         if (it.spp == 0 || it.max_depth == 0) return set_error(SC_EINVAL, where + "spp and max_depth must be >= 1");
         if (it.cam.w == 0 || it.cam.h == 0) return set_error(SC_EINVAL, where + "camera has no pixels");

@@ -443,7 +443,8 @@ static bool debug_sync() {
 
 constexpr uint32_t kMaxLevels = 64;   // wide levels (the radix tree is at most 62 deep)
 constexpr uint32_t kMeta = 8 + kMaxLevels + 1;
-constexpr uint32_t kLevelBatch = 4;  // collapse levels launched between host checks
+constexpr uint32_t kLevelBatch = 12;  // collapse levels launched between host checks
+constexpr uint32_t kEmitEager = 1024;  // emitter records read back with the level counts
 
 sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max, std::vector<uint32_t>& emit_prim,
                          std::vector<float>& emit_v) {
@@ -518,6 +519,13 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max, st
     // so the host checks for the end only every kLevelBatch levels
     uint32_t h[kMeta];
     uint32_t depth = 0;
+    // the first emitter records come back with the counts (the rest, if
+    // any, after them); records past n_emit are unused
+    const uint32_t eager = n < kEmitEager ? n : kEmitEager;
+    emit_prim.resize(eager);
+    emit_v.resize(9 * (size_t)eager);
+    std::vector<uint32_t>& eager_prim = emit_prim;
+    std::vector<float>& eager_v = emit_v;
     for (uint32_t L0 = 0;; L0 += kLevelBatch) {
         if (L0 + kLevelBatch > kMaxLevels) return set_error(SC_EDEVICE, "BVH collapse did not terminate");
         for (uint32_t L = L0; L < L0 + kLevelBatch; ++L) {
@@ -527,6 +535,8 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max, st
                       leaf_max, width, wa, meta + 8 + L, wb, meta + 9 + L, meta + 1, nodes_tmp);
         }
         SC_HIP(hipMemcpyAsync(h, meta, sizeof(h), hipMemcpyDeviceToHost, st));
+        SC_HIP(hipMemcpyAsync(eager_prim.data(), e_prim, 4 * (size_t)eager, hipMemcpyDeviceToHost, st));
+        SC_HIP(hipMemcpyAsync(eager_v.data(), e_v, 36 * (size_t)eager, hipMemcpyDeviceToHost, st));
         SC_HIP(hipStreamSynchronize(st));
         if (h[0] & 1u) return set_error(SC_EINVAL, "tri_obj holds an object id outside [1, n_mat)");
         if (h[0] & 2u) return set_error(SC_EINVAL, "I holds a vertex index >= nv");
@@ -536,18 +546,20 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max, st
     const uint32_t n_nodes = h[1];
     const uint32_t n_emit = h[2];
 
-    SC_TRY(b->nodes.alloc(sizeof(BNode) * (size_t)n_nodes));
+    SC_TRY(b->nodes.ensure(sizeof(BNode) * (size_t)n_nodes));
     SC_HIP(hipMemcpyAsync(b->nodes.p, nodes_tmp, sizeof(BNode) * (size_t)n_nodes, hipMemcpyDeviceToDevice, st));
-    SC_TRY(b->tris.alloc(sizeof(float4) * 3 * (size_t)n));
+    SC_TRY(b->tris.ensure(sizeof(float4) * 3 * (size_t)n));
     SC_LAUNCH(k_gather_tris, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys, n, sc.V, sc.nv, sc.I, b->tris.as<float4>());
     emit_prim.resize(n_emit);
     emit_v.resize(9 * (size_t)n_emit);
-    if (n_emit) {
-        SC_HIP(hipMemcpyAsync(emit_prim.data(), e_prim, 4 * (size_t)n_emit, hipMemcpyDeviceToHost, st));
-        SC_HIP(hipMemcpyAsync(emit_v.data(), e_v, 36 * (size_t)n_emit, hipMemcpyDeviceToHost, st));
+    if (n_emit > eager) {
+        SC_HIP(hipMemcpyAsync(emit_prim.data() + eager, e_prim + eager, 4 * (size_t)(n_emit - eager),
+                              hipMemcpyDeviceToHost, st));
+        SC_HIP(hipMemcpyAsync(emit_v.data() + 9 * (size_t)eager, e_v + 9 * (size_t)eager,
+                              36 * (size_t)(n_emit - eager), hipMemcpyDeviceToHost, st));
+        SC_HIP(hipStreamSynchronize(st));
     }
     SC_HIP(hipGetLastError());
-    SC_HIP(hipStreamSynchronize(st));
     b->n_nodes = n_nodes;
     b->depth = depth;
     b->width = width;

@@ -100,7 +100,8 @@ struct Ctx {
     DevBuf aos;        // SoA copies for sc_trace_rays / sc_occluded
     DevBuf bvh_tmp;    // temporaries of the BVH builder (grow-only, reused)
     size_t aos_n = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // recorded, not yet read
+    std::vector<hipEvent_t> event_pool;                       // read, free for reuse
     double closest_ms = 0.0;
     uint64_t closest_launches = 0;
 };

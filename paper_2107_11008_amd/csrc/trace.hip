@@ -591,14 +591,27 @@ uint32_t trace_grid(size_t n_max) {
     return (uint32_t)(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
+// timing events are reused across launches (creating them costs host time
+// inside the timed region)
+hipEvent_t pooled_event(Ctx* c) {
+    hipEvent_t e = nullptr;
+    if (!c->event_pool.empty()) {
+        e = c->event_pool.back();
+        c->event_pool.pop_back();
+    } else {
+        (void)hipEventCreate(&e);
+    }
+    return e;
+}
+
 void launch_closest(Ctx* c, const DevScene& S, RaySoA R, HitSoA H, const uint32_t* queue, const uint32_t* count,
                     uint32_t n_static, size_t n_max) {
     uint32_t* work = next_work_slot(c);
     DevCounters* C = c->counters.as<DevCounters>();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->profile) {
-        (void)hipEventCreate(&e0);
-        (void)hipEventCreate(&e1);
+        e0 = pooled_event(c);
+        e1 = pooled_event(c);
         (void)hipEventRecord(e0, c->stream);
     }
     if (c->count_visits)
@@ -709,6 +722,8 @@ void ctx_release(Ctx* c) {
         (void)hipEventDestroy(e.second);
     }
     c->events.clear();
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    c->event_pool.clear();
 }
 
 sc_status ctx_counters(Ctx* c, sc_counters* out) {
@@ -720,8 +735,8 @@ sc_status ctx_counters(Ctx* c, sc_counters* out) {
         SC_HIP(hipEventElapsedTime(&ms, e.first, e.second));
         c->closest_ms += ms;
         c->closest_launches += 1;
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
+        c->event_pool.push_back(e.first);
+        c->event_pool.push_back(e.second);
     }
     c->events.clear();
     out->rays_closest = h.rays_closest;

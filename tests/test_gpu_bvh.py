@@ -68,3 +68,77 @@ def test_bvh_structure(which, width, leaf):
     info = bvh.info()
     assert info["max_stack"] == (width - 1) * info["depth"] + 1
     _check_tree(scene, nodes, tris, width, leaf)
+
+
+def _hits(ctx, bvh, O, D):
+    import torch
+    t, prim, u, v = ctx.trace_rays(bvh, torch.from_numpy(O).cuda(), torch.from_numpy(D).cuda())
+    return [x.cpu().numpy().copy() for x in (t, prim, u, v)]
+
+
+def _canonical(nodes):
+    """The tree as a depth-first list from the root in child-slot order
+    (child boxes, leaf ranges, internal or not): independent of the order in
+    which the builder numbered the wide nodes, which it does by atomics."""
+    out = []
+
+    def walk(i):
+        nd = nodes[i]
+        for c in range(8):
+            ch = int(nd["child"][c])
+            box = tuple(float(nd[k][c]) for k in ("lox", "loy", "loz", "hix", "hiy", "hiz"))
+            if ch == 0xFFFFFFFF:
+                out.append(("empty",))
+            elif ch & 0x80000000:
+                out.append(("leaf", box, ch))
+            else:
+                out.append(("node", box))
+                walk(ch)
+
+    walk(0)
+    return out
+
+
+def test_rebuild_in_place_matches_fresh_build():
+    """Rebuilding a handle for another scene (larger, then smaller again)
+    gives the tree a fresh build gives (up to the numbering of the wide
+    nodes) and the same hits, bit for bit."""
+    import paper_2107_11008_amd as sc
+    ctx = sc.Context(0)
+    rng = np.random.default_rng(7)
+    small = sg.config1()["scene"]
+    large = sg.config2(tri_scale=0.05, w=32, h=32)["scene"]
+    O = rng.uniform(-3, 3, size=(4096, 3)).astype(np.float32)
+    D = rng.normal(size=(4096, 3))
+    D = (D / np.linalg.norm(D, axis=1, keepdims=True)).astype(np.float32)
+    h = ctx.build_bvh(small)
+    for scene in (large, small, large):
+        dev = ctx.upload_scene(scene)
+        h = ctx.build_bvh(dev, out=h)
+        fresh = ctx.build_bvh(dev)
+        n1, t1 = h.export()
+        n2, t2 = fresh.export()
+        assert h.info() == fresh.info()
+        assert t1.tobytes() == t2.tobytes()
+        assert _canonical(n1) == _canonical(n2)
+        for a, b in zip(_hits(ctx, h, O, D), _hits(ctx, fresh, O, D)):
+            assert a.tobytes() == b.tobytes()
+        _check_tree(scene, n1, t1, 8, 4)
+
+
+def test_failed_rebuild_leaves_no_tree():
+    import paper_2107_11008_amd as sc
+    ctx = sc.Context(0)
+    c = sg.config1()
+    s = c["scene"]
+    h = ctx.build_bvh(s)
+    bad = sg.Scene(V=s.V, I=s.I, VN=s.VN, tri_obj=np.full_like(s.tri_obj, 9), materials=s.materials,
+                   point_lights=s.point_lights, targets_obj=s.targets_obj, targets_sphere=s.targets_sphere,
+                   receiver=s.receiver)
+    with pytest.raises(sc.ScError):
+        ctx.build_bvh(bad, out=h)
+    with pytest.raises(sc.ScError):
+        ctx.render(h, c["camera"], 1, 2, c["wavelengths"], 1)
+    h = ctx.build_bvh(s, out=h)   # usable again
+    img = ctx.render(h, c["camera"], 1, 2, c["wavelengths"], 1)
+    assert np.isfinite(img["rgb"].cpu().numpy()).all()
