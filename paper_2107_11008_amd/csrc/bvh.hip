@@ -1,7 +1,7 @@
 // bvh.hip -- GPU construction of the wide BVH.
 //
 // 1. per-triangle bounds and centroids, centroid bounds of the scene;
-// 2. 64-bit keys (30-bit Morton code of the centroid, triangle index);
+// 2. 64-bit keys (36-bit Morton code of the centroid, 28-bit triangle index);
 // 3. bitonic sort of the keys (LDS for short strides, global otherwise);
 // 4. binary radix tree over the sorted keys (Karras, "Maximizing
 //    parallelism in the construction of BVHs, octrees, and k-d trees",
@@ -176,14 +176,17 @@ __global__ void k_build_init(uint32_t* meta, uint32_t n_meta, uint2* work0, uint
     }
 }
 
-__device__ __forceinline__ uint32_t spread10(uint32_t x) {
-    x &= 0x3ffu;
-    x = (x | (x << 16)) & 0x030000ffu;
-    x = (x | (x << 8)) & 0x0300f00fu;
-    x = (x | (x << 4)) & 0x030c30c3u;
-    x = (x | (x << 2)) & 0x09249249u;
-    return x;
+// bits 0..11 of x moved to bits 0, 3, 6, ..., 33
+__device__ __forceinline__ unsigned long long spread12(uint32_t x) {
+    unsigned long long r = 0;
+    for (int b = 0; b < 12; ++b) r |= (unsigned long long)((x >> b) & 1u) << (3 * b);
+    return r;
 }
+
+// key = 36-bit Morton code of the centroid (12 bits per axis over the
+// centroid bounds) above the 28-bit triangle index (nt < 2^28)
+constexpr int kKeyIndexBits = 28;
+constexpr unsigned long long kKeyIndexMask = (1ull << kKeyIndexBits) - 1;
 
 __global__ void k_morton(const float* __restrict__ bounds, uint32_t nt, uint32_t n_pad, const uint32_t* __restrict__ cb,
                          unsigned long long* __restrict__ keys) {
@@ -191,7 +194,7 @@ __global__ void k_morton(const float* __restrict__ bounds, uint32_t nt, uint32_t
     for (int k = 0; k < 3; ++k) {
         lo[k] = unordered(cb[k]);
         const float ext = unordered(cb[3 + k]) - lo[k];
-        inv[k] = ext > 0.0f ? 1023.0f / ext : 0.0f;
+        inv[k] = ext > 0.0f ? 4095.0f / ext : 0.0f;
     }
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += gridDim.x * blockDim.x) {
         if (i >= nt) {
@@ -203,11 +206,11 @@ __global__ void k_morton(const float* __restrict__ bounds, uint32_t nt, uint32_t
             const float l = bounds[6 * (size_t)i + k], h = bounds[6 * (size_t)i + 3 + k];
             float c = 0.5f * l + 0.5f * h;
             float f = isfinite(c) ? (c - lo[k]) * inv[k] : 0.0f;
-            f = fminf(fmaxf(f, 0.0f), 1023.0f);
+            f = fminf(fmaxf(f, 0.0f), 4095.0f);
             q[k] = (uint32_t)f;
         }
-        const uint32_t m = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
-        keys[i] = ((unsigned long long)m << 32) | (unsigned long long)i;
+        const unsigned long long m = (spread12(q[0]) << 2) | (spread12(q[1]) << 1) | spread12(q[2]);
+        keys[i] = (m << kKeyIndexBits) | (unsigned long long)i;
     }
 }
 
@@ -291,7 +294,7 @@ __global__ void k_radix_tree(const unsigned long long* __restrict__ keys, uint32
 __global__ void k_sparse_level0(const unsigned long long* __restrict__ keys, const float* __restrict__ tb, uint32_t n,
                                 float* __restrict__ st) {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        const uint32_t prim = (uint32_t)(keys[p] & 0xffffffffull);
+        const uint32_t prim = (uint32_t)(keys[p] & kKeyIndexMask);
         for (int k = 0; k < 6; ++k) st[6 * (size_t)p + k] = tb[6 * (size_t)prim + k];
     }
 }
@@ -399,7 +402,7 @@ __global__ void k_collapse(uint32_t n, const int32_t* __restrict__ left, const i
 __global__ void k_gather_tris(const unsigned long long* __restrict__ keys, uint32_t n, const float* __restrict__ V,
                               uint32_t nv, const uint32_t* __restrict__ I, float4* __restrict__ tris) {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        const uint32_t prim = (uint32_t)(keys[p] & 0xffffffffull);
+        const uint32_t prim = (uint32_t)(keys[p] & kKeyIndexMask);
         const uint32_t* idx = I + 3 * (size_t)prim;
         const float* a = V + 3 * (size_t)min(idx[0], nv - 1);
         const float* b = V + 3 * (size_t)min(idx[1], nv - 1);
