@@ -33,7 +33,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2107_11008_amd", "csrc", "trace.hip")
 
 def _src_hash():
     h = hashlib.sha256()
-    for f in ("trace.hip", "sc_device.h", "sc_kernels.h", "sc_types.h"):
+    for f in ("trace.hip", "sc_path.h", "sc_device.h", "sc_kernels.h", "sc_types.h", "bvh.hip"):
         with open(os.path.join(ROOT, "paper_2107_11008_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -35,10 +35,16 @@ __device__ __forceinline__ void push(uint2 (*lds)[BS], Spill& s, int& sp, uint2 
     else s.e[sp - kLdsStack] = e;
     ++sp;
 }
+// The spill side is read through a volatile reference: otherwise the
+// compiler merges both reads into one generic (flat) load through a
+// selected address, which is slower than an LDS read and waits for every
+// outstanding memory operation.
 template <int BS>
 __device__ __forceinline__ uint2 pop(uint2 (*lds)[BS], Spill& s, int& sp) {
     --sp;
-    return sp < kLdsStack ? lds[sp][threadIdx.x] : s.e[sp - kLdsStack];
+    if (sp < kLdsStack) return lds[sp][threadIdx.x];
+    const volatile uint2& v = s.e[sp - kLdsStack];
+    return make_uint2(v.x, v.y);
 }
 
 __device__ __forceinline__ void cswap(uint32_t& ka, uint32_t& va, uint32_t& kb, uint32_t& vb) {
