@@ -551,7 +551,8 @@ sc_status build_wide_bvh(Ctx* ctx, Bvh* b, uint32_t width, uint32_t leaf_max, st
 
     SC_TRY(b->nodes.ensure(sizeof(BNode) * (size_t)n_nodes));
     SC_HIP(hipMemcpyAsync(b->nodes.p, nodes_tmp, sizeof(BNode) * (size_t)n_nodes, hipMemcpyDeviceToDevice, st));
-    SC_TRY(b->tris.ensure(sizeof(float4) * 3 * (size_t)n));
+    // padded: the traversal fetches 14 float4 from a leaf's first triangle
+    SC_TRY(b->tris.ensure(sizeof(float4) * (3 * (size_t)n + 14)));
     SC_LAUNCH(k_gather_tris, dim3(grid_for(n, bs)), dim3(bs), 0, st, keys, n, sc.V, sc.nv, sc.I, b->tris.as<float4>());
     emit_prim.resize(n_emit);
     emit_v.resize(9 * (size_t)n_emit);

@@ -71,25 +71,50 @@ struct NodeTest {
     uint32_t ref[8];
 };
 
-// Box tests of the 8 children against (o, inv); near/far planes chosen by
-// the sign of each direction component.  key = entry distance bits, or
-// 0xffffffff when the child is missed or lies beyond tlim.
-__device__ __forceinline__ void test_node(const BNode* __restrict__ nd, F3 o, F3 inv, float tlim, NodeTest& r) {
-    const float4* q = reinterpret_cast<const float4*>(nd);
-    // q[0..1] lox, q[2..3] hix, q[4..5] loy, q[6..7] hiy, q[8..9] loz, q[10..11] hiz, q[12..13] child
-    const bool px = inv.x >= 0.0f, py = inv.y >= 0.0f, pz = inv.z >= 0.0f;
-    const float4 nx0 = q[px ? 0 : 2], nx1 = q[px ? 1 : 3], fx0 = q[px ? 2 : 0], fx1 = q[px ? 3 : 1];
-    const float4 ny0 = q[py ? 4 : 6], ny1 = q[py ? 5 : 7], fy0 = q[py ? 6 : 4], fy1 = q[py ? 7 : 5];
-    const float4 nz0 = q[pz ? 8 : 10], nz1 = q[pz ? 9 : 11], fz0 = q[pz ? 10 : 8], fz1 = q[pz ? 11 : 9];
-    const uint4 c0 = reinterpret_cast<const uint4*>(nd)[12];
-    const uint4 c1 = reinterpret_cast<const uint4*>(nd)[13];
-    const float nx[8] = {nx0.x, nx0.y, nx0.z, nx0.w, nx1.x, nx1.y, nx1.z, nx1.w};
-    const float fx[8] = {fx0.x, fx0.y, fx0.z, fx0.w, fx1.x, fx1.y, fx1.z, fx1.w};
-    const float ny[8] = {ny0.x, ny0.y, ny0.z, ny0.w, ny1.x, ny1.y, ny1.z, ny1.w};
-    const float fy[8] = {fy0.x, fy0.y, fy0.z, fy0.w, fy1.x, fy1.y, fy1.z, fy1.w};
-    const float nz[8] = {nz0.x, nz0.y, nz0.z, nz0.w, nz1.x, nz1.y, nz1.z, nz1.w};
-    const float fz[8] = {fz0.x, fz0.y, fz0.z, fz0.w, fz1.x, fz1.y, fz1.z, fz1.w};
-    const uint32_t ch[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+// One fetch serves both kinds of step: 14 float4 from the step's base, a
+// node (its child boxes and child words) or a leaf (up to 4 triangles of 48
+// bytes, contiguous in the leaf-ordered array; the array is padded so the
+// fetch stays inside it).  Every lane issues the same loads, so a wave whose
+// lanes are at nodes and at leaves waits for one memory round trip, not
+// two.  For a node the plane pairs of each axis are fetched near first:
+// word index j ^ flip, flip = 2 on axes with a negative direction
+// component (the node stores lower planes in words 0-1 of each axis and
+// upper planes in words 2-3); leaves use flip = 0.
+struct Fetch {
+    float4 q[14];
+};
+
+__device__ __forceinline__ void fetch14(const float4* __restrict__ base, uint32_t fx, uint32_t fy, uint32_t fz,
+                                        Fetch& f) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f.q[j] = base[j ^ fx];
+#pragma unroll
+    for (int j = 4; j < 8; ++j) f.q[j] = base[j ^ fy];
+#pragma unroll
+    for (int j = 8; j < 12; ++j) f.q[j] = base[j ^ fz];
+    f.q[12] = base[12];
+    f.q[13] = base[13];
+    // all 14 values are taken here, before the node/leaf branch: otherwise
+    // the compiler moves the loads only one branch reads into that branch,
+    // which brings back the second round trip (the asm is empty)
+#pragma unroll
+    for (int j = 0; j < 14; ++j) asm volatile("" ::"v"(f.q[j].x), "v"(f.q[j].y), "v"(f.q[j].z), "v"(f.q[j].w));
+}
+
+// Box tests of the 8 children of a fetched node against (o, inv).  key =
+// entry distance bits, or 0xffffffff when the child is missed or lies
+// beyond tlim.
+__device__ __forceinline__ void test_node(const Fetch& f, F3 o, F3 inv, float tlim, NodeTest& r) {
+    const float4* q = f.q;
+    const float nx[8] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w};
+    const float fx[8] = {q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
+    const float ny[8] = {q[4].x, q[4].y, q[4].z, q[4].w, q[5].x, q[5].y, q[5].z, q[5].w};
+    const float fy[8] = {q[6].x, q[6].y, q[6].z, q[6].w, q[7].x, q[7].y, q[7].z, q[7].w};
+    const float nz[8] = {q[8].x, q[8].y, q[8].z, q[8].w, q[9].x, q[9].y, q[9].z, q[9].w};
+    const float fz[8] = {q[10].x, q[10].y, q[10].z, q[10].w, q[11].x, q[11].y, q[11].z, q[11].w};
+    const uint32_t ch[8] = {__float_as_uint(q[12].x), __float_as_uint(q[12].y), __float_as_uint(q[12].z),
+                            __float_as_uint(q[12].w), __float_as_uint(q[13].x), __float_as_uint(q[13].y),
+                            __float_as_uint(q[13].z), __float_as_uint(q[13].w)};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const float tnx = (nx[c] - o.x) * inv.x, tfx = (fx[c] - o.x) * inv.x;
@@ -124,13 +149,30 @@ struct TravState {
     F3 o, inv;
     float tb, bV, bW, brcp;
     uint32_t pb, ref;
+    uint32_t flip;   // per-axis node word flips, 2 bits each (see fetch14)
     int sp;
 };
+
+__device__ __forceinline__ uint32_t axis_flips(F3 inv) {
+    return (inv.x >= 0.0f ? 0u : 2u) | (inv.y >= 0.0f ? 0u : 2u) << 2 | (inv.z >= 0.0f ? 0u : 2u) << 4;
+}
+
+// base of a step's fetch and its word flips: the node, or the leaf's
+// first triangle with no flips
+__device__ __forceinline__ const float4* step_base(const DevScene& S, uint32_t ref, uint32_t flip, uint32_t& fl) {
+    if (ref & SC_LEAF_BIT) {
+        fl = 0u;
+        return S.tris + 3 * (size_t)(ref & SC_LEAF_FIRST_MASK);
+    }
+    fl = flip;
+    return reinterpret_cast<const float4*>(S.nodes + ref);
+}
 
 __device__ __forceinline__ void trav_init(TravState& t, F3 o, F3 d) {
     t.rp = ray_prepare(o, d);
     t.o = o;
     t.inv = F3{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
+    t.flip = axis_flips(t.inv);
     t.tb = INFINITY;
     t.bV = 0.0f; t.bW = 0.0f; t.brcp = 0.0f;
     t.pb = 0xffffffffu;
@@ -138,12 +180,27 @@ __device__ __forceinline__ void trav_init(TravState& t, F3 o, F3 d) {
     t.sp = 0;
 }
 
+// Triangle k of a leaf fetch (k < 4) or, past the fetch, from memory.
+__device__ __forceinline__ void leaf_tri(const DevScene& S, const Fetch& f, uint32_t first, uint32_t k, float4& a,
+                                         float4& b, float4& c) {
+    if (k < 4) {
+        a = f.q[3 * k]; b = f.q[3 * k + 1]; c = f.q[3 * k + 2];
+    } else {
+        const float4* tp = S.tris + 3 * (size_t)(first + k);
+        a = tp[0]; b = tp[1]; c = tp[2];
+    }
+}
+
 template <int BS, bool COUNT>
 __device__ __forceinline__ bool trav_step(const DevScene& S, TravState& t, uint2 (*lds)[BS], Spill& st,
                                           VisitCount& vc) {
+    uint32_t fl;
+    const float4* base = step_base(S, t.ref, t.flip, fl);
+    Fetch f;
+    fetch14(base, fl & 3u, (fl >> 2) & 3u, fl >> 4, f);
     if (!(t.ref & SC_LEAF_BIT)) {
         NodeTest nt;
-        test_node(S.nodes + t.ref, t.o, t.inv, search_limit(t.tb), nt);
+        test_node(f, t.o, t.inv, search_limit(t.tb), nt);
         if (COUNT) ++vc.nodes;
         sort8(nt.key, nt.ref);
         if (nt.key[0] != 0xffffffffu) {
@@ -157,25 +214,14 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, TravState& t, uint2
         const uint32_t first = t.ref & SC_LEAF_FIRST_MASK;
         const uint32_t cnt = ((t.ref >> 28) & 7u) + 1u;
         if (COUNT) vc.tris += cnt;
-        // triangles in groups of 4, all loads of a group issued before
-        // its tests (indexes clamped to the leaf, extra tests skipped)
-        for (uint32_t k0 = 0; k0 < cnt; k0 += 4) {
-            float4 ta[4], tb4[4], tc[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t k = min(k0 + (uint32_t)j, cnt - 1u);
-                const float4* tp = S.tris + 3 * (size_t)(first + k);
-                ta[j] = tp[0]; tb4[j] = tp[1]; tc[j] = tp[2];
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (k0 + (uint32_t)j >= cnt) break;
-                const uint32_t prim = __float_as_uint(ta[j].w);
-                TriHit h;
-                if (tri_test(t.rp, perm(t.rp, ta[j]), perm(t.rp, tb4[j]), perm(t.rp, tc[j]), h)) {
-                    if (h.t < t.tb || (h.t == t.tb && prim < t.pb)) {
-                        t.tb = h.t; t.pb = prim; t.bV = h.V; t.bW = h.W; t.brcp = h.rcp;
-                    }
+        for (uint32_t k = 0; k < cnt; ++k) {
+            float4 a, b, c;
+            leaf_tri(S, f, first, k, a, b, c);
+            const uint32_t prim = __float_as_uint(a.w);
+            TriHit h;
+            if (tri_test(t.rp, perm(t.rp, a), perm(t.rp, b), perm(t.rp, c), h)) {
+                if (h.t < t.tb || (h.t == t.tb && prim < t.pb)) {
+                    t.tb = h.t; t.pb = prim; t.bV = h.V; t.bW = h.W; t.brcp = h.rcp;
                 }
             }
         }
@@ -212,7 +258,7 @@ struct AnyState {
     RayPre rp;
     F3 o, inv;
     float tmax, tlim;
-    uint32_t excl, ref;
+    uint32_t excl, ref, flip;
     int sp;
     bool hit;
 };
@@ -221,6 +267,7 @@ __device__ __forceinline__ void any_init(AnyState& t, F3 o, F3 d, float tmax, ui
     t.rp = ray_prepare(o, d);
     t.o = o;
     t.inv = F3{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
+    t.flip = axis_flips(t.inv);
     t.tmax = tmax;
     t.tlim = search_limit(tmax);
     t.excl = excl;
@@ -231,32 +278,27 @@ __device__ __forceinline__ void any_init(AnyState& t, F3 o, F3 d, float tmax, ui
 
 template <int BS>
 __device__ __forceinline__ bool any_step(const DevScene& S, AnyState& t, uint2 (*lds)[BS], Spill& st) {
+    uint32_t fl;
+    const float4* base = step_base(S, t.ref, t.flip, fl);
+    Fetch f;
+    fetch14(base, fl & 3u, (fl >> 2) & 3u, fl >> 4, f);
     if (!(t.ref & SC_LEAF_BIT)) {
         NodeTest nt;
-        test_node(S.nodes + t.ref, t.o, t.inv, t.tlim, nt);
+        test_node(f, t.o, t.inv, t.tlim, nt);
 #pragma unroll
         for (int c = 0; c < 8; ++c)
             if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, t.sp, make_uint2(nt.ref[c], nt.key[c]));
     } else {
         const uint32_t first = t.ref & SC_LEAF_FIRST_MASK;
         const uint32_t cnt = ((t.ref >> 28) & 7u) + 1u;
-        for (uint32_t k0 = 0; k0 < cnt; k0 += 4) {
-            float4 ta[4], tb4[4], tc[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t k = min(k0 + (uint32_t)j, cnt - 1u);
-                const float4* tp = S.tris + 3 * (size_t)(first + k);
-                ta[j] = tp[0]; tb4[j] = tp[1]; tc[j] = tp[2];
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (k0 + (uint32_t)j >= cnt) break;
-                if (__float_as_uint(ta[j].w) == t.excl) continue;
-                TriHit h;
-                if (tri_test(t.rp, perm(t.rp, ta[j]), perm(t.rp, tb4[j]), perm(t.rp, tc[j]), h) && h.t < t.tmax) {
-                    t.hit = true;
-                    return true;
-                }
+        for (uint32_t k = 0; k < cnt; ++k) {
+            float4 a, b, c;
+            leaf_tri(S, f, first, k, a, b, c);
+            if (__float_as_uint(a.w) == t.excl) continue;
+            TriHit h;
+            if (tri_test(t.rp, perm(t.rp, a), perm(t.rp, b), perm(t.rp, c), h) && h.t < t.tmax) {
+                t.hit = true;
+                return true;
             }
         }
     }
