@@ -84,11 +84,14 @@ def cpu_baseline(cfg, rays_per_step, step_s):
 
 def denoise_fps(ctx):
     """The second half of the metric: 1080p frames/s at relMSE <= 0.01
-    against a 1024-spp reference, denoised 4 spp vs plain rendering, on the
+    against a 1024-spp reference, denoised vs plain rendering, on the
     held-out large scene (seed 200000, ~2M triangles).  Plain: the smallest
     power-of-two spp from 4 whose render meets the bar, with the scene's
-    2^24-photon caustic pass.  Denoised: 2^20 photons + 4 spp with the
-    ground-truth buffers + the U-Net with the committed trained weights."""
+    2^24-photon caustic pass.  Denoised: photon pass + render with the
+    ground-truth buffers + the U-Net with the committed trained weights, at
+    the cheapest input (spp in {1, 2, 4}, photons in {2^18, 2^20}) whose
+    denoised image meets the same bar; the 4-spp, 2^20-photon input is
+    reported beside it."""
     import torch
 
     import paper_2107_11008_amd as sc
@@ -105,11 +108,11 @@ def denoise_fps(ctx):
                                                                                902)["map"], outputs=("rgb",))["rgb"]
     outs = {}
 
-    def denoised():
-        m = ctx.trace_photons(bvh, 1 << 20, md, wl, 11, out=outs.get("m_d"))["map"]
+    def denoised(spp, photons):
+        m = ctx.trace_photons(bvh, photons, md, wl, 11, out=outs.get("m_d"))["map"]
         outs["m_d"] = m
-        r = ctx.render(bvh, cam, 4, md, wl, 12, caustic_map=m, outputs=("rgb", "albedo", "normal", "depthn", "trans"),
-                       out=outs.get("r_d"))
+        r = ctx.render(bvh, cam, spp, md, wl, 12, caustic_map=m,
+                       outputs=("rgb", "albedo", "normal", "depthn", "trans"), out=outs.get("r_d"))
         outs["r_d"] = r
         outs["den"] = net.denoise(r, out=outs.get("den"))
         return outs["den"]
@@ -130,8 +133,15 @@ def denoise_fps(ctx):
         torch.cuda.synchronize()
         return img, (time.perf_counter() - t) / reps
 
-    img_d, t_d = timed(denoised, 5)
-    e_d = D.rel_mse(img_d, ref)
+    tried = []
+    for photons in (1 << 18, 1 << 20):
+        for spp in (1, 2, 4):
+            img_d, t_d = timed(lambda: denoised(spp, photons), 5)
+            tried.append({"spp": spp, "photons": photons, "relmse": round(D.rel_mse(img_d, ref), 5),
+                          "ms": round(t_d * 1e3, 2), "fps": round(1.0 / t_d, 2)})
+    passing = [d for d in tried if d["relmse"] <= 0.01]
+    best = min(passing, key=lambda d: d["ms"]) if passing else None
+    fixed = [d for d in tried if d["spp"] == 4 and d["photons"] == 1 << 20][0]
     n_star, t_p, e_p = None, None, None
     spp = 4
     while spp <= 1024:
@@ -142,12 +152,13 @@ def denoise_fps(ctx):
             break
         spp *= 2
     res = {"scene": "large glass scene, seed 200000, 1920x1080, %d triangles" % scene.nt,
-           "denoised": {"spp": 4, "photons": 1 << 20, "relmse": round(e_d, 5), "ms": round(t_d * 1e3, 2),
-                        "fps": round(1.0 / t_d, 2)},
+           "denoised": best, "denoised_4spp": fixed,
            "plain": None if n_star is None else {"spp": n_star, "photons": cfg["n_photons"], "relmse": round(e_p, 5),
-                                                 "ms": round(t_p * 1e3, 2), "fps": round(1.0 / t_p, 2)}}
-    if n_star is not None and e_d <= 0.01:
-        res["fps_ratio"] = round(t_p / t_d, 2)
+                                                 "ms": round(t_p * 1e3, 2), "fps": round(1.0 / t_p, 2)},
+           "denoised_inputs_tried": [(d["spp"], d["photons"], d["relmse"], d["ms"]) for d in tried]}
+    if n_star is not None and best is not None:
+        res["fps_ratio"] = round(t_p * 1e3 / best["ms"], 2)
+        res["fps_ratio_4spp"] = round(t_p * 1e3 / fixed["ms"], 2) if fixed["relmse"] <= 0.01 else None
     return res
 
 
@@ -171,6 +182,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-denoise", action="store_true")
+    ap.add_argument("--staged-depth", type=int, default=None,
+                    help="bounces run as one launch per stage before per-lane path finishing "
+                         "(library default if omitted; 0 = all bounces staged)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration for rocprofv3 --pmc)")
@@ -188,6 +202,8 @@ def main():
     cfg = sg.config2()
     scene, wl, cam = cfg["scene"], cfg["wavelengths"], cfg["camera"]
     ctx = sc.Context(0)
+    if args.staged_depth is not None:
+        ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, args.staged_depth)
     stream = torch.cuda.current_stream()
 
     if args.calib_copy_mib:
@@ -224,8 +240,9 @@ def main():
     bvh = step()
     cnt = ctx.counters()
     ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 0)
-    nodes_per_ray = cnt["node_visits"] / cnt["rays_closest"]
-    tris_per_ray = cnt["tri_tests"] / cnt["rays_closest"]
+    # visits are counted by the staged closest-hit kernel, over its own rays
+    nodes_per_ray = cnt["node_visits"] / cnt["closest_rays_timed"]
+    tris_per_ray = cnt["tri_tests"] / cnt["closest_rays_timed"]
     rays_per_step = cnt["rays_closest"] + cnt["rays_shadow"]
     info = bvh.info()
     del bvh
@@ -248,7 +265,7 @@ def main():
     bytes_per_ray = 24 + 4 + 16 + nodes_per_ray * 256 + tris_per_ray * 48
     launches = c["closest_launches"]
     avg_ms = c["closest_ms"] / max(launches, 1)
-    alg_bytes_per_launch = bytes_per_ray * c["rays_closest"] / max(launches, 1)
+    alg_bytes_per_launch = bytes_per_ray * c["closest_rays_timed"] / max(launches, 1)
     achieved = alg_bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = _traffic_per_launch()
 
@@ -298,7 +315,7 @@ def main():
                      "alg_bytes_per_launch": round(alg_bytes_per_launch),
                      "bytes_per_ray": round(bytes_per_ray, 1), "nodes_per_ray": round(nodes_per_ray, 3),
                      "tris_per_ray": round(tris_per_ray, 3),
-                     "kernel_Mrays_s": round(c["rays_closest"] / (c["closest_ms"] * 1e-3) / 1e6, 1)},
+                     "kernel_Mrays_s": round(c["closest_rays_timed"] / (c["closest_ms"] * 1e-3) / 1e6, 1)},
     }
     if not args.no_denoise:
         line["denoise_1080p"] = denoise_fps(ctx)

@@ -177,16 +177,20 @@ typedef struct {
 typedef struct {
     uint64_t rays_closest;    /* closest-hit queries (camera, ground truth, photons) */
     uint64_t rays_shadow;     /* any-hit queries */
-    uint64_t node_visits;     /* wide nodes fetched by closest-hit traversal (visit counting on) */
-    uint64_t tri_tests;       /* triangles tested by closest-hit traversal (visit counting on) */
-    uint64_t closest_launches;/* closest-hit kernel launches timed (profiling on) */
+    uint64_t node_visits;     /* wide nodes fetched by the staged closest-hit kernel (visit counting on) */
+    uint64_t tri_tests;       /* triangles tested by the staged closest-hit kernel (visit counting on) */
+    uint64_t closest_launches;/* staged closest-hit kernel launches timed (profiling on) */
     double closest_ms;        /* their summed duration from HIP events (profiling on) */
-    uint64_t closest_rays_timed; /* rays processed by the timed launches */
+    uint64_t closest_rays_timed; /* closest-hit rays traced by the staged kernel (the rest of
+                                  * rays_closest by the per-lane path finishing kernels) */
 } sc_counters;
 
 #define SC_OPT_COUNT_VISITS 1 /* 0/1: closest-hit traversal counts node and triangle visits */
 #define SC_OPT_PROFILE 2      /* 0/1: time every closest-hit launch with HIP events */
 #define SC_OPT_QUEUE_CAP 3    /* paths per wavefront chunk (default 1<<23) */
+#define SC_OPT_STAGED_DEPTH 4 /* bounces traced as one launch per stage before the remaining paths
+                               * are each finished by one lane (default 5; 0 = every bounce staged);
+                               * any value gives the same output bit for bit */
 
 uint32_t sc_abi_version(void);
 const char* sc_last_error(void);

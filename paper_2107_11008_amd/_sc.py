@@ -40,6 +40,7 @@ atexit.register(_release_all)
 SC_OPT_COUNT_VISITS = 1
 SC_OPT_PROFILE = 2
 SC_OPT_QUEUE_CAP = 3
+SC_OPT_STAGED_DEPTH = 4
 
 
 class ScError(RuntimeError):

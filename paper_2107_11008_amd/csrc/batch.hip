@@ -56,14 +56,11 @@ __global__ __launch_bounds__(BS) void k_batch_photons(const BatchScene* __restri
             if (p >= bs.n_photons) break;
             PhotonPath ph;
             if (!photon_emit(bs.S, bs.wl, bs.photon_seed, bs.n_photons, p, ph)) continue;
-            for (uint32_t depth = 1; depth <= bs.max_depth; ++depth) {
-                const HitRec h = trace_closest<BS, false>(bs.S, ph.o, ph.d, lds, st, vc);
-                int outcome = -1;
-                int64_t cc = -1;
-                const bool cont = photon_event(bs.S, bs.wl, bs.photon_seed, p, depth, bs.max_depth, h, ph, outcome, cc);
-                if (cc >= 0) atomicAdd(&bs.acc[cc], __double2ull_rn((double)ph.phi * bs.scale));
-                if (!cont) break;
-            }
+            uint32_t n_cl = 0;
+            photon_continue<BS>(bs.S, bs.wl, bs.photon_seed, p, 1, bs.max_depth, ph, lds, st, vc, n_cl,
+                                [&](int64_t cc, const PhotonPath& q) {
+                                    atomicAdd(&bs.acc[cc], __double2ull_rn((double)q.phi * bs.scale));
+                                });
         }
     }
 }
@@ -91,26 +88,9 @@ __global__ __launch_bounds__(BS) void k_batch_render(const BatchScene* __restric
                 for (uint32_t sample = 0; sample < bs.spp; ++sample) {
                     for (uint32_t slot = 0; slot < bs.K; ++slot) {
                         CamPath P = camera_start(bs.cam, bs.wl, bs.seed, pix, sample, slot);
-                        for (uint32_t depth = 1; depth <= bs.max_depth; ++depth) {
-                            const HitRec h = trace_closest<BS, false>(bs.S, P.o, P.d, lds, st, vc);
-                            if (h.prim == 0xffffffffu) break;
-                            const uint32_t type = bs.S.mat[bs.S.tri_obj[h.prim]].type;
-                            if (type == SC_MAT_EMISSIVE) {
-                                camera_emission(bs.S, h, P);
-                                break;
-                            }
-                            if (type == SC_MAT_DIELECTRIC) {
-                                if (!camera_dielectric(bs.S, bs.seed, pix, sample, slot, depth, bs.max_depth, h, P))
-                                    break;
-                                continue;
-                            }
-                            ShadowReq sr;
-                            const bool cont = camera_diffuse(bs.S, bs.wl, bs.cmap, bs.seed, pix, sample, slot, depth,
-                                                             bs.max_depth, h, P, sr);
-                            if (sr.shoot && !trace_any<BS>(bs.S, sr.o, sr.d, sr.tmax, sr.excl, lds, st))
-                                P.L = P.L + sr.contrib;
-                            if (!cont) break;
-                        }
+                        uint32_t n_cl = 0, n_sh = 0;
+                        camera_continue<BS, false>(bs.S, bs.wl, bs.cmap, bs.seed, pix, sample, slot, 1, bs.max_depth, P,
+                                                   lds, st, vc, n_cl, n_sh);
                         film_add(bs.wl, bs.K, slot, P.L, P.lam, acc);
                     }
                 }

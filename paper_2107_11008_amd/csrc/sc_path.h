@@ -652,4 +652,57 @@ __device__ __forceinline__ bool photon_event(const DevScene& S, const WaveDev& w
     return false;
 }
 
+// ---------------------------------------------------------------- whole paths
+// A camera path from its current ray at surface hit depth0 to its end, one
+// bounce after another in the same order as the staged kernels (closest
+// hit; emission, dielectric event, or diffuse event with its shadow ray
+// and caustic gather): P.L is final on return.  n_closest and n_shadow
+// count the rays traced.
+template <int BS, bool COUNT>
+__device__ __forceinline__ void camera_continue(const DevScene& S, const WaveDev& wl, const float* cmap, uint64_t seed,
+                                                uint32_t pix, uint32_t sample, uint32_t slot, uint32_t depth0,
+                                                uint32_t max_depth, CamPath& P, uint2 (*lds)[BS], Spill& st,
+                                                VisitCount& vc, uint32_t& n_closest, uint32_t& n_shadow) {
+    for (uint32_t depth = depth0; depth <= max_depth; ++depth) {
+        const HitRec h = trace_closest<BS, COUNT>(S, P.o, P.d, lds, st, vc);
+        ++n_closest;
+        if (h.prim == 0xffffffffu) break;
+        const uint32_t type = S.mat[S.tri_obj[h.prim]].type;
+        if (type == SC_MAT_EMISSIVE) {
+            camera_emission(S, h, P);
+            break;
+        }
+        if (type == SC_MAT_DIELECTRIC) {
+            if (!camera_dielectric(S, seed, pix, sample, slot, depth, max_depth, h, P)) break;
+            continue;
+        }
+        ShadowReq sr;
+        const bool cont = camera_diffuse(S, wl, cmap, seed, pix, sample, slot, depth, max_depth, h, P, sr);
+        if (sr.shoot) {
+            ++n_shadow;
+            if (!trace_any<BS>(S, sr.o, sr.d, sr.tmax, sr.excl, lds, st)) P.L = P.L + sr.contrib;
+        }
+        if (!cont) break;
+    }
+}
+
+// A photon from its current ray at surface hit depth0 to its end; every
+// deposit is handed to dep(cell_channel, photon).  Returns the outcome of
+// the last event; n_closest counts the rays traced.
+template <int BS, class Dep>
+__device__ __forceinline__ int photon_continue(const DevScene& S, const WaveDev& wl, uint64_t seed, uint64_t p,
+                                               uint32_t depth0, uint32_t max_depth, PhotonPath& ph, uint2 (*lds)[BS],
+                                               Spill& st, VisitCount& vc, uint32_t& n_closest, Dep dep) {
+    for (uint32_t depth = depth0; depth <= max_depth; ++depth) {
+        const HitRec h = trace_closest<BS, false>(S, ph.o, ph.d, lds, st, vc);
+        ++n_closest;
+        int outcome = -1;
+        int64_t cc = -1;
+        const bool cont = photon_event(S, wl, seed, p, depth, max_depth, h, ph, outcome, cc);
+        if (cc >= 0) dep(cc, ph);
+        if (!cont) return outcome;
+    }
+    return -1;
+}
+
 }  // namespace scd

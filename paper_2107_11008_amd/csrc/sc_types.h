@@ -108,6 +108,7 @@ constexpr uint32_t QC_CUR = 0, QC_DIFF = 64, QC_DIEL = 128, QC_SHADOW = 192, QC_
 struct DevCounters {
     unsigned long long rays_closest;
     unsigned long long rays_shadow;
+    unsigned long long rays_staged;   // closest-hit rays of the k_closest launches
     unsigned long long node_visits;
     unsigned long long tri_tests;
     unsigned long long ph_count[9];

@@ -145,7 +145,10 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
         }
     }
     // every ray of the list is traced exactly once
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(&C->rays_closest, (unsigned long long)n);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) {
+        atomicAdd(&C->rays_closest, (unsigned long long)n);
+        atomicAdd(&C->rays_staged, (unsigned long long)n);
+    }
     if (COUNT) {
         const unsigned long long c_nodes = wave_sum_u64(vc.nodes), c_tris = wave_sum_u64(vc.tris);
         if (lane_id() == 0 && c_nodes) {
@@ -494,6 +497,89 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
     }
 }
 
+// ------------------------------------------------------------------ path finishing
+// After the first bounces have run as one launch per stage, the paths still
+// alive are few and a launch per further bounce would cost a whole traversal
+// latency each.  These kernels give each remaining path (or photon) to one
+// lane, which follows it to its end with the same per-path functions, so
+// the outputs are the same bit for bit.  Paths come in chunks of 64 per
+// wave, the first by the wave's index, the rest from the launch's counter.
+__device__ __forceinline__ void count_rays(uint32_t n_cl, uint32_t n_sh, DevCounters* C) {
+    const unsigned long long a = wave_sum_u64(n_cl), b = wave_sum_u64(n_sh);
+    if (lane_id() == 0) {
+        if (a) atomicAdd(&C->rays_closest, a);
+        if (b) atomicAdd(&C->rays_shadow, b);
+    }
+}
+
+__global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo ci, WaveDev wl, PathState P,
+                                                            const float* __restrict__ cmap,
+                                                            const uint32_t* __restrict__ queue,
+                                                            const uint32_t* __restrict__ count, uint32_t depth0,
+                                                            uint32_t* __restrict__ work, DevCounters* __restrict__ C) {
+    __shared__ uint2 lds[kLdsStack][kTraceBS];
+    Spill st;
+    VisitCount vc;
+    const uint32_t n = *count;
+    uint32_t n_cl = 0, n_sh = 0;
+    uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
+    while (base < n) {
+        const uint32_t i = base + lane_id();
+        if (i < n) {
+            const uint32_t pid = queue[i];
+            uint32_t pix, sample, slot;
+            pid_decode(ci, pid, pix, sample, slot);
+            CamPath c = load_path(P, pid);
+            camera_continue<kTraceBS, false>(S, wl, cmap, ci.seed, pix, sample, slot, depth0, ci.max_depth, c, lds, st,
+                                             vc, n_cl, n_sh);
+            P.L[pid] = c.L;
+        }
+        uint32_t next = 0;
+        if (lane_id() == 0) next = atomicAdd(work, 64u);
+        base = __shfl(next, 0) + gridDim.x * blockDim.x;
+    }
+    count_rays(n_cl, n_sh, C);
+}
+
+__global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth0,
+                                                             PhotonState Ph, const uint32_t* __restrict__ queue,
+                                                             const uint32_t* __restrict__ count,
+                                                             uint32_t* __restrict__ work,
+                                                             unsigned long long* __restrict__ acc,
+                                                             uint32_t* __restrict__ cnt_map,
+                                                             DevCounters* __restrict__ C) {
+    __shared__ uint2 lds[kLdsStack][kTraceBS];
+    Spill st;
+    VisitCount vc;
+    const uint32_t n = *count;
+    uint32_t n_cl = 0;
+    uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
+    while (base < n) {
+        const uint32_t i = base + lane_id();
+        if (i < n) {
+            const uint32_t id = queue[i];
+            PhotonPath ph;
+            ph.o = F3{Ph.ox[id], Ph.oy[id], Ph.oz[id]};
+            ph.d = F3{Ph.dx[id], Ph.dy[id], Ph.dz[id]};
+            ph.phi = Ph.phi[id];
+            ph.lam = Ph.lambda[id];
+            ph.slot = Ph.slot[id];
+            ph.spec = Ph.spec[id];
+            const int outcome = photon_continue<kTraceBS>(
+                S, wl, pi.seed, pi.p0 + id, depth0, pi.max_depth, ph, lds, st, vc, n_cl,
+                [&](int64_t cc, const PhotonPath& q) {
+                    atomicAdd(&acc[cc], __double2ull_rn((double)q.phi * pi.scale));
+                    if (cnt_map) atomicAdd(&cnt_map[cc], 1u);
+                });
+            if (outcome >= 0) ph_stat(C, pi, outcome, ph.phi);
+        }
+        uint32_t next = 0;
+        if (lane_id() == 0) next = atomicAdd(work, 64u);
+        base = __shfl(next, 0) + gridDim.x * blockDim.x;
+    }
+    count_rays(n_cl, 0u, C);
+}
+
 __global__ void k_map_finalize(const unsigned long long* __restrict__ acc, size_t n, double inv_scale,
                                float* __restrict__ map) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -745,7 +831,7 @@ sc_status ctx_counters(Ctx* c, sc_counters* out) {
     out->tri_tests = h.tri_tests;
     out->closest_launches = c->closest_launches;
     out->closest_ms = c->closest_ms;
-    out->closest_rays_timed = 0;
+    out->closest_rays_timed = h.rays_staged;
     return SC_OK;
 }
 
@@ -780,6 +866,7 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
     SC_TRY(c->qcounts.ensure(4 * (size_t)frame_words));
     q.counts = c->qcounts.as<uint32_t>();
     reset_work(c);
+    const uint32_t staged = c->staged_depth && c->staged_depth < max_depth ? c->staged_depth : max_depth;
 
     const bool want_aov = out.obj || out.trans || out.tri || out.depth || out.depthn || out.normal || out.normal_cam ||
                           out.albedo;
@@ -802,7 +889,7 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
             hipLaunchKernelGGL(k_raygen, dim3(grid_for(n, bs)), dim3(bs), 0, st, ci, wd, P, n, q.cur, q.counts);
             uint32_t* cur = q.cur;
             uint32_t* nxt = q.next;
-            for (uint32_t depth = 1; depth <= max_depth; ++depth) {
+            for (uint32_t depth = 1; depth <= staged; ++depth) {
                 uint32_t* fc = q.counts + (size_t)(depth - 1) * QC_FRAME;
                 launch_closest(c, S, R, H, cur, fc + QC_CUR, 0u, n);
                 hipLaunchKernelGGL(k_classify, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, P, cur, fc, q.diffuse,
@@ -814,6 +901,10 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
                 launch_anyhit(c, S, SR, q.shadow, fc + QC_SHADOW, 0u, n, nullptr, P.L);
                 std::swap(cur, nxt);
             }
+            if (staged < max_depth)
+                hipLaunchKernelGGL(k_finish_camera, dim3(trace_grid(n)), dim3(kTraceBS), 0, st, S, ci, wd, P, cmap, cur,
+                                   q.counts + (size_t)staged * QC_FRAME + QC_CUR, staged + 1, next_work_slot(c),
+                                   c->counters.as<DevCounters>());
             hipLaunchKernelGGL(k_film_accumulate, dim3(grid_for(hw, bs)), dim3(bs), 0, st, ci, wd, P.L, P.lambda, ns,
                                out.rgb);
         }
@@ -872,7 +963,8 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
                                c->counters.as<DevCounters>());
             uint32_t* cur = q.cur;
             uint32_t* nxt = q.next;
-            for (uint32_t depth = 1; depth <= max_depth; ++depth) {
+            const uint32_t staged = c->staged_depth && c->staged_depth < max_depth ? c->staged_depth : max_depth;
+            for (uint32_t depth = 1; depth <= staged; ++depth) {
                 uint32_t* fc = q.counts + (size_t)(depth - 1) * QC_FRAME;
                 launch_closest(c, S, R, H, cur, fc + QC_CUR, 0u, n);
                 hipLaunchKernelGGL(k_photon_event, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, wd, pi, depth, Ph, cur,
@@ -880,6 +972,10 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
                                    c->counters.as<DevCounters>());
                 std::swap(cur, nxt);
             }
+            if (staged < max_depth)
+                hipLaunchKernelGGL(k_finish_photons, dim3(trace_grid(n)), dim3(kTraceBS), 0, st, S, wd, pi, staged + 1,
+                                   Ph, cur, q.counts + (size_t)staged * QC_FRAME + QC_CUR, next_work_slot(c),
+                                   c->acc64.as<unsigned long long>(), count_map, c->counters.as<DevCounters>());
         }
     }
     hipLaunchKernelGGL(k_map_finalize, dim3(grid_for(cells, bs)), dim3(bs), 0, st, c->acc64.as<unsigned long long>(),
