@@ -485,7 +485,7 @@ sc_status sc_unet_forward(sc_ctx* ctx, sc_unet* net, const float* feat, uint32_t
 sc_status sc_unet_backward(sc_ctx* ctx, sc_unet* net, const float* dpred, float* grad) {
     if (!ctx || !net || !dpred || !grad) return set_error(SC_EINVAL, "NULL argument");
     scl::Unet& u = net->u;
-    if (!u.acts.p) return set_error(SC_EINVAL, "sc_unet_backward needs a preceding sc_unet_forward");
+    if (!u.acts.p || !u.cat_valid) return set_error(SC_EINVAL, "sc_unet_backward needs a preceding sc_unet_forward");
     SC_TRY(scl::unet_pack_dpred(&u, dpred));
     SC_TRY(scl::unet_backward_packed(&u));
     SC_HIP(hipMemcpyAsync(grad, u.grad.p, 4 * u.n_params, hipMemcpyDeviceToDevice, ctx->c.stream));
@@ -522,7 +522,7 @@ sc_status sc_denoise(sc_ctx* ctx, sc_unet* net, const sc_aov* in, uint32_t w, ui
     SC_TRY(check_shape(u, 1, W, H));
     SC_TRY(scl::unet_prepare(&u, 1, H, W));
     SC_TRY(scl::unet_features(&u, *in, w, h));
-    SC_TRY(scl::unet_forward_packed(&u));
+    SC_TRY(scl::unet_forward_packed(&u, false));
     SC_TRY(scl::unet_output_rgb(&u, w, h, out_rgb));
     return SC_OK;
 }

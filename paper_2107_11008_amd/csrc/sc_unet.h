@@ -37,6 +37,7 @@ struct Unet {
     uint32_t B = 0, H = 0, W = 0;
     UnetTensors t;
     uint64_t step = 0;
+    bool cat_valid = false;   // the last forward pass kept what a backward pass reads
 };
 
 sc_status unet_create(Ctx* c, const uint32_t* widths, uint32_t levels, Unet* u);
@@ -44,7 +45,9 @@ sc_status unet_refresh(Unet* u);
 sc_status unet_prepare(Unet* u, uint32_t B, uint32_t H, uint32_t W);
 sc_status unet_pack_input(Unet* u, const float* feat);
 sc_status unet_pack_dpred(Unet* u, const float* dpred);
-sc_status unet_forward_packed(Unet* u);
+// keep_cat: materialise the decoder concatenations (needed by a backward
+// pass); inference reads them in place.
+sc_status unet_forward_packed(Unet* u, bool keep_cat = true);
 sc_status unet_backward_packed(Unet* u);
 sc_status unet_loss(Unet* u, const float* target, float* loss_dev);
 sc_status unet_adam(Unet* u, float lr);

@@ -66,19 +66,27 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
     const uint32_t K = KS * KS * cin_p;
     floatx4 acc[4];
     for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    // this lane's k-group (8 channels of one tap, as cin_p is a multiple of
+    // 16) advances by 32 per step: tap and channel are carried along
+    uint32_t tap = (8 * g) / cin_p, ci = (8 * g) % cin_p;
+    const size_t pix0 = ((size_t)b * H + y) * W + x;
     for (uint32_t k0 = 0; k0 < kpad; k0 += 32) {
         const uint32_t kk = k0 + 8 * g;
         Frag a;
         a.u = make_uint4(0u, 0u, 0u, 0u);
         if (pvalid && kk < K) {
-            const uint32_t tap = kk / cin_p, ci = kk % cin_p;
-            const int dy = KS == 3 ? (int)(tap / 3) - 1 : 0;
-            const int dx = KS == 3 ? (int)(tap % 3) - 1 : 0;
+            const int dy = KS == 3 ? (int)(tap >= 6 ? 2 : (tap >= 3 ? 1 : 0)) - 1 : 0;
+            const int dx = KS == 3 ? (int)(tap - 3 * (uint32_t)(dy + 1)) - 1 : 0;
             const int yy = (int)y + dy, xx = (int)x + dx;
             if (yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W) {
-                const size_t src = (((size_t)b * H + yy) * W + xx) * cin_p + ci;
+                const size_t src = (size_t)((long long)pix0 + (long long)dy * W + dx) * cin_p + ci;
                 a.u = *reinterpret_cast<const uint4*>(X + src);
             }
+        }
+        ci += 32;
+        while (ci >= cin_p) {
+            ci -= cin_p;
+            ++tap;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -106,6 +114,117 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
             if (relu) v = fmaxf(v, 0.0f);
             if (Yf) Yf[(size_t)po * y_stride + y_off + co] = v;
             else Y[(size_t)po * y_stride + y_off + co] = to_bf16(v);
+        }
+    }
+}
+
+// 3x3 convolution with LDS tiles.  A block computes an 8 x 16 tile of output
+// pixels x 64 output channels (blockIdx.y selects the channel group); the
+// input channels are taken 32 at a time: the tile with its 1-pixel halo and
+// the 64 x 9 x 32 weights of the chunk are staged in LDS, then every tap
+// reads its operands there.  Wave w computes tile rows 2w and 2w+1 (two
+// 16-pixel A operands sharing each weight operand).  Channels past cin_p in
+// the last chunk are zero in both tiles.  With X2 given, the input is the
+// concatenation [nearest 2x upsampling of X (c_split channels at H/2 x W/2),
+// X2 (cin_p - c_split channels)], read in place (decoder inference).
+constexpr int kTR = 8, kTC = 16, kHR = kTR + 2, kHC = kTC + 2;
+constexpr int kCC = 32;                 // input channels per chunk
+constexpr int kWP = 9 * kCC + 8;        // LDS pitch of a weight row (bf16), padded against bank conflicts
+
+__global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ X2,
+                                               uint32_t c_split, uint32_t H, uint32_t W, uint32_t cin_p,
+                                               const uint16_t* __restrict__ Wt, uint32_t kpad,
+                                               const float* __restrict__ bias, uint32_t cout_p, uint32_t cout_real,
+                                               uint16_t* __restrict__ Y, float* __restrict__ Yf, uint32_t y_stride,
+                                               uint32_t y_off, int relu) {
+    __shared__ uint4 xs4[kHR * kHC * kCC / 8];
+    __shared__ uint4 ws4[64 * kWP / 8];
+    const uint16_t* xs = reinterpret_cast<const uint16_t*>(xs4);
+    const uint16_t* ws = reinterpret_cast<const uint16_t*>(ws4);
+    const uint32_t tiles_x = (W + kTC - 1) / kTC, tiles_y = (H + kTR - 1) / kTR;
+    uint32_t bid = blockIdx.x;
+    const uint32_t tx = bid % tiles_x;
+    bid /= tiles_x;
+    const uint32_t ty = bid % tiles_y;
+    const uint32_t b = bid / tiles_y;
+    const uint32_t cg = blockIdx.y;
+    const uint32_t x0 = tx * kTC, y0 = ty * kTR;
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t pl = lane & 15, g = lane >> 4;
+    const uint32_t nt_total = cout_p / 16;
+    const uint32_t nt_here = min(4u, nt_total - cg * 4);   // 16-channel tiles of this group
+    floatx4 acc[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[r][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t c0 = 0; c0 < cin_p; c0 += kCC) {
+        const uint32_t cn = min((uint32_t)kCC, cin_p - c0);
+        __syncthreads();   // the previous chunk is no longer read
+        for (uint32_t t = threadIdx.x; t < kHR * kHC * 4; t += 256) {
+            const uint32_t piece = t & 3, pix = t >> 2;
+            const int yy = (int)y0 + (int)(pix / kHC) - 1, xx = (int)x0 + (int)(pix % kHC) - 1;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            const uint32_t c = c0 + piece * 8;
+            if (piece * 8 < cn && yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W) {
+                const size_t pix_full = ((size_t)b * H + yy) * W + xx;
+                if (!X2)
+                    v = *reinterpret_cast<const uint4*>(X + pix_full * cin_p + c);
+                else if (c < c_split)   // nearest 2x upsampling of the coarser tensor
+                    v = *reinterpret_cast<const uint4*>(
+                        X + (((size_t)b * (H / 2) + (uint32_t)yy / 2) * (W / 2) + (uint32_t)xx / 2) * c_split + c);
+                else
+                    v = *reinterpret_cast<const uint4*>(X2 + pix_full * (cin_p - c_split) + (c - c_split));
+            }
+            xs4[pix * (kCC / 8) + piece] = v;
+        }
+        for (uint32_t t = threadIdx.x; t < 16 * nt_here * 9 * 4; t += 256) {
+            const uint32_t piece = t & 3, rest = t >> 2;
+            const uint32_t tap = rest % 9, col = rest / 9;
+            const uint32_t co = cg * 64 + col;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (piece * 8 < cn)
+                v = *reinterpret_cast<const uint4*>(Wt + (size_t)co * kpad + (size_t)tap * cin_p + c0 + piece * 8);
+            ws4[(col * kWP + tap * kCC) / 8 + piece] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            Frag a0, a1;
+            a0.u = *reinterpret_cast<const uint4*>(xs + (((2 * wv + dy) * kHC) + pl + dx) * kCC + 8 * g);
+            a1.u = *reinterpret_cast<const uint4*>(xs + (((2 * wv + 1 + dy) * kHC) + pl + dx) * kCC + 8 * g);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if ((uint32_t)j < nt_here) {
+                    Frag bw;
+                    bw.u = *reinterpret_cast<const uint4*>(ws + (j * 16 + pl) * kWP + tap * kCC + 8 * g);
+                    acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.v, bw.v, acc[0][j], 0, 0, 0);
+                    acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.v, bw.v, acc[1][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const uint32_t yy = y0 + 2 * wv + r;
+        if (yy >= H) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if ((uint32_t)j >= nt_here) continue;
+            const uint32_t co = (cg * 4 + j) * 16 + pl;
+            if (co >= cout_real) continue;
+            const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t xx = x0 + 4 * g + i;
+                if (xx >= W) continue;
+                const size_t po = ((size_t)b * H + yy) * W + xx;
+                float v = acc[r][j][i] + bv;
+                if (relu) v = fmaxf(v, 0.0f);
+                if (Yf) Yf[po * y_stride + y_off + co] = v;
+                else Y[po * y_stride + y_off + co] = to_bf16(v);
+            }
         }
     }
 }
@@ -266,18 +385,21 @@ __global__ void k_maxpool_bwd(const uint16_t* __restrict__ dY, const uint8_t* __
 }
 
 // C[b,y,x,:] = [ D[b,y/2,x/2,:cu] | E[b,y,x,:ce] ]
+// 8 channels (16 bytes) per step; cu and ce are multiples of 16
 __global__ void k_upcat(const uint16_t* __restrict__ D, uint32_t cu, const uint16_t* __restrict__ E, uint32_t ce,
                         uint32_t B, uint32_t H, uint32_t W, uint16_t* __restrict__ Cc) {
-    const uint32_t ct = cu + ce;
-    const size_t n = (size_t)B * H * W * ct;
+    const uint32_t ct8 = (cu + ce) / 8;
+    const size_t n = (size_t)B * H * W * ct8;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t c = i % ct;
-        const size_t pix = i / ct;
+        const uint32_t c = (uint32_t)(i % ct8) * 8;
+        const size_t pix = i / ct8;
         const uint32_t x = pix % W;
         const size_t r = pix / W;
         const uint32_t y = r % H;
         const uint32_t b = r / H;
-        Cc[i] = c < cu ? D[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * cu + c] : E[pix * ce + (c - cu)];
+        const uint16_t* src = c < cu ? D + (((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * cu + c
+                                     : E + pix * ce + (c - cu);
+        reinterpret_cast<uint4*>(Cc)[i] = *reinterpret_cast<const uint4*>(src);
     }
 }
 
@@ -575,15 +697,18 @@ sc_status ensure_acts(Unet* u, uint32_t B, uint32_t H, uint32_t W) {
 
 void conv_launch(hipStream_t st, const UnetLayer& L, const uint16_t* X, uint32_t P, uint32_t H, uint32_t W,
                  const uint16_t* Wt, uint32_t cin_p, uint32_t kpad, const float* bias, uint32_t cout_p,
-                 uint32_t cout_real, uint16_t* Y, float* Yf, uint32_t y_stride, int relu) {
+                 uint32_t cout_real, uint16_t* Y, float* Yf, uint32_t y_stride, int relu,
+                 const uint16_t* X2 = nullptr, uint32_t c_split = 0) {
     const uint32_t n_tiles = (P + 15) / 16;
     const uint32_t groups = (cout_p / 16 + 3) / 4;
     const size_t waves = (size_t)n_tiles * groups;
     const uint32_t grid = (uint32_t)((waves + 3) / 4);
-    if (L.ks == 3)
-        hipLaunchKernelGGL(k_conv<3>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
-                           cout_real, Y, Yf, y_stride, 0u, relu);
-    else
+    if (L.ks == 3) {
+        const uint32_t B = P / (H * W);
+        const uint32_t tiles = ((W + kTC - 1) / kTC) * ((H + kTR - 1) / kTR) * B;
+        hipLaunchKernelGGL(k_conv3, dim3(tiles, (cout_p / 16 + 3) / 4), dim3(256), 0, st, X, X2, c_split, H, W,
+                           cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
+    } else
         hipLaunchKernelGGL(k_conv<1>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
                            cout_real, Y, Yf, y_stride, 0u, relu);
 }
@@ -591,7 +716,7 @@ void conv_launch(hipStream_t st, const UnetLayer& L, const uint16_t* X, uint32_t
 }  // namespace
 
 // Forward pass over the packed input in u->acts (T.in); prediction in u->pred.
-sc_status unet_forward_packed(Unet* u) {
+sc_status unet_forward_packed(Unet* u, bool keep_cat) {
     hipStream_t st = u->ctx->stream;
     const uint32_t L = (uint32_t)u->widths.size();
     uint16_t* A = u->acts.as<uint16_t>();
@@ -619,14 +744,21 @@ sc_status unet_forward_packed(Unet* u) {
     }
     for (int i = (int)L - 2; i >= 0; --i) {
         const uint32_t H = u->H >> i, W = u->W >> i, P = u->B * H * W;
-        hipLaunchKernelGGL(k_upcat, dim3(blocks((size_t)P * (hc + u->widths[i]))), dim3(256), 0, st, h, hc,
-                           A + T.enc_b[i], u->widths[i], u->B, H, W, A + T.cat[i]);
-        h = A + T.cat[i];
+        const uint16_t* skip = nullptr;   // read in place by the first convolution
+        uint32_t split = 0;
+        if (keep_cat) {   // the backward pass reads the concatenation
+            hipLaunchKernelGGL(k_upcat, dim3(blocks((size_t)P * (hc + u->widths[i]) / 8)), dim3(256), 0, st, h, hc,
+                               A + T.enc_b[i], u->widths[i], u->B, H, W, A + T.cat[i]);
+            h = A + T.cat[i];
+        } else {
+            skip = A + T.enc_b[i];
+            split = hc;
+        }
         for (int part = 0; part < 2; ++part) {
             const UnetLayer& Ly = u->layers[li++];
             uint16_t* out = A + (part == 0 ? T.dec_a[i] : T.dec_b[i]);
             conv_launch(st, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p, Ly.cout, out,
-                        nullptr, Ly.cout, 1);
+                        nullptr, Ly.cout, 1, part == 0 ? skip : nullptr, part == 0 ? split : 0u);
             h = out;
             hc = Ly.cout;
         }
@@ -635,6 +767,7 @@ sc_status unet_forward_packed(Unet* u) {
     const uint32_t P0 = u->B * u->H * u->W;
     conv_launch(st, Lo, h, P0, u->H, u->W, wf + Lo.wf_off, Lo.cin_p, Lo.kpad, th + Lo.b_off, Lo.cout_p, Lo.cout,
                 nullptr, u->pred.as<float>(), 3, 0);
+    u->cat_valid = keep_cat;
     SC_HIP(hipGetLastError());
     return SC_OK;
 }
