@@ -139,18 +139,27 @@ struct VisitCount {
     unsigned long long nodes = 0, tris = 0;
 };
 
-// Closest hit: lexicographic minimum of (t, triangle) over the scene,
-// as a resumable traversal: trav_step advances one ray by one node visit or
-// one leaf and returns true when the ray is finished (trav_result is then
-// final).  Any visiting order gives the same result: boxes are tested
-// conservatively and hits are compared by (t, triangle).
-struct TravState {
+// Resumable traversal of one ray, closest hit or any hit.
+//  * closest hit: the lexicographic minimum of (t, triangle) over the scene;
+//  * any hit: is there a triangle other than excl with 0 < t < tmax?
+// A step visits one node or one leaf and returns true when the ray is done
+// (then trav_result, or Trav::hit for an any-hit ray, is final).  Any
+// visiting order gives the same result: boxes are tested conservatively
+// and closest hits are compared by (t, triangle).  MODE fixes the kind at
+// compile time (kClosest, kAny) or reads it from the state (kEither), so
+// one kernel can follow camera rays and shadow rays with the same code.
+enum TravMode { kClosest = 0, kAny = 1, kEither = 2 };
+
+struct Trav {
     RayPre rp;
     F3 o, inv;
-    float tb, bV, bW, brcp;
-    uint32_t pb, ref;
-    uint32_t flip;   // per-axis node word flips, 2 bits each (see fetch14)
+    float tb;          // closest: best t so far; any: tmax
+    float bV, bW, brcp;
+    uint32_t pb;       // closest: best triangle; any: the excluded triangle
+    uint32_t ref;
+    uint32_t flip;     // per-axis node word flips, 2 bits each (see fetch14)
     int sp;
+    bool any, hit;
 };
 
 __device__ __forceinline__ uint32_t axis_flips(F3 inv) {
@@ -168,16 +177,23 @@ __device__ __forceinline__ const float4* step_base(const DevScene& S, uint32_t r
     return reinterpret_cast<const float4*>(S.nodes + ref);
 }
 
-__device__ __forceinline__ void trav_init(TravState& t, F3 o, F3 d) {
+__device__ __forceinline__ void trav_begin(Trav& t, F3 o, F3 d, bool any, float tmax, uint32_t excl) {
     t.rp = ray_prepare(o, d);
     t.o = o;
     t.inv = F3{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
     t.flip = axis_flips(t.inv);
-    t.tb = INFINITY;
+    t.tb = any ? tmax : INFINITY;
+    t.pb = any ? excl : 0xffffffffu;
     t.bV = 0.0f; t.bW = 0.0f; t.brcp = 0.0f;
-    t.pb = 0xffffffffu;
     t.ref = 0;   // root node
     t.sp = 0;
+    t.any = any;
+    t.hit = false;
+}
+
+__device__ __forceinline__ void trav_init(Trav& t, F3 o, F3 d) { trav_begin(t, o, d, false, 0.0f, 0u); }
+__device__ __forceinline__ void any_init(Trav& t, F3 o, F3 d, float tmax, uint32_t excl) {
+    trav_begin(t, o, d, true, tmax, excl);
 }
 
 // Triangle k of a leaf fetch (k < 4) or, past the fetch, from memory.
@@ -191,9 +207,9 @@ __device__ __forceinline__ void leaf_tri(const DevScene& S, const Fetch& f, uint
     }
 }
 
-template <int BS, bool COUNT>
-__device__ __forceinline__ bool trav_step(const DevScene& S, TravState& t, uint2 (*lds)[BS], Spill& st,
-                                          VisitCount& vc) {
+template <int BS, bool COUNT, int MODE>
+__device__ __forceinline__ bool tstep(const DevScene& S, Trav& t, uint2 (*lds)[BS], Spill& st, VisitCount& vc) {
+    const bool any = MODE == kAny ? true : (MODE == kClosest ? false : t.any);
     uint32_t fl;
     const float4* base = step_base(S, t.ref, t.flip, fl);
     Fetch f;
@@ -202,13 +218,20 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, TravState& t, uint2
         NodeTest nt;
         test_node(f, t.o, t.inv, search_limit(t.tb), nt);
         if (COUNT) ++vc.nodes;
-        sort8(nt.key, nt.ref);
-        if (nt.key[0] != 0xffffffffu) {
+        if (MODE == kAny) {
+            // order does not matter for a yes/no answer
 #pragma unroll
-            for (int c = 7; c >= 1; --c)
+            for (int c = 0; c < 8; ++c)
                 if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, t.sp, make_uint2(nt.ref[c], nt.key[c]));
-            t.ref = nt.ref[0];
-            return false;
+        } else {
+            sort8(nt.key, nt.ref);
+            if (nt.key[0] != 0xffffffffu) {
+#pragma unroll
+                for (int c = 7; c >= 1; --c)
+                    if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, t.sp, make_uint2(nt.ref[c], nt.key[c]));
+                t.ref = nt.ref[0];
+                return false;
+            }
         }
     } else {
         const uint32_t first = t.ref & SC_LEAF_FIRST_MASK;
@@ -218,15 +241,27 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, TravState& t, uint2
             float4 a, b, c;
             leaf_tri(S, f, first, k, a, b, c);
             const uint32_t prim = __float_as_uint(a.w);
+            if (any && prim == t.pb) continue;
             TriHit h;
             if (tri_test(t.rp, perm(t.rp, a), perm(t.rp, b), perm(t.rp, c), h)) {
-                if (h.t < t.tb || (h.t == t.tb && prim < t.pb)) {
+                if (any) {
+                    if (h.t < t.tb) {
+                        t.hit = true;
+                        return true;
+                    }
+                } else if (h.t < t.tb || (h.t == t.tb && prim < t.pb)) {
                     t.tb = h.t; t.pb = prim; t.bV = h.V; t.bW = h.W; t.brcp = h.rcp;
                 }
             }
         }
     }
-    // next entry from the stack that is still within reach
+    if (MODE == kAny) {
+        if (t.sp == 0) return true;
+        t.ref = pop<BS>(lds, st, t.sp).x;
+        return false;
+    }
+    // next entry from the stack that is still within reach (an any-hit
+    // ray pushed only entries within reach of tmax)
     while (t.sp > 0) {
         const uint2 e = pop<BS>(lds, st, t.sp);
         if (__uint_as_float(e.y) <= search_limit(t.tb)) {
@@ -237,82 +272,32 @@ __device__ __forceinline__ bool trav_step(const DevScene& S, TravState& t, uint2
     return true;
 }
 
-__device__ __forceinline__ HitRec trav_result(const TravState& t) {
+template <int BS, bool COUNT>
+__device__ __forceinline__ bool trav_step(const DevScene& S, Trav& t, uint2 (*lds)[BS], Spill& st, VisitCount& vc) {
+    return tstep<BS, COUNT, kClosest>(S, t, lds, st, vc);
+}
+
+__device__ __forceinline__ HitRec trav_result(const Trav& t) {
     return HitRec{t.tb, t.bV * t.brcp, t.bW * t.brcp, t.pb};
 }
 
 template <int BS, bool COUNT>
 __device__ __forceinline__ HitRec trace_closest(const DevScene& S, F3 o, F3 d, uint2 (*lds)[BS], Spill& st,
                                                 VisitCount& vc) {
-    TravState t;
+    Trav t;
     trav_init(t, o, d);
-    while (!trav_step<BS, COUNT>(S, t, lds, st, vc)) {
+    while (!tstep<BS, COUNT, kClosest>(S, t, lds, st, vc)) {
     }
     return trav_result(t);
-}
-
-// Any hit: is there a triangle other than excl with 0 < t < tmax?  As a
-// resumable traversal: any_step advances by one node visit or one leaf and
-// returns true when the answer (AnyState::hit) is known.
-struct AnyState {
-    RayPre rp;
-    F3 o, inv;
-    float tmax, tlim;
-    uint32_t excl, ref, flip;
-    int sp;
-    bool hit;
-};
-
-__device__ __forceinline__ void any_init(AnyState& t, F3 o, F3 d, float tmax, uint32_t excl) {
-    t.rp = ray_prepare(o, d);
-    t.o = o;
-    t.inv = F3{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
-    t.flip = axis_flips(t.inv);
-    t.tmax = tmax;
-    t.tlim = search_limit(tmax);
-    t.excl = excl;
-    t.ref = 0;
-    t.sp = 0;
-    t.hit = false;
-}
-
-template <int BS>
-__device__ __forceinline__ bool any_step(const DevScene& S, AnyState& t, uint2 (*lds)[BS], Spill& st) {
-    uint32_t fl;
-    const float4* base = step_base(S, t.ref, t.flip, fl);
-    Fetch f;
-    fetch14(base, fl & 3u, (fl >> 2) & 3u, fl >> 4, f);
-    if (!(t.ref & SC_LEAF_BIT)) {
-        NodeTest nt;
-        test_node(f, t.o, t.inv, t.tlim, nt);
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (nt.key[c] != 0xffffffffu) push<BS>(lds, st, t.sp, make_uint2(nt.ref[c], nt.key[c]));
-    } else {
-        const uint32_t first = t.ref & SC_LEAF_FIRST_MASK;
-        const uint32_t cnt = ((t.ref >> 28) & 7u) + 1u;
-        for (uint32_t k = 0; k < cnt; ++k) {
-            float4 a, b, c;
-            leaf_tri(S, f, first, k, a, b, c);
-            if (__float_as_uint(a.w) == t.excl) continue;
-            TriHit h;
-            if (tri_test(t.rp, perm(t.rp, a), perm(t.rp, b), perm(t.rp, c), h) && h.t < t.tmax) {
-                t.hit = true;
-                return true;
-            }
-        }
-    }
-    if (t.sp == 0) return true;
-    t.ref = pop<BS>(lds, st, t.sp).x;
-    return false;
 }
 
 template <int BS>
 __device__ __forceinline__ bool trace_any(const DevScene& S, F3 o, F3 d, float tmax, uint32_t excl, uint2 (*lds)[BS],
                                           Spill& st) {
-    AnyState t;
+    Trav t;
     any_init(t, o, d, tmax, excl);
-    while (!any_step<BS>(S, t, lds, st)) {
+    VisitCount vc;
+    while (!tstep<BS, false, kAny>(S, t, lds, st, vc)) {
     }
     return t.hit;
 }

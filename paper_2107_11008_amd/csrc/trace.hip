@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
     RayFeed feed;
     feed.init(n, work);
     VisitCount vc;
-    TravState t;
+    Trav t;
     uint32_t pid = 0;
     bool active = false;
     for (;;) {
