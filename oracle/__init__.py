@@ -25,7 +25,8 @@ _LIB = None
 
 class Material(C.Structure):
     _fields_ = [("type", C.c_uint32), ("albedo_mode", C.c_uint32), ("rho_a", C.c_float), ("rho_b", C.c_float),
-                ("cauchy_a", C.c_float), ("cauchy_b", C.c_float), ("le", C.c_float), ("pad", C.c_float)]
+                ("cauchy_a", C.c_float), ("cauchy_b", C.c_float), ("le", C.c_float), ("priority", C.c_uint32),
+                ("sigma", C.c_float * 3), ("roughness", C.c_float)]
 
 
 class SceneS(C.Structure):
@@ -81,6 +82,9 @@ def lib():
         L.sco_any.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
         L.sco_dielectric.argtypes = [vp, vp, vp, vp, f32, f32, f32, f32, vp, vp, vp, vp]
         L.sco_fresnel.argtypes = [f32, f32, f32, f32]
+        L.sco_exp_neg.argtypes = [f32]
+        L.sco_exp_neg.restype = f32
+        L.sco_media_step.argtypes = [vp, vp, u32, u32, C.c_int, f32, vp, vp, vp, vp, vp]
         L.sco_fresnel.restype = f32
         L.sco_camera_ray.argtypes = [vp, u32, u32, f32, f32, vp, vp]
         L.sco_trace_photons.argtypes = [vp, vp, u64, u64, u64, u32, vp, u64, vp, vp, vp]
@@ -200,6 +204,24 @@ def dielectric(d, Ng, Ns, P, lam, ca, cb, uF):
 
 def fresnel(n1, n2, ci, ct):
     return lib().sco_fresnel(float(n1), float(n2), float(ci), float(ct))
+
+
+def exp_neg(x):
+    return lib().sco_exp_neg(float(x))
+
+
+def media_step(osc: "OracleScene", ids, k: int, entering: bool, lam: float):
+    """One crossing of a dielectric surface of object k with the media set
+    ``ids``: returns (ids_after, real, n1, n2)."""
+    a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32).reshape(-1))
+    out = np.zeros(4, np.uint32)
+    n_after, real = C.c_uint32(0), C.c_int(0)
+    n1, n2 = C.c_float(0.0), C.c_float(0.0)
+    rc = lib().sco_media_step(C.byref(osc.c), _p(a), len(a), int(k), int(bool(entering)), float(lam), _p(out),
+                              C.byref(n_after), C.byref(real), C.byref(n1), C.byref(n2))
+    if rc != 0:
+        raise ValueError("sco_media_step: invalid arguments")
+    return [int(x) for x in out[: n_after.value]], bool(real.value), n1.value, n2.value
 
 
 def camera_ray(cam, x, y, jx=0.5, jy=0.5):

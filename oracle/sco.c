@@ -15,6 +15,7 @@
  */
 #include "sco.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -497,15 +498,18 @@ float sco_fresnel(float n1, float n2, float ci, float ct) {
     return 0.5f * (rs * rs + rp * rp);
 }
 
-/* Returns 1 with the new direction and reflected flag, 0 if no valid
- * outgoing direction exists even with the geometric normal. */
-static int dielectric_dir(const frame_t* f, v3 d, float lambda_nm, float ca, float cb, float uF,
-                          v3* dout, int* refl_out, float* R_out) {
+/* Refractive index from the two-term Cauchy law, lambda in nm. */
+static float cauchy_n(float ca, float cb, float lambda_nm) {
     float l = lambda_nm * 0.001f;
-    float n = ca + cb / (l * l);
-    float n1, n2, eta;
-    if (f->entering) { n1 = 1.0f; n2 = n; eta = 1.0f / n; }
-    else { n1 = n; n2 = 1.0f; eta = n; }
+    return ca + cb / (l * l);
+}
+
+/* Returns 1 with the new direction and reflected flag, 0 if no valid
+ * outgoing direction exists even with the geometric normal.  n1 is the
+ * index on the side the ray comes from, n2 the one across the surface. */
+static int dielectric_dir(const frame_t* f, v3 d, float n1, float n2, float uF,
+                          v3* dout, int* refl_out, float* R_out) {
+    float eta = n1 / n2;
     v3 N = f->Ns;
     float ci = -vdot(d, N);
     int geometric = 0;
@@ -549,12 +553,137 @@ int sco_dielectric(const float d[3], const float Ng[3], const float Ns[3], const
     f.Ns = ns;
     v3 out;
     int refl;
-    if (!dielectric_dir(&f, dd, lambda_nm, ca, cb, u_fresnel, &out, &refl, R_out)) return 0;
+    float n = cauchy_n(ca, cb, lambda_nm);
+    float n1 = f.entering ? 1.0f : n, n2 = f.entering ? n : 1.0f;
+    if (!dielectric_dir(&f, dd, n1, n2, u_fresnel, &out, &refl, R_out)) return 0;
     v3 o = offset_ray(f.P, refl ? f.Nf : vneg(f.Nf));
     o_out[0] = o.x; o_out[1] = o.y; o_out[2] = o.z;
     d_out[0] = out.x; d_out[1] = out.y; d_out[2] = out.z;
     *reflected = refl;
     return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Absorption inside glass (Beer-Lambert): over a path length t in a    */
+/* medium of absorption coefficient sigma the weight drops by            */
+/* exp(-sigma t).  sigma is given at 450, 550 and 650 nm and taken       */
+/* piecewise linear in lambda in between, constant outside.             */
+/* ------------------------------------------------------------------ */
+
+/* exp(-x) for x >= 0 with its own arithmetic, so that both sides of a
+ * parity check compute the same bits: Cody-Waite reduction
+ * x = k ln2 + r with |r| <= ln2 / 2 (ln2 split in a 16-bit head and a
+ * tail, so k * head is exact), e^-r from its degree-7 Taylor polynomial
+ * (truncation below 6e-9 relative on that interval), then the exact
+ * scaling by 2^-k.  Results below 2^-125 are returned as 0. */
+float sco_exp_neg(float x) {
+    if (!(x > 0.0f)) return 1.0f;
+    if (x > 87.0f) return 0.0f;
+    float kf = floorf(x * 1.44269504f + 0.5f);
+    int k = (int)kf;
+    float r = (x - kf * 0.693145751953125f) - kf * 1.428606765330187e-06f;
+    float q = -r;
+    float p = (float)(1.0 / 5040.0) + q * (float)(1.0 / 40320.0);
+    p = (float)(1.0 / 720.0) + q * p;
+    p = (float)(1.0 / 120.0) + q * p;
+    p = (float)(1.0 / 24.0) + q * p;
+    p = (float)(1.0 / 6.0) + q * p;
+    p = 0.5f + q * p;
+    p = 1.0f + q * p;
+    p = 1.0f + q * p;
+    return p * i2f_bits((127 - k) << 23);
+}
+
+static float sigma_at(const sco_material* m, float lam) {
+    if (lam <= 450.0f) return m->sigma[0];
+    if (lam >= 650.0f) return m->sigma[2];
+    if (lam < 550.0f) return m->sigma[0] + (m->sigma[1] - m->sigma[0]) * ((lam - 450.0f) / 100.0f);
+    return m->sigma[1] + (m->sigma[2] - m->sigma[1]) * ((lam - 550.0f) / 100.0f);
+}
+
+/* ------------------------------------------------------------------ */
+/* Nested and overlapping dielectrics (Schmidt and Budge, "Simple Nested */
+/* Dielectrics in Ray Traced Images", J. Graphics Tools 7(2), 2002).     */
+/* A path carries the set of dielectric objects it is inside, at most    */
+/* MEDIA_CAP of them.  The medium at a point is the member of highest    */
+/* priority (ties: the larger object id).  A surface of object k is a    */
+/* real interface only if k is that member on the surface's inner side;  */
+/* otherwise it lies inside a medium of higher priority and the path     */
+/* crosses it unchanged, only the set changes (a false hit).  At a real  */
+/* interface the index on the outer side is that of the medium left      */
+/* when k is removed (air, n = 1, if none).  Refraction updates the set; */
+/* reflection keeps it.  When the set is full, an object of lower        */
+/* priority than every member is not added, else the lowest member is    */
+/* replaced.                                                            */
+/* ------------------------------------------------------------------ */
+
+#define MEDIA_CAP 4
+typedef struct { uint32_t id[MEDIA_CAP]; uint32_t n; } media_t;
+
+static uint64_t med_key(const sco_scene* s, uint32_t k) { return ((uint64_t)s->mat[k].priority << 32) | k; }
+
+static uint32_t med_top(const sco_scene* s, const media_t* L) {
+    uint32_t best = 0;
+    for (uint32_t i = 0; i < L->n; i++)
+        if (best == 0 || med_key(s, L->id[i]) > med_key(s, best)) best = L->id[i];
+    return best;
+}
+
+static void med_add(const sco_scene* s, media_t* L, uint32_t k) {
+    for (uint32_t i = 0; i < L->n; i++) if (L->id[i] == k) return;
+    if (L->n < MEDIA_CAP) { L->id[L->n++] = k; return; }
+    uint32_t lo = 0;
+    for (uint32_t i = 1; i < MEDIA_CAP; i++) if (med_key(s, L->id[i]) < med_key(s, L->id[lo])) lo = i;
+    if (med_key(s, k) > med_key(s, L->id[lo])) L->id[lo] = k;
+}
+
+static void med_remove(media_t* L, uint32_t k) {
+    for (uint32_t i = 0; i < L->n; i++)
+        if (L->id[i] == k) { L->id[i] = L->id[L->n - 1]; L->n--; return; }
+}
+
+typedef struct { int real; float n1, n2; media_t after; } iface_t;
+
+static void interface_at(const sco_scene* s, const media_t* L, uint32_t k, int entering, float lam, iface_t* I) {
+    media_t in = *L, out = *L;
+    med_add(s, &in, k);
+    med_remove(&out, k);
+    I->after = entering ? in : out;
+    I->real = med_top(s, &in) == k;
+    uint32_t o = med_top(s, &out);
+    const sco_material* mk_ = &s->mat[k];
+    float nk = cauchy_n(mk_->cauchy_a, mk_->cauchy_b, lam);
+    float no = o ? cauchy_n(s->mat[o].cauchy_a, s->mat[o].cauchy_b, lam) : 1.0f;
+    I->n1 = entering ? no : nk;
+    I->n2 = entering ? nk : no;
+}
+
+/* Weight left after a segment of length t in the current medium. */
+static float medium_weight(const sco_scene* s, const media_t* L, float lam, float t) {
+    uint32_t o = med_top(s, L);
+    if (!o) return 1.0f;
+    float sg = sigma_at(&s->mat[o], lam);
+    if (!(sg > 0.0f)) return 1.0f;
+    return sco_exp_neg(sg * t);
+}
+
+int sco_media_step(const sco_scene* s, const uint32_t* ids, uint32_t n, uint32_t k, int entering, float lam,
+                   uint32_t* ids_after, uint32_t* n_after, int* real, float* n1, float* n2) {
+    if (!s || !s->mat || n > MEDIA_CAP || k == 0 || k >= s->n_mat) return -1;
+    media_t L;
+    L.n = n;
+    for (uint32_t i = 0; i < n; i++) {
+        if (ids[i] == 0 || ids[i] >= s->n_mat) return -1;
+        L.id[i] = ids[i];
+    }
+    iface_t I;
+    interface_at(s, &L, k, entering, lam, &I);
+    for (uint32_t i = 0; i < I.after.n; i++) ids_after[i] = I.after.id[i];
+    *n_after = I.after.n;
+    *real = I.real;
+    *n1 = I.n1;
+    *n2 = I.n2;
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -753,12 +882,15 @@ static float trace_path(pt_ctx* X, v3 o, v3 d, uint32_t pix, uint32_t sample, ui
     const derived_t* D = X->D;
     float T = 1.0f, L = 0.0f;
     int diffuse_seen = 0;
+    media_t med;
+    med.n = 0;   /* the camera is in air */
     for (uint32_t depth = 1; depth <= X->max_depth; depth++) {
         float t, u, v;
         uint32_t prim;
         closest_one(s, X->bvh, o, d, &t, &prim, &u, &v);
         X->segments++;
         if (prim == 0xffffffffu) break;
+        T = T * medium_weight(s, &med, lam, t);
         uint32_t obj = s->tri_obj[prim];
         const sco_material* m = &s->mat[obj];
         frame_t f;
@@ -768,10 +900,18 @@ static float trace_path(pt_ctx* X, v3 o, v3 d, uint32_t pix, uint32_t sample, ui
             break;
         }
         if (m->type == 1) {
+            iface_t I;
+            interface_at(s, &med, obj, f.entering, lam, &I);
+            if (!I.real) {
+                med = I.after;
+                o = offset_ray(f.P, vneg(f.Nf));
+                continue;
+            }
             uint32_t r[4];
             rng_cam(X->seed, pix, sample, depth, 1, slot, r);
             v3 nd; int refl;
-            if (!dielectric_dir(&f, d, lam, m->cauchy_a, m->cauchy_b, u01(r[2]), &nd, &refl, NULL)) break;
+            if (!dielectric_dir(&f, d, I.n1, I.n2, u01(r[2]), &nd, &refl, NULL)) break;
+            if (!refl) med = I.after;
             o = offset_ray(f.P, refl ? f.Nf : vneg(f.Nf));
             d = nd;
             continue;
@@ -809,6 +949,7 @@ static float trace_path(pt_ctx* X, v3 o, v3 d, uint32_t pix, uint32_t sample, ui
                 if (cosx > 0.0f) {
                     contrib = ((((T * rho) * INV_PI_F) * lp[3]) * cosx) / r2;
                     contrib = contrib * (float)D->n_entries;
+                    contrib = contrib * medium_weight(s, &med, lam, dist);
                     tmax = dist;
                     shoot = 1;
                 }
@@ -827,6 +968,7 @@ static float trace_path(pt_ctx* X, v3 o, v3 d, uint32_t pix, uint32_t sample, ui
                     float le = s->mat[s->tri_obj[lprim]].le;
                     contrib = ((((((T * rho) * INV_PI_F) * le) * cosx) * cosl) / r2) * D->a_tot;
                     contrib = contrib * (float)D->n_entries;
+                    contrib = contrib * medium_weight(s, &med, lam, dist);
                     tmax = dist * 0.9999f;
                     excl = lprim;
                     shoot = 1;
@@ -863,6 +1005,13 @@ static int check_common(const sco_scene* s, const sco_wavelengths* wl, uint32_t 
     if (wl->mode == 1 && (wl->bins == 0 || !(wl->hi > wl->lo))) return -1;
     if (wl->mode > 1) return -1;
     for (uint32_t i = 0; i < s->nt; i++) if (s->tri_obj[i] == 0 || s->tri_obj[i] >= s->n_mat) return -1;
+    for (uint32_t k = 1; k < s->n_mat; k++) {
+        const sco_material* m = &s->mat[k];
+        if (m->type != 1) continue;
+        for (int c = 0; c < 3; c++) if (!(m->sigma[c] >= 0.0f && m->sigma[c] <= FLT_MAX)) return -1;
+        if (!(m->roughness >= 0.0f && m->roughness <= 1.0f)) return -1;
+        if (m->roughness != 0.0f) return -1;
+    }
     return 0;
 }
 
@@ -1114,6 +1263,8 @@ int sco_trace_photons(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons
         }
         v3 d = om;
         uint32_t spec = 0;
+        media_t med;
+        med.n = 0;   /* lights are in air */
         int outcome = SCO_PH_TRUNCATED;
         for (uint32_t depth = 1; depth <= max_depth; depth++) {
             float t, u, v;
@@ -1121,18 +1272,27 @@ int sco_trace_photons(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons
             closest_one(s, bvh, o, d, &t, &prim, &u, &v);
             st.segments++;
             if (prim == 0xffffffffu) { outcome = SCO_PH_ESCAPED; break; }
+            phi = phi * medium_weight(s, &med, lam, t);
             uint32_t obj = s->tri_obj[prim];
             const sco_material* mt = &s->mat[obj];
             frame_t f;
             hit_frame(s, prim, u, v, d, &f);
             if (mt->type == 2) { outcome = SCO_PH_ABSORBED; break; }
             if (mt->type == 1) {
+                iface_t I;
+                interface_at(s, &med, obj, f.entering, lam, &I);
+                if (!I.real) {
+                    med = I.after;
+                    o = offset_ray(f.P, vneg(f.Nf));
+                    continue;
+                }
                 uint32_t r1[4];
                 rng_ph(seed, p, depth, 1, r1);
                 v3 nd; int refl;
-                if (!dielectric_dir(&f, d, lam, mt->cauchy_a, mt->cauchy_b, u01(r1[2]), &nd, &refl, NULL)) {
+                if (!dielectric_dir(&f, d, I.n1, I.n2, u01(r1[2]), &nd, &refl, NULL)) {
                     outcome = SCO_PH_LOST; break;
                 }
+                if (!refl) med = I.after;
                 o = offset_ray(f.P, refl ? f.Nf : vneg(f.Nf));
                 d = nd;
                 spec++;

@@ -18,7 +18,10 @@
  *     traced as spectral paths through smooth dielectric meshes with
  *     Cauchy dispersion, exact Fresnel and total internal reflection, next
  *     event estimation on diffuse surfaces, and a photon-traced caustic map
- *     on a receiver plane.
+ *     on a receiver plane;
+ *   - glass colour and thickness (Sec. III-C lists both among the scene
+ *     variations) as Beer-Lambert absorption inside each dielectric, with
+ *     nested and overlapping dielectrics resolved by priority.
  *
  * All pointers are host pointers.  Functions return 0 on success and a
  * negative value on invalid arguments.
@@ -37,7 +40,9 @@ typedef struct {
     float rho_a, rho_b;
     float cauchy_a, cauchy_b;  /* n(lambda) = a + b / lambda_um^2 */
     float le;                  /* emitted radiance (front face only) */
-    float pad;
+    uint32_t priority;         /* dielectric: nesting priority (ties: larger object id wins) */
+    float sigma[3];            /* dielectric: absorption coefficient (1/m) at 450, 550, 650 nm */
+    float roughness;           /* dielectric: GGX alpha; 0 = smooth */
 } sco_material;
 
 typedef struct {
@@ -123,6 +128,16 @@ int sco_dielectric(const float d[3], const float Ng[3], const float Ns[3], const
                    float lambda_nm, float ca, float cb, float u_fresnel,
                    float o_out[3], float d_out[3], int* reflected, float* R_out);
 float sco_fresnel(float n1, float n2, float ci, float ct);
+/* exp(-x) for x >= 0 in the oracle's own float arithmetic (Beer-Lambert
+ * weights); 1 for x <= 0, 0 for x > 87. */
+float sco_exp_neg(float x);
+/* One surface crossing of nested dielectrics: the set ids[0..n) of media
+ * the path is inside, a hit on dielectric object k from its front
+ * (entering = 1) or back.  Returns the set after crossing, whether the
+ * surface is a real interface, and the indices n1 (the side the path comes
+ * from) and n2 (across) at lambda. */
+int sco_media_step(const sco_scene* s, const uint32_t* ids, uint32_t n, uint32_t k, int entering, float lam,
+                   uint32_t* ids_after, uint32_t* n_after, int* real, float* n1, float* n2);
 void sco_camera_ray(const sco_camera* cam, uint32_t x, uint32_t y, float jx, float jy, float o[3], float d[3]);
 
 /* Photon pass over photon indices [p0, p1) of a pass of n_photons.

@@ -49,7 +49,8 @@ class ScError(RuntimeError):
 
 class Material(C.Structure):
     _fields_ = [("type", C.c_uint32), ("albedo_mode", C.c_uint32), ("rho_a", C.c_float), ("rho_b", C.c_float),
-                ("cauchy_a", C.c_float), ("cauchy_b", C.c_float), ("le", C.c_float), ("pad", C.c_float)]
+                ("cauchy_a", C.c_float), ("cauchy_b", C.c_float), ("le", C.c_float), ("priority", C.c_uint32),
+                ("sigma", C.c_float * 3), ("roughness", C.c_float)]
 
 
 class Scene(C.Structure):

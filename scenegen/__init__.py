@@ -34,11 +34,15 @@ ALBEDO_TEXTURE = 2
 WL_FIXED = 0
 WL_UNIFORM = 1
 
+# One record per object (48 bytes).  Dielectrics also carry a nesting
+# priority, absorption coefficients in 1/m at 450, 550 and 650 nm, and a
+# GGX roughness (0 = smooth); the other types ignore those fields.
 MATERIAL_DTYPE = np.dtype([
     ("type", "<u4"), ("albedo_mode", "<u4"),
     ("rho_a", "<f4"), ("rho_b", "<f4"),
     ("cauchy_a", "<f4"), ("cauchy_b", "<f4"),
-    ("le", "<f4"), ("pad", "<f4"),
+    ("le", "<f4"), ("priority", "<u4"),
+    ("sigma", "<f4", (3,)), ("roughness", "<f4"),
 ])
 
 
@@ -623,3 +627,48 @@ def ball_lens(level: int, receiver_z: float, light_dist: float = 1.0e4, aperture
     scene.targets_obj = np.array([2], dtype=np.uint32)
     scene.targets_sphere = np.array([[0.0, 0.0, 0.0, aperture]], dtype=np.float32)
     return scene
+
+
+def glass(n: float = 1.5, b: float = 0.0, sigma=(0.0, 0.0, 0.0), priority: int = 0, roughness: float = 0.0):
+    """Dielectric material: Cauchy n(lambda) = n + b / lambda_um^2,
+    absorption coefficients (1/m) at 450, 550 and 650 nm, nesting priority
+    and GGX roughness."""
+    return dict(type=MAT_DIELECTRIC, cauchy_a=n, cauchy_b=b, sigma=np.asarray(sigma, dtype=np.float32),
+                priority=priority, roughness=roughness)
+
+
+def slab_stack(layers, receiver_z: float = 0.0, light_dist: float = 1.0e4, aperture: float = 0.05,
+               wc: int = 64, ext: float = 1.0):
+    """Axis-aligned glass boxes centred on the z axis, given as
+    (size_xyz, z_centre, material) from the outermost in, under a distant
+    point light on +z.  The photon target is a sphere of radius
+    ``aperture`` at the centre of the first box, so photons form a beam at
+    normal incidence.  A diffuse receiver square of side ``ext`` lies at
+    ``receiver_z`` below the boxes."""
+    b = SceneBuilder()
+    h = ext * 0.5
+    plane = quad((-h, -h, receiver_z), (h, -h, receiver_z), (h, h, receiver_z), (-h, h, receiver_z), (0, 0, 1))
+    recv = b.add(plane, dict(type=MAT_DIFFUSE, albedo_mode=ALBEDO_CONST, rho_a=0.5))
+    for size, zc, mat in layers:
+        m = box(size)
+        b.add(Mesh(m.V + np.array([0.0, 0.0, zc]), m.I, m.VN), mat)
+    b.point_light((0.0, 0.0, light_dist), 1.0)
+    scene = b.build(Receiver(recv, wc, wc, -h, -h, ext, ext), name="slabs")
+    scene.targets_obj = np.array([2], dtype=np.uint32)
+    scene.targets_sphere = np.array([[0.0, 0.0, layers[0][1], aperture]], dtype=np.float32)
+    return scene
+
+
+def slab_over_light(thickness: float, mat: dict, le: float = 1.0, w: int = 8, h: int = 8):
+    """A 2 x 2 m glass box of the given thickness (bottom face at z = 0.5)
+    over an upward-facing emitter at z = 0, seen from straight above by a
+    far camera (eye at z = 1000, 0.01 degree field), so every camera ray
+    meets the glass at normal incidence to within 1e-4 rad."""
+    b = SceneBuilder()
+    light = quad((-2, -2, 0), (2, -2, 0), (2, 2, 0), (-2, 2, 0), (0, 0, 1))
+    b.add(light, dict(type=MAT_EMISSIVE, le=le))
+    m = box((2.0, 2.0, thickness))
+    b.add(Mesh(m.V + np.array([0.0, 0.0, 0.5 + 0.5 * thickness]), m.I, m.VN), mat)
+    scene = b.build(None, name="slab-light")
+    cam = look_at((0.0, 0.0, 1000.0), (0.0, 0.0, 0.0), (0, 1, 0), 0.01, w, h)
+    return scene, cam
