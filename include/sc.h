@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SC_ABI_VERSION 1u
+#define SC_ABI_VERSION 2u
 
 typedef int32_t sc_status;
 #define SC_OK 0
@@ -59,9 +59,22 @@ typedef struct sc_ctx sc_ctx;
 typedef struct sc_bvh sc_bvh;
 
 /* Materials: one per object id.  DIFFUSE is Lambertian (two-sided);
- * DIELECTRIC is smooth glass in air with n(lambda) = cauchy_a +
- * cauchy_b / lambda_um^2 (dispersion, Abstract); EMISSIVE emits radiance
- * `le` from its front face (counter-clockwise winding). */
+ * DIELECTRIC is smooth glass with n(lambda) = cauchy_a + cauchy_b /
+ * lambda_um^2 (dispersion, Abstract); EMISSIVE emits radiance `le` from
+ * its front face (counter-clockwise winding).
+ *
+ * Glass colour and thickness (scene variations of Sec. III-C): a segment
+ * of length t inside a dielectric keeps exp(-sigma(lambda) t) of its
+ * weight (Beer-Lambert), sigma given in 1/m at 450, 550 and 650 nm,
+ * piecewise linear in lambda between them and constant outside; all zero
+ * is clear glass.  Nested and overlapping dielectrics follow Schmidt and
+ * Budge (J. Graphics Tools 7(2), 2002): each camera path and photon keeps
+ * the set of dielectrics it is inside (at most 4); the medium at a point
+ * is the member of highest `priority` (ties: larger object id); a surface
+ * is an interface only where its object is that medium on the inner side,
+ * and there the outer index is that of the next medium (air if none);
+ * other surfaces are crossed unchanged.  Cameras and lights are in air.
+ * `roughness` is reserved for rough glass and must be 0. */
 #define SC_MAT_DIFFUSE 0u
 #define SC_MAT_DIELECTRIC 1u
 #define SC_MAT_EMISSIVE 2u
@@ -74,8 +87,10 @@ typedef struct {
     float rho_a, rho_b;
     float cauchy_a, cauchy_b;
     float le;
-    float pad;
-} sc_material; /* 32 bytes */
+    uint32_t priority;  /* dielectric nesting priority */
+    float sigma[3];     /* dielectric absorption (1/m) at 450, 550, 650 nm; finite, >= 0 */
+    float roughness;    /* 0 */
+} sc_material; /* 48 bytes */
 
 typedef struct {
     const float* V;          /* device [nv][3] vertex positions */
@@ -83,7 +98,7 @@ typedef struct {
     const float* VN;         /* device [nv][3] unit vertex normals, or NULL for flat shading */
     const uint32_t* tri_obj; /* device [nt] object id of each triangle, 1..n_mat-1 */
     uint32_t nv, nt;
-    const sc_material* mat;  /* host [n_mat]; index = object id, row 0 unused */
+    const sc_material* mat;  /* host [n_mat], n_mat <= 65536; index = object id, row 0 unused */
     uint32_t n_mat;
     const float* point_lights; /* host [n_pl][4]: x, y, z, intensity (W/sr, flat spectrum) */
     uint32_t n_pl;

@@ -43,6 +43,9 @@ SC_OPT_QUEUE_CAP = 3
 SC_OPT_STAGED_DEPTH = 4
 
 
+ABI_VERSION = 2   # must match SC_ABI_VERSION in include/sc.h
+
+
 class ScError(RuntimeError):
     pass
 
@@ -174,6 +177,8 @@ def load(path: str = LIB_PATH):
         fn = getattr(L, name)
         if name not in ("sc_abi_version", "sc_last_error"):
             fn.restype = i32
+    if L.sc_abi_version() != ABI_VERSION:
+        raise ScError(f"{path} has ABI version {L.sc_abi_version()}, the binding expects {ABI_VERSION}: rebuild it")
     _lib = L
     return L
 

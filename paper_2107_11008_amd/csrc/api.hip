@@ -2,6 +2,7 @@
 // tables, and dispatch to the GPU passes.
 #pragma clang fp contract(off)
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -150,9 +151,17 @@ sc_status check_scene(const sc_scene* sc) {
     if (sc->nt == 0 || sc->nv == 0) return set_error(SC_EINVAL, "scene has no triangles");
     if (sc->nt > (1u << 28) - 1) return set_error(SC_EUNSUPPORTED, "more than 2^28 - 1 triangles");
     if (sc->n_mat < 2) return set_error(SC_EINVAL, "n_mat must be >= 2 (row 0 is unused)");
+    if (sc->n_mat > 65536u) return set_error(SC_EUNSUPPORTED, "more than 65536 materials (object ids are 16-bit in media sets)");
     for (uint32_t i = 1; i < sc->n_mat; ++i) {
         const sc_material& m = sc->mat[i];
         if (m.type > SC_MAT_EMISSIVE) return set_error(SC_EINVAL, "unknown material type");
+        if (m.type == SC_MAT_DIELECTRIC) {
+            for (int c = 0; c < 3; ++c)
+                if (!(m.sigma[c] >= 0.0f && m.sigma[c] <= FLT_MAX))
+                    return set_error(SC_EINVAL, "dielectric absorption must be finite and >= 0");
+            if (!(m.roughness >= 0.0f && m.roughness <= 1.0f)) return set_error(SC_EINVAL, "roughness must be in [0, 1]");
+            if (m.roughness != 0.0f) return set_error(SC_EUNSUPPORTED, "rough dielectrics are not supported");
+        }
         if (m.type == SC_MAT_DIFFUSE && m.albedo_mode > SC_ALBEDO_TEXTURE) return set_error(SC_EINVAL, "unknown albedo mode");
         if (m.type == SC_MAT_DIFFUSE && m.albedo_mode == SC_ALBEDO_TEXTURE && !sc->tex)
             return set_error(SC_EINVAL, "texture albedo without a texture");

@@ -293,13 +293,15 @@ __device__ __forceinline__ float fresnel(float n1, float n2, float ci, float ct)
     return 0.5f * (rs * rs + rp * rp);
 }
 
-__device__ __forceinline__ bool dielectric(const Frame& f, F3 d, float lambda_nm, float ca, float cb, float uF,
-                                           F3& out, bool& refl) {
+// two-term Cauchy law, lambda in nm
+__device__ __forceinline__ float cauchy_index(float ca, float cb, float lambda_nm) {
     const float l = lambda_nm * 0.001f;
-    const float n = ca + cb / (l * l);
-    float n1, n2, eta;
-    if (f.entering) { n1 = 1.0f; n2 = n; eta = 1.0f / n; }
-    else { n1 = n; n2 = 1.0f; eta = n; }
+    return ca + cb / (l * l);
+}
+
+// n1: index on the side the ray comes from, n2: index across the surface
+__device__ __forceinline__ bool dielectric(const Frame& f, F3 d, float n1, float n2, float uF, F3& out, bool& refl) {
+    const float eta = n1 / n2;
     F3 N = f.Ns;
     float ci = -dot(d, N);
     bool geometric = false;
@@ -336,6 +338,41 @@ __device__ __forceinline__ bool dielectric(const Frame& f, F3 d, float lambda_nm
         geometric = true;
     }
     return false;
+}
+
+// ---------------------------------------------------------------- absorbing glass
+// Beer-Lambert: a path segment of length t inside a medium keeps
+// exp(-sigma t) of its weight.  sigma is given at 450, 550 and 650 nm and
+// taken piecewise linear in lambda between them, constant outside.
+
+// exp(-x) for x >= 0 without libm: Cody-Waite reduction x = k ln2 + r,
+// |r| <= ln2/2 (ln2 split into a 16-bit head, exact when multiplied by k,
+// and a tail); e^-r from its degree-7 Taylor polynomial (truncation below
+// 6e-9 relative); exact scaling by 2^-k, which stays a normal number for
+// x <= 87.  1 for x <= 0, 0 for x > 87.
+__device__ __forceinline__ float exp_neg(float x) {
+    if (!(x > 0.0f)) return 1.0f;
+    if (x > 87.0f) return 0.0f;
+    const float kf = floorf(x * 1.44269504f + 0.5f);
+    const int k = (int)kf;
+    const float r = (x - kf * 0.693145751953125f) - kf * 1.428606765330187e-06f;
+    const float q = -r;
+    float p = (float)(1.0 / 5040.0) + q * (float)(1.0 / 40320.0);
+    p = (float)(1.0 / 720.0) + q * p;
+    p = (float)(1.0 / 120.0) + q * p;
+    p = (float)(1.0 / 24.0) + q * p;
+    p = (float)(1.0 / 6.0) + q * p;
+    p = 0.5f + q * p;
+    p = 1.0f + q * p;
+    p = 1.0f + q * p;
+    return p * __int_as_float((127 - k) << 23);
+}
+
+__device__ __forceinline__ float absorption(const sc_material& m, float lam) {
+    if (lam <= 450.0f) return m.sigma[0];
+    if (lam >= 650.0f) return m.sigma[2];
+    if (lam < 550.0f) return m.sigma[0] + (m.sigma[1] - m.sigma[0]) * ((lam - 450.0f) / 100.0f);
+    return m.sigma[1] + (m.sigma[2] - m.sigma[1]) * ((lam - 550.0f) / 100.0f);
 }
 
 // ---------------------------------------------------------------- scene lookups

@@ -303,10 +303,93 @@ __device__ __forceinline__ bool trace_any(const DevScene& S, F3 o, F3 d, float t
 }
 
 // ---------------------------------------------------------------- camera paths
+// ---------------------------------------------------------------- nested dielectrics
+// Each path carries the set of dielectric objects it is inside (the
+// nested-dielectric rules of Schmidt and Budge, J. Graphics Tools 7(2),
+// 2002): up to kMedia object ids of 16 bits in one 64-bit word, ordered by
+// descending (priority, object id), unused entries 0.  The medium at the
+// path is the first entry.  A surface of object k is a real interface only
+// where k heads the set on its inner side; elsewhere it lies inside a
+// medium of higher priority and the path crosses it unchanged, only the
+// set changes.  At a real interface the index on the outer side is that of
+// the set's head once k is removed (air, n = 1, if none).  Refraction takes
+// the set across the surface, reflection keeps the old one.  A full set
+// drops its last entry to admit a higher-ranked object and ignores a lower
+// one.
+constexpr int kMedia = 4;
+
+__device__ __forceinline__ uint64_t media_key(const DevScene& S, uint32_t id) {
+    return ((uint64_t)S.mat[id].priority << 32) | id;
+}
+__device__ __forceinline__ uint32_t media_entry(uint64_t M, int i) { return (uint32_t)(M >> (16 * i)) & 0xffffu; }
+
+__device__ __forceinline__ uint64_t media_add(const DevScene& S, uint64_t M, uint32_t k) {
+    const uint64_t kk = media_key(S, k);
+    uint32_t e[kMedia];
+    int pos = 0;
+    for (int i = 0; i < kMedia; ++i) {
+        e[i] = media_entry(M, i);
+        if (e[i] == k) return M;
+        if (e[i] != 0u && media_key(S, e[i]) > kk) pos = i + 1;
+    }
+    if (pos == kMedia) return M;
+    uint64_t out = 0ull;
+    for (int j = 0, i = 0; j < kMedia; ++j) {
+        const uint32_t v = j == pos ? k : e[i++];
+        out |= (uint64_t)v << (16 * j);
+    }
+    return out;
+}
+
+__device__ __forceinline__ uint64_t media_remove(uint64_t M, uint32_t k) {
+    for (int i = 0; i < kMedia; ++i) {
+        if (media_entry(M, i) == k) {
+            const uint64_t low = M & ((1ull << (16 * i)) - 1ull);
+            const uint64_t high = i + 1 < kMedia ? (M >> (16 * (i + 1))) << (16 * i) : 0ull;
+            return low | high;
+        }
+    }
+    return M;
+}
+
+struct Crossing {
+    bool real;        // a true interface (else the path passes straight on)
+    float n1, n2;     // index on the incoming side and across
+    uint64_t after;   // the set on the far side
+};
+
+__device__ __forceinline__ Crossing media_cross(const DevScene& S, uint64_t M, uint32_t k, bool entering, float lam) {
+    const uint64_t in = media_add(S, M, k), out = media_remove(M, k);
+    Crossing c;
+    c.after = entering ? in : out;
+    c.real = media_entry(in, 0) == k;
+    const uint32_t o = media_entry(out, 0);
+    const sc_material mk = S.mat[k];
+    const float nk = cauchy_index(mk.cauchy_a, mk.cauchy_b, lam);
+    float no = 1.0f;
+    if (o != 0u) {
+        const sc_material mo = S.mat[o];
+        no = cauchy_index(mo.cauchy_a, mo.cauchy_b, lam);
+    }
+    c.n1 = entering ? no : nk;
+    c.n2 = entering ? nk : no;
+    return c;
+}
+
+// weight kept over a segment of length t in the medium heading set M
+__device__ __forceinline__ float medium_weight(const DevScene& S, uint64_t M, float lam, float t) {
+    const uint32_t o = media_entry(M, 0);
+    if (o == 0u) return 1.0f;
+    const float sg = absorption(S.mat[o], lam);
+    if (!(sg > 0.0f)) return 1.0f;
+    return exp_neg(sg * t);
+}
+
 struct CamPath {
     F3 o, d;
     float T, L, lam;
     uint32_t flags;   // bit 0: a diffuse vertex was seen
+    uint64_t med;     // media set (the camera is in air)
 };
 
 struct ShadowReq {
@@ -328,6 +411,7 @@ __device__ __forceinline__ CamPath camera_start(const sc_camera& cam, const Wave
     P.T = 1.0f;
     P.L = 0.0f;
     P.flags = 0u;
+    P.med = 0ull;
     return P;
 }
 
@@ -338,19 +422,29 @@ __device__ __forceinline__ void camera_emission(const DevScene& S, const HitRec&
     F3 p0, p1, p2;
     tri_vertices(S, h.prim, p0, p1, p2);
     const F3 Ng = normalize(cross(p1 - p0, p2 - p0));
-    if (dot(P.d, Ng) < 0.0f) P.L = P.L + P.T * m.le;
+    const float T = P.T * medium_weight(S, P.med, P.lam, h.t);
+    if (dot(P.d, Ng) < 0.0f) P.L = P.L + T * m.le;
 }
 
-// dielectric hit: reflect or refract; false if the path ends here
+// dielectric hit: absorption over the segment, then reflect, refract or
+// (a surface hidden inside a higher-priority medium) pass straight on;
+// false if the path ends here
 __device__ __forceinline__ bool camera_dielectric(const DevScene& S, uint64_t seed, uint32_t pix, uint32_t sample,
                                                   uint32_t slot, uint32_t depth, uint32_t max_depth, const HitRec& h,
                                                   CamPath& P) {
+    P.T = P.T * medium_weight(S, P.med, P.lam, h.t);
     const Frame f = hit_frame(S, h.prim, h.u, h.v, P.d);
-    const sc_material m = S.mat[S.tri_obj[h.prim]];
+    const Crossing c = media_cross(S, P.med, S.tri_obj[h.prim], f.entering, P.lam);
+    if (!c.real) {
+        P.med = c.after;
+        P.o = offset_ray(f.P, neg(f.Nf));
+        return depth < max_depth;
+    }
     const U4 r = rng_camera(seed, pix, sample, depth, 1, slot);
     F3 nd;
     bool refl;
-    if (!dielectric(f, P.d, P.lam, m.cauchy_a, m.cauchy_b, unit(r.c), nd, refl)) return false;
+    if (!dielectric(f, P.d, c.n1, c.n2, unit(r.c), nd, refl)) return false;
+    if (!refl) P.med = c.after;
     P.o = offset_ray(f.P, refl ? f.Nf : neg(f.Nf));
     P.d = nd;
     return depth < max_depth;
@@ -367,7 +461,7 @@ __device__ __forceinline__ bool camera_diffuse(const DevScene& S, const WaveDev&
     const Frame f = hit_frame(S, h.prim, h.u, h.v, P.d);
     const sc_material m = S.mat[obj];
     const float rho = albedo(S, m, f.P);
-    const float T = P.T;
+    const float T = P.T * medium_weight(S, P.med, P.lam, h.t);
     P.flags = P.flags | 1u;
     const F3 os = offset_ray(f.P, f.Nf);
     sr.shoot = false;
@@ -395,6 +489,7 @@ __device__ __forceinline__ bool camera_diffuse(const DevScene& S, const WaveDev&
             if (cosx > 0.0f) {
                 float contrib = ((((T * rho) * kInvPi) * lp[3]) * cosx) / r2;
                 contrib = contrib * (float)S.n_entries;
+                contrib = contrib * medium_weight(S, P.med, P.lam, dist);
                 sr = ShadowReq{os, om, dist, contrib, 0xffffffffu, true};
             }
         } else {
@@ -412,6 +507,7 @@ __device__ __forceinline__ bool camera_diffuse(const DevScene& S, const WaveDev&
                 const float le = S.mat[S.tri_obj[lprim]].le;
                 float contrib = ((((((T * rho) * kInvPi) * le) * cosx) * cosl) / r2) * S.a_tot;
                 contrib = contrib * (float)S.n_entries;
+                contrib = contrib * medium_weight(S, P.med, P.lam, dist);
                 sr = ShadowReq{os, om, dist * 0.9999f, contrib, lprim, true};
             }
         }
@@ -486,6 +582,7 @@ struct PhotonPath {
     F3 o, d;
     float phi, lam;
     uint32_t slot, spec;
+    uint64_t med;     // media set (lights are in air)
 };
 
 // 1 - cos(theta) of the cone subtended by a sphere of squared radius rr at
@@ -586,6 +683,7 @@ __device__ __forceinline__ bool photon_emit(const DevScene& S, const WaveDev& wl
     ph.lam = lam;
     ph.slot = slot;
     ph.spec = 0u;
+    ph.med = 0ull;
     return alive;
 }
 
@@ -599,6 +697,7 @@ __device__ __forceinline__ bool photon_event(const DevScene& S, const WaveDev& w
         outcome = SC_PH_ESCAPED;
         return false;
     }
+    ph.phi = ph.phi * medium_weight(S, ph.med, ph.lam, h.t);
     const uint32_t obj = S.tri_obj[h.prim];
     const sc_material m = S.mat[obj];
     const Frame f = hit_frame(S, h.prim, h.u, h.v, ph.d);
@@ -607,13 +706,22 @@ __device__ __forceinline__ bool photon_event(const DevScene& S, const WaveDev& w
         return false;
     }
     if (m.type == SC_MAT_DIELECTRIC) {
+        const Crossing c = media_cross(S, ph.med, obj, f.entering, ph.lam);
+        if (!c.real) {
+            ph.med = c.after;
+            ph.o = offset_ray(f.P, neg(f.Nf));
+            if (depth < max_depth) return true;
+            outcome = SC_PH_TRUNCATED;
+            return false;
+        }
         const U4 r = rng_photon(seed, p, depth, 1);
         F3 nd;
         bool refl;
-        if (!dielectric(f, ph.d, ph.lam, m.cauchy_a, m.cauchy_b, unit(r.c), nd, refl)) {
+        if (!dielectric(f, ph.d, c.n1, c.n2, unit(r.c), nd, refl)) {
             outcome = SC_PH_LOST;
             return false;
         }
+        if (!refl) ph.med = c.after;
         ph.o = offset_ray(f.P, refl ? f.Nf : neg(f.Nf));
         ph.d = nd;
         ph.spec = ph.spec + 1u;

@@ -69,6 +69,7 @@ struct PathState {
     float* L;                            // accumulated radiance
     float* lambda;
     uint32_t* flags;                     // bit0: a diffuse vertex was seen
+    uint64_t* med;                       // media set (nested dielectrics)
     // hit of the current ray
     float *t, *u, *v;
     uint32_t* prim;
@@ -84,6 +85,7 @@ struct PhotonState {
     float* lambda;
     uint32_t* slot;   // map channel
     uint32_t* spec;   // dielectric events so far
+    uint64_t* med;    // media set (nested dielectrics)
     float *t, *u, *v;
     uint32_t* prim;
 };

@@ -245,6 +245,7 @@ __device__ __forceinline__ CamPath load_path(const PathState& P, uint32_t pid) {
     c.L = P.L[pid];
     c.lam = P.lambda[pid];
     c.flags = P.flags[pid];
+    c.med = P.med[pid];
     return c;
 }
 __device__ __forceinline__ void store_ray(const PathState& P, uint32_t pid, const CamPath& c) {
@@ -265,6 +266,7 @@ __global__ void k_raygen(CamInfo ci, WaveDev wl, PathState P, uint32_t n, uint32
         P.L[pid] = c.L;
         P.lambda[pid] = c.lam;
         P.flags[pid] = c.flags;
+        P.med[pid] = c.med;
         queue[pid] = pid;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) counts[QC_CUR] = n;
@@ -315,7 +317,11 @@ __global__ void k_shade_dielectric(DevScene S, CamInfo ci, PathState P, uint32_t
             pid_decode(ci, pid, pix, sample, slot);
             CamPath c = load_path(P, pid);
             cont = camera_dielectric(S, ci.seed, pix, sample, slot, depth, ci.max_depth, load_hit(P, pid), c);
-            if (cont) store_ray(P, pid, c);
+            if (cont) {
+                store_ray(P, pid, c);
+                P.T[pid] = c.T;
+                P.med[pid] = c.med;
+            }
         }
         block_push(cont, pid, q_next, counts + QC_NEXT);
     }
@@ -430,6 +436,7 @@ __global__ void k_photon_emit(DevScene S, WaveDev wl, PhInfo pi, uint32_t n, Pho
                 Ph.lambda[i] = ph.lam;
                 Ph.slot[i] = ph.slot;
                 Ph.spec[i] = ph.spec;
+                Ph.med[i] = ph.med;
             }
         }
         block_push(alive, i, queue, counts + QC_CUR);
@@ -476,6 +483,7 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
             ph.lam = Ph.lambda[id];
             ph.slot = Ph.slot[id];
             ph.spec = Ph.spec[id];
+            ph.med = Ph.med[id];
             int outcome = -1;
             int64_t cc = -1;
             cont = photon_event(S, wl, pi.seed, pi.p0 + id, depth, pi.max_depth,
@@ -483,7 +491,9 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
             if (cont) {
                 Ph.ox[id] = ph.o.x; Ph.oy[id] = ph.o.y; Ph.oz[id] = ph.o.z;
                 Ph.dx[id] = ph.d.x; Ph.dy[id] = ph.d.y; Ph.dz[id] = ph.d.z;
+                Ph.phi[id] = ph.phi;
                 Ph.spec[id] = ph.spec;
+                Ph.med[id] = ph.med;
             }
             if (!cont) ph_stat(C, pi, outcome, ph.phi);
             if (cc >= 0) {
@@ -565,6 +575,7 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
             ph.lam = Ph.lambda[id];
             ph.slot = Ph.slot[id];
             ph.spec = Ph.spec[id];
+            ph.med = Ph.med[id];
             const int outcome = photon_continue<kTraceBS>(
                 S, wl, pi.seed, pi.p0 + id, depth0, pi.max_depth, ph, lds, st, vc, n_cl,
                 [&](int64_t cc, const PhotonPath& q) {
@@ -605,8 +616,8 @@ constexpr uint32_t kWorkSlots = 256;     // traversal launches between clears
 constexpr uint32_t kWorkStride = 64;     // words per launch: one counter on its own line
 
 // carve n-element arrays out of one allocation, 256-byte aligned
-size_t path_bytes(size_t n) { return 25 * (n * 4 + 256); }
-size_t photon_bytes(size_t n) { return 16 * (n * 4 + 256); }
+size_t path_bytes(size_t n) { return 27 * (n * 4 + 256); }
+size_t photon_bytes(size_t n) { return 18 * (n * 4 + 256); }
 
 PathState carve_path(void* p, size_t n) {
     Carver c{static_cast<char*>(p)};
@@ -614,7 +625,7 @@ PathState carve_path(void* p, size_t n) {
     P.ox = c.take<float>(n); P.oy = c.take<float>(n); P.oz = c.take<float>(n);
     P.dx = c.take<float>(n); P.dy = c.take<float>(n); P.dz = c.take<float>(n);
     P.T = c.take<float>(n); P.L = c.take<float>(n); P.lambda = c.take<float>(n);
-    P.flags = c.take<uint32_t>(n);
+    P.flags = c.take<uint32_t>(n); P.med = c.take<uint64_t>(n);
     P.t = c.take<float>(n); P.u = c.take<float>(n); P.v = c.take<float>(n); P.prim = c.take<uint32_t>(n);
     P.sox = c.take<float>(n); P.soy = c.take<float>(n); P.soz = c.take<float>(n);
     P.sdx = c.take<float>(n); P.sdy = c.take<float>(n); P.sdz = c.take<float>(n);
@@ -628,7 +639,7 @@ PhotonState carve_photon(void* p, size_t n) {
     P.ox = c.take<float>(n); P.oy = c.take<float>(n); P.oz = c.take<float>(n);
     P.dx = c.take<float>(n); P.dy = c.take<float>(n); P.dz = c.take<float>(n);
     P.phi = c.take<float>(n); P.lambda = c.take<float>(n);
-    P.slot = c.take<uint32_t>(n); P.spec = c.take<uint32_t>(n);
+    P.slot = c.take<uint32_t>(n); P.spec = c.take<uint32_t>(n); P.med = c.take<uint64_t>(n);
     P.t = c.take<float>(n); P.u = c.take<float>(n); P.v = c.take<float>(n); P.prim = c.take<uint32_t>(n);
     return P;
 }

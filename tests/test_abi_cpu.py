@@ -29,7 +29,19 @@ def test_library_exports_every_declared_symbol():
     for n in _declared():
         assert n in exported, n
         assert hasattr(lib, n)
-    assert lib.sc_abi_version() == 1
+    assert lib.sc_abi_version() == sc._sc.ABI_VERSION == 2
+
+
+def test_material_record_layout():
+    """The 48-byte material record: header, binding and scene arrays agree."""
+    import ctypes
+    import paper_2107_11008_amd as sc
+    import scenegen as sg
+    hdr = open(os.path.join(ROOT, "include", "sc.h")).read()
+    assert "} sc_material; /* 48 bytes */" in hdr
+    assert ctypes.sizeof(sc._sc.Material) == 48 == sg.MATERIAL_DTYPE.itemsize
+    for name, _ in sc._sc.Material._fields_:
+        assert getattr(sc._sc.Material, name).offset == sg.MATERIAL_DTYPE.fields[name][1], name
 
 
 def test_binding_lists_all_exports():

@@ -35,10 +35,12 @@ def _run(ctx, cfg, staged, spp):
         ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, 5)
 
 
-@pytest.mark.parametrize("which", ["c1", "c2s"])
+@pytest.mark.parametrize("which", ["c1", "c2s", "glass"])
 def test_switch_depth_does_not_change_outputs(ctx, which):
     if which == "c1":
         cfg, spp = sg.config1(), 2
+    elif which == "glass":
+        cfg, spp = sg.tinted_nested(), 3
     else:
         cfg, spp = sg.config2(tri_scale=0.05, w=48, h=40), 3
         cfg["n_photons"] = 1 << 17

@@ -68,10 +68,6 @@ def _nest_scene():
     return orc.OracleScene(sg.slab_stack(layers), use_bvh=False)
 
 
-def _n(x):
-    return pytest.approx(x, rel=0, abs=0)
-
-
 def test_media_single_object_is_plain_air_glass():
     s = _nest_scene()
     after, real, n1, n2 = orc.media_step(s, [], 2, True, 550.0)
@@ -263,3 +259,10 @@ def test_camera_paths_through_absorbing_slab():
         assert j >= 0 and abs(k - (2 * j + 1)) < 2e-4 * (2 * j + 1), (k, float(lv))
         passes.append(j)
     assert np.mean(np.array(passes) == 0) > 0.9
+
+
+def test_oracle_material_layout_matches_scene_records():
+    import ctypes
+    assert ctypes.sizeof(orc.Material) == 48 == sg.MATERIAL_DTYPE.itemsize
+    for name, _ in orc.Material._fields_:
+        assert getattr(orc.Material, name).offset == sg.MATERIAL_DTYPE.fields[name][1], name
