@@ -74,7 +74,11 @@ typedef struct sc_bvh sc_bvh;
  * is an interface only where its object is that medium on the inner side,
  * and there the outer index is that of the next medium (air if none);
  * other surfaces are crossed unchanged.  Cameras and lights are in air.
- * `roughness` is reserved for rough glass and must be 0. */
+ * Glass roughness (Sec. III-C): `roughness` > 0 is the GGX width alpha of
+ * a microfacet interface (Walter et al., EGSR 2007): a microfacet normal
+ * drawn with density D(m)|m.n|, reflection or refraction at it chosen by
+ * its Fresnel reflectance, path weight |i.m| G1(i) G1(o) / (|i.n||m.n|)
+ * (Smith G1); 0 is smooth glass. */
 #define SC_MAT_DIFFUSE 0u
 #define SC_MAT_DIELECTRIC 1u
 #define SC_MAT_EMISSIVE 2u
@@ -89,7 +93,7 @@ typedef struct {
     float le;
     uint32_t priority;  /* dielectric nesting priority */
     float sigma[3];     /* dielectric absorption (1/m) at 450, 550, 650 nm; finite, >= 0 */
-    float roughness;    /* 0 */
+    float roughness;    /* dielectric GGX alpha in [0, 1]; 0 = smooth */
 } sc_material; /* 48 bytes */
 
 typedef struct {

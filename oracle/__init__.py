@@ -82,6 +82,7 @@ def lib():
         L.sco_any.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
         L.sco_dielectric.argtypes = [vp, vp, vp, vp, f32, f32, f32, f32, vp, vp, vp, vp]
         L.sco_fresnel.argtypes = [f32, f32, f32, f32]
+        L.sco_rough_dielectric.argtypes = [vp, vp, f32, f32, f32, u32, vp, vp, vp, vp]
         L.sco_exp_neg.argtypes = [f32]
         L.sco_exp_neg.restype = f32
         L.sco_media_step.argtypes = [vp, vp, u32, u32, C.c_int, f32, vp, vp, vp, vp, vp]
@@ -204,6 +205,22 @@ def dielectric(d, Ng, Ns, P, lam, ca, cb, uF):
 
 def fresnel(n1, n2, ci, ct):
     return lib().sco_fresnel(float(n1), float(n2), float(ci), float(ct))
+
+
+def rough_dielectric(d, n, n1, n2, alpha, u):
+    """GGX interface draws: u float32 [count, 3] -> (directions [count, 3],
+    reflected int32 [count] (1, 0, or -1 for no valid direction), weights)."""
+    u = np.ascontiguousarray(u, dtype=np.float32).reshape(-1, 3)
+    d = np.ascontiguousarray(d, dtype=np.float32)
+    n = np.ascontiguousarray(n, dtype=np.float32)
+    out = np.zeros((len(u), 3), np.float32)
+    refl = np.zeros(len(u), np.int32)
+    w = np.zeros(len(u), np.float32)
+    rc = lib().sco_rough_dielectric(_p(d), _p(n), float(n1), float(n2), float(alpha), len(u), _p(u), _p(out),
+                                    _p(refl), _p(w))
+    if rc != 0:
+        raise ValueError("sco_rough_dielectric: invalid arguments")
+    return out, refl, w
 
 
 def exp_neg(x):

@@ -564,6 +564,95 @@ int sco_dielectric(const float d[3], const float Ng[3], const float Ns[3], const
 }
 
 /* ------------------------------------------------------------------ */
+/* Rough dielectric interface (Walter, Marschner, Li and Torrance,       */
+/* "Microfacet Models for Refraction through Rough Surfaces", EGSR 2007): */
+/* GGX microfacets of width alpha.  A microfacet normal m is drawn with   */
+/* density D(m) |m.n| around the macro normal n (the shading normal on    */
+/* the incoming side, else the geometric one):                           */
+/*   tan^2 theta_m = alpha^2 u0 / (1 - u0),  phi_m = 2 pi u1;             */
+/* the Fresnel reflectance at m decides reflection (uF < F) or           */
+/* refraction across m, and the path weight is                           */
+/*   w = |i.m| G1(i) G1(o) / (|i.n| |m.n|),                              */
+/*   G1(v) = 2 / (1 + sqrt(1 + alpha^2 tan^2 theta_v))  (Smith),          */
+/* their sampling weight with the Fresnel factor taken by the choice.    */
+/* A draw with i.m <= 0, or whose outgoing direction is on the wrong     */
+/* side of the surface or of m, has weight 0: the path ends.             */
+/* ------------------------------------------------------------------ */
+
+static float smith_g1(float c, float a2) {
+    float c2 = c * c;
+    float t2 = (1.0f - c2) / c2;
+    return 2.0f / (1.0f + sqrtf(1.0f + a2 * t2));
+}
+
+static int rough_dir(const frame_t* f, v3 d, float n1, float n2, float alpha, float u0, float u1, float uF,
+                     v3* dout, int* refl_out, float* w_out) {
+    float eta = n1 / n2;
+    v3 N = f->Ns;
+    if (!(-vdot(d, N) > 0.0f)) N = f->Nf;
+    float a2 = alpha * alpha;
+    float tm2 = (a2 * u0) / (1.0f - u0);
+    float cm = 1.0f / sqrtf(1.0f + tm2);
+    float sm = sqrtf(fmaxf(0.0f, 1.0f - cm * cm));
+    float sp, cp;
+    sco_sincos2pi(u1, &sp, &cp);
+    v3 t1, t2;
+    onb(N, &t1, &t2);
+    v3 m = vnorm(vadd(vadd(vscale(t1, sm * cp), vscale(t2, sm * sp)), vscale(N, cm)));
+    float ci = -vdot(d, m);
+    if (!(ci > 0.0f)) return 0;
+    float k = 1.0f - (eta * eta) * (1.0f - ci * ci);
+    int refl;
+    float ct = 0.0f;
+    if (k <= 0.0f) {
+        refl = 1;
+    } else {
+        ct = sqrtf(k);
+        refl = uF < sco_fresnel(n1, n2, ci, ct);
+    }
+    v3 out;
+    if (refl) out = vadd(d, vscale(m, ci + ci));
+    else out = vadd(vscale(d, eta), vscale(m, eta * ci - ct));
+    out = vnorm(out);
+    float side = vdot(out, f->Nf);
+    float on = vdot(out, N), om = vdot(out, m);
+    int ok = refl ? (side > 0.0f && on > 0.0f && om > 0.0f) : (side < 0.0f && on < 0.0f && om < 0.0f);
+    if (!ok) return 0;
+    float in_ = -vdot(d, N);
+    float w = ((ci * smith_g1(in_, a2)) * smith_g1(fabsf(on), a2)) / (in_ * vdot(m, N));
+    *dout = out;
+    *refl_out = refl;
+    *w_out = w;
+    return 1;
+}
+
+int sco_rough_dielectric(const float d[3], const float n[3], float n1, float n2, float alpha, uint32_t count,
+                         const float* u, float* d_out, int32_t* reflected, float* weight) {
+    if (!d || !n || !u || !d_out || !reflected || !weight || !(alpha > 0.0f && alpha <= 1.0f)) return -1;
+    frame_t f;
+    v3 dd = mk(d[0], d[1], d[2]);
+    f.P = mk(0.0f, 0.0f, 0.0f);
+    f.Ng = mk(n[0], n[1], n[2]);
+    f.entering = vdot(dd, f.Ng) < 0.0f;
+    f.Nf = f.entering ? f.Ng : vneg(f.Ng);
+    f.Ns = f.Nf;
+    for (uint32_t i = 0; i < count; i++) {
+        v3 out = mk(0.0f, 0.0f, 0.0f);
+        int refl = 0;
+        float w = 0.0f;
+        if (!rough_dir(&f, dd, n1, n2, alpha, u[3 * (size_t)i], u[3 * (size_t)i + 1], u[3 * (size_t)i + 2],
+                       &out, &refl, &w)) {
+            refl = -1;
+            w = 0.0f;
+        }
+        d_out[3 * (size_t)i] = out.x; d_out[3 * (size_t)i + 1] = out.y; d_out[3 * (size_t)i + 2] = out.z;
+        reflected[i] = refl;
+        weight[i] = w;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Absorption inside glass (Beer-Lambert): over a path length t in a    */
 /* medium of absorption coefficient sigma the weight drops by            */
 /* exp(-sigma t).  sigma is given at 450, 550 and 650 nm and taken       */
@@ -910,7 +999,14 @@ static float trace_path(pt_ctx* X, v3 o, v3 d, uint32_t pix, uint32_t sample, ui
             uint32_t r[4];
             rng_cam(X->seed, pix, sample, depth, 1, slot, r);
             v3 nd; int refl;
-            if (!dielectric_dir(&f, d, I.n1, I.n2, u01(r[2]), &nd, &refl, NULL)) break;
+            if (m->roughness > 0.0f) {
+                float w;
+                if (!rough_dir(&f, d, I.n1, I.n2, m->roughness, u01(r[0]), u01(r[1]), u01(r[2]), &nd, &refl, &w))
+                    break;
+                T = T * w;
+            } else if (!dielectric_dir(&f, d, I.n1, I.n2, u01(r[2]), &nd, &refl, NULL)) {
+                break;
+            }
             if (!refl) med = I.after;
             o = offset_ray(f.P, refl ? f.Nf : vneg(f.Nf));
             d = nd;
@@ -1010,7 +1106,6 @@ static int check_common(const sco_scene* s, const sco_wavelengths* wl, uint32_t 
         if (m->type != 1) continue;
         for (int c = 0; c < 3; c++) if (!(m->sigma[c] >= 0.0f && m->sigma[c] <= FLT_MAX)) return -1;
         if (!(m->roughness >= 0.0f && m->roughness <= 1.0f)) return -1;
-        if (m->roughness != 0.0f) return -1;
     }
     return 0;
 }
@@ -1289,7 +1384,14 @@ int sco_trace_photons(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons
                 uint32_t r1[4];
                 rng_ph(seed, p, depth, 1, r1);
                 v3 nd; int refl;
-                if (!dielectric_dir(&f, d, I.n1, I.n2, u01(r1[2]), &nd, &refl, NULL)) {
+                if (mt->roughness > 0.0f) {
+                    float w;
+                    if (!rough_dir(&f, d, I.n1, I.n2, mt->roughness, u01(r1[0]), u01(r1[1]), u01(r1[2]), &nd, &refl,
+                                   &w)) {
+                        outcome = SCO_PH_LOST; break;
+                    }
+                    phi = phi * w;
+                } else if (!dielectric_dir(&f, d, I.n1, I.n2, u01(r1[2]), &nd, &refl, NULL)) {
                     outcome = SCO_PH_LOST; break;
                 }
                 if (!refl) med = I.after;

@@ -19,9 +19,10 @@
  *     Cauchy dispersion, exact Fresnel and total internal reflection, next
  *     event estimation on diffuse surfaces, and a photon-traced caustic map
  *     on a receiver plane;
- *   - glass colour and thickness (Sec. III-C lists both among the scene
- *     variations) as Beer-Lambert absorption inside each dielectric, with
- *     nested and overlapping dielectrics resolved by priority.
+ *   - glass colour, thickness and roughness (Sec. III-C lists them among
+ *     the scene variations) as Beer-Lambert absorption inside each
+ *     dielectric, GGX microfacet refraction, and nested and overlapping
+ *     dielectrics resolved by priority.
  *
  * All pointers are host pointers.  Functions return 0 on success and a
  * negative value on invalid arguments.
@@ -42,7 +43,7 @@ typedef struct {
     float le;                  /* emitted radiance (front face only) */
     uint32_t priority;         /* dielectric: nesting priority (ties: larger object id wins) */
     float sigma[3];            /* dielectric: absorption coefficient (1/m) at 450, 550, 650 nm */
-    float roughness;           /* dielectric: GGX alpha; 0 = smooth */
+    float roughness;           /* dielectric: GGX alpha in [0, 1]; 0 = smooth */
 } sco_material;
 
 typedef struct {
@@ -128,6 +129,13 @@ int sco_dielectric(const float d[3], const float Ng[3], const float Ns[3], const
                    float lambda_nm, float ca, float cb, float u_fresnel,
                    float o_out[3], float d_out[3], int* reflected, float* R_out);
 float sco_fresnel(float n1, float n2, float ci, float ct);
+/* Rough (GGX) dielectric interface, exposed for the microfacet pins:
+ * direction d arriving at a surface of normal n (either orientation),
+ * index n1 on the incoming side and n2 across, GGX alpha in (0, 1];
+ * count draws u[i][3] = (u0, u1, uF).  Out: direction, reflected flag
+ * (1 reflected, 0 refracted, -1 no valid direction) and path weight. */
+int sco_rough_dielectric(const float d[3], const float n[3], float n1, float n2, float alpha, uint32_t count,
+                         const float* u, float* d_out, int32_t* reflected, float* weight);
 /* exp(-x) for x >= 0 in the oracle's own float arithmetic (Beer-Lambert
  * weights); 1 for x <= 0, 0 for x > 87. */
 float sco_exp_neg(float x);

@@ -160,7 +160,6 @@ sc_status check_scene(const sc_scene* sc) {
                 if (!(m.sigma[c] >= 0.0f && m.sigma[c] <= FLT_MAX))
                     return set_error(SC_EINVAL, "dielectric absorption must be finite and >= 0");
             if (!(m.roughness >= 0.0f && m.roughness <= 1.0f)) return set_error(SC_EINVAL, "roughness must be in [0, 1]");
-            if (m.roughness != 0.0f) return set_error(SC_EUNSUPPORTED, "rough dielectrics are not supported");
         }
         if (m.type == SC_MAT_DIFFUSE && m.albedo_mode > SC_ALBEDO_TEXTURE) return set_error(SC_EINVAL, "unknown albedo mode");
         if (m.type == SC_MAT_DIFFUSE && m.albedo_mode == SC_ALBEDO_TEXTURE && !sc->tex)

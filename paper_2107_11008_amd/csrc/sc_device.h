@@ -340,6 +340,59 @@ __device__ __forceinline__ bool dielectric(const Frame& f, F3 d, float n1, float
     return false;
 }
 
+// ---------------------------------------------------------------- rough dielectric
+// GGX microfacet refraction (Walter, Marschner, Li and Torrance, EGSR
+// 2007).  A microfacet normal m is drawn with density D(m)|m.n| around the
+// macro normal n (shading normal on the incoming side, else geometric):
+// tan^2 theta_m = alpha^2 u0 / (1 - u0), phi_m = 2 pi u1.  Fresnel at m
+// picks reflection (uF < F) or refraction across m; the path weight is
+// |i.m| G1(i) G1(o) / (|i.n| |m.n|) with Smith's
+// G1(v) = 2 / (1 + sqrt(1 + alpha^2 tan^2 theta_v)).  False (weight 0)
+// when i.m <= 0 or the outgoing direction lies on the wrong side of the
+// surface or of m.
+__device__ __forceinline__ float smith_g1(float c, float a2) {
+    const float c2 = c * c;
+    const float t2 = (1.0f - c2) / c2;
+    return 2.0f / (1.0f + sqrtf(1.0f + a2 * t2));
+}
+
+__device__ __forceinline__ bool rough_dielectric(const Frame& f, F3 d, float n1, float n2, float alpha, float u0,
+                                                 float u1, float uF, F3& out, bool& refl, float& w) {
+    const float eta = n1 / n2;
+    F3 N = f.Ns;
+    if (!(-dot(d, N) > 0.0f)) N = f.Nf;
+    const float a2 = alpha * alpha;
+    const float tm2 = (a2 * u0) / (1.0f - u0);
+    const float cm = 1.0f / sqrtf(1.0f + tm2);
+    const float sm = sqrtf(fmaxf(0.0f, 1.0f - cm * cm));
+    float sp, cp;
+    sincos_turn(u1, sp, cp);
+    F3 t1, t2;
+    basis(N, t1, t2);
+    const F3 m = normalize((t1 * (sm * cp) + t2 * (sm * sp)) + N * cm);
+    const float ci = -dot(d, m);
+    if (!(ci > 0.0f)) return false;
+    const float k = 1.0f - (eta * eta) * (1.0f - ci * ci);
+    float ct = 0.0f;
+    if (k <= 0.0f) {
+        refl = true;
+    } else {
+        ct = sqrtf(k);
+        refl = uF < fresnel(n1, n2, ci, ct);
+    }
+    F3 o;
+    if (refl) o = d + m * (ci + ci);
+    else o = d * eta + m * (eta * ci - ct);
+    o = normalize(o);
+    const float side = dot(o, f.Nf), on = dot(o, N), om = dot(o, m);
+    const bool ok = refl ? (side > 0.0f && on > 0.0f && om > 0.0f) : (side < 0.0f && on < 0.0f && om < 0.0f);
+    if (!ok) return false;
+    const float in_ = -dot(d, N);
+    w = ((ci * smith_g1(in_, a2)) * smith_g1(fabsf(on), a2)) / (in_ * dot(m, N));
+    out = o;
+    return true;
+}
+
 // ---------------------------------------------------------------- absorbing glass
 // Beer-Lambert: a path segment of length t inside a medium keeps
 // exp(-sigma t) of its weight.  sigma is given at 450, 550 and 650 nm and

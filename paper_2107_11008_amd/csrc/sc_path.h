@@ -426,9 +426,10 @@ __device__ __forceinline__ void camera_emission(const DevScene& S, const HitRec&
     if (dot(P.d, Ng) < 0.0f) P.L = P.L + T * m.le;
 }
 
-// dielectric hit: absorption over the segment, then reflect, refract or
-// (a surface hidden inside a higher-priority medium) pass straight on;
-// false if the path ends here
+// dielectric hit: absorption over the segment, then reflect, refract
+// (smooth, or through a GGX microfacet with its weight) or, for a surface
+// hidden inside a higher-priority medium, pass straight on; false if the
+// path ends here
 __device__ __forceinline__ bool camera_dielectric(const DevScene& S, uint64_t seed, uint32_t pix, uint32_t sample,
                                                   uint32_t slot, uint32_t depth, uint32_t max_depth, const HitRec& h,
                                                   CamPath& P) {
@@ -443,7 +444,14 @@ __device__ __forceinline__ bool camera_dielectric(const DevScene& S, uint64_t se
     const U4 r = rng_camera(seed, pix, sample, depth, 1, slot);
     F3 nd;
     bool refl;
-    if (!dielectric(f, P.d, c.n1, c.n2, unit(r.c), nd, refl)) return false;
+    const float alpha = S.mat[S.tri_obj[h.prim]].roughness;
+    if (alpha > 0.0f) {
+        float w;
+        if (!rough_dielectric(f, P.d, c.n1, c.n2, alpha, unit(r.a), unit(r.b), unit(r.c), nd, refl, w)) return false;
+        P.T = P.T * w;
+    } else if (!dielectric(f, P.d, c.n1, c.n2, unit(r.c), nd, refl)) {
+        return false;
+    }
     if (!refl) P.med = c.after;
     P.o = offset_ray(f.P, refl ? f.Nf : neg(f.Nf));
     P.d = nd;
@@ -717,7 +725,14 @@ __device__ __forceinline__ bool photon_event(const DevScene& S, const WaveDev& w
         const U4 r = rng_photon(seed, p, depth, 1);
         F3 nd;
         bool refl;
-        if (!dielectric(f, ph.d, c.n1, c.n2, unit(r.c), nd, refl)) {
+        if (m.roughness > 0.0f) {
+            float w;
+            if (!rough_dielectric(f, ph.d, c.n1, c.n2, m.roughness, unit(r.a), unit(r.b), unit(r.c), nd, refl, w)) {
+                outcome = SC_PH_LOST;
+                return false;
+            }
+            ph.phi = ph.phi * w;
+        } else if (!dielectric(f, ph.d, c.n1, c.n2, unit(r.c), nd, refl)) {
             outcome = SC_PH_LOST;
             return false;
         }

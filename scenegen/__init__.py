@@ -675,23 +675,24 @@ def slab_over_light(thickness: float, mat: dict, le: float = 1.0, w: int = 8, h:
 
 
 def tinted_nested(level: int = 3, w: int = 48, h: int = 40, n_photons: int = 1 << 15):
-    """Coloured and nested glass over a checker plane: a tinted sphere A
-    (radius 1) holding a denser, darker inclusion B (radius 0.45, higher
-    priority), overlapped by a sphere C of middle priority, and a thin
-    absorbing slab D; one point and one area light, spectral 380-720 nm,
-    depth 12.  Every crossing rule shows up: air-glass, glass-glass,
-    surfaces hidden inside a higher-priority medium, absorption on camera
-    paths, shadow rays and photons."""
+    """Coloured, rough and nested glass over a checker plane: a tinted
+    sphere A (radius 1) holding a denser, darker inclusion B (radius 0.45,
+    higher priority), overlapped by a rough sphere C (GGX alpha 0.25) of
+    middle priority, and a thin absorbing rough slab D (alpha 0.1); one
+    point and one area light, spectral 380-720 nm, depth 12.  Every
+    crossing rule shows up: air-glass, glass-glass, surfaces hidden inside
+    a higher-priority medium, smooth and microfacet interfaces, absorption
+    on camera paths, shadow rays and photons."""
     b = SceneBuilder()
     plane = quad((-4, -4, 0), (4, -4, 0), (4, 4, 0), (-4, 4, 0), (0, 0, 1))
     recv = b.add(plane, dict(type=MAT_DIFFUSE, albedo_mode=ALBEDO_CHECKER, rho_a=0.8, rho_b=0.3))
     b.add(icosphere(level, 1.0, (0.0, 0.0, 1.2)), glass(1.5, 0.0042, sigma=(0.2, 0.8, 1.6)), photon_target=True)
     b.add(icosphere(level, 0.45, (0.2, 0.0, 1.3)), glass(1.8, 0.01, sigma=(3.0, 1.0, 0.5), priority=2))
-    b.add(icosphere(level, 0.7, (1.3, 0.3, 1.0)), glass(1.33, 0.003, sigma=(0.0, 0.3, 0.0), priority=1),
-          photon_target=True)
+    b.add(icosphere(level, 0.7, (1.3, 0.3, 1.0)),
+          glass(1.33, 0.003, sigma=(0.0, 0.3, 0.0), priority=1, roughness=0.25), photon_target=True)
     slab = box((0.8, 0.8, 0.06))
-    b.add(Mesh(slab.V + np.array([-1.7, -0.6, 0.7]), slab.I, slab.VN), glass(1.6, 0.005, sigma=(4.0, 4.0, 0.5)),
-          photon_target=True)
+    b.add(Mesh(slab.V + np.array([-1.7, -0.6, 0.7]), slab.I, slab.VN),
+          glass(1.6, 0.005, sigma=(4.0, 4.0, 0.5), roughness=0.1), photon_target=True)
     b.point_light((2.0, 3.0, 6.0), 40.0)
     light = quad((-1.5, 1.0, 4.0), (-1.5, 1.6, 4.0), (-0.9, 1.6, 4.0), (-0.9, 1.0, 4.0), (0, 0, -1))
     b.add(light, dict(type=MAT_EMISSIVE, le=20.0))

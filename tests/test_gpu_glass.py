@@ -1,4 +1,4 @@
-"""Parity of the HIP path with the oracle on absorbing, nested and
+"""Parity of the HIP path with the oracle on absorbing, rough, nested and
 overlapping glass, through the C ABI.
 
 Bar, as for clear glass: photon counts per cell exact, caustic-map cells
@@ -117,8 +117,8 @@ def test_nested_absorbing_slab_closed_form_at_scale(ctx):
 
 
 @pytest.mark.parametrize("field,value", [("sigma", (-1.0, 0.0, 0.0)), ("sigma", (0.0, float("nan"), 0.0)),
-                                         ("sigma", (0.0, 0.0, float("inf"))), ("roughness", 0.2),
-                                         ("roughness", -0.1)])
+                                         ("sigma", (0.0, 0.0, float("inf"))), ("roughness", 1.5),
+                                         ("roughness", -0.1), ("roughness", float("nan"))])
 def test_bad_glass_parameters_rejected(ctx, field, value):
     import paper_2107_11008_amd as sc
     c = sg.config1()

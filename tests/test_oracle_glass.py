@@ -266,3 +266,26 @@ def test_oracle_material_layout_matches_scene_records():
     assert ctypes.sizeof(orc.Material) == 48 == sg.MATERIAL_DTYPE.itemsize
     for name, _ in orc.Material._fields_:
         assert getattr(orc.Material, name).offset == sg.MATERIAL_DTYPE.fields[name][1], name
+
+
+def test_nearly_smooth_rough_slab_keeps_the_closed_form():
+    """A microfacet slab with tiny alpha behaves as the smooth one, absorption
+    included (the rough branch carries the media set and the weights)."""
+    mat = sg.glass(1.5, sigma=(1.0, 3.0, 8.0), roughness=1e-4)
+    got, tol = _transmittance([((1.0, 1.0, 0.4), 0.7, mat)], 500.0, n_photons=1 << 15)
+    want = _stack(_interface(1.0, 1.5), _layer(math.exp(-2.0 * 0.4)), _interface(1.5, 1.0))
+    assert abs(got - want) < tol, (got, want)
+
+
+def test_rough_slab_conserves_flux():
+    """Single-scattering microfacet glass loses a little energy, never gains:
+    the flux over all photon outcomes stays within [0.9, 1] of the emitted."""
+    layers = [((1.0, 1.0, 0.4), 0.7, sg.glass(1.5, roughness=0.3))]
+    wl = sg.Wavelengths(sg.WL_FIXED, 1, (550.0,))
+    n = 1 << 15
+    _, _, _, st = orc.trace_photons(orc.OracleScene(sg.slab_stack(layers)), n, 32, wl, 5)
+    _, _, _, st0 = orc.trace_photons(orc.OracleScene(sg.slab_stack([(s, z, sg.glass(1.5)) for s, z, _ in layers])),
+                                     n, 32, wl, 5)
+    tot = sum(v[0] for k, v in st.items() if k != "segments")
+    tot0 = sum(v[0] for k, v in st0.items() if k != "segments")
+    assert 0.9 * tot0 < tot < tot0 * (1.0 + 2.5 / math.sqrt(n))
