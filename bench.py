@@ -175,6 +175,46 @@ def batch_compare(ctx):
     return res
 
 
+def glass_variants(ctx, steps=5, warmup=2):
+    """The same medium-scene step on the richer glass: every object tinted
+    and every second one rough ("rich"), and the clear scene under a light
+    twice the size at the same power ("soft_light_x2")."""
+    import torch
+
+    import scenegen as sg
+    res = {}
+    for name, kw in (("rich", dict(glass_style="rich")), ("soft_light_x2", dict(light_scale=2.0))):
+        cfg = sg.config2(**kw)
+        wl, cam = cfg["wavelengths"], cfg["camera"]
+        dscene = ctx.upload_scene(cfg["scene"])
+        outs = {}
+
+        def step():
+            outs["bvh"] = ctx.build_bvh(dscene, out=outs.get("bvh"))
+            ph = ctx.trace_photons(outs["bvh"], cfg["n_photons"], cfg["max_depth"], wl, cfg["photon_seed"],
+                                   out=outs.get("map"))
+            outs["map"] = ph["map"]
+            outs["img"] = ctx.render(outs["bvh"], cam, cfg["spp"], cfg["max_depth"], wl, cfg["render_seed"],
+                                     caustic_map=ph["map"], out=outs.get("img"))
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.reset_counters()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        c = ctx.counters()
+        rays = c["rays_closest"] + c["rays_shadow"]
+        res[name] = {"ms_per_step": round(secs / steps * 1e3, 3), "Mrays_s": round(rays / secs / 1e6, 1),
+                     "rays_per_step": rays // steps, "steps": steps}
+        outs.clear()
+        del dscene
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +226,7 @@ def main():
                     help="bounces run as one launch per stage before per-lane path finishing "
                          "(library default if omitted; 0 = all bounces staged)")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-glass-variants", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -317,6 +358,8 @@ def main():
                      "tris_per_ray": round(tris_per_ray, 3),
                      "kernel_Mrays_s": round(c["closest_rays_timed"] / (c["closest_ms"] * 1e-3) / 1e6, 1)},
     }
+    if not args.no_glass_variants:
+        line["glass_variants"] = glass_variants(ctx)
     if not args.no_denoise:
         line["denoise_1080p"] = denoise_fps(ctx)
     if not args.no_batch:

@@ -440,7 +440,25 @@ def value_noise(rng: np.random.Generator, n: int, octaves: int = 4, lo=0.2, hi=0
 GLASS_C1 = dict(type=MAT_DIELECTRIC, cauchy_a=1.5, cauchy_b=0.0042)
 
 
-def config1(level: int = 3):
+def _square_light(center, side, down_intensity):
+    """Downward-facing square emitter of the given side whose intensity
+    along its normal (le * area) equals ``down_intensity`` W/sr."""
+    cx, cy, cz = center
+    h = 0.5 * side
+    q = quad((cx - h, cy - h, cz), (cx - h, cy + h, cz), (cx + h, cy + h, cz), (cx + h, cy - h, cz), (0, 0, -1))
+    return q, dict(type=MAT_EMISSIVE, le=down_intensity / (side * side))
+
+
+def _scaled_light(p0, p1, p2, p3, le, scale):
+    """An area light quad scaled by ``scale`` about its centre, radiance
+    divided by scale^2 so that its power stays the same."""
+    P = np.array([p0, p1, p2, p3], dtype=np.float64)
+    c = P.mean(0)
+    P = c + (P - c) * scale
+    return quad(*[tuple(p) for p in P], (0, 0, -1)), dict(type=MAT_EMISSIVE, le=le / (scale * scale))
+
+
+def config1(level: int = 3, light_size: float = 0.0):
     """Tiny scene: glass icosphere over an 8x8 m checker plane, one point light.
 
     Glass icosphere (level 3 = 1,280 triangles, radius 1, centre (0,0,1.5))
@@ -448,13 +466,20 @@ def config1(level: int = 3):
     two-triangle plane [-4,4]^2 at z=0 with a 1 m checker of albedo 0.8/0.2;
     a 50 W/sr point light at (2,3,6); a 128x128 pinhole camera; three fixed
     wavelengths 650/550/450 nm (R,G,B); a 256x256 caustic map on the plane.
+
+    ``light_size`` > 0 is the caustic-softness knob: the point light becomes
+    a downward-facing square emitter of that side with the same intensity
+    along its normal, so caustics blur as it grows.
     """
     b = SceneBuilder()
     plane = quad((-4, -4, 0), (4, -4, 0), (4, 4, 0), (-4, 4, 0), (0, 0, 1))
     recv_obj = b.add(plane, dict(type=MAT_DIFFUSE, albedo_mode=ALBEDO_CHECKER, rho_a=0.8, rho_b=0.2))
     b.add(icosphere(level, 1.0, (0.0, 0.0, 1.5)), GLASS_C1, photon_target=True)
-    b.point_light((2.0, 3.0, 6.0), 50.0)
-    scene = b.build(Receiver(recv_obj, 256, 256, -4.0, -4.0, 8.0, 8.0), name=f"c1-ico{level}")
+    if light_size > 0.0:
+        b.add(*_square_light((2.0, 3.0, 6.0), light_size, 50.0))
+    else:
+        b.point_light((2.0, 3.0, 6.0), 50.0)
+    scene = b.build(Receiver(recv_obj, 256, 256, -4.0, -4.0, 8.0, 8.0), name=f"c1-ico{level}" + (f"-light{light_size:g}" if light_size > 0.0 else ""))
     cam = look_at((0.0, -7.0, 5.0), (0.0, 0.0, 0.8), (0, 0, 1), 40.0, 128, 128)
     wl = Wavelengths(WL_FIXED, 3, (650.0, 550.0, 450.0))
     return dict(scene=scene, camera=cam, wavelengths=wl, spp=1, max_depth=8,
@@ -466,12 +491,20 @@ def _glass(rng):
                 cauchy_b=float(rng.uniform(0.003, 0.01)))
 
 
-def config2(seed: int = 2000, tri_scale: float = 1.0, w: int = 512, h: int = 512):
+def config2(seed: int = 2000, tri_scale: float = 1.0, w: int = 512, h: int = 512, light_scale: float = 1.0,
+            glass_style: str = "clear"):
     """Medium scene: eight seeded glass objects (4 lathe + 4 superquadric,
     10k-50k triangles each, ~2e5 total) resting on a 4x4 m value-noise
     textured plane, one 0.5x0.5 m area light, 512x512, spectral 380-720 nm.
-    ``tri_scale`` shrinks the triangle counts for quick tests."""
+    ``tri_scale`` shrinks the triangle counts for quick tests;
+    ``light_scale`` resizes the light at constant power (caustic softness);
+    ``glass_style="rich"`` tints every object (absorption 0.5-6 per metre
+    per wavelength knot) and roughens every second one (GGX alpha
+    0.05-0.3), same geometry."""
     rng = np.random.default_rng(seed)
+    rich = np.random.default_rng(seed + 7) if glass_style == "rich" else None
+    if glass_style not in ("clear", "rich"):
+        raise ValueError(glass_style)
     b = SceneBuilder()
     plane = quad((-2, -2, 0), (2, -2, 0), (2, 2, 0), (-2, 2, 0), (0, 0, 1))
     tex = value_noise(rng, 512)
@@ -490,9 +523,13 @@ def config2(seed: int = 2000, tri_scale: float = 1.0, w: int = 512, h: int = 512
         R = _rotation(rng.uniform(0, 2 * math.pi), math.radians(rng.uniform(0, 30)), rng.uniform(0, 2 * math.pi))
         sx, sy = slots[order[i]]
         t = np.array([sx + rng.uniform(-0.04, 0.04), sy + rng.uniform(-0.06, 0.06), 0.0])
-        b.add(place(mesh, R, t, rest_on=0.0), _glass(rng), photon_target=True)
-    light = quad((0.05, -0.45, 2.5), (0.05, 0.05, 2.5), (0.55, 0.05, 2.5), (0.55, -0.45, 2.5), (0, 0, -1))
-    b.add(light, dict(type=MAT_EMISSIVE, le=12.0))
+        mat = _glass(rng)
+        if rich is not None:
+            mat["sigma"] = rich.uniform(0.5, 6.0, size=3).astype(np.float32)
+            mat["roughness"] = float(rich.uniform(0.05, 0.3)) if i % 2 else 0.0
+        b.add(place(mesh, R, t, rest_on=0.0), mat, photon_target=True)
+    b.add(*_scaled_light((0.05, -0.45, 2.5), (0.05, 0.05, 2.5), (0.55, 0.05, 2.5), (0.55, -0.45, 2.5), 12.0,
+                         light_scale))
     scene = b.build(Receiver(recv, 1024, 1024, -2.0, -2.0, 4.0, 4.0), tex=tex, tex_rect=(-2.0, -2.0, 4.0, 4.0),
                     name=f"c2-{seed}")
     cam = look_at((0.0, -1.6, 1.6), (0.0, 0.0, 0.05), (0, 0, 1), 40.0, w, h)
@@ -501,10 +538,11 @@ def config2(seed: int = 2000, tri_scale: float = 1.0, w: int = 512, h: int = 512
                 n_photons=1 << 22, scene_seed=seed, render_seed=seed + 1, photon_seed=seed + 2)
 
 
-def config3(seed: int = 3000, tri_scale: float = 1.0, w: int = 1920, h: int = 1080):
+def config3(seed: int = 3000, tri_scale: float = 1.0, w: int = 1920, h: int = 1080, light_scale: float = 1.0):
     """Large scene: 40 overlapping glass meshes (~1.2M triangles) plus opaque
     diffuse clutter (~0.8M triangles) on a textured floor, two area lights,
-    1920x1080, 64 spp spectral, depth 16."""
+    1920x1080, 64 spp spectral, depth 16.  ``light_scale`` resizes both
+    lights at constant power (caustic softness)."""
     rng = np.random.default_rng(seed)
     b = SceneBuilder()
     plane = quad((-3, -3, 0), (3, -3, 0), (3, 3, 0), (-3, 3, 0), (0, 0, 1))
@@ -537,10 +575,8 @@ def config3(seed: int = 3000, tri_scale: float = 1.0, w: int = 1920, h: int = 10
         rho = float(rng.uniform(0.2, 0.8))
         b.add(place(mesh, R, t, rest_on=0.0), dict(type=MAT_DIFFUSE, albedo_mode=ALBEDO_CONST, rho_a=rho))
         made += len(mesh.I)
-    l1 = quad((-1.2, -0.6, 3.0), (-1.2, 0.0, 3.0), (-0.6, 0.0, 3.0), (-0.6, -0.6, 3.0), (0, 0, -1))
-    l2 = quad((0.8, 0.4, 2.6), (0.8, 0.8, 2.6), (1.2, 0.8, 2.6), (1.2, 0.4, 2.6), (0, 0, -1))
-    b.add(l1, dict(type=MAT_EMISSIVE, le=8.0))
-    b.add(l2, dict(type=MAT_EMISSIVE, le=10.0))
+    b.add(*_scaled_light((-1.2, -0.6, 3.0), (-1.2, 0.0, 3.0), (-0.6, 0.0, 3.0), (-0.6, -0.6, 3.0), 8.0, light_scale))
+    b.add(*_scaled_light((0.8, 0.4, 2.6), (0.8, 0.8, 2.6), (1.2, 0.8, 2.6), (1.2, 0.4, 2.6), 10.0, light_scale))
     scene = b.build(Receiver(recv, 2048, 2048, -3.0, -3.0, 6.0, 6.0), tex=tex, tex_rect=(-3.0, -3.0, 6.0, 6.0),
                     name=f"c3-{seed}")
     cam = look_at((0.0, -3.2, 2.2), (0.0, 0.0, 0.1), (0, 0, 1), 45.0, w, h)

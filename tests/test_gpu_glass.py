@@ -71,6 +71,20 @@ def test_tinted_nested_parity(ctx):
     assert o["rgb"].max() > 0
 
 
+def test_soft_light_parity(ctx):
+    """The caustic-softness knob: the point light as a square emitter."""
+    c = sg.config1(light_size=0.6)
+    c["n_photons"] = 1 << 15
+    _parity(ctx, c, 1)
+
+
+def test_rich_medium_scene_parity(ctx):
+    """The medium scene with tinted and rough glass, shrunk."""
+    c = sg.config2(tri_scale=0.03, w=40, h=32, glass_style="rich")
+    c["n_photons"] = 1 << 14
+    _parity(ctx, c, 2)
+
+
 def test_overlapping_glass_parity():
     """The large scene's 40 overlapping glass meshes, shrunk: surfaces
     inside other glass are crossed by priority on both sides."""
