@@ -76,9 +76,9 @@ typedef struct sc_bvh sc_bvh;
  * other surfaces are crossed unchanged.  Cameras and lights are in air.
  * Glass roughness (Sec. III-C): `roughness` > 0 is the GGX width alpha of
  * a microfacet interface (Walter et al., EGSR 2007): a microfacet normal
- * drawn with density D(m)|m.n|, reflection or refraction at it chosen by
- * its Fresnel reflectance, path weight |i.m| G1(i) G1(o) / (|i.n||m.n|)
- * (Smith G1); 0 is smooth glass. */
+ * drawn from the distribution of visible normals (Heitz, JCGT 2018),
+ * reflection or refraction at it chosen by its Fresnel reflectance, path
+ * weight G1(o) <= 1 (Smith); 0 is smooth glass. */
 #define SC_MAT_DIFFUSE 0u
 #define SC_MAT_DIELECTRIC 1u
 #define SC_MAT_EMISSIVE 2u

@@ -564,19 +564,21 @@ int sco_dielectric(const float d[3], const float Ng[3], const float Ns[3], const
 }
 
 /* ------------------------------------------------------------------ */
-/* Rough dielectric interface (Walter, Marschner, Li and Torrance,       */
-/* "Microfacet Models for Refraction through Rough Surfaces", EGSR 2007): */
-/* GGX microfacets of width alpha.  A microfacet normal m is drawn with   */
-/* density D(m) |m.n| around the macro normal n (the shading normal on    */
-/* the incoming side, else the geometric one):                           */
-/*   tan^2 theta_m = alpha^2 u0 / (1 - u0),  phi_m = 2 pi u1;             */
-/* the Fresnel reflectance at m decides reflection (uF < F) or           */
-/* refraction across m, and the path weight is                           */
-/*   w = |i.m| G1(i) G1(o) / (|i.n| |m.n|),                              */
-/*   G1(v) = 2 / (1 + sqrt(1 + alpha^2 tan^2 theta_v))  (Smith),          */
-/* their sampling weight with the Fresnel factor taken by the choice.    */
-/* A draw with i.m <= 0, or whose outgoing direction is on the wrong     */
-/* side of the surface or of m, has weight 0: the path ends.             */
+/* Rough dielectric interface: the GGX microfacet model of Walter,       */
+/* Marschner, Li and Torrance ("Microfacet Models for Refraction through */
+/* Rough Surfaces", EGSR 2007) with width alpha, Smith shadowing          */
+/*   G1(v) = 2 / (1 + sqrt(1 + alpha^2 tan^2 theta_v)),                  */
+/* sampled through the distribution of visible normals (Heitz,           */
+/* "Sampling the GGX Distribution of Visible Normals", JCGT 7(4), 2018): */
+/* m is drawn with density G1(i) max(0, i.m) D(m) / (i.n) by stretching  */
+/* i into the alpha = 1 configuration, drawing a point on the projected   */
+/* hemisphere seen from there (r = sqrt(u0), phi = 2 pi u1, the second   */
+/* coordinate warped towards the visible half) and stretching its normal */
+/* back.  The Fresnel reflectance at m then picks reflection (uF < F) or  */
+/* refraction across m, and the path weight is G1(o) <= 1 either way.    */
+/* The macro normal n is the shading normal on the incoming side, else   */
+/* the geometric one.  A draw whose outgoing direction lies on the wrong */
+/* side of the surface or of m has weight 0: the path ends.              */
 /* ------------------------------------------------------------------ */
 
 static float smith_g1(float c, float a2) {
@@ -591,14 +593,26 @@ static int rough_dir(const frame_t* f, v3 d, float n1, float n2, float alpha, fl
     v3 N = f->Ns;
     if (!(-vdot(d, N) > 0.0f)) N = f->Nf;
     float a2 = alpha * alpha;
-    float tm2 = (a2 * u0) / (1.0f - u0);
-    float cm = 1.0f / sqrtf(1.0f + tm2);
-    float sm = sqrtf(fmaxf(0.0f, 1.0f - cm * cm));
-    float sp, cp;
-    sco_sincos2pi(u1, &sp, &cp);
+    /* the incoming direction in the frame (t1, t2, N), stretched */
     v3 t1, t2;
     onb(N, &t1, &t2);
-    v3 m = vnorm(vadd(vadd(vscale(t1, sm * cp), vscale(t2, sm * sp)), vscale(N, cm)));
+    v3 iw = vneg(d);
+    v3 vh = vnorm(mk(alpha * vdot(iw, t1), alpha * vdot(iw, t2), vdot(iw, N)));
+    float lensq = vh.x * vh.x + vh.y * vh.y;
+    v3 b1 = lensq > 0.0f ? vscale(mk(-vh.y, vh.x, 0.0f), 1.0f / sqrtf(lensq)) : mk(1.0f, 0.0f, 0.0f);
+    v3 b2 = vcross(vh, b1);
+    /* a point of the projected disc, warped to the visible half */
+    float r = sqrtf(u0);
+    float sp, cp;
+    sco_sincos2pi(u1, &sp, &cp);
+    float p1 = r * cp, p2 = r * sp;
+    float h = 0.5f * (1.0f + vh.z);
+    p2 = (1.0f - h) * sqrtf(fmaxf(0.0f, 1.0f - p1 * p1)) + h * p2;
+    float p3 = sqrtf(fmaxf(0.0f, (1.0f - p1 * p1) - p2 * p2));
+    v3 nh = vadd(vadd(vscale(b1, p1), vscale(b2, p2)), vscale(vh, p3));
+    /* back to the alpha configuration and to world space */
+    v3 ne = vnorm(mk(alpha * nh.x, alpha * nh.y, fmaxf(0.0f, nh.z)));
+    v3 m = vnorm(vadd(vadd(vscale(t1, ne.x), vscale(t2, ne.y)), vscale(N, ne.z)));
     float ci = -vdot(d, m);
     if (!(ci > 0.0f)) return 0;
     float k = 1.0f - (eta * eta) * (1.0f - ci * ci);
@@ -618,11 +632,9 @@ static int rough_dir(const frame_t* f, v3 d, float n1, float n2, float alpha, fl
     float on = vdot(out, N), om = vdot(out, m);
     int ok = refl ? (side > 0.0f && on > 0.0f && om > 0.0f) : (side < 0.0f && on < 0.0f && om < 0.0f);
     if (!ok) return 0;
-    float in_ = -vdot(d, N);
-    float w = ((ci * smith_g1(in_, a2)) * smith_g1(fabsf(on), a2)) / (in_ * vdot(m, N));
     *dout = out;
     *refl_out = refl;
-    *w_out = w;
+    *w_out = smith_g1(fabsf(on), a2);
     return 1;
 }
 

@@ -341,15 +341,16 @@ __device__ __forceinline__ bool dielectric(const Frame& f, F3 d, float n1, float
 }
 
 // ---------------------------------------------------------------- rough dielectric
-// GGX microfacet refraction (Walter, Marschner, Li and Torrance, EGSR
-// 2007).  A microfacet normal m is drawn with density D(m)|m.n| around the
-// macro normal n (shading normal on the incoming side, else geometric):
-// tan^2 theta_m = alpha^2 u0 / (1 - u0), phi_m = 2 pi u1.  Fresnel at m
-// picks reflection (uF < F) or refraction across m; the path weight is
-// |i.m| G1(i) G1(o) / (|i.n| |m.n|) with Smith's
-// G1(v) = 2 / (1 + sqrt(1 + alpha^2 tan^2 theta_v)).  False (weight 0)
-// when i.m <= 0 or the outgoing direction lies on the wrong side of the
-// surface or of m.
+// GGX microfacet refraction (Walter, Marschner, Li and Torrance, EGSR 2007)
+// with Smith G1(v) = 2 / (1 + sqrt(1 + alpha^2 tan^2 theta_v)), sampled
+// from the distribution of visible normals (Heitz, JCGT 7(4), 2018): the
+// incoming direction is stretched to the alpha = 1 configuration, a point
+// of the projected hemisphere is drawn (r = sqrt(u0), phi = 2 pi u1, the
+// second coordinate warped towards the visible half), and its normal is
+// stretched back.  Fresnel at m picks reflection (uF < F) or refraction;
+// the weight is G1(o) <= 1.  The macro normal is the shading normal on the
+// incoming side, else the geometric one.  False when the outgoing
+// direction lies on the wrong side of the surface or of m.
 __device__ __forceinline__ float smith_g1(float c, float a2) {
     const float c2 = c * c;
     const float t2 = (1.0f - c2) / c2;
@@ -362,14 +363,24 @@ __device__ __forceinline__ bool rough_dielectric(const Frame& f, F3 d, float n1,
     F3 N = f.Ns;
     if (!(-dot(d, N) > 0.0f)) N = f.Nf;
     const float a2 = alpha * alpha;
-    const float tm2 = (a2 * u0) / (1.0f - u0);
-    const float cm = 1.0f / sqrtf(1.0f + tm2);
-    const float sm = sqrtf(fmaxf(0.0f, 1.0f - cm * cm));
-    float sp, cp;
-    sincos_turn(u1, sp, cp);
     F3 t1, t2;
     basis(N, t1, t2);
-    const F3 m = normalize((t1 * (sm * cp) + t2 * (sm * sp)) + N * cm);
+    const F3 iw = neg(d);
+    const F3 vh = normalize(F3{alpha * dot(iw, t1), alpha * dot(iw, t2), dot(iw, N)});
+    const float lensq = vh.x * vh.x + vh.y * vh.y;
+    const F3 b1 = lensq > 0.0f ? F3{-vh.y, vh.x, 0.0f} * (1.0f / sqrtf(lensq)) : F3{1.0f, 0.0f, 0.0f};
+    const F3 b2 = cross(vh, b1);
+    const float r = sqrtf(u0);
+    float sp, cp;
+    sincos_turn(u1, sp, cp);
+    const float p1 = r * cp;
+    float p2 = r * sp;
+    const float h = 0.5f * (1.0f + vh.z);
+    p2 = (1.0f - h) * sqrtf(fmaxf(0.0f, 1.0f - p1 * p1)) + h * p2;
+    const float p3 = sqrtf(fmaxf(0.0f, (1.0f - p1 * p1) - p2 * p2));
+    const F3 nh = (b1 * p1 + b2 * p2) + vh * p3;
+    const F3 ne = normalize(F3{alpha * nh.x, alpha * nh.y, fmaxf(0.0f, nh.z)});
+    const F3 m = normalize((t1 * ne.x + t2 * ne.y) + N * ne.z);
     const float ci = -dot(d, m);
     if (!(ci > 0.0f)) return false;
     const float k = 1.0f - (eta * eta) * (1.0f - ci * ci);
@@ -387,8 +398,7 @@ __device__ __forceinline__ bool rough_dielectric(const Frame& f, F3 d, float n1,
     const float side = dot(o, f.Nf), on = dot(o, N), om = dot(o, m);
     const bool ok = refl ? (side > 0.0f && on > 0.0f && om > 0.0f) : (side < 0.0f && on < 0.0f && om < 0.0f);
     if (!ok) return false;
-    const float in_ = -dot(d, N);
-    w = ((ci * smith_g1(in_, a2)) * smith_g1(fabsf(on), a2)) / (in_ * dot(m, N));
+    w = smith_g1(fabsf(on), a2);
     out = o;
     return true;
 }

@@ -2,11 +2,12 @@
 
 Glass roughness is one of the scene variations of the paper's ablation
 (Sec. III-C); the oracle models it with the microfacet refraction model of
-Walter, Marschner, Li and Torrance (EGSR 2007), sampled through microfacet
-normals drawn from D(m) |m.n| with the Fresnel term at m choosing
-reflection or refraction.  The pin is their closed-form BSDF: the
-expected sampling weight that lands in a bin of outgoing directions must
-equal the integral over that bin of
+Walter, Marschner, Li and Torrance (EGSR 2007), sampled through the
+distribution of visible normals (Heitz, JCGT 2018) with the Fresnel term
+at m choosing reflection or refraction, so that every weight is
+G1(o) <= 1.  The pin is Walter et al.'s closed-form BSDF, which does not
+depend on how it is sampled: the expected sampling weight that lands in a
+bin of outgoing directions must equal the integral over that bin of
 
     f_r |o.n| = F(i.h) D(h) G(i, o) / (4 |i.n|)                       (eq. 20)
     f_t |o.n| = |i.h| |o.h| n_o^2 (1 - F(i.h)) D(h) G(i, o)
@@ -117,7 +118,7 @@ def test_sampling_matches_walter_bsdf(theta_i, n1, n2, alpha):
     u = rng.random((N, 3), dtype=np.float32)
     o, refl, w = orc.rough_dielectric(d, np.array([0.0, 0.0, 1.0], np.float32), n1, n2, alpha, u)
     o, w = o.astype(np.float64), w.astype(np.float64)
-    assert np.all(np.isfinite(w)) and np.all(w >= 0.0)
+    assert np.all(np.isfinite(w)) and np.all(w >= 0.0) and np.all(w <= 1.0)
     for reflect in (True, False):
         want = _bin_integrals(i, n1, n2, alpha, reflect)
         s1, s2 = _sample_bins(o, w, refl == (1 if reflect else 0), reflect)
