@@ -38,7 +38,8 @@ class SceneS(C.Structure):
                 ("tex", C.c_void_p), ("tex_w", C.c_uint32), ("tex_h", C.c_uint32),
                 ("tex_x0", C.c_float), ("tex_y0", C.c_float), ("tex_ext_u", C.c_float), ("tex_ext_v", C.c_float),
                 ("recv_obj", C.c_uint32), ("recv_wc", C.c_uint32), ("recv_hc", C.c_uint32),
-                ("recv_x0", C.c_float), ("recv_y0", C.c_float), ("recv_ext_u", C.c_float), ("recv_ext_v", C.c_float)]
+                ("recv_x0", C.c_float), ("recv_y0", C.c_float), ("recv_ext_u", C.c_float), ("recv_ext_v", C.c_float),
+                ("tex_rgb", C.c_void_p)]
 
 
 class CameraS(C.Structure):
@@ -60,6 +61,10 @@ class AovS(C.Structure):
 class PhotonStatsS(C.Structure):
     _fields_ = [("flux", C.c_double * 9), ("count", C.c_uint64 * 9), ("segments", C.c_uint64)]
 
+
+# one stored photon of the general photon map (40 bytes, as sco_pm_rec)
+PM_REC_DTYPE = np.dtype([("pos", "<f4", (3,)), ("nrm", "<f4", (3,)), ("phi", "<f4"), ("channel", "<u4"),
+                         ("photon", "<u8")])
 
 PH_OUTCOMES = ("deposited", "outside", "direct", "elsewhere", "escaped", "absorbed", "truncated", "lost",
                "emit_dead")
@@ -90,6 +95,12 @@ def lib():
         L.sco_camera_ray.argtypes = [vp, u32, u32, f32, f32, vp, vp]
         L.sco_trace_photons.argtypes = [vp, vp, u64, u64, u64, u32, vp, u64, vp, vp, vp]
         L.sco_render.argtypes = [vp, vp, vp, u32, u32, vp, u64, vp, vp, u32, vp, vp]
+        L.sco_pm_trace.argtypes = [vp, vp, u64, u64, u64, u32, vp, u64, vp, u64, vp, vp]
+        L.sco_pm_scale.argtypes = [vp, u64]
+        L.sco_pm_scale.restype = C.c_double
+        L.sco_pm_gather.argtypes = [vp, u64, f32, vp, vp, u32]
+        L.sco_pm_gather.restype = f32
+        L.sco_render_pm.argtypes = [vp, vp, vp, u32, u32, vp, u64, vp, u64, f32, vp, u32, vp, vp]
         L.sco_path_samples.argtypes = [vp, vp, vp, u32, u32, vp, u64, vp, vp, u32, vp, vp]
         _LIB = L
     return _LIB
@@ -106,7 +117,8 @@ class OracleScene:
     def __init__(self, scene, use_bvh: bool = True):
         self.scene = scene
         s = scene
-        self._keep = [s.V, s.I, s.VN, s.tri_obj, s.materials, s.point_lights, s.targets_obj, s.targets_sphere, s.tex]
+        self._keep = [s.V, s.I, s.VN, s.tri_obj, s.materials, s.point_lights, s.targets_obj, s.targets_sphere, s.tex,
+                      s.tex_rgb]
         st = SceneS()
         st.V, st.I, st.VN, st.tri_obj = _p(s.V), _p(s.I), _p(s.VN), _p(s.tri_obj)
         st.nv, st.nt = s.nv, s.nt
@@ -115,6 +127,9 @@ class OracleScene:
         st.tg_obj, st.tg_sph, st.n_tg = _p(s.targets_obj), _p(s.targets_sphere), len(s.targets_obj)
         if s.tex is not None:
             st.tex, st.tex_h, st.tex_w = _p(s.tex), s.tex.shape[0], s.tex.shape[1]
+            st.tex_x0, st.tex_y0, st.tex_ext_u, st.tex_ext_v = s.tex_rect
+        if s.tex_rgb is not None:
+            st.tex_rgb, st.tex_h, st.tex_w = _p(s.tex_rgb), s.tex_rgb.shape[0], s.tex_rgb.shape[1]
             st.tex_x0, st.tex_y0, st.tex_ext_u, st.tex_ext_v = s.tex_rect
         r = s.receiver
         if r is not None:
@@ -293,6 +308,57 @@ def render(osc: OracleScene, cam, spp: int, max_depth: int, wl, seed: int, caust
     seg = C.c_uint64()
     rc = lib().sco_render(C.byref(osc.c), None if brute else osc.bvh, C.byref(cs), spp, max_depth, C.byref(w),
                           seed, _p(cmap), _p(pix), 0 if pix is None else len(pix), C.byref(a), C.byref(seg))
+    assert rc == 0, rc
+    out["segments"] = seg.value
+    return out
+
+
+def pm_trace(osc: OracleScene, n_photons: int, max_depth: int, wl, seed: int, p0: int = 0, p1=None):
+    """General photon map pass: (records PM_REC_DTYPE in photon order, stats)."""
+    p1 = n_photons if p1 is None else p1
+    cap = max(p1 - p0, 1)
+    recs = np.zeros(cap, PM_REC_DTYPE)
+    n = C.c_uint64()
+    st = PhotonStatsS()
+    w = wavelengths_struct(wl)
+    rc = lib().sco_pm_trace(C.byref(osc.c), osc.bvh, n_photons, p0, p1, max_depth, C.byref(w), seed,
+                            recs.ctypes.data, cap, C.byref(n), C.byref(st))
+    assert rc == 0, rc
+    stats = {k: (st.flux[i], st.count[i]) for i, k in enumerate(PH_OUTCOMES)}
+    stats["segments"] = st.segments
+    return recs[: n.value].copy(), stats
+
+
+def pm_scale(recs):
+    recs = np.ascontiguousarray(recs, dtype=PM_REC_DTYPE)
+    return lib().sco_pm_scale(recs.ctypes.data, len(recs))
+
+
+def pm_gather(recs, radius, P, N, channel):
+    recs = np.ascontiguousarray(recs, dtype=PM_REC_DTYPE)
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    N = np.ascontiguousarray(N, dtype=np.float32)
+    return lib().sco_pm_gather(recs.ctypes.data, len(recs), float(radius), P.ctypes.data, N.ctypes.data, int(channel))
+
+
+def render_pm(osc: OracleScene, cam, spp: int, max_depth: int, wl, seed: int, recs, radius: float, pixels=None):
+    """sco_render with the general photon map; returns the same dict as render()."""
+    H, W = cam.h, cam.w
+    out = dict(rgb=np.zeros((H, W, 3), np.float32), obj=np.zeros((H, W), np.uint32),
+               trans=np.zeros((H, W), np.uint8), tri=np.full((H, W), 0xFFFFFFFF, np.uint32),
+               depth=np.zeros((H, W), np.float32), depthn=np.zeros((H, W), np.float32),
+               normal=np.zeros((H, W, 3), np.float32), normal_cam=np.zeros((H, W, 3), np.float32),
+               albedo=np.zeros((H, W), np.float32))
+    a = AovS()
+    for k, v in out.items():
+        setattr(a, k, v.ctypes.data)
+    recs = np.ascontiguousarray(recs, dtype=PM_REC_DTYPE)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.uint32)
+    seg = C.c_uint64()
+    rc = lib().sco_render_pm(C.byref(osc.c), osc.bvh, C.byref(camera_struct(cam)), spp, max_depth,
+                             C.byref(wavelengths_struct(wl)), seed, recs.ctypes.data if len(recs) else None,
+                             len(recs), float(radius), _p(pix), 0 if pix is None else len(pix), C.byref(a),
+                             C.byref(seg))
     assert rc == 0, rc
     out["segments"] = seg.value
     return out

@@ -845,7 +845,7 @@ static void derive(const sco_scene* s, derived_t* D) {
         D->inv_cell_area = (float)(((double)s->recv_wc * (double)s->recv_hc) /
                                    ((double)s->recv_ext_u * (double)s->recv_ext_v));
     }
-    if (s->tex) {
+    if (s->tex || s->tex_rgb) {
         D->tex_sx = (float)s->tex_w / s->tex_ext_u;
         D->tex_sy = (float)s->tex_h / s->tex_ext_v;
     }
@@ -859,22 +859,45 @@ static uint32_t cdf_pick(const float* cdf, uint32_t n, float u) {
     return n - 1;
 }
 
-static float albedo_at(const sco_scene* s, const derived_t* D, const sco_material* m, v3 P) {
+/* nearest texel of the texture rectangle under P (edges clamped) */
+static size_t texel_at(const sco_scene* s, const derived_t* D, v3 P) {
+    float fx = (P.x - s->tex_x0) * D->tex_sx;
+    float fy = (P.y - s->tex_y0) * D->tex_sy;
+    int i = (int)floorf(fx), j = (int)floorf(fy);
+    if (i < 0) i = 0;
+    if (i > (int)s->tex_w - 1) i = (int)s->tex_w - 1;
+    if (j < 0) j = 0;
+    if (j > (int)s->tex_h - 1) j = (int)s->tex_h - 1;
+    return (size_t)j * s->tex_w + (size_t)i;
+}
+
+/* Albedo at P for wavelength lam.  An RGB texel is read as reflectance
+ * B at 450 nm, G at 550 nm and R at 650 nm, linear in lambda between
+ * them and constant outside (the same rule as the absorption knots). */
+static float albedo_at(const sco_scene* s, const derived_t* D, const sco_material* m, v3 P, float lam) {
     if (m->albedo_mode == 1) {
         int ix = (int)floorf(P.x), iy = (int)floorf(P.y);
         return ((ix + iy) & 1) == 0 ? m->rho_a : m->rho_b;
     }
-    if (m->albedo_mode == 2 && s->tex) {
-        float fx = (P.x - s->tex_x0) * D->tex_sx;
-        float fy = (P.y - s->tex_y0) * D->tex_sy;
-        int i = (int)floorf(fx), j = (int)floorf(fy);
-        if (i < 0) i = 0;
-        if (i > (int)s->tex_w - 1) i = (int)s->tex_w - 1;
-        if (j < 0) j = 0;
-        if (j > (int)s->tex_h - 1) j = (int)s->tex_h - 1;
-        return s->tex[(size_t)j * s->tex_w + (size_t)i];
+    if (m->albedo_mode == 2 && s->tex) return s->tex[texel_at(s, D, P)];
+    if (m->albedo_mode == 3 && s->tex_rgb) {
+        const float* c = s->tex_rgb + 3 * texel_at(s, D, P);
+        float r = c[0], g = c[1], b = c[2];
+        if (lam <= 450.0f) return b;
+        if (lam >= 650.0f) return r;
+        if (lam < 550.0f) return b + (g - b) * ((lam - 450.0f) / 100.0f);
+        return g + (r - g) * ((lam - 550.0f) / 100.0f);
     }
     return m->rho_a;
+}
+
+/* Grey albedo of the ground-truth output: the mean of an RGB texel. */
+static float albedo_grey(const sco_scene* s, const derived_t* D, const sco_material* m, v3 P) {
+    if (m->albedo_mode == 3 && s->tex_rgb) {
+        const float* c = s->tex_rgb + 3 * texel_at(s, D, P);
+        return ((c[0] + c[1]) + c[2]) / 3.0f;
+    }
+    return albedo_at(s, D, m, P, 550.0f);
 }
 
 /* Receiver cell of a point: floor of the scaled offset, the upper edge
@@ -976,7 +999,10 @@ typedef struct {
     const sco_scene* s; const sco_bvh* bvh; const derived_t* D; const sco_wavelengths* wl;
     const float* map; uint32_t C; uint64_t seed; uint32_t max_depth;
     uint64_t segments;
+    const sco_pm_rec* pm; uint64_t n_pm; double pm_scale; float pm_radius;   /* general photon map, or pm == NULL */
 } pt_ctx;
+
+static float pm_gather(const sco_pm_rec* recs, uint64_t n, double scale, float radius, v3 P, v3 N, uint32_t ch);
 
 static float trace_path(pt_ctx* X, v3 o, v3 d, uint32_t pix, uint32_t sample, uint32_t slot, float lam) {
     const sco_scene* s = X->s;
@@ -1025,11 +1051,17 @@ static float trace_path(pt_ctx* X, v3 o, v3 d, uint32_t pix, uint32_t sample, ui
             continue;
         }
         /* diffuse (Lambertian, two-sided through the facing normal) */
-        float rho = albedo_at(s, D, m, f.P);
+        float rho = albedo_at(s, D, m, f.P, lam);
         diffuse_seen = 1;
         v3 os = offset_ray(f.P, f.Nf);
-        /* caustic gather from the photon map cell under the point */
-        if (X->map && s->recv_obj && obj == s->recv_obj) {
+        /* caustic gather: the general photon map on every diffuse surface,
+         * else the receiver map cell under the point */
+        if (X->pm) {
+            uint32_t b = (X->wl->mode == 0) ? slot : lambda_bin(X->wl, lam);
+            float E = pm_gather(X->pm, X->n_pm, X->pm_scale, X->pm_radius, f.P, f.Nf, b);
+            float g = ((T * rho) * INV_PI_F) * E;
+            L = L + g;
+        } else if (X->map && s->recv_obj && obj == s->recv_obj) {
             int64_t cell = recv_cell(s, D, f.P);
             if (cell >= 0) {
                 uint32_t b = (X->wl->mode == 0) ? slot : lambda_bin(X->wl, lam);
@@ -1115,6 +1147,7 @@ static int check_common(const sco_scene* s, const sco_wavelengths* wl, uint32_t 
     for (uint32_t i = 0; i < s->nt; i++) if (s->tri_obj[i] == 0 || s->tri_obj[i] >= s->n_mat) return -1;
     for (uint32_t k = 1; k < s->n_mat; k++) {
         const sco_material* m = &s->mat[k];
+        if (m->type == 0 && m->albedo_mode == 3 && !s->tex_rgb) return -1;
         if (m->type != 1) continue;
         for (int c = 0; c < 3; c++) if (!(m->sigma[c] >= 0.0f && m->sigma[c] <= FLT_MAX)) return -1;
         if (!(m->roughness >= 0.0f && m->roughness <= 1.0f)) return -1;
@@ -1128,7 +1161,7 @@ int sco_path_samples(const sco_scene* s, const sco_bvh* bvh, const sco_camera* c
     if (check_common(s, wl, max_depth) || !cam || spp == 0 || !L) return -1;
     derived_t D;
     derive(s, &D);
-    pt_ctx X = {s, bvh, &D, wl, caustic_map, map_channels(wl), seed, max_depth, 0};
+    pt_ctx X = {s, bvh, &D, wl, caustic_map, map_channels(wl), seed, max_depth, 0, NULL, 0, 1.0, 0.0f};
     uint32_t K = wl->mode == 0 ? wl->k : 1;
     for (uint32_t sm = 0; sm < spp; sm++) {
         for (uint32_t i = 0; i < n_pix; i++) {
@@ -1155,9 +1188,10 @@ int sco_path_samples(const sco_scene* s, const sco_bvh* bvh, const sco_camera* c
 /* outputs of the pixel-centre ray.                                      */
 /* ------------------------------------------------------------------ */
 
-int sco_render(const sco_scene* s, const sco_bvh* bvh, const sco_camera* cam, uint32_t spp, uint32_t max_depth,
-               const sco_wavelengths* wl, uint64_t seed, const float* caustic_map,
-               const uint32_t* pix, uint32_t n_pix, sco_aov* out, uint64_t* segments) {
+static int render_impl(const sco_scene* s, const sco_bvh* bvh, const sco_camera* cam, uint32_t spp,
+                       uint32_t max_depth, const sco_wavelengths* wl, uint64_t seed, const float* caustic_map,
+                       const sco_pm_rec* pm, uint64_t n_pm, float pm_radius,
+                       const uint32_t* pix, uint32_t n_pix, sco_aov* out, uint64_t* segments) {
     if (check_common(s, wl, max_depth) || !cam || !out || spp == 0 || cam->w == 0 || cam->h == 0) return -1;
     derived_t D;
     derive(s, &D);
@@ -1165,7 +1199,8 @@ int sco_render(const sco_scene* s, const sco_bvh* bvh, const sco_camera* cam, ui
     memset(&S, 0, sizeof(S));
     int spectral = wl->mode == 1;
     if (spectral) sensor_make(wl, &S);
-    pt_ctx X = {s, bvh, &D, wl, caustic_map, map_channels(wl), seed, max_depth, 0};
+    pt_ctx X = {s, bvh, &D, wl, caustic_map, map_channels(wl), seed, max_depth, 0,
+                pm, n_pm, pm ? sco_pm_scale(pm, n_pm) : 1.0, pm_radius};
     uint32_t npx = pix ? n_pix : cam->w * cam->h;
     float inv_spp = 1.0f / (float)spp;
     v3 R = vnorm(mk(cam->right[0], cam->right[1], cam->right[2]));
@@ -1218,7 +1253,7 @@ int sco_render(const sco_scene* s, const sco_bvh* bvh, const sco_camera* cam, ui
             depn = fminf(t / 10.0f, 1.0f);
             N = f.Ns;
             Nc = mk(vdot(N, R), vdot(N, U), -vdot(N, F));
-            alb = m->type == 0 ? albedo_at(s, &D, m, f.P) : (m->type == 1 ? 1.0f : 0.0f);
+            alb = m->type == 0 ? albedo_grey(s, &D, m, f.P) : (m->type == 1 ? 1.0f : 0.0f);
         }
         if (out->obj) out->obj[p] = obj;
         if (out->trans) out->trans[p] = (uint8_t)(obj && s->mat[obj].type == 1);
@@ -1252,6 +1287,21 @@ int sco_render(const sco_scene* s, const sco_bvh* bvh, const sco_camera* cam, ui
     return 0;
 }
 
+int sco_render(const sco_scene* s, const sco_bvh* bvh, const sco_camera* cam, uint32_t spp, uint32_t max_depth,
+               const sco_wavelengths* wl, uint64_t seed, const float* caustic_map,
+               const uint32_t* pix, uint32_t n_pix, sco_aov* out, uint64_t* segments) {
+    return render_impl(s, bvh, cam, spp, max_depth, wl, seed, caustic_map, NULL, 0, 0.0f, pix, n_pix, out, segments);
+}
+
+int sco_render_pm(const sco_scene* s, const sco_bvh* bvh, const sco_camera* cam, uint32_t spp, uint32_t max_depth,
+                  const sco_wavelengths* wl, uint64_t seed, const sco_pm_rec* recs, uint64_t n_rec, float radius,
+                  const uint32_t* pix, uint32_t n_pix, sco_aov* out, uint64_t* segments) {
+    if ((!recs && n_rec) || !(radius > 0.0f && radius <= FLT_MAX)) return -1;
+    static const sco_pm_rec none;
+    return render_impl(s, bvh, cam, spp, max_depth, wl, seed, NULL, recs ? recs : &none, n_rec, radius, pix, n_pix,
+                       out, segments);
+}
+
 /* ------------------------------------------------------------------ */
 /* Photons: emitted from the lights into cones around the photon target  */
 /* spheres (one cone per target, picked in proportion to its solid angle */
@@ -1263,10 +1313,13 @@ int sco_render(const sco_scene* s, const sco_bvh* bvh, const sco_camera* cam, ui
 /* direction (the exact mixture density).                               */
 /* ------------------------------------------------------------------ */
 
-int sco_trace_photons(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons, uint64_t p0, uint64_t p1,
-                      uint32_t max_depth, const sco_wavelengths* wl, uint64_t seed,
-                      double* map_sum, uint32_t* count, sco_photon_stats* stats) {
-    if (check_common(s, wl, max_depth) || !map_sum || !s->recv_obj || p1 > n_photons || p0 > p1) return -1;
+/* The photon pass.  With recs == NULL, deposits go to the receiver map
+ * (map_sum, count); otherwise every deposit, on any diffuse object, is
+ * appended to recs in photon order (general photon map). */
+static int photon_pass(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons, uint64_t p0, uint64_t p1,
+                       uint32_t max_depth, const sco_wavelengths* wl, uint64_t seed,
+                       double* map_sum, uint32_t* count, sco_pm_rec* recs, uint64_t cap, uint64_t* n_rec,
+                       sco_photon_stats* stats) {
     derived_t D;
     derive(s, &D);
     uint32_t C = map_channels(wl);
@@ -1413,6 +1466,17 @@ int sco_trace_photons(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons
                 continue;
             }
             if (spec == 0) { outcome = SCO_PH_DIRECT; break; }
+            if (recs) {
+                if (*n_rec >= cap) { free(cum); derive_free(&D); return -1; }
+                sco_pm_rec* q = &recs[(*n_rec)++];
+                q->pos[0] = f.P.x; q->pos[1] = f.P.y; q->pos[2] = f.P.z;
+                q->nrm[0] = f.Nf.x; q->nrm[1] = f.Nf.y; q->nrm[2] = f.Nf.z;
+                q->phi = phi;
+                q->channel = slot;
+                q->photon = p;
+                outcome = SCO_PH_DEPOSITED;
+                break;
+            }
             if (obj != s->recv_obj) { outcome = SCO_PH_ELSEWHERE; break; }
             int64_t cell = recv_cell(s, &D, f.P);
             if (cell < 0) { outcome = SCO_PH_OUTSIDE; break; }
@@ -1429,4 +1493,60 @@ int sco_trace_photons(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons
     if (stats) *stats = st;
     derive_free(&D);
     return 0;
+}
+
+int sco_trace_photons(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons, uint64_t p0, uint64_t p1,
+                      uint32_t max_depth, const sco_wavelengths* wl, uint64_t seed,
+                      double* map_sum, uint32_t* count, sco_photon_stats* stats) {
+    if (check_common(s, wl, max_depth) || !map_sum || !s->recv_obj || p1 > n_photons || p0 > p1) return -1;
+    return photon_pass(s, bvh, n_photons, p0, p1, max_depth, wl, seed, map_sum, count, NULL, 0, NULL, stats);
+}
+
+int sco_pm_trace(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons, uint64_t p0, uint64_t p1,
+                 uint32_t max_depth, const sco_wavelengths* wl, uint64_t seed,
+                 sco_pm_rec* recs, uint64_t cap, uint64_t* n_rec, sco_photon_stats* stats) {
+    if (check_common(s, wl, max_depth) || !recs || !n_rec || p1 > n_photons || p0 > p1) return -1;
+    *n_rec = 0;
+    return photon_pass(s, bvh, n_photons, p0, p1, max_depth, wl, seed, NULL, NULL, recs, cap, n_rec, stats);
+}
+
+/* ------------------------------------------------------------------ */
+/* General photon map: density estimation over a disc.  The irradiance   */
+/* of channel c at a surface point x with facing normal n is the flux of */
+/* the stored photons of that channel within distance r of x, deposited  */
+/* on the same side (n_p . n > 0), over the disc area pi r^2 (Jensen,     */
+/* "Global Illumination using Photon Maps", EGWR 1996, with a fixed      */
+/* radius).  The flux sum is exact: each photon's flux is taken in 64-bit */
+/* fixed point, q = round(phi 2^S), with 2^S the largest power of two     */
+/* such that n_stored * max(phi) * 2^S <= 2^62, so that no subset sum can */
+/* overflow and the order of summation does not matter; then             */
+/*   E = (float)(sum q * (1 / (2^S pi r^2)))  in double.                   */
+/* ------------------------------------------------------------------ */
+
+double sco_pm_scale(const sco_pm_rec* recs, uint64_t n) {
+    float pmax = 0.0f;
+    for (uint64_t i = 0; i < n; i++) if (recs[i].phi > pmax) pmax = recs[i].phi;
+    if (n == 0 || !(pmax > 0.0f)) return 1.0;
+    int e;
+    frexp(ldexp(1.0, 62) / ((double)n * (double)pmax), &e);
+    return ldexp(1.0, e - 1);
+}
+
+static float pm_gather(const sco_pm_rec* recs, uint64_t n, double scale, float radius, v3 P, v3 N, uint32_t ch) {
+    float r2 = radius * radius;
+    uint64_t sum = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        const sco_pm_rec* q = &recs[i];
+        if (q->channel != ch) continue;
+        if (!(vdot(mk(q->nrm[0], q->nrm[1], q->nrm[2]), N) > 0.0f)) continue;
+        v3 dlt = vsub(mk(q->pos[0], q->pos[1], q->pos[2]), P);
+        if (vdot(dlt, dlt) < r2) sum += (uint64_t)nearbyint((double)q->phi * scale);
+    }
+    double c = 1.0 / ((scale * 3.14159265358979323846) * ((double)radius * (double)radius));
+    return (float)((double)sum * c);
+}
+
+float sco_pm_gather(const sco_pm_rec* recs, uint64_t n, float radius, const float P[3], const float N[3],
+                    uint32_t channel) {
+    return pm_gather(recs, n, sco_pm_scale(recs, n), radius, mk(P[0], P[1], P[2]), mk(N[0], N[1], N[2]), channel);
 }

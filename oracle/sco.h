@@ -37,7 +37,7 @@ extern "C" {
 
 typedef struct {
     uint32_t type;         /* 0 diffuse, 1 dielectric, 2 emissive */
-    uint32_t albedo_mode;  /* 0 constant rho_a, 1 checker (1 m, rho_a even), 2 texture */
+    uint32_t albedo_mode;  /* 0 constant rho_a, 1 checker (1 m, rho_a even), 2 grey texture, 3 RGB texture */
     float rho_a, rho_b;
     float cauchy_a, cauchy_b;  /* n(lambda) = a + b / lambda_um^2 */
     float le;                  /* emitted radiance (front face only) */
@@ -65,6 +65,7 @@ typedef struct {
     uint32_t recv_obj;        /* 0 = no receiver */
     uint32_t recv_wc, recv_hc;
     float recv_x0, recv_y0, recv_ext_u, recv_ext_v;
+    const float* tex_rgb;     /* [tex_h][tex_w][3] RGB albedo or NULL (same size and rectangle as tex) */
 } sco_scene;
 
 typedef struct {
@@ -105,6 +106,14 @@ enum {
     SCO_PH_EMIT_DEAD = 8
 };
 
+/* One photon of the general photon map (40 bytes). */
+typedef struct {
+    float pos[3];       /* deposit point */
+    float nrm[3];       /* geometric normal on the side the photon arrived from */
+    float phi;          /* flux */
+    uint32_t channel;   /* map channel: wavelength slot or spectral bin */
+    uint64_t photon;    /* photon index */
+} sco_pm_rec;
 typedef struct sco_bvh sco_bvh;
 
 /* Counter-based generator (Salmon et al., SC'11): 10 rounds of Philox4x32. */
@@ -155,6 +164,25 @@ int sco_trace_photons(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons
                       uint32_t max_depth, const sco_wavelengths* wl, uint64_t seed,
                       double* map_sum, uint32_t* count, sco_photon_stats* stats);
 
+/* Photon pass into the general photon map: every photon that reaches a
+ * diffuse surface (any object) after at least one dielectric event is
+ * stored there, in photon order, up to cap records (-1 beyond). */
+int sco_pm_trace(const sco_scene* s, const sco_bvh* bvh, uint64_t n_photons, uint64_t p0, uint64_t p1,
+                 uint32_t max_depth, const sco_wavelengths* wl, uint64_t seed,
+                 sco_pm_rec* recs, uint64_t cap, uint64_t* n_rec, sco_photon_stats* stats);
+/* Fixed-point scale 2^S of the disc sums: the largest power of two with
+ * n * max(phi) * 2^S <= 2^62 (1 if there is no positive flux). */
+double sco_pm_scale(const sco_pm_rec* recs, uint64_t n);
+/* Irradiance estimate of channel at P (facing normal N) over the disc of
+ * the given radius: sum of round(phi 2^S) of the records of that channel
+ * on the same side within the radius, times 1 / (2^S pi r^2). */
+float sco_pm_gather(const sco_pm_rec* recs, uint64_t n, float radius, const float P[3], const float N[3],
+                    uint32_t channel);
+/* sco_render with caustics gathered from the general photon map on every
+ * diffuse surface instead of the receiver map. */
+int sco_render_pm(const sco_scene* s, const sco_bvh* bvh, const sco_camera* cam, uint32_t spp, uint32_t max_depth,
+                  const sco_wavelengths* wl, uint64_t seed, const sco_pm_rec* recs, uint64_t n_rec, float radius,
+                  const uint32_t* pix, uint32_t n_pix, sco_aov* out, uint64_t* segments);
 /* Render the listed pixels (all if pix == NULL).  caustic_map: float
  * [recv_hc][recv_wc][C] or NULL (caustics off).  Output arrays are full
  * size and may individually be NULL.  segments (may be NULL) receives the

@@ -30,6 +30,7 @@ MAT_EMISSIVE = 2
 ALBEDO_CONST = 0
 ALBEDO_CHECKER = 1
 ALBEDO_TEXTURE = 2
+ALBEDO_TEXTURE_RGB = 3
 
 WL_FIXED = 0
 WL_UNIFORM = 1
@@ -96,6 +97,7 @@ class Scene:
     tex: Optional[np.ndarray] = None   # float32 [th,tw] grey albedo
     tex_rect: tuple = (0.0, 0.0, 1.0, 1.0)   # x0, y0, ext_u, ext_v
     name: str = ""
+    tex_rgb: Optional[np.ndarray] = None   # float32 [th,tw,3] RGB albedo (same size and rectangle as tex)
 
     @property
     def nt(self) -> int:
@@ -115,6 +117,10 @@ class Scene:
         assert int(self.tri_obj.max(initial=1)) < len(self.materials)
         if self.VN is not None:
             assert self.VN.dtype == np.float32 and self.VN.shape == self.V.shape
+        if self.tex_rgb is not None:
+            assert self.tex_rgb.dtype == np.float32 and self.tex_rgb.ndim == 3 and self.tex_rgb.shape[2] == 3
+            assert self.tex is None or self.tex.shape == self.tex_rgb.shape[:2]
+            assert self.tex_rgb.flags["C_CONTIGUOUS"]
         for a in ("V", "I", "tri_obj", "materials", "point_lights", "targets_obj", "targets_sphere"):
             assert getattr(self, a).flags["C_CONTIGUOUS"], a
 
@@ -376,7 +382,7 @@ class SceneBuilder:
     def point_light(self, pos, intensity):
         self.lights.append((*pos, intensity))
 
-    def build(self, receiver: Optional[Receiver], tex=None, tex_rect=(0, 0, 1, 1), name="") -> Scene:
+    def build(self, receiver: Optional[Receiver], tex=None, tex_rect=(0, 0, 1, 1), name="", tex_rgb=None) -> Scene:
         V = np.concatenate(self.Vs).astype(np.float32)
         N = np.concatenate(self.Ns)
         N = (N / np.maximum(np.linalg.norm(N, axis=1, keepdims=True), 1e-300)).astype(np.float32)
@@ -395,6 +401,7 @@ class SceneBuilder:
             tex=None if tex is None else np.ascontiguousarray(tex.astype(np.float32)),
             tex_rect=tuple(float(x) for x in tex_rect),
             name=name,
+            tex_rgb=None if tex_rgb is None else np.ascontiguousarray(tex_rgb.astype(np.float32)),
         )
         s.validate()
         return s
@@ -538,16 +545,24 @@ def config2(seed: int = 2000, tri_scale: float = 1.0, w: int = 512, h: int = 512
                 n_photons=1 << 22, scene_seed=seed, render_seed=seed + 1, photon_seed=seed + 2)
 
 
-def config3(seed: int = 3000, tri_scale: float = 1.0, w: int = 1920, h: int = 1080, light_scale: float = 1.0):
+def config3(seed: int = 3000, tri_scale: float = 1.0, w: int = 1920, h: int = 1080, light_scale: float = 1.0,
+            floor: str = "grey"):
     """Large scene: 40 overlapping glass meshes (~1.2M triangles) plus opaque
     diffuse clutter (~0.8M triangles) on a textured floor, two area lights,
     1920x1080, 64 spp spectral, depth 16.  ``light_scale`` resizes both
-    lights at constant power (caustic softness)."""
+    lights at constant power (caustic softness); ``floor="rgb"`` gives the
+    floor an RGB value-noise albedo texture (same geometry)."""
     rng = np.random.default_rng(seed)
     b = SceneBuilder()
     plane = quad((-3, -3, 0), (3, -3, 0), (3, 3, 0), (-3, 3, 0), (0, 0, 1))
     tex = value_noise(rng, 1024)
-    recv = b.add(plane, dict(type=MAT_DIFFUSE, albedo_mode=ALBEDO_TEXTURE))
+    tex_rgb = None
+    if floor == "rgb":
+        crng = np.random.default_rng(seed + 11)
+        tex_rgb = np.stack([value_noise(crng, 1024, lo=0.1, hi=0.9) for _ in range(3)], -1)
+    elif floor != "grey":
+        raise ValueError(floor)
+    recv = b.add(plane, dict(type=MAT_DIFFUSE, albedo_mode=ALBEDO_TEXTURE if tex_rgb is None else ALBEDO_TEXTURE_RGB))
     glass_tris = int(1_200_000 * tri_scale)
     per = max(200, glass_tris // 40)
     for i in range(40):
@@ -578,7 +593,7 @@ def config3(seed: int = 3000, tri_scale: float = 1.0, w: int = 1920, h: int = 10
     b.add(*_scaled_light((-1.2, -0.6, 3.0), (-1.2, 0.0, 3.0), (-0.6, 0.0, 3.0), (-0.6, -0.6, 3.0), 8.0, light_scale))
     b.add(*_scaled_light((0.8, 0.4, 2.6), (0.8, 0.8, 2.6), (1.2, 0.8, 2.6), (1.2, 0.4, 2.6), 10.0, light_scale))
     scene = b.build(Receiver(recv, 2048, 2048, -3.0, -3.0, 6.0, 6.0), tex=tex, tex_rect=(-3.0, -3.0, 6.0, 6.0),
-                    name=f"c3-{seed}")
+                    name=f"c3-{seed}" + ("-rgb" if tex_rgb is not None else ""), tex_rgb=tex_rgb)
     cam = look_at((0.0, -3.2, 2.2), (0.0, 0.0, 0.1), (0, 0, 1), 45.0, w, h)
     wl = Wavelengths(WL_UNIFORM, 1, (550.0,), 380.0, 720.0, 16)
     return dict(scene=scene, camera=cam, wavelengths=wl, spp=64, max_depth=16,
@@ -619,12 +634,18 @@ def config4_item(j: int, base_seed: int = 4000):
 # small scenes used by the pins
 # --------------------------------------------------------------------------
 
-def plane_only(albedo=0.8, light=(2.0, 3.0, 6.0), intensity=50.0, w=32, h=32):
+def plane_only(albedo=0.8, light=(2.0, 3.0, 6.0), intensity=50.0, w=32, h=32, rgb=None):
+    """``rgb``: an RGB albedo texture [th, tw, 3] over the plane instead of
+    the constant ``albedo``."""
     b = SceneBuilder()
     plane = quad((-4, -4, 0), (4, -4, 0), (4, 4, 0), (-4, 4, 0), (0, 0, 1))
-    recv = b.add(plane, dict(type=MAT_DIFFUSE, albedo_mode=ALBEDO_CONST, rho_a=albedo))
+    if rgb is None:
+        recv = b.add(plane, dict(type=MAT_DIFFUSE, albedo_mode=ALBEDO_CONST, rho_a=albedo))
+    else:
+        recv = b.add(plane, dict(type=MAT_DIFFUSE, albedo_mode=ALBEDO_TEXTURE_RGB))
     b.point_light(light, intensity)
-    scene = b.build(Receiver(recv, 64, 64, -4.0, -4.0, 8.0, 8.0), name="plane")
+    scene = b.build(Receiver(recv, 64, 64, -4.0, -4.0, 8.0, 8.0), name="plane",
+                    tex_rgb=None if rgb is None else np.asarray(rgb, np.float32), tex_rect=(-4.0, -4.0, 8.0, 8.0))
     cam = look_at((0.0, -7.0, 5.0), (0.0, 0.0, 0.0), (0, 0, 1), 40.0, w, h)
     return scene, cam
 
