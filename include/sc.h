@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SC_ABI_VERSION 2u
+#define SC_ABI_VERSION 3u
 
 typedef int32_t sc_status;
 #define SC_OK 0
@@ -85,6 +85,9 @@ typedef struct sc_bvh sc_bvh;
 #define SC_ALBEDO_CONST 0u    /* rho_a */
 #define SC_ALBEDO_CHECKER 1u  /* 1 m squares on x,y: rho_a where floor(x)+floor(y) is even, else rho_b */
 #define SC_ALBEDO_TEXTURE 2u  /* the scene texture, nearest texel over its rectangle */
+#define SC_ALBEDO_TEXTURE_RGB 3u /* the scene's RGB texture, nearest texel: reflectance B at 450 nm,
+                                    G at 550 nm, R at 650 nm, linear in lambda between them and
+                                    constant outside; grey albedo output = (R + G + B) / 3 */
 
 typedef struct {
     uint32_t type, albedo_mode;
@@ -115,6 +118,8 @@ typedef struct {
     uint32_t recv_obj;         /* receiver object of the caustic map, 0 = none */
     uint32_t recv_wc, recv_hc; /* caustic-map cells along x and y */
     float recv_x0, recv_y0, recv_ext_u, recv_ext_v; /* receiver rectangle on x,y */
+    const float* tex_rgb;      /* device [tex_h][tex_w][3] RGB albedo, or NULL; same size and
+                                  rectangle as tex (which may then be NULL) */
 } sc_scene;
 
 typedef struct {
@@ -277,6 +282,50 @@ sc_status sc_occluded(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O
 sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, uint32_t max_depth,
                            const sc_wavelengths* wl, uint64_t seed, float* caustic_map, uint32_t* count_map,
                            sc_photon_stats* stats);
+
+/* General photon map (caustics on every diffuse surface, Sec. III-D-6):
+ * the photon pass of sc_trace_photons, but every photon that reaches a
+ * diffuse surface of any object after at least one dielectric event is
+ * stored there (position, geometric normal on its side, flux, map
+ * channel, photon index) in a hashed grid of cells 3 * radius wide.  The
+ * irradiance of channel c at a surface point x with facing normal n is
+ * the flux of the stored photons of channel c within `radius` of x on the
+ * same side (n_p . n > 0), over pi radius^2 (Jensen's density estimate
+ * with a fixed radius).  The sum is exact and order independent: each flux
+ * is taken as round(phi 2^S) in 64-bit fixed point, 2^S the largest power
+ * of two with n_stored * max(phi) * 2^S <= 2^62, and
+ * E = (float)(sum * (1 / (2^S pi radius^2))) in double.
+ * Up to 2^24 photons; radius > 0 and no stored coordinate beyond
+ * 2^16 * 3 * radius from the origin (else EUNSUPPORTED).  Synchronises.
+ * stats: host, or NULL.  The handle owns its device memory until
+ * sc_pmap_free. */
+typedef struct sc_pmap sc_pmap;
+typedef struct {
+    uint64_t n_stored;   /* photons stored */
+    float radius;
+    uint32_t channels;   /* as the wavelength setting of the pass */
+    double scale;        /* 2^S */
+    uint32_t buckets;    /* hash table size (a power of two) */
+    uint64_t bytes;      /* device memory held */
+} sc_pmap_info;
+sc_status sc_pmap_trace(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, uint32_t max_depth,
+                        const sc_wavelengths* wl, uint64_t seed, float radius, sc_pmap** out,
+                        sc_photon_stats* stats);
+sc_status sc_pmap_get_info(const sc_pmap* pm, sc_pmap_info* out);
+/* Host copies of the stored photons in photon-index order (any may be
+ * NULL): pos [n][3], nrm [n][3], phi [n], channel [n], photon [n]. */
+sc_status sc_pmap_export(const sc_pmap* pm, float* pos, float* nrm, float* phi, uint32_t* channel,
+                         uint64_t* photon);
+/* Irradiance estimates at n device points P [n][3] with facing normals
+ * N [n][3] for channels ch [n] into device E [n]. */
+sc_status sc_pmap_gather(sc_ctx* ctx, const sc_pmap* pm, uint32_t n, const float* P, const float* N,
+                         const uint32_t* ch, float* E);
+sc_status sc_pmap_free(sc_pmap* pm);
+/* sc_render with the caustic gather taken from the general photon map at
+ * every diffuse vertex (instead of the receiver map).  EINVAL if the map's
+ * channels differ from the wavelength setting's. */
+sc_status sc_render_pmap(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
+                         const sc_wavelengths* wl, uint64_t seed, const sc_pmap* pm, const sc_aov* out);
 
 /* Render spp samples per pixel with at most max_depth surface hits per
  * path.  caustic_map: device map from sc_trace_photons with the same

@@ -23,11 +23,12 @@ _lib = None
 
 # Live handles, released before the HIP runtime and PyTorch shut down: this
 # hook is registered after torch's, so it runs first.
-_live = {"batch": weakref.WeakSet(), "unet": weakref.WeakSet(), "bvh": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+_live = {"batch": weakref.WeakSet(), "unet": weakref.WeakSet(), "pmap": weakref.WeakSet(), "bvh": weakref.WeakSet(),
+         "ctx": weakref.WeakSet()}
 
 
 def _release_all():
-    for kind in ("batch", "unet", "bvh", "ctx"):
+    for kind in ("batch", "unet", "pmap", "bvh", "ctx"):
         for obj in list(_live[kind]):
             try:
                 obj.close()
@@ -43,7 +44,7 @@ SC_OPT_QUEUE_CAP = 3
 SC_OPT_STAGED_DEPTH = 4
 
 
-ABI_VERSION = 2   # must match SC_ABI_VERSION in include/sc.h
+ABI_VERSION = 3   # must match SC_ABI_VERSION in include/sc.h
 
 
 class ScError(RuntimeError):
@@ -65,7 +66,8 @@ class Scene(C.Structure):
                 ("tex", C.c_void_p), ("tex_w", C.c_uint32), ("tex_h", C.c_uint32),
                 ("tex_x0", C.c_float), ("tex_y0", C.c_float), ("tex_ext_u", C.c_float), ("tex_ext_v", C.c_float),
                 ("recv_obj", C.c_uint32), ("recv_wc", C.c_uint32), ("recv_hc", C.c_uint32),
-                ("recv_x0", C.c_float), ("recv_y0", C.c_float), ("recv_ext_u", C.c_float), ("recv_ext_v", C.c_float)]
+                ("recv_x0", C.c_float), ("recv_y0", C.c_float), ("recv_ext_u", C.c_float), ("recv_ext_v", C.c_float),
+                ("tex_rgb", C.c_void_p)]
 
 
 class BvhOpts(C.Structure):
@@ -108,6 +110,11 @@ class PhotonStats(C.Structure):
     _fields_ = [("flux", C.c_double * 9), ("count", C.c_uint64 * 9), ("segments", C.c_uint64)]
 
 
+class PmapInfo(C.Structure):
+    _fields_ = [("n_stored", C.c_uint64), ("radius", C.c_float), ("channels", C.c_uint32), ("scale", C.c_double),
+                ("buckets", C.c_uint32), ("bytes", C.c_uint64)]
+
+
 class Counters(C.Structure):
     _fields_ = [("rays_closest", C.c_uint64), ("rays_shadow", C.c_uint64), ("node_visits", C.c_uint64),
                 ("tri_tests", C.c_uint64), ("closest_launches", C.c_uint64), ("closest_ms", C.c_double),
@@ -127,7 +134,8 @@ EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set
            "sc_unet_create", "sc_unet_free", "sc_unet_num_params", "sc_unet_set_params", "sc_unet_get_params",
            "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise",
            "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch",
-           "sc_caustic_mask", "sc_outline", "sc_occlusion_boundary"]
+           "sc_caustic_mask", "sc_outline", "sc_occlusion_boundary",
+           "sc_pmap_trace", "sc_pmap_get_info", "sc_pmap_export", "sc_pmap_gather", "sc_pmap_free", "sc_render_pmap"]
 
 
 def load(path: str = LIB_PATH):
@@ -157,6 +165,13 @@ def load(path: str = LIB_PATH):
     L.sc_occluded.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
     L.sc_trace_photons.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, vp, vp, C.POINTER(PhotonStats)]
     L.sc_render.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, C.POINTER(Aov)]
+    L.sc_pmap_trace.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, C.c_float, C.POINTER(vp),
+                                C.POINTER(PhotonStats)]
+    L.sc_pmap_get_info.argtypes = [vp, C.POINTER(PmapInfo)]
+    L.sc_pmap_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.sc_pmap_gather.argtypes = [vp, vp, u32, vp, vp, vp, vp]
+    L.sc_pmap_free.argtypes = [vp]
+    L.sc_render_pmap.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, C.POINTER(Aov)]
     L.sc_caustic_mask.argtypes = [vp, vp, vp, vp, u32, u32, C.c_float, vp]
     L.sc_outline.argtypes = [vp, vp, u32, u32, u32, vp]
     L.sc_occlusion_boundary.argtypes = [vp, vp, u32, u32, C.c_float, vp]
@@ -313,7 +328,9 @@ class Context:
     def render(self, bvh: "Bvh", cam, spp: int, max_depth: int, wl, seed: int,
                caustic_map: Optional[torch.Tensor] = None, outputs=("rgb", "obj", "trans", "tri", "depth", "depthn",
                                                                       "normal", "normal_cam", "albedo"),
-               out: Optional[dict] = None):
+               out: Optional[dict] = None, pmap: Optional["PhotonMap"] = None):
+        """Render (sc_render); with pmap= the caustic gather comes from a
+        general photon map on every diffuse surface (sc_render_pmap)."""
         H, W = cam.h, cam.w
         shapes = dict(rgb=((H, W, 3), torch.float32), obj=((H, W), torch.int32), trans=((H, W), torch.uint8),
                       tri=((H, W), torch.int32), depth=((H, W), torch.float32), depthn=((H, W), torch.float32),
@@ -328,9 +345,29 @@ class Context:
             setattr(a, k, _ptr(res[k]))
         cs = camera_struct(cam)
         w = wavelengths_struct(wl)
-        _check(load().sc_render(self.h, bvh.h, C.byref(cs), int(spp), int(max_depth), C.byref(w), int(seed),
-                                _ptr(caustic_map), C.byref(a)), "sc_render")
+        if pmap is not None:
+            _check(load().sc_render_pmap(self.h, bvh.h, C.byref(cs), int(spp), int(max_depth), C.byref(w), int(seed),
+                                         pmap.h, C.byref(a)), "sc_render_pmap")
+        else:
+            _check(load().sc_render(self.h, bvh.h, C.byref(cs), int(spp), int(max_depth), C.byref(w), int(seed),
+                                    _ptr(caustic_map), C.byref(a)), "sc_render")
         return res
+
+    def pmap_trace(self, bvh: "Bvh", n_photons: int, max_depth: int, wl, seed: int, radius: float,
+                   stats: bool = False) -> "PhotonMap":
+        """General photon map: caustic photons stored on every diffuse surface
+        (sc_pmap_trace).  With stats=True the outcome statistics are kept in
+        the result's .stats."""
+        st = PhotonStats() if stats else None
+        h = C.c_void_p()
+        w = wavelengths_struct(wl)
+        _check(load().sc_pmap_trace(self.h, bvh.h, int(n_photons), int(max_depth), C.byref(w), int(seed), float(radius),
+                                    C.byref(h), C.byref(st) if st is not None else None), "sc_pmap_trace")
+        pm = PhotonMap(self, h)
+        if stats:
+            pm.stats = {k: (st.flux[i], st.count[i]) for i, k in enumerate(PH_OUTCOMES)}
+            pm.stats["segments"] = st.segments
+        return pm
 
 
 def _gt_methods():
@@ -384,6 +421,7 @@ class SceneDev:
         self.VN = _dev(scene.VN, dev) if scene.VN is not None else None
         self.tri_obj = _dev(scene.tri_obj.view(np.int32), dev)
         self.tex = _dev(scene.tex, dev) if scene.tex is not None else None
+        self.tex_rgb = _dev(scene.tex_rgb, dev) if getattr(scene, "tex_rgb", None) is not None else None
         self._mat = np.ascontiguousarray(scene.materials)
         self._pl = np.ascontiguousarray(scene.point_lights, dtype=np.float32)
         self._tgo = np.ascontiguousarray(scene.targets_obj, dtype=np.uint32)
@@ -398,6 +436,9 @@ class SceneDev:
         s.n_tg = len(self._tgo)
         if self.tex is not None:
             s.tex, s.tex_h, s.tex_w = _ptr(self.tex), scene.tex.shape[0], scene.tex.shape[1]
+            s.tex_x0, s.tex_y0, s.tex_ext_u, s.tex_ext_v = scene.tex_rect
+        if self.tex_rgb is not None:
+            s.tex_rgb, s.tex_h, s.tex_w = _ptr(self.tex_rgb), scene.tex_rgb.shape[0], scene.tex_rgb.shape[1]
             s.tex_x0, s.tex_y0, s.tex_ext_u, s.tex_ext_v = scene.tex_rect
         r = scene.receiver
         if r is not None:
@@ -449,6 +490,51 @@ class Bvh:
     def close(self):
         if getattr(self, "h", None):
             load().sc_bvh_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PhotonMap:
+    """A general photon map on the device (sc_pmap_*)."""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx = ctx
+        self.h = h
+        self.stats = None
+        _live["pmap"].add(self)
+
+    def info(self) -> dict:
+        i = PmapInfo()
+        _check(load().sc_pmap_get_info(self.h, C.byref(i)), "sc_pmap_get_info")
+        return {k: getattr(i, k) for k, _ in PmapInfo._fields_}
+
+    def export(self) -> dict:
+        """Host copies of the stored photons in photon-index order."""
+        n = self.info()["n_stored"]
+        out = dict(pos=np.zeros((n, 3), np.float32), nrm=np.zeros((n, 3), np.float32), phi=np.zeros(n, np.float32),
+                   channel=np.zeros(n, np.uint32), photon=np.zeros(n, np.uint64))
+        _check(load().sc_pmap_export(self.h, *[out[k].ctypes.data for k in ("pos", "nrm", "phi", "channel", "photon")]),
+               "sc_pmap_export")
+        return out
+
+    def gather(self, P: torch.Tensor, N: torch.Tensor, ch: torch.Tensor) -> torch.Tensor:
+        """Irradiance estimates at device points P [n, 3] with facing normals
+        N [n, 3] for channels ch [n] (int32)."""
+        n = P.shape[0]
+        E = torch.empty(n, dtype=torch.float32, device=self.ctx.device)
+        _check(load().sc_pmap_gather(self.ctx.h, self.h, n, _ptr(P), _ptr(N), _ptr(ch), _ptr(E)), "sc_pmap_gather")
+        return E
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().sc_pmap_free(self.h)
             self.h = None
 
     def __del__(self):

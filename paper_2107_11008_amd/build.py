@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsc.so")
-SOURCES = ["api.hip", "bvh.hip", "trace.hip", "unet.hip", "batch.hip", "gt.hip"]
+SOURCES = ["api.hip", "bvh.hip", "trace.hip", "pmap.hip", "unet.hip", "batch.hip", "gt.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -161,9 +161,11 @@ sc_status check_scene(const sc_scene* sc) {
                     return set_error(SC_EINVAL, "dielectric absorption must be finite and >= 0");
             if (!(m.roughness >= 0.0f && m.roughness <= 1.0f)) return set_error(SC_EINVAL, "roughness must be in [0, 1]");
         }
-        if (m.type == SC_MAT_DIFFUSE && m.albedo_mode > SC_ALBEDO_TEXTURE) return set_error(SC_EINVAL, "unknown albedo mode");
+        if (m.type == SC_MAT_DIFFUSE && m.albedo_mode > SC_ALBEDO_TEXTURE_RGB) return set_error(SC_EINVAL, "unknown albedo mode");
         if (m.type == SC_MAT_DIFFUSE && m.albedo_mode == SC_ALBEDO_TEXTURE && !sc->tex)
             return set_error(SC_EINVAL, "texture albedo without a texture");
+        if (m.type == SC_MAT_DIFFUSE && m.albedo_mode == SC_ALBEDO_TEXTURE_RGB && !sc->tex_rgb)
+            return set_error(SC_EINVAL, "RGB texture albedo without an RGB texture");
     }
     if (sc->n_pl && !sc->point_lights) return set_error(SC_EINVAL, "point_lights is NULL");
     if (sc->n_tg && (!sc->targets_obj || !sc->targets_sphere)) return set_error(SC_EINVAL, "photon targets are NULL");
@@ -172,7 +174,7 @@ sc_status check_scene(const sc_scene* sc) {
         if (sc->recv_wc == 0 || sc->recv_hc == 0 || !(sc->recv_ext_u > 0.0f) || !(sc->recv_ext_v > 0.0f))
             return set_error(SC_EINVAL, "receiver needs cells and a positive extent");
     }
-    if (sc->tex && (sc->tex_w == 0 || sc->tex_h == 0 || !(sc->tex_ext_u > 0.0f) || !(sc->tex_ext_v > 0.0f)))
+    if ((sc->tex || sc->tex_rgb) && (sc->tex_w == 0 || sc->tex_h == 0 || !(sc->tex_ext_u > 0.0f) || !(sc->tex_ext_v > 0.0f)))
         return set_error(SC_EINVAL, "texture needs a size and a positive extent");
     return SC_OK;
 }
@@ -245,9 +247,11 @@ sc_status build_into(scl::Ctx* c, scl::Bvh* b, const sc_scene* sc, uint32_t widt
     D.mat = b->mat.as<sc_material>(); D.n_mat = sc->n_mat;
     D.pl = b->pl.as<float>(); D.n_pl = sc->n_pl;
     D.tg = b->tg.as<float>(); D.n_tg = sc->n_tg;
-    D.tex = sc->tex; D.tex_w = sc->tex_w; D.tex_h = sc->tex_h; D.tex_x0 = sc->tex_x0; D.tex_y0 = sc->tex_y0;
-    D.tex_sx = sc->tex ? (float)sc->tex_w / sc->tex_ext_u : 0.0f;
-    D.tex_sy = sc->tex ? (float)sc->tex_h / sc->tex_ext_v : 0.0f;
+    D.tex = sc->tex; D.tex_rgb = sc->tex_rgb;
+    D.tex_w = sc->tex_w; D.tex_h = sc->tex_h; D.tex_x0 = sc->tex_x0; D.tex_y0 = sc->tex_y0;
+    const bool any_tex = sc->tex || sc->tex_rgb;
+    D.tex_sx = any_tex ? (float)sc->tex_w / sc->tex_ext_u : 0.0f;
+    D.tex_sy = any_tex ? (float)sc->tex_h / sc->tex_ext_v : 0.0f;
     D.recv_obj = sc->recv_obj; D.recv_wc = sc->recv_wc; D.recv_hc = sc->recv_hc;
     D.recv_x0 = sc->recv_x0; D.recv_y0 = sc->recv_y0;
     D.cell_sx = sc->recv_obj ? (float)sc->recv_wc / sc->recv_ext_u : 0.0f;
@@ -351,6 +355,74 @@ sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, u
     if (stats) memset(stats, 0, sizeof(*stats));
     return scl::trace_photons(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n_photons, max_depth, *wl, seed, caustic_map,
                               count_map, stats);
+}
+
+sc_status sc_pmap_trace(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, uint32_t max_depth,
+                        const sc_wavelengths* wl, uint64_t seed, float radius, sc_pmap** out, sc_photon_stats* stats) {
+    if (!ctx || !bvh || !out) return set_error(SC_EINVAL, "ctx, bvh or out is NULL");
+    *out = nullptr;
+    SC_TRY(check_built(bvh));
+    SC_TRY(check_wavelengths(wl));
+    if (max_depth == 0) return set_error(SC_EINVAL, "max_depth must be >= 1");
+    if (stats) memset(stats, 0, sizeof(*stats));
+    sc_pmap* h = new (std::nothrow) sc_pmap();
+    if (!h) return set_error(SC_ENOMEM, "host allocation failed");
+    const sc_status s = scl::pmap_trace(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n_photons, max_depth, *wl, seed,
+                                        radius, &h->p, stats);
+    if (s != SC_OK) {
+        delete h;
+        return s;
+    }
+    *out = h;
+    return SC_OK;
+}
+
+sc_status sc_pmap_get_info(const sc_pmap* pm, sc_pmap_info* out) {
+    if (!pm || !out) return set_error(SC_EINVAL, "pmap or out is NULL");
+    out->n_stored = pm->p.n;
+    out->radius = pm->p.radius;
+    out->channels = pm->p.channels;
+    out->scale = pm->p.scale;
+    out->buckets = pm->p.buckets;
+    out->bytes = pm->p.mem.bytes;
+    return SC_OK;
+}
+
+sc_status sc_pmap_export(const sc_pmap* pm, float* pos, float* nrm, float* phi, uint32_t* channel, uint64_t* photon) {
+    if (!pm) return set_error(SC_EINVAL, "pmap is NULL");
+    return scl::pmap_export(&pm->p, pos, nrm, phi, channel, photon);
+}
+
+sc_status sc_pmap_gather(sc_ctx* ctx, const sc_pmap* pm, uint32_t n, const float* P, const float* N,
+                         const uint32_t* ch, float* E) {
+    if (!ctx || !pm) return set_error(SC_EINVAL, "ctx or pmap is NULL");
+    if (n && (!P || !N || !ch || !E)) return set_error(SC_EINVAL, "gather arrays are NULL");
+    if (pm->p.ctx != &ctx->c) return set_error(SC_EINVAL, "pmap belongs to another context");
+    return scl::pmap_gather(&ctx->c, &pm->p, n, P, N, ch, E);
+}
+
+sc_status sc_pmap_free(sc_pmap* pm) {
+    if (pm) {
+        if (pm->p.ctx) (void)hipStreamSynchronize(pm->p.ctx->stream);
+        delete pm;
+    }
+    return SC_OK;
+}
+
+sc_status sc_render_pmap(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
+                         const sc_wavelengths* wl, uint64_t seed, const sc_pmap* pm, const sc_aov* out) {
+    if (!ctx || !bvh || !cam || !out || !pm) return set_error(SC_EINVAL, "ctx, bvh, camera, pmap or out is NULL");
+    SC_TRY(check_built(bvh));
+    SC_TRY(check_wavelengths(wl));
+    if (spp == 0) return set_error(SC_EINVAL, "spp must be >= 1");
+    if (max_depth == 0) return set_error(SC_EINVAL, "max_depth must be >= 1");
+    if (cam->w == 0 || cam->h == 0) return set_error(SC_EINVAL, "camera has no pixels");
+    if ((uint64_t)cam->w * cam->h > (1ull << 28)) return set_error(SC_EUNSUPPORTED, "image too large");
+    if (pm->p.ctx != &ctx->c) return set_error(SC_EINVAL, "pmap belongs to another context");
+    const uint32_t ch = wl->mode == SC_WL_FIXED ? wl->k : wl->bins;
+    if (ch != pm->p.channels) return set_error(SC_EINVAL, "the photon map has other channels than the wavelength setting");
+    return scl::render(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), *cam, spp, max_depth, *wl, seed, nullptr, *out,
+                       &pm->p.dev);
 }
 
 sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,

@@ -57,9 +57,9 @@ __global__ __launch_bounds__(BS) void k_batch_photons(const BatchScene* __restri
             PhotonPath ph;
             if (!photon_emit(bs.S, bs.wl, bs.photon_seed, bs.n_photons, p, ph)) continue;
             uint32_t n_cl = 0;
-            photon_continue<BS>(bs.S, bs.wl, bs.photon_seed, p, 1, bs.max_depth, ph, lds, st, vc, n_cl,
-                                [&](int64_t cc, const PhotonPath& q) {
-                                    atomicAdd(&bs.acc[cc], __double2ull_rn((double)q.phi * bs.scale));
+            photon_continue<BS>(bs.S, bs.wl, bs.photon_seed, p, 1, bs.max_depth, false, ph, lds, st, vc, n_cl,
+                                [&](const Deposit& dp, const PhotonPath& q) {
+                                    atomicAdd(&bs.acc[dp.cell_ch], __double2ull_rn((double)q.phi * bs.scale));
                                 });
         }
     }
@@ -89,8 +89,8 @@ __global__ __launch_bounds__(BS) void k_batch_render(const BatchScene* __restric
                     for (uint32_t slot = 0; slot < bs.K; ++slot) {
                         CamPath P = camera_start(bs.cam, bs.wl, bs.seed, pix, sample, slot);
                         uint32_t n_cl = 0, n_sh = 0;
-                        camera_continue<BS, false>(bs.S, bs.wl, bs.cmap, bs.seed, pix, sample, slot, 1, bs.max_depth, P,
-                                                   lds, st, vc, n_cl, n_sh);
+                        camera_continue<BS, false>(bs.S, bs.wl, bs.cmap, PMapDev{}, bs.seed, pix, sample, slot, 1,
+                                                   bs.max_depth, P, lds, st, vc, n_cl, n_sh);
                         film_add(bs.wl, bs.K, slot, P.L, P.lam, acc);
                     }
                 }

@@ -439,20 +439,42 @@ __device__ __forceinline__ float absorption(const sc_material& m, float lam) {
 }
 
 // ---------------------------------------------------------------- scene lookups
-__device__ __forceinline__ float albedo(const DevScene& S, const sc_material& m, F3 P) {
+// nearest texel of the texture rectangle under P, edges clamped
+__device__ __forceinline__ size_t texel(const DevScene& S, F3 P) {
+    const float fx = (P.x - S.tex_x0) * S.tex_sx;
+    const float fy = (P.y - S.tex_y0) * S.tex_sy;
+    int i = (int)floorf(fx), j = (int)floorf(fy);
+    i = i < 0 ? 0 : (i > (int)S.tex_w - 1 ? (int)S.tex_w - 1 : i);
+    j = j < 0 ? 0 : (j > (int)S.tex_h - 1 ? (int)S.tex_h - 1 : j);
+    return (size_t)j * S.tex_w + (size_t)i;
+}
+
+// albedo at P for wavelength lam; an RGB texel is reflectance B at 450 nm,
+// G at 550 nm and R at 650 nm, linear in lambda between, constant outside
+__device__ __forceinline__ float albedo(const DevScene& S, const sc_material& m, F3 P, float lam) {
     if (m.albedo_mode == SC_ALBEDO_CHECKER) {
         const int ix = (int)floorf(P.x), iy = (int)floorf(P.y);
         return ((ix + iy) & 1) == 0 ? m.rho_a : m.rho_b;
     }
-    if (m.albedo_mode == SC_ALBEDO_TEXTURE && S.tex) {
-        const float fx = (P.x - S.tex_x0) * S.tex_sx;
-        const float fy = (P.y - S.tex_y0) * S.tex_sy;
-        int i = (int)floorf(fx), j = (int)floorf(fy);
-        i = i < 0 ? 0 : (i > (int)S.tex_w - 1 ? (int)S.tex_w - 1 : i);
-        j = j < 0 ? 0 : (j > (int)S.tex_h - 1 ? (int)S.tex_h - 1 : j);
-        return S.tex[(size_t)j * S.tex_w + (size_t)i];
+    if (m.albedo_mode == SC_ALBEDO_TEXTURE && S.tex) return S.tex[texel(S, P)];
+    if (m.albedo_mode == SC_ALBEDO_TEXTURE_RGB && S.tex_rgb) {
+        const float* c = S.tex_rgb + 3 * texel(S, P);
+        const float r = c[0], g = c[1], b = c[2];
+        if (lam <= 450.0f) return b;
+        if (lam >= 650.0f) return r;
+        if (lam < 550.0f) return b + (g - b) * ((lam - 450.0f) / 100.0f);
+        return g + (r - g) * ((lam - 550.0f) / 100.0f);
     }
     return m.rho_a;
+}
+
+// grey albedo of the ground-truth output: the mean of an RGB texel
+__device__ __forceinline__ float albedo_grey(const DevScene& S, const sc_material& m, F3 P) {
+    if (m.albedo_mode == SC_ALBEDO_TEXTURE_RGB && S.tex_rgb) {
+        const float* c = S.tex_rgb + 3 * texel(S, P);
+        return ((c[0] + c[1]) + c[2]) / 3.0f;
+    }
+    return albedo(S, m, P, 550.0f);
 }
 
 // receiver cell (floor rule, upper edge clamped); -1 outside the rectangle

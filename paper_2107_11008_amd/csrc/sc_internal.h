@@ -100,6 +100,8 @@ struct Ctx {
     uint32_t sensor_n = 0;
     DevBuf aos;        // SoA copies for sc_trace_rays / sc_occluded
     DevBuf bvh_tmp;    // temporaries of the BVH builder (grow-only, reused)
+    DevBuf pm_rec;     // records of a general photon map pass (grow-only)
+    DevBuf pm_tmp;     // bucket ids, counts, cursors and scan sums of the photon map build
     size_t aos_n = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;   // recorded, not yet read
     std::vector<hipEvent_t> event_pool;                       // read, free for reuse
@@ -117,6 +119,19 @@ struct Bvh {
     float max_power = 0.0f;
 };
 
+// A general photon map: stored photons counting-sorted into hash buckets.
+struct Pmap {
+    Ctx* ctx = nullptr;
+    DevBuf mem;                              // sorted records and bucket starts
+    PMapDev dev{};                           // device view
+    const float* phi = nullptr;              // sorted fluxes (export)
+    const unsigned long long* photon = nullptr;   // sorted photon indices (export)
+    uint64_t n = 0;
+    float radius = 0.0f;
+    uint32_t channels = 0, buckets = 0;
+    double scale = 1.0;
+};
+
 // Builds b->nodes and b->tris for b->scene_in (b->mat must already hold the
 // materials on the device).  Also returns the emissive triangles in index
 // order with their vertices (9 floats each).  Synchronises the stream.
@@ -130,4 +145,7 @@ struct sc_ctx {
 };
 struct sc_bvh {
     scl::Bvh b;
+};
+struct sc_pmap {
+    scl::Pmap p;
 };

@@ -28,10 +28,18 @@ struct ShadowSoA {
 
 namespace scl {
 
+// pmap: general photon map for the caustic gather, or null (receiver map cmap)
 sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t max_depth, const sc_wavelengths& wl,
-                 uint64_t seed, const float* cmap, const sc_aov& out);
+                 uint64_t seed, const float* cmap, const sc_aov& out, const PMapDev* pmap = nullptr);
+// rec: records of a general photon map (deposits on every diffuse surface),
+// or null (receiver map)
 sc_status trace_photons(Ctx* c, Bvh* b, uint64_t n_photons, uint32_t max_depth, const sc_wavelengths& wl,
-                        uint64_t seed, float* map, uint32_t* count_map, sc_photon_stats* stats);
+                        uint64_t seed, float* map, uint32_t* count_map, sc_photon_stats* stats,
+                        const PmRecords* rec = nullptr);
+sc_status pmap_trace(Ctx* c, Bvh* b, uint64_t n_photons, uint32_t max_depth, const sc_wavelengths& wl, uint64_t seed,
+                     float radius, Pmap* pm, sc_photon_stats* stats);
+sc_status pmap_export(const Pmap* pm, float* pos, float* nrm, float* phi, uint32_t* channel, uint64_t* photon);
+sc_status pmap_gather(Ctx* c, const Pmap* pm, uint32_t n, const float* P, const float* N, const uint32_t* ch, float* E);
 sc_status trace_rays(Ctx* c, Bvh* b, uint32_t n, const float* O, const float* D, float* t, uint32_t* prim, float* u,
                      float* v);
 sc_status occluded(Ctx* c, Bvh* b, uint32_t n, const float* O, const float* D, const float* tmax,

@@ -385,6 +385,51 @@ __device__ __forceinline__ float medium_weight(const DevScene& S, uint64_t M, fl
     return exp_neg(sg * t);
 }
 
+// ---------------------------------------------------------------- general photon map
+// Irradiance of channel ch at P (facing normal N): the fixed-point flux of
+// the stored photons of that channel on the same side (n_p . N > 0) within
+// r of P, times 1 / (2^S pi r^2).  The cells (3 r wide) overlapping the box
+// P +- 1.1 r, at most 2 per axis, are visited through their buckets; a
+// record counts only in its own cell, so a bucket shared by two visited
+// cells is not counted twice.  The integer sum does not depend on the
+// order of the records.  Points more than 2^20 cells from the origin are
+// far from every stored photon (those lie within 2^16 cells).
+__device__ __forceinline__ int pm_cell(float v, float inv_h) { return (int)floorf(v * inv_h); }
+
+__device__ __forceinline__ uint32_t pm_bucket(int x, int y, int z, uint32_t ch, uint32_t mask) {
+    return (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u) ^ (ch * 2654435761u)) &
+           mask;
+}
+
+__device__ __forceinline__ float pmap_gather(const PMapDev& pm, F3 P, F3 N, uint32_t ch) {
+    const float lim = 1048576.0f;
+    if (!(fabsf(P.x * pm.inv_h) < lim && fabsf(P.y * pm.inv_h) < lim && fabsf(P.z * pm.inv_h) < lim)) return 0.0f;
+    const float rr = pm.r * 1.1f;
+    const int x0 = pm_cell(P.x - rr, pm.inv_h), x1 = min(pm_cell(P.x + rr, pm.inv_h), x0 + 1);
+    const int y0 = pm_cell(P.y - rr, pm.inv_h), y1 = min(pm_cell(P.y + rr, pm.inv_h), y0 + 1);
+    const int z0 = pm_cell(P.z - rr, pm.inv_h), z1 = min(pm_cell(P.z + rr, pm.inv_h), z0 + 1);
+    unsigned long long sum = 0ull;
+    for (int z = z0; z <= z1; ++z) {
+        for (int y = y0; y <= y1; ++y) {
+            for (int x = x0; x <= x1; ++x) {
+                const uint32_t b = pm_bucket(x, y, z, ch, pm.mask);
+                const uint32_t e = pm.start[b + 1];
+                for (uint32_t k = pm.start[b]; k < e; ++k) {
+                    if (pm.ch[k] != ch) continue;
+                    const F3 q{pm.px[k], pm.py[k], pm.pz[k]};
+                    if (pm_cell(q.x, pm.inv_h) != x || pm_cell(q.y, pm.inv_h) != y || pm_cell(q.z, pm.inv_h) != z)
+                        continue;
+                    const F3 n{pm.nx[k], pm.ny[k], pm.nz[k]};
+                    if (!(dot(n, N) > 0.0f)) continue;
+                    const F3 dl = q - P;
+                    if (dot(dl, dl) < pm.r2) sum += pm.q[k];
+                }
+            }
+        }
+    }
+    return (float)((double)sum * pm.c);
+}
+
 struct CamPath {
     F3 o, d;
     float T, L, lam;
@@ -462,19 +507,25 @@ __device__ __forceinline__ bool camera_dielectric(const DevScene& S, uint64_t se
 // shadow ray (its contribution is added if unoccluded), cosine-weighted
 // bounce; false if the path ends here
 __device__ __forceinline__ bool camera_diffuse(const DevScene& S, const WaveDev& wl, const float* __restrict__ cmap,
-                                               uint64_t seed, uint32_t pix, uint32_t sample, uint32_t slot,
-                                               uint32_t depth, uint32_t max_depth, const HitRec& h, CamPath& P,
-                                               ShadowReq& sr) {
+                                               const PMapDev& pm, uint64_t seed, uint32_t pix, uint32_t sample,
+                                               uint32_t slot, uint32_t depth, uint32_t max_depth, const HitRec& h,
+                                               CamPath& P, ShadowReq& sr) {
     const uint32_t obj = S.tri_obj[h.prim];
     const Frame f = hit_frame(S, h.prim, h.u, h.v, P.d);
     const sc_material m = S.mat[obj];
-    const float rho = albedo(S, m, f.P);
+    const float rho = albedo(S, m, f.P, P.lam);
     const float T = P.T * medium_weight(S, P.med, P.lam, h.t);
     P.flags = P.flags | 1u;
     const F3 os = offset_ray(f.P, f.Nf);
     sr.shoot = false;
-    // caustic gather
-    if (cmap && S.recv_obj && obj == S.recv_obj) {
+    // caustic gather: the general photon map on every diffuse surface, else
+    // the receiver map cell under the point
+    if (pm.on) {
+        const uint32_t b = wl.mode == SC_WL_FIXED ? slot : spectral_bin(wl, P.lam);
+        const float E = pmap_gather(pm, f.P, f.Nf, b);
+        const float g = ((T * rho) * kInvPi) * E;
+        P.L = P.L + g;
+    } else if (cmap && S.recv_obj && obj == S.recv_obj) {
         const int64_t cell = receiver_cell(S, f.P);
         if (cell >= 0) {
             const uint32_t b = wl.mode == SC_WL_FIXED ? slot : spectral_bin(wl, P.lam);
@@ -572,7 +623,7 @@ __device__ __forceinline__ void aov_write(const DevScene& S, const sc_camera& ca
         depn = fminf(h.t / 10.0f, 1.0f);
         N = f.Ns;
         Nc = F3{dot(N, Rh), dot(N, Uh), -dot(N, Fh)};
-        alb = m.type == SC_MAT_DIFFUSE ? albedo(S, m, f.P) : (m.type == SC_MAT_DIELECTRIC ? 1.0f : 0.0f);
+        alb = m.type == SC_MAT_DIFFUSE ? albedo_grey(S, m, f.P) : (m.type == SC_MAT_DIELECTRIC ? 1.0f : 0.0f);
         trans = m.type == SC_MAT_DIELECTRIC ? 1 : 0;
     }
     if (out.obj) out.obj[pix] = obj;
@@ -695,12 +746,21 @@ __device__ __forceinline__ bool photon_emit(const DevScene& S, const WaveDev& wl
     return alive;
 }
 
+// A deposit: receiver-map index (cell * channels + channel), or for the
+// general map the channel with the point and the geometric normal on the
+// photon's side; cell_ch = -1 for none.
+struct Deposit {
+    int64_t cell_ch;
+    F3 P, N;
+};
+
 // One photon interaction.  Returns true if the photon continues; sets
-// outcome (SC_PH_*) when it ends, and cell_ch >= 0 for a deposit.
+// outcome (SC_PH_*) when it ends, and dp.cell_ch >= 0 for a deposit (on the
+// receiver, or with `general` on any diffuse surface).
 __device__ __forceinline__ bool photon_event(const DevScene& S, const WaveDev& wl, uint64_t seed, uint64_t p,
-                                             uint32_t depth, uint32_t max_depth, const HitRec& h, PhotonPath& ph,
-                                             int& outcome, int64_t& cell_ch) {
-    cell_ch = -1;
+                                             uint32_t depth, uint32_t max_depth, bool general, const HitRec& h,
+                                             PhotonPath& ph, int& outcome, Deposit& dp) {
+    dp.cell_ch = -1;
     if (h.prim == 0xffffffffu) {
         outcome = SC_PH_ESCAPED;
         return false;
@@ -746,6 +806,11 @@ __device__ __forceinline__ bool photon_event(const DevScene& S, const WaveDev& w
     }
     if (ph.spec == 0u) {
         outcome = SC_PH_DIRECT;
+    } else if (general) {
+        outcome = SC_PH_DEPOSITED;
+        dp.cell_ch = (int64_t)ph.slot;
+        dp.P = f.P;
+        dp.N = f.Nf;
     } else if (obj != S.recv_obj) {
         outcome = SC_PH_ELSEWHERE;
     } else {
@@ -754,7 +819,7 @@ __device__ __forceinline__ bool photon_event(const DevScene& S, const WaveDev& w
             outcome = SC_PH_OUTSIDE;
         } else {
             outcome = SC_PH_DEPOSITED;
-            cell_ch = cell * (int64_t)wl.channels + (int64_t)ph.slot;
+            dp.cell_ch = cell * (int64_t)wl.channels + (int64_t)ph.slot;
         }
     }
     return false;
@@ -767,10 +832,11 @@ __device__ __forceinline__ bool photon_event(const DevScene& S, const WaveDev& w
 // and caustic gather): P.L is final on return.  n_closest and n_shadow
 // count the rays traced.
 template <int BS, bool COUNT>
-__device__ __forceinline__ void camera_continue(const DevScene& S, const WaveDev& wl, const float* cmap, uint64_t seed,
-                                                uint32_t pix, uint32_t sample, uint32_t slot, uint32_t depth0,
-                                                uint32_t max_depth, CamPath& P, uint2 (*lds)[BS], Spill& st,
-                                                VisitCount& vc, uint32_t& n_closest, uint32_t& n_shadow) {
+__device__ __forceinline__ void camera_continue(const DevScene& S, const WaveDev& wl, const float* cmap,
+                                                const PMapDev& pm, uint64_t seed, uint32_t pix, uint32_t sample,
+                                                uint32_t slot, uint32_t depth0, uint32_t max_depth, CamPath& P,
+                                                uint2 (*lds)[BS], Spill& st, VisitCount& vc, uint32_t& n_closest,
+                                                uint32_t& n_shadow) {
     for (uint32_t depth = depth0; depth <= max_depth; ++depth) {
         const HitRec h = trace_closest<BS, COUNT>(S, P.o, P.d, lds, st, vc);
         ++n_closest;
@@ -785,7 +851,7 @@ __device__ __forceinline__ void camera_continue(const DevScene& S, const WaveDev
             continue;
         }
         ShadowReq sr;
-        const bool cont = camera_diffuse(S, wl, cmap, seed, pix, sample, slot, depth, max_depth, h, P, sr);
+        const bool cont = camera_diffuse(S, wl, cmap, pm, seed, pix, sample, slot, depth, max_depth, h, P, sr);
         if (sr.shoot) {
             ++n_shadow;
             if (!trace_any<BS>(S, sr.o, sr.d, sr.tmax, sr.excl, lds, st)) P.L = P.L + sr.contrib;
@@ -795,19 +861,20 @@ __device__ __forceinline__ void camera_continue(const DevScene& S, const WaveDev
 }
 
 // A photon from its current ray at surface hit depth0 to its end; every
-// deposit is handed to dep(cell_channel, photon).  Returns the outcome of
-// the last event; n_closest counts the rays traced.
+// deposit is handed to dep(deposit, photon).  Returns the outcome of the
+// last event; n_closest counts the rays traced.
 template <int BS, class Dep>
 __device__ __forceinline__ int photon_continue(const DevScene& S, const WaveDev& wl, uint64_t seed, uint64_t p,
-                                               uint32_t depth0, uint32_t max_depth, PhotonPath& ph, uint2 (*lds)[BS],
-                                               Spill& st, VisitCount& vc, uint32_t& n_closest, Dep dep) {
+                                               uint32_t depth0, uint32_t max_depth, bool general, PhotonPath& ph,
+                                               uint2 (*lds)[BS], Spill& st, VisitCount& vc, uint32_t& n_closest,
+                                               Dep dep) {
     for (uint32_t depth = depth0; depth <= max_depth; ++depth) {
         const HitRec h = trace_closest<BS, false>(S, ph.o, ph.d, lds, st, vc);
         ++n_closest;
         int outcome = -1;
-        int64_t cc = -1;
-        const bool cont = photon_event(S, wl, seed, p, depth, max_depth, h, ph, outcome, cc);
-        if (cc >= 0) dep(cc, ph);
+        Deposit dp;
+        const bool cont = photon_event(S, wl, seed, p, depth, max_depth, general, h, ph, outcome, dp);
+        if (dp.cell_ch >= 0) dep(dp, ph);
         if (!cont) return outcome;
     }
     return -1;

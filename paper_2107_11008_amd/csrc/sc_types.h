@@ -35,6 +35,7 @@ struct DevScene {
     const float* tg;      // [n_tg][4]
     uint32_t n_tg;
     const float* tex;
+    const float* tex_rgb;   // [tex_h][tex_w][3] or null
     uint32_t tex_w, tex_h;
     float tex_x0, tex_y0, tex_sx, tex_sy;
     uint32_t recv_obj, recv_wc, recv_hc;
@@ -88,6 +89,28 @@ struct PhotonState {
     uint64_t* med;    // media set (nested dielectrics)
     float *t, *u, *v;
     uint32_t* prim;
+};
+
+// device view of a general photon map: stored photons sorted into hash
+// buckets of (cell, channel), cells 3 r wide
+struct PMapDev {
+    const float *px, *py, *pz, *nx, *ny, *nz;
+    const unsigned long long* q;   // flux in fixed point, round(phi 2^S)
+    const uint32_t* ch;
+    const uint32_t* start;         // [buckets + 1] first record of each bucket
+    uint32_t mask;                 // buckets - 1
+    uint32_t on;                   // 0: caustics from the receiver map instead
+    float r, r2, inv_h;            // radius, radius^2, 1 / cell width
+    double c;                      // 1 / (2^S pi r^2)
+};
+
+// photons appended by a general-map photon pass
+struct PmRecords {
+    float *px, *py, *pz, *nx, *ny, *nz, *phi;
+    uint32_t* ch;
+    unsigned long long* photon;
+    uint32_t* stat;   // [0] records, [1] largest flux (bits), [2] largest |coordinate| (bits)
+    uint32_t cap;
 };
 
 struct Queues {

@@ -328,8 +328,8 @@ __global__ void k_shade_dielectric(DevScene S, CamInfo ci, PathState P, uint32_t
 }
 
 __global__ void k_shade_diffuse(DevScene S, CamInfo ci, WaveDev wl, PathState P, uint32_t depth,
-                                const float* __restrict__ cmap, const uint32_t* __restrict__ q, uint32_t* counts,
-                                uint32_t* q_next, uint32_t* q_shadow) {
+                                const float* __restrict__ cmap, PMapDev pm, const uint32_t* __restrict__ q,
+                                uint32_t* counts, uint32_t* q_next, uint32_t* q_shadow) {
     const uint32_t n = counts[QC_DIFF];
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
@@ -343,7 +343,8 @@ __global__ void k_shade_diffuse(DevScene S, CamInfo ci, WaveDev wl, PathState P,
             uint32_t pix, sample, slot;
             pid_decode(ci, pid, pix, sample, slot);
             CamPath c = load_path(P, pid);
-            cont = camera_diffuse(S, wl, cmap, ci.seed, pix, sample, slot, depth, ci.max_depth, load_hit(P, pid), c, sr);
+            cont = camera_diffuse(S, wl, cmap, pm, ci.seed, pix, sample, slot, depth, ci.max_depth, load_hit(P, pid), c,
+                                  sr);
             P.L[pid] = c.L;
             P.flags[pid] = c.flags;
             if (sr.shoot) {
@@ -410,6 +411,8 @@ struct PhInfo {
     uint32_t max_depth;
     double scale;       // fixed-point scale of the caustic accumulator
     int stats;
+    int general;        // deposits go to rec (general photon map) instead of the receiver map
+    PmRecords rec;
 };
 
 __device__ __forceinline__ void ph_stat(DevCounters* C, const PhInfo& pi, int outcome, float phi) {
@@ -464,6 +467,45 @@ __device__ __forceinline__ void deposit(bool want, uint32_t cell, unsigned long 
     }
 }
 
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    return v;
+}
+
+// Store one photon of a general photon map: one counter atomic per wave.
+// Flux and coordinates are non-negative or compared by magnitude, so their
+// maxima are tracked on the float bits.
+__device__ __forceinline__ void pm_store(const PmRecords& R, uint32_t k, const Deposit& dp, uint32_t ch, float phi,
+                                         uint64_t photon) {
+    if (k >= R.cap) return;
+    R.px[k] = dp.P.x; R.py[k] = dp.P.y; R.pz[k] = dp.P.z;
+    R.nx[k] = dp.N.x; R.ny[k] = dp.N.y; R.nz[k] = dp.N.z;
+    R.phi[k] = phi;
+    R.ch[k] = ch;
+    R.photon[k] = photon;
+}
+
+__device__ __forceinline__ uint32_t pm_extent_bits(const Deposit& dp) {
+    return __float_as_uint(fmaxf(fabsf(dp.P.x), fmaxf(fabsf(dp.P.y), fabsf(dp.P.z))));
+}
+
+__device__ __forceinline__ void pm_append(bool want, const PmRecords& R, const Deposit& dp, uint32_t ch, float phi,
+                                          uint64_t photon) {
+    const unsigned long long m = __ballot(want);
+    if (m == 0ull) return;
+    const uint32_t leader = __ffsll((long long)m) - 1;
+    const uint32_t mphi = wave_max_u32(want ? __float_as_uint(phi) : 0u);
+    const uint32_t mext = wave_max_u32(want ? pm_extent_bits(dp) : 0u);
+    uint32_t base = 0;
+    if (lane_id() == leader) {
+        base = atomicAdd(&R.stat[0], (uint32_t)__popcll(m));
+        atomicMax(&R.stat[1], mphi);
+        atomicMax(&R.stat[2], mext);
+    }
+    base = __shfl(base, (int)leader);
+    if (want) pm_store(R, base + lanes_below(m), dp, ch, phi, photon);
+}
+
 __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth, PhotonState Ph,
                                const uint32_t* __restrict__ queue, uint32_t* counts, uint32_t* q_next,
                                unsigned long long* acc, uint32_t* cnt_map, DevCounters* C) {
@@ -474,6 +516,9 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
         bool cont = false, dep = false;
         uint32_t id = 0, cell_ch = 0;
         unsigned long long q = 0;
+        float phi = 0.0f;
+        Deposit dp;
+        dp.cell_ch = -1;
         if (i < n) {
             id = queue[i];
             PhotonPath ph;
@@ -485,9 +530,8 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
             ph.spec = Ph.spec[id];
             ph.med = Ph.med[id];
             int outcome = -1;
-            int64_t cc = -1;
-            cont = photon_event(S, wl, pi.seed, pi.p0 + id, depth, pi.max_depth,
-                                HitRec{Ph.t[id], Ph.u[id], Ph.v[id], Ph.prim[id]}, ph, outcome, cc);
+            cont = photon_event(S, wl, pi.seed, pi.p0 + id, depth, pi.max_depth, pi.general != 0,
+                                HitRec{Ph.t[id], Ph.u[id], Ph.v[id], Ph.prim[id]}, ph, outcome, dp);
             if (cont) {
                 Ph.ox[id] = ph.o.x; Ph.oy[id] = ph.o.y; Ph.oz[id] = ph.o.z;
                 Ph.dx[id] = ph.d.x; Ph.dy[id] = ph.d.y; Ph.dz[id] = ph.d.z;
@@ -496,13 +540,15 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
                 Ph.med[id] = ph.med;
             }
             if (!cont) ph_stat(C, pi, outcome, ph.phi);
-            if (cc >= 0) {
+            if (dp.cell_ch >= 0) {
                 dep = true;
-                cell_ch = (uint32_t)cc;
+                cell_ch = (uint32_t)dp.cell_ch;
                 q = __double2ull_rn((double)ph.phi * pi.scale);
+                phi = ph.phi;
             }
         }
-        deposit(dep, cell_ch, q, acc, cnt_map);
+        if (pi.general) pm_append(dep, pi.rec, dp, cell_ch, phi, pi.p0 + id);
+        else deposit(dep, cell_ch, q, acc, cnt_map);
         block_push(cont, id, q_next, counts + QC_NEXT);
     }
 }
@@ -523,7 +569,7 @@ __device__ __forceinline__ void count_rays(uint32_t n_cl, uint32_t n_sh, DevCoun
 }
 
 __global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo ci, WaveDev wl, PathState P,
-                                                            const float* __restrict__ cmap,
+                                                            const float* __restrict__ cmap, PMapDev pm,
                                                             const uint32_t* __restrict__ queue,
                                                             const uint32_t* __restrict__ count, uint32_t depth0,
                                                             uint32_t* __restrict__ work, DevCounters* __restrict__ C) {
@@ -540,8 +586,8 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo 
             uint32_t pix, sample, slot;
             pid_decode(ci, pid, pix, sample, slot);
             CamPath c = load_path(P, pid);
-            camera_continue<kTraceBS, false>(S, wl, cmap, ci.seed, pix, sample, slot, depth0, ci.max_depth, c, lds, st,
-                                             vc, n_cl, n_sh);
+            camera_continue<kTraceBS, false>(S, wl, cmap, pm, ci.seed, pix, sample, slot, depth0, ci.max_depth, c, lds,
+                                             st, vc, n_cl, n_sh);
             P.L[pid] = c.L;
         }
         uint32_t next = 0;
@@ -577,10 +623,17 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
             ph.spec = Ph.spec[id];
             ph.med = Ph.med[id];
             const int outcome = photon_continue<kTraceBS>(
-                S, wl, pi.seed, pi.p0 + id, depth0, pi.max_depth, ph, lds, st, vc, n_cl,
-                [&](int64_t cc, const PhotonPath& q) {
-                    atomicAdd(&acc[cc], __double2ull_rn((double)q.phi * pi.scale));
-                    if (cnt_map) atomicAdd(&cnt_map[cc], 1u);
+                S, wl, pi.seed, pi.p0 + id, depth0, pi.max_depth, pi.general != 0, ph, lds, st, vc, n_cl,
+                [&](const Deposit& dp, const PhotonPath& q) {
+                    if (pi.general) {
+                        const uint32_t k = atomicAdd(&pi.rec.stat[0], 1u);
+                        atomicMax(&pi.rec.stat[1], __float_as_uint(q.phi));
+                        atomicMax(&pi.rec.stat[2], pm_extent_bits(dp));
+                        pm_store(pi.rec, k, dp, (uint32_t)dp.cell_ch, q.phi, pi.p0 + id);
+                        return;
+                    }
+                    atomicAdd(&acc[dp.cell_ch], __double2ull_rn((double)q.phi * pi.scale));
+                    if (cnt_map) atomicAdd(&cnt_map[dp.cell_ch], 1u);
                 });
             if (outcome >= 0) ph_stat(C, pi, outcome, ph.phi);
         }
@@ -856,8 +909,10 @@ sc_status ctx_reset_counters(Ctx* c) {
 }
 
 sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t max_depth, const sc_wavelengths& wl,
-                 uint64_t seed, const float* cmap, const sc_aov& out) {
+                 uint64_t seed, const float* cmap, const sc_aov& out, const PMapDev* pmap) {
     hipStream_t st = c->stream;
+    PMapDev pm{};
+    if (pmap) pm = *pmap;
     const DevScene& S = b->scene;
     const size_t hw = (size_t)cam.w * cam.h;
     const uint32_t K = wl.mode == SC_WL_FIXED ? wl.k : 1;
@@ -908,12 +963,12 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
                 hipLaunchKernelGGL(k_shade_dielectric, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, P, depth,
                                    q.dielectric, fc, nxt);
                 hipLaunchKernelGGL(k_shade_diffuse, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, wd, P, depth, cmap,
-                                   q.diffuse, fc, nxt, q.shadow);
+                                   pm, q.diffuse, fc, nxt, q.shadow);
                 launch_anyhit(c, S, SR, q.shadow, fc + QC_SHADOW, 0u, n, nullptr, P.L);
                 std::swap(cur, nxt);
             }
             if (staged < max_depth)
-                hipLaunchKernelGGL(k_finish_camera, dim3(trace_grid(n)), dim3(kTraceBS), 0, st, S, ci, wd, P, cmap, cur,
+                hipLaunchKernelGGL(k_finish_camera, dim3(trace_grid(n)), dim3(kTraceBS), 0, st, S, ci, wd, P, cmap, pm, cur,
                                    q.counts + (size_t)staged * QC_FRAME + QC_CUR, staged + 1, next_work_slot(c),
                                    c->counters.as<DevCounters>());
             hipLaunchKernelGGL(k_film_accumulate, dim3(grid_for(hw, bs)), dim3(bs), 0, st, ci, wd, P.L, P.lambda, ns,
@@ -927,16 +982,19 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
 }
 
 sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc_wavelengths& wl, uint64_t seed,
-                        float* map, uint32_t* count_map, sc_photon_stats* stats) {
+                        float* map, uint32_t* count_map, sc_photon_stats* stats, const PmRecords* rec) {
     hipStream_t st = c->stream;
     const DevScene& S = b->scene;
     WaveDev wd;
     SC_TRY(make_wave(c, wl, wd));
-    const size_t cells = (size_t)S.recv_wc * S.recv_hc * wd.channels;
-    SC_TRY(c->acc64.ensure(cells * sizeof(unsigned long long)));
+    // the general photon map keeps records instead of the receiver map
+    const size_t cells = rec ? 0 : (size_t)S.recv_wc * S.recv_hc * wd.channels;
+    SC_TRY(c->acc64.ensure(std::max<size_t>(cells, 1) * sizeof(unsigned long long)));
     const uint32_t bs = 256;
-    hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(cells, bs)), dim3(bs), 0, st, c->acc64.as<unsigned long long>(), cells);
-    if (count_map)
+    if (cells)
+        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(cells, bs)), dim3(bs), 0, st, c->acc64.as<unsigned long long>(),
+                           cells);
+    if (count_map && cells)
         hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(cells, bs)), dim3(bs), 0, st, count_map, (uint32_t)cells);
     DevCounters before{};
     if (stats) {
@@ -968,7 +1026,7 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
         const HitSoA H{Ph.t, Ph.prim, Ph.u, Ph.v};
         for (uint64_t p0 = 0; p0 < N; p0 += chunk) {
             const uint32_t n = (uint32_t)std::min<uint64_t>(chunk, N - p0);
-            PhInfo pi{seed, N, p0, max_depth, scale, stats ? 1 : 0};
+            PhInfo pi{seed, N, p0, max_depth, scale, stats ? 1 : 0, rec ? 1 : 0, rec ? *rec : PmRecords{}};
             hipLaunchKernelGGL(k_zero_u32, dim3(32), dim3(256), 0, st, q.counts, frame_words);
             hipLaunchKernelGGL(k_photon_emit, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, wd, pi, n, Ph, q.cur, q.counts,
                                c->counters.as<DevCounters>());
@@ -989,8 +1047,9 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
                                    c->acc64.as<unsigned long long>(), count_map, c->counters.as<DevCounters>());
         }
     }
-    hipLaunchKernelGGL(k_map_finalize, dim3(grid_for(cells, bs)), dim3(bs), 0, st, c->acc64.as<unsigned long long>(),
-                       cells, 1.0 / scale, map);
+    if (cells)
+        hipLaunchKernelGGL(k_map_finalize, dim3(grid_for(cells, bs)), dim3(bs), 0, st,
+                           c->acc64.as<unsigned long long>(), cells, 1.0 / scale, map);
     SC_HIP(hipGetLastError());
     if (stats) {
         DevCounters after;
