@@ -1,7 +1,7 @@
 """Pins of the oracle's general photon map and RGB albedo textures.
 
 The paper's caustics land on whatever surface lies behind the glass
-(Sec. III-D-4: light "projected unto another surface"); the general
+(Sec. III-D-6: caustic light falling on another surface); the general
 photon map stores every caustic photon at its first diffuse hit on any
 object and estimates irradiance over a disc of radius r (Jensen's photon
 map density estimate with a fixed radius).  What pins it:
