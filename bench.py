@@ -215,6 +215,60 @@ def glass_variants(ctx, steps=5, warmup=2):
     return res
 
 
+def general_photon_map(ctx, reps=3):
+    """The general photon map (caustic photons on every diffuse surface):
+    photon pass plus hashed-grid build, and the render gathering from it,
+    against the receiver map on the same scene.  Medium scene at its own
+    settings (radius = one receiver cell, 3.9 mm); clutter scene = the
+    large-scene generator at a quarter of its triangles, RGB floor,
+    960x540, 4 spp, 2^22 photons, radius 4 mm."""
+    import torch
+
+    import scenegen as sg
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) / reps * 1e3
+
+    res = {}
+    c3 = sg.config3(tri_scale=0.25, w=960, h=540, floor="rgb")
+    c3.update(spp=4, n_photons=1 << 22)
+    for name, cfg, radius in (("medium", sg.config2(), 4.0 / 1024), ("clutter", c3, 0.004)):
+        wl, cam, md = cfg["wavelengths"], cfg["camera"], cfg["max_depth"]
+        bvh = ctx.build_bvh(cfg["scene"])
+        outs = {}
+        ph, t_ph = timed(lambda: ctx.trace_photons(bvh, cfg["n_photons"], md, wl, cfg["photon_seed"],
+                                                   out=outs.get("map")))
+        outs["map"] = ph["map"]
+        img, t_r = timed(lambda: ctx.render(bvh, cam, cfg["spp"], md, wl, cfg["render_seed"], caustic_map=ph["map"],
+                                            outputs=("rgb",), out=outs.get("img")))
+        outs["img"] = img
+        holder = {}
+
+        def pm_pass():
+            holder["pm"] = ctx.pmap_trace(bvh, cfg["n_photons"], md, wl, cfg["photon_seed"], radius,
+                                          out=holder.get("pm"))
+            return holder["pm"]
+
+        pm, t_pm = timed(pm_pass)
+        _, t_rp = timed(lambda: ctx.render(bvh, cam, cfg["spp"], md, wl, cfg["render_seed"], pmap=pm,
+                                           outputs=("rgb",), out=outs.get("img")))
+        inf = pm.info()
+        res[name] = {"triangles": cfg["scene"].nt, "pixels": cam.w * cam.h, "spp": cfg["spp"],
+                     "photons": cfg["n_photons"], "radius_m": radius, "stored": inf["n_stored"],
+                     "buckets": inf["buckets"], "map_MB": round(inf["bytes"] / 2 ** 20, 1),
+                     "receiver_map": {"photons_ms": round(t_ph, 3), "render_ms": round(t_r, 3)},
+                     "general_map": {"photons_and_build_ms": round(t_pm, 3), "render_ms": round(t_rp, 3)}}
+        pm.close()
+        del bvh, outs
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +281,7 @@ def main():
                          "(library default if omitted; 0 = all bounces staged)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-glass-variants", action="store_true")
+    ap.add_argument("--no-pmap", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -360,6 +415,8 @@ def main():
     }
     if not args.no_glass_variants:
         line["glass_variants"] = glass_variants(ctx)
+    if not args.no_pmap:
+        line["general_photon_map"] = general_photon_map(ctx)
     if not args.no_denoise:
         line["denoise_1080p"] = denoise_fps(ctx)
     if not args.no_batch:

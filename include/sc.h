@@ -287,7 +287,8 @@ sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, u
  * the photon pass of sc_trace_photons, but every photon that reaches a
  * diffuse surface of any object after at least one dielectric event is
  * stored there (position, geometric normal on its side, flux, map
- * channel, photon index) in a hashed grid of cells 3 * radius wide.  The
+ * channel, photon index) in a hashed grid of cells 3 * radius wide
+ * (offset by half a cell).  The
  * irradiance of channel c at a surface point x with facing normal n is
  * the flux of the stored photons of channel c within `radius` of x on the
  * same side (n_p . n > 0), over pi radius^2 (Jensen's density estimate
@@ -311,6 +312,13 @@ typedef struct {
 sc_status sc_pmap_trace(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, uint32_t max_depth,
                         const sc_wavelengths* wl, uint64_t seed, float radius, sc_pmap** out,
                         sc_photon_stats* stats);
+/* sc_pmap_trace into an existing handle, reusing its device memory where
+ * it is large enough (the per-frame rebuild).  After a failure the handle
+ * holds no map: gathers and renders with it fail with EINVAL until a
+ * rebuild succeeds. */
+sc_status sc_pmap_retrace(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, uint32_t max_depth,
+                          const sc_wavelengths* wl, uint64_t seed, float radius, sc_pmap* pm,
+                          sc_photon_stats* stats);
 sc_status sc_pmap_get_info(const sc_pmap* pm, sc_pmap_info* out);
 /* Host copies of the stored photons in photon-index order (any may be
  * NULL): pos [n][3], nrm [n][3], phi [n], channel [n], photon [n]. */

@@ -135,7 +135,8 @@ EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set
            "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise",
            "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch",
            "sc_caustic_mask", "sc_outline", "sc_occlusion_boundary",
-           "sc_pmap_trace", "sc_pmap_get_info", "sc_pmap_export", "sc_pmap_gather", "sc_pmap_free", "sc_render_pmap"]
+           "sc_pmap_trace", "sc_pmap_retrace", "sc_pmap_get_info", "sc_pmap_export", "sc_pmap_gather",
+           "sc_pmap_free", "sc_render_pmap"]
 
 
 def load(path: str = LIB_PATH):
@@ -167,6 +168,8 @@ def load(path: str = LIB_PATH):
     L.sc_render.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, C.POINTER(Aov)]
     L.sc_pmap_trace.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, C.c_float, C.POINTER(vp),
                                 C.POINTER(PhotonStats)]
+    L.sc_pmap_retrace.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, C.c_float, vp,
+                                  C.POINTER(PhotonStats)]
     L.sc_pmap_get_info.argtypes = [vp, C.POINTER(PmapInfo)]
     L.sc_pmap_export.argtypes = [vp, vp, vp, vp, vp, vp]
     L.sc_pmap_gather.argtypes = [vp, vp, u32, vp, vp, vp, vp]
@@ -354,16 +357,23 @@ class Context:
         return res
 
     def pmap_trace(self, bvh: "Bvh", n_photons: int, max_depth: int, wl, seed: int, radius: float,
-                   stats: bool = False) -> "PhotonMap":
+                   stats: bool = False, out: Optional["PhotonMap"] = None) -> "PhotonMap":
         """General photon map: caustic photons stored on every diffuse surface
-        (sc_pmap_trace).  With stats=True the outcome statistics are kept in
-        the result's .stats."""
+        (sc_pmap_trace; with out=, rebuilt in that handle's memory by
+        sc_pmap_retrace).  With stats=True the outcome statistics are kept
+        in the result's .stats."""
         st = PhotonStats() if stats else None
-        h = C.c_void_p()
         w = wavelengths_struct(wl)
-        _check(load().sc_pmap_trace(self.h, bvh.h, int(n_photons), int(max_depth), C.byref(w), int(seed), float(radius),
-                                    C.byref(h), C.byref(st) if st is not None else None), "sc_pmap_trace")
-        pm = PhotonMap(self, h)
+        pst = C.byref(st) if st is not None else None
+        if out is not None:
+            _check(load().sc_pmap_retrace(self.h, bvh.h, int(n_photons), int(max_depth), C.byref(w), int(seed),
+                                          float(radius), out.h, pst), "sc_pmap_retrace")
+            pm = out
+        else:
+            h = C.c_void_p()
+            _check(load().sc_pmap_trace(self.h, bvh.h, int(n_photons), int(max_depth), C.byref(w), int(seed),
+                                        float(radius), C.byref(h), pst), "sc_pmap_trace")
+            pm = PhotonMap(self, h)
         if stats:
             pm.stats = {k: (st.flux[i], st.count[i]) for i, k in enumerate(PH_OUTCOMES)}
             pm.stats["segments"] = st.segments

@@ -377,8 +377,22 @@ sc_status sc_pmap_trace(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, uint
     return SC_OK;
 }
 
+sc_status sc_pmap_retrace(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, uint32_t max_depth,
+                          const sc_wavelengths* wl, uint64_t seed, float radius, sc_pmap* pm, sc_photon_stats* stats) {
+    if (!ctx || !bvh || !pm) return set_error(SC_EINVAL, "ctx, bvh or pmap is NULL");
+    if (pm->p.ctx && pm->p.ctx != &ctx->c) return set_error(SC_EINVAL, "pmap belongs to another context");
+    pm->p.valid = false;
+    SC_TRY(check_built(bvh));
+    SC_TRY(check_wavelengths(wl));
+    if (max_depth == 0) return set_error(SC_EINVAL, "max_depth must be >= 1");
+    if (stats) memset(stats, 0, sizeof(*stats));
+    return scl::pmap_trace(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n_photons, max_depth, *wl, seed, radius, &pm->p,
+                           stats);
+}
+
 sc_status sc_pmap_get_info(const sc_pmap* pm, sc_pmap_info* out) {
     if (!pm || !out) return set_error(SC_EINVAL, "pmap or out is NULL");
+    if (!pm->p.valid) return set_error(SC_EINVAL, "pmap holds no map (a rebuild failed)");
     out->n_stored = pm->p.n;
     out->radius = pm->p.radius;
     out->channels = pm->p.channels;
@@ -390,6 +404,7 @@ sc_status sc_pmap_get_info(const sc_pmap* pm, sc_pmap_info* out) {
 
 sc_status sc_pmap_export(const sc_pmap* pm, float* pos, float* nrm, float* phi, uint32_t* channel, uint64_t* photon) {
     if (!pm) return set_error(SC_EINVAL, "pmap is NULL");
+    if (!pm->p.valid) return set_error(SC_EINVAL, "pmap holds no map (a rebuild failed)");
     return scl::pmap_export(&pm->p, pos, nrm, phi, channel, photon);
 }
 
@@ -398,6 +413,7 @@ sc_status sc_pmap_gather(sc_ctx* ctx, const sc_pmap* pm, uint32_t n, const float
     if (!ctx || !pm) return set_error(SC_EINVAL, "ctx or pmap is NULL");
     if (n && (!P || !N || !ch || !E)) return set_error(SC_EINVAL, "gather arrays are NULL");
     if (pm->p.ctx != &ctx->c) return set_error(SC_EINVAL, "pmap belongs to another context");
+    if (!pm->p.valid) return set_error(SC_EINVAL, "pmap holds no map (a rebuild failed)");
     return scl::pmap_gather(&ctx->c, &pm->p, n, P, N, ch, E);
 }
 
@@ -419,6 +435,7 @@ sc_status sc_render_pmap(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, u
     if (cam->w == 0 || cam->h == 0) return set_error(SC_EINVAL, "camera has no pixels");
     if ((uint64_t)cam->w * cam->h > (1ull << 28)) return set_error(SC_EUNSUPPORTED, "image too large");
     if (pm->p.ctx != &ctx->c) return set_error(SC_EINVAL, "pmap belongs to another context");
+    if (!pm->p.valid) return set_error(SC_EINVAL, "pmap holds no map (a rebuild failed)");
     const uint32_t ch = wl->mode == SC_WL_FIXED ? wl->k : wl->bins;
     if (ch != pm->p.channels) return set_error(SC_EINVAL, "the photon map has other channels than the wavelength setting");
     return scl::render(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), *cam, spp, max_depth, *wl, seed, nullptr, *out,

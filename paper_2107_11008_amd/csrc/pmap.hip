@@ -116,8 +116,8 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
 }
 
 struct PmSorted {
-    float *px, *py, *pz, *nx, *ny, *nz, *phi;
-    uint32_t* ch;
+    float4* rec;   // [n][2] as in PMapDev
+    float* phi;
     unsigned long long *q, *photon;
 };
 
@@ -127,10 +127,9 @@ __global__ void k_pm_scatter(PmRecords R, uint32_t n, const uint32_t* __restrict
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t b = bucket[i];
         const uint32_t k = start[b] + atomicAdd(&cursor[b], 1u);
-        O.px[k] = R.px[i]; O.py[k] = R.py[i]; O.pz[k] = R.pz[i];
-        O.nx[k] = R.nx[i]; O.ny[k] = R.ny[i]; O.nz[k] = R.nz[i];
+        O.rec[2 * (size_t)k] = make_float4(R.px[i], R.py[i], R.pz[i], __uint_as_float(R.ch[i]));
+        O.rec[2 * (size_t)k + 1] = make_float4(R.nx[i], R.ny[i], R.nz[i], 0.0f);
         O.phi[k] = R.phi[i];
-        O.ch[k] = R.ch[i];
         O.q[k] = __double2ull_rn((double)R.phi[i] * scale);
         O.photon[k] = R.photon[i];
     }
@@ -175,17 +174,15 @@ size_t record_bytes(size_t cap) { return 8 * slot(cap, 4) + slot(cap, 8) + 256 +
 PmSorted carve_sorted(void* p, size_t n, uint32_t buckets, uint32_t** start) {
     Carver c{static_cast<char*>(p)};
     PmSorted O;
-    O.px = c.take<float>(n); O.py = c.take<float>(n); O.pz = c.take<float>(n);
-    O.nx = c.take<float>(n); O.ny = c.take<float>(n); O.nz = c.take<float>(n);
+    O.rec = c.take<float4>(2 * n);
     O.phi = c.take<float>(n);
-    O.ch = c.take<uint32_t>(n);
     O.q = c.take<unsigned long long>(n);
     O.photon = c.take<unsigned long long>(n);
     *start = c.take<uint32_t>((size_t)buckets + 1);
     return O;
 }
 size_t sorted_bytes(size_t n, uint32_t buckets) {
-    return 8 * slot(n, 4) + 2 * slot(n, 8) + slot((size_t)buckets + 1, 4) + 11 * 256;
+    return slot(2 * n, 16) + slot(n, 4) + 2 * slot(n, 8) + slot((size_t)buckets + 1, 4) + 6 * 256;
 }
 
 }  // namespace
@@ -215,13 +212,13 @@ sc_status pmap_trace(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc_wa
         scale = ldexp(1.0, e - 1);
     }
     const float inv_h = 1.0f / (3.0f * radius);
-    if (!((double)ext * (double)inv_h + 1.1 * (double)radius * (double)inv_h < 65536.0))
+    if (!((double)ext * (double)inv_h + 1.1 * (double)radius * (double)inv_h + 0.5 < 65536.0))
         return set_error(SC_EUNSUPPORTED, "radius too small for the extent of the stored photons (2^16 cells)");
     uint32_t buckets = 1024;
     while (buckets < 2ull * n && buckets < (1u << 26)) buckets <<= 1;
 
-    pm->mem.release();
-    SC_TRY(pm->mem.alloc(sorted_bytes(std::max<uint32_t>(n, 1), buckets)));
+    pm->valid = false;
+    SC_TRY(pm->mem.ensure(sorted_bytes(std::max<uint32_t>(n, 1), buckets)));   // grow-only: a rebuild reuses it
     uint32_t* start = nullptr;
     const PmSorted O = carve_sorted(pm->mem.p, std::max<uint32_t>(n, 1), buckets, &start);
     const uint32_t nb = (buckets + kScanBlock - 1) / kScanBlock;
@@ -254,10 +251,8 @@ sc_status pmap_trace(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc_wa
     pm->photon = O.photon;
     pm->phi = O.phi;
     PMapDev& d = pm->dev;
-    d.px = O.px; d.py = O.py; d.pz = O.pz;
-    d.nx = O.nx; d.ny = O.ny; d.nz = O.nz;
+    d.rec = O.rec;
     d.q = O.q;
-    d.ch = O.ch;
     d.start = start;
     d.mask = buckets - 1;
     d.on = 1;
@@ -265,31 +260,30 @@ sc_status pmap_trace(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc_wa
     d.r2 = radius * radius;
     d.inv_h = inv_h;
     d.c = 1.0 / ((scale * 3.14159265358979323846) * ((double)radius * (double)radius));
+    pm->valid = true;
     return SC_OK;
 }
 
 sc_status pmap_export(const Pmap* pm, float* pos, float* nrm, float* phi, uint32_t* channel, uint64_t* photon) {
     const size_t n = pm->n;
     if (n == 0) return SC_OK;
-    std::vector<float> px(n), py(n), pz(n), nx(n), ny(n), nz(n), ph(n);
-    std::vector<uint32_t> ch(n);
+    std::vector<float4> rec(2 * n);
+    std::vector<float> ph(n);
     std::vector<unsigned long long> id(n);
-    const PMapDev& d = pm->dev;
     SC_HIP(hipStreamSynchronize(pm->ctx->stream));
-    struct { const void* src; void* dst; size_t bytes; } cp[] = {
-        {d.px, px.data(), 4 * n}, {d.py, py.data(), 4 * n}, {d.pz, pz.data(), 4 * n},
-        {d.nx, nx.data(), 4 * n}, {d.ny, ny.data(), 4 * n}, {d.nz, nz.data(), 4 * n},
-        {pm->phi, ph.data(), 4 * n}, {d.ch, ch.data(), 4 * n}, {pm->photon, id.data(), 8 * n}};
-    for (const auto& e : cp) SC_HIP(hipMemcpy(e.dst, e.src, e.bytes, hipMemcpyDeviceToHost));
+    SC_HIP(hipMemcpy(rec.data(), pm->dev.rec, 2 * n * sizeof(float4), hipMemcpyDeviceToHost));
+    SC_HIP(hipMemcpy(ph.data(), pm->phi, n * sizeof(float), hipMemcpyDeviceToHost));
+    SC_HIP(hipMemcpy(id.data(), pm->photon, n * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     std::vector<size_t> order(n);
     std::iota(order.begin(), order.end(), size_t{0});
     std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return id[a] < id[b]; });
     for (size_t j = 0; j < n; ++j) {
         const size_t k = order[j];
-        if (pos) { pos[3 * j] = px[k]; pos[3 * j + 1] = py[k]; pos[3 * j + 2] = pz[k]; }
-        if (nrm) { nrm[3 * j] = nx[k]; nrm[3 * j + 1] = ny[k]; nrm[3 * j + 2] = nz[k]; }
+        const float4 a = rec[2 * k], b = rec[2 * k + 1];
+        if (pos) { pos[3 * j] = a.x; pos[3 * j + 1] = a.y; pos[3 * j + 2] = a.z; }
+        if (nrm) { nrm[3 * j] = b.x; nrm[3 * j + 1] = b.y; nrm[3 * j + 2] = b.z; }
         if (phi) phi[j] = ph[k];
-        if (channel) channel[j] = ch[k];
+        if (channel) memcpy(&channel[j], &a.w, 4);
         if (photon) photon[j] = id[k];
     }
     return SC_OK;

@@ -130,6 +130,7 @@ struct Pmap {
     float radius = 0.0f;
     uint32_t channels = 0, buckets = 0;
     double scale = 1.0;
+    bool valid = false;                      // false after a failed rebuild
 };
 
 // Builds b->nodes and b->tris for b->scene_in (b->mat must already hold the

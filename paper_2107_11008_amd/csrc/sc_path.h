@@ -388,13 +388,16 @@ __device__ __forceinline__ float medium_weight(const DevScene& S, uint64_t M, fl
 // ---------------------------------------------------------------- general photon map
 // Irradiance of channel ch at P (facing normal N): the fixed-point flux of
 // the stored photons of that channel on the same side (n_p . N > 0) within
-// r of P, times 1 / (2^S pi r^2).  The cells (3 r wide) overlapping the box
-// P +- 1.1 r, at most 2 per axis, are visited through their buckets; a
-// record counts only in its own cell, so a bucket shared by two visited
-// cells is not counted twice.  The integer sum does not depend on the
-// order of the records.  Points more than 2^20 cells from the origin are
-// far from every stored photon (those lie within 2^16 cells).
-__device__ __forceinline__ int pm_cell(float v, float inv_h) { return (int)floorf(v * inv_h); }
+// r of P, times 1 / (2^S pi r^2).  Cells are 3 r wide and offset by half a
+// cell (a floor at a multiple of the width lies mid-cell); the cells
+// overlapping the box P +- 1.1 r, at most 2 per axis, are visited through
+// their buckets, whose ranges are all loaded before any record so the
+// misses overlap.  A record counts only in its own cell, so a bucket
+// shared by two visited cells is not counted twice.  The integer sum does
+// not depend on the order of the records.  Points more than 2^20 cells
+// from the origin are far from every stored photon (those lie within 2^16
+// cells).
+__device__ __forceinline__ int pm_cell(float v, float inv_h) { return (int)floorf(v * inv_h + 0.5f); }
 
 __device__ __forceinline__ uint32_t pm_bucket(int x, int y, int z, uint32_t ch, uint32_t mask) {
     return (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u) ^ (ch * 2654435761u)) &
@@ -405,26 +408,33 @@ __device__ __forceinline__ float pmap_gather(const PMapDev& pm, F3 P, F3 N, uint
     const float lim = 1048576.0f;
     if (!(fabsf(P.x * pm.inv_h) < lim && fabsf(P.y * pm.inv_h) < lim && fabsf(P.z * pm.inv_h) < lim)) return 0.0f;
     const float rr = pm.r * 1.1f;
-    const int x0 = pm_cell(P.x - rr, pm.inv_h), x1 = min(pm_cell(P.x + rr, pm.inv_h), x0 + 1);
-    const int y0 = pm_cell(P.y - rr, pm.inv_h), y1 = min(pm_cell(P.y + rr, pm.inv_h), y0 + 1);
-    const int z0 = pm_cell(P.z - rr, pm.inv_h), z1 = min(pm_cell(P.z + rr, pm.inv_h), z0 + 1);
+    const int x0 = pm_cell(P.x - rr, pm.inv_h), nx = min(pm_cell(P.x + rr, pm.inv_h) - x0, 1);
+    const int y0 = pm_cell(P.y - rr, pm.inv_h), ny = min(pm_cell(P.y + rr, pm.inv_h) - y0, 1);
+    const int z0 = pm_cell(P.z - rr, pm.inv_h), nz = min(pm_cell(P.z + rr, pm.inv_h) - z0, 1);
+    uint32_t s0[8], s1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int dx = j & 1, dy = (j >> 1) & 1, dz = j >> 2;
+        s0[j] = 0u;
+        s1[j] = 0u;
+        if (dx <= nx && dy <= ny && dz <= nz) {
+            const uint32_t b = pm_bucket(x0 + dx, y0 + dy, z0 + dz, ch, pm.mask);
+            s0[j] = pm.start[b];
+            s1[j] = pm.start[b + 1];
+        }
+    }
     unsigned long long sum = 0ull;
-    for (int z = z0; z <= z1; ++z) {
-        for (int y = y0; y <= y1; ++y) {
-            for (int x = x0; x <= x1; ++x) {
-                const uint32_t b = pm_bucket(x, y, z, ch, pm.mask);
-                const uint32_t e = pm.start[b + 1];
-                for (uint32_t k = pm.start[b]; k < e; ++k) {
-                    if (pm.ch[k] != ch) continue;
-                    const F3 q{pm.px[k], pm.py[k], pm.pz[k]};
-                    if (pm_cell(q.x, pm.inv_h) != x || pm_cell(q.y, pm.inv_h) != y || pm_cell(q.z, pm.inv_h) != z)
-                        continue;
-                    const F3 n{pm.nx[k], pm.ny[k], pm.nz[k]};
-                    if (!(dot(n, N) > 0.0f)) continue;
-                    const F3 dl = q - P;
-                    if (dot(dl, dl) < pm.r2) sum += pm.q[k];
-                }
-            }
+    for (int j = 0; j < 8; ++j) {
+        const int x = x0 + (j & 1), y = y0 + ((j >> 1) & 1), z = z0 + (j >> 2);
+        for (uint32_t k = s0[j]; k < s1[j]; ++k) {
+            const float4 a = pm.rec[2 * (size_t)k];
+            if (__float_as_uint(a.w) != ch) continue;
+            if (pm_cell(a.x, pm.inv_h) != x || pm_cell(a.y, pm.inv_h) != y || pm_cell(a.z, pm.inv_h) != z) continue;
+            const float4 b = pm.rec[2 * (size_t)k + 1];
+            const F3 n{b.x, b.y, b.z};
+            if (!(dot(n, N) > 0.0f)) continue;
+            const F3 dl = F3{a.x, a.y, a.z} - P;
+            if (dot(dl, dl) < pm.r2) sum += pm.q[k];
         }
     }
     return (float)((double)sum * pm.c);

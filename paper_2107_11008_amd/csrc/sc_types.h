@@ -94,9 +94,8 @@ struct PhotonState {
 // device view of a general photon map: stored photons sorted into hash
 // buckets of (cell, channel), cells 3 r wide
 struct PMapDev {
-    const float *px, *py, *pz, *nx, *ny, *nz;
+    const float4* rec;             // [n][2]: (x, y, z, channel as bits), (nx, ny, nz, 0)
     const unsigned long long* q;   // flux in fixed point, round(phi 2^S)
-    const uint32_t* ch;
     const uint32_t* start;         // [buckets + 1] first record of each bucket
     uint32_t mask;                 // buckets - 1
     uint32_t on;                   // 0: caustics from the receiver map instead

@@ -168,3 +168,31 @@ def test_pmap_argument_errors(ctx):
     pm = ctx.pmap_trace(bvh, 1 << 12, 8, c["wavelengths"], 1, 0.05)
     with pytest.raises(sc.ScError):
         ctx.render(bvh, c["camera"], 1, 8, sg.Wavelengths(sg.WL_UNIFORM, 1, (550.0,), 380.0, 720.0, 16), 1, pmap=pm)
+
+
+def test_retrace_in_place(ctx):
+    """A map rebuilt in an existing handle equals a fresh one; after a failed
+    rebuild the handle refuses use until a rebuild succeeds."""
+    import paper_2107_11008_amd as sc
+    c = _clutter()
+    wl = c["wavelengths"]
+    bvh = ctx.build_bvh(c["scene"])
+    pm = ctx.pmap_trace(bvh, 1 << 10, 6, wl, 1, 0.05)
+    args = (bvh, c["n_photons"], c["max_depth"], wl, c["photon_seed"], 0.03)
+    assert ctx.pmap_trace(*args, out=pm) is pm                      # grows the handle's memory
+    fresh = ctx.pmap_trace(*args)
+    a, b = pm.export(), fresh.export()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert pm.info() == fresh.info()
+    with pytest.raises(sc.ScError):
+        ctx.pmap_trace(bvh, c["n_photons"], c["max_depth"], wl, c["photon_seed"], 0.0, out=pm)
+    P = torch.zeros((1, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(sc.ScError):
+        pm.gather(P, P, torch.zeros(1, dtype=torch.int32, device="cuda"))
+    with pytest.raises(sc.ScError):
+        ctx.render(bvh, c["camera"], 1, 4, wl, 1, pmap=pm, outputs=("rgb",))
+    ctx.pmap_trace(*args, out=pm)
+    a = pm.export()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
