@@ -287,7 +287,7 @@ sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, u
  * the photon pass of sc_trace_photons, but every photon that reaches a
  * diffuse surface of any object after at least one dielectric event is
  * stored there (position, geometric normal on its side, flux, map
- * channel, photon index) in a hashed grid of cells 3 * radius wide
+ * channel, photon index) in a hashed grid of cells 2.25 * radius wide
  * (offset by half a cell).  The
  * irradiance of channel c at a surface point x with facing normal n is
  * the flux of the stored photons of channel c within `radius` of x on the
@@ -296,8 +296,8 @@ sc_status sc_trace_photons(sc_ctx* ctx, const sc_bvh* bvh, uint64_t n_photons, u
  * is taken as round(phi 2^S) in 64-bit fixed point, 2^S the largest power
  * of two with n_stored * max(phi) * 2^S <= 2^62, and
  * E = (float)(sum * (1 / (2^S pi radius^2))) in double.
- * Up to 2^24 photons; radius > 0 and no stored coordinate beyond
- * 2^16 * 3 * radius from the origin (else EUNSUPPORTED).  Synchronises.
+ * Up to 2^24 photons; radius > 0 and no stored coordinate beyond about
+ * 2^16 * 2.25 * radius from the origin (else EUNSUPPORTED).  Synchronises.
  * stats: host, or NULL.  The handle owns its device memory until
  * sc_pmap_free. */
 typedef struct sc_pmap sc_pmap;

@@ -9,7 +9,7 @@
 // and largest coordinate fix the fixed-point scale 2^S (the largest power
 // of two with n * max(phi) * 2^S <= 2^62) and check the grid's range.
 // Records are then counting-sorted into buckets of (cell, channel), cells
-// 3 r wide: a bucket count, a three-phase exclusive scan and a scatter.
+// 2.25 r wide: a bucket count, a three-phase exclusive scan and a scatter.
 // The order inside a bucket is whatever the atomics give; the gather sums
 // integers, so it does not matter.
 #include <hip/hip_runtime.h>
@@ -37,11 +37,11 @@ __global__ void k_pm_zero(uint32_t* p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
 
-__global__ void k_pm_bucket(PmRecords R, uint32_t n, float inv_h, uint32_t mask, uint32_t* __restrict__ bucket,
-                            uint32_t* __restrict__ counts) {
+__global__ void k_pm_bucket(PmRecords R, uint32_t n, float inv_h, uint32_t cbits, uint32_t mask,
+                            uint32_t* __restrict__ bucket, uint32_t* __restrict__ counts) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t b = pm_bucket(pm_cell(R.px[i], inv_h), pm_cell(R.py[i], inv_h), pm_cell(R.pz[i], inv_h), R.ch[i],
-                                     mask);
+                                     cbits, mask);
         bucket[i] = b;
         atomicAdd(&counts[b], 1u);
     }
@@ -118,18 +118,21 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
 struct PmSorted {
     float4* rec;   // [n][2] as in PMapDev
     float* phi;
+    uint32_t* ch;  // channel (export)
     unsigned long long *q, *photon;
 };
 
-__global__ void k_pm_scatter(PmRecords R, uint32_t n, const uint32_t* __restrict__ bucket,
+__global__ void k_pm_scatter(PmRecords R, uint32_t n, float inv_h, const uint32_t* __restrict__ bucket,
                              const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor, double scale,
                              PmSorted O) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t b = bucket[i];
         const uint32_t k = start[b] + atomicAdd(&cursor[b], 1u);
-        O.rec[2 * (size_t)k] = make_float4(R.px[i], R.py[i], R.pz[i], __uint_as_float(R.ch[i]));
-        O.rec[2 * (size_t)k + 1] = make_float4(R.nx[i], R.ny[i], R.nz[i], 0.0f);
+        const uint64_t tag = pm_tag(pm_cell(R.px[i], inv_h), pm_cell(R.py[i], inv_h), pm_cell(R.pz[i], inv_h));
+        O.rec[2 * (size_t)k] = make_float4(R.px[i], R.py[i], R.pz[i], __uint_as_float((uint32_t)tag));
+        O.rec[2 * (size_t)k + 1] = make_float4(R.nx[i], R.ny[i], R.nz[i], __uint_as_float((uint32_t)(tag >> 32)));
         O.phi[k] = R.phi[i];
+        O.ch[k] = R.ch[i];
         O.q[k] = __double2ull_rn((double)R.phi[i] * scale);
         O.photon[k] = R.photon[i];
     }
@@ -176,13 +179,14 @@ PmSorted carve_sorted(void* p, size_t n, uint32_t buckets, uint32_t** start) {
     PmSorted O;
     O.rec = c.take<float4>(2 * n);
     O.phi = c.take<float>(n);
+    O.ch = c.take<uint32_t>(n);
     O.q = c.take<unsigned long long>(n);
     O.photon = c.take<unsigned long long>(n);
     *start = c.take<uint32_t>((size_t)buckets + 1);
     return O;
 }
 size_t sorted_bytes(size_t n, uint32_t buckets) {
-    return slot(2 * n, 16) + slot(n, 4) + 2 * slot(n, 8) + slot((size_t)buckets + 1, 4) + 6 * 256;
+    return slot(2 * n, 16) + 2 * slot(n, 4) + 2 * slot(n, 8) + slot((size_t)buckets + 1, 4) + 7 * 256;
 }
 
 }  // namespace
@@ -211,11 +215,14 @@ sc_status pmap_trace(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc_wa
         frexp(ldexp(1.0, 62) / ((double)n * (double)phimax), &e);
         scale = ldexp(1.0, e - 1);
     }
-    const float inv_h = 1.0f / (3.0f * radius);
+    const float inv_h = 1.0f / (2.25f * radius);
     if (!((double)ext * (double)inv_h + 1.1 * (double)radius * (double)inv_h + 0.5 < 65536.0))
         return set_error(SC_EUNSUPPORTED, "radius too small for the extent of the stored photons (2^16 cells)");
+    const uint32_t channels = wl.mode == SC_WL_FIXED ? wl.k : wl.bins;
+    uint32_t cbits = 0;
+    while ((1u << cbits) < channels) ++cbits;
     uint32_t buckets = 1024;
-    while (buckets < 2ull * n && buckets < (1u << 26)) buckets <<= 1;
+    while ((buckets < 2ull * n || buckets < (2u << cbits)) && buckets < (1u << 26)) buckets <<= 1;
 
     pm->valid = false;
     SC_TRY(pm->mem.ensure(sorted_bytes(std::max<uint32_t>(n, 1), buckets)));   // grow-only: a rebuild reuses it
@@ -233,28 +240,33 @@ sc_status pmap_trace(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc_wa
     const uint32_t bs = 256;
     hipLaunchKernelGGL(k_pm_zero, dim3(grid_of(buckets, bs)), dim3(bs), 0, st, counts, (size_t)buckets);
     hipLaunchKernelGGL(k_pm_zero, dim3(grid_of(buckets, bs)), dim3(bs), 0, st, cursor, (size_t)buckets);
-    if (n) hipLaunchKernelGGL(k_pm_bucket, dim3(grid_of(n, bs)), dim3(bs), 0, st, R, n, inv_h, buckets - 1, bucket, counts);
+    if (n)
+        hipLaunchKernelGGL(k_pm_bucket, dim3(grid_of(n, bs)), dim3(bs), 0, st, R, n, inv_h, cbits, buckets - 1, bucket,
+                           counts);
     hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(256), 0, st, counts, buckets, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, bsum, nb, start + buckets);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, st, counts, buckets, bsum, start);
     if (n)
-        hipLaunchKernelGGL(k_pm_scatter, dim3(grid_of(n, bs)), dim3(bs), 0, st, R, n, bucket, start, cursor, scale, O);
+        hipLaunchKernelGGL(k_pm_scatter, dim3(grid_of(n, bs)), dim3(bs), 0, st, R, n, inv_h, bucket, start, cursor,
+                           scale, O);
     SC_HIP(hipGetLastError());
     SC_HIP(hipStreamSynchronize(st));
 
     pm->ctx = c;
     pm->n = n;
     pm->radius = radius;
-    pm->channels = wl.mode == SC_WL_FIXED ? wl.k : wl.bins;
+    pm->channels = channels;
     pm->buckets = buckets;
     pm->scale = scale;
     pm->photon = O.photon;
     pm->phi = O.phi;
+    pm->ch = O.ch;
     PMapDev& d = pm->dev;
     d.rec = O.rec;
     d.q = O.q;
     d.start = start;
     d.mask = buckets - 1;
+    d.cbits = cbits;
     d.on = 1;
     d.r = radius;
     d.r2 = radius * radius;
@@ -269,10 +281,12 @@ sc_status pmap_export(const Pmap* pm, float* pos, float* nrm, float* phi, uint32
     if (n == 0) return SC_OK;
     std::vector<float4> rec(2 * n);
     std::vector<float> ph(n);
+    std::vector<uint32_t> ch(n);
     std::vector<unsigned long long> id(n);
     SC_HIP(hipStreamSynchronize(pm->ctx->stream));
     SC_HIP(hipMemcpy(rec.data(), pm->dev.rec, 2 * n * sizeof(float4), hipMemcpyDeviceToHost));
     SC_HIP(hipMemcpy(ph.data(), pm->phi, n * sizeof(float), hipMemcpyDeviceToHost));
+    SC_HIP(hipMemcpy(ch.data(), pm->ch, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
     SC_HIP(hipMemcpy(id.data(), pm->photon, n * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     std::vector<size_t> order(n);
     std::iota(order.begin(), order.end(), size_t{0});
@@ -283,7 +297,7 @@ sc_status pmap_export(const Pmap* pm, float* pos, float* nrm, float* phi, uint32
         if (pos) { pos[3 * j] = a.x; pos[3 * j + 1] = a.y; pos[3 * j + 2] = a.z; }
         if (nrm) { nrm[3 * j] = b.x; nrm[3 * j + 1] = b.y; nrm[3 * j + 2] = b.z; }
         if (phi) phi[j] = ph[k];
-        if (channel) memcpy(&channel[j], &a.w, 4);
+        if (channel) channel[j] = ch[k];
         if (photon) photon[j] = id[k];
     }
     return SC_OK;

@@ -125,6 +125,7 @@ struct Pmap {
     DevBuf mem;                              // sorted records and bucket starts
     PMapDev dev{};                           // device view
     const float* phi = nullptr;              // sorted fluxes (export)
+    const uint32_t* ch = nullptr;            // sorted channels (export)
     const unsigned long long* photon = nullptr;   // sorted photon indices (export)
     uint64_t n = 0;
     float radius = 0.0f;

@@ -388,20 +388,29 @@ __device__ __forceinline__ float medium_weight(const DevScene& S, uint64_t M, fl
 // ---------------------------------------------------------------- general photon map
 // Irradiance of channel ch at P (facing normal N): the fixed-point flux of
 // the stored photons of that channel on the same side (n_p . N > 0) within
-// r of P, times 1 / (2^S pi r^2).  Cells are 3 r wide and offset by half a
-// cell (a floor at a multiple of the width lies mid-cell); the cells
+// r of P, times 1 / (2^S pi r^2).  Cells are 2.25 r wide and offset by half
+// a cell (a floor at a multiple of the width lies mid-cell); the cells
 // overlapping the box P +- 1.1 r, at most 2 per axis, are visited through
 // their buckets, whose ranges are all loaded before any record so the
-// misses overlap.  A record counts only in its own cell, so a bucket
-// shared by two visited cells is not counted twice.  The integer sum does
-// not depend on the order of the records.  Points more than 2^20 cells
-// from the origin are far from every stored photon (those lie within 2^16
-// cells).
+// misses overlap.  A bucket holds one channel only (its low bits), and a
+// record counts only in its own cell (its packed cell coordinates are
+// stored with it), so a bucket shared by two visited cells is not counted
+// twice.  The integer sum does not depend on the order of the records.
+// Points more than 2^20 cells from the origin are far from every stored
+// photon (those lie within 2^16 cells).
 __device__ __forceinline__ int pm_cell(float v, float inv_h) { return (int)floorf(v * inv_h + 0.5f); }
 
-__device__ __forceinline__ uint32_t pm_bucket(int x, int y, int z, uint32_t ch, uint32_t mask) {
-    return (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u) ^ (ch * 2654435761u)) &
-           mask;
+// packed cell coordinates (18 bits each, offset by 2^17): low 32 bits and high 22
+__device__ __forceinline__ uint64_t pm_tag(int x, int y, int z) {
+    return (uint64_t)((uint32_t)(x + 131072) & 0x3ffffu) | ((uint64_t)((uint32_t)(y + 131072) & 0x3ffffu) << 18) |
+           ((uint64_t)((uint32_t)(z + 131072) & 0x3ffffu) << 36);
+}
+
+// the channel is the low cbits of the bucket, so a bucket holds one
+// channel and the buckets of one cell's channels are adjacent
+__device__ __forceinline__ uint32_t pm_bucket(int x, int y, int z, uint32_t ch, uint32_t cbits, uint32_t mask) {
+    const uint32_t h = ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u);
+    return ((h << cbits) | ch) & mask;
 }
 
 __device__ __forceinline__ float pmap_gather(const PMapDev& pm, F3 P, F3 N, uint32_t ch) {
@@ -418,23 +427,23 @@ __device__ __forceinline__ float pmap_gather(const PMapDev& pm, F3 P, F3 N, uint
         s0[j] = 0u;
         s1[j] = 0u;
         if (dx <= nx && dy <= ny && dz <= nz) {
-            const uint32_t b = pm_bucket(x0 + dx, y0 + dy, z0 + dz, ch, pm.mask);
+            const uint32_t b = pm_bucket(x0 + dx, y0 + dy, z0 + dz, ch, pm.cbits, pm.mask);
             s0[j] = pm.start[b];
             s1[j] = pm.start[b + 1];
         }
     }
     unsigned long long sum = 0ull;
     for (int j = 0; j < 8; ++j) {
-        const int x = x0 + (j & 1), y = y0 + ((j >> 1) & 1), z = z0 + (j >> 2);
+        const uint64_t tag = pm_tag(x0 + (j & 1), y0 + ((j >> 1) & 1), z0 + (j >> 2));
+        const uint32_t tlo = (uint32_t)tag, thi = (uint32_t)(tag >> 32);
         for (uint32_t k = s0[j]; k < s1[j]; ++k) {
             const float4 a = pm.rec[2 * (size_t)k];
-            if (__float_as_uint(a.w) != ch) continue;
-            if (pm_cell(a.x, pm.inv_h) != x || pm_cell(a.y, pm.inv_h) != y || pm_cell(a.z, pm.inv_h) != z) continue;
             const float4 b = pm.rec[2 * (size_t)k + 1];
-            const F3 n{b.x, b.y, b.z};
-            if (!(dot(n, N) > 0.0f)) continue;
+            if (__float_as_uint(a.w) != tlo || __float_as_uint(b.w) != thi) continue;
             const F3 dl = F3{a.x, a.y, a.z} - P;
-            if (dot(dl, dl) < pm.r2) sum += pm.q[k];
+            if (!(dot(dl, dl) < pm.r2)) continue;
+            const F3 n{b.x, b.y, b.z};
+            if (dot(n, N) > 0.0f) sum += pm.q[k];
         }
     }
     return (float)((double)sum * pm.c);

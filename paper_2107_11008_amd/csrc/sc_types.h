@@ -92,12 +92,13 @@ struct PhotonState {
 };
 
 // device view of a general photon map: stored photons sorted into hash
-// buckets of (cell, channel), cells 3 r wide
+// buckets of (cell, channel), cells 2.25 r wide
 struct PMapDev {
-    const float4* rec;             // [n][2]: (x, y, z, channel as bits), (nx, ny, nz, 0)
+    const float4* rec;             // [n][2]: (x, y, z, cell tag low bits), (nx, ny, nz, cell tag high bits)
     const unsigned long long* q;   // flux in fixed point, round(phi 2^S)
     const uint32_t* start;         // [buckets + 1] first record of each bucket
     uint32_t mask;                 // buckets - 1
+    uint32_t cbits;                // channel bits at the bottom of a bucket index
     uint32_t on;                   // 0: caustics from the receiver map instead
     float r, r2, inv_h;            // radius, radius^2, 1 / cell width
     double c;                      // 1 / (2^S pi r^2)

@@ -327,9 +327,13 @@ __global__ void k_shade_dielectric(DevScene S, CamInfo ci, PathState P, uint32_t
     }
 }
 
+// PM: caustics gathered from a general photon map (pm), else from the
+// receiver map cmap; the template lets the default path drop the gather.
+template <bool PM>
 __global__ void k_shade_diffuse(DevScene S, CamInfo ci, WaveDev wl, PathState P, uint32_t depth,
-                                const float* __restrict__ cmap, PMapDev pm, const uint32_t* __restrict__ q,
+                                const float* __restrict__ cmap, PMapDev pm_arg, const uint32_t* __restrict__ q,
                                 uint32_t* counts, uint32_t* q_next, uint32_t* q_shadow) {
+    const PMapDev pm = PM ? pm_arg : PMapDev{};
     const uint32_t n = counts[QC_DIFF];
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
@@ -568,11 +572,13 @@ __device__ __forceinline__ void count_rays(uint32_t n_cl, uint32_t n_sh, DevCoun
     }
 }
 
+template <bool PM>
 __global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo ci, WaveDev wl, PathState P,
-                                                            const float* __restrict__ cmap, PMapDev pm,
+                                                            const float* __restrict__ cmap, PMapDev pm_arg,
                                                             const uint32_t* __restrict__ queue,
                                                             const uint32_t* __restrict__ count, uint32_t depth0,
                                                             uint32_t* __restrict__ work, DevCounters* __restrict__ C) {
+    const PMapDev pm = PM ? pm_arg : PMapDev{};
     __shared__ uint2 lds[kLdsStack][kTraceBS];
     Spill st;
     VisitCount vc;
@@ -962,15 +968,21 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
                                    q.dielectric, n);
                 hipLaunchKernelGGL(k_shade_dielectric, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, P, depth,
                                    q.dielectric, fc, nxt);
-                hipLaunchKernelGGL(k_shade_diffuse, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, wd, P, depth, cmap,
-                                   pm, q.diffuse, fc, nxt, q.shadow);
+                if (pm.on)
+                    hipLaunchKernelGGL(k_shade_diffuse<true>, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, wd, P,
+                                       depth, cmap, pm, q.diffuse, fc, nxt, q.shadow);
+                else
+                    hipLaunchKernelGGL(k_shade_diffuse<false>, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, wd, P,
+                                       depth, cmap, pm, q.diffuse, fc, nxt, q.shadow);
                 launch_anyhit(c, S, SR, q.shadow, fc + QC_SHADOW, 0u, n, nullptr, P.L);
                 std::swap(cur, nxt);
             }
-            if (staged < max_depth)
-                hipLaunchKernelGGL(k_finish_camera, dim3(trace_grid(n)), dim3(kTraceBS), 0, st, S, ci, wd, P, cmap, pm, cur,
+            if (staged < max_depth) {
+                auto kfin = pm.on ? k_finish_camera<true> : k_finish_camera<false>;
+                hipLaunchKernelGGL(kfin, dim3(trace_grid(n)), dim3(kTraceBS), 0, st, S, ci, wd, P, cmap, pm, cur,
                                    q.counts + (size_t)staged * QC_FRAME + QC_CUR, staged + 1, next_work_slot(c),
                                    c->counters.as<DevCounters>());
+            }
             hipLaunchKernelGGL(k_film_accumulate, dim3(grid_for(hw, bs)), dim3(bs), 0, st, ci, wd, P.L, P.lambda, ns,
                                out.rgb);
         }
