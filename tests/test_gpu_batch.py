@@ -94,3 +94,27 @@ def test_batch_rejects_bad_tuning(setup):
         sc.Batch(ctx, items, dict(block_size=96, blocks_per_cu=4, px_per_item=64))
     with pytest.raises(sc.ScError):
         sc.Batch(ctx, items, dict(block_size=64, blocks_per_cu=4, px_per_item=100))
+
+
+def test_batch_with_richer_glass_and_rgb_texture():
+    """Absorbing, rough, nested and overlapping glass and an RGB-textured
+    floor in the batched form: still the single-scene outputs, bit for bit
+    (the per-path functions carry the media set and the weights)."""
+    import paper_2107_11008_amd as sc
+    ctx = sc.Context(0)
+    cfgs = [sg.tinted_nested(w=40, h=32), sg.config3(tri_scale=0.01, w=48, h=32, floor="rgb"),
+            sg.config2(tri_scale=0.03, w=40, h=32, glass_style="rich")]
+    items, refs = [], []
+    for c in cfgs:
+        bvh = ctx.build_bvh(c["scene"])
+        n_ph, spp = 1 << 14, 2
+        items.append(dict(bvh=bvh, cam=c["camera"], spp=spp, max_depth=c["max_depth"], wl=c["wavelengths"],
+                          seed=c["render_seed"], photon_seed=c["photon_seed"], n_photons=n_ph))
+        m = ctx.trace_photons(bvh, n_ph, c["max_depth"], c["wavelengths"], c["photon_seed"])["map"]
+        r = ctx.render(bvh, c["camera"], spp, c["max_depth"], c["wavelengths"], c["render_seed"], caustic_map=m)
+        r["caustic_map"] = m
+        refs.append(r)
+    b = sc.Batch(ctx, items, dict(block_size=128, blocks_per_cu=4, px_per_item=64, use_graph=1))
+    b.run()
+    torch.cuda.synchronize()
+    _check(b, refs)
