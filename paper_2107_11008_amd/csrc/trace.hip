@@ -561,9 +561,11 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
 // After the first bounces have run as one launch per stage, the paths still
 // alive are few and a launch per further bounce would cost a whole traversal
 // latency each.  These kernels give each remaining path (or photon) to one
-// lane, which follows it to its end with the same per-path functions, so
-// the outputs are the same bit for bit.  Paths come in chunks of 64 per
-// wave, the first by the wave's index, the rest from the launch's counter.
+// lane, which follows it one bounce per loop turn with the same per-path
+// functions, so the outputs are the same bit for bit.  A lane whose path has
+// ended takes the next one through the same feed as the traversal kernel
+// (per-wave batches, refilled once enough lanes are idle), so a wave does not
+// wait for its longest path with the other lanes idle.
 __device__ __forceinline__ void count_rays(uint32_t n_cl, uint32_t n_sh, DevCounters* C) {
     const unsigned long long a = wave_sum_u64(n_cl), b = wave_sum_u64(n_sh);
     if (lane_id() == 0) {
@@ -583,22 +585,48 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo 
     Spill st;
     VisitCount vc;
     const uint32_t n = *count;
+    RayFeed feed;
+    feed.init(n, work);
     uint32_t n_cl = 0, n_sh = 0;
-    uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
-    while (base < n) {
-        const uint32_t i = base + lane_id();
-        if (i < n) {
-            const uint32_t pid = queue[i];
-            uint32_t pix, sample, slot;
+    CamPath c;
+    uint32_t pid = 0, pix = 0, sample = 0, slot = 0, depth = 0;
+    bool active = false;
+    for (;;) {
+        const uint32_t i = feed.take(!active);
+        if (i != 0xffffffffu) {
+            pid = queue[i];
             pid_decode(ci, pid, pix, sample, slot);
-            CamPath c = load_path(P, pid);
-            camera_continue<kTraceBS, false>(S, wl, cmap, pm, ci.seed, pix, sample, slot, depth0, ci.max_depth, c, lds,
-                                             st, vc, n_cl, n_sh);
-            P.L[pid] = c.L;
+            c = load_path(P, pid);
+            depth = depth0;
+            active = true;
         }
-        uint32_t next = 0;
-        if (lane_id() == 0) next = atomicAdd(work, 64u);
-        base = __shfl(next, 0) + gridDim.x * blockDim.x;
+        if (__ballot(active) == 0ull) break;
+        if (!active) continue;
+        // one bounce, as in camera_continue
+        const HitRec h = trace_closest<kTraceBS, false>(S, c.o, c.d, lds, st, vc);
+        ++n_cl;
+        bool cont = false;
+        if (h.prim != 0xffffffffu) {
+            const uint32_t type = S.mat[S.tri_obj[h.prim]].type;
+            if (type == SC_MAT_EMISSIVE) {
+                camera_emission(S, h, c);
+            } else if (type == SC_MAT_DIELECTRIC) {
+                cont = camera_dielectric(S, ci.seed, pix, sample, slot, depth, ci.max_depth, h, c);
+            } else {
+                ShadowReq sr;
+                cont = camera_diffuse(S, wl, cmap, pm, ci.seed, pix, sample, slot, depth, ci.max_depth, h, c, sr);
+                if (sr.shoot) {
+                    ++n_sh;
+                    if (!trace_any<kTraceBS>(S, sr.o, sr.d, sr.tmax, sr.excl, lds, st)) c.L = c.L + sr.contrib;
+                }
+            }
+        }
+        if (cont) {
+            ++depth;
+        } else {
+            P.L[pid] = c.L;
+            active = false;
+        }
     }
     count_rays(n_cl, n_sh, C);
 }
@@ -614,13 +642,16 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
     Spill st;
     VisitCount vc;
     const uint32_t n = *count;
+    RayFeed feed;
+    feed.init(n, work);
     uint32_t n_cl = 0;
-    uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
-    while (base < n) {
-        const uint32_t i = base + lane_id();
-        if (i < n) {
-            const uint32_t id = queue[i];
-            PhotonPath ph;
+    PhotonPath ph;
+    uint32_t id = 0, depth = 0;
+    bool active = false;
+    for (;;) {
+        const uint32_t i = feed.take(!active);
+        if (i != 0xffffffffu) {
+            id = queue[i];
             ph.o = F3{Ph.ox[id], Ph.oy[id], Ph.oz[id]};
             ph.d = F3{Ph.dx[id], Ph.dy[id], Ph.dz[id]};
             ph.phi = Ph.phi[id];
@@ -628,24 +659,35 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
             ph.slot = Ph.slot[id];
             ph.spec = Ph.spec[id];
             ph.med = Ph.med[id];
-            const int outcome = photon_continue<kTraceBS>(
-                S, wl, pi.seed, pi.p0 + id, depth0, pi.max_depth, pi.general != 0, ph, lds, st, vc, n_cl,
-                [&](const Deposit& dp, const PhotonPath& q) {
-                    if (pi.general) {
-                        const uint32_t k = atomicAdd(&pi.rec.stat[0], 1u);
-                        atomicMax(&pi.rec.stat[1], __float_as_uint(q.phi));
-                        atomicMax(&pi.rec.stat[2], pm_extent_bits(dp));
-                        pm_store(pi.rec, k, dp, (uint32_t)dp.cell_ch, q.phi, pi.p0 + id);
-                        return;
-                    }
-                    atomicAdd(&acc[dp.cell_ch], __double2ull_rn((double)q.phi * pi.scale));
-                    if (cnt_map) atomicAdd(&cnt_map[dp.cell_ch], 1u);
-                });
-            if (outcome >= 0) ph_stat(C, pi, outcome, ph.phi);
+            depth = depth0;
+            active = true;
         }
-        uint32_t next = 0;
-        if (lane_id() == 0) next = atomicAdd(work, 64u);
-        base = __shfl(next, 0) + gridDim.x * blockDim.x;
+        if (__ballot(active) == 0ull) break;
+        if (!active) continue;
+        // one interaction, as in photon_continue
+        const HitRec h = trace_closest<kTraceBS, false>(S, ph.o, ph.d, lds, st, vc);
+        ++n_cl;
+        int outcome = -1;
+        Deposit dp;
+        const bool cont =
+            photon_event(S, wl, pi.seed, pi.p0 + id, depth, pi.max_depth, pi.general != 0, h, ph, outcome, dp);
+        if (dp.cell_ch >= 0) {
+            if (pi.general) {
+                const uint32_t k = atomicAdd(&pi.rec.stat[0], 1u);
+                atomicMax(&pi.rec.stat[1], __float_as_uint(ph.phi));
+                atomicMax(&pi.rec.stat[2], pm_extent_bits(dp));
+                pm_store(pi.rec, k, dp, (uint32_t)dp.cell_ch, ph.phi, pi.p0 + id);
+            } else {
+                atomicAdd(&acc[dp.cell_ch], __double2ull_rn((double)ph.phi * pi.scale));
+                if (cnt_map) atomicAdd(&cnt_map[dp.cell_ch], 1u);
+            }
+        }
+        if (cont) {
+            ++depth;
+        } else {
+            if (outcome >= 0) ph_stat(C, pi, outcome, ph.phi);
+            active = false;
+        }
     }
     count_rays(n_cl, 0u, C);
 }
