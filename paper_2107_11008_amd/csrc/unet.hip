@@ -119,10 +119,11 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
 }
 
 // 3x3 convolution with LDS tiles.  A block computes an 8 x 16 tile of output
-// pixels x 64 output channels (blockIdx.y selects the channel group); the
-// input channels are taken 32 at a time: the tile with its 1-pixel halo and
-// the 64 x 9 x 32 weights of the chunk are staged in LDS, then every tap
-// reads its operands there.  Wave w computes tile rows 2w and 2w+1 (two
+// pixels x 16 NT output channels (blockIdx.y selects the channel group; NT
+// is 4, or 2 for layers of at most 32 channels, whose smaller weight tile
+// lets more blocks share a CU); the input channels are taken 32 at a time:
+// the tile with its 1-pixel halo and the 16 NT x 9 x 32 weights of the
+// chunk are staged in LDS, then every tap reads its operands there.  Wave w computes tile rows 2w and 2w+1 (two
 // 16-pixel A operands sharing each weight operand).  Channels past cin_p in
 // the last chunk are zero in both tiles.  With X2 given, the input is the
 // concatenation [nearest 2x upsampling of X (c_split channels at H/2 x W/2),
@@ -131,6 +132,7 @@ constexpr int kTR = 8, kTC = 16, kHR = kTR + 2, kHC = kTC + 2;
 constexpr int kCC = 32;                 // input channels per chunk
 constexpr int kWP = 9 * kCC + 8;        // LDS pitch of a weight row (bf16), padded against bank conflicts
 
+template <int NT>
 __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ X2,
                                                uint32_t c_split, uint32_t H, uint32_t W, uint32_t cin_p,
                                                const uint16_t* __restrict__ Wt, uint32_t kpad,
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
                                                uint16_t* __restrict__ Y, float* __restrict__ Yf, uint32_t y_stride,
                                                uint32_t y_off, int relu) {
     __shared__ uint4 xs4[kHR * kHC * kCC / 8];
-    __shared__ uint4 ws4[64 * kWP / 8];
+    __shared__ uint4 ws4[16 * NT * kWP / 8];
     const uint16_t* xs = reinterpret_cast<const uint16_t*>(xs4);
     const uint16_t* ws = reinterpret_cast<const uint16_t*>(ws4);
     const uint32_t tiles_x = (W + kTC - 1) / kTC, tiles_y = (H + kTR - 1) / kTR;
@@ -152,12 +154,12 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t pl = lane & 15, g = lane >> 4;
     const uint32_t nt_total = cout_p / 16;
-    const uint32_t nt_here = min(4u, nt_total - cg * 4);   // 16-channel tiles of this group
-    floatx4 acc[2][4];
+    const uint32_t nt_here = min((uint32_t)NT, nt_total - cg * NT);   // 16-channel tiles of this group
+    floatx4 acc[2][NT];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[r][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int j = 0; j < NT; ++j) acc[r][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     for (uint32_t c0 = 0; c0 < cin_p; c0 += kCC) {
         const uint32_t cn = min((uint32_t)kCC, cin_p - c0);
         __syncthreads();   // the previous chunk is no longer read
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
         for (uint32_t t = threadIdx.x; t < 16 * nt_here * 9 * 4; t += 256) {
             const uint32_t piece = t & 3, rest = t >> 2;
             const uint32_t tap = rest % 9, col = rest / 9;
-            const uint32_t co = cg * 64 + col;
+            const uint32_t co = cg * 16 * NT + col;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (piece * 8 < cn)
                 v = *reinterpret_cast<const uint4*>(Wt + (size_t)co * kpad + (size_t)tap * cin_p + c0 + piece * 8);
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
             a0.u = *reinterpret_cast<const uint4*>(xs + (((2 * wv + dy) * kHC) + pl + dx) * kCC + 8 * g);
             a1.u = *reinterpret_cast<const uint4*>(xs + (((2 * wv + 1 + dy) * kHC) + pl + dx) * kCC + 8 * g);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < NT; ++j) {
                 if ((uint32_t)j < nt_here) {
                     Frag bw;
                     bw.u = *reinterpret_cast<const uint4*>(ws + (j * 16 + pl) * kWP + tap * kCC + 8 * g);
@@ -210,9 +212,9 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
         const uint32_t yy = y0 + 2 * wv + r;
         if (yy >= H) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NT; ++j) {
             if ((uint32_t)j >= nt_here) continue;
-            const uint32_t co = (cg * 4 + j) * 16 + pl;
+            const uint32_t co = (cg * NT + j) * 16 + pl;
             if (co >= cout_real) continue;
             const float bv = bias ? bias[co] : 0.0f;
 #pragma unroll
@@ -706,8 +708,12 @@ void conv_launch(hipStream_t st, const UnetLayer& L, const uint16_t* X, uint32_t
     if (L.ks == 3) {
         const uint32_t B = P / (H * W);
         const uint32_t tiles = ((W + kTC - 1) / kTC) * ((H + kTR - 1) / kTR) * B;
-        hipLaunchKernelGGL(k_conv3, dim3(tiles, (cout_p / 16 + 3) / 4), dim3(256), 0, st, X, X2, c_split, H, W,
-                           cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
+        if (cout_p <= 32)
+            hipLaunchKernelGGL(k_conv3<2>, dim3(tiles, (cout_p / 16 + 1) / 2), dim3(256), 0, st, X, X2, c_split, H, W,
+                               cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
+        else
+            hipLaunchKernelGGL(k_conv3<4>, dim3(tiles, (cout_p / 16 + 3) / 4), dim3(256), 0, st, X, X2, c_split, H, W,
+                               cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
     } else
         hipLaunchKernelGGL(k_conv<1>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
                            cout_real, Y, Yf, y_stride, 0u, relu);
