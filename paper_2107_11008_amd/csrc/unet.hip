@@ -119,9 +119,10 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
 }
 
 // 3x3 convolution with LDS tiles.  A block computes an 8 x 16 tile of output
-// pixels x 16 NT output channels (blockIdx.y selects the channel group; NT
-// is 4, or 2 for layers of at most 32 channels, whose smaller weight tile
-// lets more blocks share a CU); the input channels are taken 32 at a time:
+// pixels x 16 NT output channels (blockIdx.y selects the channel group; NT =
+// kConvTiles = 2: 30 KB of LDS per block, 5 blocks per CU; measured at
+// 1080p, 4 tiles with 49 KB and 3 blocks per CU took 1.97 ms per frame, 2
+// tiles 1.55 ms, 1 tile 1.87 ms); the input channels are taken 32 at a time:
 // the tile with its 1-pixel halo and the 16 NT x 9 x 32 weights of the
 // chunk are staged in LDS, then every tap reads its operands there.  Wave w computes tile rows 2w and 2w+1 (two
 // 16-pixel A operands sharing each weight operand).  Channels past cin_p in
@@ -131,6 +132,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
 constexpr int kTR = 8, kTC = 16, kHR = kTR + 2, kHC = kTC + 2;
 constexpr int kCC = 32;                 // input channels per chunk
 constexpr int kWP = 9 * kCC + 8;        // LDS pitch of a weight row (bf16), padded against bank conflicts
+constexpr int kConvTiles = 2;           // 16-channel output tiles per block
 
 template <int NT>
 __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ X2,
@@ -708,12 +710,9 @@ void conv_launch(hipStream_t st, const UnetLayer& L, const uint16_t* X, uint32_t
     if (L.ks == 3) {
         const uint32_t B = P / (H * W);
         const uint32_t tiles = ((W + kTC - 1) / kTC) * ((H + kTR - 1) / kTR) * B;
-        if (cout_p <= 32)
-            hipLaunchKernelGGL(k_conv3<2>, dim3(tiles, (cout_p / 16 + 1) / 2), dim3(256), 0, st, X, X2, c_split, H, W,
-                               cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
-        else
-            hipLaunchKernelGGL(k_conv3<4>, dim3(tiles, (cout_p / 16 + 3) / 4), dim3(256), 0, st, X, X2, c_split, H, W,
-                               cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
+        hipLaunchKernelGGL(k_conv3<kConvTiles>, dim3(tiles, (cout_p / 16 + kConvTiles - 1) / kConvTiles), dim3(256), 0,
+                           st, X, X2, c_split, H, W, cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u,
+                           relu);
     } else
         hipLaunchKernelGGL(k_conv<1>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
                            cout_real, Y, Yf, y_stride, 0u, relu);
