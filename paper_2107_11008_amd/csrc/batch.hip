@@ -37,7 +37,7 @@ __device__ __forceinline__ uint32_t scene_of(const BatchScene* __restrict__ B, u
 }
 
 template <int BS>
-__global__ __launch_bounds__(BS) void k_batch_photons(const BatchScene* __restrict__ B, uint32_t n_scenes,
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_photons(const BatchScene* __restrict__ B, uint32_t n_scenes,
                                                       uint32_t n_items, uint32_t per_item, uint32_t* work) {
     __shared__ uint2 lds[kLdsStack][BS];
     Spill st;
