@@ -283,26 +283,64 @@ def test_invalid_arguments_raise(ctx):
         ctx.build_bvh(s2)
 
 
-def test_c2_full_size_sampled_pixels(ctx):
-    """The full 512x512, 16 spp medium scene in the launch configuration the
-    benchmark times, checked on a seeded sample of pixels the oracle
-    renders one by one (gathering from the same caustic map)."""
-    c = sg.config2()
+def _full_size_sampled(ctx, c, n_map_photons=1 << 16, n_pix=96):
+    """Render the full-size image on the GPU in the benchmark's launch
+    configuration and a seeded sample of its pixels with the oracle, both
+    gathering from one caustic map the oracle builds (full map resolution,
+    fewer photons than the benchmark so that the oracle finishes quickly)."""
     scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
-    bvh = ctx.build_bvh(scene)
-    gm = ctx.trace_photons(bvh, c["n_photons"], c["max_depth"], wl, c["photon_seed"])["map"]
-    g = ctx.render(bvh, cam, c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=gm)
-    rng = np.random.default_rng(11)
-    pix = np.sort(rng.choice(cam.w * cam.h, size=96, replace=False)).astype(np.uint32)
     osc = oracle.OracleScene(scene)
-    o = oracle.render(osc, cam, c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=gm.cpu().numpy(),
-                      pixels=pix)
+    om, _, _, _ = oracle.trace_photons(osc, n_map_photons, c["max_depth"], wl, c["photon_seed"])
+    bvh = ctx.build_bvh(scene)
+    g = ctx.render(bvh, cam, c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=_t(om))
+    rng = np.random.default_rng(11)
+    pix = np.sort(rng.choice(cam.w * cam.h, size=n_pix, replace=False)).astype(np.uint32)
+    o = oracle.render(osc, cam, c["spp"], c["max_depth"], wl, c["render_seed"], caustic_map=om, pixels=pix)
     m = np.zeros(cam.w * cam.h, bool)
     m[pix] = True
     m = m.reshape(cam.h, cam.w)
     assert np.array_equal(_bits(g["rgb"].cpu().numpy()[m]), _bits(o["rgb"][m]))
     _cmp_aov(g, o, mask=m)
-    # full-size ground truth: every pixel
+    return g, osc
+
+
+def test_c2_rich_glass_full_size_sampled_pixels(ctx):
+    """The medium scene with tinted and rough glass (a benchmark leg) at
+    full size, on sampled pixels."""
+    _full_size_sampled(ctx, sg.config2(glass_style="rich"))
+
+
+def test_c2_general_map_full_size_sampled_pixels(ctx):
+    """The full-size medium scene rendered with the general photon map (a
+    benchmark leg), on sampled pixels; each side builds its map from its own
+    photon pass of 2^16 photons (the stored photons are equal bit for bit)."""
+    c = sg.config2()
+    scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
+    radius, n_ph = 4.0 / 1024, 1 << 16
+    osc = oracle.OracleScene(scene)
+    recs, _ = oracle.pm_trace(osc, n_ph, c["max_depth"], wl, c["photon_seed"])
+    bvh = ctx.build_bvh(scene)
+    pm = ctx.pmap_trace(bvh, n_ph, c["max_depth"], wl, c["photon_seed"], radius)
+    g = ctx.render(bvh, cam, c["spp"], c["max_depth"], wl, c["render_seed"], pmap=pm, outputs=("rgb",))
+    rng = np.random.default_rng(12)
+    pix = np.sort(rng.choice(cam.w * cam.h, size=96, replace=False)).astype(np.uint32)
+    o = oracle.render_pm(osc, cam, c["spp"], c["max_depth"], wl, c["render_seed"], recs, radius, pixels=pix)
+    m = np.zeros(cam.w * cam.h, bool)
+    m[pix] = True
+    m = m.reshape(cam.h, cam.w)
+    assert np.array_equal(_bits(g["rgb"].cpu().numpy()[m]), _bits(o["rgb"][m]))
+    assert o["rgb"][m].max() > 0
+
+
+def test_c2_full_size_sampled_pixels(ctx):
+    """The full 512x512, 16 spp medium scene in the launch configuration the
+    benchmark times, checked on a seeded sample of pixels the oracle
+    renders one by one (both gathering from one oracle-built caustic map),
+    and its ground truth on every 7th pixel."""
+    c = sg.config2()
+    scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
+    g, osc = _full_size_sampled(ctx, c)
+    # full-size ground truth: every 7th pixel
     ogt = oracle.render(osc, cam, 1, 1, wl, 1, pixels=np.arange(0, cam.w * cam.h, 7, dtype=np.uint32))
     m2 = np.zeros(cam.w * cam.h, bool)
     m2[::7] = True
