@@ -83,6 +83,7 @@ struct Ctx {
     bool profile = false;
     uint64_t queue_cap = 1ull << 23;
     uint32_t staged_depth = 5;   // bounces run as separate launches before paths are finished per lane
+    uint64_t conv_big_tile = 2048;   // 16-row U-Net convolution tiles needed before they are used
     uint64_t photon_cap = 1ull << 22;
     DevBuf counters;   // DevCounters
     DevBuf work;       // per-launch work counters of the traversal kernels

@@ -61,15 +61,19 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
     const uint32_t pl = lane & 15, g = lane >> 4;
     const uint32_t p = tile * 16 + pl;
     const bool pvalid = p < P;
-    const uint32_t x = pvalid ? p % W : 0, rest = pvalid ? p / W : 0;
-    const uint32_t y = rest % H, b = rest / H;
+    uint32_t x = 0, y = 0;
+    if (KS == 3 && pvalid) {   // a 1x1 convolution needs no pixel coordinates
+        const uint32_t rest = p / W;
+        x = p - rest * W;
+        y = rest % H;
+    }
     const uint32_t K = KS * KS * cin_p;
     floatx4 acc[4];
     for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     // this lane's k-group (8 channels of one tap, as cin_p is a multiple of
     // 16) advances by 32 per step: tap and channel are carried along
     uint32_t tap = (8 * g) / cin_p, ci = (8 * g) % cin_p;
-    const size_t pix0 = ((size_t)b * H + y) * W + x;
+    const size_t pix0 = p;   // = (b H + y) W + x
     for (uint32_t k0 = 0; k0 < kpad; k0 += 32) {
         const uint32_t kk = k0 + 8 * g;
         Frag a;
@@ -118,29 +122,32 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
     }
 }
 
-// 3x3 convolution with LDS tiles.  A block computes an 8 x 16 tile of output
-// pixels x 16 NT output channels (blockIdx.y selects the channel group; NT =
-// kConvTiles = 2: 30 KB of LDS per block, 5 blocks per CU; measured at
-// 1080p, 4 tiles with 49 KB and 3 blocks per CU took 1.97 ms per frame, 2
-// tiles 1.55 ms, 1 tile 1.87 ms); the input channels are taken 32 at a time:
-// the tile with its 1-pixel halo and the 16 NT x 9 x 32 weights of the
-// chunk are staged in LDS, then every tap reads its operands there.  Wave w computes tile rows 2w and 2w+1 (two
-// 16-pixel A operands sharing each weight operand).  Channels past cin_p in
-// the last chunk are zero in both tiles.  With X2 given, the input is the
-// concatenation [nearest 2x upsampling of X (c_split channels at H/2 x W/2),
-// X2 (cin_p - c_split channels)], read in place (decoder inference).
-constexpr int kTR = 8, kTC = 16, kHR = kTR + 2, kHC = kTC + 2;
+// 3x3 convolution with LDS tiles.  A block computes a 4 RW x 16 tile of
+// output pixels x 16 NT output channels (blockIdx.y selects the channel
+// group); wave w computes tile rows RW w .. RW w + RW - 1, RW 16-pixel A
+// operands sharing each weight operand.  The input channels are taken 32 at a
+// time: the tile with its 1-pixel halo and the 16 NT x 9 x 32 weights of the
+// chunk are staged in LDS, then every tap reads its operands there.
+// Channels past cin_p in the last chunk are zero in both tiles.  With X2
+// given, the input is the concatenation [nearest 2x upsampling of X (c_split
+// channels at H/2 x W/2), X2 (cin_p - c_split channels)], read in place
+// (decoder inference).  Every output sums chunk by chunk and tap by tap, so
+// the tile shape does not change a result.  Pixel and element indices fit in
+// 32 bits (the host checks P * channels < 2^31); addresses are formed once
+// per row.
+constexpr int kTC = 16, kHC = kTC + 2;
 constexpr int kCC = 32;                 // input channels per chunk
 constexpr int kWP = 9 * kCC + 8;        // LDS pitch of a weight row (bf16), padded against bank conflicts
 constexpr int kConvTiles = 2;           // 16-channel output tiles per block
 
-template <int NT>
+template <int NT, int RW>
 __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ X2,
                                                uint32_t c_split, uint32_t H, uint32_t W, uint32_t cin_p,
                                                const uint16_t* __restrict__ Wt, uint32_t kpad,
                                                const float* __restrict__ bias, uint32_t cout_p, uint32_t cout_real,
                                                uint16_t* __restrict__ Y, float* __restrict__ Yf, uint32_t y_stride,
                                                uint32_t y_off, int relu) {
+    constexpr int kTR = 4 * RW, kHR = kTR + 2;
     __shared__ uint4 xs4[kHR * kHC * kCC / 8];
     __shared__ uint4 ws4[16 * NT * kWP / 8];
     const uint16_t* xs = reinterpret_cast<const uint16_t*>(xs4);
@@ -157,9 +164,11 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
     const uint32_t pl = lane & 15, g = lane >> 4;
     const uint32_t nt_total = cout_p / 16;
     const uint32_t nt_here = min((uint32_t)NT, nt_total - cg * NT);   // 16-channel tiles of this group
-    floatx4 acc[2][NT];
+    const uint32_t c_rest = cin_p - c_split;
+    const uint32_t Hh = H / 2, Wh = W / 2;
+    floatx4 acc[RW][NT];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < RW; ++r)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[r][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     for (uint32_t c0 = 0; c0 < cin_p; c0 += kCC) {
@@ -167,67 +176,74 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
         __syncthreads();   // the previous chunk is no longer read
         for (uint32_t t = threadIdx.x; t < kHR * kHC * 4; t += 256) {
             const uint32_t piece = t & 3, pix = t >> 2;
-            const int yy = (int)y0 + (int)(pix / kHC) - 1, xx = (int)x0 + (int)(pix % kHC) - 1;
+            const uint32_t py = pix / kHC, px = pix - py * kHC;
+            const uint32_t yy = y0 + py - 1u, xx = x0 + px - 1u;   // wraps to a large value at -1
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             const uint32_t c = c0 + piece * 8;
-            if (piece * 8 < cn && yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W) {
-                const size_t pix_full = ((size_t)b * H + yy) * W + xx;
+            if (piece * 8 < cn && yy < H && xx < W) {
+                const uint32_t pix_full = (b * H + yy) * W + xx;
                 if (!X2)
-                    v = *reinterpret_cast<const uint4*>(X + pix_full * cin_p + c);
+                    v = *reinterpret_cast<const uint4*>(X + (size_t)pix_full * cin_p + c);
                 else if (c < c_split)   // nearest 2x upsampling of the coarser tensor
-                    v = *reinterpret_cast<const uint4*>(
-                        X + (((size_t)b * (H / 2) + (uint32_t)yy / 2) * (W / 2) + (uint32_t)xx / 2) * c_split + c);
+                    v = *reinterpret_cast<const uint4*>(X + (size_t)((b * Hh + yy / 2) * Wh + xx / 2) * c_split + c);
                 else
-                    v = *reinterpret_cast<const uint4*>(X2 + pix_full * (cin_p - c_split) + (c - c_split));
+                    v = *reinterpret_cast<const uint4*>(X2 + (size_t)pix_full * c_rest + (c - c_split));
             }
-            xs4[pix * (kCC / 8) + piece] = v;
+            xs4[t] = v;   // pixel pix, channels 8 piece .. 8 piece + 7 of the chunk
         }
+        const uint16_t* wsrc = Wt + (size_t)(cg * 16 * NT) * kpad + c0;
         for (uint32_t t = threadIdx.x; t < 16 * nt_here * 9 * 4; t += 256) {
             const uint32_t piece = t & 3, rest = t >> 2;
-            const uint32_t tap = rest % 9, col = rest / 9;
-            const uint32_t co = cg * 16 * NT + col;
+            const uint32_t col = rest / 9, tap = rest - col * 9;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (piece * 8 < cn)
-                v = *reinterpret_cast<const uint4*>(Wt + (size_t)co * kpad + (size_t)tap * cin_p + c0 + piece * 8);
+            if (piece * 8 < cn) v = *reinterpret_cast<const uint4*>(wsrc + col * kpad + tap * cin_p + piece * 8);
             ws4[(col * kWP + tap * kCC) / 8 + piece] = v;
         }
         __syncthreads();
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;
-            Frag a0, a1;
-            a0.u = *reinterpret_cast<const uint4*>(xs + (((2 * wv + dy) * kHC) + pl + dx) * kCC + 8 * g);
-            a1.u = *reinterpret_cast<const uint4*>(xs + (((2 * wv + 1 + dy) * kHC) + pl + dx) * kCC + 8 * g);
+            Frag a[RW];
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+                a[r].u = *reinterpret_cast<const uint4*>(xs + (((RW * wv + r + dy) * kHC) + pl + dx) * kCC + 8 * g);
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
                 if ((uint32_t)j < nt_here) {
                     Frag bw;
                     bw.u = *reinterpret_cast<const uint4*>(ws + (j * 16 + pl) * kWP + tap * kCC + 8 * g);
-                    acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.v, bw.v, acc[0][j], 0, 0, 0);
-                    acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.v, bw.v, acc[1][j], 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < RW; ++r)
+                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r].v, bw.v, acc[r][j], 0, 0, 0);
                 }
             }
         }
     }
+    float bv[NT];
+    bool cok[NT];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const uint32_t yy = y0 + 2 * wv + r;
+    for (int j = 0; j < NT; ++j) {
+        const uint32_t co = (cg * NT + j) * 16 + pl;
+        cok[j] = (uint32_t)j < nt_here && co < cout_real;
+        bv[j] = (cok[j] && bias) ? bias[co] : 0.0f;
+    }
+    const uint32_t xb = x0 + 4 * g;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const uint32_t yy = y0 + RW * wv + r;
         if (yy >= H) continue;
+        const size_t row = (size_t)((b * H + yy) * W + xb) * y_stride + y_off + (cg * NT) * 16 + pl;
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            if ((uint32_t)j >= nt_here) continue;
-            const uint32_t co = (cg * NT + j) * 16 + pl;
-            if (co >= cout_real) continue;
-            const float bv = bias ? bias[co] : 0.0f;
+        for (int i = 0; i < 4; ++i) {
+            if (xb + i >= W) continue;
+            const size_t o = row + (size_t)i * y_stride;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t xx = x0 + 4 * g + i;
-                if (xx >= W) continue;
-                const size_t po = ((size_t)b * H + yy) * W + xx;
-                float v = acc[r][j][i] + bv;
+            for (int j = 0; j < NT; ++j) {
+                if (!cok[j]) continue;
+                float v = acc[r][j][i] + bv[j];
                 if (relu) v = fmaxf(v, 0.0f);
-                if (Yf) Yf[po * y_stride + y_off + co] = v;
-                else Y[po * y_stride + y_off + co] = to_bf16(v);
+                if (Yf) Yf[o + j * 16] = v;
+                else Y[o + j * 16] = to_bf16(v);
             }
         }
     }
@@ -342,28 +358,43 @@ __global__ void k_relu_mask(const uint16_t* __restrict__ dY, const uint16_t* __r
         dZ[i] = from_bf16(Y[i]) > 0.0f ? dY[i] : (uint16_t)0;
 }
 
+// 2x2 max pooling, 8 channels (16 bytes) per step; the arg-max (0..3, the
+// first of equal maxima) is kept for the backward pass.  H and W are even and
+// C a multiple of 8; element indices fit in 32 bits.
 __global__ void k_maxpool(const uint16_t* __restrict__ X, uint32_t B, uint32_t H, uint32_t W, uint32_t C,
                           uint16_t* __restrict__ Y, uint8_t* __restrict__ idx) {
-    const uint32_t h = H / 2, w = W / 2;
-    const size_t n = (size_t)B * h * w * C;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t c = i % C;
-        size_t r = i / C;
-        const uint32_t x = r % w;
-        r /= w;
-        const uint32_t y = r % h;
-        const uint32_t b = r / h;
-        float best = -INFINITY;
-        uint8_t bi = 0;
-        uint16_t bv = 0;
-        for (uint32_t q = 0; q < 4; ++q) {
-            const uint32_t yy = 2 * y + (q >> 1), xx = 2 * x + (q & 1);
-            const uint16_t v = X[(((size_t)b * H + yy) * W + xx) * C + c];
-            const float f = from_bf16(v);
-            if (f > best) { best = f; bi = (uint8_t)q; bv = v; }
+    const uint32_t h = H / 2, w = W / 2, c8n = C / 8;
+    const uint32_t n = B * h * w * c8n;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t pix = i / c8n, c = (i - pix * c8n) * 8;
+        const uint32_t by = pix / w, x = pix - by * w;   // by = b h + y, so the input rows are 2 by and 2 by + 1
+        union {
+            uint4 u;
+            uint16_t h[8];
+        } q[4], out;
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k)
+            q[k].u = *reinterpret_cast<const uint4*>(X + (size_t)((2 * by + (k >> 1)) * W + 2 * x + (k & 1)) * C + c);
+        uint32_t bi[2] = {0u, 0u};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            float best = -INFINITY;
+            uint32_t sel = 0;
+            uint16_t bvv = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) {
+                const float f = from_bf16(q[k].h[e]);
+                if (f > best) {
+                    best = f;
+                    sel = k;
+                    bvv = q[k].h[e];
+                }
+            }
+            out.h[e] = bvv;
+            bi[e >> 2] |= sel << (8 * (e & 3));
         }
-        Y[i] = bv;
-        idx[i] = bi;
+        reinterpret_cast<uint4*>(Y)[i] = out.u;
+        reinterpret_cast<uint2*>(idx)[i] = make_uint2(bi[0], bi[1]);
     }
 }
 
@@ -442,24 +473,33 @@ __global__ void k_pack_input(const float* __restrict__ f, uint32_t P, uint32_t i
     }
 }
 
-// features from the renderer's outputs into a zero-padded canvas
+// features from the renderer's outputs into a zero-padded canvas of 16
+// channels per pixel (two 16-byte stores)
 __global__ void k_features(const float* __restrict__ rgb, const float* __restrict__ albedo,
                            const float* __restrict__ normal, const float* __restrict__ depthn,
                            const uint8_t* __restrict__ trans, uint32_t w, uint32_t h, uint32_t W, uint32_t H,
-                           uint32_t cin_p, uint16_t* __restrict__ X) {
-    const size_t n = (size_t)W * H;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t x = i % W, y = i / W;
+                           uint16_t* __restrict__ X) {
+    const uint32_t n = W * H;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t y = i / W, x = i - y * W;
         float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (x < w && y < h) {
-            const size_t p = (size_t)y * w + x;
+            const uint32_t p = y * w + x;
             for (int c = 0; c < 3; ++c) v[c] = log1pf(fmaxf(rgb[3 * p + c], 0.0f));
             v[3] = albedo ? albedo[p] : 0.0f;
             for (int c = 0; c < 3; ++c) v[4 + c] = normal ? normal[3 * p + c] : 0.0f;
             v[7] = depthn ? depthn[p] : 0.0f;
             v[8] = trans ? (float)trans[p] : 0.0f;
         }
-        for (uint32_t c = 0; c < cin_p; ++c) X[i * cin_p + c] = c < 9 ? to_bf16(v[c]) : (uint16_t)0;
+        union {
+            uint4 u[2];
+            uint16_t h[16];
+        } o;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) o.h[c] = c < 9 ? to_bf16(v[c]) : (uint16_t)0;
+        uint4* dst = reinterpret_cast<uint4*>(X + (size_t)i * 16);
+        dst[0] = o.u[0];
+        dst[1] = o.u[1];
     }
 }
 
@@ -646,8 +686,9 @@ sc_status ensure_acts(Unet* u, uint32_t B, uint32_t H, uint32_t W) {
     if (u->B == B && u->H == H && u->W == W && u->acts.p) return SC_OK;
     const uint32_t L = (uint32_t)u->widths.size();
     // offsets (in bf16 elements) of every tensor
-    size_t off = 0;
+    size_t off = 0, largest = 0;
     auto take = [&](size_t n) {
+        largest = std::max(largest, n);
         size_t o = off;
         off += (n + 127) / 128 * 128;
         return o;
@@ -691,6 +732,8 @@ sc_status ensure_acts(Unet* u, uint32_t B, uint32_t H, uint32_t W) {
     T.g2 = take(maxt);
     T.skip.assign(L, 0);
     for (uint32_t i = 0; i + 1 < L; ++i) T.skip[i] = take((P0 >> (2 * i)) * u->widths[i]);
+    if (largest >= ((size_t)1 << 31))   // the kernels index the elements of one tensor in 32 bits
+        return set_error(SC_EUNSUPPORTED, "U-Net tensor of 2^31 elements or more");
     SC_TRY(u->acts.alloc(2 * off));
     SC_TRY(u->pred.alloc(4 * P0 * 3));
     u->B = B;
@@ -699,7 +742,8 @@ sc_status ensure_acts(Unet* u, uint32_t B, uint32_t H, uint32_t W) {
     return SC_OK;
 }
 
-void conv_launch(hipStream_t st, const UnetLayer& L, const uint16_t* X, uint32_t P, uint32_t H, uint32_t W,
+void conv_launch(hipStream_t st, uint64_t big_tile, const UnetLayer& L, const uint16_t* X, uint32_t P, uint32_t H,
+                 uint32_t W,
                  const uint16_t* Wt, uint32_t cin_p, uint32_t kpad, const float* bias, uint32_t cout_p,
                  uint32_t cout_real, uint16_t* Y, float* Yf, uint32_t y_stride, int relu,
                  const uint16_t* X2 = nullptr, uint32_t c_split = 0) {
@@ -708,11 +752,19 @@ void conv_launch(hipStream_t st, const UnetLayer& L, const uint16_t* X, uint32_t
     const size_t waves = (size_t)n_tiles * groups;
     const uint32_t grid = (uint32_t)((waves + 3) / 4);
     if (L.ks == 3) {
+        // 16-row tiles (4 rows per wave: each weight operand feeds 4 MFMAs,
+        // 40 KB of LDS, 4 blocks per CU) where a layer has at least big_tile
+        // of them (default 2048: several per CU), 8-row tiles otherwise
         const uint32_t B = P / (H * W);
-        const uint32_t tiles = ((W + kTC - 1) / kTC) * ((H + kTR - 1) / kTR) * B;
-        hipLaunchKernelGGL(k_conv3<kConvTiles>, dim3(tiles, (cout_p / 16 + kConvTiles - 1) / kConvTiles), dim3(256), 0,
-                           st, X, X2, c_split, H, W, cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u,
-                           relu);
+        const uint32_t gy = (cout_p / 16 + kConvTiles - 1) / kConvTiles;
+        const uint32_t tx = (W + kTC - 1) / kTC;
+        const uint32_t t16 = tx * ((H + 15) / 16) * B;
+        if ((uint64_t)t16 * gy >= big_tile)
+            hipLaunchKernelGGL((k_conv3<kConvTiles, 4>), dim3(t16, gy), dim3(256), 0, st, X, X2, c_split, H, W, cin_p,
+                               Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
+        else
+            hipLaunchKernelGGL((k_conv3<kConvTiles, 2>), dim3(tx * ((H + 7) / 8) * B, gy), dim3(256), 0, st, X, X2,
+                               c_split, H, W, cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
     } else
         hipLaunchKernelGGL(k_conv<1>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
                            cout_real, Y, Yf, y_stride, 0u, relu);
@@ -723,6 +775,7 @@ void conv_launch(hipStream_t st, const UnetLayer& L, const uint16_t* X, uint32_t
 // Forward pass over the packed input in u->acts (T.in); prediction in u->pred.
 sc_status unet_forward_packed(Unet* u, bool keep_cat) {
     hipStream_t st = u->ctx->stream;
+    const uint64_t big = u->ctx->conv_big_tile;
     const uint32_t L = (uint32_t)u->widths.size();
     uint16_t* A = u->acts.as<uint16_t>();
     const float* th = u->theta.as<float>();
@@ -741,8 +794,8 @@ sc_status unet_forward_packed(Unet* u, bool keep_cat) {
         for (int part = 0; part < 2; ++part) {
             const UnetLayer& Ly = u->layers[li++];
             uint16_t* out = A + (part == 0 ? T.enc_a[i] : T.enc_b[i]);
-            conv_launch(st, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p, Ly.cout, out,
-                        nullptr, Ly.cout, 1);
+            conv_launch(st, big, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p, Ly.cout,
+                        out, nullptr, Ly.cout, 1);
             h = out;
             hc = Ly.cout;
         }
@@ -762,15 +815,15 @@ sc_status unet_forward_packed(Unet* u, bool keep_cat) {
         for (int part = 0; part < 2; ++part) {
             const UnetLayer& Ly = u->layers[li++];
             uint16_t* out = A + (part == 0 ? T.dec_a[i] : T.dec_b[i]);
-            conv_launch(st, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p, Ly.cout, out,
-                        nullptr, Ly.cout, 1, part == 0 ? skip : nullptr, part == 0 ? split : 0u);
+            conv_launch(st, big, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p, Ly.cout,
+                        out, nullptr, Ly.cout, 1, part == 0 ? skip : nullptr, part == 0 ? split : 0u);
             h = out;
             hc = Ly.cout;
         }
     }
     const UnetLayer& Lo = u->layers[li];
     const uint32_t P0 = u->B * u->H * u->W;
-    conv_launch(st, Lo, h, P0, u->H, u->W, wf + Lo.wf_off, Lo.cin_p, Lo.kpad, th + Lo.b_off, Lo.cout_p, Lo.cout,
+    conv_launch(st, big, Lo, h, P0, u->H, u->W, wf + Lo.wf_off, Lo.cin_p, Lo.kpad, th + Lo.b_off, Lo.cout_p, Lo.cout,
                 nullptr, u->pred.as<float>(), 3, 0);
     u->cat_valid = keep_cat;
     SC_HIP(hipGetLastError());
@@ -804,8 +857,8 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
     hipLaunchKernelGGL(k_bias_grad, dim3(std::min<uint32_t>(1024, (P + 3) / 4)), dim3(256), 0, st, dZ, P, Ly.cout_p,
                        Ly.cout, g + Ly.b_off);
     if (dX)
-        conv_launch(st, Ly, dZ, P, H, W, u->wd.as<uint16_t>() + Ly.wd_off, Ly.cout_p, Ly.kpad_t, nullptr, Ly.cin_p,
-                    Ly.cin_p, dX, nullptr, Ly.cin_p, 0);
+        conv_launch(st, u->ctx->conv_big_tile, Ly, dZ, P, H, W, u->wd.as<uint16_t>() + Ly.wd_off, Ly.cout_p,
+                    Ly.kpad_t, nullptr, Ly.cin_p, Ly.cin_p, dX, nullptr, Ly.cin_p, 0);
 }
 
 }  // namespace
@@ -917,7 +970,7 @@ sc_status unet_adam(Unet* u, float lr) {
 
 sc_status unet_features(Unet* u, const sc_aov& in, uint32_t w, uint32_t h) {
     hipLaunchKernelGGL(k_features, dim3(blocks((size_t)u->W * u->H)), dim3(256), 0, u->ctx->stream, in.rgb, in.albedo,
-                       in.normal, in.depthn, in.trans, w, h, u->W, u->H, 16u, u->acts.as<uint16_t>() + u->t.in);
+                       in.normal, in.depthn, in.trans, w, h, u->W, u->H, u->acts.as<uint16_t>() + u->t.in);
     SC_HIP(hipGetLastError());
     return SC_OK;
 }

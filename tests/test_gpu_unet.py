@@ -39,10 +39,24 @@ def _inputs(rng, n, h, w):
     return x
 
 
-@pytest.mark.parametrize("widths,n,h,w", [((16, 32), 1, 16, 16), ((32, 48, 64, 96, 128), 2, 32, 48),
-                                          ((32, 48, 64, 96, 128), 1, 48, 32)])
-def test_forward_matches_oracle(ctx, widths, n, h, w):
+@pytest.fixture
+def tiles(ctx):
+    """Sets the 3x3 convolution's tile threshold (0: 16-row tiles for every
+    layer) and restores the default afterwards."""
     import paper_2107_11008_amd as sc
+
+    def set_(v):
+        ctx.set_option(sc._sc.SC_OPT_CONV_BIG_TILE, v)
+    yield set_
+    set_(2048)
+
+
+@pytest.mark.parametrize("widths,n,h,w,big", [((16, 32), 1, 16, 16, 2048), ((32, 48, 64, 96, 128), 2, 32, 48, 2048),
+                                              ((32, 48, 64, 96, 128), 1, 48, 32, 2048),
+                                              ((32, 48, 64, 96, 128), 2, 48, 80, 0)])
+def test_forward_matches_oracle(ctx, tiles, widths, n, h, w, big):
+    import paper_2107_11008_amd as sc
+    tiles(big)
     rng = np.random.default_rng(1)
     th = U.init_params(3, widths)
     th = th + rng.normal(scale=0.02, size=th.shape).astype(np.float32)   # non-zero biases
@@ -54,10 +68,11 @@ def test_forward_matches_oracle(ctx, widths, n, h, w):
     assert np.array_equal(net.get_params(), th)
 
 
-@pytest.mark.parametrize("widths,n,h,w,cos_all,rel_all,cos_layer",
-                         [((16, 32), 2, 16, 16, 0.999, 3e-2, 0.99),
-                          ((32, 48, 64, 96, 128), 1, 32, 32, 0.98, 0.25, 0.95)])
-def test_backward_matches_oracle(ctx, widths, n, h, w, cos_all, rel_all, cos_layer):
+@pytest.mark.parametrize("widths,n,h,w,cos_all,rel_all,cos_layer,big",
+                         [((16, 32), 2, 16, 16, 0.999, 3e-2, 0.99, 2048),
+                          ((16, 32), 2, 32, 48, 0.999, 3e-2, 0.99, 0),
+                          ((32, 48, 64, 96, 128), 1, 32, 32, 0.98, 0.25, 0.95, 2048)])
+def test_backward_matches_oracle(ctx, tiles, widths, n, h, w, cos_all, rel_all, cos_layer, big):
     """The two-level network exercises every kernel (3x3 and 1x1 forward,
     input and weight gradients, pooling, upsampling, concatenation, bias)
     at the tight bar.  Through five levels bfloat16 rounding decisions
@@ -67,6 +82,7 @@ def test_backward_matches_oracle(ctx, widths, n, h, w, cos_all, rel_all, cos_lay
     0.154 and per-layer cosines >= 0.967, so the deep network is held to
     cosine >= 0.98, relative L2 <= 0.25, per layer >= 0.95."""
     import paper_2107_11008_amd as sc
+    tiles(big)
     rng = np.random.default_rng(2)
     th = U.init_params(4, widths) + rng.normal(scale=0.02, size=U.n_params(widths)).astype(np.float32)
     net = sc.UNet(ctx, widths, th)
@@ -85,6 +101,29 @@ def test_backward_matches_oracle(ctx, widths, n, h, w, cos_all, rel_all, cos_lay
     for name in pg:
         assert _cos(pg[name][0], po[name][0]) >= cos_layer, name
         assert _cos(pg[name][1], po[name][1]) >= cos_layer, name
+
+
+def test_conv_tile_shapes_agree(ctx, tiles):
+    """16-row and 8-row tiles of the 3x3 convolution sum every output chunk
+    by chunk and tap by tap in the same order: predictions are equal bit for
+    bit (ragged tiles at every level of a 48 x 80 input), and the gradients
+    differ only by the order of the weight gradient's float atomics."""
+    import paper_2107_11008_amd as sc
+    widths = (32, 48, 64, 96, 128)
+    rng = np.random.default_rng(5)
+    th = U.init_params(4, widths) + rng.normal(scale=0.02, size=U.n_params(widths)).astype(np.float32)
+    net = sc.UNet(ctx, widths, th)
+    x = torch.from_numpy(_inputs(rng, 2, 48, 80)).cuda()
+    dp = torch.from_numpy((rng.normal(size=(2, 48, 80, 3)) / 7680).astype(np.float32)).cuda()
+    res = []
+    for big in (0, 1 << 32):
+        tiles(big)
+        p = net.forward(x).cpu().numpy()
+        res.append((p, net.backward(dp).cpu().numpy()))
+    assert np.array_equal(res[0][0].view(np.uint32), res[1][0].view(np.uint32))
+    assert _rel(res[0][1], res[1][1]) <= 1e-4
+    with pytest.raises(sc.ScError):
+        ctx.set_option(sc._sc.SC_OPT_CONV_BIG_TILE, -1)
 
 
 def test_train_step_matches_oracle(ctx):
