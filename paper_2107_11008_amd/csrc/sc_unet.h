@@ -38,6 +38,7 @@ struct Unet {
     UnetTensors t;
     uint64_t step = 0;
     bool cat_valid = false;   // the last forward pass kept what a backward pass reads
+    uint32_t cus = 256;       // compute units of the device (sizes the persistent convolution grid)
 };
 
 sc_status unet_create(Ctx* c, const uint32_t* widths, uint32_t levels, Unet* u);

@@ -24,6 +24,8 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
     // round to nearest even
@@ -122,130 +124,194 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
     }
 }
 
-// 3x3 convolution with LDS tiles.  A block computes a 4 RW x 16 tile of
-// output pixels x 16 NT output channels (blockIdx.y selects the channel
-// group); wave w computes tile rows RW w .. RW w + RW - 1, RW 16-pixel A
-// operands sharing each weight operand.  The input channels are taken 32 at a
-// time: the tile with its 1-pixel halo and the 16 NT x 9 x 32 weights of the
-// chunk are staged in LDS, then every tap reads its operands there.
-// Channels past cin_p in the last chunk are zero in both tiles.  With X2
-// given, the input is the concatenation [nearest 2x upsampling of X (c_split
-// channels at H/2 x W/2), X2 (cin_p - c_split channels)], read in place
-// (decoder inference).  Every output sums chunk by chunk and tap by tap, so
-// the tile shape does not change a result.  Pixel and element indices fit in
-// 32 bits (the host checks P * channels < 2^31); addresses are formed once
-// per row.
+// 3x3 convolution on the matrix cores.  A block owns 16 NT output channels
+// (blockIdx.y selects the group) and walks pixel tiles of 4 RW x 16 with a
+// stride of the grid; wave w computes tile rows RW w .. RW w + RW - 1.  The
+// input channels are taken 32 at a time: the tile with its 1-pixel halo and
+// the 16 NT x 9 x 32 weights of the chunk are staged in LDS, then every tap
+// reads its operands there.  While a chunk is multiplied, the input pixels of
+// the next (tile, chunk) are already being loaded into registers.  With one
+// chunk (MODE 0: cin_p <= 32) the weights are staged once per block.  The
+// operands are weights x pixels, so a lane receives 4 consecutive output
+// channels of one pixel and writes them with one 8-byte store.  Channels past
+// cin_p in the last chunk are zero in both tiles.  MODE 2: the input is the
+// concatenation [nearest 2x upsampling of X (c_split channels at H/2 x W/2),
+// X2 (cin_p - c_split channels)], read in place (decoder inference).  Every
+// output sums chunk by chunk and tap by tap, so neither the tile shape nor the
+// grid changes a result.  Element indices of one tensor fit in 32 bits (the
+// host checks P * channels < 2^31); H and W are even.
 constexpr int kTC = 16, kHC = kTC + 2;
 constexpr int kCC = 32;                 // input channels per chunk
 constexpr int kWP = 9 * kCC + 8;        // LDS pitch of a weight row (bf16), padded against bank conflicts
 constexpr int kConvTiles = 2;           // 16-channel output tiles per block
 
-template <int NT, int RW>
+template <int NT, int RW, int MODE>
 __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ X2,
-                                               uint32_t c_split, uint32_t H, uint32_t W, uint32_t cin_p,
+                                               uint32_t c_split, uint32_t B, uint32_t H, uint32_t W, uint32_t cin_p,
                                                const uint16_t* __restrict__ Wt, uint32_t kpad,
-                                               const float* __restrict__ bias, uint32_t cout_p, uint32_t cout_real,
-                                               uint16_t* __restrict__ Y, float* __restrict__ Yf, uint32_t y_stride,
-                                               uint32_t y_off, int relu) {
+                                               const float* __restrict__ bias, uint32_t cout_p,
+                                               uint16_t* __restrict__ Y, uint32_t y_stride, int relu) {
     constexpr int kTR = 4 * RW, kHR = kTR + 2;
-    __shared__ uint4 xs4[kHR * kHC * kCC / 8];
+    constexpr int kXS = kHR * kHC * 4;       // 16-byte pieces of a staged tile
+    constexpr int kXI = (kXS + 255) / 256;   // ... per thread
+    __shared__ uint4 xs4[kXS];
     __shared__ uint4 ws4[16 * NT * kWP / 8];
     const uint16_t* xs = reinterpret_cast<const uint16_t*>(xs4);
     const uint16_t* ws = reinterpret_cast<const uint16_t*>(ws4);
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, pl = lane & 15, g = lane >> 4;
+    const uint32_t piece = tid & 3;          // this thread's 8-channel piece in every staged pixel
     const uint32_t tiles_x = (W + kTC - 1) / kTC, tiles_y = (H + kTR - 1) / kTR;
-    uint32_t bid = blockIdx.x;
-    const uint32_t tx = bid % tiles_x;
-    bid /= tiles_x;
-    const uint32_t ty = bid % tiles_y;
-    const uint32_t b = bid / tiles_y;
+    const uint32_t n_tiles = tiles_x * tiles_y * B;
     const uint32_t cg = blockIdx.y;
-    const uint32_t x0 = tx * kTC, y0 = ty * kTR;
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t pl = lane & 15, g = lane >> 4;
-    const uint32_t nt_total = cout_p / 16;
-    const uint32_t nt_here = min((uint32_t)NT, nt_total - cg * NT);   // 16-channel tiles of this group
-    const uint32_t c_rest = cin_p - c_split;
-    const uint32_t Hh = H / 2, Wh = W / 2;
+    const uint32_t nt_here = min((uint32_t)NT, cout_p / 16 - cg * NT);   // 16-channel tiles of this group
+    const uint32_t n_chunks = (cin_p + kCC - 1) / kCC;
+    const uint32_t Hh = H / 2, Wh = W / 2, c_rest = cin_p - c_split;
+    // this thread's staged pixels: row and column in the haloed tile and the
+    // element offset from the tile's corner pixel (y0 - 1, x0 - 1) (MODE 2:
+    // from the upsampled corner and, for X2, from the corner)
+    uint32_t sy[kXI], sx[kXI];
+    int32_t so[kXI], so2[kXI];
+#pragma unroll
+    for (int k = 0; k < kXI; ++k) {
+        const uint32_t t = tid + 256 * k, pix = t >> 2;
+        const bool in = t < kXS;
+        sy[k] = in ? pix / kHC : 0x7fffffffu;   // beyond any image: never loaded
+        sx[k] = in ? pix % kHC : 0u;
+        if (MODE == 2) {
+            const int fy = (int)((sy[k] + 1) / 2) - 1, fx = (int)((sx[k] + 1) / 2) - 1;
+            so[k] = in ? (fy * (int)Wh + fx) * (int)c_split + (int)piece * 8 : 0;
+            so2[k] = in ? ((int)sy[k] * (int)W + (int)sx[k]) * (int)c_rest + (int)piece * 8 : 0;
+        } else {
+            so[k] = in ? ((int)sy[k] * (int)W + (int)sx[k]) * (int)cin_p + (int)piece * 8 : 0;
+            so2[k] = 0;
+        }
+    }
+    auto corner = [&](uint32_t tile, uint32_t& b, uint32_t& y0, uint32_t& x0) {
+        const uint32_t tx = tile % tiles_x, rest = tile / tiles_x;
+        x0 = tx * kTC;
+        y0 = (rest % tiles_y) * kTR;
+        b = rest / tiles_y;
+    };
+    auto fetch = [&](uint32_t tile, uint32_t c0, uint4 (&v)[kXI]) {
+        uint32_t b, y0, x0;
+        corner(tile, b, y0, x0);
+        const uint32_t cn = min((uint32_t)kCC, cin_p - c0);
+        const bool pok = piece * 8 < cn;
+        const int64_t corner_px = ((int64_t)(b * H + y0) - 1) * W + (int64_t)x0 - 1;
+        const uint16_t* src;
+        const uint16_t* src2 = nullptr;
+        bool up = false;
+        if (MODE == 2) {
+            up = c0 + piece * 8 < c_split;
+            src = X + ((int64_t)(b * Hh + y0 / 2) * Wh + x0 / 2) * c_split + c0;
+            src2 = X2 + corner_px * c_rest + ((int64_t)c0 - (int64_t)c_split);
+        } else {
+            src = X + corner_px * cin_p + c0;
+        }
+#pragma unroll
+        for (int k = 0; k < kXI; ++k) {
+            v[k] = make_uint4(0u, 0u, 0u, 0u);
+            const uint32_t yy = y0 - 1u + sy[k], xx = x0 - 1u + sx[k];   // -1 wraps to a large value
+            if (pok && yy < H && xx < W) {
+                if (MODE == 2 && !up)
+                    v[k] = *reinterpret_cast<const uint4*>(src2 + so2[k]);
+                else
+                    v[k] = *reinterpret_cast<const uint4*>(src + so[k]);
+            }
+        }
+    };
+    uint32_t tile = blockIdx.x, chunk = 0;
+    if (tile >= n_tiles) return;   // the whole block
+    uint4 pv[kXI];
+    fetch(tile, 0, pv);
     floatx4 acc[RW][NT];
 #pragma unroll
     for (int r = 0; r < RW; ++r)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[r][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (uint32_t c0 = 0; c0 < cin_p; c0 += kCC) {
-        const uint32_t cn = min((uint32_t)kCC, cin_p - c0);
-        __syncthreads();   // the previous chunk is no longer read
-        for (uint32_t t = threadIdx.x; t < kHR * kHC * 4; t += 256) {
-            const uint32_t piece = t & 3, pix = t >> 2;
-            const uint32_t py = pix / kHC, px = pix - py * kHC;
-            const uint32_t yy = y0 + py - 1u, xx = x0 + px - 1u;   // wraps to a large value at -1
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            const uint32_t c = c0 + piece * 8;
-            if (piece * 8 < cn && yy < H && xx < W) {
-                const uint32_t pix_full = (b * H + yy) * W + xx;
-                if (!X2)
-                    v = *reinterpret_cast<const uint4*>(X + (size_t)pix_full * cin_p + c);
-                else if (c < c_split)   // nearest 2x upsampling of the coarser tensor
-                    v = *reinterpret_cast<const uint4*>(X + (size_t)((b * Hh + yy / 2) * Wh + xx / 2) * c_split + c);
-                else
-                    v = *reinterpret_cast<const uint4*>(X2 + (size_t)pix_full * c_rest + (c - c_split));
+    bool w_staged = false;
+    while (true) {
+        const uint32_t c0 = chunk * kCC;
+        __syncthreads();   // the previous item's operands are no longer read
+#pragma unroll
+        for (int k = 0; k < kXI; ++k)
+            if (tid + 256 * k < (uint32_t)kXS) xs4[tid + 256 * k] = pv[k];
+        if (MODE != 0 || !w_staged) {
+            const uint32_t cn = min((uint32_t)kCC, cin_p - c0);
+            const uint16_t* wsrc = Wt + (size_t)(cg * 16 * NT) * kpad + c0;
+            for (uint32_t t = tid; t < 16 * nt_here * 9 * 4; t += 256) {
+                const uint32_t rest = t >> 2;
+                const uint32_t col = rest / 9, tap = rest - col * 9;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (piece * 8 < cn) v = *reinterpret_cast<const uint4*>(wsrc + col * kpad + tap * cin_p + piece * 8);
+                ws4[(col * kWP + tap * kCC) / 8 + piece] = v;
             }
-            xs4[t] = v;   // pixel pix, channels 8 piece .. 8 piece + 7 of the chunk
-        }
-        const uint16_t* wsrc = Wt + (size_t)(cg * 16 * NT) * kpad + c0;
-        for (uint32_t t = threadIdx.x; t < 16 * nt_here * 9 * 4; t += 256) {
-            const uint32_t piece = t & 3, rest = t >> 2;
-            const uint32_t col = rest / 9, tap = rest - col * 9;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (piece * 8 < cn) v = *reinterpret_cast<const uint4*>(wsrc + col * kpad + tap * cin_p + piece * 8);
-            ws4[(col * kWP + tap * kCC) / 8 + piece] = v;
+            w_staged = true;
         }
         __syncthreads();
+        uint32_t ntile = tile, nchunk = chunk + 1;
+        if (nchunk == n_chunks) {
+            nchunk = 0;
+            ntile += gridDim.x;
+        }
+        const bool more = ntile < n_tiles;
+        if (more) fetch(ntile, nchunk * kCC, pv);   // in flight while this item is multiplied
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;
-            Frag a[RW];
+            Frag px[RW];
 #pragma unroll
             for (int r = 0; r < RW; ++r)
-                a[r].u = *reinterpret_cast<const uint4*>(xs + (((RW * wv + r + dy) * kHC) + pl + dx) * kCC + 8 * g);
+                px[r].u = *reinterpret_cast<const uint4*>(xs + (((RW * wv + r + dy) * kHC) + pl + dx) * kCC + 8 * g);
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
                 if ((uint32_t)j < nt_here) {
-                    Frag bw;
-                    bw.u = *reinterpret_cast<const uint4*>(ws + (j * 16 + pl) * kWP + tap * kCC + 8 * g);
+                    Frag wt;
+                    wt.u = *reinterpret_cast<const uint4*>(ws + (j * 16 + pl) * kWP + tap * kCC + 8 * g);
 #pragma unroll
                     for (int r = 0; r < RW; ++r)
-                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r].v, bw.v, acc[r][j], 0, 0, 0);
+                        acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt.v, px[r].v, acc[r][j], 0, 0, 0);
                 }
             }
         }
-    }
-    float bv[NT];
-    bool cok[NT];
+        if (chunk + 1 == n_chunks) {   // the tile is complete: channels 4 g .. 4 g + 3 of pixel pl
+            uint32_t b, y0, x0;
+            corner(tile, b, y0, x0);
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const uint32_t co = (cg * NT + j) * 16 + pl;
-        cok[j] = (uint32_t)j < nt_here && co < cout_real;
-        bv[j] = (cok[j] && bias) ? bias[co] : 0.0f;
-    }
-    const uint32_t xb = x0 + 4 * g;
+            for (int r = 0; r < RW; ++r) {
+                const uint32_t yy = y0 + RW * wv + r;
+                if (yy < H && x0 + pl < W) {
+                    uint16_t* dst = Y + (size_t)((b * H + yy) * W + x0 + pl) * y_stride + cg * NT * 16 + 4 * g;
 #pragma unroll
-    for (int r = 0; r < RW; ++r) {
-        const uint32_t yy = y0 + RW * wv + r;
-        if (yy >= H) continue;
-        const size_t row = (size_t)((b * H + yy) * W + xb) * y_stride + y_off + (cg * NT) * 16 + pl;
+                    for (int j = 0; j < NT; ++j) {
+                        if ((uint32_t)j >= nt_here) continue;
+                        const float* bj = bias + (cg * NT + j) * 16 + 4 * g;
+                        float2v lo, hi;
+                        lo[0] = acc[r][j][0] + (bias ? bj[0] : 0.0f);
+                        lo[1] = acc[r][j][1] + (bias ? bj[1] : 0.0f);
+                        hi[0] = acc[r][j][2] + (bias ? bj[2] : 0.0f);
+                        hi[1] = acc[r][j][3] + (bias ? bj[3] : 0.0f);
+                        if (relu) {
+                            lo[0] = fmaxf(lo[0], 0.0f);
+                            lo[1] = fmaxf(lo[1], 0.0f);
+                            hi[0] = fmaxf(hi[0], 0.0f);
+                            hi[1] = fmaxf(hi[1], 0.0f);
+                        }
+                        const bf16x2 l2 = __builtin_convertvector(lo, bf16x2);   // round to nearest even
+                        const bf16x2 h2 = __builtin_convertvector(hi, bf16x2);
+                        uint2 o;
+                        __builtin_memcpy(&o.x, &l2, 4);
+                        __builtin_memcpy(&o.y, &h2, 4);
+                        *reinterpret_cast<uint2*>(dst + 16 * j) = o;
+                    }
+                }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (xb + i >= W) continue;
-            const size_t o = row + (size_t)i * y_stride;
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                if (!cok[j]) continue;
-                float v = acc[r][j][i] + bv[j];
-                if (relu) v = fmaxf(v, 0.0f);
-                if (Yf) Yf[o + j * 16] = v;
-                else Y[o + j * 16] = to_bf16(v);
+                for (int j = 0; j < NT; ++j) acc[r][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
             }
         }
+        if (!more) break;
+        tile = ntile;
+        chunk = nchunk;
     }
 }
 
@@ -615,6 +681,9 @@ uint32_t round_up(uint32_t v, uint32_t m) { return (v + m - 1) / m * m; }
 sc_status unet_create(Ctx* c, const uint32_t* widths, uint32_t levels, Unet* u) {
     if (levels < 2 || levels > 6) return set_error(SC_EINVAL, "levels must be 2..6");
     u->ctx = c;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+        u->cus = (uint32_t)cus;
     u->widths.assign(widths, widths + levels);
     for (uint32_t i = 0; i < levels; ++i)
         if (widths[i] == 0 || widths[i] % 16 != 0 || widths[i] > 256)
@@ -742,30 +811,63 @@ sc_status ensure_acts(Unet* u, uint32_t B, uint32_t H, uint32_t W) {
     return SC_OK;
 }
 
-void conv_launch(hipStream_t st, uint64_t big_tile, const UnetLayer& L, const uint16_t* X, uint32_t P, uint32_t H,
-                 uint32_t W,
-                 const uint16_t* Wt, uint32_t cin_p, uint32_t kpad, const float* bias, uint32_t cout_p,
+// blocks of a k_conv3 variant that one CU keeps resident (registers and LDS)
+template <int RW, int MODE>
+uint32_t conv3_per_cu() {
+    static uint32_t n = 0;
+    if (!n) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_conv3<kConvTiles, RW, MODE>, 256, 0) != hipSuccess ||
+            v < 1)
+            v = 1;
+        n = (uint32_t)v;
+    }
+    return n;
+}
+
+void conv_launch(hipStream_t st, uint32_t cus, uint64_t big_tile, const UnetLayer& L, const uint16_t* X, uint32_t P,
+                 uint32_t H, uint32_t W, const uint16_t* Wt, uint32_t cin_p, uint32_t kpad, const float* bias, uint32_t cout_p,
                  uint32_t cout_real, uint16_t* Y, float* Yf, uint32_t y_stride, int relu,
                  const uint16_t* X2 = nullptr, uint32_t c_split = 0) {
     const uint32_t n_tiles = (P + 15) / 16;
     const uint32_t groups = (cout_p / 16 + 3) / 4;
     const size_t waves = (size_t)n_tiles * groups;
     const uint32_t grid = (uint32_t)((waves + 3) / 4);
-    if (L.ks == 3) {
-        // 16-row tiles (4 rows per wave: each weight operand feeds 4 MFMAs,
-        // 40 KB of LDS, 4 blocks per CU) where a layer has at least big_tile
-        // of them (default 2048: several per CU), 8-row tiles otherwise
+    if (L.ks == 3 && !Yf && cout_real == cout_p) {
+        // 16-row tiles (4 rows per wave: each weight operand feeds 4 MFMAs)
+        // where a layer has at least big_tile of them, 8-row tiles otherwise;
+        // the grid holds what the CUs keep resident, each block walking
+        // several tiles
         const uint32_t B = P / (H * W);
         const uint32_t gy = (cout_p / 16 + kConvTiles - 1) / kConvTiles;
         const uint32_t tx = (W + kTC - 1) / kTC;
-        const uint32_t t16 = tx * ((H + 15) / 16) * B;
-        if ((uint64_t)t16 * gy >= big_tile)
-            hipLaunchKernelGGL((k_conv3<kConvTiles, 4>), dim3(t16, gy), dim3(256), 0, st, X, X2, c_split, H, W, cin_p,
-                               Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
-        else
-            hipLaunchKernelGGL((k_conv3<kConvTiles, 2>), dim3(tx * ((H + 7) / 8) * B, gy), dim3(256), 0, st, X, X2,
-                               c_split, H, W, cin_p, Wt, kpad, bias, cout_p, cout_real, Y, Yf, y_stride, 0u, relu);
-    } else
+        const uint32_t t16 = tx * ((H + 15) / 16) * B, t8 = tx * ((H + 7) / 8) * B;
+        const bool big = (uint64_t)t16 * gy >= big_tile;
+        const int mode = X2 ? 2 : (cin_p <= (uint32_t)kCC ? 0 : 1);
+        const uint32_t tiles = big ? t16 : t8;
+        const uint32_t per_cu = big ? (mode == 0 ? conv3_per_cu<4, 0>() : mode == 1 ? conv3_per_cu<4, 1>()
+                                                                                 : conv3_per_cu<4, 2>())
+                                    : (mode == 0 ? conv3_per_cu<2, 0>() : mode == 1 ? conv3_per_cu<2, 1>()
+                                                                                 : conv3_per_cu<2, 2>());
+        const uint32_t gx = std::max(1u, std::min(tiles, (cus * per_cu + gy - 1) / gy));
+        const dim3 grid(gx, gy);
+#define SC_CONV3(RW, MODE)                                                                                          \
+    hipLaunchKernelGGL((k_conv3<kConvTiles, RW, MODE>), grid, dim3(256), 0, st, X, X2, c_split, B, H, W, cin_p, Wt, \
+                       kpad, bias, cout_p, Y, y_stride, relu)
+        if (big) {
+            if (mode == 0) SC_CONV3(4, 0);
+            else if (mode == 1) SC_CONV3(4, 1);
+            else SC_CONV3(4, 2);
+        } else {
+            if (mode == 0) SC_CONV3(2, 0);
+            else if (mode == 1) SC_CONV3(2, 1);
+            else SC_CONV3(2, 2);
+        }
+#undef SC_CONV3
+    } else if (L.ks == 3)   // float output or partial channel tiles: the plain implicit GEMM
+        hipLaunchKernelGGL(k_conv<3>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
+                           cout_real, Y, Yf, y_stride, 0u, relu);
+    else
         hipLaunchKernelGGL(k_conv<1>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
                            cout_real, Y, Yf, y_stride, 0u, relu);
 }
@@ -794,8 +896,8 @@ sc_status unet_forward_packed(Unet* u, bool keep_cat) {
         for (int part = 0; part < 2; ++part) {
             const UnetLayer& Ly = u->layers[li++];
             uint16_t* out = A + (part == 0 ? T.enc_a[i] : T.enc_b[i]);
-            conv_launch(st, big, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p, Ly.cout,
-                        out, nullptr, Ly.cout, 1);
+            conv_launch(st, u->cus, big, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p,
+                        Ly.cout, out, nullptr, Ly.cout, 1);
             h = out;
             hc = Ly.cout;
         }
@@ -815,16 +917,16 @@ sc_status unet_forward_packed(Unet* u, bool keep_cat) {
         for (int part = 0; part < 2; ++part) {
             const UnetLayer& Ly = u->layers[li++];
             uint16_t* out = A + (part == 0 ? T.dec_a[i] : T.dec_b[i]);
-            conv_launch(st, big, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p, Ly.cout,
-                        out, nullptr, Ly.cout, 1, part == 0 ? skip : nullptr, part == 0 ? split : 0u);
+            conv_launch(st, u->cus, big, Ly, h, P, H, W, wf + Ly.wf_off, Ly.cin_p, Ly.kpad, th + Ly.b_off, Ly.cout_p,
+                        Ly.cout, out, nullptr, Ly.cout, 1, part == 0 ? skip : nullptr, part == 0 ? split : 0u);
             h = out;
             hc = Ly.cout;
         }
     }
     const UnetLayer& Lo = u->layers[li];
     const uint32_t P0 = u->B * u->H * u->W;
-    conv_launch(st, big, Lo, h, P0, u->H, u->W, wf + Lo.wf_off, Lo.cin_p, Lo.kpad, th + Lo.b_off, Lo.cout_p, Lo.cout,
-                nullptr, u->pred.as<float>(), 3, 0);
+    conv_launch(st, u->cus, big, Lo, h, P0, u->H, u->W, wf + Lo.wf_off, Lo.cin_p, Lo.kpad, th + Lo.b_off, Lo.cout_p,
+                Lo.cout, nullptr, u->pred.as<float>(), 3, 0);
     u->cat_valid = keep_cat;
     SC_HIP(hipGetLastError());
     return SC_OK;
@@ -857,7 +959,7 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
     hipLaunchKernelGGL(k_bias_grad, dim3(std::min<uint32_t>(1024, (P + 3) / 4)), dim3(256), 0, st, dZ, P, Ly.cout_p,
                        Ly.cout, g + Ly.b_off);
     if (dX)
-        conv_launch(st, u->ctx->conv_big_tile, Ly, dZ, P, H, W, u->wd.as<uint16_t>() + Ly.wd_off, Ly.cout_p,
+        conv_launch(st, u->cus, u->ctx->conv_big_tile, Ly, dZ, P, H, W, u->wd.as<uint16_t>() + Ly.wd_off, Ly.cout_p,
                     Ly.kpad_t, nullptr, Ly.cin_p, Ly.cin_p, dX, nullptr, Ly.cin_p, 0);
 }
 
