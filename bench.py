@@ -175,6 +175,63 @@ def batch_compare(ctx):
     return res
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # dense bf16 matrix-core peak of one MI355X
+
+
+def unet_flops(widths, h, w, in_ch=9, out_ch=3):
+    """2 x multiply-adds of the U-Net's convolutions on an h x w canvas (real
+    channel counts, not the padded ones the kernels multiply)."""
+    f, cin = 0, in_ch
+    for i, c in enumerate(widths):
+        p = (h >> i) * (w >> i)
+        f += 2 * p * 9 * (cin * c + c * c)
+        cin = c
+    for i in range(len(widths) - 2, -1, -1):
+        p = (h >> i) * (w >> i)
+        c = widths[i]
+        f += 2 * p * 9 * ((cin + c) * c + c * c)
+        cin = c
+    return f + 2 * h * w * cin * out_ch
+
+
+def unet_1080p(ctx, reps=20):
+    """U-Net inference alone on a 1920x1080 frame of synthetic buffers (the
+    committed trained weights): ms per call from HIP events around `reps`
+    calls, and the achieved fraction of the bf16 matrix-core peak."""
+    import torch
+
+    import paper_2107_11008_amd as sc
+    from paper_2107_11008_amd import denoiser as D
+    params, meta = D.load_weights()
+    if params is None:
+        return None
+    widths = tuple(meta["widths"])
+    net = sc.UNet(ctx, widths, params)
+    h, w = 1080, 1920
+    g = torch.Generator().manual_seed(1)
+    aov = {"rgb": torch.rand((h, w, 3), generator=g), "albedo": torch.rand((h, w), generator=g),
+           "normal": torch.rand((h, w, 3), generator=g) * 2 - 1, "depthn": torch.rand((h, w), generator=g),
+           "trans": (torch.rand((h, w), generator=g) < 0.3).to(torch.uint8)}
+    aov = {k: v.cuda() for k, v in aov.items()}   # the context runs on torch's current stream: events see it
+    out = net.denoise(aov)
+    for _ in range(3):
+        net.denoise(aov, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        net.denoise(aov, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    hc = (h + 15) // 16 * 16            # the padded canvas the network runs on
+    fl = unet_flops(widths, hc, w)
+    tf = fl / (ms * 1e-3) / 1e12
+    return {"widths": list(widths), "canvas": [w, hc], "ms": round(ms, 4), "gflop": round(fl / 1e9, 1),
+            "achieved_tflops": round(tf, 1), "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+            "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4)}
+
+
 def glass_variants(ctx, steps=5, warmup=2):
     """The same medium-scene step on the richer glass: every object tinted
     and every second one rough ("rich"), and the clear scene under a light
@@ -282,6 +339,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-glass-variants", action="store_true")
     ap.add_argument("--no-pmap", action="store_true")
+    ap.add_argument("--no-unet", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -417,6 +475,8 @@ def main():
         line["glass_variants"] = glass_variants(ctx)
     if not args.no_pmap:
         line["general_photon_map"] = general_photon_map(ctx)
+    if not args.no_unet:
+        line["unet_1080p"] = unet_1080p(ctx)
     if not args.no_denoise:
         line["denoise_1080p"] = denoise_fps(ctx)
     if not args.no_batch:
