@@ -215,7 +215,7 @@ typedef struct {
 #define SC_OPT_STAGED_DEPTH 4 /* bounces traced as one launch per stage before the remaining paths
                                * are each finished by one lane (default 5; 0 = every bounce staged);
                                * any value gives the same output bit for bit */
-#define SC_OPT_CONV_BIG_TILE 5 /* U-Net 3x3 convolutions use 16-row pixel tiles when a layer has at
+#define SC_OPT_CONV_BIG_TILE 5 /* U-Net 3x3 convolutions use 12-row pixel tiles when a layer has at
                                 * least this many of them (default 2048; 0 = always), 8-row tiles
                                 * otherwise; any value gives the same output bit for bit */
 

@@ -41,7 +41,7 @@ def _inputs(rng, n, h, w):
 
 @pytest.fixture
 def tiles(ctx):
-    """Sets the 3x3 convolution's tile threshold (0: 16-row tiles for every
+    """Sets the 3x3 convolution's tile threshold (0: 12-row tiles for every
     layer) and restores the default afterwards."""
     import paper_2107_11008_amd as sc
 
@@ -104,7 +104,7 @@ def test_backward_matches_oracle(ctx, tiles, widths, n, h, w, cos_all, rel_all, 
 
 
 def test_conv_tile_shapes_agree(ctx, tiles):
-    """16-row and 8-row tiles of the 3x3 convolution sum every output chunk
+    """12-row and 8-row tiles of the 3x3 convolution sum every output chunk
     by chunk and tap by tap in the same order: predictions are equal bit for
     bit (ragged tiles at every level of a 48 x 80 input), and the gradients
     differ only by the order of the weight gradient's float atomics."""
