@@ -322,6 +322,61 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
     }
 }
 
+// 1x1 convolution to float outputs (the network's last layer, 16 padded
+// output channels): each wave keeps the weights of up to kOutChunks k-chunks
+// of 32 as MFMA operands and walks 16-pixel tiles with a stride of the grid.
+// The operands are weights x pixels, so lane (pixel l%16, group l/16)
+// receives output channels 4 (l/16) .. 4 (l/16) + 3 of its pixel.  The sums
+// run over the k-chunks in order, as in k_conv.
+constexpr uint32_t kOutChunks = 4;
+__global__ __launch_bounds__(256) void k_conv1_out(const uint16_t* __restrict__ X, uint32_t P, uint32_t cin_p,
+                                                   const uint16_t* __restrict__ Wt, uint32_t kpad,
+                                                   const float* __restrict__ bias, uint32_t cout_real,
+                                                   float* __restrict__ Yf, uint32_t y_stride, int relu) {
+    const uint32_t lane = threadIdx.x & 63, pl = lane & 15, g = lane >> 4;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t nk = kpad / 32;
+    Frag wt[kOutChunks];
+#pragma unroll
+    for (uint32_t c = 0; c < kOutChunks; ++c) {
+        wt[c].u = make_uint4(0u, 0u, 0u, 0u);
+        if (c < nk && 32 * c + 8 * g < cin_p)
+            wt[c].u = *reinterpret_cast<const uint4*>(Wt + pl * kpad + 32 * c + 8 * g);
+    }
+    float bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t co = 4 * g + i;
+        bv[i] = (co < cout_real && bias) ? bias[co] : 0.0f;
+    }
+    const uint32_t n_tiles = (P + 15) / 16;
+    for (uint32_t t = wave; t < n_tiles; t += n_waves) {
+        const uint32_t p = t * 16 + pl;
+        floatx4 acc = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (uint32_t c = 0; c < kOutChunks; ++c) {
+            if (c < nk) {
+                Frag px;
+                px.u = make_uint4(0u, 0u, 0u, 0u);
+                const uint32_t k = 32 * c + 8 * g;
+                if (p < P && k < cin_p) px.u = *reinterpret_cast<const uint4*>(X + (size_t)p * cin_p + k);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wt[c].v, px.v, acc, 0, 0, 0);
+            }
+        }
+        if (p < P) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t co = 4 * g + i;
+                if (co >= cout_real) continue;
+                float v = acc[i] + bv[i];
+                if (relu) v = fmaxf(v, 0.0f);
+                Yf[(size_t)p * y_stride + co] = v;
+            }
+        }
+    }
+}
+
 // Weight gradient: dW[co][k] = sum_p dZ[p][co] * X[shift_tap(p)][ci] with
 // k = tap * cin_p + ci.  One wave: 16 output channels x 64 k over a chunk
 // of pixels (32 per MFMA step), added into dW with float atomics.
@@ -878,6 +933,9 @@ void conv_launch(hipStream_t st, uint32_t cus, uint64_t big_tile, const UnetLaye
     } else if (L.ks == 3)   // float output or partial channel tiles: the plain implicit GEMM
         hipLaunchKernelGGL(k_conv<3>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
                            cout_real, Y, Yf, y_stride, 0u, relu);
+    else if (Yf && cout_p == 16 && kpad <= 32 * kOutChunks)   // the output layer
+        hipLaunchKernelGGL(k_conv1_out, dim3(std::max(1u, std::min((n_tiles + 3) / 4, cus * 8))), dim3(256), 0, st, X,
+                           P, cin_p, Wt, kpad, bias, cout_real, Yf, y_stride, relu);
     else
         hipLaunchKernelGGL(k_conv<1>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
                            cout_real, Y, Yf, y_stride, 0u, relu);
