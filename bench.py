@@ -336,6 +336,8 @@ def main():
     ap.add_argument("--staged-depth", type=int, default=None,
                     help="bounces run as one launch per stage before per-lane path finishing "
                          "(library default if omitted; 0 = all bounces staged)")
+    ap.add_argument("--photon-staged-depth", type=int, default=None,
+                    help="the same for photon paths (library default if omitted)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-glass-variants", action="store_true")
     ap.add_argument("--no-pmap", action="store_true")
@@ -358,6 +360,8 @@ def main():
     ctx = sc.Context(0)
     if args.staged_depth is not None:
         ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, args.staged_depth)
+    if args.photon_staged_depth is not None:
+        ctx.set_option(sc._sc.SC_OPT_PHOTON_STAGED_DEPTH, args.photon_staged_depth)
     stream = torch.cuda.current_stream()
 
     if args.calib_copy_mib:

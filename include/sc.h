@@ -212,12 +212,14 @@ typedef struct {
 #define SC_OPT_COUNT_VISITS 1 /* 0/1: closest-hit traversal counts node and triangle visits */
 #define SC_OPT_PROFILE 2      /* 0/1: time every closest-hit launch with HIP events */
 #define SC_OPT_QUEUE_CAP 3    /* paths per wavefront chunk (default 1<<23) */
-#define SC_OPT_STAGED_DEPTH 4 /* bounces traced as one launch per stage before the remaining paths
-                               * are each finished by one lane (default 5; 0 = every bounce staged);
-                               * any value gives the same output bit for bit */
+#define SC_OPT_STAGED_DEPTH 4 /* camera-path bounces traced as one launch per stage before the
+                               * remaining paths are each finished by one lane (default 4; 0 =
+                               * every bounce staged); any value gives the same output bit for bit */
 #define SC_OPT_CONV_BIG_TILE 5 /* U-Net 3x3 convolutions use 12-row pixel tiles when a layer has at
                                 * least this many of them (default 2048; 0 = always), 8-row tiles
                                 * otherwise; any value gives the same output bit for bit */
+#define SC_OPT_PHOTON_STAGED_DEPTH 6 /* the same switch for photon paths (default 1: after the
+                                      * first bounce every photon is finished by one lane) */
 
 uint32_t sc_abi_version(void);
 const char* sc_last_error(void);

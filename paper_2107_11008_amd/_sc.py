@@ -43,6 +43,7 @@ SC_OPT_PROFILE = 2
 SC_OPT_QUEUE_CAP = 3
 SC_OPT_STAGED_DEPTH = 4
 SC_OPT_CONV_BIG_TILE = 5
+SC_OPT_PHOTON_STAGED_DEPTH = 6
 
 
 ABI_VERSION = 3   # must match SC_ABI_VERSION in include/sc.h

@@ -1086,7 +1086,8 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
                                c->counters.as<DevCounters>());
             uint32_t* cur = q.cur;
             uint32_t* nxt = q.next;
-            const uint32_t staged = c->staged_depth && c->staged_depth < max_depth ? c->staged_depth : max_depth;
+            const uint32_t psd = c->photon_staged_depth;
+            const uint32_t staged = psd && psd < max_depth ? psd : max_depth;
             for (uint32_t depth = 1; depth <= staged; ++depth) {
                 uint32_t* fc = q.counts + (size_t)(depth - 1) * QC_FRAME;
                 launch_closest(c, S, R, H, cur, fc + QC_CUR, 0u, n);

@@ -10,7 +10,8 @@ import scenegen as sg
 
 pytestmark = pytest.mark.gpu
 
-DEPTHS = (0, 1, 2, 3, 5)
+# (camera, photon) switch depths; the first is the reference
+DEPTHS = ((0, 0), (1, 1), (2, 5), (3, 2), (5, 1), (1, 3))
 
 
 @pytest.fixture(scope="module")
@@ -21,7 +22,8 @@ def ctx():
 
 def _run(ctx, cfg, staged, spp):
     import paper_2107_11008_amd as sc
-    ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, staged)
+    ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, staged[0])
+    ctx.set_option(sc._sc.SC_OPT_PHOTON_STAGED_DEPTH, staged[1])
     try:
         bvh = ctx.build_bvh(cfg["scene"])
         md, wl = cfg["max_depth"], cfg["wavelengths"]
@@ -32,7 +34,8 @@ def _run(ctx, cfg, staged, spp):
         return ({k: v.cpu().numpy().copy() for k, v in img.items()}, ph["map"].cpu().numpy().copy(),
                 ph["count"].cpu().numpy().copy(), ph["stats"])
     finally:
-        ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, 5)
+        ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, 4)      # the library's defaults
+        ctx.set_option(sc._sc.SC_OPT_PHOTON_STAGED_DEPTH, 1)
 
 
 @pytest.mark.parametrize("which", ["c1", "c2s", "glass"])
@@ -44,7 +47,7 @@ def test_switch_depth_does_not_change_outputs(ctx, which):
     else:
         cfg, spp = sg.config2(tri_scale=0.05, w=48, h=40), 3
         cfg["n_photons"] = 1 << 17
-    base = _run(ctx, cfg, 0, spp)
+    base = _run(ctx, cfg, DEPTHS[0], spp)
     assert np.isfinite(base[0]["rgb"]).all() and base[0]["rgb"].max() > 0
     for staged in DEPTHS[1:]:
         other = _run(ctx, cfg, staged, spp)
@@ -62,5 +65,6 @@ def test_switch_depth_does_not_change_outputs(ctx, which):
 
 def test_bad_staged_depth_rejected(ctx):
     import paper_2107_11008_amd as sc
-    with pytest.raises(sc.ScError):
-        ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, -1)
+    for opt in (sc._sc.SC_OPT_STAGED_DEPTH, sc._sc.SC_OPT_PHOTON_STAGED_DEPTH):
+        with pytest.raises(sc.ScError):
+            ctx.set_option(opt, -1)
