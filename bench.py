@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s; 1080p frames/s at relMSE≤0.01 vs 1024spp, denoised vs plain"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_closest_c2_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traversal_c2_traffic.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_2107_11008_amd", "csrc", "trace.hip")
 
 
@@ -39,14 +39,14 @@ def _src_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic_per_launch():
-    """HBM bytes per closest-hit launch from the committed rocprofv3 counter
+def _traffic_per_launch(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when absent or taken on different kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     txt = open(TRAFFIC_FILE).read()
     m = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
-    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch " + re.escape(kernel) + r":\s*([0-9.eE+]+)", txt)
     if not m or not b or m.group(1) != _src_hash():
         return None
     return float(b.group(1))
@@ -392,7 +392,7 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # visit counts of the traversal kernel (same kernel, counting variant), untimed
+    # visit counts of the traversal kernels (same kernels, counting variants), untimed
     ctx.reset_counters()
     ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 1)
     bvh = step()
@@ -401,6 +401,9 @@ def main():
     # visits are counted by the staged closest-hit kernel, over its own rays
     nodes_per_ray = cnt["node_visits"] / cnt["closest_rays_timed"]
     tris_per_ray = cnt["tri_tests"] / cnt["closest_rays_timed"]
+    # and by the photon path finishing kernel, over its own segments
+    fin_nodes_per_ray = cnt["finish_node_visits"] / max(cnt["finish_rays"], 1)
+    fin_tris_per_ray = cnt["finish_tri_tests"] / max(cnt["finish_rays"], 1)
     rays_per_step = cnt["rays_closest"] + cnt["rays_shadow"]
     info = bvh.info()
     del bvh
@@ -425,7 +428,40 @@ def main():
     avg_ms = c["closest_ms"] / max(launches, 1)
     alg_bytes_per_launch = bytes_per_ray * c["closest_rays_timed"] / max(launches, 1)
     achieved = alg_bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = _traffic_per_launch()
+    roof_closest = {"bound": "hbm", "kernel": "k_closest (staged closest-hit traversal)",
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic_per_launch("k_closest<false>"),
+                    "avg_launch_ms": round(avg_ms, 5), "launches": launches,
+                    "alg_bytes_per_launch": round(alg_bytes_per_launch),
+                    "bytes_per_ray": round(bytes_per_ray, 1), "nodes_per_ray": round(nodes_per_ray, 3),
+                    "tris_per_ray": round(tris_per_ray, 3),
+                    "kernel_Mrays_s": round(c["closest_rays_timed"] / (c["closest_ms"] * 1e-3) / 1e6, 1),
+                    "ms_per_step": round(c["closest_ms"] / args.steps, 4)}
+    # photon path finishing: per path its state (48 B) and queue entry (4 B)
+    # are read once; per closest-hit segment the nodes and triangles fetched
+    f_launches = c["finish_launches"]
+    roof_finish = None
+    if f_launches:
+        f_ms = c["finish_ms"] / f_launches
+        f_bytes = (c["finish_paths"] * 52 + c["finish_rays"] * (fin_nodes_per_ray * 256 + fin_tris_per_ray * 48)) \
+            / f_launches
+        f_ach = f_bytes / (f_ms * 1e-3) / 1e9
+        roof_finish = {"bound": "hbm", "kernel": "k_finish_photons (per-lane photon path finishing)",
+                       "achieved": round(f_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(f_ach / HBM_PEAK_GBS, 4),
+                       "traffic": _traffic_per_launch("k_finish_photons<false>"),
+                       "avg_launch_ms": round(f_ms, 5), "launches": f_launches, "alg_bytes_per_launch": round(f_bytes),
+                       "paths_per_launch": round(c["finish_paths"] / f_launches),
+                       "rays_per_launch": round(c["finish_rays"] / f_launches),
+                       "nodes_per_ray": round(fin_nodes_per_ray, 3), "tris_per_ray": round(fin_tris_per_ray, 3),
+                       "kernel_Mrays_s": round(c["finish_rays"] / (c["finish_ms"] * 1e-3) / 1e6, 1),
+                       "ms_per_step": round(c["finish_ms"] / args.steps, 4)}
+    # the roofline object is the kernel with the most time per step; the
+    # other traversal kernel is reported beside it
+    if roof_finish and roof_finish["ms_per_step"] > roof_closest["ms_per_step"]:
+        roofline, roofline_other = roof_finish, roof_closest
+    else:
+        roofline, roofline_other = roof_closest, roof_finish
 
     # breakdown of one step (separately, untimed for the headline)
     torch.cuda.synchronize()
@@ -465,15 +501,8 @@ def main():
                          "render": round((tb3 - tb2) * 1e3, 3)},
         "bvh": {"nodes": info["n_nodes"], "depth": info["depth"], "node_bytes": info["node_bytes"],
                 "tri_bytes": info["tri_bytes"]},
-        "roofline": {"bound": "hbm", "kernel": "k_closest (closest-hit traversal)",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "avg_launch_ms": round(avg_ms, 5), "launches": launches,
-                     "alg_bytes_per_launch": round(alg_bytes_per_launch),
-                     "bytes_per_ray": round(bytes_per_ray, 1), "nodes_per_ray": round(nodes_per_ray, 3),
-                     "tris_per_ray": round(tris_per_ray, 3),
-                     "kernel_Mrays_s": round(c["closest_rays_timed"] / (c["closest_ms"] * 1e-3) / 1e6, 1)},
+        "roofline": roofline,
+        "roofline_other_traversal_kernel": roofline_other,
     }
     if not args.no_glass_variants:
         line["glass_variants"] = glass_variants(ctx)

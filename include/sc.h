@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SC_ABI_VERSION 3u
+#define SC_ABI_VERSION 4u
 
 typedef int32_t sc_status;
 #define SC_OK 0
@@ -207,6 +207,12 @@ typedef struct {
     double closest_ms;        /* their summed duration from HIP events (profiling on) */
     uint64_t closest_rays_timed; /* closest-hit rays traced by the staged kernel (the rest of
                                   * rays_closest by the per-lane path finishing kernels) */
+    uint64_t finish_launches; /* photon path finishing kernel launches timed (profiling on) */
+    double finish_ms;         /* their summed duration from HIP events (profiling on) */
+    uint64_t finish_paths;    /* photon paths the finishing kernel took over */
+    uint64_t finish_rays;     /* closest-hit rays it traced for them */
+    uint64_t finish_node_visits; /* wide nodes it fetched (visit counting on) */
+    uint64_t finish_tri_tests;   /* triangles it tested (visit counting on) */
 } sc_counters;
 
 #define SC_OPT_COUNT_VISITS 1 /* 0/1: closest-hit traversal counts node and triangle visits */

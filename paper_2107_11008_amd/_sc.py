@@ -46,7 +46,7 @@ SC_OPT_CONV_BIG_TILE = 5
 SC_OPT_PHOTON_STAGED_DEPTH = 6
 
 
-ABI_VERSION = 3   # must match SC_ABI_VERSION in include/sc.h
+ABI_VERSION = 4   # must match SC_ABI_VERSION in include/sc.h
 
 
 class ScError(RuntimeError):
@@ -120,7 +120,9 @@ class PmapInfo(C.Structure):
 class Counters(C.Structure):
     _fields_ = [("rays_closest", C.c_uint64), ("rays_shadow", C.c_uint64), ("node_visits", C.c_uint64),
                 ("tri_tests", C.c_uint64), ("closest_launches", C.c_uint64), ("closest_ms", C.c_double),
-                ("closest_rays_timed", C.c_uint64)]
+                ("closest_rays_timed", C.c_uint64), ("finish_launches", C.c_uint64), ("finish_ms", C.c_double),
+                ("finish_paths", C.c_uint64), ("finish_rays", C.c_uint64), ("finish_node_visits", C.c_uint64),
+                ("finish_tri_tests", C.c_uint64)]
 
 
 NODE_DTYPE = np.dtype([("lox", "<f4", 8), ("hix", "<f4", 8), ("loy", "<f4", 8), ("hiy", "<f4", 8),

@@ -109,6 +109,9 @@ struct Ctx {
     std::vector<hipEvent_t> event_pool;                       // read, free for reuse
     double closest_ms = 0.0;
     uint64_t closest_launches = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> fin_events;   // photon finishing launches, not yet read
+    double finish_ms = 0.0;
+    uint64_t finish_launches = 0;
 };
 
 struct Bvh {

@@ -136,6 +136,10 @@ struct DevCounters {
     unsigned long long rays_staged;   // closest-hit rays of the k_closest launches
     unsigned long long node_visits;
     unsigned long long tri_tests;
+    unsigned long long fin_paths;    // photon paths taken over by k_finish_photons
+    unsigned long long fin_rays;     // closest-hit rays it traced
+    unsigned long long fin_nodes;    // wide nodes it fetched (visit counting on)
+    unsigned long long fin_tris;     // triangles it tested (visit counting on)
     unsigned long long ph_count[9];
     double ph_flux[9];
 };

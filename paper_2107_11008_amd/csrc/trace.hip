@@ -631,6 +631,7 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo 
     count_rays(n_cl, n_sh, C);
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth0,
                                                              PhotonState Ph, const uint32_t* __restrict__ queue,
                                                              const uint32_t* __restrict__ count,
@@ -665,7 +666,7 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
         if (__ballot(active) == 0ull) break;
         if (!active) continue;
         // one interaction, as in photon_continue
-        const HitRec h = trace_closest<kTraceBS, false>(S, ph.o, ph.d, lds, st, vc);
+        const HitRec h = trace_closest<kTraceBS, COUNT>(S, ph.o, ph.d, lds, st, vc);
         ++n_cl;
         int outcome = -1;
         Deposit dp;
@@ -690,6 +691,16 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
         }
     }
     count_rays(n_cl, 0u, C);
+    const unsigned long long c_rays = wave_sum_u64(n_cl);
+    if (lane_id() == 0 && c_rays) atomicAdd(&C->fin_rays, c_rays);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(&C->fin_paths, (unsigned long long)n);
+    if (COUNT) {
+        const unsigned long long c_nodes = wave_sum_u64(vc.nodes), c_tris = wave_sum_u64(vc.tris);
+        if (lane_id() == 0 && c_nodes) {
+            atomicAdd(&C->fin_nodes, c_nodes);
+            atomicAdd(&C->fin_tris, c_tris);
+        }
+    }
 }
 
 __global__ void k_map_finalize(const unsigned long long* __restrict__ acc, size_t n, double inv_scale,
@@ -920,6 +931,11 @@ void ctx_release(Ctx* c) {
         (void)hipEventDestroy(e.second);
     }
     c->events.clear();
+    for (auto& e : c->fin_events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    c->fin_events.clear();
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     c->event_pool.clear();
 }
@@ -937,6 +953,21 @@ sc_status ctx_counters(Ctx* c, sc_counters* out) {
         c->event_pool.push_back(e.second);
     }
     c->events.clear();
+    for (auto& e : c->fin_events) {
+        float ms = 0.0f;
+        SC_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+        c->finish_ms += ms;
+        c->finish_launches += 1;
+        c->event_pool.push_back(e.first);
+        c->event_pool.push_back(e.second);
+    }
+    c->fin_events.clear();
+    out->finish_launches = c->finish_launches;
+    out->finish_ms = c->finish_ms;
+    out->finish_paths = h.fin_paths;
+    out->finish_rays = h.fin_rays;
+    out->finish_node_visits = h.fin_nodes;
+    out->finish_tri_tests = h.fin_tris;
     out->rays_closest = h.rays_closest;
     out->rays_shadow = h.rays_shadow;
     out->node_visits = h.node_visits;
@@ -953,6 +984,8 @@ sc_status ctx_reset_counters(Ctx* c) {
     ctx_release(c);
     c->closest_ms = 0.0;
     c->closest_launches = 0;
+    c->finish_ms = 0.0;
+    c->finish_launches = 0;
     return SC_OK;
 }
 
@@ -1096,10 +1129,27 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
                                    c->counters.as<DevCounters>());
                 std::swap(cur, nxt);
             }
-            if (staged < max_depth)
-                hipLaunchKernelGGL(k_finish_photons, dim3(trace_grid(n)), dim3(kTraceBS), 0, st, S, wd, pi, staged + 1,
-                                   Ph, cur, q.counts + (size_t)staged * QC_FRAME + QC_CUR, next_work_slot(c),
-                                   c->acc64.as<unsigned long long>(), count_map, c->counters.as<DevCounters>());
+            if (staged < max_depth) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (c->profile) {
+                    e0 = pooled_event(c);
+                    e1 = pooled_event(c);
+                    (void)hipEventRecord(e0, st);
+                }
+                uint32_t* fcount = q.counts + (size_t)staged * QC_FRAME + QC_CUR;
+                if (c->count_visits)
+                    hipLaunchKernelGGL(k_finish_photons<true>, dim3(trace_grid(n)), dim3(kTraceBS), 0, st, S, wd, pi,
+                                       staged + 1, Ph, cur, fcount, next_work_slot(c),
+                                       c->acc64.as<unsigned long long>(), count_map, c->counters.as<DevCounters>());
+                else
+                    hipLaunchKernelGGL(k_finish_photons<false>, dim3(trace_grid(n)), dim3(kTraceBS), 0, st, S, wd, pi,
+                                       staged + 1, Ph, cur, fcount, next_work_slot(c),
+                                       c->acc64.as<unsigned long long>(), count_map, c->counters.as<DevCounters>());
+                if (c->profile) {
+                    (void)hipEventRecord(e1, st);
+                    c->fin_events.emplace_back(e0, e1);
+                }
+            }
         }
     }
     if (cells)
