@@ -68,6 +68,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 // ------------------------------------------------------------------ ray feed
 constexpr uint32_t kRefill = 16;   // idle lanes that trigger a refill
+constexpr uint32_t kEventBatch = 32;   // pending photon events that are run together
 
 // Persistent lanes: each wave owns a batch of rays [next, end) of the
 // launch's list (the first batch by the wave's index in the grid, the rest
@@ -647,10 +648,16 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
     feed.init(n, work);
     uint32_t n_cl = 0;
     PhotonPath ph;
+    Trav t;
     uint32_t id = 0, depth = 0;
-    bool active = false;
+    // each lane: 0 idle, 1 tracing its path's current segment, 2 hit found
+    // and its photon event pending.  Traversal advances one step per loop
+    // turn, so no lane waits for the slowest ray of its wave; the events
+    // run together once kEventBatch lanes have one pending (or no lane is
+    // tracing), so the event code is not entered for one lane at a time.
+    uint32_t state = 0;
     for (;;) {
-        const uint32_t i = feed.take(!active);
+        const uint32_t i = feed.take(state == 0);
         if (i != 0xffffffffu) {
             id = queue[i];
             ph.o = F3{Ph.ox[id], Ph.oy[id], Ph.oz[id]};
@@ -661,12 +668,16 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
             ph.spec = Ph.spec[id];
             ph.med = Ph.med[id];
             depth = depth0;
-            active = true;
+            trav_init(t, ph.o, ph.d);
+            state = 1;
         }
-        if (__ballot(active) == 0ull) break;
-        if (!active) continue;
+        if (__ballot(state != 0) == 0ull) break;
+        if (state == 1 && trav_step<kTraceBS, COUNT>(S, t, lds, st, vc)) state = 2;
+        const unsigned long long pend = __ballot(state == 2);
+        if (pend == 0ull || ((uint32_t)__popcll(pend) < kEventBatch && __ballot(state == 1) != 0ull)) continue;
+        if (state != 2) continue;
         // one interaction, as in photon_continue
-        const HitRec h = trace_closest<kTraceBS, COUNT>(S, ph.o, ph.d, lds, st, vc);
+        const HitRec h = trav_result(t);
         ++n_cl;
         int outcome = -1;
         Deposit dp;
@@ -685,9 +696,11 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
         }
         if (cont) {
             ++depth;
+            trav_init(t, ph.o, ph.d);
+            state = 1;
         } else {
             if (outcome >= 0) ph_stat(C, pi, outcome, ph.phi);
-            active = false;
+            state = 0;
         }
     }
     count_rays(n_cl, 0u, C);
