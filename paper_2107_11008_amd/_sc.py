@@ -117,6 +117,17 @@ class PmapInfo(C.Structure):
                 ("buckets", C.c_uint32), ("bytes", C.c_uint64)]
 
 
+def _quiet_close(obj):
+    """Release a handle from __del__; at interpreter shutdown (module globals
+    may already be gone) the process exit frees it instead."""
+    try:
+        if sys is None or sys.is_finalizing():
+            return
+        obj.close()
+    except Exception:
+        pass
+
+
 class Counters(C.Structure):
     _fields_ = [("rays_closest", C.c_uint64), ("rays_shadow", C.c_uint64), ("node_visits", C.c_uint64),
                 ("tri_tests", C.c_uint64), ("closest_launches", C.c_uint64), ("closest_ms", C.c_double),
@@ -260,11 +271,9 @@ class Context:
             self.h = None
 
     def __del__(self):
-        if sys.is_finalizing():
-            return
         try:
-            self.close()
-        except Exception:
+            _quiet_close(self)
+        except Exception:   # module globals already cleared at shutdown
             pass
 
     def set_option(self, opt: int, value: int):
@@ -507,11 +516,9 @@ class Bvh:
             self.h = None
 
     def __del__(self):
-        if sys.is_finalizing():
-            return
         try:
-            self.close()
-        except Exception:
+            _quiet_close(self)
+        except Exception:   # module globals already cleared at shutdown
             pass
 
 
@@ -552,11 +559,9 @@ class PhotonMap:
             self.h = None
 
     def __del__(self):
-        if sys.is_finalizing():
-            return
         try:
-            self.close()
-        except Exception:
+            _quiet_close(self)
+        except Exception:   # module globals already cleared at shutdown
             pass
 
 
@@ -622,11 +627,9 @@ class UNet:
             self.h = None
 
     def __del__(self):
-        if sys.is_finalizing():
-            return
         try:
-            self.close()
-        except Exception:
+            _quiet_close(self)
+        except Exception:   # module globals already cleared at shutdown
             pass
 
 
@@ -694,9 +697,7 @@ class Batch:
             self.h = None
 
     def __del__(self):
-        if sys.is_finalizing():
-            return
         try:
-            self.close()
-        except Exception:
+            _quiet_close(self)
+        except Exception:   # module globals already cleared at shutdown
             pass
