@@ -656,6 +656,8 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
     // run together once kEventBatch lanes have one pending (or no lane is
     // tracing), so the event code is not entered for one lane at a time.
     uint32_t state = 0;
+    // general photon maps: events wait for every lane (measured faster there)
+    const uint32_t ev_batch = pi.general ? 65u : kEventBatch;
     for (;;) {
         const uint32_t i = feed.take(state == 0);
         if (i != 0xffffffffu) {
@@ -674,26 +676,25 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
         if (__ballot(state != 0) == 0ull) break;
         if (state == 1 && trav_step<kTraceBS, COUNT>(S, t, lds, st, vc)) state = 2;
         const unsigned long long pend = __ballot(state == 2);
-        if (pend == 0ull || ((uint32_t)__popcll(pend) < kEventBatch && __ballot(state == 1) != 0ull)) continue;
-        if (state != 2) continue;
-        // one interaction, as in photon_continue
-        const HitRec h = trav_result(t);
-        ++n_cl;
+        if (pend == 0ull || ((uint32_t)__popcll(pend) < ev_batch && __ballot(state == 1) != 0ull)) continue;
+        // the wave is converged here (the test above is the same for every
+        // lane): the deposits below merge their atomics over the wave
+        bool cont = false, dep = false;
         int outcome = -1;
         Deposit dp;
-        const bool cont =
-            photon_event(S, wl, pi.seed, pi.p0 + id, depth, pi.max_depth, pi.general != 0, h, ph, outcome, dp);
-        if (dp.cell_ch >= 0) {
-            if (pi.general) {
-                const uint32_t k = atomicAdd(&pi.rec.stat[0], 1u);
-                atomicMax(&pi.rec.stat[1], __float_as_uint(ph.phi));
-                atomicMax(&pi.rec.stat[2], pm_extent_bits(dp));
-                pm_store(pi.rec, k, dp, (uint32_t)dp.cell_ch, ph.phi, pi.p0 + id);
-            } else {
-                atomicAdd(&acc[dp.cell_ch], __double2ull_rn((double)ph.phi * pi.scale));
-                if (cnt_map) atomicAdd(&cnt_map[dp.cell_ch], 1u);
-            }
+        dp.cell_ch = -1;
+        if (state == 2) {   // one interaction, as in photon_continue
+            const HitRec h = trav_result(t);
+            ++n_cl;
+            cont = photon_event(S, wl, pi.seed, pi.p0 + id, depth, pi.max_depth, pi.general != 0, h, ph, outcome,
+                                dp);
+            dep = dp.cell_ch >= 0;
         }
+        if (pi.general)
+            pm_append(dep, pi.rec, dp, (uint32_t)dp.cell_ch, ph.phi, pi.p0 + id);
+        else
+            deposit(dep, (uint32_t)dp.cell_ch, dep ? __double2ull_rn((double)ph.phi * pi.scale) : 0ull, acc, cnt_map);
+        if (state != 2) continue;
         if (cont) {
             ++depth;
             trav_init(t, ph.o, ph.d);
