@@ -232,6 +232,76 @@ def unet_1080p(ctx, reps=20):
             "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4)}
 
 
+def _event_ms(fn, reps):
+    """Mean ms per call of fn from HIP events on torch's current stream (the
+    library context runs on it), after one untimed call."""
+    import torch
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def unet_train_step(ctx, reps=10, batch=12, crop=128):
+    """One U-Net training step (forward, loss, input and weight gradients,
+    Adam) on a batch of 12 128x128 crops, the denoiser's training shape, with
+    the committed network's widths: ms per step and the achieved fraction of
+    the bf16 matrix-core peak, counting forward + input gradient + weight
+    gradient as 3x the forward multiply-adds."""
+    import torch
+
+    import paper_2107_11008_amd as sc
+    from paper_2107_11008_amd import denoiser as D
+    params, meta = D.load_weights()
+    if params is None:
+        return None
+    widths = tuple(meta["widths"])
+    net = sc.UNet(ctx, widths, params)
+    g = torch.Generator().manual_seed(2)
+    feat = torch.rand((batch, crop, crop, 9), generator=g).cuda()
+    target = torch.rand((batch, crop, crop, 3), generator=g).cuda()
+    ms = _event_ms(lambda: net.train_step(feat, target, 1e-4, want_loss=False), reps)
+    fl = 3 * batch * unet_flops(widths, crop, crop)
+    tf = fl / (ms * 1e-3) / 1e12
+    net.close()
+    return {"batch": [batch, crop, crop], "ms": round(ms, 4), "gflop": round(fl / 1e9, 1),
+            "achieved_tflops": round(tf, 1), "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+            "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4)}
+
+
+def ground_truth_1080p(ctx, reps=20):
+    """Ground-truth post-processing at 1920x1080 on the held-out large
+    scene's own buffers (a 1-spp render with and without the caustic gather:
+    rgb, first-hit ids, transparency, depth): the local / non-local caustic
+    mask, 3-pixel outlines and occlusion boundaries, each timed with HIP
+    events; GB/s in algorithmic bytes (each input read once, each output
+    written once) against the 8 TB/s HBM peak."""
+    import scenegen as sg
+    cfg = sg.config3(seed=200000)
+    md, wl, cam = cfg["max_depth"], cfg["wavelengths"], cfg["camera"]
+    bvh = ctx.build_bvh(cfg["scene"])
+    m = ctx.trace_photons(bvh, 1 << 18, md, wl, 11)["map"]
+    a = ctx.render(bvh, cam, 1, md, wl, 12, caustic_map=m, outputs=("rgb", "obj", "trans", "depth"))
+    b = ctx.render(bvh, cam, 1, md, wl, 12, caustic_map=None, outputs=("rgb",))
+    n = cam.w * cam.h
+    legs = {"caustic_mask": (lambda: ctx.caustic_mask(a["rgb"], b["rgb"], a["trans"], 0.01), n * (12 + 12 + 1 + 1)),
+            "outline_3px": (lambda: ctx.outline(a["obj"], 3), n * (4 + 1)),
+            "occlusion_boundary": (lambda: ctx.occlusion_boundary(a["depth"], 0.1), n * (4 + 1))}
+    res = {"pixels": n}
+    for k, (fn, by) in legs.items():
+        ms = _event_ms(fn, reps)
+        gbs = by / (ms * 1e-3) / 1e9
+        res[k] = {"us": round(ms * 1e3, 2), "alg_MB": round(by / 1e6, 1), "GB_s": round(gbs, 1),
+                  "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    del bvh
+    return res
+
+
 def glass_variants(ctx, steps=5, warmup=2):
     """The same medium-scene step on the richer glass: every object tinted
     and every second one rough ("rich"), and the clear scene under a light
@@ -342,6 +412,8 @@ def main():
     ap.add_argument("--no-glass-variants", action="store_true")
     ap.add_argument("--no-pmap", action="store_true")
     ap.add_argument("--no-unet", action="store_true")
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-gt", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -510,6 +582,10 @@ def main():
         line["general_photon_map"] = general_photon_map(ctx)
     if not args.no_unet:
         line["unet_1080p"] = unet_1080p(ctx)
+    if not args.no_train:
+        line["unet_train_step"] = unet_train_step(ctx)
+    if not args.no_gt:
+        line["ground_truth_1080p"] = ground_truth_1080p(ctx)
     if not args.no_denoise:
         line["denoise_1080p"] = denoise_fps(ctx)
     if not args.no_batch:

@@ -657,8 +657,12 @@ __global__ void k_l1_loss(const float* __restrict__ pred, const float* __restric
         }
         dY[i] = to_bf16(g);
     }
+    // one atomic per block
+    __shared__ float part[4];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss_sum, s);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss_sum, (part[0] + part[1]) + (part[2] + part[3]));
 }
 
 // given dpred float [P][3] -> bf16 [P][cout_p]
@@ -1014,8 +1018,12 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
     float* dWp = u->dwp.as<float>();
     hipLaunchKernelGGL(k_zero_f, dim3(blocks((size_t)Ly.cout_p * kreal)), dim3(256), 0, st, dWp,
                        (size_t)Ly.cout_p * kreal);
-    const uint32_t chunk = 4096;
-    const size_t waves = (size_t)(Ly.cout_p / 16) * ((kreal + 63) / 64) * ((P + chunk - 1) / chunk);
+    // pixels per wave: enough waves to fill the chip (about 8192), 256 to
+    // 4096 pixels each (the partial sums meet in float atomics)
+    const uint32_t tiles = (Ly.cout_p / 16) * ((kreal + 63) / 64);
+    const uint32_t want_chunks = (8192 + tiles - 1) / tiles;
+    const uint32_t chunk = std::min(4096u, std::max(256u, ((P + want_chunks - 1) / want_chunks + 31) / 32 * 32));
+    const size_t waves = (size_t)tiles * ((P + chunk - 1) / chunk);
     if (Ly.ks == 3)
         hipLaunchKernelGGL(k_wgrad<3>, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, st, dZ, Ly.cout_p, Xin,
                            Ly.cin_p, P, H, W, chunk, dWp, kreal);
@@ -1122,7 +1130,8 @@ sc_status unet_loss(Unet* u, const float* target, float* loss_dev) {
     const uint32_t P = u->B * u->H * u->W;
     hipStream_t st = u->ctx->stream;
     hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(64), 0, st, loss_dev, (size_t)1);
-    hipLaunchKernelGGL(k_l1_loss, dim3(blocks((size_t)P * 16)), dim3(256), 0, st, u->pred.as<float>(), target, P, 16u,
+    hipLaunchKernelGGL(k_l1_loss, dim3(std::min(1024u, blocks((size_t)P * 16))), dim3(256), 0, st,
+                       u->pred.as<float>(), target, P, 16u,
                        1.0f / (float)((size_t)P * 3), u->acts.as<uint16_t>() + u->t.g0, loss_dev);
     SC_HIP(hipGetLastError());
     return SC_OK;
