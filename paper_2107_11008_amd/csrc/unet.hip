@@ -1033,7 +1033,7 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
     hipLaunchKernelGGL(k_unpad_grad, dim3(blocks((size_t)Ly.cout * taps * Ly.cin)), dim3(256), 0, st, dWp, Ly.cout,
                        Ly.cin, Ly.ks, Ly.cin_p, g + Ly.w_off);
     hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(256), 0, st, g + Ly.b_off, (size_t)Ly.cout);
-    hipLaunchKernelGGL(k_bias_grad, dim3(std::min<uint32_t>(1024, (P + 3) / 4)), dim3(256), 0, st, dZ, P, Ly.cout_p,
+    hipLaunchKernelGGL(k_bias_grad, dim3(std::min<uint32_t>(256, (P + 3) / 4)), dim3(256), 0, st, dZ, P, Ly.cout_p,
                        Ly.cout, g + Ly.b_off);
     if (dX)
         conv_launch(st, u->cus, u->ctx->conv_big_tile, Ly, dZ, P, H, W, u->wd.as<uint16_t>() + Ly.wd_off, Ly.cout_p,

@@ -68,3 +68,36 @@ def test_bad_staged_depth_rejected(ctx):
     for opt in (sc._sc.SC_OPT_STAGED_DEPTH, sc._sc.SC_OPT_PHOTON_STAGED_DEPTH):
         with pytest.raises(sc.ScError):
             ctx.set_option(opt, -1)
+
+
+def test_finishing_counters(ctx):
+    """The counters behind the photon finishing kernel's roofline: with
+    profiling and visit counting on, one timed launch per photon pass; it
+    takes over the photons still alive after the staged bounce and traces at
+    least one segment each; every photon segment is counted once, by the
+    staged kernel or by the finishing kernel (equal to the pass's segment
+    statistic); counting does not change the map."""
+    import paper_2107_11008_amd as sc
+    c = sg.config2(tri_scale=0.05, w=32, h=24)
+    md, wl = c["max_depth"], c["wavelengths"]
+    n = 1 << 16
+    bvh = ctx.build_bvh(c["scene"])
+    plain = ctx.trace_photons(bvh, n, md, wl, c["photon_seed"])["map"].cpu().numpy()
+    ctx.reset_counters()
+    ctx.set_option(sc._sc.SC_OPT_PROFILE, 1)
+    ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 1)
+    try:
+        r = ctx.trace_photons(bvh, n, md, wl, c["photon_seed"], stats=True)
+        k = ctx.counters()
+    finally:
+        ctx.set_option(sc._sc.SC_OPT_PROFILE, 0)
+        ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 0)
+    assert r["map"].cpu().numpy().tobytes() == plain.tobytes()
+    assert k["finish_launches"] == 1 and k["finish_ms"] > 0.0
+    assert 0 < k["finish_paths"] < n
+    assert k["finish_rays"] >= k["finish_paths"]
+    assert k["closest_rays_timed"] + k["finish_rays"] == k["rays_closest"] == r["stats"]["segments"]
+    assert k["finish_node_visits"] >= k["finish_rays"] and k["finish_tri_tests"] > 0
+    ctx.reset_counters()
+    k = ctx.counters()
+    assert k["finish_launches"] == 0 and k["finish_rays"] == 0 and k["finish_ms"] == 0.0
