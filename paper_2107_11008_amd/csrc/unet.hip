@@ -461,21 +461,32 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dZ, 
     }
 }
 
-__global__ void k_bias_grad(const uint16_t* __restrict__ dZ, uint32_t P, uint32_t cout_p, uint32_t cout_real,
-                            float* __restrict__ db) {
-    // block: 256 threads over a pixel range, one channel per thread group
-    const uint32_t c = threadIdx.x % 64;
-    const uint32_t sub = threadIdx.x / 64;
-    __shared__ float part[4][64];
-    for (uint32_t c0 = 0; c0 < cout_real; c0 += 64) {
-        float s = 0.0f;
-        const uint32_t cc = c0 + c;
-        if (cc < cout_real)
-            for (uint32_t p = blockIdx.x * 4 + sub; p < P; p += gridDim.x * 4) s += from_bf16(dZ[(size_t)p * cout_p + cc]);
-        part[sub][c] = s;
-        __syncthreads();
-        if (sub == 0 && cc < cout_real) atomicAdd(&db[cc], part[0][c] + part[1][c] + part[2][c] + part[3][c]);
-        __syncthreads();
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dZ, uint32_t P, uint32_t cout_p,
+                                                   uint32_t cout_real, float* __restrict__ db) {
+    // a thread sums 8 channels (one 16-byte load per pixel) over a strided
+    // pixel range; the block's partial sums meet in LDS, then one atomic
+    // per channel and block.  cout_p is a multiple of 16, at most 256.
+    const uint32_t c8n = cout_p / 8, nsub = 256 / c8n;
+    const uint32_t c8 = threadIdx.x % c8n, sub = threadIdx.x / c8n;
+    __shared__ float part[256 * 8];
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (sub < nsub)
+        for (uint32_t p = blockIdx.x * nsub + sub; p < P; p += gridDim.x * nsub) {
+            union {
+                uint4 u;
+                uint16_t h[8];
+            } v;
+            v.u = *reinterpret_cast<const uint4*>(dZ + (size_t)p * cout_p + 8 * c8);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += from_bf16(v.h[e]);
+        }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) part[threadIdx.x * 8 + e] = s[e];
+    __syncthreads();
+    for (uint32_t c = threadIdx.x; c < cout_real; c += blockDim.x) {
+        float t = 0.0f;
+        for (uint32_t q = 0; q < nsub; ++q) t += part[(q * c8n + c / 8) * 8 + c % 8];
+        atomicAdd(&db[c], t);
     }
 }
 
