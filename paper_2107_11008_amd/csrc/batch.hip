@@ -36,9 +36,23 @@ __device__ __forceinline__ uint32_t scene_of(const BatchScene* __restrict__ B, u
     return lo;
 }
 
+// lanes of the wave below this one in mask m
+__device__ __forceinline__ uint32_t below(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+constexpr uint32_t kBatchEvents = 32;   // pending photon events that are run together
+
+// A wave takes one work item (per_item photons of one scene) at a time.
+// Within it a lane whose photon has ended takes the item's next photon; the
+// traversal of every lane advances one step per loop turn and the photon
+// events run together once kBatchEvents lanes have one pending (or no lane
+// is tracing), so no lane waits for the longest path of its wave.  Every
+// photon's arithmetic is that of photon_continue; deposits are integer
+// atomics, so the map does not depend on the schedule.
 template <int BS>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_photons(const BatchScene* __restrict__ B, uint32_t n_scenes,
-                                                      uint32_t n_items, uint32_t per_item, uint32_t* work) {
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_photons(
+    const BatchScene* __restrict__ B, uint32_t n_scenes, uint32_t n_items, uint32_t per_item, uint32_t* work) {
     __shared__ uint2 lds[kLdsStack][BS];
     Spill st;
     VisitCount vc;
@@ -51,16 +65,50 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const uint32_t s = scene_of(B, n_scenes, item, true);
         const BatchScene& bs = B[s];
         const uint64_t first = (uint64_t)(item - bs.ph_item_begin) * per_item;
-        for (uint32_t j = lane; j < per_item; j += 64) {
-            const uint64_t p = first + j;
-            if (p >= bs.n_photons) break;
-            PhotonPath ph;
-            if (!photon_emit(bs.S, bs.wl, bs.photon_seed, bs.n_photons, p, ph)) continue;
-            uint32_t n_cl = 0;
-            photon_continue<BS>(bs.S, bs.wl, bs.photon_seed, p, 1, bs.max_depth, false, ph, lds, st, vc, n_cl,
-                                [&](const Deposit& dp, const PhotonPath& q) {
-                                    atomicAdd(&bs.acc[dp.cell_ch], __double2ull_rn((double)q.phi * bs.scale));
-                                });
+        const uint64_t left = first < bs.n_photons ? bs.n_photons - first : 0ull;
+        const uint32_t count = left < per_item ? (uint32_t)left : per_item;
+        uint32_t next = 0;   // the item's next photon (the same in every lane)
+        uint32_t state = 0;  // 0 idle, 1 tracing, 2 hit found and its event pending
+        uint32_t depth = 0;
+        uint64_t p = 0;
+        PhotonPath ph;
+        Trav t;
+        for (;;) {
+            const unsigned long long idle = __ballot(state == 0);
+            if (idle != 0ull && next < count) {
+                const uint32_t k = next + below(idle);
+                next = min(count, next + (uint32_t)__popcll(idle));
+                if (state == 0 && k < count) {
+                    p = first + k;
+                    if (photon_emit(bs.S, bs.wl, bs.photon_seed, bs.n_photons, p, ph)) {
+                        depth = 1;
+                        trav_init(t, ph.o, ph.d);
+                        state = 1;
+                    }
+                }
+            }
+            if (__ballot(state != 0) == 0ull) {
+                if (next >= count) break;
+                continue;
+            }
+            if (state == 1 && trav_step<BS, false>(bs.S, t, lds, st, vc)) state = 2;
+            const unsigned long long pend = __ballot(state == 2);
+            if (pend == 0ull || ((uint32_t)__popcll(pend) < kBatchEvents && __ballot(state == 1) != 0ull)) continue;
+            if (state != 2) continue;
+            // one interaction, as in photon_continue
+            const HitRec h = trav_result(t);
+            int outcome = -1;
+            Deposit dp;
+            const bool cont =
+                photon_event(bs.S, bs.wl, bs.photon_seed, p, depth, bs.max_depth, false, h, ph, outcome, dp);
+            if (dp.cell_ch >= 0) atomicAdd(&bs.acc[dp.cell_ch], __double2ull_rn((double)ph.phi * bs.scale));
+            if (cont && depth < bs.max_depth) {
+                ++depth;
+                trav_init(t, ph.o, ph.d);
+                state = 1;
+            } else {
+                state = 0;
+            }
         }
     }
 }
