@@ -377,90 +377,6 @@ __global__ __launch_bounds__(256) void k_conv1_out(const uint16_t* __restrict__ 
     }
 }
 
-// Weight gradient: dW[co][k] = sum_p dZ[p][co] * X[shift_tap(p)][ci] with
-// k = tap * cin_p + ci.  One wave: 16 output channels x 64 k over a chunk
-// of pixels (32 per MFMA step), added into dW with float atomics.
-template <int KS>
-__global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ dZ, uint32_t cout_p,
-                                               const uint16_t* __restrict__ X, uint32_t cin_p, uint32_t P,
-                                               uint32_t H, uint32_t W, uint32_t chunk, float* __restrict__ dW,
-                                               uint32_t kreal) {
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t co_tiles = cout_p / 16;
-    const uint32_t k_groups = (kreal + 63) / 64;
-    const uint32_t n_chunks = (P + chunk - 1) / chunk;
-    const uint32_t total = co_tiles * k_groups * n_chunks;
-    if (wave >= total) return;
-    const uint32_t ct = wave % co_tiles;
-    const uint32_t kg = (wave / co_tiles) % k_groups;
-    const uint32_t ch = wave / (co_tiles * k_groups);
-    const uint32_t pl = lane & 15, g = lane >> 4;
-    const uint32_t co = ct * 16 + pl;
-    // per B tile: weight column k = kg*64 + j*16 + pl -> (tap, ci)
-    int dyv[4], dxv[4];
-    uint32_t civ[4];
-    bool kval[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t k = kg * 64 + j * 16 + pl;
-        kval[j] = k < kreal;
-        const uint32_t tap = kval[j] ? k / cin_p : 0, ci = kval[j] ? k % cin_p : 0;
-        dyv[j] = KS == 3 ? (int)(tap / 3) - 1 : 0;
-        dxv[j] = KS == 3 ? (int)(tap % 3) - 1 : 0;
-        civ[j] = ci;
-    }
-    floatx4 acc[4];
-    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    const uint32_t p_begin = ch * chunk;
-    const uint32_t p_end = min(P, p_begin + chunk);
-    for (uint32_t p0 = p_begin; p0 < p_end; p0 += 32) {
-        Frag a;
-        uint16_t av[8];
-        uint32_t pxs[8], pys[8], pbs[8];
-        bool pv[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const uint32_t p = p0 + 8 * g + e;
-            pv[e] = p < p_end;
-            const uint32_t pp = pv[e] ? p : 0;
-            pxs[e] = pp % W;
-            const uint32_t r = pp / W;
-            pys[e] = r % H;
-            pbs[e] = r / H;
-            av[e] = pv[e] ? dZ[(size_t)pp * cout_p + co] : (uint16_t)0;
-        }
-        a.u = make_uint4(av[0] | ((uint32_t)av[1] << 16), av[2] | ((uint32_t)av[3] << 16),
-                         av[4] | ((uint32_t)av[5] << 16), av[6] | ((uint32_t)av[7] << 16));
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            uint16_t bv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int yy = (int)pys[e] + dyv[j], xx = (int)pxs[e] + dxv[j];
-                const bool in = pv[e] && kval[j] && yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W;
-                bv[e] = in ? X[(((size_t)pbs[e] * H + yy) * W + xx) * cin_p + civ[j]] : (uint16_t)0;
-            }
-            Frag bw;
-            bw.u = make_uint4(bv[0] | ((uint32_t)bv[1] << 16), bv[2] | ((uint32_t)bv[3] << 16),
-                              bv[4] | ((uint32_t)bv[5] << 16), bv[6] | ((uint32_t)bv[7] << 16));
-            // D[m = co][n = k]: A = dZ^T (co x pixels), B = X_shift (pixels x k)
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, bw.v, acc[j], 0, 0, 0);
-        }
-    }
-    // lane holds D[co = ct*16 + 4*g + i][k = kg*64 + j*16 + pl]
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t k = kg * 64 + j * 16 + pl;
-        if (k >= kreal) continue;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t c = ct * 16 + 4 * g + i;
-            atomicAdd(&dW[(size_t)c * kreal + k], acc[j][i]);
-        }
-    }
-}
-
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dZ, uint32_t P, uint32_t cout_p,
                                                    uint32_t cout_real, float* __restrict__ db) {
     // a thread sums 8 channels (one 16-byte load per pixel) over a strided
@@ -487,6 +403,107 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ 
         float t = 0.0f;
         for (uint32_t q = 0; q < nsub; ++q) t += part[(q * c8n + c / 8) * 8 + c % 8];
         atomicAdd(&db[c], t);
+    }
+}
+
+// Weight gradient through LDS: dW[co][k] = sum_p dZ[p][co] * X[shift_tap(p)][ci]
+// (k = tap * cin_p + ci).  A block owns 16 CT output channels x 64 KW
+// columns k (CT = channel tiles, KW = 4 / CT waves per tile, each wave one
+// channel tile x 4 column tiles) and a range of pixels, taken 32 at a time:
+// dZ (16 CT channels) and the shifted input (64 KW columns, 8 consecutive
+// channels of one tap per 16-byte load) are loaded with 16-byte loads and
+// stored transposed in LDS ([channel][pixel]), so every MFMA operand (8
+// pixels of one channel) is one 16-byte LDS read.  Partial sums meet in
+// dW with float atomics.  cin_p and cout_p are multiples of 16.
+constexpr int kWgPx = 32;             // pixels per step
+constexpr int kWgPitch = kWgPx + 8;   // LDS row pitch (bf16)
+template <int KS, int CT>
+__global__ __launch_bounds__(256) void k_wgrad_lds(const uint16_t* __restrict__ dZ, uint32_t cout_p,
+                                                   const uint16_t* __restrict__ X, uint32_t cin_p, uint32_t P,
+                                                   uint32_t H, uint32_t W, uint32_t chunk, float* __restrict__ dW,
+                                                   uint32_t kreal) {
+    constexpr int KW = 4 / CT;          // waves along k per channel tile
+    constexpr int NB = 64 * KW;         // columns k of the block
+    __shared__ __align__(16) uint16_t dzT[16 * CT][kWgPitch];
+    __shared__ __align__(16) uint16_t xT[NB][kWgPitch];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, pl = lane & 15, g = lane >> 4;
+    const uint32_t co_groups = (cout_p / 16 + CT - 1) / CT;
+    const uint32_t k_groups = (kreal + NB - 1) / NB;
+    uint32_t bid = blockIdx.x;
+    const uint32_t cgp = bid % co_groups;
+    bid /= co_groups;
+    const uint32_t kgp = bid % k_groups;
+    const uint32_t ch = bid / k_groups;
+    const uint32_t co0 = cgp * 16 * CT, k0 = kgp * NB;
+    const uint32_t p_begin = ch * chunk, p_end = min(P, p_begin + chunk);
+    const uint32_t ctile = wv / KW, kq = wv % KW;   // this wave: channel tile, quarter of the columns
+    const bool wave_on = co0 + 16 * ctile < cout_p;
+    floatx4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t p0 = p_begin; p0 < p_end; p0 += kWgPx) {
+        __syncthreads();   // the previous step's tiles are no longer read
+        // dZ: 16 CT channels x 32 pixels, 8 channels per piece
+        for (uint32_t t = tid; t < 2 * CT * kWgPx; t += 256) {
+            const uint32_t px = t % kWgPx, c8 = t / kWgPx;
+            const uint32_t p = p0 + px, c = co0 + 8 * c8;
+            union {
+                uint4 u;
+                uint16_t h[8];
+            } v;
+            v.u = make_uint4(0u, 0u, 0u, 0u);
+            if (p < p_end && c < cout_p) v.u = *reinterpret_cast<const uint4*>(dZ + (size_t)p * cout_p + c);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dzT[8 * c8 + e][px] = v.h[e];
+        }
+        // shifted input: NB columns x 32 pixels, 8 columns (8 channels of one tap) per piece
+        for (uint32_t t = tid; t < NB / 8 * kWgPx; t += 256) {
+            const uint32_t px = t % kWgPx, k8 = t / kWgPx;
+            const uint32_t p = p0 + px, k = k0 + 8 * k8;
+            union {
+                uint4 u;
+                uint16_t h[8];
+            } v;
+            v.u = make_uint4(0u, 0u, 0u, 0u);
+            if (p < p_end && k < kreal) {
+                const uint32_t tap = k / cin_p, ci = k - tap * cin_p;
+                int dy = 0, dx = 0;
+                if (KS == 3) {
+                    dy = (int)(tap / 3) - 1;
+                    dx = (int)(tap % 3) - 1;
+                }
+                const uint32_t rest = p / W, x = p - rest * W, y = rest % H;
+                const int yy = (int)y + dy, xx = (int)x + dx;
+                if (yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W)
+                    v.u = *reinterpret_cast<const uint4*>(X + (size_t)((int)p + dy * (int)W + dx) * cin_p + ci);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xT[8 * k8 + e][px] = v.h[e];
+        }
+        __syncthreads();
+        if (wave_on) {
+            Frag a;
+            a.u = *reinterpret_cast<const uint4*>(&dzT[16 * ctile + pl][8 * g]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                Frag b;
+                b.u = *reinterpret_cast<const uint4*>(&xT[64 * kq + 16 * j + pl][8 * g]);
+                // D[m = channel][n = column]: A = dZ^T (channels x pixels), B = X_shift (pixels x columns)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    if (!wave_on) return;
+    // lane holds D[channel 16 ctile + 4 g + i][column 64 kq + 16 j + pl]
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t k = k0 + 64 * kq + 16 * j + pl;
+        if (k >= kreal) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t c = co0 + 16 * ctile + 4 * g + i;
+            atomicAdd(&dW[(size_t)c * kreal + k], acc[j][i]);
+        }
     }
 }
 
@@ -1029,18 +1046,29 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
     float* dWp = u->dwp.as<float>();
     hipLaunchKernelGGL(k_zero_f, dim3(blocks((size_t)Ly.cout_p * kreal)), dim3(256), 0, st, dWp,
                        (size_t)Ly.cout_p * kreal);
-    // pixels per wave: enough waves to fill the chip (about 8192), 256 to
-    // 4096 pixels each (the partial sums meet in float atomics)
-    const uint32_t tiles = (Ly.cout_p / 16) * ((kreal + 63) / 64);
-    const uint32_t want_chunks = (8192 + tiles - 1) / tiles;
-    const uint32_t chunk = std::min(4096u, std::max(256u, ((P + want_chunks - 1) / want_chunks + 31) / 32 * 32));
-    const size_t waves = (size_t)tiles * ((P + chunk - 1) / chunk);
-    if (Ly.ks == 3)
-        hipLaunchKernelGGL(k_wgrad<3>, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, st, dZ, Ly.cout_p, Xin,
-                           Ly.cin_p, P, H, W, chunk, dWp, kreal);
-    else
-        hipLaunchKernelGGL(k_wgrad<1>, dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, st, dZ, Ly.cout_p, Xin,
-                           Ly.cin_p, P, H, W, chunk, dWp, kreal);
+    // channel tiles per block (3 rounds up to 4: one wave idles), pixels per
+    // block sized for about 2048 blocks, 256 to 8192 each (the partial sums
+    // meet in float atomics)
+    const uint32_t ctn = Ly.cout_p / 16;
+    const uint32_t CT = ctn >= 3 ? 4u : ctn;
+    const uint32_t nb = 64 * (4 / CT);
+    const uint32_t tiles = (ctn + CT - 1) / CT * ((kreal + nb - 1) / nb);
+    const uint32_t want_chunks = (2048 + tiles - 1) / tiles;
+    const uint32_t chunk = std::min(8192u, std::max(256u, ((P + want_chunks - 1) / want_chunks + 31) / 32 * 32));
+    const uint32_t grid = tiles * ((P + chunk - 1) / chunk);
+#define SC_WGRAD(KS_, CT_)                                                                                          \
+    hipLaunchKernelGGL((k_wgrad_lds<KS_, CT_>), dim3(grid), dim3(256), 0, st, dZ, Ly.cout_p, Xin, Ly.cin_p, P, H, W, \
+                       chunk, dWp, kreal)
+    if (Ly.ks == 3) {
+        if (CT == 4) SC_WGRAD(3, 4);
+        else if (CT == 2) SC_WGRAD(3, 2);
+        else SC_WGRAD(3, 1);
+    } else {
+        if (CT == 4) SC_WGRAD(1, 4);
+        else if (CT == 2) SC_WGRAD(1, 2);
+        else SC_WGRAD(1, 1);
+    }
+#undef SC_WGRAD
     hipLaunchKernelGGL(k_unpad_grad, dim3(blocks((size_t)Ly.cout * taps * Ly.cin)), dim3(256), 0, st, dWp, Ly.cout,
                        Ly.cin, Ly.ks, Ly.cin_p, g + Ly.w_off);
     hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(256), 0, st, g + Ly.b_off, (size_t)Ly.cout);
