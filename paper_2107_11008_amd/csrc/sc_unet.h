@@ -33,7 +33,7 @@ struct Unet {
     std::vector<uint32_t> widths;
     std::vector<UnetLayer> layers;
     size_t n_params = 0;
-    DevBuf theta, m, v, grad, wf, wd, dwp, loss, acts, pred;
+    DevBuf theta, m, v, grad, wf, wd, loss, acts, pred;
     uint32_t B = 0, H = 0, W = 0;
     UnetTensors t;
     uint64_t step = 0;

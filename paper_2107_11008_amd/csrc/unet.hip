@@ -420,8 +420,8 @@ constexpr int kWgPitch = kWgPx + 8;   // LDS row pitch (bf16)
 template <int KS, int CT>
 __global__ __launch_bounds__(256) void k_wgrad_lds(const uint16_t* __restrict__ dZ, uint32_t cout_p,
                                                    const uint16_t* __restrict__ X, uint32_t cin_p, uint32_t P,
-                                                   uint32_t H, uint32_t W, uint32_t chunk, float* __restrict__ dW,
-                                                   uint32_t kreal) {
+                                                   uint32_t H, uint32_t W, uint32_t chunk, float* __restrict__ gw,
+                                                   uint32_t kreal, uint32_t cout, uint32_t cin) {
     constexpr int KW = 4 / CT;          // waves along k per channel tile
     constexpr int NB = 64 * KW;         // columns k of the block
     __shared__ __align__(16) uint16_t dzT[16 * CT][kWgPitch];
@@ -494,15 +494,18 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(const uint16_t* __restrict__ 
         }
     }
     if (!wave_on) return;
-    // lane holds D[channel 16 ctile + 4 g + i][column 64 kq + 16 j + pl]
+    // lane holds D[channel 16 ctile + 4 g + i][column 64 kq + 16 j + pl]; the
+    // real (unpadded) entries go to the parameter gradient [cout][tap][cin]
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint32_t k = k0 + 64 * kq + 16 * j + pl;
         if (k >= kreal) continue;
+        const uint32_t tap = k / cin_p, ci = k - tap * cin_p;
+        if (ci >= cin) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t c = co0 + 16 * ctile + 4 * g + i;
-            atomicAdd(&dW[(size_t)c * kreal + k], acc[j][i]);
+            if (c < cout) atomicAdd(&gw[((size_t)c * (KS * KS) + tap) * cin + ci], acc[j][i]);
         }
     }
 }
@@ -726,19 +729,6 @@ __global__ void k_convert(const float* __restrict__ w, uint32_t cout, uint32_t c
     }
 }
 
-// scatter dW [cout_p][taps*cin_p] (padded) into the packed float gradient
-__global__ void k_unpad_grad(const float* __restrict__ dWp, uint32_t cout, uint32_t cin, uint32_t ks,
-                             uint32_t cin_p, float* __restrict__ g) {
-    const uint32_t taps = ks * ks;
-    const size_t n = (size_t)cout * taps * cin;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t ci = i % cin;
-        const size_t r = i / cin;
-        const uint32_t tap = r % taps, co = r / taps;
-        g[i] = dWp[(size_t)co * taps * cin_p + (size_t)tap * cin_p + ci];
-    }
-}
-
 __global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, size_t n, float lr, float b1, float b2, float eps, float c1,
                        float c2) {
@@ -820,9 +810,6 @@ sc_status unet_create(Ctx* c, const uint32_t* widths, uint32_t levels, Unet* u) 
     SC_TRY(u->grad.alloc(4 * u->n_params));
     SC_TRY(u->wf.alloc(2 * wf));
     SC_TRY(u->wd.alloc(2 * wd));
-    size_t maxw = 0;
-    for (auto& L : u->layers) maxw = std::max(maxw, (size_t)L.cout_p * L.ks * L.ks * L.cin_p);
-    SC_TRY(u->dwp.alloc(4 * maxw));
     SC_TRY(u->loss.alloc(16));
     hipLaunchKernelGGL(k_zero_f, dim3(blocks(u->n_params)), dim3(256), 0, c->stream, u->theta.as<float>(), u->n_params);
     hipLaunchKernelGGL(k_zero_f, dim3(blocks(u->n_params)), dim3(256), 0, c->stream, u->m.as<float>(), u->n_params);
@@ -1043,9 +1030,6 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
     float* g = u->grad.as<float>();
     const uint32_t taps = Ly.ks * Ly.ks;
     const uint32_t kreal = taps * Ly.cin_p;
-    float* dWp = u->dwp.as<float>();
-    hipLaunchKernelGGL(k_zero_f, dim3(blocks((size_t)Ly.cout_p * kreal)), dim3(256), 0, st, dWp,
-                       (size_t)Ly.cout_p * kreal);
     // channel tiles per block (3 rounds up to 4: one wave idles), pixels per
     // block sized for about 2048 blocks, 256 to 8192 each (the partial sums
     // meet in float atomics)
@@ -1058,7 +1042,7 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
     const uint32_t grid = tiles * ((P + chunk - 1) / chunk);
 #define SC_WGRAD(KS_, CT_)                                                                                          \
     hipLaunchKernelGGL((k_wgrad_lds<KS_, CT_>), dim3(grid), dim3(256), 0, st, dZ, Ly.cout_p, Xin, Ly.cin_p, P, H, W, \
-                       chunk, dWp, kreal)
+                       chunk, g + Ly.w_off, kreal, Ly.cout, Ly.cin)
     if (Ly.ks == 3) {
         if (CT == 4) SC_WGRAD(3, 4);
         else if (CT == 2) SC_WGRAD(3, 2);
@@ -1069,9 +1053,7 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
         else SC_WGRAD(1, 1);
     }
 #undef SC_WGRAD
-    hipLaunchKernelGGL(k_unpad_grad, dim3(blocks((size_t)Ly.cout * taps * Ly.cin)), dim3(256), 0, st, dWp, Ly.cout,
-                       Ly.cin, Ly.ks, Ly.cin_p, g + Ly.w_off);
-    hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(256), 0, st, g + Ly.b_off, (size_t)Ly.cout);
+    // the weight and bias gradients add into u->grad, cleared once per backward pass
     hipLaunchKernelGGL(k_bias_grad, dim3(std::min<uint32_t>(256, (P + 3) / 4)), dim3(256), 0, st, dZ, P, Ly.cout_p,
                        Ly.cout, g + Ly.b_off);
     if (dX)
@@ -1092,6 +1074,8 @@ sc_status unet_backward_packed(Unet* u) {
     uint16_t* gn = A + T.g2;      // gradient w.r.t. the previous tensor
     size_t li = u->layers.size() - 1;
     const uint32_t P0 = u->B * u->H * u->W;
+    // every layer's weight and bias gradients add into the cleared buffer
+    hipLaunchKernelGGL(k_zero_f, dim3(blocks(u->n_params)), dim3(256), 0, st, u->grad.as<float>(), u->n_params);
     // output layer (no activation): dZ = dY
     {
         const UnetLayer& Lo = u->layers[li];
