@@ -97,6 +97,8 @@ struct Ctx {
     DevBuf photon;     // PhotonState arrays
     size_t photon_n = 0;
     DevBuf acc64;      // fixed-point caustic accumulator
+    size_t acc_clean = 0;   // leading entries of acc64 known to be zero
+    DevBuf touched;    // cells a photon pass made non-zero (count first)
     DevBuf sensor;     // sensor curve table of the range [sensor_lo, sensor_hi]
     float sensor_lo = -1.0f, sensor_hi = -1.0f;
     uint32_t sensor_n = 0;

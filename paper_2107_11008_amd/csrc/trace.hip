@@ -418,6 +418,7 @@ struct PhInfo {
     int stats;
     int general;        // deposits go to rec (general photon map) instead of the receiver map
     PmRecords rec;
+    uint32_t* touched;  // receiver map: [0] count, then the cells the pass made non-zero
 };
 
 __device__ __forceinline__ void ph_stat(DevCounters* C, const PhInfo& pi, int outcome, float phi) {
@@ -453,8 +454,11 @@ __global__ void k_photon_emit(DevScene S, WaveDev wl, PhInfo pi, uint32_t n, Pho
 
 // Deposit fixed-point flux; lanes of a wave that hit the same cell as the
 // first depositing lane combine into one atomic.
+// Every lane of the wave calls it.  With `touched`, a cell that an add takes
+// from zero is appended to it (one counter atomic per wave), so the map can
+// be finalised and the accumulator cleared cell by cell.
 __device__ __forceinline__ void deposit(bool want, uint32_t cell, unsigned long long q, unsigned long long* acc,
-                                        uint32_t* cnt_map) {
+                                        uint32_t* cnt_map, uint32_t* touched) {
     const unsigned long long m = __ballot(want);
     if (m == 0ull) return;
     const uint32_t leader = __ffsll((long long)m) - 1;
@@ -462,13 +466,36 @@ __device__ __forceinline__ void deposit(bool want, uint32_t cell, unsigned long 
     const bool same = want && cell == lcell;
     const unsigned long long ms = __ballot(same);
     const unsigned long long part = wave_sum_u64(same ? q : 0ull);
+    bool first = false;
+    uint32_t fcell = 0;
     if (lane_id() == leader) {
-        atomicAdd(&acc[lcell], part);
+        if (touched) {
+            const unsigned long long old = atomicAdd(&acc[lcell], part);
+            first = old == 0ull && part != 0ull;
+            fcell = lcell;
+        } else {
+            atomicAdd(&acc[lcell], part);
+        }
         if (cnt_map) atomicAdd(&cnt_map[lcell], (uint32_t)__popcll(ms));
     }
     if (want && !same) {
-        atomicAdd(&acc[cell], q);
+        if (touched) {
+            const unsigned long long old = atomicAdd(&acc[cell], q);
+            first = old == 0ull && q != 0ull;
+            fcell = cell;
+        } else {
+            atomicAdd(&acc[cell], q);
+        }
         if (cnt_map) atomicAdd(&cnt_map[cell], 1u);
+    }
+    if (!touched) return;
+    const unsigned long long fm = __ballot(first);
+    if (fm != 0ull) {
+        const uint32_t lo = __ffsll((long long)fm) - 1;
+        uint32_t base = 0;
+        if (lane_id() == lo) base = atomicAdd(touched, (uint32_t)__popcll(fm));
+        base = __shfl(base, (int)lo);
+        if (first) touched[1 + base + lanes_below(fm)] = fcell;
     }
 }
 
@@ -553,7 +580,7 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
             }
         }
         if (pi.general) pm_append(dep, pi.rec, dp, cell_ch, phi, pi.p0 + id);
-        else deposit(dep, cell_ch, q, acc, cnt_map);
+        else deposit(dep, cell_ch, q, acc, cnt_map, pi.touched);
         block_push(cont, id, q_next, counts + QC_NEXT);
     }
 }
@@ -693,7 +720,8 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
         if (pi.general)
             pm_append(dep, pi.rec, dp, (uint32_t)dp.cell_ch, ph.phi, pi.p0 + id);
         else
-            deposit(dep, (uint32_t)dp.cell_ch, dep ? __double2ull_rn((double)ph.phi * pi.scale) : 0ull, acc, cnt_map);
+            deposit(dep, (uint32_t)dp.cell_ch, dep ? __double2ull_rn((double)ph.phi * pi.scale) : 0ull, acc, cnt_map,
+                    pi.touched);
         if (state != 2) continue;
         if (cont) {
             ++depth;
@@ -717,10 +745,28 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_photons(DevScene S, WaveDev
     }
 }
 
-__global__ void k_map_finalize(const unsigned long long* __restrict__ acc, size_t n, double inv_scale,
-                               float* __restrict__ map) {
+// the receiver map from the cells a pass touched (the rest of the map was
+// filled with zeros); their accumulator entries are cleared for the next pass
+__global__ void k_map_finalize(const uint32_t* __restrict__ touched, unsigned long long* __restrict__ acc,
+                               double inv_scale, float* __restrict__ map) {
+    const uint32_t n = touched[0];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t c = touched[1 + i];
+        map[c] = (float)((double)acc[c] * inv_scale);
+        acc[c] = 0ull;
+    }
+}
+
+// the whole receiver map (passes with many photons per cell)
+__global__ void k_map_finalize_all(const unsigned long long* __restrict__ acc, size_t n, double inv_scale,
+                                   float* __restrict__ map) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         map[i] = (float)((double)acc[i] * inv_scale);
+}
+
+__global__ void k_zero_f32x4(float4* p, size_t n4) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 inline uint32_t grid_for(size_t n, uint32_t bs, uint32_t cap = 8192) {
@@ -1090,11 +1136,28 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
     SC_TRY(make_wave(c, wl, wd));
     // the general photon map keeps records instead of the receiver map
     const size_t cells = rec ? 0 : (size_t)S.recv_wc * S.recv_hc * wd.channels;
+    const void* acc_before = c->acc64.p;
     SC_TRY(c->acc64.ensure(std::max<size_t>(cells, 1) * sizeof(unsigned long long)));
+    if (c->acc64.p != acc_before) c->acc_clean = 0;   // fresh memory
+    SC_TRY(c->touched.ensure((cells + 1) * sizeof(uint32_t)));
     const uint32_t bs = 256;
-    if (cells)
-        hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(cells, bs)), dim3(bs), 0, st, c->acc64.as<unsigned long long>(),
-                           cells);
+    // Passes with few photons per cell (a large map) keep the accumulator all
+    // zero between passes: each clears the cells it touched, listed by the
+    // deposits.  Passes with many photons per cell convert and clear the map
+    // in full (streaming beats scattered access there).  Either way the map
+    // is the same.  The accumulator is cleared in full after new memory, a
+    // dense pass or a pass that did not finish.
+    const bool sparse = cells > 8 * N;
+    size_t clean_after = c->acc_clean;
+    if (cells) {
+        if (!sparse || c->acc_clean < cells) {
+            hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(cells, bs)), dim3(bs), 0, st,
+                               c->acc64.as<unsigned long long>(), cells);
+            clean_after = cells;
+        }
+        c->acc_clean = 0;
+        if (sparse) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, c->touched.as<uint32_t>(), 1u);
+    }
     if (count_map && cells)
         hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(cells, bs)), dim3(bs), 0, st, count_map, (uint32_t)cells);
     DevCounters before{};
@@ -1127,7 +1190,8 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
         const HitSoA H{Ph.t, Ph.prim, Ph.u, Ph.v};
         for (uint64_t p0 = 0; p0 < N; p0 += chunk) {
             const uint32_t n = (uint32_t)std::min<uint64_t>(chunk, N - p0);
-            PhInfo pi{seed, N, p0, max_depth, scale, stats ? 1 : 0, rec ? 1 : 0, rec ? *rec : PmRecords{}};
+            PhInfo pi{seed, N, p0, max_depth, scale, stats ? 1 : 0, rec ? 1 : 0, rec ? *rec : PmRecords{},
+                      cells && sparse ? c->touched.as<uint32_t>() : nullptr};
             hipLaunchKernelGGL(k_zero_u32, dim3(32), dim3(256), 0, st, q.counts, frame_words);
             hipLaunchKernelGGL(k_photon_emit, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, wd, pi, n, Ph, q.cur, q.counts,
                                c->counters.as<DevCounters>());
@@ -1166,10 +1230,21 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
             }
         }
     }
-    if (cells)
-        hipLaunchKernelGGL(k_map_finalize, dim3(grid_for(cells, bs)), dim3(bs), 0, st,
+    if (cells && !sparse) {
+        hipLaunchKernelGGL(k_map_finalize_all, dim3(grid_for(cells, bs)), dim3(bs), 0, st,
                            c->acc64.as<unsigned long long>(), cells, 1.0 / scale, map);
+        clean_after = 0;
+    } else if (cells) {
+        if (((uintptr_t)map & 15u) == 0)
+            hipLaunchKernelGGL(k_zero_f32x4, dim3(grid_for(cells / 4, bs)), dim3(bs), 0, st,
+                               reinterpret_cast<float4*>(map), cells / 4);
+        if (((uintptr_t)map & 15u) != 0 || cells % 4 != 0)
+            hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(cells, bs)), dim3(bs), 0, st, map, cells);
+        hipLaunchKernelGGL(k_map_finalize, dim3(grid_for(std::min<size_t>(cells, N), bs)), dim3(bs), 0, st,
+                           c->touched.as<uint32_t>(), c->acc64.as<unsigned long long>(), 1.0 / scale, map);
+    }
     SC_HIP(hipGetLastError());
+    if (cells) c->acc_clean = clean_after;
     if (stats) {
         DevCounters after;
         SC_HIP(hipStreamSynchronize(st));

@@ -345,3 +345,21 @@ def test_c2_full_size_sampled_pixels(ctx):
     m2 = np.zeros(cam.w * cam.h, bool)
     m2[::7] = True
     _cmp_aov(g, ogt, mask=m2.reshape(cam.h, cam.w))
+
+
+def test_photon_map_independent_of_earlier_passes(ctx):
+    """The fixed-point accumulator is cleared cell by cell after each pass:
+    a receiver map equals itself bit for bit when passes over other scenes,
+    receiver sizes and photon counts, and a general photon map pass, ran in
+    between on the same context."""
+    c1 = sg.config1()
+    c2 = _scene_c2_small()
+    wl1, wl2 = c1["wavelengths"], c2["wavelengths"]
+    b1, b2 = ctx.build_bvh(c1["scene"]), ctx.build_bvh(c2["scene"])
+    first = ctx.trace_photons(b1, 1 << 14, c1["max_depth"], wl1, 5)["map"].cpu().numpy().copy()
+    ctx.trace_photons(b2, 1 << 15, c2["max_depth"], wl2, 6)
+    ctx.pmap_trace(b2, 1 << 13, c2["max_depth"], wl2, 7, 0.05)
+    ctx.trace_photons(b1, 1 << 12, c1["max_depth"], wl1, 8)
+    again = ctx.trace_photons(b1, 1 << 14, c1["max_depth"], wl1, 5)["map"].cpu().numpy()
+    assert first.tobytes() == again.tobytes()
+    assert first.max() > 0
