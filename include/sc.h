@@ -348,8 +348,12 @@ sc_status sc_render_pmap(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, u
 
 /* Render spp samples per pixel with at most max_depth surface hits per
  * path.  caustic_map: device map from sc_trace_photons with the same
- * wavelength setting, or NULL (caustic gather off).  EINVAL on spp == 0,
- * max_depth == 0, w*h == 0, an invalid wavelength setting or a NULL out. */
+ * wavelength setting, or NULL (caustic gather off).  With out->rgb NULL
+ * only the ground truth of the pixel-centre rays is written.  The BVH is
+ * only read: a context on the same device other than the one that built it
+ * may render from it (on its own stream) while it is not being rebuilt.
+ * EINVAL on spp == 0, max_depth == 0, w*h == 0, an invalid wavelength
+ * setting or a NULL out. */
 sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
                     const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, const sc_aov* out);
 

@@ -363,3 +363,28 @@ def test_photon_map_independent_of_earlier_passes(ctx):
     again = ctx.trace_photons(b1, 1 << 14, c1["max_depth"], wl1, 5)["map"].cpu().numpy()
     assert first.tobytes() == again.tobytes()
     assert first.max() > 0
+
+
+def test_second_context_renders_from_shared_bvh(ctx):
+    """A BVH is only read by rendering: a second context bound to another
+    stream renders the same ground truth from it, bit for bit, while the
+    first context traces photons on its own stream."""
+    import paper_2107_11008_amd as sc
+    c = sg.config1()
+    scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
+    bvh = ctx.build_bvh(scene)
+    keys = ("obj", "trans", "tri", "depth", "depthn", "normal", "albedo")
+    ref = ctx.render(bvh, cam, 1, c["max_depth"], wl, 3, outputs=keys)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ctx2 = sc.Context(0)
+    e = torch.cuda.Event()
+    e.record(torch.cuda.current_stream())
+    side.wait_event(e)
+    g = ctx2.render(bvh, cam, 1, c["max_depth"], wl, 3, outputs=keys)
+    ctx.trace_photons(bvh, 1 << 14, c["max_depth"], wl, 4)
+    torch.cuda.synchronize()
+    for k in keys:
+        a, b = ref[k].cpu().numpy(), g[k].cpu().numpy()
+        assert a.tobytes() == b.tobytes(), k
+    ctx2.close()
