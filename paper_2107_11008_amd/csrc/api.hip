@@ -80,6 +80,9 @@ sc_status sc_create(int device, void* hip_stream, sc_ctx** out) {
     if (!x) return set_error(SC_ENOMEM, "host allocation failed");
     x->c.device = device;
     x->c.stream = static_cast<hipStream_t>(hip_stream);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        x->c.cus = (uint32_t)cus;
     sc_status s = scl::ctx_init(&x->c);
     if (s != SC_OK) {
         delete x;

@@ -82,6 +82,7 @@ struct Ctx {
     bool count_visits = false;
     bool profile = false;
     uint64_t queue_cap = 1ull << 23;
+    uint32_t cus = 256;          // compute units of the device (sizes persistent grids)
     uint32_t staged_depth = 4;   // camera bounces run as separate launches before paths are finished per lane
     uint32_t photon_staged_depth = 1;   // the same for photon paths
     uint64_t conv_big_tile = 2048;   // 16-row U-Net convolution tiles needed before they are used
