@@ -76,34 +76,42 @@ def lib():
         path = _build.LIB
         if not os.path.exists(path):
             _build.build()
-        L = C.CDLL(path)
-        vp, u32, u64, f32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_float
-        L.sco_philox.argtypes = [vp, vp, vp]
-        L.sco_sincos2pi.argtypes = [f32, vp, vp]
-        L.sco_bvh_build.argtypes = [vp]
-        L.sco_bvh_build.restype = vp
-        L.sco_bvh_free.argtypes = [vp]
-        L.sco_closest.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp]
-        L.sco_any.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
-        L.sco_dielectric.argtypes = [vp, vp, vp, vp, f32, f32, f32, f32, vp, vp, vp, vp]
-        L.sco_fresnel.argtypes = [f32, f32, f32, f32]
-        L.sco_rough_dielectric.argtypes = [vp, vp, f32, f32, f32, u32, vp, vp, vp, vp]
-        L.sco_exp_neg.argtypes = [f32]
-        L.sco_exp_neg.restype = f32
-        L.sco_media_step.argtypes = [vp, vp, u32, u32, C.c_int, f32, vp, vp, vp, vp, vp]
-        L.sco_fresnel.restype = f32
-        L.sco_camera_ray.argtypes = [vp, u32, u32, f32, f32, vp, vp]
-        L.sco_trace_photons.argtypes = [vp, vp, u64, u64, u64, u32, vp, u64, vp, vp, vp]
-        L.sco_render.argtypes = [vp, vp, vp, u32, u32, vp, u64, vp, vp, u32, vp, vp]
-        L.sco_pm_trace.argtypes = [vp, vp, u64, u64, u64, u32, vp, u64, vp, u64, vp, vp]
-        L.sco_pm_scale.argtypes = [vp, u64]
-        L.sco_pm_scale.restype = C.c_double
-        L.sco_pm_gather.argtypes = [vp, u64, f32, vp, vp, u32]
-        L.sco_pm_gather.restype = f32
-        L.sco_render_pm.argtypes = [vp, vp, vp, u32, u32, vp, u64, vp, u64, f32, vp, u32, vp, vp]
-        L.sco_path_samples.argtypes = [vp, vp, vp, u32, u32, vp, u64, vp, vp, u32, vp, vp]
-        _LIB = L
+        _LIB = load(path)
     return _LIB
+
+
+def load(path):
+    """Open an oracle library at `path` and declare its functions (the
+    mutation tests open deliberately broken builds of sco.c this way)."""
+    L = C.CDLL(path)
+    vp, u32, u64, f32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_float
+    L.sco_philox.argtypes = [vp, vp, vp]
+    L.sco_sincos2pi.argtypes = [f32, vp, vp]
+    L.sco_bvh_build.argtypes = [vp]
+    L.sco_bvh_build.restype = vp
+    L.sco_bvh_free.argtypes = [vp]
+    L.sco_closest.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp]
+    L.sco_any.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
+    L.sco_dielectric.argtypes = [vp, vp, vp, vp, f32, f32, f32, f32, vp, vp, vp, vp]
+    L.sco_fresnel.argtypes = [f32, f32, f32, f32]
+    L.sco_rough_dielectric.argtypes = [vp, vp, f32, f32, f32, u32, vp, vp, vp, vp]
+    L.sco_exp_neg.argtypes = [f32]
+    L.sco_exp_neg.restype = f32
+    L.sco_media_step.argtypes = [vp, vp, u32, u32, C.c_int, f32, vp, vp, vp, vp, vp]
+    L.sco_fresnel.restype = f32
+    L.sco_camera_ray.argtypes = [vp, u32, u32, f32, f32, vp, vp]
+    L.sco_onb.argtypes = [vp, vp, vp]
+    L.sco_cosine_dir.argtypes = [vp, u32, vp, vp]
+    L.sco_trace_photons.argtypes = [vp, vp, u64, u64, u64, u32, vp, u64, vp, vp, vp]
+    L.sco_render.argtypes = [vp, vp, vp, u32, u32, vp, u64, vp, vp, u32, vp, vp]
+    L.sco_pm_trace.argtypes = [vp, vp, u64, u64, u64, u32, vp, u64, vp, u64, vp, vp]
+    L.sco_pm_scale.argtypes = [vp, u64]
+    L.sco_pm_scale.restype = C.c_double
+    L.sco_pm_gather.argtypes = [vp, u64, f32, vp, vp, u32]
+    L.sco_pm_gather.restype = f32
+    L.sco_render_pm.argtypes = [vp, vp, vp, u32, u32, vp, u64, vp, u64, f32, vp, u32, vp, vp]
+    L.sco_path_samples.argtypes = [vp, vp, vp, u32, u32, vp, u64, vp, vp, u32, vp, vp]
+    return L
 
 
 def _p(a):
@@ -254,6 +262,25 @@ def media_step(osc: "OracleScene", ids, k: int, entering: bool, lam: float):
     if rc != 0:
         raise ValueError("sco_media_step: invalid arguments")
     return [int(x) for x in out[: n_after.value]], bool(real.value), n1.value, n2.value
+
+
+def onb(n):
+    """Duff et al.'s orthonormal basis (t1, t2) about unit n (float32)."""
+    n = np.ascontiguousarray(n, dtype=np.float32)
+    t1 = np.zeros(3, np.float32)
+    t2 = np.zeros(3, np.float32)
+    lib().sco_onb(_p(n), _p(t1), _p(t2))
+    return t1, t2
+
+
+def cosine_dir(n, u):
+    """The Lambert bounce of a diffuse vertex: directions [count, 3] about
+    unit n from draws u float32 [count, 2] = (u0, u1)."""
+    n = np.ascontiguousarray(n, dtype=np.float32)
+    u = np.ascontiguousarray(u, dtype=np.float32).reshape(-1, 2)
+    out = np.zeros((len(u), 3), np.float32)
+    lib().sco_cosine_dir(_p(n), len(u), _p(u), _p(out))
+    return out
 
 
 def camera_ray(cam, x, y, jx=0.5, jy=0.5):

@@ -480,6 +480,37 @@ static void onb(v3 n, v3* t1, v3* t2) {
     *t2 = mk(b, sign + (n.y * n.y) * a, -n.y);
 }
 
+/* Cosine-weighted direction about unit n (Lambert bounce): a uniform
+ * point of the unit disc, radius sqrt(u0) and angle 2 pi u1, lifted to
+ * the hemisphere by z = sqrt(1 - u0) (Malley's method), expressed in the
+ * frame above.  The density is cos(theta) / pi, so sin^2(theta) = u0 and
+ * the azimuth 2 pi u1 are both uniform. */
+static v3 cosine_dir(v3 n, float u0, float u1) {
+    float rr = sqrtf(u0);
+    float sp, cp;
+    sco_sincos2pi(u1, &sp, &cp);
+    float x = rr * cp, y = rr * sp;
+    float z = sqrtf(fmaxf(0.0f, 1.0f - u0));
+    v3 t1, t2;
+    onb(n, &t1, &t2);
+    return vnorm(vadd(vadd(vscale(t1, x), vscale(t2, y)), vscale(n, z)));
+}
+
+void sco_onb(const float n[3], float t1[3], float t2[3]) {
+    v3 a, b;
+    onb(mk(n[0], n[1], n[2]), &a, &b);
+    t1[0] = a.x; t1[1] = a.y; t1[2] = a.z;
+    t2[0] = b.x; t2[1] = b.y; t2[2] = b.z;
+}
+
+void sco_cosine_dir(const float n[3], uint32_t count, const float* u, float* d_out) {
+    v3 nn = mk(n[0], n[1], n[2]);
+    for (uint32_t i = 0; i < count; i++) {
+        v3 d = cosine_dir(nn, u[2 * (size_t)i], u[2 * (size_t)i + 1]);
+        d_out[3 * (size_t)i] = d.x; d_out[3 * (size_t)i + 1] = d.y; d_out[3 * (size_t)i + 2] = d.z;
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Smooth dielectric interface.                                         */
 /*   n(lambda) = A + B / lambda_um^2       (two-term Cauchy dispersion)  */
@@ -1123,15 +1154,7 @@ static float trace_path(pt_ctx* X, v3 o, v3 d, uint32_t pix, uint32_t sample, ui
         /* cosine-weighted bounce */
         uint32_t r[4];
         rng_cam(X->seed, pix, sample, depth, 1, slot, r);
-        float u0 = u01(r[0]), u1 = u01(r[1]);
-        float rr = sqrtf(u0);
-        float sp, cp;
-        sco_sincos2pi(u1, &sp, &cp);
-        float x = rr * cp, y = rr * sp;
-        float z = sqrtf(fmaxf(0.0f, 1.0f - u0));
-        v3 t1, t2;
-        onb(f.Nf, &t1, &t2);
-        d = vnorm(vadd(vadd(vscale(t1, x), vscale(t2, y)), vscale(f.Nf, z)));
+        d = cosine_dir(f.Nf, u01(r[0]), u01(r[1]));
         o = os;
         T = T * rho;
     }

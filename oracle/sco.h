@@ -155,6 +155,11 @@ float sco_exp_neg(float x);
  * from) and n2 (across) at lambda. */
 int sco_media_step(const sco_scene* s, const uint32_t* ids, uint32_t n, uint32_t k, int entering, float lam,
                    uint32_t* ids_after, uint32_t* n_after, int* real, float* n1, float* n2);
+/* The frame and the Lambert bounce of diffuse vertices, exposed for the
+ * pins: Duff et al.'s orthonormal basis (t1, t2) about unit n, and count
+ * cosine-weighted directions about unit n from draws u[i] = (u0, u1). */
+void sco_onb(const float n[3], float t1[3], float t2[3]);
+void sco_cosine_dir(const float n[3], uint32_t count, const float* u, float* d_out);
 void sco_camera_ray(const sco_camera* cam, uint32_t x, uint32_t y, float jx, float jy, float o[3], float d[3]);
 
 /* Photon pass over photon indices [p0, p1) of a pass of n_photons.
