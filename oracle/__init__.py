@@ -313,10 +313,8 @@ def trace_photons(osc: OracleScene, n_photons: int, max_depth: int, wl, seed: in
     return msum.astype(np.float32), msum, cnt, stats
 
 
-def render(osc: OracleScene, cam, spp: int, max_depth: int, wl, seed: int, caustic_map=None, pixels=None,
-           want_tie: bool = False, brute: bool = False):
-    """Returns a dict of full-size arrays (only listed pixels written) and
-    the number of ray queries made."""
+def render_outputs(cam, want_tie: bool = False):
+    """Full-size output arrays of a render (miss values where unwritten)."""
     H, W = cam.h, cam.w
     out = dict(rgb=np.zeros((H, W, 3), np.float32), obj=np.zeros((H, W), np.uint32),
                trans=np.zeros((H, W), np.uint8), tri=np.full((H, W), 0xFFFFFFFF, np.uint32),
@@ -325,6 +323,18 @@ def render(osc: OracleScene, cam, spp: int, max_depth: int, wl, seed: int, caust
                albedo=np.zeros((H, W), np.float32))
     if want_tie:
         out["tie"] = np.zeros((H, W), np.uint8)
+    return out
+
+
+def render(osc: OracleScene, cam, spp: int, max_depth: int, wl, seed: int, caustic_map=None, pixels=None,
+           want_tie: bool = False, brute: bool = False, out=None):
+    """Returns a dict of full-size arrays (only listed pixels written) and
+    the number of ray queries made.  `out` (from render_outputs) is written
+    in place when given; calls on disjoint pixel lists may share it."""
+    if out is None:
+        out = render_outputs(cam, want_tie)
+    else:
+        out = {k: v for k, v in out.items() if k != "segments"}
     a = AovS()
     for k, v in out.items():
         setattr(a, k, v.ctypes.data)

@@ -371,6 +371,40 @@ static void closest_one(const sco_scene* s, const sco_bvh* bvh, v3 o, v3 d, floa
     *t = tb; *prim = pb; *u = ub; *v = vb;
 }
 
+/* Distance of the nearest hit on any triangle other than excl (+inf if
+ * none): brute force without a tree, else the tree walk of closest_one
+ * with excl skipped. */
+static float nearest_other(const sco_scene* s, const sco_bvh* bvh, v3 o, v3 d, uint32_t excl) {
+    ray_t r;
+    ray_prep(&r, o, d);
+    float tb = INFINITY, ub = 0.0f, vb = 0.0f;
+    uint32_t pb = 0xffffffffu;
+    if (!bvh) {
+        for (uint32_t i = 0; i < s->nt; i++)
+            if (i != excl) consider(s, &r, i, &tb, &pb, &ub, &vb);
+        return tb;
+    }
+    uint32_t stack[128];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const bnode* n = &bvh->nodes[stack[--sp]];
+        double te = box_entry(n, o, d, INFINITY);
+        if (isinf(te) || te > tlimit(tb)) continue;
+        if (n->left < 0) {
+            for (uint32_t k = 0; k < n->count; k++) {
+                uint32_t i = bvh->prims[n->first + k];
+                if (i != excl) consider(s, &r, i, &tb, &pb, &ub, &vb);
+            }
+        } else {
+            if (sp + 2 > 128) abort();
+            stack[sp++] = (uint32_t)n->right;
+            stack[sp++] = (uint32_t)n->left;
+        }
+    }
+    return tb;
+}
+
 static int any_one(const sco_scene* s, const sco_bvh* bvh, v3 o, v3 d, float tmax, uint32_t excl) {
     ray_t r;
     ray_prep(&r, o, d);
@@ -1290,15 +1324,7 @@ static int render_impl(const sco_scene* s, const sco_bvh* bvh, const sco_camera*
             /* second-nearest distinct triangle along the same ray */
             uint8_t tie = 0;
             if (prim != 0xffffffffu) {
-                ray_t r;
-                ray_prep(&r, o, d);
-                double t2 = INFINITY;
-                for (uint32_t k = 0; k < s->nt; k++) {
-                    if (k == prim) continue;
-                    v3 a, b, c; float tt, uu, vv;
-                    tri_verts(s, k, &a, &b, &c);
-                    if (tri_hit(&r, a, b, c, &tt, &uu, &vv) && (double)tt < t2) t2 = tt;
-                }
+                double t2 = (double)nearest_other(s, bvh, o, d, prim);
                 tie = (t2 - (double)t) < 1e-6 * (double)t;
             }
             out->tie[p] = tie;

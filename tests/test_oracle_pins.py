@@ -536,3 +536,26 @@ def test_c1_caustic_peak_location():
         assert 105 <= i <= 107 and 95 <= j <= 96, (ch, i, j)
         share = msum[j, i, ch] / msum[:, :, ch].sum()
         assert abs(share / share_expected[ch] - 1) < 0.3, (ch, share)
+
+
+def test_tie_flag_tree_equals_brute_force():
+    """The near-tie flag (a second distinct triangle within 1e-6 t of the
+    first hit) found through the oracle's tree equals the brute-force scan
+    over all triangles, on a scene built to have ties: two overlapping
+    planes 2e-7 m apart above a third plane."""
+    b = sg.SceneBuilder()
+    dm = dict(type=sg.MAT_DIFFUSE, albedo_mode=sg.ALBEDO_CONST, rho_a=0.5)
+    b.add(sg.quad((-3, -3, 0), (0.5, -3, 0), (0.5, 3, 0), (-3, 3, 0), (0, 0, 1)), dm)
+    z = 2e-7
+    b.add(sg.quad((-0.5, -3, z), (3, -3, z), (3, 3, z), (-0.5, 3, z), (0, 0, 1)), dm)
+    b.add(sg.quad((-4, -4, -0.01), (4, -4, -0.01), (4, 4, -0.01), (-4, 4, -0.01), (0, 0, 1)), dm)
+    b.add(sg.icosphere(2, 0.4, (1.0, 0.5, 0.6)), dm)
+    scene = b.build(None)
+    cam = sg.look_at((0.0, -3.0, 4.0), (0.0, 0.0, 0.0), (0, 0, 1), 60.0, 40, 32)
+    osc = oracle.OracleScene(scene)
+    wl = sg.Wavelengths(sg.WL_FIXED, 1, (550.0,))
+    a = oracle.render(osc, cam, 1, 1, wl, 3, want_tie=True)
+    bf = oracle.render(osc, cam, 1, 1, wl, 3, want_tie=True, brute=True)
+    assert np.array_equal(a["tie"], bf["tie"])
+    assert np.array_equal(a["tri"], bf["tri"])
+    assert 0 < a["tie"].sum() < a["tie"].size
