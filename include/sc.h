@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SC_ABI_VERSION 4u
+#define SC_ABI_VERSION 5u
 
 typedef int32_t sc_status;
 #define SC_OK 0
@@ -213,11 +213,25 @@ typedef struct {
     uint64_t finish_rays;     /* closest-hit rays it traced for them */
     uint64_t finish_node_visits; /* wide nodes it fetched (visit counting on) */
     uint64_t finish_tri_tests;   /* triangles it tested (visit counting on) */
+    uint64_t anyhit_launches;    /* any-hit kernel launches timed (profiling on) */
+    double anyhit_ms;            /* their summed duration from HIP events (profiling on) */
+    uint64_t anyhit_rays;        /* shadow rays the any-hit kernel traced (the rest of rays_shadow by
+                                  * the camera path finishing kernel) */
+    uint64_t anyhit_node_visits; /* wide nodes it fetched (visit counting on) */
+    uint64_t anyhit_tri_tests;   /* triangles it tested (visit counting on) */
+    uint64_t cam_finish_launches;  /* camera path finishing kernel launches timed (profiling on) */
+    double cam_finish_ms;          /* their summed duration from HIP events (profiling on) */
+    uint64_t cam_finish_paths;     /* camera paths it took over */
+    uint64_t cam_finish_rays;      /* closest-hit rays it traced for them */
+    uint64_t cam_finish_shadow_rays; /* shadow rays it traced for them */
+    uint64_t cam_finish_node_visits; /* wide nodes both kinds of ray fetched (visit counting on) */
+    uint64_t cam_finish_tri_tests;   /* triangles both kinds tested (visit counting on) */
 } sc_counters;
 
-#define SC_OPT_COUNT_VISITS 1 /* 0/1: closest-hit traversal counts node and triangle visits */
-#define SC_OPT_PROFILE 2      /* 0/1: time every closest-hit launch with HIP events */
-#define SC_OPT_QUEUE_CAP 3    /* paths per wavefront chunk (default 1<<23) */
+#define SC_OPT_COUNT_VISITS 1 /* 0/1: the traversal kernels count node and triangle visits */
+#define SC_OPT_PROFILE 2      /* 0/1: time every traversal launch (closest hit, any hit, path
+                               * finishing) with HIP events */
+#define SC_OPT_QUEUE_CAP 3    /* camera paths per wavefront chunk (1024..2^30, default 1<<27) */
 #define SC_OPT_STAGED_DEPTH 4 /* camera-path bounces traced as one launch per stage before the
                                * remaining paths are each finished by one lane (default 4; 0 =
                                * every bounce staged); any value gives the same output bit for bit */
@@ -226,6 +240,7 @@ typedef struct {
                                 * otherwise; any value gives the same output bit for bit */
 #define SC_OPT_PHOTON_STAGED_DEPTH 6 /* the same switch for photon paths (default 1: after the
                                       * first bounce every photon is finished by one lane) */
+#define SC_OPT_PHOTON_CAP 7   /* photons per photon-pass chunk (1024..2^28, default 1<<24) */
 
 uint32_t sc_abi_version(void);
 const char* sc_last_error(void);

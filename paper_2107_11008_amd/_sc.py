@@ -44,9 +44,10 @@ SC_OPT_QUEUE_CAP = 3
 SC_OPT_STAGED_DEPTH = 4
 SC_OPT_CONV_BIG_TILE = 5
 SC_OPT_PHOTON_STAGED_DEPTH = 6
+SC_OPT_PHOTON_CAP = 7
 
 
-ABI_VERSION = 4   # must match SC_ABI_VERSION in include/sc.h
+ABI_VERSION = 5   # must match SC_ABI_VERSION in include/sc.h
 
 
 class ScError(RuntimeError):
@@ -133,7 +134,12 @@ class Counters(C.Structure):
                 ("tri_tests", C.c_uint64), ("closest_launches", C.c_uint64), ("closest_ms", C.c_double),
                 ("closest_rays_timed", C.c_uint64), ("finish_launches", C.c_uint64), ("finish_ms", C.c_double),
                 ("finish_paths", C.c_uint64), ("finish_rays", C.c_uint64), ("finish_node_visits", C.c_uint64),
-                ("finish_tri_tests", C.c_uint64)]
+                ("finish_tri_tests", C.c_uint64), ("anyhit_launches", C.c_uint64), ("anyhit_ms", C.c_double),
+                ("anyhit_rays", C.c_uint64), ("anyhit_node_visits", C.c_uint64), ("anyhit_tri_tests", C.c_uint64),
+                ("cam_finish_launches", C.c_uint64), ("cam_finish_ms", C.c_double),
+                ("cam_finish_paths", C.c_uint64), ("cam_finish_rays", C.c_uint64),
+                ("cam_finish_shadow_rays", C.c_uint64), ("cam_finish_node_visits", C.c_uint64),
+                ("cam_finish_tri_tests", C.c_uint64)]
 
 
 NODE_DTYPE = np.dtype([("lox", "<f4", 8), ("hix", "<f4", 8), ("loy", "<f4", 8), ("hiy", "<f4", 8),

@@ -81,12 +81,19 @@ struct Ctx {
     hipStream_t stream = nullptr;
     bool count_visits = false;
     bool profile = false;
-    uint64_t queue_cap = 1ull << 23;
+    // camera paths per wavefront chunk: all 64 samples of a 1080p frame
+    // (132.7 M paths, ~17 GB of path state and queues) run as one chunk, so
+    // the staged launches are large and the per-lane finishing tail is paid
+    // once per frame (large scene: 2^23 / 2^24 / 2^25 / 2^26 / 2^27 paths
+    // per chunk gave 257.6 / 218.5 / 205.5 / 196.8 / 190.6 ms per step)
+    uint64_t queue_cap = 1ull << 27;
     uint32_t cus = 256;          // compute units of the device (sizes persistent grids)
     uint32_t staged_depth = 4;   // camera bounces run as separate launches before paths are finished per lane
     uint32_t photon_staged_depth = 1;   // the same for photon paths
     uint64_t conv_big_tile = 2048;   // 16-row U-Net convolution tiles needed before they are used
-    uint64_t photon_cap = 1ull << 22;
+    // photons per photon-pass chunk (2^24 photons of the large scene in one
+    // chunk: 34.8 / 29.8 / 27.5 ms per pass at 2^22 / 2^23 / 2^24; ~1.5 GB)
+    uint64_t photon_cap = 1ull << 24;
     DevBuf counters;   // DevCounters
     DevBuf work;       // per-launch work counters of the traversal kernels
     uint32_t work_slot = 0;
@@ -115,6 +122,12 @@ struct Ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> fin_events;   // photon finishing launches, not yet read
     double finish_ms = 0.0;
     uint64_t finish_launches = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> any_events;   // any-hit launches, not yet read
+    double any_ms = 0.0;
+    uint64_t any_launches = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> cam_events;   // camera path finishing launches, not yet read
+    double cam_ms = 0.0;
+    uint64_t cam_launches = 0;
 };
 
 struct Bvh {

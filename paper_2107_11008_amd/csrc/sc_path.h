@@ -291,15 +291,20 @@ __device__ __forceinline__ HitRec trace_closest(const DevScene& S, F3 o, F3 d, u
     return trav_result(t);
 }
 
+template <int BS, bool COUNT>
+__device__ __forceinline__ bool trace_any(const DevScene& S, F3 o, F3 d, float tmax, uint32_t excl, uint2 (*lds)[BS],
+                                          Spill& st, VisitCount& vc) {
+    Trav t;
+    any_init(t, o, d, tmax, excl);
+    while (!tstep<BS, COUNT, kAny>(S, t, lds, st, vc)) {
+    }
+    return t.hit;
+}
 template <int BS>
 __device__ __forceinline__ bool trace_any(const DevScene& S, F3 o, F3 d, float tmax, uint32_t excl, uint2 (*lds)[BS],
                                           Spill& st) {
-    Trav t;
-    any_init(t, o, d, tmax, excl);
     VisitCount vc;
-    while (!tstep<BS, false, kAny>(S, t, lds, st, vc)) {
-    }
-    return t.hit;
+    return trace_any<BS, false>(S, o, d, tmax, excl, lds, st, vc);
 }
 
 // ---------------------------------------------------------------- camera paths

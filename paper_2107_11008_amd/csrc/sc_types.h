@@ -140,6 +140,14 @@ struct DevCounters {
     unsigned long long fin_rays;     // closest-hit rays it traced
     unsigned long long fin_nodes;    // wide nodes it fetched (visit counting on)
     unsigned long long fin_tris;     // triangles it tested (visit counting on)
+    unsigned long long any_rays;     // shadow rays of the k_anyhit launches
+    unsigned long long any_nodes;    // wide nodes they fetched (visit counting on)
+    unsigned long long any_tris;     // triangles they tested (visit counting on)
+    unsigned long long cf_paths;     // camera paths taken over by k_finish_camera
+    unsigned long long cf_rays;      // closest-hit rays it traced
+    unsigned long long cf_shadow;    // shadow rays it traced
+    unsigned long long cf_nodes;     // wide nodes both kinds fetched (visit counting on)
+    unsigned long long cf_tris;      // triangles both kinds tested (visit counting on)
     unsigned long long ph_count[9];
     double ph_flux[9];
 };

@@ -165,12 +165,14 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
 // wave's index in the grid, the rest from the launch's atomic counter.  For
 // shadow rays of camera paths, an unoccluded segment adds its stored
 // contribution to L.
+template <bool COUNT>
 __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, const uint32_t* __restrict__ queue,
                                                      const uint32_t* __restrict__ count, uint32_t n_static,
                                                      uint32_t* __restrict__ work, uint8_t* __restrict__ occ_out,
                                                      float* __restrict__ L, DevCounters* __restrict__ C) {
     __shared__ uint2 lds[kLdsStack][kTraceBS];
     Spill st;
+    VisitCount vc;
     const uint32_t n = count ? *count : n_static;
     uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
     while (base < n) {
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
             const F3 o{R.ox[pid], R.oy[pid], R.oz[pid]};
             const F3 d{R.dx[pid], R.dy[pid], R.dz[pid]};
             const uint32_t excl = R.excl ? R.excl[pid] : 0xffffffffu;
-            const bool occluded = trace_any<kTraceBS>(S, o, d, R.tmax[pid], excl, lds, st);
+            const bool occluded = trace_any<kTraceBS, COUNT>(S, o, d, R.tmax[pid], excl, lds, st, vc);
             if (occ_out) occ_out[pid] = occluded ? 1 : 0;
             if (L && !occluded) L[pid] = L[pid] + R.contrib[pid];
         }
@@ -188,7 +190,17 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
         if (lane_id() == 0) next = atomicAdd(work, 64u);
         base = __shfl(next, 0) + gridDim.x * blockDim.x;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(&C->rays_shadow, (unsigned long long)n);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) {
+        atomicAdd(&C->rays_shadow, (unsigned long long)n);
+        atomicAdd(&C->any_rays, (unsigned long long)n);
+    }
+    if (COUNT) {
+        const unsigned long long c_nodes = wave_sum_u64(vc.nodes), c_tris = wave_sum_u64(vc.tris);
+        if (lane_id() == 0 && c_nodes) {
+            atomicAdd(&C->any_nodes, c_nodes);
+            atomicAdd(&C->any_tris, c_tris);
+        }
+    }
 }
 
 // ------------------------------------------------------------------ helpers
@@ -602,7 +614,7 @@ __device__ __forceinline__ void count_rays(uint32_t n_cl, uint32_t n_sh, DevCoun
     }
 }
 
-template <bool PM>
+template <bool PM, bool COUNT>
 __global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo ci, WaveDev wl, PathState P,
                                                             const float* __restrict__ cmap, PMapDev pm_arg,
                                                             const uint32_t* __restrict__ queue,
@@ -631,7 +643,7 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo 
         if (__ballot(active) == 0ull) break;
         if (!active) continue;
         // one bounce, as in camera_continue
-        const HitRec h = trace_closest<kTraceBS, false>(S, c.o, c.d, lds, st, vc);
+        const HitRec h = trace_closest<kTraceBS, COUNT>(S, c.o, c.d, lds, st, vc);
         ++n_cl;
         bool cont = false;
         if (h.prim != 0xffffffffu) {
@@ -645,7 +657,8 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo 
                 cont = camera_diffuse(S, wl, cmap, pm, ci.seed, pix, sample, slot, depth, ci.max_depth, h, c, sr);
                 if (sr.shoot) {
                     ++n_sh;
-                    if (!trace_any<kTraceBS>(S, sr.o, sr.d, sr.tmax, sr.excl, lds, st)) c.L = c.L + sr.contrib;
+                    if (!trace_any<kTraceBS, COUNT>(S, sr.o, sr.d, sr.tmax, sr.excl, lds, st, vc))
+                        c.L = c.L + sr.contrib;
                 }
             }
         }
@@ -657,6 +670,19 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_camera(DevScene S, CamInfo 
         }
     }
     count_rays(n_cl, n_sh, C);
+    const unsigned long long c_rays = wave_sum_u64(n_cl), c_sh = wave_sum_u64(n_sh);
+    if (lane_id() == 0 && (c_rays || c_sh)) {
+        atomicAdd(&C->cf_rays, c_rays);
+        atomicAdd(&C->cf_shadow, c_sh);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicAdd(&C->cf_paths, (unsigned long long)n);
+    if (COUNT) {
+        const unsigned long long c_nodes = wave_sum_u64(vc.nodes), c_tris = wave_sum_u64(vc.tris);
+        if (lane_id() == 0 && c_nodes) {
+            atomicAdd(&C->cf_nodes, c_nodes);
+            atomicAdd(&C->cf_tris, c_tris);
+        }
+    }
 }
 
 template <bool COUNT>
@@ -900,11 +926,37 @@ void launch_closest(Ctx* c, const DevScene& S, RaySoA R, HitSoA H, const uint32_
     }
 }
 
+// HIP events around a launch when profiling is on; kind selects the list
+// the pair is kept in until the counters are read
+struct Timed {
+    Ctx* c;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>>* list;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    Timed(Ctx* ctx, std::vector<std::pair<hipEvent_t, hipEvent_t>>& l) : c(ctx), list(&l) {
+        if (c->profile) {
+            e0 = pooled_event(c);
+            e1 = pooled_event(c);
+            (void)hipEventRecord(e0, c->stream);
+        }
+    }
+    ~Timed() {
+        if (c->profile) {
+            (void)hipEventRecord(e1, c->stream);
+            list->emplace_back(e0, e1);
+        }
+    }
+};
+
 void launch_anyhit(Ctx* c, const DevScene& S, ShadowSoA R, const uint32_t* queue, const uint32_t* count,
                    uint32_t n_static, size_t n_max, uint8_t* occ, float* L) {
     uint32_t* work = next_work_slot(c);
-    hipLaunchKernelGGL(k_anyhit, dim3(trace_grid(c, n_max)), dim3(kTraceBS), 0, c->stream, S, R, queue, count, n_static,
-                       work, occ, L, c->counters.as<DevCounters>());
+    Timed tm(c, c->any_events);
+    if (c->count_visits)
+        hipLaunchKernelGGL(k_anyhit<true>, dim3(trace_grid(c, n_max)), dim3(kTraceBS), 0, c->stream, S, R, queue, count,
+                           n_static, work, occ, L, c->counters.as<DevCounters>());
+    else
+        hipLaunchKernelGGL(k_anyhit<false>, dim3(trace_grid(c, n_max)), dim3(kTraceBS), 0, c->stream, S, R, queue,
+                           count, n_static, work, occ, L, c->counters.as<DevCounters>());
 }
 
 }  // namespace
@@ -1001,6 +1053,13 @@ void ctx_release(Ctx* c) {
         (void)hipEventDestroy(e.second);
     }
     c->fin_events.clear();
+    for (auto* l : {&c->any_events, &c->cam_events}) {
+        for (auto& e : *l) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        l->clear();
+    }
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     c->event_pool.clear();
 }
@@ -1027,6 +1086,36 @@ sc_status ctx_counters(Ctx* c, sc_counters* out) {
         c->event_pool.push_back(e.second);
     }
     c->fin_events.clear();
+    for (auto& e : c->any_events) {
+        float ms = 0.0f;
+        SC_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+        c->any_ms += ms;
+        c->any_launches += 1;
+        c->event_pool.push_back(e.first);
+        c->event_pool.push_back(e.second);
+    }
+    c->any_events.clear();
+    for (auto& e : c->cam_events) {
+        float ms = 0.0f;
+        SC_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+        c->cam_ms += ms;
+        c->cam_launches += 1;
+        c->event_pool.push_back(e.first);
+        c->event_pool.push_back(e.second);
+    }
+    c->cam_events.clear();
+    out->anyhit_launches = c->any_launches;
+    out->anyhit_ms = c->any_ms;
+    out->anyhit_rays = h.any_rays;
+    out->anyhit_node_visits = h.any_nodes;
+    out->anyhit_tri_tests = h.any_tris;
+    out->cam_finish_launches = c->cam_launches;
+    out->cam_finish_ms = c->cam_ms;
+    out->cam_finish_paths = h.cf_paths;
+    out->cam_finish_rays = h.cf_rays;
+    out->cam_finish_shadow_rays = h.cf_shadow;
+    out->cam_finish_node_visits = h.cf_nodes;
+    out->cam_finish_tri_tests = h.cf_tris;
     out->finish_launches = c->finish_launches;
     out->finish_ms = c->finish_ms;
     out->finish_paths = h.fin_paths;
@@ -1051,6 +1140,10 @@ sc_status ctx_reset_counters(Ctx* c) {
     c->closest_launches = 0;
     c->finish_ms = 0.0;
     c->finish_launches = 0;
+    c->any_ms = 0.0;
+    c->any_launches = 0;
+    c->cam_ms = 0.0;
+    c->cam_launches = 0;
     return SC_OK;
 }
 
@@ -1118,9 +1211,12 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
                 std::swap(cur, nxt);
             }
             if (staged < max_depth) {
-                auto kfin = pm.on ? k_finish_camera<true> : k_finish_camera<false>;
+                auto kfin = pm.on ? (c->count_visits ? k_finish_camera<true, true> : k_finish_camera<true, false>)
+                                  : (c->count_visits ? k_finish_camera<false, true> : k_finish_camera<false, false>);
+                uint32_t* work = next_work_slot(c);
+                Timed tm(c, c->cam_events);
                 hipLaunchKernelGGL(kfin, dim3(trace_grid(c, n)), dim3(kTraceBS), 0, st, S, ci, wd, P, cmap, pm, cur,
-                                   q.counts + (size_t)staged * QC_FRAME + QC_CUR, staged + 1, next_work_slot(c),
+                                   q.counts + (size_t)staged * QC_FRAME + QC_CUR, staged + 1, work,
                                    c->counters.as<DevCounters>());
             }
             hipLaunchKernelGGL(k_film_accumulate, dim3(grid_for(hw, bs)), dim3(bs), 0, st, ci, wd, P.L, P.lambda, ns,

@@ -207,8 +207,9 @@ def test_radiance_c1_own_maps(ctx):
 @pytest.mark.parametrize("spp,cap", [(3, None), (5, 4096)])
 def test_radiance_c2_small_spectral(ctx, spp, cap):
     """Spectral sampling, area light, texture, several objects; with a tiny
-    queue capacity the image is processed in many sample chunks and must
-    not change."""
+    queue capacity the image is processed in many sample chunks, and with a
+    tiny photon chunk the photon pass in many chunks, and neither output
+    may change."""
     c = _scene_c2_small()
     scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
     osc = oracle.OracleScene(scene)
@@ -217,13 +218,15 @@ def test_radiance_c2_small_spectral(ctx, spp, cap):
     o = oracle.render(osc, cam, spp, c["max_depth"], wl, c["render_seed"], caustic_map=om)
     if cap:
         ctx.set_option(3, cap)
+        ctx.set_option(7, cap)
     try:
         bvh = ctx.build_bvh(scene)
         r = ctx.trace_photons(bvh, n_ph, c["max_depth"], wl, c["photon_seed"], counts=True)
         _photon_cmp(r["map"].cpu().numpy(), r["count"].cpu().numpy(), msum, ocnt)
         g = ctx.render(bvh, cam, spp, c["max_depth"], wl, c["render_seed"], caustic_map=_t(om))
     finally:
-        ctx.set_option(3, 1 << 23)
+        ctx.set_option(3, 1 << 27)
+        ctx.set_option(7, 1 << 24)
     assert np.array_equal(_bits(g["rgb"].cpu().numpy()), _bits(o["rgb"]))
     _cmp_aov(g, o)
 
