@@ -270,12 +270,14 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
     (1024 spp, 2^22 photons) give the reference's noise floor (their relMSE,
     halved).  Accuracy is the mean relMSE over the scenes.
 
+    Both kinds of frame trace their photons on a second stream, which the
+    render overlaps up to its first diffuse shading (sc_render_overlap).
     Plain: photon pass + render; for each photon count in {2^16, 2^18,
     2^20, 2^22, 2^24} the smallest power-of-two spp from 4 whose mean
     relMSE meets the bar, then the cheapest of those.  Denoised: photon
     pass + render + U-Net (the committed trained weights), the
-    ground-truth buffers from a second context on a second stream
-    overlapping the photon pass; the 4-spp input at the smallest photon
+    ground-truth buffers traced on the second stream after the photons;
+    the 4-spp input at the smallest photon
     count in {2^16, 2^18, 2^20} that meets the bar is the headline, the
     cheapest input over spp in {1, 2, 4} is reported beside it.  Frame
     times are means over the scenes (HIP-synchronised wall clock)."""
@@ -294,27 +296,37 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
         ctx_gt = sc.Context(0)
     outs = {}
 
-    def denoised(bvh, cam, wl, md, spp, photons):
+    # Both kinds of frame trace their photons on a second context and
+    # stream while the render's ray generation and first traversal run; the
+    # render waits for the map only at its first diffuse shading.
+    def photons_on_side(bvh, wl, md, photons, key):
         e0 = torch.cuda.Event()
         e0.record(main)
-        side.wait_event(e0)            # the previous frame's U-Net has read the buffers
+        side.wait_event(e0)            # the previous frame has finished with the buffers
+        m = ctx_gt.trace_photons(bvh, photons, md, wl, 11, out=outs.get(key))["map"]
+        outs[key] = m
+        e_map = torch.cuda.Event()
+        e_map.record(side)
+        return m, e_map
+
+    def denoised(bvh, cam, wl, md, spp, photons):
+        m, e_map = photons_on_side(bvh, wl, md, photons, "m_d")
         g = ctx_gt.render(bvh, cam, 1, md, wl, 12, outputs=("albedo", "normal", "depthn", "trans"),
                           out=outs.get("g_d"))
         outs["g_d"] = g
-        e1 = torch.cuda.Event()
-        e1.record(side)
-        m = ctx.trace_photons(bvh, photons, md, wl, 11, out=outs.get("m_d"))["map"]
-        outs["m_d"] = m
-        r = ctx.render(bvh, cam, spp, md, wl, 12, caustic_map=m, outputs=("rgb",), out=outs.get("r_d"))
+        e_gt = torch.cuda.Event()
+        e_gt.record(side)
+        r = ctx.render(bvh, cam, spp, md, wl, 12, caustic_map=m, outputs=("rgb",), out=outs.get("r_d"),
+                       map_ready=e_map)
         outs["r_d"] = r
-        main.wait_event(e1)
+        main.wait_event(e_gt)
         outs["den"] = net.denoise(dict(g, rgb=r["rgb"]), out=outs.get("den"))
         return outs["den"]
 
     def plain(bvh, cam, wl, md, spp, photons):
-        m = ctx.trace_photons(bvh, photons, md, wl, 11, out=outs.get("m_p"))["map"]
-        outs["m_p"] = m
-        r = ctx.render(bvh, cam, spp, md, wl, 12, caustic_map=m, outputs=("rgb",), out=outs.get("r_p"))
+        m, e_map = photons_on_side(bvh, wl, md, photons, "m_p")
+        r = ctx.render(bvh, cam, spp, md, wl, 12, caustic_map=m, outputs=("rgb",), out=outs.get("r_p"),
+                       map_ready=e_map)
         outs["r_p"] = r
         return r["rgb"]
 

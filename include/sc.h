@@ -372,6 +372,19 @@ sc_status sc_render_pmap(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, u
 sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
                     const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, const sc_aov* out);
 
+/* sc_render gathering from a caustic map whose photon pass may still be
+ * running on another stream (another context's sc_trace_photons): the
+ * render's stream waits for map_ready (a hipEvent_t recorded on that
+ * stream after the pass) only before its first kernel that reads the map,
+ * the diffuse shading of the first bounce; camera ray generation, the
+ * ground-truth rays and the first traversal overlap the photon pass.  The
+ * output is that of sc_render with the finished map.  The event must be
+ * recorded before this call (stream order, as hipStreamWaitEvent).  EINVAL
+ * as sc_render, and on a NULL caustic_map or map_ready. */
+sc_status sc_render_overlap(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
+                            const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, void* map_ready,
+                            const sc_aov* out);
+
 /* ------------------------------------------------------------------
  * Ground-truth passes over sc_render's buffers (Sec. III-D).  Each is a
  * plain per-pixel definition; device arrays [h][w].

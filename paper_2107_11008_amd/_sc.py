@@ -151,7 +151,7 @@ PH_OUTCOMES = ("deposited", "outside", "direct", "elsewhere", "escaped", "absorb
 EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set_stream", "sc_set_option",
            "sc_sync", "sc_get_counters", "sc_reset_counters", "sc_build_bvh", "sc_bvh_rebuild", "sc_bvh_get_info",
            "sc_bvh_free", "sc_bvh_export",
-           "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render",
+           "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render", "sc_render_overlap",
            "sc_unet_create", "sc_unet_free", "sc_unet_num_params", "sc_unet_set_params", "sc_unet_get_params",
            "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise",
            "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch",
@@ -187,6 +187,8 @@ def load(path: str = LIB_PATH):
     L.sc_occluded.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
     L.sc_trace_photons.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, vp, vp, C.POINTER(PhotonStats)]
     L.sc_render.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, C.POINTER(Aov)]
+    L.sc_render_overlap.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, vp,
+                                    C.POINTER(Aov)]
     L.sc_pmap_trace.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, C.c_float, C.POINTER(vp),
                                 C.POINTER(PhotonStats)]
     L.sc_pmap_retrace.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, C.c_float, vp,
@@ -350,9 +352,14 @@ class Context:
     def render(self, bvh: "Bvh", cam, spp: int, max_depth: int, wl, seed: int,
                caustic_map: Optional[torch.Tensor] = None, outputs=("rgb", "obj", "trans", "tri", "depth", "depthn",
                                                                       "normal", "normal_cam", "albedo"),
-               out: Optional[dict] = None, pmap: Optional["PhotonMap"] = None):
+               out: Optional[dict] = None, pmap: Optional["PhotonMap"] = None,
+               map_ready: Optional[torch.cuda.Event] = None):
         """Render (sc_render); with pmap= the caustic gather comes from a
-        general photon map on every diffuse surface (sc_render_pmap)."""
+        general photon map on every diffuse surface (sc_render_pmap); with
+        map_ready= (an event recorded after the photon pass that writes
+        caustic_map, on another stream) the render overlaps that pass and
+        waits for the event only where it first reads the map
+        (sc_render_overlap)."""
         H, W = cam.h, cam.w
         shapes = dict(rgb=((H, W, 3), torch.float32), obj=((H, W), torch.int32), trans=((H, W), torch.uint8),
                       tri=((H, W), torch.int32), depth=((H, W), torch.float32), depthn=((H, W), torch.float32),
@@ -370,6 +377,10 @@ class Context:
         if pmap is not None:
             _check(load().sc_render_pmap(self.h, bvh.h, C.byref(cs), int(spp), int(max_depth), C.byref(w), int(seed),
                                          pmap.h, C.byref(a)), "sc_render_pmap")
+        elif map_ready is not None:
+            _check(load().sc_render_overlap(self.h, bvh.h, C.byref(cs), int(spp), int(max_depth), C.byref(w),
+                                            int(seed), _ptr(caustic_map), C.c_void_p(map_ready.cuda_event),
+                                            C.byref(a)), "sc_render_overlap")
         else:
             _check(load().sc_render(self.h, bvh.h, C.byref(cs), int(spp), int(max_depth), C.byref(w), int(seed),
                                     _ptr(caustic_map), C.byref(a)), "sc_render")

@@ -470,6 +470,22 @@ sc_status sc_render(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32
     return scl::render(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), *cam, spp, max_depth, *wl, seed, caustic_map, *out);
 }
 
+sc_status sc_render_overlap(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam, uint32_t spp, uint32_t max_depth,
+                            const sc_wavelengths* wl, uint64_t seed, const float* caustic_map, void* map_ready,
+                            const sc_aov* out) {
+    if (!ctx || !bvh || !cam || !out) return set_error(SC_EINVAL, "ctx, bvh, camera or out is NULL");
+    if (!caustic_map || !map_ready) return set_error(SC_EINVAL, "caustic_map or map_ready is NULL");
+    SC_TRY(check_built(bvh));
+    SC_TRY(check_wavelengths(wl));
+    if (spp == 0) return set_error(SC_EINVAL, "spp must be >= 1");
+    if (max_depth == 0) return set_error(SC_EINVAL, "max_depth must be >= 1");
+    if (cam->w == 0 || cam->h == 0) return set_error(SC_EINVAL, "camera has no pixels");
+    if ((uint64_t)cam->w * cam->h > (1ull << 28)) return set_error(SC_EUNSUPPORTED, "image too large");
+    if (!bvh->b.scene.recv_obj) return set_error(SC_EINVAL, "caustic map given but no receiver");
+    return scl::render(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), *cam, spp, max_depth, *wl, seed, caustic_map, *out,
+                       nullptr, static_cast<hipEvent_t>(map_ready));
+}
+
 sc_status sc_batch_create(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune* tune, sc_batch** out) {
     if (!ctx || !items || !out) return set_error(SC_EINVAL, "ctx, items or out is NULL");
     *out = nullptr;

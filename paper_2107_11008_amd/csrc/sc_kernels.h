@@ -29,8 +29,11 @@ struct ShadowSoA {
 namespace scl {
 
 // pmap: general photon map for the caustic gather, or null (receiver map cmap)
+// map_ready: an event the stream waits for before the first kernel that
+// reads cmap (the photon pass that writes it may run on another stream)
 sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t max_depth, const sc_wavelengths& wl,
-                 uint64_t seed, const float* cmap, const sc_aov& out, const PMapDev* pmap = nullptr);
+                 uint64_t seed, const float* cmap, const sc_aov& out, const PMapDev* pmap = nullptr,
+                 hipEvent_t map_ready = nullptr);
 // rec: records of a general photon map (deposits on every diffuse surface),
 // or null (receiver map)
 sc_status trace_photons(Ctx* c, Bvh* b, uint64_t n_photons, uint32_t max_depth, const sc_wavelengths& wl,

@@ -1148,7 +1148,7 @@ sc_status ctx_reset_counters(Ctx* c) {
 }
 
 sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t max_depth, const sc_wavelengths& wl,
-                 uint64_t seed, const float* cmap, const sc_aov& out, const PMapDev* pmap) {
+                 uint64_t seed, const float* cmap, const sc_aov& out, const PMapDev* pmap, hipEvent_t map_ready) {
     hipStream_t st = c->stream;
     PMapDev pm{};
     if (pmap) pm = *pmap;
@@ -1201,6 +1201,9 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
                                    q.dielectric, n);
                 hipLaunchKernelGGL(k_shade_dielectric, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, P, depth,
                                    q.dielectric, fc, nxt);
+                // the diffuse stage is the first reader of the caustic map;
+                // everything before it may overlap the pass that writes it
+                if (map_ready && s0 == 0 && depth == 1) SC_HIP(hipStreamWaitEvent(st, map_ready, 0));
                 if (pm.on)
                     hipLaunchKernelGGL(k_shade_diffuse<true>, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, wd, P,
                                        depth, cmap, pm, q.diffuse, fc, nxt, q.shadow);

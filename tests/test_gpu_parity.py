@@ -391,3 +391,34 @@ def test_second_context_renders_from_shared_bvh(ctx):
         a, b = ref[k].cpu().numpy(), g[k].cpu().numpy()
         assert a.tobytes() == b.tobytes(), k
     ctx2.close()
+
+
+def test_render_overlap_equals_render(ctx):
+    """sc_render_overlap with the photon pass on another context and stream
+    (the render waits for its event only at the first diffuse shading)
+    gives sc_render's output bit for bit, for every output."""
+    import paper_2107_11008_amd as sc
+    c = _scene_c2_small()
+    scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
+    bvh = ctx.build_bvh(scene)
+    ref_map = ctx.trace_photons(bvh, 1 << 15, c["max_depth"], wl, c["photon_seed"])["map"]
+    ref = ctx.render(bvh, cam, 3, c["max_depth"], wl, c["render_seed"], caustic_map=ref_map)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ctx2 = sc.Context(0)
+    main = torch.cuda.current_stream()
+    for rep in range(3):
+        e0 = torch.cuda.Event()
+        e0.record(main)
+        side.wait_event(e0)
+        m = ctx2.trace_photons(bvh, 1 << 15, c["max_depth"], wl, c["photon_seed"])["map"]
+        e_map = torch.cuda.Event()
+        e_map.record(side)
+        g = ctx.render(bvh, cam, 3, c["max_depth"], wl, c["render_seed"], caustic_map=m, map_ready=e_map)
+        torch.cuda.synchronize()
+        assert m.cpu().numpy().tobytes() == ref_map.cpu().numpy().tobytes()
+        for k in ref:
+            assert ref[k].cpu().numpy().tobytes() == g[k].cpu().numpy().tobytes(), k
+    with pytest.raises(sc.ScError):
+        ctx.render(bvh, cam, 1, c["max_depth"], wl, 1, caustic_map=None, map_ready=torch.cuda.Event())
+    ctx2.close()
