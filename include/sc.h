@@ -27,6 +27,10 @@
  *     must stay valid until the stream has passed the call (and, for the
  *     scene arrays, for the lifetime of the sc_bvh built from them).
  *     Arrays named "host" are read during the call only.
+ *   - Handles (sc_bvh, sc_pmap, sc_unet, sc_batch) may be freed before or
+ *     after the context they were made on.  After that context is destroyed
+ *     a BVH can still be rendered from by other contexts on its device;
+ *     calls that need the handle's own context fail with EINVAL.
  *   - All kernels run on the context's stream.  Calls return after
  *     enqueueing, except sc_build_bvh (sizes its allocations), calls that
  *     fill host statistics, and sc_sync/sc_get_counters.  Argument errors

@@ -96,6 +96,8 @@ sc_status sc_destroy(sc_ctx* ctx) {
     if (!ctx) return set_error(SC_EINVAL, "ctx is NULL");
     (void)hipStreamSynchronize(ctx->c.stream);
     scl::ctx_release(&ctx->c);
+    for (scl::Ctx** slot : ctx->c.handles) *slot = nullptr;   // handles outlive their context safely
+    ctx->c.handles.clear();
     delete ctx;
     return SC_OK;
 }
@@ -198,7 +200,7 @@ sc_status check_scene(const sc_scene* sc) {
 // Device buffers of b are reused when large enough.
 sc_status build_into(scl::Ctx* c, scl::Bvh* b, const sc_scene* sc, uint32_t width, uint32_t leaf_max) {
     hipStream_t st = c->stream;
-    b->ctx = c;
+    scl::attach(c, &b->ctx);
     b->scene_in = *sc;
     b->scene = DevScene{};
     std::vector<float> tg(4 * (size_t)sc->n_tg);
@@ -327,6 +329,7 @@ sc_status sc_bvh_get_info(const sc_bvh* bvh, sc_bvh_info* out) {
 sc_status sc_bvh_export(const sc_bvh* bvh, void* nodes_host, void* tris_host) {
     if (!bvh) return set_error(SC_EINVAL, "bvh is NULL");
     const scl::Bvh& b = bvh->b;
+    if (!b.ctx) return set_error(SC_EINVAL, "the bvh's context was destroyed");
     SC_HIP(hipStreamSynchronize(b.ctx->stream));
     if (nodes_host) SC_HIP(hipMemcpy(nodes_host, b.nodes.p, sizeof(BNode) * (size_t)b.n_nodes, hipMemcpyDeviceToHost));
     if (tris_host) SC_HIP(hipMemcpy(tris_host, b.tris.p, 48 * (size_t)b.scene.nt, hipMemcpyDeviceToHost));
@@ -335,7 +338,8 @@ sc_status sc_bvh_export(const sc_bvh* bvh, void* nodes_host, void* tris_host) {
 
 sc_status sc_bvh_free(sc_bvh* bvh) {
     if (!bvh) return set_error(SC_EINVAL, "bvh is NULL");
-    (void)hipStreamSynchronize(bvh->b.ctx->stream);
+    if (bvh->b.ctx) (void)hipStreamSynchronize(bvh->b.ctx->stream);
+    scl::detach(&bvh->b.ctx);
     delete bvh;
     return SC_OK;
 }
@@ -435,6 +439,7 @@ sc_status sc_pmap_gather(sc_ctx* ctx, const sc_pmap* pm, uint32_t n, const float
 sc_status sc_pmap_free(sc_pmap* pm) {
     if (pm) {
         if (pm->p.ctx) (void)hipStreamSynchronize(pm->p.ctx->stream);
+        scl::detach(&pm->p.ctx);
         delete pm;
     }
     return SC_OK;
@@ -528,7 +533,8 @@ sc_status sc_batch_run(sc_ctx* ctx, sc_batch* batch) {
 
 sc_status sc_batch_free(sc_batch* batch) {
     if (!batch) return set_error(SC_EINVAL, "batch is NULL");
-    (void)hipStreamSynchronize(batch->bt.ctx->stream);
+    if (batch->bt.ctx) (void)hipStreamSynchronize(batch->bt.ctx->stream);
+    scl::detach(&batch->bt.ctx);
     delete batch;
     return SC_OK;
 }
@@ -559,7 +565,8 @@ sc_status sc_unet_create(sc_ctx* ctx, const uint32_t* widths, uint32_t levels, s
 
 sc_status sc_unet_free(sc_unet* net) {
     if (!net) return set_error(SC_EINVAL, "net is NULL");
-    (void)hipStreamSynchronize(net->u.ctx->stream);
+    if (net->u.ctx) (void)hipStreamSynchronize(net->u.ctx->stream);
+    scl::detach(&net->u.ctx);
     delete net;
     return SC_OK;
 }
@@ -573,6 +580,7 @@ sc_status sc_unet_num_params(const sc_unet* net, uint64_t* n) {
 sc_status sc_unet_set_params(sc_unet* net, const float* host) {
     if (!net || !host) return set_error(SC_EINVAL, "net or params is NULL");
     scl::Unet& u = net->u;
+    if (!u.ctx) return set_error(SC_EINVAL, "the network's context was destroyed");
     SC_HIP(hipStreamSynchronize(u.ctx->stream));
     SC_HIP(hipMemcpy(u.theta.p, host, 4 * u.n_params, hipMemcpyHostToDevice));
     SC_HIP(hipMemset(u.m.p, 0, 4 * u.n_params));
@@ -585,6 +593,7 @@ sc_status sc_unet_set_params(sc_unet* net, const float* host) {
 
 sc_status sc_unet_get_params(sc_unet* net, float* host) {
     if (!net || !host) return set_error(SC_EINVAL, "net or params is NULL");
+    if (!net->u.ctx) return set_error(SC_EINVAL, "the network's context was destroyed");
     SC_HIP(hipStreamSynchronize(net->u.ctx->stream));
     SC_HIP(hipMemcpy(host, net->u.theta.p, 4 * net->u.n_params, hipMemcpyDeviceToHost));
     return SC_OK;
@@ -601,6 +610,7 @@ static sc_status check_shape(const scl::Unet& u, uint32_t n, uint32_t w, uint32_
 sc_status sc_unet_forward(sc_ctx* ctx, sc_unet* net, const float* feat, uint32_t n, uint32_t w, uint32_t h,
                           float* pred) {
     if (!ctx || !net || !feat || !pred) return set_error(SC_EINVAL, "NULL argument");
+    if (!net->u.ctx) return set_error(SC_EINVAL, "the network's context was destroyed");
     scl::Unet& u = net->u;
     SC_TRY(check_shape(u, n, w, h));
     SC_TRY(scl::unet_prepare(&u, n, h, w));
@@ -612,6 +622,7 @@ sc_status sc_unet_forward(sc_ctx* ctx, sc_unet* net, const float* feat, uint32_t
 
 sc_status sc_unet_backward(sc_ctx* ctx, sc_unet* net, const float* dpred, float* grad) {
     if (!ctx || !net || !dpred || !grad) return set_error(SC_EINVAL, "NULL argument");
+    if (!net->u.ctx) return set_error(SC_EINVAL, "the network's context was destroyed");
     scl::Unet& u = net->u;
     if (!u.acts.p || !u.cat_valid) return set_error(SC_EINVAL, "sc_unet_backward needs a preceding sc_unet_forward");
     SC_TRY(scl::unet_pack_dpred(&u, dpred));
@@ -623,6 +634,7 @@ sc_status sc_unet_backward(sc_ctx* ctx, sc_unet* net, const float* dpred, float*
 sc_status sc_unet_train_step(sc_ctx* ctx, sc_unet* net, const float* feat, const float* target, uint32_t n,
                              uint32_t w, uint32_t h, float lr, float* loss) {
     if (!ctx || !net || !feat || !target) return set_error(SC_EINVAL, "NULL argument");
+    if (!net->u.ctx) return set_error(SC_EINVAL, "the network's context was destroyed");
     if (!(lr > 0.0f)) return set_error(SC_EINVAL, "lr must be > 0");
     scl::Unet& u = net->u;
     SC_TRY(check_shape(u, n, w, h));
@@ -643,6 +655,7 @@ sc_status sc_unet_train_step(sc_ctx* ctx, sc_unet* net, const float* feat, const
 
 sc_status sc_denoise(sc_ctx* ctx, sc_unet* net, const sc_aov* in, uint32_t w, uint32_t h, float* out_rgb) {
     if (!ctx || !net || !in || !in->rgb || !out_rgb) return set_error(SC_EINVAL, "NULL argument");
+    if (!net->u.ctx) return set_error(SC_EINVAL, "the network's context was destroyed");
     if (w == 0 || h == 0) return set_error(SC_EINVAL, "empty image");
     scl::Unet& u = net->u;
     const uint32_t m = 1u << (u.widths.size() - 1);

@@ -186,7 +186,7 @@ void launch_all(hipStream_t st, const BatchScene* dB, uint32_t n, uint32_t ph_it
 namespace scl {
 
 sc_status batch_create(Ctx* c, uint32_t n, const sc_batch_item* items, const sc_tune& tune, Batch* bt) {
-    bt->ctx = c;
+    scl::attach(c, &bt->ctx);
     bt->tune = tune;
     bt->n = n;
     std::vector<BatchScene> hs(n);

@@ -252,7 +252,7 @@ sc_status pmap_trace(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc_wa
     SC_HIP(hipGetLastError());
     SC_HIP(hipStreamSynchronize(st));
 
-    pm->ctx = c;
+    attach(c, &pm->ctx);
     pm->n = n;
     pm->radius = radius;
     pm->channels = channels;

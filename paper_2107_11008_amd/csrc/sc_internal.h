@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <set>
 #include <string>
 #include <utility>
 #include <vector>
@@ -128,7 +129,23 @@ struct Ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> cam_events;   // camera path finishing launches, not yet read
     double cam_ms = 0.0;
     uint64_t cam_launches = 0;
+    // the context pointers of the handles (BVH, photon map, U-Net, batch)
+    // made on this context: cleared when it is destroyed, so a handle freed
+    // after its context does not touch it
+    std::set<Ctx**> handles;
 };
+
+// record that the handle whose context pointer is *slot belongs to c
+inline void attach(Ctx* c, Ctx** slot) {
+    if (*slot && *slot != c) (*slot)->handles.erase(slot);
+    *slot = c;
+    if (c) c->handles.insert(slot);
+}
+// the handle is being freed: its context forgets it
+inline void detach(Ctx** slot) {
+    if (*slot) (*slot)->handles.erase(slot);
+    *slot = nullptr;
+}
 
 struct Bvh {
     Ctx* ctx = nullptr;

@@ -764,7 +764,7 @@ uint32_t round_up(uint32_t v, uint32_t m) { return (v + m - 1) / m * m; }
 
 sc_status unet_create(Ctx* c, const uint32_t* widths, uint32_t levels, Unet* u) {
     if (levels < 2 || levels > 6) return set_error(SC_EINVAL, "levels must be 2..6");
-    u->ctx = c;
+    attach(c, &u->ctx);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
         u->cus = (uint32_t)cus;

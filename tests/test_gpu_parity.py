@@ -422,3 +422,30 @@ def test_render_overlap_equals_render(ctx):
     with pytest.raises(sc.ScError):
         ctx.render(bvh, cam, 1, c["max_depth"], wl, 1, caustic_map=None, map_ready=torch.cuda.Event())
     ctx2.close()
+
+
+def test_handles_outlive_their_context(ctx):
+    """Handles made on a context that is destroyed first: the BVH still
+    renders from another context (bit for bit as before), the network's
+    calls fail with an error instead of touching the freed context, and
+    freeing both afterwards is safe."""
+    import paper_2107_11008_amd as sc
+    c = sg.config1()
+    scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
+    ctx2 = sc.Context(0)
+    bvh = ctx2.build_bvh(scene)
+    keys = ("obj", "tri", "depth")
+    ref = ctx2.render(bvh, cam, 1, c["max_depth"], wl, 3, outputs=keys)
+    ref = {k: v.cpu().numpy().copy() for k, v in ref.items()}
+    net = sc.UNet(ctx2, (16, 16), None)
+    torch.cuda.synchronize()
+    ctx2.close()
+    g = ctx.render(bvh, cam, 1, c["max_depth"], wl, 3, outputs=keys)
+    for k in keys:
+        assert g[k].cpu().numpy().tobytes() == ref[k].tobytes(), k
+    with pytest.raises(sc.ScError):
+        net.get_params()
+    with pytest.raises(sc.ScError):
+        bvh.export()
+    net.close()
+    bvh.close()
