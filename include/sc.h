@@ -295,6 +295,19 @@ sc_status sc_bvh_export(const sc_bvh* bvh, void* nodes_host, void* tris_host);
  * vertices 1 and 2 (u, v may be NULL). */
 sc_status sc_trace_rays(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D,
                         float* t, uint32_t* prim, float* u, float* v);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * closest hits of sc_trace_rays, bit for bit, without any allocation by
+ * the library.  The rays are staged in a fixed array of device memory that
+ * the library holds on every GPU it runs on until the process ends
+ * (6 x 4 MiB: at most sc_trace_rays_noalloc_max() = 2^20 rays per call;
+ * more is EINVAL, reported before anything is enqueued).  Every call on a
+ * GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams, other contexts, other threads) race; calls in stream order on
+ * one stream do not.  Arguments and outputs as sc_trace_rays. */
+sc_status sc_trace_rays_noalloc(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D,
+                                float* t, uint32_t* prim, float* u, float* v);
+uint32_t sc_trace_rays_noalloc_max(void);
 /* Any hit with 0 < t < tmax[i], ignoring triangle excl[i] (excl may be
  * NULL); occluded[i] = 0/1.  All device arrays. */
 sc_status sc_occluded(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D,

@@ -151,7 +151,8 @@ PH_OUTCOMES = ("deposited", "outside", "direct", "elsewhere", "escaped", "absorb
 EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set_stream", "sc_set_option",
            "sc_sync", "sc_get_counters", "sc_reset_counters", "sc_build_bvh", "sc_bvh_rebuild", "sc_bvh_get_info",
            "sc_bvh_free", "sc_bvh_export",
-           "sc_trace_rays", "sc_occluded", "sc_trace_photons", "sc_render", "sc_render_overlap",
+           "sc_trace_rays", "sc_trace_rays_noalloc", "sc_trace_rays_noalloc_max", "sc_occluded", "sc_trace_photons",
+           "sc_render", "sc_render_overlap",
            "sc_unet_create", "sc_unet_free", "sc_unet_num_params", "sc_unet_set_params", "sc_unet_get_params",
            "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise",
            "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch",
@@ -185,6 +186,8 @@ def load(path: str = LIB_PATH):
     L.sc_bvh_export.argtypes = [vp, vp, vp]
     L.sc_trace_rays.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp]
     L.sc_occluded.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp]
+    L.sc_trace_rays_noalloc.argtypes = [vp, vp, u32, vp, vp, vp, vp, vp, vp]
+    L.sc_trace_rays_noalloc_max.restype = u32
     L.sc_trace_photons.argtypes = [vp, vp, u64, u32, C.POINTER(Wavelengths), u64, vp, vp, C.POINTER(PhotonStats)]
     L.sc_render.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, C.POINTER(Aov)]
     L.sc_render_overlap.argtypes = [vp, vp, C.POINTER(Camera), u32, u32, C.POINTER(Wavelengths), u64, vp, vp,
@@ -216,7 +219,7 @@ def load(path: str = LIB_PATH):
     L.sc_denoise.argtypes = [vp, vp, C.POINTER(Aov), u32, u32, vp]
     for name in EXPORTS:
         fn = getattr(L, name)
-        if name not in ("sc_abi_version", "sc_last_error"):
+        if name not in ("sc_abi_version", "sc_last_error", "sc_trace_rays_noalloc_max"):
             fn.restype = i32
     if L.sc_abi_version() != ABI_VERSION:
         raise ScError(f"{path} has ABI version {L.sc_abi_version()}, the binding expects {ABI_VERSION}: rebuild it")
@@ -322,6 +325,14 @@ class Context:
         _check(load().sc_trace_rays(self.h, bvh.h, n, _ptr(O), _ptr(D), _ptr(t), _ptr(prim), _ptr(u), _ptr(v)),
                "sc_trace_rays")
         return t, prim, u, v
+
+    def trace_rays_noalloc(self, bvh: "Bvh", O: torch.Tensor, D: torch.Tensor, t: torch.Tensor,
+                           prim: torch.Tensor, u: Optional[torch.Tensor] = None, v: Optional[torch.Tensor] = None):
+        """sc_trace_rays_noalloc: closest hits into caller-given outputs,
+        with no device allocation by the library (at most
+        sc_trace_rays_noalloc_max() rays)."""
+        _check(load().sc_trace_rays_noalloc(self.h, bvh.h, O.shape[0], _ptr(O), _ptr(D), _ptr(t), _ptr(prim),
+                                            _ptr(u), _ptr(v)), "sc_trace_rays_noalloc")
 
     def occluded(self, bvh: "Bvh", O, D, tmax, excl=None):
         n = O.shape[0]

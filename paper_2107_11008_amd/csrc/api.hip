@@ -84,6 +84,7 @@ sc_status sc_create(int device, void* hip_stream, sc_ctx** out) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         x->c.cus = (uint32_t)cus;
     sc_status s = scl::ctx_init(&x->c);
+    if (s == SC_OK) s = scl::scratch_init(device);   // the allocation-free entry point's array on this device
     if (s != SC_OK) {
         delete x;
         return s;
@@ -352,6 +353,17 @@ sc_status sc_trace_rays(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float*
     if (!O || !D || !t || !prim) return set_error(SC_EINVAL, "O, D, t and prim are required");
     return scl::trace_rays(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n, O, D, t, prim, u, v);
 }
+
+sc_status sc_trace_rays_noalloc(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D, float* t,
+                                uint32_t* prim, float* u, float* v) {
+    if (!ctx || !bvh) return set_error(SC_EINVAL, "ctx or bvh is NULL");
+    SC_TRY(check_built(bvh));
+    if (n == 0) return SC_OK;
+    if (!O || !D || !t || !prim) return set_error(SC_EINVAL, "O, D, t and prim are required");
+    return scl::trace_rays_noalloc(&ctx->c, const_cast<scl::Bvh*>(&bvh->b), n, O, D, t, prim, u, v);
+}
+
+uint32_t sc_trace_rays_noalloc_max(void) { return scl::trace_rays_noalloc_max(); }
 
 sc_status sc_occluded(sc_ctx* ctx, const sc_bvh* bvh, uint32_t n, const float* O, const float* D, const float* tmax,
                       const uint32_t* excl, uint8_t* occ) {

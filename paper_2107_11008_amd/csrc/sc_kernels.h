@@ -39,6 +39,11 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
 sc_status trace_photons(Ctx* c, Bvh* b, uint64_t n_photons, uint32_t max_depth, const sc_wavelengths& wl,
                         uint64_t seed, float* map, uint32_t* count_map, sc_photon_stats* stats,
                         const PmRecords* rec = nullptr);
+// allocation-free closest hit: rays staged in a fixed per-device array
+sc_status scratch_init(int device);
+uint32_t trace_rays_noalloc_max();
+sc_status trace_rays_noalloc(Ctx* c, Bvh* b, uint32_t n, const float* O, const float* D, float* t, uint32_t* prim,
+                             float* u, float* v);
 sc_status pmap_trace(Ctx* c, Bvh* b, uint64_t n_photons, uint32_t max_depth, const sc_wavelengths& wl, uint64_t seed,
                      float radius, Pmap* pm, sc_photon_stats* stats);
 sc_status pmap_export(const Pmap* pm, float* pos, float* nrm, float* phi, uint32_t* channel, uint64_t* photon);

@@ -15,6 +15,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <string>
+
 #include "sc_device.h"
 #include "sc_internal.h"
 #include "sc_kernels.h"
@@ -1377,6 +1380,65 @@ sc_status trace_rays(Ctx* c, Bvh* b, uint32_t n, const float* O, const float* D,
                        RaySoA{ox, oy, oz, dx, dy, dz}, nullptr, nullptr, none);
     reset_work(c);
     launch_closest(c, b->scene, R, HitSoA{t, prim, u, v}, nullptr, nullptr, n, n);
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+// ------------------------------------------------------------------
+// Closest hit without allocation.  The rays are staged into a fixed,
+// file-scope device array (one copy per GPU, held until the process
+// ends) instead of the context's grow-only buffer; the traversal kernel is
+// k_closest, as in trace_rays.  Host code uses the array only through the
+// address hipGetSymbolAddress returns on each device.
+constexpr uint32_t kNoAllocMaxRays = 1u << 20;
+constexpr size_t kNoAllocArray = (size_t)kNoAllocMaxRays * 4 + 256;   // one SoA array, 256-byte aligned
+constexpr int kNoAllocMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[6 * kNoAllocArray];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// With `device` current: look up this device's copy of the array (once).
+sc_status scratch_init(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kNoAllocMaxDevices) return set_error(SC_EUNSUPPORTED, "device index beyond 63");
+    if (g_scratch_ptr[device]) return SC_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return set_error(SC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = p;
+    return SC_OK;
+}
+
+uint32_t trace_rays_noalloc_max() { return kNoAllocMaxRays; }
+
+sc_status trace_rays_noalloc(Ctx* c, Bvh* b, uint32_t n, const float* O, const float* D, float* t, uint32_t* prim,
+                             float* u, float* v) {
+    if (n > kNoAllocMaxRays)
+        return set_error(SC_EINVAL, "n = " + std::to_string(n) + " rays exceeds the allocation-free maximum of " +
+                                        std::to_string(kNoAllocMaxRays));
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (c->device >= 0 && c->device < kNoAllocMaxDevices) base = g_scratch_ptr[c->device];
+    }
+    if (!base) return set_error(SC_EDEVICE, "no scratch address for the context's device");
+    Carver cv{static_cast<char*>(base)};
+    float* ox = cv.take<float>(kNoAllocMaxRays); float* oy = cv.take<float>(kNoAllocMaxRays);
+    float* oz = cv.take<float>(kNoAllocMaxRays); float* dx = cv.take<float>(kNoAllocMaxRays);
+    float* dy = cv.take<float>(kNoAllocMaxRays); float* dz = cv.take<float>(kNoAllocMaxRays);
+    const RaySoA R{ox, oy, oz, dx, dy, dz};
+    const ShadowSoA none{};
+    // every staged entry [0, n) is written before it is read; nothing in the
+    // array has to start at zero
+    hipLaunchKernelGGL(k_rays_from_aos, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, O, D, n, R, nullptr, nullptr,
+                       none);
+    reset_work(c);
+    uint32_t* work = next_work_slot(c);
+    hipLaunchKernelGGL(k_closest<false>, dim3(trace_grid(c, n)), dim3(kTraceBS), 0, c->stream, b->scene, R,
+                       HitSoA{t, prim, u, v}, nullptr, nullptr, n, work, c->counters.as<DevCounters>());
     SC_HIP(hipGetLastError());
     return SC_OK;
 }
