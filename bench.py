@@ -426,7 +426,8 @@ def batch_compare(ctx):
     cfgs = [sg.config4_item(j) for j in range(64)]
     best = A.autotune(ctx, cfgs)
     res = A.compare(ctx, cfgs, best)
-    res["tuning"] = {k: best[k] for k in ("width", "block_size", "blocks_per_cu", "px_per_item")}
+    res["tuning"] = {k: best[k] for k in ("width", "block_size", "blocks_per_cu", "px_per_item", "ph_per_item",
+                                          "tuning_s", "cached") if k in best}
     return res
 
 

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SC_ABI_VERSION 5u
+#define SC_ABI_VERSION 6u
 
 typedef int32_t sc_status;
 #define SC_OK 0
@@ -58,6 +58,7 @@ typedef int32_t sc_status;
 #define SC_ENOMEM (-2)        /* device allocation failed */
 #define SC_EDEVICE (-3)       /* HIP runtime error */
 #define SC_EUNSUPPORTED (-4)  /* valid but unsupported request */
+#define SC_EABORTED (-5)      /* a multi-step operation stopped at a failed step; outputs unchanged */
 
 typedef struct sc_ctx sc_ctx;
 typedef struct sc_bvh sc_bvh;
@@ -453,18 +454,37 @@ typedef struct {
 typedef struct {
     uint32_t block_size;      /* threads per block: 64, 128 or 256 */
     uint32_t blocks_per_cu;   /* persistent blocks per compute unit, 1..32 */
-    uint32_t px_per_item;     /* pixels or photons per work item: a multiple of 64, <= 4096 */
+    uint32_t px_per_item;     /* pixels per work item (the tile a wave takes): a multiple of 64, <= 4096 */
     uint32_t use_graph;       /* 1: capture in a hipGraph at creation, replay at every run */
+    uint32_t ph_per_item;     /* photons per work item (the grain a wave takes from the photon queue): a
+                                 multiple of 64, <= 65536; 0 = px_per_item */
+    uint32_t bvh_width;       /* sc_autotune's choice of BVH width (4 or 8) for the items' trees;
+                                 sc_batch_create ignores it (the trees are built by the caller) */
 } sc_tune;
 
 /* Prepare a batch (the items' device buffers must outlive it).  tune NULL
- * = {128, 8, 64, 1}.  EINVAL on an invalid item or tuning value. */
+ * = {128, 8, 64, 1, 0, 8}.  EINVAL on an invalid item or tuning value. */
 sc_status sc_batch_create(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune* tune, sc_batch** out);
 /* Run every photon pass and render of the batch (one graph launch). */
 sc_status sc_batch_run(sc_ctx* ctx, sc_batch* batch);
 sc_status sc_batch_free(sc_batch* batch);
 /* create + run + free; synchronises. */
 sc_status sc_render_batch(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune* tune);
+/* Autotuner of the batched form (the many-scene capture of Sec. IV-A-2):
+ * chooses the persistent grid (block_size, blocks_per_cu), the pixel tile
+ * (px_per_item), the photon queue grain (ph_per_item) and the BVH width
+ * for this batch by timing candidates with HIP events on reduced copies
+ * of it (1 sample per pixel, 1/8 of the photons, the items' own output
+ * buffers, which hold unspecified values afterwards), one dimension at a
+ * time from {128, 8, 64, 1, 256, 8}: the grid over {64, 128, 256} x {2, 4,
+ * 8}, then the tile over {64, 128, 256, 512}, the grain over {64, 256,
+ * 1024, 4096}, then width 4 (trees rebuilt from the items' scenes) against
+ * the items' own trees.  No choice changes any output: the batch is the
+ * one-scene result bit for bit for every setting.  out receives the
+ * fastest setting (use_graph = 1).  Synchronises.  EINVAL on invalid
+ * items (as sc_batch_create); SC_EABORTED when a candidate's run fails
+ * (sc_last_error names it; out is left unchanged). */
+sc_status sc_autotune(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, sc_tune* out);
 
 /* ------------------------------------------------------------------
  * Learned denoiser.  A U-Net (the network family the paper trains for
@@ -506,6 +526,13 @@ sc_status sc_unet_backward(sc_ctx* ctx, sc_unet* net, const float* dpred, float*
  * the call does not synchronise) receives the loss before the update. */
 sc_status sc_unet_train_step(sc_ctx* ctx, sc_unet* net, const float* feat, const float* target, uint32_t n,
                              uint32_t w, uint32_t h, float lr, float* loss);
+/* The network's input features of a w x h render (the buffers of
+ * sc_render: in->rgb required, albedo, normal, depthn, trans may be NULL
+ * = 0): device feat [h][w][9] f32 = log(1 + max(rgb, 0)) x3, albedo,
+ * normal x3, depthn, trans.  The same per-pixel function builds the
+ * denoiser's input inside sc_denoise, so training pairs made with it see
+ * exactly the inference features. */
+sc_status sc_unet_features(sc_ctx* ctx, const sc_aov* in, uint32_t w, uint32_t h, float* feat);
 /* Denoise a render: in->rgb, albedo, normal, depthn, trans (device, as
  * written by sc_render; albedo/normal/depthn/trans may be NULL) of size
  * w x h -> device out_rgb [h][w][3] linear rgb.  Any w, h (padded inside). */

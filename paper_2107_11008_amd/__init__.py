@@ -6,6 +6,6 @@ refraction, dispersion and caustics, depth, normals and the object mask,
 plus the photon caustic map.  ``Context`` / ``Bvh`` in ``_sc`` are the thin
 Python binding (argument marshalling only).
 """
-from ._sc import Batch, Bvh, Context, PhotonMap, ScError, UNet, load  # noqa: F401
+from ._sc import Batch, Bvh, Context, PhotonMap, ScError, UNet, autotune_batch, load  # noqa: F401
 
-__all__ = ["Context", "Bvh", "Batch", "PhotonMap", "UNet", "ScError", "load"]
+__all__ = ["Context", "Bvh", "Batch", "PhotonMap", "UNet", "ScError", "autotune_batch", "load"]

@@ -47,7 +47,7 @@ SC_OPT_PHOTON_STAGED_DEPTH = 6
 SC_OPT_PHOTON_CAP = 7
 
 
-ABI_VERSION = 5   # must match SC_ABI_VERSION in include/sc.h
+ABI_VERSION = 6   # must match SC_ABI_VERSION in include/sc.h
 
 
 class ScError(RuntimeError):
@@ -106,7 +106,7 @@ class BatchItem(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("block_size", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("px_per_item", C.c_uint32),
-                ("use_graph", C.c_uint32)]
+                ("use_graph", C.c_uint32), ("ph_per_item", C.c_uint32), ("bvh_width", C.c_uint32)]
 
 
 class PhotonStats(C.Structure):
@@ -154,8 +154,8 @@ EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set
            "sc_trace_rays", "sc_trace_rays_noalloc", "sc_trace_rays_noalloc_max", "sc_occluded", "sc_trace_photons",
            "sc_render", "sc_render_overlap",
            "sc_unet_create", "sc_unet_free", "sc_unet_num_params", "sc_unet_set_params", "sc_unet_get_params",
-           "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_denoise",
-           "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch",
+           "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_unet_features", "sc_denoise",
+           "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch", "sc_autotune",
            "sc_caustic_mask", "sc_outline", "sc_occlusion_boundary",
            "sc_pmap_trace", "sc_pmap_retrace", "sc_pmap_get_info", "sc_pmap_export", "sc_pmap_gather",
            "sc_pmap_free", "sc_render_pmap"]
@@ -208,6 +208,7 @@ def load(path: str = LIB_PATH):
     L.sc_batch_run.argtypes = [vp, vp]
     L.sc_batch_free.argtypes = [vp]
     L.sc_render_batch.argtypes = [vp, u32, vp, C.POINTER(Tune)]
+    L.sc_autotune.argtypes = [vp, u32, vp, C.POINTER(Tune)]
     L.sc_unet_create.argtypes = [vp, vp, u32, C.POINTER(vp)]
     L.sc_unet_free.argtypes = [vp]
     L.sc_unet_num_params.argtypes = [vp, C.POINTER(u64)]
@@ -217,6 +218,7 @@ def load(path: str = LIB_PATH):
     L.sc_unet_backward.argtypes = [vp, vp, vp, vp]
     L.sc_unet_train_step.argtypes = [vp, vp, vp, vp, u32, u32, u32, C.c_float, C.POINTER(C.c_float)]
     L.sc_denoise.argtypes = [vp, vp, C.POINTER(Aov), u32, u32, vp]
+    L.sc_unet_features.argtypes = [vp, C.POINTER(Aov), u32, u32, vp]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("sc_abi_version", "sc_last_error", "sc_trace_rays_noalloc_max"):
@@ -325,6 +327,18 @@ class Context:
         _check(load().sc_trace_rays(self.h, bvh.h, n, _ptr(O), _ptr(D), _ptr(t), _ptr(prim), _ptr(u), _ptr(v)),
                "sc_trace_rays")
         return t, prim, u, v
+
+    def unet_features(self, aov: dict, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The denoiser's input features [h][w][9] of a render's buffers
+        (sc_unet_features): the same function sc_denoise applies."""
+        h, w = aov["rgb"].shape[:2]
+        a = Aov()
+        for k in ("rgb", "albedo", "normal", "depthn", "trans"):
+            if k in aov and aov[k] is not None:
+                setattr(a, k, _ptr(aov[k]))
+        o = out if out is not None else torch.empty((h, w, 9), dtype=torch.float32, device=self.device)
+        _check(load().sc_unet_features(self.h, C.byref(a), w, h, _ptr(o)), "sc_unet_features")
+        return o
 
     def trace_rays_noalloc(self, bvh: "Bvh", O: torch.Tensor, D: torch.Tensor, t: torch.Tensor,
                            prim: torch.Tensor, u: Optional[torch.Tensor] = None, v: Optional[torch.Tensor] = None):
@@ -664,6 +678,43 @@ class UNet:
 _gt_methods()
 
 
+def _batch_items(ctx: "Context", items, outs_keep: list):
+    """The sc_batch_item array for a list of item dicts (see Batch), with
+    output tensors allocated here and appended to outs_keep."""
+    arr = (BatchItem * len(items))()
+    for i, it in enumerate(items):
+        a = arr[i]
+        a.bvh = it["bvh"].h
+        a.cam = camera_struct(it["cam"])
+        a.spp, a.max_depth = int(it["spp"]), int(it["max_depth"])
+        a.wl = wavelengths_struct(it["wl"])
+        a.seed, a.photon_seed, a.n_photons = int(it["seed"]), int(it.get("photon_seed", 0)), int(it.get("n_photons", 0))
+        cm = it.get("caustic_map")
+        if cm is None and a.n_photons:
+            r = it["bvh"].scene.receiver
+            cm = torch.empty((r.hc, r.wc, it["wl"].channels), dtype=torch.float32, device=ctx.device)
+        a.caustic_map = _ptr(cm)
+        H, W = it["cam"].h, it["cam"].w
+        outs = {"caustic_map": cm}
+        for k in it.get("outputs", ("rgb", "obj", "trans", "tri", "depth", "depthn", "normal", "normal_cam",
+                                    "albedo")):
+            c, dt = Batch._SHAPES[k]
+            outs[k] = torch.empty((H, W) if c is None else (H, W, c), dtype=dt, device=ctx.device)
+            setattr(a.out, k, _ptr(outs[k]))
+        outs_keep.append(outs)
+    return arr
+
+
+def autotune_batch(ctx: "Context", items) -> dict:
+    """sc_autotune: the fastest batch setting for these items (their output
+    buffers, allocated here, are scratch)."""
+    keep = []
+    arr = _batch_items(ctx, items, keep)
+    t = Tune()
+    _check(load().sc_autotune(ctx.h, len(items), C.cast(arr, C.c_void_p), C.byref(t)), "sc_autotune")
+    return {k: getattr(t, k) for k, _ in Tune._fields_}
+
+
 class Batch:
     """Many scenes rendered by the persistent, graph-captured batch kernels.
 
@@ -679,34 +730,14 @@ class Batch:
     def __init__(self, ctx: Context, items, tune: Optional[dict] = None):
         self.ctx = ctx
         self.items = items
-        arr = (BatchItem * len(items))()
         self._outs = []
         self._keep = []
-        for i, it in enumerate(items):
-            a = arr[i]
-            a.bvh = it["bvh"].h
-            a.cam = camera_struct(it["cam"])
-            a.spp, a.max_depth = int(it["spp"]), int(it["max_depth"])
-            a.wl = wavelengths_struct(it["wl"])
-            a.seed, a.photon_seed, a.n_photons = int(it["seed"]), int(it.get("photon_seed", 0)), int(it.get("n_photons", 0))
-            cm = it.get("caustic_map")
-            if cm is None and a.n_photons:
-                r = it["bvh"].scene.receiver
-                cm = torch.empty((r.hc, r.wc, it["wl"].channels), dtype=torch.float32, device=ctx.device)
-            a.caustic_map = _ptr(cm)
-            H, W = it["cam"].h, it["cam"].w
-            outs = {"caustic_map": cm}
-            for k in it.get("outputs", ("rgb", "obj", "trans", "tri", "depth", "depthn", "normal", "normal_cam",
-                                        "albedo")):
-                c, dt = self._SHAPES[k]
-                outs[k] = torch.empty((H, W) if c is None else (H, W, c), dtype=dt, device=ctx.device)
-                setattr(a.out, k, _ptr(outs[k]))
-            self._outs.append(outs)
+        arr = _batch_items(ctx, items, self._outs)
         self._arr = arr
         t = None
         if tune is not None:
             t = Tune(int(tune["block_size"]), int(tune["blocks_per_cu"]), int(tune["px_per_item"]),
-                     int(tune.get("use_graph", 1)))
+                     int(tune.get("use_graph", 1)), int(tune.get("ph_per_item", 0)), int(tune.get("bvh_width", 8)))
         h = C.c_void_p()
         _check(load().sc_batch_create(ctx.h, len(items), C.cast(arr, C.c_void_p), C.byref(t) if t else None,
                                       C.byref(h)), "sc_batch_create")

@@ -1,17 +1,13 @@
-"""Autotuner of the batched persistent launch.
-
-Chooses the BVH width (4 or 8 children per node), the persistent grid
-(threads per block, blocks per compute unit) and the work-item tile (pixels
-or photons a wave takes at a time) for a batch of scenes by timing every
-candidate on the batch itself at reduced cost (1 sample per pixel, 1/8 of
-the photons).  No choice changes any output: the batch result is bit-identical
-for every setting.  Results are cached in a JSON file keyed by the batch's
-shape.
+"""Autotuner of the batched persistent launch: a thin wrapper over
+sc_autotune (the library's C autotuner, which times candidate settings of
+the persistent grid, pixel tile, photon queue grain and BVH width on
+reduced copies of the batch).  No choice changes any output: the batch
+result is bit-identical for every setting.  Results are cached in a JSON
+file keyed by the batch's shape.
 """
 from __future__ import annotations
 
 import hashlib
-import itertools
 import json
 import os
 import time
@@ -21,11 +17,7 @@ import torch
 from . import _sc as sc
 
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sc_autotune.json")
-
-WIDTHS = (4, 8)
-BLOCK_SIZES = (64, 128, 256)
-BLOCKS_PER_CU = (2, 4, 8)
-TILES = (64, 256)
+KEYS = ("width", "block_size", "blocks_per_cu", "px_per_item", "ph_per_item", "use_graph")
 
 
 def signature(cfgs) -> str:
@@ -43,9 +35,10 @@ def _items(cfgs, bvhs, spp=None, photon_div=1):
             for c, b in zip(cfgs, bvhs)]
 
 
-def autotune(ctx, cfgs, cache_path: str = CACHE, reps: int = 2, log=None) -> dict:
-    """Best {width, block_size, blocks_per_cu, px_per_item} for the batch
-    described by cfgs (scenegen configs)."""
+def autotune(ctx, cfgs, cache_path: str = CACHE, log=None) -> dict:
+    """Best {width, block_size, blocks_per_cu, px_per_item, ph_per_item,
+    use_graph} for the batch described by cfgs (scenegen configs), from
+    sc_autotune on the batch built with 8-wide trees."""
     sig = signature(cfgs)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -54,31 +47,19 @@ def autotune(ctx, cfgs, cache_path: str = CACHE, reps: int = 2, log=None) -> dic
                 cache = json.load(f)
         except (OSError, ValueError):
             cache = {}
-    if sig in cache:
+    if sig in cache and all(k in cache[sig] for k in KEYS):
         return dict(cache[sig], cached=True)
-    results = []
-    for width in WIDTHS:
-        bvhs = [ctx.build_bvh(c["scene"], width=width) for c in cfgs]
-        items = _items(cfgs, bvhs, spp=1, photon_div=8)
-        for bs, bpc, tile in itertools.product(BLOCK_SIZES, BLOCKS_PER_CU, TILES):
-            tune = dict(block_size=bs, blocks_per_cu=bpc, px_per_item=tile, use_graph=1)
-            b = sc.Batch(ctx, items, tune)
-            b.run()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                b.run()
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) / reps * 1e3
-            results.append((ms, width, bs, bpc, tile))
-            if log:
-                log(f"autotune width {width} block {bs} blocks/CU {bpc} tile {tile}: {ms:.2f} ms")
-            b.close()
-        for bv in bvhs:
-            bv.close()
-    ms, width, bs, bpc, tile = min(results)
-    best = dict(width=width, block_size=bs, blocks_per_cu=bpc, px_per_item=tile, use_graph=1, probe_ms=ms,
-                candidates=len(results))
+    bvhs = [ctx.build_bvh(c["scene"], width=8) for c in cfgs]
+    t0 = time.perf_counter()
+    t = sc.autotune_batch(ctx, _items(cfgs, bvhs))
+    secs = time.perf_counter() - t0
+    for b in bvhs:
+        b.close()
+    best = dict(width=t["bvh_width"], block_size=t["block_size"], blocks_per_cu=t["blocks_per_cu"],
+                px_per_item=t["px_per_item"], ph_per_item=t["ph_per_item"], use_graph=t["use_graph"],
+                tuning_s=round(secs, 2))
+    if log:
+        log(f"autotune: {best}")
     if cache_path:
         cache[sig] = best
         try:
@@ -96,7 +77,8 @@ def compare(ctx, cfgs, tuned: dict, reps: int = 2, log=None) -> dict:
     render per scene).  BVH builds are done before either is timed."""
     bvhs = [ctx.build_bvh(c["scene"], width=tuned["width"]) for c in cfgs]
     items = _items(cfgs, bvhs)
-    b = sc.Batch(ctx, items, {k: tuned[k] for k in ("block_size", "blocks_per_cu", "px_per_item", "use_graph")})
+    b = sc.Batch(ctx, items, {k: tuned[k] for k in ("block_size", "blocks_per_cu", "px_per_item", "ph_per_item",
+                                                     "use_graph")})
     b.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()

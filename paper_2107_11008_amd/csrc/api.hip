@@ -503,16 +503,19 @@ sc_status sc_render_overlap(sc_ctx* ctx, const sc_bvh* bvh, const sc_camera* cam
                        nullptr, static_cast<hipEvent_t>(map_ready));
 }
 
-sc_status sc_batch_create(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune* tune, sc_batch** out) {
-    if (!ctx || !items || !out) return set_error(SC_EINVAL, "ctx, items or out is NULL");
-    *out = nullptr;
-    if (n == 0) return set_error(SC_EINVAL, "empty batch");
-    sc_tune t = tune ? *tune : sc_tune{128, 8, 64, 1};
+static sc_status check_tune(const sc_tune& t) {
     if (!(t.block_size == 64 || t.block_size == 128 || t.block_size == 256))
         return set_error(SC_EINVAL, "block_size must be 64, 128 or 256");
     if (t.blocks_per_cu < 1 || t.blocks_per_cu > 32) return set_error(SC_EINVAL, "blocks_per_cu must be 1..32");
     if (t.px_per_item < 64 || t.px_per_item > 4096 || t.px_per_item % 64)
         return set_error(SC_EINVAL, "px_per_item must be a multiple of 64 up to 4096");
+    if (t.ph_per_item > 65536 || t.ph_per_item % 64)
+        return set_error(SC_EINVAL, "ph_per_item must be 0 or a multiple of 64 up to 65536");
+    return SC_OK;
+}
+
+static sc_status check_batch_items(sc_ctx* ctx, uint32_t n, const sc_batch_item* items) {
+    if (n == 0) return set_error(SC_EINVAL, "empty batch");
     for (uint32_t i = 0; i < n; ++i) {
         const sc_batch_item& it = items[i];
         const std::string where = "batch item " + std::to_string(i) + ": ";
@@ -526,6 +529,15 @@ sc_status sc_batch_create(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, c
             return set_error(SC_EINVAL, where + "caustics need a receiver");
         if (it.bvh->b.ctx != &ctx->c) return set_error(SC_EINVAL, where + "bvh belongs to another context");
     }
+    return SC_OK;
+}
+
+sc_status sc_batch_create(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune* tune, sc_batch** out) {
+    if (!ctx || !items || !out) return set_error(SC_EINVAL, "ctx, items or out is NULL");
+    *out = nullptr;
+    const sc_tune t = tune ? *tune : sc_tune{128, 8, 64, 1, 0, 8};
+    SC_TRY(check_tune(t));
+    SC_TRY(check_batch_items(ctx, n, items));
     sc_batch* b = new (std::nothrow) sc_batch();
     if (!b) return set_error(SC_ENOMEM, "host allocation failed");
     sc_status s = scl::batch_create(&ctx->c, n, items, t, &b->bt);
@@ -558,6 +570,115 @@ sc_status sc_render_batch(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, c
     if (s == SC_OK && hipStreamSynchronize(ctx->c.stream) != hipSuccess) s = set_error(SC_EDEVICE, "batch failed");
     sc_batch_free(b);
     return s;
+}
+
+// The scene a built BVH was made from: the caller's device arrays as given
+// at build time, the host tables read back from the handle's device copies.
+static sc_status scene_of_bvh(const scl::Bvh& b, sc_scene& sc, std::vector<sc_material>& mat, std::vector<float>& pl,
+                              std::vector<float>& tg, std::vector<uint32_t>& tg_obj) {
+    sc = b.scene_in;
+    mat.resize(sc.n_mat);
+    pl.resize(4 * (size_t)sc.n_pl);
+    tg.resize(4 * (size_t)sc.n_tg);
+    tg_obj.assign(sc.n_tg, 1u);
+    if (b.ctx) SC_HIP(hipStreamSynchronize(b.ctx->stream));
+    SC_HIP(hipMemcpy(mat.data(), b.mat.p, sizeof(sc_material) * mat.size(), hipMemcpyDeviceToHost));
+    if (sc.n_pl) SC_HIP(hipMemcpy(pl.data(), b.pl.p, 4 * pl.size(), hipMemcpyDeviceToHost));
+    if (sc.n_tg) SC_HIP(hipMemcpy(tg.data(), b.tg.p, 4 * tg.size(), hipMemcpyDeviceToHost));
+    sc.mat = mat.data();
+    sc.point_lights = sc.n_pl ? pl.data() : nullptr;
+    sc.targets_sphere = sc.n_tg ? tg.data() : nullptr;
+    sc.targets_obj = sc.n_tg ? tg_obj.data() : nullptr;
+    return SC_OK;
+}
+
+// mean ms of two runs of the batch with tuning t (after one untimed run)
+static sc_status time_batch(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, const sc_tune& t, float* ms) {
+    sc_batch* b = nullptr;
+    SC_TRY(sc_batch_create(ctx, n, items, &t, &b));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    sc_status s = SC_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) s = set_error(SC_EDEVICE, "event");
+    if (s == SC_OK) s = sc_batch_run(ctx, b);
+    if (s == SC_OK && hipEventRecord(e0, ctx->c.stream) != hipSuccess) s = set_error(SC_EDEVICE, "event record");
+    for (int r = 0; r < 2 && s == SC_OK; ++r) s = sc_batch_run(ctx, b);
+    if (s == SC_OK && hipEventRecord(e1, ctx->c.stream) != hipSuccess) s = set_error(SC_EDEVICE, "event record");
+    if (s == SC_OK && hipEventSynchronize(e1) != hipSuccess) s = set_error(SC_EDEVICE, "batch run failed");
+    if (s == SC_OK && hipEventElapsedTime(ms, e0, e1) != hipSuccess) s = set_error(SC_EDEVICE, "event time");
+    if (s == SC_OK) *ms *= 0.5f;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    sc_batch_free(b);
+    return s;
+}
+
+sc_status sc_autotune(sc_ctx* ctx, uint32_t n, const sc_batch_item* items, sc_tune* out) {
+    if (!ctx || !items || !out) return set_error(SC_EINVAL, "ctx, items or out is NULL");
+    SC_TRY(check_batch_items(ctx, n, items));
+    // reduced copies: 1 sample per pixel, 1/8 of the photons (at least 64)
+    std::vector<sc_batch_item> red(items, items + n);
+    for (auto& it : red) {
+        it.spp = 1;
+        if (it.n_photons) it.n_photons = std::max<uint64_t>(64, it.n_photons / 8);
+    }
+    sc_tune best{128, 8, 64, 1, 256, 8};
+    float best_ms = 0.0f;
+    auto trial = [&](const sc_tune& t, const std::vector<sc_batch_item>& its, float* ms) -> sc_status {
+        const sc_status s = time_batch(ctx, n, its.data(), t, ms);
+        if (s != SC_OK)
+            return set_error(SC_EABORTED, std::string("autotune candidate {") + std::to_string(t.block_size) + ", " +
+                                              std::to_string(t.blocks_per_cu) + ", " + std::to_string(t.px_per_item) +
+                                              ", " + std::to_string(t.ph_per_item) + "} failed: " + sc_last_error());
+        return SC_OK;
+    };
+    SC_TRY(trial(best, red, &best_ms));
+    for (uint32_t bs : {64u, 128u, 256u})
+        for (uint32_t bpc : {2u, 4u, 8u}) {
+            sc_tune t = best;
+            t.block_size = bs;
+            t.blocks_per_cu = bpc;
+            float ms = 0.0f;
+            SC_TRY(trial(t, red, &ms));
+            if (ms < best_ms) { best_ms = ms; best = t; }
+        }
+    for (uint32_t px : {64u, 128u, 256u, 512u}) {
+        sc_tune t = best;
+        t.px_per_item = px;
+        float ms = 0.0f;
+        SC_TRY(trial(t, red, &ms));
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    for (uint32_t ph : {64u, 256u, 1024u, 4096u}) {
+        sc_tune t = best;
+        t.ph_per_item = ph;
+        float ms = 0.0f;
+        SC_TRY(trial(t, red, &ms));
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    // BVH width: the items' trees against 4-wide trees of the same scenes
+    const uint32_t own = items[0].bvh->b.width;
+    const uint32_t other = own == 8 ? 4u : 8u;
+    std::vector<sc_bvh*> alt(n, nullptr);
+    sc_status s = SC_OK;
+    for (uint32_t i = 0; i < n && s == SC_OK; ++i) {
+        sc_scene sc;
+        std::vector<sc_material> mat;
+        std::vector<float> pl, tg;
+        std::vector<uint32_t> tgo;
+        s = scene_of_bvh(items[i].bvh->b, sc, mat, pl, tg, tgo);
+        const sc_bvh_opts o{other, items[i].bvh->b.leaf_max};
+        if (s == SC_OK) s = sc_build_bvh(ctx, &sc, &o, &alt[i]);
+        red[i].bvh = alt[i];
+    }
+    float ms = 0.0f;
+    if (s == SC_OK) s = trial(best, red, &ms);
+    for (sc_bvh* b : alt)
+        if (b) sc_bvh_free(b);
+    if (s != SC_OK) return s == SC_EABORTED ? s : set_error(SC_EABORTED, std::string("autotune: ") + sc_last_error());
+    best.bvh_width = ms < best_ms ? other : own;
+    best.use_graph = 1;
+    *out = best;
+    return SC_OK;
 }
 
 sc_status sc_unet_create(sc_ctx* ctx, const uint32_t* widths, uint32_t levels, sc_unet** out) {
@@ -663,6 +784,13 @@ sc_status sc_unet_train_step(sc_ctx* ctx, sc_unet* net, const float* feat, const
         *loss = s / (float)((double)n * w * h * 3);
     }
     return SC_OK;
+}
+
+sc_status sc_unet_features(sc_ctx* ctx, const sc_aov* in, uint32_t w, uint32_t h, float* feat) {
+    if (!ctx || !in || !in->rgb || !feat) return set_error(SC_EINVAL, "NULL argument");
+    if (w == 0 || h == 0) return set_error(SC_EINVAL, "empty image");
+    if ((uint64_t)w * h > (1ull << 28)) return set_error(SC_EUNSUPPORTED, "image too large");
+    return scl::features_f32(&ctx->c, *in, w, h, feat);
 }
 
 sc_status sc_denoise(sc_ctx* ctx, sc_unet* net, const sc_aov* in, uint32_t w, uint32_t h, float* out_rgb) {

@@ -173,12 +173,12 @@ __global__ void k_batch_finalize(const BatchScene* __restrict__ B) {
 
 template <int BS>
 void launch_all(hipStream_t st, const BatchScene* dB, uint32_t n, uint32_t ph_items, uint32_t px_items,
-                uint32_t per_item, uint32_t* work, uint32_t grid, uint32_t zero_grid) {
+                uint32_t per_ph, uint32_t per_px, uint32_t* work, uint32_t grid, uint32_t zero_grid) {
     hipLaunchKernelGGL(k_batch_zero, dim3(zero_grid, n), dim3(256), 0, st, dB, work);
     if (ph_items)
-        hipLaunchKernelGGL(k_batch_photons<BS>, dim3(grid), dim3(BS), 0, st, dB, n, ph_items, per_item, work);
+        hipLaunchKernelGGL(k_batch_photons<BS>, dim3(grid), dim3(BS), 0, st, dB, n, ph_items, per_ph, work);
     hipLaunchKernelGGL(k_batch_finalize, dim3(zero_grid, n), dim3(256), 0, st, dB);
-    hipLaunchKernelGGL(k_batch_render<BS>, dim3(grid), dim3(BS), 0, st, dB, n, px_items, per_item, work + 1);
+    hipLaunchKernelGGL(k_batch_render<BS>, dim3(grid), dim3(BS), 0, st, dB, n, px_items, per_px, work + 1);
 }
 
 }  // namespace
@@ -192,6 +192,7 @@ sc_status batch_create(Ctx* c, uint32_t n, const sc_batch_item* items, const sc_
     std::vector<BatchScene> hs(n);
     uint32_t ph_items = 0, px_items = 0;
     const uint32_t per = tune.px_per_item;
+    const uint32_t per_ph = tune.ph_per_item ? tune.ph_per_item : tune.px_per_item;
     size_t acc_total = 0, map_total = 0, tab_total = 0;
     std::vector<std::vector<float>> tabs(n);
     std::vector<uint32_t> ntab(n, 0);
@@ -238,7 +239,7 @@ sc_status batch_create(Ctx* c, uint32_t n, const sc_batch_item* items, const sc_
         B.item_begin = px_items;
         px_items += (B.hw + per - 1) / per;
         B.ph_item_begin = ph_items;
-        ph_items += (uint32_t)((it.n_photons + per - 1) / per);
+        ph_items += (uint32_t)((it.n_photons + per_ph - 1) / per_ph);
         const size_t cells = B.S.recv_obj ? (size_t)B.S.recv_wc * B.S.recv_hc * B.wl.channels : 0;
         B.cells = it.n_photons ? cells : 0;
         B.acc = bt->acc.as<unsigned long long>() + acc_off;
@@ -283,10 +284,11 @@ sc_status batch_create(Ctx* c, uint32_t n, const sc_batch_item* items, const sc_
 void Batch::launch(hipStream_t st) {
     const BatchScene* dB = scenes.as<BatchScene>();
     uint32_t* w = work.as<uint32_t>();
+    const uint32_t per_ph = tune.ph_per_item ? tune.ph_per_item : tune.px_per_item;
     switch (tune.block_size) {
-        case 64: launch_all<64>(st, dB, n, ph_items, px_items, tune.px_per_item, w, grid, zero_grid); break;
-        case 128: launch_all<128>(st, dB, n, ph_items, px_items, tune.px_per_item, w, grid, zero_grid); break;
-        default: launch_all<256>(st, dB, n, ph_items, px_items, tune.px_per_item, w, grid, zero_grid); break;
+        case 64: launch_all<64>(st, dB, n, ph_items, px_items, per_ph, tune.px_per_item, w, grid, zero_grid); break;
+        case 128: launch_all<128>(st, dB, n, ph_items, px_items, per_ph, tune.px_per_item, w, grid, zero_grid); break;
+        default: launch_all<256>(st, dB, n, ph_items, px_items, per_ph, tune.px_per_item, w, grid, zero_grid); break;
     }
 }
 

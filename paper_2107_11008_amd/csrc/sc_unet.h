@@ -54,5 +54,7 @@ sc_status unet_loss(Unet* u, const float* target, float* loss_dev);
 sc_status unet_adam(Unet* u, float lr);
 sc_status unet_features(Unet* u, const sc_aov& in, uint32_t w, uint32_t h);
 sc_status unet_output_rgb(Unet* u, uint32_t w, uint32_t h, float* out);
+// the network's input features of a w x h render as float [h][w][9]
+sc_status features_f32(Ctx* c, const sc_aov& in, uint32_t w, uint32_t h, float* out);
 
 }  // namespace scl

@@ -632,6 +632,33 @@ __global__ void k_pack_input(const float* __restrict__ f, uint32_t P, uint32_t i
     }
 }
 
+// The network's 9 input features of pixel p of a render: log(1 + rgb)
+// (negative radiance clamped to 0), grey albedo, world normal, normalised
+// depth, transparent bit; absent buffers give 0.  The only definition of
+// the feature map: inference (k_features) and training inputs
+// (k_features_f32, sc_unet_features) both use it.
+__device__ __forceinline__ void feature9(const float* __restrict__ rgb, const float* __restrict__ albedo,
+                                         const float* __restrict__ normal, const float* __restrict__ depthn,
+                                         const uint8_t* __restrict__ trans, uint32_t p, float* v) {
+    for (int c = 0; c < 3; ++c) v[c] = log1pf(fmaxf(rgb[3 * (size_t)p + c], 0.0f));
+    v[3] = albedo ? albedo[p] : 0.0f;
+    for (int c = 0; c < 3; ++c) v[4 + c] = normal ? normal[3 * (size_t)p + c] : 0.0f;
+    v[7] = depthn ? depthn[p] : 0.0f;
+    v[8] = trans ? (float)trans[p] : 0.0f;
+}
+
+// features as float [h][w][9] (the training input of sc_unet_train_step)
+__global__ void k_features_f32(const float* __restrict__ rgb, const float* __restrict__ albedo,
+                               const float* __restrict__ normal, const float* __restrict__ depthn,
+                               const uint8_t* __restrict__ trans, uint32_t n, float* __restrict__ F) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float v[9];
+        feature9(rgb, albedo, normal, depthn, trans, i, v);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) F[9 * (size_t)i + c] = v[c];
+    }
+}
+
 // features from the renderer's outputs into a zero-padded canvas of 16
 // channels per pixel (two 16-byte stores)
 __global__ void k_features(const float* __restrict__ rgb, const float* __restrict__ albedo,
@@ -642,14 +669,7 @@ __global__ void k_features(const float* __restrict__ rgb, const float* __restric
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t y = i / W, x = i - y * W;
         float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if (x < w && y < h) {
-            const uint32_t p = y * w + x;
-            for (int c = 0; c < 3; ++c) v[c] = log1pf(fmaxf(rgb[3 * p + c], 0.0f));
-            v[3] = albedo ? albedo[p] : 0.0f;
-            for (int c = 0; c < 3; ++c) v[4 + c] = normal ? normal[3 * p + c] : 0.0f;
-            v[7] = depthn ? depthn[p] : 0.0f;
-            v[8] = trans ? (float)trans[p] : 0.0f;
-        }
+        if (x < w && y < h) feature9(rgb, albedo, normal, depthn, trans, y * w + x, v);
         union {
             uint4 u[2];
             uint16_t h[16];
@@ -1174,6 +1194,14 @@ sc_status unet_adam(Unet* u, float lr) {
 sc_status unet_features(Unet* u, const sc_aov& in, uint32_t w, uint32_t h) {
     hipLaunchKernelGGL(k_features, dim3(blocks((size_t)u->W * u->H)), dim3(256), 0, u->ctx->stream, in.rgb, in.albedo,
                        in.normal, in.depthn, in.trans, w, h, u->W, u->H, u->acts.as<uint16_t>() + u->t.in);
+    SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+sc_status features_f32(Ctx* c, const sc_aov& in, uint32_t w, uint32_t h, float* out) {
+    const size_t n = (size_t)w * h;
+    hipLaunchKernelGGL(k_features_f32, dim3(blocks(n)), dim3(256), 0, c->stream, in.rgb, in.albedo, in.normal,
+                       in.depthn, in.trans, (uint32_t)n, out);
     SC_HIP(hipGetLastError());
     return SC_OK;
 }

@@ -38,10 +38,10 @@ def rel_mse(x: torch.Tensor, ref: torch.Tensor, eps: float = 0.01) -> float:
     return float(((x - ref) ** 2 / (ref * ref + eps)).mean())
 
 
-def features(r: dict) -> torch.Tensor:
-    """[H,W,9] float: log1p(rgb), albedo, normal, depth/10, transparent."""
-    return torch.cat([torch.log1p(r["rgb"].clamp_min(0)), r["albedo"][..., None], r["normal"],
-                      r["depthn"][..., None], r["trans"][..., None].float()], -1).contiguous()
+def features(ctx, r: dict) -> torch.Tensor:
+    """[H,W,9] float: log1p(rgb), albedo, normal, depth/10, transparent,
+    built by the library (sc_unet_features), the function sc_denoise uses."""
+    return ctx.unet_features(r)
 
 
 def render_pair(ctx, cfg, spp_in: int, spp_ref: int, ph_in: int, ph_ref: int, seed: int, cam=None, bvh=None):
@@ -53,7 +53,7 @@ def render_pair(ctx, cfg, spp_in: int, spp_ref: int, ph_in: int, ph_ref: int, se
                       outputs=("rgb", "albedo", "normal", "depthn", "trans"))
     m_ref = ctx.trace_photons(bvh, ph_ref, cfg["max_depth"], wl, seed + 21)["map"]
     r_ref = ctx.render(bvh, cam, spp_ref, cfg["max_depth"], wl, seed + 22, caustic_map=m_ref, outputs=("rgb",))
-    return features(r_in), r_ref["rgb"].contiguous()
+    return features(ctx, r_in), r_ref["rgb"].contiguous()
 
 
 def crop_camera(cam, x0: int, y0: int, w: int, h: int):

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     for n in _declared():
         assert n in exported, n
         assert hasattr(lib, n)
-    assert lib.sc_abi_version() == sc._sc.ABI_VERSION == 5
+    assert lib.sc_abi_version() == sc._sc.ABI_VERSION == 6
 
 
 def test_material_record_layout():

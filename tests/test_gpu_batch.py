@@ -49,7 +49,11 @@ def _check(batch, refs):
 
 @pytest.mark.parametrize("tune", [None, dict(block_size=64, blocks_per_cu=4, px_per_item=64, use_graph=0),
                                   dict(block_size=256, blocks_per_cu=2, px_per_item=256, use_graph=1),
-                                  dict(block_size=128, blocks_per_cu=16, px_per_item=128, use_graph=1)])
+                                  dict(block_size=128, blocks_per_cu=16, px_per_item=128, use_graph=1),
+                                  dict(block_size=128, blocks_per_cu=8, px_per_item=64, ph_per_item=4096,
+                                       use_graph=1),
+                                  dict(block_size=256, blocks_per_cu=4, px_per_item=512, ph_per_item=64,
+                                       use_graph=0)])
 def test_batch_equals_sequential(setup, tune):
     import paper_2107_11008_amd as sc
     ctx, items, refs = setup
@@ -87,6 +91,27 @@ def test_bvh_width_does_not_change_batch(setup):
     _check(b, refs)
 
 
+def test_autotune_picks_a_valid_setting(setup):
+    """sc_autotune returns a setting inside its candidate sets; the batch
+    run with it (and its BVH width) equals the one-scene outputs."""
+    import paper_2107_11008_amd as sc
+    ctx, items, refs = setup
+    t = sc.autotune_batch(ctx, items)
+    assert t["block_size"] in (64, 128, 256) and t["blocks_per_cu"] in (2, 4, 8)
+    assert t["px_per_item"] in (64, 128, 256, 512) and t["ph_per_item"] in (64, 256, 1024, 4096)
+    assert t["bvh_width"] in (4, 8) and t["use_graph"] == 1
+    its = items
+    if t["bvh_width"] != 8:
+        its = [dict(it, bvh=ctx.build_bvh(it["bvh"].scene, width=t["bvh_width"])) for it in items]
+    b = sc.Batch(ctx, its, t)
+    b.run()
+    torch.cuda.synchronize()
+    _check(b, refs)
+    bad = [dict(items[0], spp=0)]
+    with pytest.raises(sc.ScError):
+        sc.autotune_batch(ctx, bad)
+
+
 def test_batch_rejects_bad_tuning(setup):
     import paper_2107_11008_amd as sc
     ctx, items, _ = setup
@@ -94,6 +119,8 @@ def test_batch_rejects_bad_tuning(setup):
         sc.Batch(ctx, items, dict(block_size=96, blocks_per_cu=4, px_per_item=64))
     with pytest.raises(sc.ScError):
         sc.Batch(ctx, items, dict(block_size=64, blocks_per_cu=4, px_per_item=100))
+    with pytest.raises(sc.ScError):
+        sc.Batch(ctx, items, dict(block_size=64, blocks_per_cu=4, px_per_item=64, ph_per_item=96))
 
 
 def test_batch_with_richer_glass_and_rgb_texture():
