@@ -526,6 +526,26 @@ sc_status sc_unet_backward(sc_ctx* ctx, sc_unet* net, const float* dpred, float*
  * the call does not synchronise) receives the loss before the update. */
 sc_status sc_unet_train_step(sc_ctx* ctx, sc_unet* net, const float* feat, const float* target, uint32_t n,
                              uint32_t w, uint32_t h, float lr, float* loss);
+/* One convolution layer of a network alone, on the same kernels the
+ * network runs (per-layer checks; a building block).  layer = index in
+ * parameter order (encoder levels two 3x3 layers each, decoder levels two
+ * 3x3 layers each, the 1x1 output layer last).  X: device f32
+ * [n][h][w][cin], rounded to bfloat16 on entry as the network stores
+ * activations (bfloat16-representable inputs are taken exactly).
+ * Forward: Y device f32 [n][h][w][cout] = act(conv(X, W) + b), act = ReLU
+ * if relu, else identity; a 3x3 layer's output is the bfloat16 value the
+ * network stores, the 1x1 layer's the float prediction.  Backward, given
+ * dZ = dL/d(conv output before act), device f32 [n][h][w][cout] rounded to
+ * bfloat16 on entry: dX device f32 [n][h][w][cin] (the bfloat16 input
+ * gradient the network feeds back; may be NULL) and dW device f32
+ * [cout*k*k*cin + cout], weights [cout][k][k][cin] then bias, float
+ * accumulation.  The backward call overwrites that layer's part of the
+ * network's gradient buffer.  Both synchronise (they hold temporaries).
+ * n*h*w <= 2^26; EINVAL on a bad layer index or empty shape. */
+sc_status sc_unet_layer_forward(sc_ctx* ctx, sc_unet* net, uint32_t layer, const float* X, uint32_t n, uint32_t h,
+                                uint32_t w, int32_t relu, float* Y);
+sc_status sc_unet_layer_backward(sc_ctx* ctx, sc_unet* net, uint32_t layer, const float* X, const float* dZ,
+                                 uint32_t n, uint32_t h, uint32_t w, float* dX, float* dW);
 /* The network's input features of a w x h render (the buffers of
  * sc_render: in->rgb required, albedo, normal, depthn, trans may be NULL
  * = 0): device feat [h][w][9] f32 = log(1 + max(rgb, 0)) x3, albedo,

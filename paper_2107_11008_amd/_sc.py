@@ -154,7 +154,8 @@ EXPORTS = ["sc_abi_version", "sc_last_error", "sc_create", "sc_destroy", "sc_set
            "sc_trace_rays", "sc_trace_rays_noalloc", "sc_trace_rays_noalloc_max", "sc_occluded", "sc_trace_photons",
            "sc_render", "sc_render_overlap",
            "sc_unet_create", "sc_unet_free", "sc_unet_num_params", "sc_unet_set_params", "sc_unet_get_params",
-           "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_unet_features", "sc_denoise",
+           "sc_unet_forward", "sc_unet_backward", "sc_unet_train_step", "sc_unet_features",
+           "sc_unet_layer_forward", "sc_unet_layer_backward", "sc_denoise",
            "sc_batch_create", "sc_batch_run", "sc_batch_free", "sc_render_batch", "sc_autotune",
            "sc_caustic_mask", "sc_outline", "sc_occlusion_boundary",
            "sc_pmap_trace", "sc_pmap_retrace", "sc_pmap_get_info", "sc_pmap_export", "sc_pmap_gather",
@@ -219,6 +220,8 @@ def load(path: str = LIB_PATH):
     L.sc_unet_train_step.argtypes = [vp, vp, vp, vp, u32, u32, u32, C.c_float, C.POINTER(C.c_float)]
     L.sc_denoise.argtypes = [vp, vp, C.POINTER(Aov), u32, u32, vp]
     L.sc_unet_features.argtypes = [vp, C.POINTER(Aov), u32, u32, vp]
+    L.sc_unet_layer_forward.argtypes = [vp, vp, u32, vp, u32, u32, u32, i32, vp]
+    L.sc_unet_layer_backward.argtypes = [vp, vp, u32, vp, vp, u32, u32, u32, vp, vp]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("sc_abi_version", "sc_last_error", "sc_trace_rays_noalloc_max"):
@@ -621,6 +624,16 @@ class UNet:
         n = C.c_uint64()
         _check(load().sc_unet_num_params(self.h, C.byref(n)), "sc_unet_num_params")
         self.n_params = n.value
+        # (cout, k, cin) of every convolution in parameter order
+        L, cin = [], 9
+        for w in self.widths:
+            L += [(w, 3, cin), (w, 3, w)]
+            cin = w
+        for i in range(len(self.widths) - 2, -1, -1):
+            L += [(self.widths[i], 3, cin + self.widths[i]), (self.widths[i], 3, self.widths[i])]
+            cin = self.widths[i]
+        L.append((3, 1, cin))
+        self.layer_shapes = L
         if params is not None:
             self.set_params(params)
 
@@ -652,6 +665,27 @@ class UNet:
         _check(load().sc_unet_train_step(self.ctx.h, self.h, _ptr(feat), _ptr(target), n, w, h, float(lr),
                                          C.byref(loss) if want_loss else None), "sc_unet_train_step")
         return loss.value if want_loss else None
+
+    def layer_forward(self, layer: int, x: torch.Tensor, relu: bool = True) -> torch.Tensor:
+        """sc_unet_layer_forward: one convolution of the network alone;
+        x float [n][h][w][cin] -> float [n][h][w][cout]."""
+        n, h, w, _ = x.shape
+        cout = self.layer_shapes[layer][0]
+        y = torch.empty((n, h, w, cout), dtype=torch.float32, device=self.ctx.device)
+        _check(load().sc_unet_layer_forward(self.ctx.h, self.h, layer, _ptr(x), n, h, w, int(relu), _ptr(y)),
+               "sc_unet_layer_forward")
+        return y
+
+    def layer_backward(self, layer: int, x: torch.Tensor, dz: torch.Tensor):
+        """sc_unet_layer_backward: (dX float [n][h][w][cin], dW float
+        [cout*k*k*cin + cout]) of one convolution given dz."""
+        n, h, w, cin = x.shape
+        cout, k, _ = self.layer_shapes[layer]
+        dx = torch.empty_like(x)
+        dw = torch.empty(cout * k * k * cin + cout, dtype=torch.float32, device=self.ctx.device)
+        _check(load().sc_unet_layer_backward(self.ctx.h, self.h, layer, _ptr(x), _ptr(dz), n, h, w, _ptr(dx), _ptr(dw)),
+               "sc_unet_layer_backward")
+        return dx, dw
 
     def denoise(self, aov: dict, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         h, w = aov["rgb"].shape[:2]

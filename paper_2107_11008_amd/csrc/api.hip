@@ -786,6 +786,28 @@ sc_status sc_unet_train_step(sc_ctx* ctx, sc_unet* net, const float* feat, const
     return SC_OK;
 }
 
+static sc_status check_layer(sc_unet* net, uint32_t layer, uint32_t n, uint32_t h, uint32_t w) {
+    if (!net->u.ctx) return set_error(SC_EINVAL, "the network's context was destroyed");
+    if (layer >= net->u.layers.size()) return set_error(SC_EINVAL, "layer index out of range");
+    if (n == 0 || w == 0 || h == 0) return set_error(SC_EINVAL, "empty batch");
+    if ((uint64_t)n * w * h > (1ull << 26)) return set_error(SC_EUNSUPPORTED, "batch too large");
+    return SC_OK;
+}
+
+sc_status sc_unet_layer_forward(sc_ctx* ctx, sc_unet* net, uint32_t layer, const float* X, uint32_t n, uint32_t h,
+                                uint32_t w, int32_t relu, float* Y) {
+    if (!ctx || !net || !X || !Y) return set_error(SC_EINVAL, "NULL argument");
+    SC_TRY(check_layer(net, layer, n, h, w));
+    return scl::unet_layer_forward(&net->u, layer, X, n, h, w, relu ? 1 : 0, Y);
+}
+
+sc_status sc_unet_layer_backward(sc_ctx* ctx, sc_unet* net, uint32_t layer, const float* X, const float* dZ,
+                                 uint32_t n, uint32_t h, uint32_t w, float* dX, float* dW) {
+    if (!ctx || !net || !X || !dZ || !dW) return set_error(SC_EINVAL, "NULL argument");
+    SC_TRY(check_layer(net, layer, n, h, w));
+    return scl::unet_layer_backward(&net->u, layer, X, dZ, n, h, w, dX, dW);
+}
+
 sc_status sc_unet_features(sc_ctx* ctx, const sc_aov* in, uint32_t w, uint32_t h, float* feat) {
     if (!ctx || !in || !in->rgb || !feat) return set_error(SC_EINVAL, "NULL argument");
     if (w == 0 || h == 0) return set_error(SC_EINVAL, "empty image");

@@ -54,6 +54,13 @@ sc_status unet_loss(Unet* u, const float* target, float* loss_dev);
 sc_status unet_adam(Unet* u, float lr);
 sc_status unet_features(Unet* u, const sc_aov& in, uint32_t w, uint32_t h);
 sc_status unet_output_rgb(Unet* u, uint32_t w, uint32_t h, float* out);
+// one convolution layer alone: forward (bf16 output of a 3x3 layer as
+// float, float output of the 1x1 layer) and gradients (dX as float of the
+// bf16 values, dW float: weights then bias); both synchronise
+sc_status unet_layer_forward(Unet* u, uint32_t layer, const float* X, uint32_t n, uint32_t h, uint32_t w, int relu,
+                             float* Y);
+sc_status unet_layer_backward(Unet* u, uint32_t layer, const float* X, const float* dZ, uint32_t n, uint32_t h,
+                              uint32_t w, float* dX, float* dW);
 // the network's input features of a w x h render as float [h][w][9]
 sc_status features_f32(Ctx* c, const sc_aov& in, uint32_t w, uint32_t h, float* out);
 

@@ -716,6 +716,13 @@ __global__ void k_l1_loss(const float* __restrict__ pred, const float* __restric
     if (threadIdx.x == 0) atomicAdd(loss_sum, (part[0] + part[1]) + (part[2] + part[3]));
 }
 
+// bf16 [P][cp] -> float [P][c] (padding channels dropped)
+__global__ void k_unpack_bf16(const uint16_t* __restrict__ X, uint32_t P, uint32_t cp, uint32_t c,
+                              float* __restrict__ F) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)P * c; i += (size_t)gridDim.x * blockDim.x)
+        F[i] = __uint_as_float((uint32_t)X[(i / c) * cp + (i % c)] << 16);
+}
+
 // given dpred float [P][3] -> bf16 [P][cout_p]
 __global__ void k_pack_dpred(const float* __restrict__ dp, uint32_t P, uint32_t cout_p, uint16_t* __restrict__ dY) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)P * cout_p;
@@ -1195,6 +1202,62 @@ sc_status unet_features(Unet* u, const sc_aov& in, uint32_t w, uint32_t h) {
     hipLaunchKernelGGL(k_features, dim3(blocks((size_t)u->W * u->H)), dim3(256), 0, u->ctx->stream, in.rgb, in.albedo,
                        in.normal, in.depthn, in.trans, w, h, u->W, u->H, u->acts.as<uint16_t>() + u->t.in);
     SC_HIP(hipGetLastError());
+    return SC_OK;
+}
+
+// One convolution layer alone (the per-layer check of the kernels): the
+// input packed to bf16 as the network stores activations, the layer's own
+// launch, its output converted back to float.
+sc_status unet_layer_forward(Unet* u, uint32_t layer, const float* X, uint32_t n, uint32_t h, uint32_t w, int relu,
+                             float* Y) {
+    const UnetLayer& L = u->layers[layer];
+    hipStream_t st = u->ctx->stream;
+    const uint32_t P = n * h * w;
+    DevBuf xb, yb;
+    SC_TRY(xb.alloc(2 * (size_t)P * L.cin_p));
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks((size_t)P * L.cin_p)), dim3(256), 0, st, X, P, L.cin, L.cin_p,
+                       xb.as<uint16_t>());
+    const float* th = u->theta.as<float>();
+    const uint16_t* wf = u->wf.as<uint16_t>();
+    if (L.ks == 3) {
+        SC_TRY(yb.alloc(2 * (size_t)P * L.cout_p));
+        conv_launch(st, u->cus, u->ctx->conv_big_tile, L, xb.as<uint16_t>(), P, h, w, wf + L.wf_off, L.cin_p, L.kpad,
+                    th + L.b_off, L.cout_p, L.cout, yb.as<uint16_t>(), nullptr, L.cout, relu);
+        hipLaunchKernelGGL(k_unpack_bf16, dim3(blocks((size_t)P * L.cout)), dim3(256), 0, st, yb.as<uint16_t>(), P,
+                           L.cout, L.cout, Y);
+    } else {
+        conv_launch(st, u->cus, u->ctx->conv_big_tile, L, xb.as<uint16_t>(), P, h, w, wf + L.wf_off, L.cin_p, L.kpad,
+                    th + L.b_off, L.cout_p, L.cout, nullptr, Y, L.cout, relu);
+    }
+    SC_HIP(hipGetLastError());
+    SC_HIP(hipStreamSynchronize(st));   // the temporaries are freed on return
+    return SC_OK;
+}
+
+sc_status unet_layer_backward(Unet* u, uint32_t layer, const float* X, const float* dZ, uint32_t n, uint32_t h,
+                              uint32_t w, float* dX, float* dW) {
+    const UnetLayer& L = u->layers[layer];
+    hipStream_t st = u->ctx->stream;
+    const uint32_t P = n * h * w;
+    DevBuf xb, dzb, dxb;
+    SC_TRY(xb.alloc(2 * (size_t)P * L.cin_p));
+    SC_TRY(dzb.alloc(2 * (size_t)P * L.cout_p));
+    if (dX) SC_TRY(dxb.alloc(2 * (size_t)P * L.cin_p));
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks((size_t)P * L.cin_p)), dim3(256), 0, st, X, P, L.cin, L.cin_p,
+                       xb.as<uint16_t>());
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks((size_t)P * L.cout_p)), dim3(256), 0, st, dZ, P, L.cout, L.cout_p,
+                       dzb.as<uint16_t>());
+    // the layer's gradient entries add up in u->grad: cleared first
+    const size_t nw = (size_t)L.cout * L.ks * L.ks * L.cin;
+    hipLaunchKernelGGL(k_zero_f, dim3(blocks(nw + L.cout)), dim3(256), 0, st, u->grad.as<float>() + L.w_off,
+                       nw + L.cout);
+    conv_backward(u, L, xb.as<uint16_t>(), dzb.as<uint16_t>(), P, h, w, dX ? dxb.as<uint16_t>() : nullptr);
+    if (dX)
+        hipLaunchKernelGGL(k_unpack_bf16, dim3(blocks((size_t)P * L.cin)), dim3(256), 0, st, dxb.as<uint16_t>(), P,
+                           L.cin_p, L.cin, dX);
+    SC_HIP(hipMemcpyAsync(dW, u->grad.as<float>() + L.w_off, 4 * (nw + L.cout), hipMemcpyDeviceToDevice, st));
+    SC_HIP(hipGetLastError());
+    SC_HIP(hipStreamSynchronize(st));   // the temporaries are freed on return
     return SC_OK;
 }
 

@@ -1,11 +1,17 @@
 """The denoiser's GPU kernels (BF16 matrix cores, float accumulation)
 against the oracle U-Net run with bfloat16 rounding at the same points.
+Each convolution alone is held to the survey's bars in
+test_gpu_unet_layers.py; here the whole network.
 
-Bars: forward relative L2 error <= 1e-2 of the prediction (bfloat16 keeps
-8 significant bits; the float accumulation order differs from the
-oracle's, which can flip a rounding of an intermediate activation);
-gradients: see test_backward_matches_oracle; one Adam step moves the
-parameters in the oracle's direction (cosine >= 0.99)."""
+Forward bars: relative L2 of the prediction <= 1e-3 for the two-level
+network (measured 3.1e-8), <= 8e-3 for the five-level one (measured
+0.4e-3 to 5.8e-3).  Through five levels a rounding of an intermediate
+activation that the float accumulation order tips the other way moves
+everything after it: the oracle against itself with its parameters moved
+by 1e-6 relative differs by 5.6e-3 to 6.4e-3 on these inputs, so a bar
+below that floor would test luck.  Gradients: see
+test_backward_matches_oracle; one Adam step moves the parameters in the
+oracle's direction (cosine >= 0.99)."""
 import numpy as np
 import pytest
 import torch
@@ -51,10 +57,11 @@ def tiles(ctx):
     set_(2048)
 
 
-@pytest.mark.parametrize("widths,n,h,w,big", [((16, 32), 1, 16, 16, 2048), ((32, 48, 64, 96, 128), 2, 32, 48, 2048),
-                                              ((32, 48, 64, 96, 128), 1, 48, 32, 2048),
-                                              ((32, 48, 64, 96, 128), 2, 48, 80, 0)])
-def test_forward_matches_oracle(ctx, tiles, widths, n, h, w, big):
+@pytest.mark.parametrize("widths,n,h,w,big,bar", [((16, 32), 1, 16, 16, 2048, 1e-3),
+                                                  ((32, 48, 64, 96, 128), 2, 32, 48, 2048, 8e-3),
+                                                  ((32, 48, 64, 96, 128), 1, 48, 32, 2048, 8e-3),
+                                                  ((32, 48, 64, 96, 128), 2, 48, 80, 0, 8e-3)])
+def test_forward_matches_oracle(ctx, tiles, widths, n, h, w, big, bar):
     import paper_2107_11008_amd as sc
     tiles(big)
     rng = np.random.default_rng(1)
@@ -64,7 +71,8 @@ def test_forward_matches_oracle(ctx, tiles, widths, n, h, w, big):
     x = _inputs(rng, n, h, w)
     g = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     o = U.UNet(th, widths, bf16=True).forward(x.astype(np.float64))
-    assert _rel(g, o) <= 1e-2, _rel(g, o)
+    print(f"forward {widths} {n}x{h}x{w} tiles {big}: rel L2 {_rel(g, o):.2e}")
+    assert _rel(g, o) <= bar, _rel(g, o)
     assert np.array_equal(net.get_params(), th)
 
 
