@@ -134,6 +134,86 @@ def train(ctx, net, pairs, steps: int, batch: int, crop: int, lr: float, seed: i
     return losses
 
 
+def c5_pairs(ctx, n_scenes: int, size: int, spp_in: int, spp_ref: int, seed0: int = 100000, log=print):
+    """The training set of the denoiser's data protocol: n_scenes medium-type
+    scenes (seeds seed0..seed0+n-1, full triangle count) at size x size;
+    inputs are spp_in-sample renders with their ground-truth buffers and a
+    caustic map of 2^16, 2^18 or 2^20 photons (seeded per scene), targets
+    spp_ref-sample renders with 2^22 photons and independent seeds.  Kept
+    in device memory: features [n][size][size][9] and targets
+    [n][size][size][3] float (12.6 MB per scene at 512^2).  Scenes are
+    generated on a host thread while the GPU renders the previous one."""
+    import queue
+    import threading
+
+    import scenegen as sg
+    feats = torch.empty((n_scenes, size, size, 9), dtype=torch.float32, device=ctx.device)
+    tgts = torch.empty((n_scenes, size, size, 3), dtype=torch.float32, device=ctx.device)
+    q = queue.Queue(maxsize=4)
+
+    def produce():
+        for j in range(n_scenes):
+            q.put(sg.config2(seed=seed0 + j, w=size, h=size))
+
+    th = threading.Thread(target=produce, daemon=True)
+    th.start()
+    rng = np.random.default_rng(seed0)
+    t0 = time.time()
+    for j in range(n_scenes):
+        cfg = q.get()
+        ph_in = int(rng.choice([1 << 16, 1 << 18, 1 << 20]))
+        f, t = render_pair(ctx, cfg, spp_in, spp_ref, ph_in, 1 << 22, 7000 + 100 * j)
+        feats[j].copy_(f)
+        tgts[j].copy_(t)
+        if j % 25 == 0 or j == n_scenes - 1:
+            torch.cuda.synchronize()
+            log(f"c5 pair {j + 1}/{n_scenes} ({time.time() - t0:.1f} s)")
+    th.join()
+    return feats, tgts
+
+
+def train_tensors(ctx, net, feats, tgts, steps: int, batch: int, crop: int, lr: float, seed: int = 0, log=print):
+    """train() over device tensors of whole frames (random crops)."""
+    rng = np.random.default_rng(seed)
+    n, H, W, _ = feats.shape
+    losses = []
+    t0 = time.time()
+    for it in range(steps):
+        idx = rng.integers(0, n, size=batch)
+        ys = rng.integers(0, H - crop + 1, size=batch)
+        xs = rng.integers(0, W - crop + 1, size=batch)
+        fb = torch.stack([feats[i, y:y + crop, x:x + crop] for i, y, x in zip(idx, ys, xs)]).contiguous()
+        tb = torch.stack([tgts[i, y:y + crop, x:x + crop] for i, y, x in zip(idx, ys, xs)]).contiguous()
+        cur_lr = lr if it < 0.7 * steps else lr * 0.3
+        want = (it % 500 == 0) or it == steps - 1
+        loss = net.train_step(fb, tb, cur_lr, want_loss=want)
+        if want:
+            losses.append((it, loss))
+            log(f"train step {it} loss {loss:.5f} ({time.time() - t0:.1f} s)")
+    return losses
+
+
+def main_c5(args, log):
+    """Training on the data protocol's set (--c5): 2000 medium-type scenes at
+    512^2, 4 spp in, 1024 spp targets."""
+    ctx = sc.Context(0)
+    t0 = time.time()
+    feats, tgts = c5_pairs(ctx, args.scenes, args.size, args.spp_in, args.spp_ref, log=log)
+    log(f"c5 set ready: {args.scenes} scenes in {time.time() - t0:.1f} s")
+    net = sc.UNet(ctx, WIDTHS)
+    net.set_params(he_init(net, 12345))
+    losses = train_tensors(ctx, net, feats, tgts, args.steps, args.batch, args.crop, args.lr, log=log)
+    params = net.get_params()
+    meta = {"widths": list(WIDTHS), "n_params": int(net.n_params), "protocol": "c5",
+            "train_scenes": args.scenes, "train_size": args.size, "spp_in": args.spp_in, "spp_ref": args.spp_ref,
+            "photons_in": [1 << 16, 1 << 18, 1 << 20], "photons_ref": 1 << 22, "steps": args.steps,
+            "batch": args.batch, "crop": args.crop, "lr": args.lr,
+            "medium_scene_seeds": [100000, 100000 + args.scenes - 1], "large_scene_seeds": None,
+            "data_s": round(time.time() - t0, 1), "loss_curve": losses}
+    save_weights(params, meta, args.out)
+    log(f"saved to {args.out} ({time.time() - t0:.1f} s)")
+
+
 def main(argv=None):
     import scenegen as sg
 
@@ -152,10 +232,14 @@ def main(argv=None):
     ap.add_argument("--photons-in", type=int, default=1 << 22)
     ap.add_argument("--out", default=WEIGHTS_DIR)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--c5", action="store_true", help="the data protocol's training set (see main_c5)")
     args = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
+
+    if args.c5:
+        return main_c5(args, log)
 
     ctx = sc.Context(0)
     t0 = time.time()
