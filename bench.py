@@ -40,7 +40,8 @@ VALU_PEAK_GOPS = 256 * 64 * 2.4
 NODE_BYTES, TRI_BYTES = 256, 36          # uncompressed 8-wide node; a triangle's three vertices
 RAY_IN, HIT_OUT, OCC_OUT = 32, 16, 4     # ray record read; closest hit written; occlusion written
 OPS_PER_NODE, OPS_PER_TRI = 14 * 8, 40   # VALU operations per node visit (8 child boxes) and per triangle test
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traversal_large_traffic.md")
+TRAFFIC_FILES = {"large": os.path.join(ROOT, "profiles", "traversal_large_traffic.md"),
+                 "medium": os.path.join(ROOT, "profiles", "traversal_medium_traffic.md")}
 
 
 def _src_hash():
@@ -51,12 +52,14 @@ def _src_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic_per_launch(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when absent or taken on different kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _traffic_per_launch(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, or None when absent or taken on different
+    kernel sources."""
+    path = TRAFFIC_FILES[workload]
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
     b = re.search(r"hbm_bytes_per_launch " + re.escape(kernel) + r":\s*([0-9.eE+]+)", txt)
     if not m or not b or m.group(1) != _src_hash():
@@ -133,7 +136,7 @@ def cpu_baseline(cfg, rays_per_step, step_s):
     return res
 
 
-def _kernel_roofline(name, kernel_id, launches, ms, rays_cl, rays_sh, nodes, tris, steps, extra=None):
+def _kernel_roofline(name, kernel_id, launches, ms, rays_cl, rays_sh, nodes, tris, steps, workload, extra=None):
     """Roofline of one traversal kernel from its launches' HIP-event time and
     its counted visits (counting pass, scaled to the timed launches by the
     ray counts)."""
@@ -146,7 +149,7 @@ def _kernel_roofline(name, kernel_id, launches, ms, rays_cl, rays_sh, nodes, tri
     gbs = alg / (f_ms * 1e-3) / 1e9
     gops = ops / (f_ms * 1e-3) / 1e9
     r = {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": _traffic_per_launch(kernel_id),
+         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": _traffic_per_launch(kernel_id, workload),
          "avg_launch_ms": round(f_ms, 5), "launches": launches, "alg_bytes_per_launch": round(alg),
          "rays_per_launch": round((rays_cl + rays_sh) / launches),
          "nodes_per_ray": round(nodes / max(rays_cl + rays_sh, 1), 3),
@@ -160,7 +163,7 @@ def _kernel_roofline(name, kernel_id, launches, ms, rays_cl, rays_sh, nodes, tri
     return r
 
 
-def scene_step(ctx, cfg, steps, warmup):
+def scene_step(ctx, cfg, steps, warmup, workload):
     """Time `steps` full steps (BVH build + photon pass + ground truth +
     image) of one workload after `warmup` untimed ones; visit counts come
     from one untimed counting step of the same kernels."""
@@ -217,22 +220,22 @@ def scene_step(ctx, cfg, steps, warmup):
     rl.append(_kernel_roofline(
         "k_closest (staged closest-hit traversal)", "k_closest<false>", c["closest_launches"], c["closest_ms"],
         c["closest_rays_timed"], 0, per("closest_rays_timed", "node_visits") * closest_any,
-        per("closest_rays_timed", "tri_tests") * closest_any, steps))
+        per("closest_rays_timed", "tri_tests") * closest_any, steps, workload))
     rl.append(_kernel_roofline(
         "k_anyhit (staged shadow-ray traversal)", "k_anyhit<false>", c["anyhit_launches"], c["anyhit_ms"], 0,
         c["anyhit_rays"], per("anyhit_rays", "anyhit_node_visits") * c["anyhit_rays"],
-        per("anyhit_rays", "anyhit_tri_tests") * c["anyhit_rays"], steps))
+        per("anyhit_rays", "anyhit_tri_tests") * c["anyhit_rays"], steps, workload))
     cf_all = c["cam_finish_rays"] + c["cam_finish_shadow_rays"]
     cnt_cf_all = max(cnt["cam_finish_rays"] + cnt["cam_finish_shadow_rays"], 1)
     rl.append(_kernel_roofline(
         "k_finish_camera (per-lane camera path finishing)", "k_finish_camera<false, false>",
         c["cam_finish_launches"], c["cam_finish_ms"], c["cam_finish_rays"], c["cam_finish_shadow_rays"],
         cnt["cam_finish_node_visits"] / cnt_cf_all * cf_all, cnt["cam_finish_tri_tests"] / cnt_cf_all * cf_all, steps,
-        {"paths_per_launch": round(c["cam_finish_paths"] / max(c["cam_finish_launches"], 1))}))
+        workload, {"paths_per_launch": round(c["cam_finish_paths"] / max(c["cam_finish_launches"], 1))}))
     rl.append(_kernel_roofline(
         "k_finish_photons (per-lane photon path finishing)", "k_finish_photons<false>", c["finish_launches"],
         c["finish_ms"], c["finish_rays"], 0, per("finish_rays", "finish_node_visits") * c["finish_rays"],
-        per("finish_rays", "finish_tri_tests") * c["finish_rays"], steps,
+        per("finish_rays", "finish_tri_tests") * c["finish_rays"], steps, workload,
         {"paths_per_launch": round(c["finish_paths"] / max(c["finish_launches"], 1))}))
     rl = sorted([r for r in rl if r], key=lambda r: -r["ms_per_step"])
 
@@ -655,6 +658,8 @@ def general_photon_map(ctx, reps=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("large", "medium"), default="large",
+                    help="the step timed as the headline (medium: for profiling the medium scene alone)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -686,7 +691,7 @@ def main():
     import paper_2107_11008_amd as sc
     import scenegen as sg
 
-    cfg = sg.config3()
+    cfg = sg.config3() if args.workload == "large" else sg.config2()
     scene = cfg["scene"]
     ctx = sc.Context(0)
     if args.staged_depth is not None:
@@ -706,7 +711,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    big = scene_step(ctx, cfg, args.steps, args.warmup)
+    big = scene_step(ctx, cfg, args.steps, args.warmup, args.workload)
     secs = big["secs"]
     cam = cfg["camera"]
     line = {
@@ -722,10 +727,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"large glass scene: {cam.w}x{cam.h}, {cfg['spp']} spp, wavelengths uniform 380-720 "
-                               f"nm, max depth {cfg['max_depth']}, 2^24 caustic photons into a 2048x2048x16 map, "
-                               f"40 overlapping glass meshes and diffuse clutter ({scene.nt} triangles), two area "
-                               "lights; step = BVH build + photon pass + ground truth + image",
+        "config": {"workload": (f"large glass scene: {cam.w}x{cam.h}, {cfg['spp']} spp, wavelengths uniform 380-720 "
+                                f"nm, max depth {cfg['max_depth']}, 2^24 caustic photons into a 2048x2048x16 map, "
+                                f"40 overlapping glass meshes and diffuse clutter ({scene.nt} triangles), two area "
+                                "lights; step = BVH build + photon pass + ground truth + image")
+                   if args.workload == "large" else
+                   (f"medium glass scene: {cam.w}x{cam.h}, {cfg['spp']} spp, depth {cfg['max_depth']}, 2^22 photons "
+                    f"into 1024x1024x16, {scene.nt} triangles, one area light; step = BVH build + photon pass + "
+                    "ground truth + image"),
                    "triangles": scene.nt, "width": cam.w, "height": cam.h, "spp": cfg["spp"],
                    "max_depth": cfg["max_depth"], "photons": cfg["n_photons"]},
         "frames_per_s": round(args.steps / secs, 3),
@@ -737,9 +746,9 @@ def main():
         "paper": "no published renderer numbers (the paper renders with a game engine's hardware ray tracing on "
                  "2x GTX 1080 Ti and quotes no frame rates)",
     }
-    if not args.no_medium:
+    if not args.no_medium and args.workload == "large":
         c2 = sg.config2()
-        med = scene_step(ctx, c2, max(args.steps, 20), args.warmup)
+        med = scene_step(ctx, c2, max(args.steps, 20), args.warmup, "medium")
         line["medium_scene"] = {
             "workload": f"medium glass scene: 512x512, 16 spp, depth 12, 2^22 photons into 1024x1024x16, "
                         f"{c2['scene'].nt} triangles, one area light",
@@ -761,7 +770,8 @@ def main():
     if not args.no_batch:
         line["batch_64"] = batch_compare(ctx)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, big["rays_per_step"], secs / args.steps)
+        if args.workload == "large":
+            line["cpu_baseline"] = cpu_baseline(cfg, big["rays_per_step"], secs / args.steps)
     print(json.dumps(line), flush=True)
 
 

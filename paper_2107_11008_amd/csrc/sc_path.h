@@ -207,13 +207,34 @@ __device__ __forceinline__ void leaf_tri(const DevScene& S, const Fetch& f, uint
     }
 }
 
+// LDS-staged top of the tree: the collapse numbers nodes level by level,
+// so nodes [0, kTopNodes) are the root and its children; a kernel may copy
+// them into LDS once per block and pass the copy as `top` (then their
+// fetches read LDS), or pass nullptr.
+constexpr uint32_t kTopNodes = 9;
+constexpr uint32_t kTopMinNodes = 65536;   // trees smaller than this keep their top in cache anyway
+
 template <int BS, bool COUNT, int MODE>
-__device__ __forceinline__ bool tstep(const DevScene& S, Trav& t, uint2 (*lds)[BS], Spill& st, VisitCount& vc) {
+__device__ __forceinline__ bool tstep(const DevScene& S, Trav& t, uint2 (*lds)[BS], Spill& st, VisitCount& vc,
+                                      const float4* top = nullptr) {
     const bool any = MODE == kAny ? true : (MODE == kClosest ? false : t.any);
     uint32_t fl;
     const float4* base = step_base(S, t.ref, t.flip, fl);
     Fetch f;
-    fetch14(base, fl & 3u, (fl >> 2) & 3u, fl >> 4, f);
+    if (top && !(t.ref & SC_LEAF_BIT) && t.ref < kTopNodes) {
+        const float4* q = top + 16 * t.ref;
+        const uint32_t fx = fl & 3u, fy = (fl >> 2) & 3u, fz = fl >> 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f.q[j] = q[j ^ fx];
+#pragma unroll
+        for (int j = 4; j < 8; ++j) f.q[j] = q[j ^ fy];
+#pragma unroll
+        for (int j = 8; j < 12; ++j) f.q[j] = q[j ^ fz];
+        f.q[12] = q[12];
+        f.q[13] = q[13];
+    } else {
+        fetch14(base, fl & 3u, (fl >> 2) & 3u, fl >> 4, f);
+    }
     if (!(t.ref & SC_LEAF_BIT)) {
         NodeTest nt;
         test_node(f, t.o, t.inv, search_limit(t.tb), nt);
@@ -273,8 +294,9 @@ __device__ __forceinline__ bool tstep(const DevScene& S, Trav& t, uint2 (*lds)[B
 }
 
 template <int BS, bool COUNT>
-__device__ __forceinline__ bool trav_step(const DevScene& S, Trav& t, uint2 (*lds)[BS], Spill& st, VisitCount& vc) {
-    return tstep<BS, COUNT, kClosest>(S, t, lds, st, vc);
+__device__ __forceinline__ bool trav_step(const DevScene& S, Trav& t, uint2 (*lds)[BS], Spill& st, VisitCount& vc,
+                                          const float4* top = nullptr) {
+    return tstep<BS, COUNT, kClosest>(S, t, lds, st, vc, top);
 }
 
 __device__ __forceinline__ HitRec trav_result(const Trav& t) {
