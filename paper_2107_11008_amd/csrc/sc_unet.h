@@ -20,7 +20,7 @@ struct UnetLayer {
 
 // element offsets (bf16 units) of the activation and gradient tensors
 struct UnetTensors {
-    size_t in = 0, g0 = 0, g1 = 0, g2 = 0;
+    size_t in = 0, g0 = 0, g2 = 0;
     std::vector<size_t> pool, pool_idx, enc_a, enc_b, cat, dec_a, dec_b, skip;
     void clear() {
         pool.clear(); pool_idx.clear(); enc_a.clear(); enc_b.clear();
@@ -38,6 +38,7 @@ struct Unet {
     UnetTensors t;
     uint64_t step = 0;
     bool cat_valid = false;   // the last forward pass kept what a backward pass reads
+    bool grad_clear = false;  // grad holds zeros (the Adam step clears it as it reads it)
     uint32_t cus = 256;       // compute units of the device (sizes the persistent convolution grid)
 };
 

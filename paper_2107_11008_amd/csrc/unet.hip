@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
                                               uint32_t cin_p, const uint16_t* __restrict__ Wt, uint32_t kpad,
                                               const float* __restrict__ bias, uint32_t cout_p, uint32_t cout_real,
                                               uint16_t* __restrict__ Y, float* __restrict__ Yf, uint32_t y_stride,
-                                              uint32_t y_off, int relu) {
+                                              uint32_t y_off, int relu, const uint16_t* __restrict__ M) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t n_groups = (cout_p / 16 + 3) / 4;
@@ -118,8 +118,13 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
             if (po >= P) continue;
             float v = acc[j][i] + bv;
             if (relu) v = fmaxf(v, 0.0f);
-            if (Yf) Yf[(size_t)po * y_stride + y_off + co] = v;
-            else Y[(size_t)po * y_stride + y_off + co] = to_bf16(v);
+            const size_t o = (size_t)po * y_stride + y_off + co;
+            if (Yf) {
+                Yf[o] = v;
+            } else {
+                // M: the ReLU output this gradient flows back through (zero where it is not positive)
+                Y[o] = M && !(from_bf16(M[o]) > 0.0f) ? (uint16_t)0 : to_bf16(v);
+            }
         }
     }
 }
@@ -139,7 +144,9 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ X, ui
 // X2 (cin_p - c_split channels)], read in place (decoder inference).  Every
 // output sums chunk by chunk and tap by tap, so neither the tile shape nor the
 // grid changes a result.  Element indices of one tensor fit in 32 bits (the
-// host checks P * channels < 2^31); H and W are even.
+// host checks P * channels < 2^31); H and W are even.  M (input gradients
+// only): the ReLU output of the layer below, laid out as Y; outputs where it
+// is not positive are written as zero.
 constexpr int kTC = 16, kHC = kTC + 2;
 constexpr int kCC = 32;                 // input channels per chunk
 constexpr int kWP = 9 * kCC + 8;        // LDS pitch of a weight row (bf16), padded against bank conflicts
@@ -151,7 +158,8 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
                                                uint32_t c_split, uint32_t B, uint32_t H, uint32_t W, uint32_t cin_p,
                                                const uint16_t* __restrict__ Wt, uint32_t kpad,
                                                const float* __restrict__ bias, uint32_t cout_p,
-                                               uint16_t* __restrict__ Y, uint32_t y_stride, int relu) {
+                                               uint16_t* __restrict__ Y, uint32_t y_stride, int relu,
+                                               const uint16_t* __restrict__ M) {
     constexpr int kTR = 4 * RW, kHR = kTR + 2;
     constexpr int kXS = kHR * kHC * 4;       // 16-byte pieces of a staged tile
     constexpr int kXI = (kXS + 255) / 256;   // ... per thread
@@ -309,6 +317,13 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ X, c
                         uint2 o;
                         __builtin_memcpy(&o.x, &l2, 4);
                         __builtin_memcpy(&o.y, &h2, 4);
+                        if (M) {   // input gradient through a ReLU: zero where its output is not positive
+                            const uint2 mk = *reinterpret_cast<const uint2*>(M + (dst - Y) + 16 * j);
+                            o.x &= (from_bf16((uint16_t)mk.x) > 0.0f ? 0xFFFFu : 0u) |
+                                   (from_bf16((uint16_t)(mk.x >> 16)) > 0.0f ? 0xFFFF0000u : 0u);
+                            o.y &= (from_bf16((uint16_t)mk.y) > 0.0f ? 0xFFFFu : 0u) |
+                                   (from_bf16((uint16_t)(mk.y >> 16)) > 0.0f ? 0xFFFF0000u : 0u);
+                        }
                         *reinterpret_cast<uint2*>(dst + 16 * j) = o;
                     }
                 }
@@ -377,35 +392,6 @@ __global__ __launch_bounds__(256) void k_conv1_out(const uint16_t* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dZ, uint32_t P, uint32_t cout_p,
-                                                   uint32_t cout_real, float* __restrict__ db) {
-    // a thread sums 8 channels (one 16-byte load per pixel) over a strided
-    // pixel range; the block's partial sums meet in LDS, then one atomic
-    // per channel and block.  cout_p is a multiple of 16, at most 256.
-    const uint32_t c8n = cout_p / 8, nsub = 256 / c8n;
-    const uint32_t c8 = threadIdx.x % c8n, sub = threadIdx.x / c8n;
-    __shared__ float part[256 * 8];
-    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (sub < nsub)
-        for (uint32_t p = blockIdx.x * nsub + sub; p < P; p += gridDim.x * nsub) {
-            union {
-                uint4 u;
-                uint16_t h[8];
-            } v;
-            v.u = *reinterpret_cast<const uint4*>(dZ + (size_t)p * cout_p + 8 * c8);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) s[e] += from_bf16(v.h[e]);
-        }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) part[threadIdx.x * 8 + e] = s[e];
-    __syncthreads();
-    for (uint32_t c = threadIdx.x; c < cout_real; c += blockDim.x) {
-        float t = 0.0f;
-        for (uint32_t q = 0; q < nsub; ++q) t += part[(q * c8n + c / 8) * 8 + c % 8];
-        atomicAdd(&db[c], t);
-    }
-}
-
 // Weight gradient through LDS: dW[co][k] = sum_p dZ[p][co] * X[shift_tap(p)][ci]
 // (k = tap * cin_p + ci).  A block owns 16 CT output channels x 64 KW
 // columns k (CT = channel tiles, KW = 4 / CT waves per tile, each wave one
@@ -414,16 +400,21 @@ __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ 
 // channels of one tap per 16-byte load) are loaded with 16-byte loads and
 // stored transposed in LDS ([channel][pixel]), so every MFMA operand (8
 // pixels of one channel) is one 16-byte LDS read.  Partial sums meet in
-// dW with float atomics.  cin_p and cout_p are multiples of 16.
+// dW with float atomics.  cin_p and cout_p are multiples of 16.  The blocks
+// of the first column group also sum their staged dZ over the pixels: the
+// bias gradient gb (if not null), one float atomic per channel and block.
 constexpr int kWgPx = 32;             // pixels per step
 constexpr int kWgPitch = kWgPx + 8;   // LDS row pitch (bf16)
 template <int KS, int CT>
 __global__ __launch_bounds__(256) void k_wgrad_lds(const uint16_t* __restrict__ dZ, uint32_t cout_p,
                                                    const uint16_t* __restrict__ X, uint32_t cin_p, uint32_t P,
                                                    uint32_t H, uint32_t W, uint32_t chunk, float* __restrict__ gw,
-                                                   uint32_t kreal, uint32_t cout, uint32_t cin) {
+                                                   uint32_t kreal, uint32_t cout, uint32_t cin,
+                                                   float* __restrict__ gb) {
     constexpr int KW = 4 / CT;          // waves along k per channel tile
     constexpr int NB = 64 * KW;         // columns k of the block
+    constexpr int TPC = 256 / (16 * CT);   // threads per channel of the bias sum (4, 8, 16)
+    constexpr int PPT = kWgPx / TPC;       // ... each over 8, 4 or 2 pixels of a step
     __shared__ __align__(16) uint16_t dzT[16 * CT][kWgPitch];
     __shared__ __align__(16) uint16_t xT[NB][kWgPitch];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, pl = lane & 15, g = lane >> 4;
@@ -438,6 +429,9 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(const uint16_t* __restrict__ 
     const uint32_t p_begin = ch * chunk, p_end = min(P, p_begin + chunk);
     const uint32_t ctile = wv / KW, kq = wv % KW;   // this wave: channel tile, quarter of the columns
     const bool wave_on = co0 + 16 * ctile < cout_p;
+    const bool bias_sum = gb != nullptr && kgp == 0;
+    const uint32_t bc = tid / TPC, bq = tid % TPC;   // bias sum: channel co0 + bc, pixels PPT bq ..
+    float bsum = 0.0f;
     floatx4 acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -481,6 +475,16 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(const uint16_t* __restrict__ 
             for (int e = 0; e < 8; ++e) xT[8 * k8 + e][px] = v.h[e];
         }
         __syncthreads();
+        if (bias_sum) {   // pixels past p_end are zero in the tile
+            // one 16-, 8- or 4-byte LDS read (rows are 80 bytes apart)
+            uint16_t h[PPT];
+            const uint16_t* src = &dzT[bc][PPT * bq];
+            if constexpr (PPT == 8) *reinterpret_cast<uint4*>(h) = *reinterpret_cast<const uint4*>(src);
+            else if constexpr (PPT == 4) *reinterpret_cast<uint2*>(h) = *reinterpret_cast<const uint2*>(src);
+            else *reinterpret_cast<uint32_t*>(h) = *reinterpret_cast<const uint32_t*>(src);
+#pragma unroll
+            for (int e = 0; e < PPT; ++e) bsum += from_bf16(h[e]);
+        }
         if (wave_on) {
             Frag a;
             a.u = *reinterpret_cast<const uint4*>(&dzT[16 * ctile + pl][8 * g]);
@@ -492,6 +496,11 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(const uint16_t* __restrict__ 
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[j], 0, 0, 0);
             }
         }
+    }
+    if (bias_sum) {   // the TPC threads of a channel are adjacent lanes of one wave
+#pragma unroll
+        for (int off = TPC / 2; off > 0; off /= 2) bsum += __shfl_xor(bsum, off, 64);
+        if (bq == 0 && co0 + bc < cout) atomicAdd(&gb[co0 + bc], bsum);
     }
     if (!wave_on) return;
     // lane holds D[channel 16 ctile + 4 g + i][column 64 kq + 16 j + pl]; the
@@ -511,12 +520,6 @@ __global__ __launch_bounds__(256) void k_wgrad_lds(const uint16_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------- elementwise
-__global__ void k_relu_mask(const uint16_t* __restrict__ dY, const uint16_t* __restrict__ Y, size_t n,
-                            uint16_t* __restrict__ dZ) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        dZ[i] = from_bf16(Y[i]) > 0.0f ? dY[i] : (uint16_t)0;
-}
-
 // 2x2 max pooling, 8 channels (16 bytes) per step; the arg-max (0..3, the
 // first of equal maxima) is kept for the backward pass.  H and W are even and
 // C a multiple of 8; element indices fit in 32 bits.
@@ -557,24 +560,43 @@ __global__ void k_maxpool(const uint16_t* __restrict__ X, uint32_t B, uint32_t H
     }
 }
 
-// dX = scatter of dY to the arg-max position (+ add, the skip gradient)
+// dX = scatter of dY to the arg-max position (+ add, the skip gradient),
+// then zero where M (the ReLU output at dX's place, if not null) is not
+// positive.  8 channels (16 bytes) per step; C is a multiple of 8.
 __global__ void k_maxpool_bwd(const uint16_t* __restrict__ dY, const uint8_t* __restrict__ idx, uint32_t B,
                               uint32_t H, uint32_t W, uint32_t C, const uint16_t* __restrict__ add,
-                              uint16_t* __restrict__ dX) {
-    const size_t n = (size_t)B * H * W * C;
+                              const uint16_t* __restrict__ M, uint16_t* __restrict__ dX) {
+    const uint32_t c8n = C / 8;
+    const size_t n = (size_t)B * H * W * c8n;
     const uint32_t w = W / 2, h = H / 2;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t c = i % C;
-        size_t r = i / C;
+        const uint32_t c8 = i % c8n;
+        size_t r = i / c8n;
         const uint32_t x = r % W;
         r /= W;
         const uint32_t y = r % H;
         const uint32_t b = r / H;
-        const size_t o = (((size_t)b * h + y / 2) * w + x / 2) * C + c;
-        const uint32_t q = ((y & 1) << 1) | (x & 1);
-        float v = idx[o] == q ? from_bf16(dY[o]) : 0.0f;
-        if (add) v += from_bf16(add[i]);
-        dX[i] = to_bf16(v);
+        const size_t o = (((size_t)b * h + y / 2) * w + x / 2) * C + 8 * c8;
+        const uint8_t q = (uint8_t)(((y & 1) << 1) | (x & 1));
+        union {
+            uint4 u;
+            uint16_t h[8];
+        } g, a, m, out;
+        union {
+            uint2 u;
+            uint8_t b[8];
+        } ix;
+        g.u = *reinterpret_cast<const uint4*>(dY + o);
+        ix.u = *reinterpret_cast<const uint2*>(idx + o);
+        a.u = add ? reinterpret_cast<const uint4*>(add)[i] : make_uint4(0u, 0u, 0u, 0u);
+        m.u = M ? reinterpret_cast<const uint4*>(M)[i] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            float v = ix.b[e] == q ? from_bf16(g.h[e]) : 0.0f;
+            if (add) v += from_bf16(a.h[e]);
+            out.h[e] = M && !(from_bf16(m.h[e]) > 0.0f) ? (uint16_t)0 : to_bf16(v);
+        }
+        reinterpret_cast<uint4*>(dX)[i] = out.u;
     }
 }
 
@@ -597,29 +619,43 @@ __global__ void k_upcat(const uint16_t* __restrict__ D, uint32_t cu, const uint1
     }
 }
 
-// dD = sum over each 2x2 block of the first cu channels; dE = the rest
+// dD = sum over each 2x2 block of the first cu channels, zero where M (the
+// ReLU output that was upsampled, if not null) is not positive; dE = the
+// rest.  8 channels (16 bytes) per step; cu and ce are multiples of 8.
 __global__ void k_upcat_bwd(const uint16_t* __restrict__ dC, uint32_t cu, uint32_t ce, uint32_t B, uint32_t H,
-                            uint32_t W, uint16_t* __restrict__ dD, uint16_t* __restrict__ dE) {
-    const uint32_t ct = cu + ce;
+                            uint32_t W, const uint16_t* __restrict__ M, uint16_t* __restrict__ dD,
+                            uint16_t* __restrict__ dE) {
+    const uint32_t ct = cu + ce, cu8 = cu / 8, ce8 = ce / 8;
     const uint32_t h = H / 2, w = W / 2;
-    const size_t nd = (size_t)B * h * w * cu;
+    union V {
+        uint4 u;
+        uint16_t h[8];
+    };
+    const size_t nd = (size_t)B * h * w * cu8;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nd; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t c = i % cu;
-        size_t r = i / cu;
+        const uint32_t c = (uint32_t)(i % cu8) * 8;
+        size_t r = i / cu8;
         const uint32_t x = r % w;
         r /= w;
         const uint32_t y = r % h;
         const uint32_t b = r / h;
-        float s = 0.0f;
+        float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (uint32_t q = 0; q < 4; ++q) {
             const uint32_t yy = 2 * y + (q >> 1), xx = 2 * x + (q & 1);
-            s += from_bf16(dC[(((size_t)b * H + yy) * W + xx) * ct + c]);
+            V v;
+            v.u = *reinterpret_cast<const uint4*>(dC + (((size_t)b * H + yy) * W + xx) * ct + c);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s[e] += from_bf16(v.h[e]);
         }
-        dD[i] = to_bf16(s);
+        V m, out;
+        m.u = M ? reinterpret_cast<const uint4*>(M)[i] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) out.h[e] = M && !(from_bf16(m.h[e]) > 0.0f) ? (uint16_t)0 : to_bf16(s[e]);
+        reinterpret_cast<uint4*>(dD)[i] = out.u;
     }
-    const size_t ne = (size_t)B * H * W * ce;
+    const size_t ne = (size_t)B * H * W * ce8;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ne; i += (size_t)gridDim.x * blockDim.x)
-        dE[i] = dC[(i / ce) * ct + cu + (i % ce)];
+        reinterpret_cast<uint4*>(dE)[i] = *reinterpret_cast<const uint4*>(dC + (i / ce8) * ct + cu + 8 * (i % ce8));
 }
 
 // network input: float [P][in_ch] -> bf16 [P][cin_p] (zero padded channels)
@@ -756,16 +792,43 @@ __global__ void k_convert(const float* __restrict__ w, uint32_t cout, uint32_t c
     }
 }
 
+// where each layer's weights sit in the float vector and the bf16 matrices
+struct LayerTab {
+    static constexpr int kMax = 4 * 6 - 1;   // layers of a 6-level network
+    uint32_t n;
+    struct Entry {
+        uint32_t w_off, nw, cin, taps, cin_p, cout_p, kpad, kpad_t, wf_off, wd_off;
+    } e[kMax];
+};
+
+// One Adam step over the float parameters, which also refreshes the bf16
+// forward and input-gradient matrices of every weight it updates (their
+// padding stays zero from the full conversion) and clears the gradient for
+// the next backward pass.
 __global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
-                       const float* __restrict__ g, size_t n, float lr, float b1, float b2, float eps, float c1,
-                       float c2) {
+                       float* __restrict__ g, size_t n, float lr, float b1, float b2, float eps, float c1, float c2,
+                       LayerTab tab, uint16_t* __restrict__ Wf, uint16_t* __restrict__ Wd) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         const float gi = g[i];
         const float mi = b1 * m[i] + (1.0f - b1) * gi;
         const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        th[i] = th[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        const float t = th[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        th[i] = t;
+        g[i] = 0.0f;
+        uint32_t l = 0;
+        while (l + 1 < tab.n && i >= tab.e[l + 1].w_off) ++l;
+        const LayerTab::Entry& E = tab.e[l];
+        uint32_t r = (uint32_t)i - E.w_off;
+        if (r < E.nw) {   // a weight [co][tap][ci] (the layer's biases follow its weights)
+            const uint32_t ci = r % E.cin;
+            r /= E.cin;
+            const uint32_t tap = r % E.taps, co = r / E.taps;
+            const uint16_t b = to_bf16(t);
+            Wf[E.wf_off + (size_t)co * E.kpad + tap * E.cin_p + ci] = b;
+            Wd[E.wd_off + (size_t)ci * E.kpad_t + (E.taps - 1 - tap) * E.cout_p + co] = b;
+        }
     }
 }
 
@@ -905,7 +968,6 @@ sc_status ensure_acts(Unet* u, uint32_t B, uint32_t H, uint32_t W) {
         maxt = std::max(maxt, P * (size_t)(2 * u->widths[std::min(i + 1, L - 1)] + u->widths[i]));
     }
     T.g0 = take(maxt);
-    T.g1 = take(maxt);
     T.g2 = take(maxt);
     T.skip.assign(L, 0);
     for (uint32_t i = 0; i + 1 < L; ++i) T.skip[i] = take((P0 >> (2 * i)) * u->widths[i]);
@@ -936,7 +998,7 @@ uint32_t conv3_per_cu() {
 void conv_launch(hipStream_t st, uint32_t cus, uint64_t big_tile, const UnetLayer& L, const uint16_t* X, uint32_t P,
                  uint32_t H, uint32_t W, const uint16_t* Wt, uint32_t cin_p, uint32_t kpad, const float* bias, uint32_t cout_p,
                  uint32_t cout_real, uint16_t* Y, float* Yf, uint32_t y_stride, int relu,
-                 const uint16_t* X2 = nullptr, uint32_t c_split = 0) {
+                 const uint16_t* X2 = nullptr, uint32_t c_split = 0, const uint16_t* M = nullptr) {
     const uint32_t n_tiles = (P + 15) / 16;
     const uint32_t groups = (cout_p / 16 + 3) / 4;
     const size_t waves = (size_t)n_tiles * groups;
@@ -965,7 +1027,7 @@ void conv_launch(hipStream_t st, uint32_t cus, uint64_t big_tile, const UnetLaye
         const dim3 grid(gx, gy);
 #define SC_CONV3(RW, MODE)                                                                                          \
     hipLaunchKernelGGL((k_conv3<kConvTiles, RW, MODE>), grid, dim3(256), 0, st, X, X2, c_split, B, H, W, cin_p, Wt, \
-                       kpad, bias, cout_p, Y, y_stride, relu)
+                       kpad, bias, cout_p, Y, y_stride, relu, M)
         if (big) {
             if (mode == 0) SC_CONV3(kBigRW, 0);
             else if (mode == 1) SC_CONV3(kBigRW, 1);
@@ -978,13 +1040,13 @@ void conv_launch(hipStream_t st, uint32_t cus, uint64_t big_tile, const UnetLaye
 #undef SC_CONV3
     } else if (L.ks == 3)   // float output or partial channel tiles: the plain implicit GEMM
         hipLaunchKernelGGL(k_conv<3>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
-                           cout_real, Y, Yf, y_stride, 0u, relu);
+                           cout_real, Y, Yf, y_stride, 0u, relu, M);
     else if (Yf && cout_p == 16 && kpad <= 32 * kOutChunks)   // the output layer
         hipLaunchKernelGGL(k_conv1_out, dim3(std::max(1u, std::min((n_tiles + 3) / 4, cus * 8))), dim3(256), 0, st, X,
                            P, cin_p, Wt, kpad, bias, cout_real, Yf, y_stride, relu);
     else
         hipLaunchKernelGGL(k_conv<1>, dim3(grid), dim3(256), 0, st, X, P, H, W, cin_p, Wt, kpad, bias, cout_p,
-                           cout_real, Y, Yf, y_stride, 0u, relu);
+                           cout_real, Y, Yf, y_stride, 0u, relu, M);
 }
 
 }  // namespace
@@ -1049,10 +1111,12 @@ sc_status unet_forward_packed(Unet* u, bool keep_cat) {
 
 namespace {
 
-// gradient of one convolution: dZ (bf16, [P][cout_p] layout) given; writes
-// the weight and bias gradient and, if dX is not null, the input gradient
+// gradient of one convolution: dZ (bf16, [P][cout_p] layout) given; adds
+// the weight and bias gradient into u->grad and, if dX is not null, writes
+// the input gradient, already passed back through the ReLU whose output is
+// relu_out (same layout as dX) when that is not null
 void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint16_t* dZ, uint32_t P, uint32_t H,
-                   uint32_t W, uint16_t* dX) {
+                   uint32_t W, uint16_t* dX, const uint16_t* relu_out) {
     hipStream_t st = u->ctx->stream;
     float* g = u->grad.as<float>();
     const uint32_t taps = Ly.ks * Ly.ks;
@@ -1069,7 +1133,7 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
     const uint32_t grid = tiles * ((P + chunk - 1) / chunk);
 #define SC_WGRAD(KS_, CT_)                                                                                          \
     hipLaunchKernelGGL((k_wgrad_lds<KS_, CT_>), dim3(grid), dim3(256), 0, st, dZ, Ly.cout_p, Xin, Ly.cin_p, P, H, W, \
-                       chunk, g + Ly.w_off, kreal, Ly.cout, Ly.cin)
+                       chunk, g + Ly.w_off, kreal, Ly.cout, Ly.cin, g + Ly.b_off)
     if (Ly.ks == 3) {
         if (CT == 4) SC_WGRAD(3, 4);
         else if (CT == 2) SC_WGRAD(3, 2);
@@ -1080,79 +1144,74 @@ void conv_backward(Unet* u, const UnetLayer& Ly, const uint16_t* Xin, const uint
         else SC_WGRAD(1, 1);
     }
 #undef SC_WGRAD
-    // the weight and bias gradients add into u->grad, cleared once per backward pass
-    hipLaunchKernelGGL(k_bias_grad, dim3(std::min<uint32_t>(256, (P + 3) / 4)), dim3(256), 0, st, dZ, P, Ly.cout_p,
-                       Ly.cout, g + Ly.b_off);
+    // the weight and bias gradients add into u->grad, cleared before the backward pass
     if (dX)
         conv_launch(st, u->cus, u->ctx->conv_big_tile, Ly, dZ, P, H, W, u->wd.as<uint16_t>() + Ly.wd_off, Ly.cout_p,
-                    Ly.kpad_t, nullptr, Ly.cin_p, Ly.cin_p, dX, nullptr, Ly.cin_p, 0);
+                    Ly.kpad_t, nullptr, Ly.cin_p, Ly.cin_p, dX, nullptr, Ly.cin_p, 0, nullptr, 0, relu_out);
 }
 
 }  // namespace
 
 // Backward pass: dY (bf16 [P0][16], gradient of the prediction) in T.g0.
+// A gradient that flows back into a ReLU output leaves the kernel that
+// produces it (input-gradient convolution, split of the concatenation,
+// scatter through the pooling) already zeroed where that output is not
+// positive, so it is the next convolution's dZ as it stands.
 sc_status unet_backward_packed(Unet* u) {
     hipStream_t st = u->ctx->stream;
     const uint32_t L = (uint32_t)u->widths.size();
     uint16_t* A = u->acts.as<uint16_t>();
     UnetTensors& T = u->t;
-    uint16_t* gcur = A + T.g0;    // gradient w.r.t. the current tensor
-    uint16_t* gz = A + T.g1;      // masked gradient
-    uint16_t* gn = A + T.g2;      // gradient w.r.t. the previous tensor
-    size_t li = u->layers.size() - 1;
+    uint16_t* gcur = A + T.g0;    // dZ of the layer at hand
+    uint16_t* gn = A + T.g2;      // the gradient being produced
     const uint32_t P0 = u->B * u->H * u->W;
-    // every layer's weight and bias gradients add into the cleared buffer
-    hipLaunchKernelGGL(k_zero_f, dim3(blocks(u->n_params)), dim3(256), 0, st, u->grad.as<float>(), u->n_params);
-    // output layer (no activation): dZ = dY
+    // every layer's weight and bias gradients add into a cleared buffer (the
+    // Adam step leaves it cleared)
+    if (!u->grad_clear)
+        hipLaunchKernelGGL(k_zero_f, dim3(blocks(u->n_params)), dim3(256), 0, st, u->grad.as<float>(), u->n_params);
+    u->grad_clear = false;
+    // output layer (no activation): dZ = dY; its input is the last ReLU output
     {
-        const UnetLayer& Lo = u->layers[li];
         const uint16_t* xin = A + T.dec_b[0];
-        if (L == 1) xin = A + T.enc_b[0];
-        conv_backward(u, Lo, xin, gcur, P0, u->H, u->W, gn);
+        conv_backward(u, u->layers.back(), xin, gcur, P0, u->H, u->W, gn, xin);
         std::swap(gcur, gn);
     }
-    // decoder levels, shallow to deep
+    // decoder levels, shallow to deep; their layers are stored from the
+    // deepest level: index 2L + 2(L-2-i) + part
     for (uint32_t i = 0; i + 1 < L; ++i) {
         const uint32_t H = u->H >> i, W = u->W >> i, P = u->B * H * W;
-        for (int part = 1; part >= 0; --part) {
-            // decoder layers are stored from the deepest level: index 2L + 2(L-2-i) + part
-            li = 2 * L + 2 * (L - 2 - i) + (size_t)part;
-            const UnetLayer& Ly = u->layers[li];
-            const uint16_t* yout = A + (part == 1 ? T.dec_b[i] : T.dec_a[i]);
-            const uint16_t* xin = A + (part == 1 ? T.dec_a[i] : T.cat[i]);
-            const size_t n = (size_t)P * Ly.cout;
-            hipLaunchKernelGGL(k_relu_mask, dim3(blocks(n)), dim3(256), 0, st, gcur, yout, n, gz);
-            conv_backward(u, Ly, xin, gz, P, H, W, gn);
-            std::swap(gcur, gn);
-        }
-        // split the concat gradient: upsampled part -> deeper level, skip part kept
+        const size_t li = 2 * L + 2 * (L - 2 - i);
+        conv_backward(u, u->layers[li + 1], A + T.dec_a[i], gcur, P, H, W, gn, A + T.dec_a[i]);
+        std::swap(gcur, gn);
+        conv_backward(u, u->layers[li], A + T.cat[i], gcur, P, H, W, gn, nullptr);   // input: the concatenation
+        std::swap(gcur, gn);
+        // split the concatenation's gradient: the upsampled part to the deeper
+        // level's output (masked by it), the skip part kept for the encoder
         const uint32_t cu = (i == L - 2) ? u->widths[L - 1] : u->widths[i + 1];
-        hipLaunchKernelGGL(k_upcat_bwd, dim3(blocks((size_t)P * (cu + u->widths[i]))), dim3(256), 0, st, gcur, cu,
-                           u->widths[i], u->B, H, W, gn, A + T.skip[i]);
+        const uint16_t* deeper = A + (i == L - 2 ? T.enc_b[L - 1] : T.dec_b[i + 1]);
+        hipLaunchKernelGGL(k_upcat_bwd, dim3(blocks((size_t)P * (cu + u->widths[i]) / 8)), dim3(256), 0, st, gcur,
+                           cu, u->widths[i], u->B, H, W, deeper, gn, A + T.skip[i]);
         std::swap(gcur, gn);
     }
     // encoder levels, deep to shallow
     for (int i = (int)L - 1; i >= 0; --i) {
         const uint32_t H = u->H >> i, W = u->W >> i, P = u->B * H * W;
-        for (int part = 1; part >= 0; --part) {
-            const UnetLayer& Ly = u->layers[2 * i + part];
-            const uint16_t* yout = A + (part == 1 ? T.enc_b[i] : T.enc_a[i]);
-            const uint16_t* xin = part == 1 ? A + T.enc_a[i] : (i > 0 ? A + T.pool[i] : A + T.in);
-            const size_t n = (size_t)P * Ly.cout;
-            hipLaunchKernelGGL(k_relu_mask, dim3(blocks(n)), dim3(256), 0, st, gcur, yout, n, gz);
-            const bool need_dx = !(i == 0 && part == 0);
-            conv_backward(u, Ly, xin, gz, P, H, W, need_dx ? gn : nullptr);
-            if (need_dx) std::swap(gcur, gn);
+        conv_backward(u, u->layers[2 * i + 1], A + T.enc_a[i], gcur, P, H, W, gn, A + T.enc_a[i]);
+        std::swap(gcur, gn);
+        if (i == 0) {   // the network input needs no gradient
+            conv_backward(u, u->layers[0], A + T.in, gcur, P, H, W, nullptr, nullptr);
+            break;
         }
-        if (i > 0) {
-            // through the pooling into level i-1, plus that level's skip gradient
-            const uint32_t c = u->widths[i - 1];
-            const size_t n = (size_t)u->B * (2 * H) * (2 * W) * c;
-            hipLaunchKernelGGL(k_maxpool_bwd, dim3(blocks(n)), dim3(256), 0, st, gcur,
-                               reinterpret_cast<const uint8_t*>(A + T.pool_idx[i]), u->B, 2 * H, 2 * W, c,
-                               A + T.skip[i - 1], gn);
-            std::swap(gcur, gn);
-        }
+        conv_backward(u, u->layers[2 * i], A + T.pool[i], gcur, P, H, W, gn, nullptr);   // input: the pooling
+        std::swap(gcur, gn);
+        // through the pooling into level i-1, plus that level's skip
+        // gradient, masked by that level's output
+        const uint32_t c = u->widths[i - 1];
+        const size_t n8 = (size_t)u->B * (2 * H) * (2 * W) * c / 8;
+        hipLaunchKernelGGL(k_maxpool_bwd, dim3(blocks(n8)), dim3(256), 0, st, gcur,
+                           reinterpret_cast<const uint8_t*>(A + T.pool_idx[i]), u->B, 2 * H, 2 * W, c,
+                           A + T.skip[i - 1], A + T.enc_b[i - 1], gn);
+        std::swap(gcur, gn);
     }
     SC_HIP(hipGetLastError());
     return SC_OK;
@@ -1192,10 +1251,19 @@ sc_status unet_adam(Unet* u, float lr) {
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = (float)(1.0 - pow(0.9, (double)u->step));
     const float c2 = (float)(1.0 - pow(0.999, (double)u->step));
+    LayerTab tab{};
+    tab.n = (uint32_t)u->layers.size();
+    for (uint32_t l = 0; l < tab.n; ++l) {
+        const UnetLayer& L = u->layers[l];
+        tab.e[l] = LayerTab::Entry{(uint32_t)L.w_off, (uint32_t)(L.b_off - L.w_off), L.cin, L.ks * L.ks, L.cin_p,
+                                   L.cout_p, L.kpad, L.kpad_t, (uint32_t)L.wf_off, (uint32_t)L.wd_off};
+    }
     hipLaunchKernelGGL(k_adam, dim3(blocks(u->n_params)), dim3(256), 0, u->ctx->stream, u->theta.as<float>(),
-                       u->m.as<float>(), u->v.as<float>(), u->grad.as<float>(), u->n_params, lr, b1, b2, 1e-8f, c1, c2);
+                       u->m.as<float>(), u->v.as<float>(), u->grad.as<float>(), u->n_params, lr, b1, b2, 1e-8f, c1, c2,
+                       tab, u->wf.as<uint16_t>(), u->wd.as<uint16_t>());
     SC_HIP(hipGetLastError());
-    return unet_refresh(u);
+    u->grad_clear = true;
+    return SC_OK;
 }
 
 sc_status unet_features(Unet* u, const sc_aov& in, uint32_t w, uint32_t h) {
@@ -1251,7 +1319,8 @@ sc_status unet_layer_backward(Unet* u, uint32_t layer, const float* X, const flo
     const size_t nw = (size_t)L.cout * L.ks * L.ks * L.cin;
     hipLaunchKernelGGL(k_zero_f, dim3(blocks(nw + L.cout)), dim3(256), 0, st, u->grad.as<float>() + L.w_off,
                        nw + L.cout);
-    conv_backward(u, L, xb.as<uint16_t>(), dzb.as<uint16_t>(), P, h, w, dX ? dxb.as<uint16_t>() : nullptr);
+    u->grad_clear = false;
+    conv_backward(u, L, xb.as<uint16_t>(), dzb.as<uint16_t>(), P, h, w, dX ? dxb.as<uint16_t>() : nullptr, nullptr);
     if (dX)
         hipLaunchKernelGGL(k_unpack_bf16, dim3(blocks((size_t)P * L.cin)), dim3(256), 0, st, dxb.as<uint16_t>(), P,
                            L.cin_p, L.cin, dX);
