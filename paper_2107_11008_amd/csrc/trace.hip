@@ -6,7 +6,8 @@
 //   raygen -> [closest hit -> classify (sort by material, compact) ->
 //              shade dielectric | shade diffuse (+ shadow ray) ->
 //              any hit (shadow) ] x depth -> film
-// Queue appends use one atomic per wave (ballot + mbcnt prefix).
+// Queue appends use one atomic per block and 8 items per thread (ballot +
+// mbcnt prefix within a wave, offsets of the waves in LDS).
 // Traversal kernels keep every lane busy: a wave takes batches of rays and
 // refills the lanes whose ray is finished while the others go on; the
 // traversal stack lives in LDS (spilling to scratch only for deep trees) and
@@ -36,28 +37,53 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Append `val` to queue q for threads with pred; one atomic per block.
-// Every thread of the block must call this (block size a multiple of 64,
-// at most 1024).
-__device__ __forceinline__ void block_push(bool pred, uint32_t val, uint32_t* q, uint32_t* cnt) {
-    __shared__ uint32_t s_w[16];
+// Queue appends of the streaming stages.  A block takes up to kPushItems
+// items per thread between two appends (item k of thread t is item
+// k * blockDim.x + t of the block's range); bit k of `keep` marks the items
+// to append, val(k) gives the value, and the kept items go to the queue in
+// item order with one atomic per block and queue.  Appends to one queue all
+// hit one counter, and same-address atomics serialise in L2: at one atomic
+// per 256 items they, not the bytes moved, bounded these stages.  Every
+// thread of the block must call this (block size a multiple of 64, at most
+// 1024).
+constexpr uint32_t kPushItems = 8;
+
+// Items per thread between two appends for a launch of n items: one sweep
+// of the grid when it can (small launches keep one item per thread and
+// every block busy), at most kPushItems.
+__device__ __forceinline__ uint32_t push_items(uint32_t n) {
+    const uint32_t threads = gridDim.x * blockDim.x;
+    const uint32_t per = (n + threads - 1) / threads;
+    return per < 1u ? 1u : (per > kPushItems ? kPushItems : per);
+}
+
+template <typename ValFn>
+__device__ __forceinline__ void block_push(uint32_t keep, ValFn val, uint32_t* q, uint32_t* cnt) {
+    __shared__ uint32_t s_off[kPushItems * 16];   // per (item, wave): count, then offset in the block's run
     __shared__ uint32_t s_base;
-    const unsigned long long m = __ballot(pred);
-    const uint32_t w = threadIdx.x >> 6;
-    if (lane_id() == 0) s_w[w] = (uint32_t)__popcll(m);
+    const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    unsigned long long m[kPushItems];
+#pragma unroll
+    for (uint32_t k = 0; k < kPushItems; ++k) m[k] = __ballot((keep >> k) & 1u);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (uint32_t k = 0; k < kPushItems; ++k) s_off[k * nw + w] = (uint32_t)__popcll(m[k]);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t tot = 0;
-        for (uint32_t k = 0; k < (blockDim.x >> 6); ++k) {
-            const uint32_t c = s_w[k];
-            s_w[k] = tot;
+        for (uint32_t j = 0; j < kPushItems * nw; ++j) {
+            const uint32_t c = s_off[j];
+            s_off[j] = tot;
             tot += c;
         }
         s_base = tot ? atomicAdd(cnt, tot) : 0u;
     }
     __syncthreads();
-    if (pred) q[s_base + s_w[w] + lanes_below(m)] = val;
-    __syncthreads();   // s_w and s_base are reused by the next call
+#pragma unroll
+    for (uint32_t k = 0; k < kPushItems; ++k)
+        if ((keep >> k) & 1u) q[s_base + s_off[k * nw + w] + lanes_below(m[k])] = val(k);
+    __syncthreads();   // s_off and s_base are reused by the next call
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -303,53 +329,53 @@ __global__ void k_raygen(CamInfo ci, WaveDev wl, PathState P, uint32_t n, uint32
 __global__ void k_classify(DevScene S, PathState P, const uint32_t* __restrict__ queue, uint32_t* counts,
                            uint32_t* q_diffuse, uint32_t* q_dielectric, uint32_t cap) {
     const uint32_t n = counts[QC_CUR];
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const uint32_t i = base + threadIdx.x;
-        bool to_diff = false, to_diel = false;
-        uint32_t pid = 0;
-        if (i < n) {
-            pid = queue[i];
+    const uint32_t per = push_items(n), span = blockDim.x * per;
+    for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+        uint32_t diff = 0, diel = 0;
+        for (uint32_t k = 0; k < per; ++k) {
+            const uint32_t i = base + k * blockDim.x + threadIdx.x;
+            if (i >= n) break;
+            const uint32_t pid = queue[i];
             const uint32_t prim = P.prim[pid];
-            if (prim != 0xffffffffu) {
-                const uint32_t type = S.mat[S.tri_obj[prim]].type;
-                if (type == SC_MAT_EMISSIVE) {
-                    CamPath c = load_path(P, pid);
-                    camera_emission(S, load_hit(P, pid), c);
-                    P.L[pid] = c.L;
-                } else if (type == SC_MAT_DIELECTRIC) {
-                    to_diel = true;
-                } else {
-                    to_diff = true;
-                }
+            if (prim == 0xffffffffu) continue;
+            const uint32_t type = S.mat[S.tri_obj[prim]].type;
+            if (type == SC_MAT_EMISSIVE) {
+                CamPath c = load_path(P, pid);
+                camera_emission(S, load_hit(P, pid), c);
+                P.L[pid] = c.L;
+            } else if (type == SC_MAT_DIELECTRIC) {
+                diel |= 1u << k;
+            } else {
+                diff |= 1u << k;
             }
         }
-        block_push(to_diel, pid, q_dielectric, counts + QC_DIEL);
-        block_push(to_diff, pid, q_diffuse, counts + QC_DIFF);
+        auto pid_of = [&](uint32_t k) { return queue[base + k * blockDim.x + threadIdx.x]; };
+        block_push(diel, pid_of, q_dielectric, counts + QC_DIEL);
+        block_push(diff, pid_of, q_diffuse, counts + QC_DIFF);
     }
 }
 
 __global__ void k_shade_dielectric(DevScene S, CamInfo ci, PathState P, uint32_t depth, const uint32_t* __restrict__ q,
                                    uint32_t* counts, uint32_t* q_next) {
     const uint32_t n = counts[QC_DIEL];
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const uint32_t i = base + threadIdx.x;
-        bool cont = false;
-        uint32_t pid = 0;
-        if (i < n) {
-            pid = q[i];
+    const uint32_t per = push_items(n), span = blockDim.x * per;
+    for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+        uint32_t cont = 0;
+        for (uint32_t k = 0; k < per; ++k) {
+            const uint32_t i = base + k * blockDim.x + threadIdx.x;
+            if (i >= n) break;
+            const uint32_t pid = q[i];
             uint32_t pix, sample, slot;
             pid_decode(ci, pid, pix, sample, slot);
             CamPath c = load_path(P, pid);
-            cont = camera_dielectric(S, ci.seed, pix, sample, slot, depth, ci.max_depth, load_hit(P, pid), c);
-            if (cont) {
+            if (camera_dielectric(S, ci.seed, pix, sample, slot, depth, ci.max_depth, load_hit(P, pid), c)) {
                 store_ray(P, pid, c);
                 P.T[pid] = c.T;
                 P.med[pid] = c.med;
+                cont |= 1u << k;
             }
         }
-        block_push(cont, pid, q_next, counts + QC_NEXT);
+        block_push(cont, [&](uint32_t k) { return q[base + k * blockDim.x + threadIdx.x]; }, q_next, counts + QC_NEXT);
     }
 }
 
@@ -361,20 +387,20 @@ __global__ void k_shade_diffuse(DevScene S, CamInfo ci, WaveDev wl, PathState P,
                                 uint32_t* counts, uint32_t* q_next, uint32_t* q_shadow) {
     const PMapDev pm = PM ? pm_arg : PMapDev{};
     const uint32_t n = counts[QC_DIFF];
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const uint32_t i = base + threadIdx.x;
-        bool cont = false;
-        ShadowReq sr;
-        sr.shoot = false;
-        uint32_t pid = 0;
-        if (i < n) {
-            pid = q[i];
+    const uint32_t per = push_items(n), span = blockDim.x * per;
+    for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+        uint32_t cont = 0, shoot = 0;
+        for (uint32_t k = 0; k < per; ++k) {
+            const uint32_t i = base + k * blockDim.x + threadIdx.x;
+            if (i >= n) break;
+            const uint32_t pid = q[i];
             uint32_t pix, sample, slot;
             pid_decode(ci, pid, pix, sample, slot);
             CamPath c = load_path(P, pid);
-            cont = camera_diffuse(S, wl, cmap, pm, ci.seed, pix, sample, slot, depth, ci.max_depth, load_hit(P, pid), c,
-                                  sr);
+            ShadowReq sr;
+            sr.shoot = false;
+            const bool more = camera_diffuse(S, wl, cmap, pm, ci.seed, pix, sample, slot, depth, ci.max_depth,
+                                             load_hit(P, pid), c, sr);
             P.L[pid] = c.L;
             P.flags[pid] = c.flags;
             if (sr.shoot) {
@@ -383,14 +409,17 @@ __global__ void k_shade_diffuse(DevScene S, CamInfo ci, WaveDev wl, PathState P,
                 P.stmax[pid] = sr.tmax;
                 P.sexcl[pid] = sr.excl;
                 P.scontrib[pid] = sr.contrib;
+                shoot |= 1u << k;
             }
-            if (cont) {
+            if (more) {
                 store_ray(P, pid, c);
                 P.T[pid] = c.T;
+                cont |= 1u << k;
             }
         }
-        block_push(sr.shoot, pid, q_shadow, counts + QC_SHADOW);
-        block_push(cont, pid, q_next, counts + QC_NEXT);
+        auto pid_of = [&](uint32_t k) { return q[base + k * blockDim.x + threadIdx.x]; };
+        block_push(shoot, pid_of, q_shadow, counts + QC_SHADOW);
+        block_push(cont, pid_of, q_next, counts + QC_NEXT);
     }
 }
 
@@ -454,26 +483,27 @@ __device__ __forceinline__ void ph_stat(DevCounters* C, const PhInfo& pi, int ou
 
 __global__ void k_photon_emit(DevScene S, WaveDev wl, PhInfo pi, uint32_t n, PhotonState Ph, uint32_t* queue,
                               uint32_t* counts, DevCounters* C) {
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const uint32_t i = base + threadIdx.x;
-        bool alive = false;
-        if (i < n) {
+    const uint32_t per = push_items(n), span = blockDim.x * per;
+    for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+        uint32_t alive = 0;
+        for (uint32_t k = 0; k < per; ++k) {
+            const uint32_t i = base + k * blockDim.x + threadIdx.x;
+            if (i >= n) break;
             PhotonPath ph;
-            alive = photon_emit(S, wl, pi.seed, pi.n_total, pi.p0 + i, ph);
-            if (!alive) {
+            if (!photon_emit(S, wl, pi.seed, pi.n_total, pi.p0 + i, ph)) {
                 if (pi.stats) atomicAdd(&C->ph_count[SC_PH_EMIT_DEAD], 1ull);
-            } else {
-                Ph.ox[i] = ph.o.x; Ph.oy[i] = ph.o.y; Ph.oz[i] = ph.o.z;
-                Ph.dx[i] = ph.d.x; Ph.dy[i] = ph.d.y; Ph.dz[i] = ph.d.z;
-                Ph.phi[i] = ph.phi;
-                Ph.lambda[i] = ph.lam;
-                Ph.slot[i] = ph.slot;
-                Ph.spec[i] = ph.spec;
-                Ph.med[i] = ph.med;
+                continue;
             }
+            Ph.ox[i] = ph.o.x; Ph.oy[i] = ph.o.y; Ph.oz[i] = ph.o.z;
+            Ph.dx[i] = ph.d.x; Ph.dy[i] = ph.d.y; Ph.dz[i] = ph.d.z;
+            Ph.phi[i] = ph.phi;
+            Ph.lambda[i] = ph.lam;
+            Ph.slot[i] = ph.slot;
+            Ph.spec[i] = ph.spec;
+            Ph.med[i] = ph.med;
+            alive |= 1u << k;
         }
-        block_push(alive, i, queue, counts + QC_CUR);
+        block_push(alive, [&](uint32_t k) { return base + k * blockDim.x + threadIdx.x; }, queue, counts + QC_CUR);
     }
 }
 
@@ -567,46 +597,53 @@ __global__ void k_photon_event(DevScene S, WaveDev wl, PhInfo pi, uint32_t depth
                                const uint32_t* __restrict__ queue, uint32_t* counts, uint32_t* q_next,
                                unsigned long long* acc, uint32_t* cnt_map, DevCounters* C) {
     const uint32_t n = counts[QC_CUR];
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const uint32_t i = base + threadIdx.x;
-        bool cont = false, dep = false;
-        uint32_t id = 0, cell_ch = 0;
-        unsigned long long q = 0;
-        float phi = 0.0f;
-        Deposit dp;
-        dp.cell_ch = -1;
-        if (i < n) {
-            id = queue[i];
-            PhotonPath ph;
-            ph.o = F3{Ph.ox[id], Ph.oy[id], Ph.oz[id]};
-            ph.d = F3{Ph.dx[id], Ph.dy[id], Ph.dz[id]};
-            ph.phi = Ph.phi[id];
-            ph.lam = Ph.lambda[id];
-            ph.slot = Ph.slot[id];
-            ph.spec = Ph.spec[id];
-            ph.med = Ph.med[id];
-            int outcome = -1;
-            cont = photon_event(S, wl, pi.seed, pi.p0 + id, depth, pi.max_depth, pi.general != 0,
-                                HitRec{Ph.t[id], Ph.u[id], Ph.v[id], Ph.prim[id]}, ph, outcome, dp);
-            if (cont) {
-                Ph.ox[id] = ph.o.x; Ph.oy[id] = ph.o.y; Ph.oz[id] = ph.o.z;
-                Ph.dx[id] = ph.d.x; Ph.dy[id] = ph.d.y; Ph.dz[id] = ph.d.z;
-                Ph.phi[id] = ph.phi;
-                Ph.spec[id] = ph.spec;
-                Ph.med[id] = ph.med;
+    const uint32_t per = push_items(n), span = blockDim.x * per;
+    for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
+        uint32_t cont = 0;
+        for (uint32_t k = 0; k < per; ++k) {
+            if (base + k * blockDim.x >= n) break;   // uniform over the block: the deposits below are wave-collective
+            const uint32_t i = base + k * blockDim.x + threadIdx.x;
+            bool dep = false;
+            uint32_t id = 0, cell_ch = 0;
+            unsigned long long fx = 0;
+            float phi = 0.0f;
+            Deposit dp;
+            dp.cell_ch = -1;
+            if (i < n) {
+                id = queue[i];
+                PhotonPath ph;
+                ph.o = F3{Ph.ox[id], Ph.oy[id], Ph.oz[id]};
+                ph.d = F3{Ph.dx[id], Ph.dy[id], Ph.dz[id]};
+                ph.phi = Ph.phi[id];
+                ph.lam = Ph.lambda[id];
+                ph.slot = Ph.slot[id];
+                ph.spec = Ph.spec[id];
+                ph.med = Ph.med[id];
+                int outcome = -1;
+                const bool more = photon_event(S, wl, pi.seed, pi.p0 + id, depth, pi.max_depth, pi.general != 0,
+                                               HitRec{Ph.t[id], Ph.u[id], Ph.v[id], Ph.prim[id]}, ph, outcome, dp);
+                if (more) {
+                    Ph.ox[id] = ph.o.x; Ph.oy[id] = ph.o.y; Ph.oz[id] = ph.o.z;
+                    Ph.dx[id] = ph.d.x; Ph.dy[id] = ph.d.y; Ph.dz[id] = ph.d.z;
+                    Ph.phi[id] = ph.phi;
+                    Ph.spec[id] = ph.spec;
+                    Ph.med[id] = ph.med;
+                    cont |= 1u << k;
+                } else {
+                    ph_stat(C, pi, outcome, ph.phi);
+                }
+                if (dp.cell_ch >= 0) {
+                    dep = true;
+                    cell_ch = (uint32_t)dp.cell_ch;
+                    fx = __double2ull_rn((double)ph.phi * pi.scale);
+                    phi = ph.phi;
+                }
             }
-            if (!cont) ph_stat(C, pi, outcome, ph.phi);
-            if (dp.cell_ch >= 0) {
-                dep = true;
-                cell_ch = (uint32_t)dp.cell_ch;
-                q = __double2ull_rn((double)ph.phi * pi.scale);
-                phi = ph.phi;
-            }
+            if (pi.general) pm_append(dep, pi.rec, dp, cell_ch, phi, pi.p0 + id);
+            else deposit(dep, cell_ch, fx, acc, cnt_map, pi.touched);
         }
-        if (pi.general) pm_append(dep, pi.rec, dp, cell_ch, phi, pi.p0 + id);
-        else deposit(dep, cell_ch, q, acc, cnt_map, pi.touched);
-        block_push(cont, id, q_next, counts + QC_NEXT);
+        block_push(cont, [&](uint32_t k) { return queue[base + k * blockDim.x + threadIdx.x]; }, q_next,
+                   counts + QC_NEXT);
     }
 }
 
