@@ -246,6 +246,12 @@ typedef struct {
 #define SC_OPT_PHOTON_STAGED_DEPTH 6 /* the same switch for photon paths (default 1: after the
                                       * first bounce every photon is finished by one lane) */
 #define SC_OPT_PHOTON_CAP 7   /* photons per photon-pass chunk (1024..2^28, default 1<<24) */
+#define SC_OPT_BVH_BUILDER 8  /* tree of later sc_build_bvh / sc_bvh_rebuild calls: 0 = binary radix
+                               * tree over 36-bit Morton codes (Karras, HPG 2012), 1 = parallel
+                               * locally-ordered clustering (Meister and Bittner, IEEE TVCG 2018),
+                               * 2 = clustering from 2^20 triangles up, radix tree below (default);
+                               * both trees are collapsed to the same wide-node layout and give
+                               * the same hits bit for bit */
 
 uint32_t sc_abi_version(void);
 const char* sc_last_error(void);

@@ -45,6 +45,7 @@ SC_OPT_STAGED_DEPTH = 4
 SC_OPT_CONV_BIG_TILE = 5
 SC_OPT_PHOTON_STAGED_DEPTH = 6
 SC_OPT_PHOTON_CAP = 7
+SC_OPT_BVH_BUILDER = 8
 
 
 ABI_VERSION = 6   # must match SC_ABI_VERSION in include/sc.h

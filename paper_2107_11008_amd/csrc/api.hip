@@ -131,6 +131,10 @@ sc_status sc_set_option(sc_ctx* ctx, int32_t option, int64_t value) {
             if (value < 1024 || value > (int64_t)1 << 28) return set_error(SC_EINVAL, "photon cap out of range");
             ctx->c.photon_cap = (uint64_t)value;
             return SC_OK;
+        case SC_OPT_BVH_BUILDER:
+            if (value < 0 || value > 2) return set_error(SC_EINVAL, "BVH builder must be 0, 1 or 2");
+            ctx->c.bvh_builder = (uint32_t)value;
+            return SC_OK;
         case SC_OPT_CONV_BIG_TILE:
             if (value < 0 || value > ((int64_t)1 << 32)) return set_error(SC_EINVAL, "tile threshold out of range");
             ctx->c.conv_big_tile = (uint64_t)value;

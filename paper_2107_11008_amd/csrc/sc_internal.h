@@ -95,6 +95,7 @@ struct Ctx {
     // photons per photon-pass chunk (2^24 photons of the large scene in one
     // chunk: 34.8 / 29.8 / 27.5 ms per pass at 2^22 / 2^23 / 2^24; ~1.5 GB)
     uint64_t photon_cap = 1ull << 24;
+    uint32_t bvh_builder = 2;   // 0: radix tree over Morton codes, 1: locally-ordered clustering, 2: by size
     DevBuf counters;   // DevCounters
     DevBuf work;       // per-launch work counters of the traversal kernels
     uint32_t work_slot = 0;

@@ -1,6 +1,7 @@
-"""Structural invariants of the GPU-built wide BVH: every triangle sits in
-exactly one leaf, leaf triangles are the scene's own vertices, and every
-child box contains everything below it."""
+"""Structural invariants of the GPU-built wide BVH (both builders: the
+radix tree over Morton codes and the locally-ordered clustering): every
+triangle sits in exactly one leaf, leaf triangles are the scene's own
+vertices, and every child box contains everything below it."""
 import numpy as np
 import pytest
 
@@ -48,11 +49,13 @@ def _check_tree(scene, nodes, tris, width, leaf_max):
     assert visited == len(nodes)
 
 
+@pytest.mark.parametrize("builder", [0, 1])
 @pytest.mark.parametrize("which,width,leaf", [("c1", 8, 4), ("c1", 4, 1), ("c2s", 8, 4), ("c2s", 4, 8),
                                               ("one", 8, 4), ("two", 8, 1)])
-def test_bvh_structure(which, width, leaf):
+def test_bvh_structure(which, width, leaf, builder):
     import paper_2107_11008_amd as sc
     ctx = sc.Context(0)
+    ctx.set_option(sc._sc.SC_OPT_BVH_BUILDER, builder)
     if which == "c1":
         scene = sg.config1()["scene"]
     elif which == "c2s":
@@ -142,3 +145,87 @@ def test_failed_rebuild_leaves_no_tree():
     h = ctx.build_bvh(s, out=h)   # usable again
     img = ctx.render(h, c["camera"], 1, 2, c["wavelengths"], 1)
     assert np.isfinite(img["rgb"].cpu().numpy()).all()
+
+
+def _rays(rng, n, scene=None):
+    O = rng.uniform(-3, 3, size=(n, 3)).astype(np.float32)
+    D = rng.normal(size=(n, 3))
+    if scene is not None:   # a third of the rays aimed at vertices
+        k = n // 3
+        tgt = scene.V[rng.integers(0, len(scene.V), size=k)]
+        D[:k] = tgt - O[:k]
+    D = (D / np.linalg.norm(D, axis=1, keepdims=True)).astype(np.float32)
+    return O, D
+
+
+@pytest.mark.parametrize("which", ["c1", "c2s", "c2"])
+def test_clustering_tree_gives_the_same_hits(which):
+    """Closest hits (t, triangle, barycentrics) from the clustering tree
+    equal the radix tree's bit for bit (ties between equal t go to the
+    smaller triangle index whatever the tree), and so do occlusion tests;
+    the clustering tree needs fewer node fetches per ray."""
+    import torch
+    import paper_2107_11008_amd as sc
+    ctx = sc.Context(0)
+    scene = {"c1": lambda: sg.config1()["scene"], "c2s": lambda: sg.config2(tri_scale=0.05, w=32, h=32)["scene"],
+             "c2": lambda: sg.config2()["scene"]}[which]()
+    rng = np.random.default_rng(11)
+    O, D = _rays(rng, 5003, scene)
+    res, visits = [], []
+    for builder in (0, 1):
+        ctx.set_option(sc._sc.SC_OPT_BVH_BUILDER, builder)
+        bvh = ctx.build_bvh(scene)
+        nodes, tris = bvh.export()
+        _check_tree(scene, nodes, tris, 8, 4)
+        ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 1)
+        ctx.reset_counters()
+        hits = _hits(ctx, bvh, O, D)
+        visits.append(ctx.counters()["node_visits"])
+        ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 0)
+        tmax = torch.full((len(O),), 1.5, dtype=torch.float32, device="cuda")
+        occ = ctx.occluded(bvh, torch.from_numpy(O).cuda(), torch.from_numpy(D).cuda(), tmax).cpu().numpy()
+        res.append((hits, occ))
+    for a, b in zip(res[0][0], res[1][0]):
+        assert a.tobytes() == b.tobytes()
+    assert np.array_equal(res[0][1], res[1][1])
+    print(f"{which}: node visits radix tree {visits[0]}, clustering {visits[1]}")
+
+
+def test_clustering_rebuild_is_deterministic():
+    """The clustering builder gives the same tree (up to the numbering of
+    the wide nodes) on a rebuild in place and on a fresh build."""
+    import paper_2107_11008_amd as sc
+    ctx = sc.Context(0)
+    ctx.set_option(sc._sc.SC_OPT_BVH_BUILDER, 1)
+    scene = sg.config2(tri_scale=0.05, w=32, h=32)["scene"]
+    dev = ctx.upload_scene(scene)
+    h = ctx.build_bvh(sg.config1()["scene"])
+    h = ctx.build_bvh(dev, out=h)
+    fresh = ctx.build_bvh(dev)
+    n1, t1 = h.export()
+    n2, t2 = fresh.export()
+    assert h.info() == fresh.info()
+    assert t1.tobytes() == t2.tobytes()
+    assert _canonical(n1) == _canonical(n2)
+
+
+def test_clustering_of_identical_triangles():
+    """3000 copies of one triangle (every union box the same, every Morton
+    code equal): the clustering still finishes with a valid tree, and every
+    ray through the triangle reports the smallest index."""
+    import torch
+    import paper_2107_11008_amd as sc
+    ctx = sc.Context(0)
+    ctx.set_option(sc._sc.SC_OPT_BVH_BUILDER, 1)
+    b = sg.SceneBuilder()
+    V = np.tile(np.array([[-1, -1, 0], [1, -1, 0], [0, 1, 0]], np.float64), (3000, 1))
+    b.add(sg.Mesh(V, np.arange(9000).reshape(3000, 3), np.tile([0, 0, 1.0], (9000, 1))),
+          dict(type=sg.MAT_DIFFUSE, rho_a=0.5))
+    scene = b.build(None)
+    bvh = ctx.build_bvh(scene)
+    nodes, tris = bvh.export()
+    _check_tree(scene, nodes, tris, 8, 4)
+    O = np.tile(np.array([[0.0, -0.2, 2.0]], np.float32), (64, 1))
+    D = np.tile(np.array([[0.0, 0.0, -1.0]], np.float32), (64, 1))
+    t, prim, _, _ = _hits(ctx, bvh, O, D)
+    assert np.all(prim == 0) and np.allclose(t, 2.0)
