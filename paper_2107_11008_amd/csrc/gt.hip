@@ -62,6 +62,69 @@ __global__ void k_cols_outline(const uint32_t* __restrict__ obj, const uint32_t*
     }
 }
 
+// The same outline in one launch for thickness t <= kTileHalo (a template
+// parameter, so the window loops unroll): a block
+// stages a kTileW x kTileH tile of ids with a t-pixel halo in LDS, takes the
+// row min / max over +-t columns (clipped to the image), then the column
+// min / max of those over +-t rows, and writes 4 output bytes per thread.
+constexpr uint32_t kTileW = 64, kTileH = 16, kTileHalo = 8;
+template <uint32_t t>
+__global__ __launch_bounds__(256) void k_outline_tile(const uint32_t* __restrict__ obj, uint32_t w, uint32_t h,
+                                                       uint8_t* __restrict__ out) {
+    static_assert(t >= 1 && t <= kTileHalo, "halo");
+    constexpr uint32_t lw = kTileW + 2 * t, lh = kTileH + 2 * t;   // the staged tile
+    __shared__ uint32_t s_obj[lh][lw];
+    __shared__ uint32_t s_mn[lh][kTileW], s_mx[lh][kTileW];
+    const uint32_t x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+    for (uint32_t k = threadIdx.x; k < lw * lh; k += blockDim.x) {
+        const uint32_t r = k / lw, c = k % lw;
+        const long long gy = (long long)y0 - t + r, gx = (long long)x0 - t + c;
+        s_obj[r][c] = (gy >= 0 && gy < h && gx >= 0 && gx < w) ? obj[(size_t)gy * w + gx] : 0u;
+    }
+    __syncthreads();
+    // rows: staged row r, output column c (image column x0 + c)
+    for (uint32_t k = threadIdx.x; k < lh * kTileW; k += blockDim.x) {
+        const uint32_t r = k / kTileW, c = k % kTileW;
+        uint32_t a = 0xffffffffu, b = 0u;
+#pragma unroll
+        for (uint32_t d = 0; d <= 2 * t; ++d) {
+            const long long gx = (long long)x0 + c + d - t;
+            if (gx < 0 || gx >= w) continue;
+            const uint32_t v = s_obj[r][c + d];
+            a = v < a ? v : a;
+            b = v > b ? v : b;
+        }
+        s_mn[r][c] = a;
+        s_mx[r][c] = b;
+    }
+    __syncthreads();
+    // columns: 4 consecutive output pixels per thread
+    const uint32_t c4 = (threadIdx.x % (kTileW / 4)) * 4, r = threadIdx.x / (kTileW / 4);
+    const uint32_t y = y0 + r;
+    if (r >= kTileH || y >= h) return;
+    uint32_t res = 0;
+    for (uint32_t e = 0; e < 4; ++e) {
+        const uint32_t c = c4 + e, x = x0 + c;
+        if (x >= w) break;
+        uint32_t a = 0xffffffffu, b = 0u;
+#pragma unroll
+        for (uint32_t d = 0; d <= 2 * t; ++d) {
+            const long long gy = (long long)y + d - t;
+            if (gy < 0 || gy >= h) continue;
+            a = s_mn[r + d][c] < a ? s_mn[r + d][c] : a;
+            b = s_mx[r + d][c] > b ? s_mx[r + d][c] : b;
+        }
+        const uint32_t o = s_obj[r + t][c + t];
+        res |= (uint32_t)((o != 0u && (a != o || b != o)) ? 1 : 0) << (8 * e);
+    }
+    const size_t i = (size_t)y * w + x0 + c4;
+    if (x0 + c4 + 4 <= w && (reinterpret_cast<uintptr_t>(out + i) & 3u) == 0) {
+        *reinterpret_cast<uint32_t*>(out + i) = res;
+    } else {
+        for (uint32_t e = 0; e < 4 && x0 + c4 + e < w; ++e) out[i + e] = (uint8_t)(res >> (8 * e));
+    }
+}
+
 // occlusion boundary: the near side of a depth jump larger than rel * depth
 __global__ void k_occlusion(const float* __restrict__ depth, uint32_t w, uint32_t h, float rel,
                             uint8_t* __restrict__ out) {
@@ -110,6 +173,18 @@ sc_status sc_outline(sc_ctx* ctx, const uint32_t* obj, uint32_t w, uint32_t h, u
     if (w == 0 || h == 0) return SC_OK;
     scl::Ctx& c = ctx->c;
     const size_t n = (size_t)w * h;
+    if (thickness <= kTileHalo) {   // one launch through LDS tiles
+        const dim3 grid((w + kTileW - 1) / kTileW, (h + kTileH - 1) / kTileH);
+        switch (thickness) {
+#define SC_OUTLINE(T) \
+    case T: hipLaunchKernelGGL(k_outline_tile<T>, grid, dim3(256), 0, c.stream, obj, w, h, out); break;
+            SC_OUTLINE(1) SC_OUTLINE(2) SC_OUTLINE(3) SC_OUTLINE(4)
+            SC_OUTLINE(5) SC_OUTLINE(6) SC_OUTLINE(7) SC_OUTLINE(8)
+#undef SC_OUTLINE
+        }
+        SC_HIP(hipGetLastError());
+        return SC_OK;
+    }
     SC_TRY(c.aos.ensure(std::max(c.aos.bytes, 2 * 4 * n + 512)));
     c.aos_n = 0;   // the SoA ray staging is reused as scratch here
     uint32_t* mn = c.aos.as<uint32_t>();

@@ -42,6 +42,22 @@ def test_outline_matches_definition(rendered, t):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("t", [1, 3, 8, 12])
+@pytest.mark.parametrize("w,h", [(131, 37), (64, 16), (1, 5), (200, 1)])
+def test_outline_ragged_images(rendered, w, h, t):
+    """Object-id images whose sides are not multiples of the 64 x 16 tile
+    (and single rows or columns), thicknesses inside the one-launch tile
+    path (<= 8) and past it (the two-pass path): equal to the definition."""
+    import torch
+    ctx = rendered[0]
+    rng = np.random.default_rng(w * 1000 + h + t)
+    ids = rng.integers(0, 4, size=(h, w)).astype(np.uint32)
+    ids = np.where(rng.uniform(size=(h, w)) < 0.8, np.repeat(ids[:, :1], w, 1), ids)   # runs of one id
+    got = ctx.outline(torch.from_numpy(ids.view(np.int32)).cuda(), t).cpu().numpy()
+    ref = gt.outline(ids, t)
+    assert np.array_equal(got, ref)
+
+
 def test_occlusion_matches_definition(rendered):
     ctx, c, bvh, _ = rendered
     r = ctx.render(bvh, c["camera"], 1, 1, c["wavelengths"], 1, outputs=("depth",))
