@@ -40,6 +40,9 @@ VALU_PEAK_GOPS = 256 * 64 * 2.4
 NODE_BYTES, TRI_BYTES = 256, 36          # uncompressed 8-wide node; a triangle's three vertices
 RAY_IN, HIT_OUT, OCC_OUT = 32, 16, 4     # ray record read; closest hit written; occlusion written
 OPS_PER_NODE, OPS_PER_TRI = 14 * 8, 40   # VALU operations per node visit (8 child boxes) and per triangle test
+# what the traversal's loads request: 14 float4 of a node (its 32 pad bytes
+# are not read) and a triangle's padded 48-byte record
+NODE_FETCH, TRI_FETCH = 14 * 16, 48
 TRAFFIC_FILES = {"large": os.path.join(ROOT, "profiles", "traversal_large_traffic.md"),
                  "medium": os.path.join(ROOT, "profiles", "traversal_medium_traffic.md")}
 
@@ -146,6 +149,8 @@ def _kernel_roofline(name, kernel_id, launches, ms, rays_cl, rays_sh, nodes, tri
     alg = (rays_cl * (RAY_IN + HIT_OUT) + rays_sh * (RAY_IN + OCC_OUT) + nodes * NODE_BYTES + tris * TRI_BYTES) \
         / launches
     ops = (nodes * OPS_PER_NODE + tris * OPS_PER_TRI) / launches
+    fetched = (rays_cl * (RAY_IN + HIT_OUT) + rays_sh * (RAY_IN + OCC_OUT) + nodes * NODE_FETCH
+               + tris * TRI_FETCH) / launches
     gbs = alg / (f_ms * 1e-3) / 1e9
     gops = ops / (f_ms * 1e-3) / 1e9
     r = {"bound": "hbm", "kernel": name, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -156,6 +161,9 @@ def _kernel_roofline(name, kernel_id, launches, ms, rays_cl, rays_sh, nodes, tri
          "tris_per_ray": round(tris / max(rays_cl + rays_sh, 1), 3),
          "valu": {"achieved_Gops": round(gops, 1), "peak_Gops": VALU_PEAK_GOPS,
                   "frac": round(gops / VALU_PEAK_GOPS, 4), "ops_per_launch": round(ops)},
+         "fetched": {"bytes_per_launch": round(fetched), "GB_s": round(fetched / (f_ms * 1e-3) / 1e9, 1),
+                     "frac": round(fetched / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "model": "224 B per node visit, 48 B per triangle test, ray and hit as above"},
          "kernel_Mrays_s": round((rays_cl + rays_sh) / (ms * 1e-3) / 1e6, 1),
          "ms_per_step": round(ms / steps, 4)}
     if extra:
