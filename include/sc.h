@@ -238,7 +238,7 @@ typedef struct {
                                * finishing) with HIP events */
 #define SC_OPT_QUEUE_CAP 3    /* camera paths per wavefront chunk (1024..2^30, default 1<<27) */
 #define SC_OPT_STAGED_DEPTH 4 /* camera-path bounces traced as one launch per stage before the
-                               * remaining paths are each finished by one lane (default 4; 0 =
+                               * remaining paths are each finished by one lane (default 2; 0 =
                                * every bounce staged); any value gives the same output bit for bit */
 #define SC_OPT_CONV_BIG_TILE 5 /* U-Net 3x3 convolutions use 12-row pixel tiles when a layer has at
                                 * least this many of them (default 2048; 0 = always), 8-row tiles
@@ -252,6 +252,11 @@ typedef struct {
                                * 2 = clustering from 2^20 triangles up, radix tree below (default);
                                * both trees are collapsed to the same wide-node layout and give
                                * the same hits bit for bit */
+#define SC_OPT_TRACE_BLOCKS 9 /* blocks of 128 threads per compute unit in the persistent traversal
+                               * grids (closest hit, any hit, path finishing; 1..16, default 8: what
+                               * the chip holds at once).  Lower values leave room for work on
+                               * another stream at the cost of this context's traversal rate; any
+                               * value gives the same output bit for bit */
 
 uint32_t sc_abi_version(void);
 const char* sc_last_error(void);

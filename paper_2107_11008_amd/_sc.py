@@ -46,6 +46,7 @@ SC_OPT_CONV_BIG_TILE = 5
 SC_OPT_PHOTON_STAGED_DEPTH = 6
 SC_OPT_PHOTON_CAP = 7
 SC_OPT_BVH_BUILDER = 8
+SC_OPT_TRACE_BLOCKS = 9
 
 
 ABI_VERSION = 6   # must match SC_ABI_VERSION in include/sc.h

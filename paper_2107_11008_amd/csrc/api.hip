@@ -131,6 +131,10 @@ sc_status sc_set_option(sc_ctx* ctx, int32_t option, int64_t value) {
             if (value < 1024 || value > (int64_t)1 << 28) return set_error(SC_EINVAL, "photon cap out of range");
             ctx->c.photon_cap = (uint64_t)value;
             return SC_OK;
+        case SC_OPT_TRACE_BLOCKS:
+            if (value < 1 || value > 16) return set_error(SC_EINVAL, "trace blocks per CU must be 1..16");
+            ctx->c.trace_blocks = (uint32_t)value;
+            return SC_OK;
         case SC_OPT_BVH_BUILDER:
             if (value < 0 || value > 2) return set_error(SC_EINVAL, "BVH builder must be 0, 1 or 2");
             ctx->c.bvh_builder = (uint32_t)value;

@@ -89,13 +89,18 @@ struct Ctx {
     // per chunk gave 257.6 / 218.5 / 205.5 / 196.8 / 190.6 ms per step)
     uint64_t queue_cap = 1ull << 27;
     uint32_t cus = 256;          // compute units of the device (sizes persistent grids)
-    uint32_t staged_depth = 4;   // camera bounces run as separate launches before paths are finished per lane
+    // camera bounces run as separate launches before the paths are finished
+    // per lane (large scene, 1 / 2 / 3 / 4 staged bounces: 1080p 64-spp step
+    // 148.1 / 151.1 / 153.6 ms at 2 / 3 / 4; plain 64-spp frame 118.6 /
+    // 113.1 / 115.2 / 118.2 ms; medium step 10.8 / 11.0 / 11.3 ms at 2 / 3 / 4)
+    uint32_t staged_depth = 2;
     uint32_t photon_staged_depth = 1;   // the same for photon paths
     uint64_t conv_big_tile = 2048;   // 16-row U-Net convolution tiles needed before they are used
     // photons per photon-pass chunk (2^24 photons of the large scene in one
     // chunk: 34.8 / 29.8 / 27.5 ms per pass at 2^22 / 2^23 / 2^24; ~1.5 GB)
     uint64_t photon_cap = 1ull << 24;
     uint32_t bvh_builder = 2;   // 0: radix tree over Morton codes, 1: locally-ordered clustering, 2: by size
+    uint32_t trace_blocks = 8;  // blocks of 128 threads per CU in the persistent traversal grids
     DevBuf counters;   // DevCounters
     DevBuf work;       // per-launch work counters of the traversal kernels
     uint32_t work_slot = 0;

@@ -1041,8 +1041,9 @@ uint32_t trace_grid(const Ctx* c, size_t n_max) {
     // have exited start their batch late and lengthen the tail: a grid the
     // chip holds at once wins.  Measured on the medium scene, 4 / 6 / 8 / 10
     // / 16 blocks per CU: 13.2 / 11.6 / 11.3 / 12.0 / 12.3 ms per step.
+    // (SC_OPT_TRACE_BLOCKS lowers it to leave room for another stream's work)
     const size_t want = (n_max + kTraceBS - 1) / kTraceBS;
-    const size_t cap = (size_t)c->cus * 8;
+    const size_t cap = (size_t)c->cus * c->trace_blocks;
     return (uint32_t)(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
@@ -1415,7 +1416,19 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
             clean_after = cells;
         }
         c->acc_clean = 0;
-        if (sparse) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, c->touched.as<uint32_t>(), 1u);
+        if (sparse) {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, c->touched.as<uint32_t>(), 1u);
+            // the float map is zero except at the cells the pass touches
+            // (converted at the end); filled here, before the tracing, so the
+            // fill does not queue behind another stream's persistent kernels
+            // while they hold every compute unit (a 1080p frame's 268 MB fill
+            // waited 3.4 ms behind its render's camera finishing)
+            if (((uintptr_t)map & 15u) == 0)
+                hipLaunchKernelGGL(k_zero_f32x4, dim3(grid_for(cells / 4, bs)), dim3(bs), 0, st,
+                                   reinterpret_cast<float4*>(map), cells / 4);
+            if (((uintptr_t)map & 15u) != 0 || cells % 4 != 0)
+                hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(cells, bs)), dim3(bs), 0, st, map, cells);
+        }
     }
     if (count_map && cells)
         hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(cells, bs)), dim3(bs), 0, st, count_map, (uint32_t)cells);
@@ -1494,11 +1507,6 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
                            c->acc64.as<unsigned long long>(), cells, 1.0 / scale, map);
         clean_after = 0;
     } else if (cells) {
-        if (((uintptr_t)map & 15u) == 0)
-            hipLaunchKernelGGL(k_zero_f32x4, dim3(grid_for(cells / 4, bs)), dim3(bs), 0, st,
-                               reinterpret_cast<float4*>(map), cells / 4);
-        if (((uintptr_t)map & 15u) != 0 || cells % 4 != 0)
-            hipLaunchKernelGGL(k_zero_f32, dim3(grid_for(cells, bs)), dim3(bs), 0, st, map, cells);
         hipLaunchKernelGGL(k_map_finalize, dim3(grid_for(std::min<size_t>(cells, N), bs)), dim3(bs), 0, st,
                            c->touched.as<uint32_t>(), c->acc64.as<unsigned long long>(), 1.0 / scale, map);
     }

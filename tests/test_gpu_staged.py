@@ -34,7 +34,7 @@ def _run(ctx, cfg, staged, spp):
         return ({k: v.cpu().numpy().copy() for k, v in img.items()}, ph["map"].cpu().numpy().copy(),
                 ph["count"].cpu().numpy().copy(), ph["stats"])
     finally:
-        ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, 4)      # the library's defaults
+        ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, 2)      # the library's defaults
         ctx.set_option(sc._sc.SC_OPT_PHOTON_STAGED_DEPTH, 1)
 
 
@@ -101,3 +101,26 @@ def test_finishing_counters(ctx):
     ctx.reset_counters()
     k = ctx.counters()
     assert k["finish_launches"] == 0 and k["finish_rays"] == 0 and k["finish_ms"] == 0.0
+
+
+def test_trace_blocks_do_not_change_outputs(ctx):
+    """Fewer blocks per CU in the persistent traversal grids (room for
+    another stream's work) give the same images, maps and photon counts bit
+    for bit."""
+    import paper_2107_11008_amd as sc
+    cfg = sg.config2(tri_scale=0.05, w=64, h=64)
+    base = _run(ctx, cfg, (2, 1), 4)
+    try:
+        for tb in (3, 5, 16):
+            ctx.set_option(sc._sc.SC_OPT_TRACE_BLOCKS, tb)
+            other = _run(ctx, cfg, (2, 1), 4)
+            for k in base[0]:
+                assert base[0][k].tobytes() == other[0][k].tobytes(), (tb, k)
+            assert base[1].tobytes() == other[1].tobytes(), tb
+            assert np.array_equal(base[2], other[2]), tb
+    finally:
+        ctx.set_option(sc._sc.SC_OPT_TRACE_BLOCKS, 8)
+    with pytest.raises(sc.ScError):
+        ctx.set_option(sc._sc.SC_OPT_TRACE_BLOCKS, 0)
+    with pytest.raises(sc.ScError):
+        ctx.set_option(sc._sc.SC_OPT_TRACE_BLOCKS, 17)
