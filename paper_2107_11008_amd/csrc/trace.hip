@@ -96,24 +96,26 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // ------------------------------------------------------------------ ray feed
-constexpr uint32_t kRefill = 16;   // idle lanes that trigger a refill
+constexpr uint32_t kRefill = 16;   // idle lanes that trigger a refill (traversal kernels)
+constexpr uint32_t kRefillPath = 8;   // ... (path finishing kernels, whose paths take longer)
 constexpr uint32_t kEventBatch = 32;   // pending photon events that are run together
 
 // Persistent lanes: each wave owns a batch of rays [next, end) of the
 // launch's list (the first batch by the wave's index in the grid, the rest
 // from the launch's atomic counter, so small launches cost no atomics); a
 // lane whose ray is finished takes the next ray of the batch once at least
-// kRefill lanes of the wave are idle while the others go on, so a wave does
-// not idle behind its slowest ray.  Batches are 64 to 256 rays, smaller for
+// `refill` lanes of the wave are idle while the others go on, so a wave
+// does not idle behind its slowest ray.  Batches are 64 to 256 rays, smaller for
 // small launches so that the rays spread over the whole grid.  All members
 // are wave-uniform.
 struct RayFeed {
-    uint32_t n, waves, batch, next, end;
+    uint32_t n, waves, batch, next, end, refill;
     uint32_t* counter;
     bool drained;
 
-    __device__ __forceinline__ void init(uint32_t n_rays, uint32_t* work) {
+    __device__ __forceinline__ void init(uint32_t n_rays, uint32_t* work, uint32_t refill_lanes = kRefill) {
         n = n_rays;
+        refill = refill_lanes;
         waves = gridDim.x * (blockDim.x >> 6);
         const uint32_t per_wave = n / (4u * waves);
         batch = per_wave >= 256u ? 256u : (per_wave >= 128u ? 128u : 64u);
@@ -128,7 +130,7 @@ struct RayFeed {
     __device__ __forceinline__ uint32_t take(bool idle_lane) {
         const unsigned long long idle = __ballot(idle_lane);
         const uint32_t n_idle = (uint32_t)__popcll(idle);
-        if (n_idle < kRefill) return 0xffffffffu;
+        if (n_idle < refill) return 0xffffffffu;
         if (next >= end && !drained) {
             uint32_t base = 0;
             if (lane_id() == 0) base = atomicAdd(counter, batch);
@@ -689,7 +691,7 @@ __global__ __launch_bounds__(kTraceBS) __attribute__((amdgpu_waves_per_eu(4, 4))
     VisitCount vc;
     const uint32_t n = *count;
     RayFeed feed;
-    feed.init(n, work);
+    feed.init(n, work, kRefillPath);
     uint32_t n_cl = 0, n_sh = 0;
     CamPath c;
     Trav t;
@@ -781,7 +783,7 @@ __global__ __launch_bounds__(kTraceBS) void k_finish_camera_pm(DevScene S, CamIn
     VisitCount vc;
     const uint32_t n = *count;
     RayFeed feed;
-    feed.init(n, work);
+    feed.init(n, work, kRefillPath);
     uint32_t n_cl = 0, n_sh = 0;
     CamPath c;
     uint32_t pid = 0, pix = 0, sample = 0, slot = 0, depth = 0;
