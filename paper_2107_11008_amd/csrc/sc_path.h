@@ -101,10 +101,16 @@ __device__ __forceinline__ void fetch14(const float4* __restrict__ base, uint32_
     for (int j = 0; j < 14; ++j) asm volatile("" ::"v"(f.q[j].x), "v"(f.q[j].y), "v"(f.q[j].z), "v"(f.q[j].w));
 }
 
-// Box tests of the 8 children of a fetched node against (o, inv).  key =
-// entry distance bits, or 0xffffffff when the child is missed or lies
-// beyond tlim.
-__device__ __forceinline__ void test_node(const Fetch& f, F3 o, F3 inv, float tlim, NodeTest& r) {
+// Box tests of the 8 children of a fetched node.  A plane p is crossed at
+// t = p * inv + c with c = -o * inv (one fused multiply-add per plane).
+// Against t = (p - o) * inv its absolute error is at most 2^-23 |c| plus a
+// relative 2^-24, so the near offsets are lowered and the far offsets
+// raised by 2^-21 |c| per axis: every box the two-operation form admits is
+// admitted (the relative margin on the far distance covers the rest, as it
+// covers the rounding of the triangle test), and the hits do not change.
+// key = entry distance bits, or 0xffffffff when the child is missed or
+// lies beyond tlim.
+__device__ __forceinline__ void test_node(const Fetch& f, F3 c, F3 inv, float tlim, NodeTest& r) {
     const float4* q = f.q;
     const float nx[8] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w};
     const float fx[8] = {q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
@@ -115,16 +121,19 @@ __device__ __forceinline__ void test_node(const Fetch& f, F3 o, F3 inv, float tl
     const uint32_t ch[8] = {__float_as_uint(q[12].x), __float_as_uint(q[12].y), __float_as_uint(q[12].z),
                             __float_as_uint(q[12].w), __float_as_uint(q[13].x), __float_as_uint(q[13].y),
                             __float_as_uint(q[13].z), __float_as_uint(q[13].w)};
+    const float mx = fabsf(c.x) * 4.76837158203125e-07f, my = fabsf(c.y) * 4.76837158203125e-07f,
+                mz = fabsf(c.z) * 4.76837158203125e-07f;   // 2^-21 |c|
+    const F3 cn{c.x - mx, c.y - my, c.z - mz}, cf{c.x + mx, c.y + my, c.z + mz};
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const float tnx = (nx[c] - o.x) * inv.x, tfx = (fx[c] - o.x) * inv.x;
-        const float tny = (ny[c] - o.y) * inv.y, tfy = (fy[c] - o.y) * inv.y;
-        const float tnz = (nz[c] - o.z) * inv.z, tfz = (fz[c] - o.z) * inv.z;
+    for (int k = 0; k < 8; ++k) {
+        const float tnx = fmaf(nx[k], inv.x, cn.x), tfx = fmaf(fx[k], inv.x, cf.x);
+        const float tny = fmaf(ny[k], inv.y, cn.y), tfy = fmaf(fy[k], inv.y, cf.y);
+        const float tnz = fmaf(nz[k], inv.z, cn.z), tfz = fmaf(fz[k], inv.z, cf.z);
         const float tn = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
         const float tf = fminf(fminf(tfx, tfy), tfz);
-        const bool hit = (tn <= tf + fabsf(tf) * 9.765625e-04f) && (tn <= tlim);
-        r.key[c] = hit ? __float_as_uint(tn) : 0xffffffffu;
-        r.ref[c] = ch[c];
+        const bool hit = (tn <= fmaf(fabsf(tf), 9.765625e-04f, tf)) && (tn <= tlim);
+        r.key[k] = hit ? __float_as_uint(tn) : 0xffffffffu;
+        r.ref[k] = ch[k];
     }
 }
 
@@ -152,7 +161,7 @@ enum TravMode { kClosest = 0, kAny = 1, kEither = 2 };
 
 struct Trav {
     RayPre rp;
-    F3 o, inv;
+    F3 c, inv;         // a plane p is crossed at p * inv + c (see test_node)
     float tb;          // closest: best t so far; any: tmax
     float bV, bW, brcp;
     uint32_t pb;       // closest: best triangle; any: the excluded triangle
@@ -179,8 +188,8 @@ __device__ __forceinline__ const float4* step_base(const DevScene& S, uint32_t r
 
 __device__ __forceinline__ void trav_begin(Trav& t, F3 o, F3 d, bool any, float tmax, uint32_t excl) {
     t.rp = ray_prepare(o, d);
-    t.o = o;
     t.inv = F3{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
+    t.c = F3{-(o.x * t.inv.x), -(o.y * t.inv.y), -(o.z * t.inv.z)};
     t.flip = axis_flips(t.inv);
     t.tb = any ? tmax : INFINITY;
     t.pb = any ? excl : 0xffffffffu;
@@ -237,7 +246,7 @@ __device__ __forceinline__ bool tstep(const DevScene& S, Trav& t, uint2 (*lds)[B
     }
     if (!(t.ref & SC_LEAF_BIT)) {
         NodeTest nt;
-        test_node(f, t.o, t.inv, search_limit(t.tb), nt);
+        test_node(f, t.c, t.inv, search_limit(t.tb), nt);
         if (COUNT) ++vc.nodes;
         if (MODE == kAny) {
             // order does not matter for a yes/no answer
