@@ -201,10 +201,11 @@ __global__ __launch_bounds__(kTraceBS) void k_closest(DevScene S, RaySoA R, HitS
 }
 
 // ------------------------------------------------------------------ any hit
-// Shadow / occlusion rays.  These end at their first hit, so a wave's rays
-// take similar times and plain chunks of 64 suffice: the first chunk by the
-// wave's index in the grid, the rest from the launch's atomic counter.  For
-// shadow rays of camera paths, an unoccluded segment adds its stored
+// Shadow / occlusion rays, with the persistent lanes of k_closest: a lane
+// whose ray has ended takes the next one from the wave's batch, so a wave
+// does not wait for its longest ray (shadow rays to the lights cross the
+// whole scene when unoccluded and end at once when blocked).  For shadow
+// rays of camera paths, an unoccluded segment adds its stored
 // contribution to L.
 template <bool COUNT>
 __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, const uint32_t* __restrict__ queue,
@@ -212,24 +213,35 @@ __global__ __launch_bounds__(kTraceBS) void k_anyhit(DevScene S, ShadowSoA R, co
                                                      uint32_t* __restrict__ work, uint8_t* __restrict__ occ_out,
                                                      float* __restrict__ L, DevCounters* __restrict__ C) {
     __shared__ uint2 lds[kLdsStack][kTraceBS];
+    __shared__ float4 top[kTopNodes * 16];   // as in k_closest
+    const bool use_top = S.n_nodes >= kTopMinNodes;
+    if (use_top) {
+        const float4* g = reinterpret_cast<const float4*>(S.nodes);
+        for (uint32_t i = threadIdx.x; i < kTopNodes * 16; i += blockDim.x) top[i] = g[i];
+        __syncthreads();
+    }
     Spill st;
     VisitCount vc;
     const uint32_t n = count ? *count : n_static;
-    uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
-    while (base < n) {
-        const uint32_t i = base + lane_id();
-        if (i < n) {
-            const uint32_t pid = queue ? queue[i] : i;
-            const F3 o{R.ox[pid], R.oy[pid], R.oz[pid]};
-            const F3 d{R.dx[pid], R.dy[pid], R.dz[pid]};
-            const uint32_t excl = R.excl ? R.excl[pid] : 0xffffffffu;
-            const bool occluded = trace_any<kTraceBS, COUNT>(S, o, d, R.tmax[pid], excl, lds, st, vc);
-            if (occ_out) occ_out[pid] = occluded ? 1 : 0;
-            if (L && !occluded) L[pid] = L[pid] + R.contrib[pid];
+    RayFeed feed;
+    feed.init(n, work);
+    Trav t;
+    uint32_t pid = 0;
+    bool active = false;
+    for (;;) {
+        const uint32_t i = feed.take(!active);
+        if (i != 0xffffffffu) {
+            pid = queue ? queue[i] : i;
+            any_init(t, F3{R.ox[pid], R.oy[pid], R.oz[pid]}, F3{R.dx[pid], R.dy[pid], R.dz[pid]}, R.tmax[pid],
+                     R.excl ? R.excl[pid] : 0xffffffffu);
+            active = true;
         }
-        uint32_t next = 0;
-        if (lane_id() == 0) next = atomicAdd(work, 64u);
-        base = __shfl(next, 0) + gridDim.x * blockDim.x;
+        if (__ballot(active) == 0ull) break;
+        if (active && tstep<kTraceBS, COUNT, kAny>(S, t, lds, st, vc, use_top ? top : nullptr)) {
+            if (occ_out) occ_out[pid] = t.hit ? 1 : 0;
+            if (L && !t.hit) L[pid] = L[pid] + R.contrib[pid];
+            active = false;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && n) {
         atomicAdd(&C->rays_shadow, (unsigned long long)n);
