@@ -274,8 +274,18 @@ def scene_step(ctx, cfg, steps, warmup, workload):
 
 
 # frame schedules of the frames/s protocol: (name, render contexts, blocks per CU of their traversal grids)
-DEN_SCHEDULES = (("one", 1, 8), ("two", 2, 8), ("two_5", 2, 5))
-PLAIN_SCHEDULES = (("one", 1, 8), ("two", 2, 8))
+def progress(msg):
+    """One progress line on stderr (the JSON result stays the only line on
+    stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# (name, render contexts, persistent blocks per CU of the render contexts,
+#  stream of the U-Net: "side" after the next frame's photons and ground
+#  truth, or "render" right after its frame's render on that render stream)
+DEN_SCHEDULES = (("one", 1, 8, "side"), ("two", 2, 8, "side"), ("two_5", 2, 5, "side"),
+                 ("two_r", 2, 8, "render"), ("two_r5", 2, 5, "render"), ("three_r", 3, 8, "render"))
+PLAIN_SCHEDULES = (("one", 1, 8, "side"), ("two", 2, 8, "side"))
 
 
 def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
@@ -299,8 +309,10 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
     overlap the previous frame's finishing tail ("two"); and, for denoised
     frames, the same with the render contexts' persistent traversal grids
     at 5 instead of 8 blocks per CU, leaving room for the side stream's
-    photon pass, ground truth and U-Net ("two_5").  `schedules` counts the
-    scenes each schedule won.
+    photon pass, ground truth and U-Net ("two_5"); and both of these with
+    each frame's U-Net on its render stream right after the render, so the
+    next frame's photon pass does not queue behind it on the side stream
+    ("two_r", "two_r5").  `schedules` counts the scenes each schedule won.
     Plain: photon pass + render; for each photon count in {2^16, 2^18,
     2^20, 2^22, 2^24} the smallest power-of-two spp from 4 whose mean
     relMSE meets the bar, then the cheapest of those.  Denoised: photon
@@ -308,8 +320,10 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
     the 4-spp input at the smallest photon count in {2^16, 2^18, 2^20}
     that meets the bar is the headline, the cheapest input over spp in
     {1, 2, 4} is reported beside it.  Frame times are means over the scenes
-    (HIP-synchronised wall clock over the timed frames, after one frame
-    that fills the pipeline)."""
+    (the steady-state frame period: after one frame that fills the
+    pipeline, the time between the first and the last completion of the
+    timed frames, from HIP events, over their number; fill and drain are
+    not counted, for plain and denoised frames alike)."""
     import torch
 
     import paper_2107_11008_amd as sc
@@ -321,11 +335,18 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
     main = torch.cuda.current_stream()
     side = torch.cuda.Stream()
     main2 = torch.cuda.Stream()
+    main3 = torch.cuda.Stream()
+    done = torch.cuda.Stream()   # frame completions, in frame order (timing only)
     with torch.cuda.stream(side):
         ctx_gt = sc.Context(0)
         net = sc.UNet(ctx_gt, tuple(meta["widths"]), params)
+    net_main = sc.UNet(ctx, tuple(meta["widths"]), params)   # U-Nets on the render streams
     with torch.cuda.stream(main2):
         ctx2 = sc.Context(0)   # a second render context for the two-render schedule
+        net_main2 = sc.UNet(ctx2, tuple(meta["widths"]), params)
+    with torch.cuda.stream(main3):
+        ctx3 = sc.Context(0)   # a third, for the three-render schedule
+        net_main3 = sc.UNet(ctx3, tuple(meta["widths"]), params)
     aov = ("albedo", "normal", "depthn", "trans")
 
     class Pipeline:
@@ -334,15 +355,23 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
         truth) and frame k's U-Net; buffers alternate between even and odd
         frames.  renders = 1: every render on the main stream; renders = 2:
         even and odd frames render on two contexts and streams, so one
-        frame's first bounces overlap the previous frame's finishing tail."""
+        frame's first bounces overlap the previous frame's finishing tail;
+        renders = 3: the same over three.  Buffers: one set per frame in
+        flight (max(2, renders)).  unet_on = "render": frame k's U-Net runs
+        on frame k's render stream once its ground truth is there.  Each
+        frame ends with a timing event on the completion stream, which waits
+        for the frames in order, so completion times never go backwards."""
 
-        def __init__(self, bvh, cam, wl, md, spp, photons, den, renders=1, blocks=8):
+        def __init__(self, bvh, cam, wl, md, spp, photons, den, renders=1, blocks=8, unet_on="side"):
             self.a = (bvh, cam, wl, md, spp, photons)
             self.den = den
+            self.unet_on = unet_on
             self.k = 0
             self.b = {}
-            self.rs = [(ctx, main), (ctx2, main2)][:renders]
-            for rctx, _ in self.rs:   # persistent traversal grids of the render contexts
+            self.rs = [(ctx, main, net_main), (ctx2, main2, net_main2), (ctx3, main3, net_main3)][:renders]
+            self.nb = max(2, renders)
+            self.rec = None
+            for rctx, _, _ in self.rs:   # persistent traversal grids of the render contexts
                 rctx.set_option(sc._sc.SC_OPT_TRACE_BLOCKS, blocks)
 
         def _side_work(self, f):
@@ -354,17 +383,21 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
             b[f"map_ev{f}"] = ev
             if self.den:
                 b[f"g{f}"] = ctx_gt.render(bvh, cam, 1, md, wl, 12, outputs=aov, out=b.get(f"g{f}"))
+                ev = torch.cuda.Event()
+                ev.record(side)
+                b[f"gt_ev{f}"] = ev
 
         def frame(self):
             bvh, cam, wl, md, spp, photons = self.a
             b = self.b
-            i, j = self.k % 2, (self.k + 1) % 2
-            rctx, rst = self.rs[self.k % len(self.rs)]
+            i, j = self.k % self.nb, (self.k + 1) % self.nb
+            rctx, rst, rnet = self.rs[self.k % len(self.rs)]
             if self.k == 0:
                 e0 = torch.cuda.Event()
                 e0.record(main)
                 side.wait_event(e0)
                 main2.wait_event(e0)
+                main3.wait_event(e0)
                 self._side_work(i)
             self._side_work(j)                      # frame k+1's photons (+ ground truth)
             rst.wait_event(b[f"map_ev{i}"])         # frame k's map
@@ -373,25 +406,42 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
             with torch.cuda.stream(rst):
                 b[f"r{i}"] = rctx.render(bvh, cam, spp, md, wl, 12, caustic_map=b[f"m{i}"], outputs=("rgb",),
                                          out=b.get(f"r{i}"))
-            e_r = torch.cuda.Event()
-            e_r.record(rst)
-            side.wait_event(e_r)                    # frame k's render is read (U-Net) or its map freed
             self.k += 1
-            if self.den:
-                b["den"] = net.denoise(dict(b[f"g{i}"], rgb=b[f"r{i}"]["rgb"]), out=b.get("den"))
-            ev = torch.cuda.Event()
-            ev.record(side)
+            if self.den and self.unet_on == "render":
+                rst.wait_event(b[f"gt_ev{i}"])      # frame k's ground truth
+                with torch.cuda.stream(rst):
+                    b[f"den{i}"] = rnet.denoise(dict(b[f"g{i}"], rgb=b[f"r{i}"]["rgb"]), out=b.get(f"den{i}"))
+                ev = torch.cuda.Event()
+                ev.record(rst)
+                side.wait_event(ev)                 # frame k's map and ground truth are free after this
+                out_ev = ev
+            else:
+                e_r = torch.cuda.Event()
+                e_r.record(rst)
+                side.wait_event(e_r)                # frame k's render is read (U-Net) or its map freed
+                if self.den:
+                    b[f"den{i}"] = net.denoise(dict(b[f"g{i}"], rgb=b[f"r{i}"]["rgb"]), out=b.get(f"den{i}"))
+                ev = torch.cuda.Event()
+                ev.record(side)
+                out_ev = ev if self.den else e_r    # the frame's image is complete
             b[f"done_ev{i}"] = ev
-            return b["den"] if self.den else b[f"r{i}"]["rgb"]
+            done.wait_event(out_ev)
+            self.rec = torch.cuda.Event(enable_timing=True)
+            self.rec.record(done)
+            return b[f"den{i}"] if self.den else b[f"r{i}"]["rgb"]
 
-    def timed(fn, reps):
-        fn()
+    def timed(p, reps):
+        """Steady-state frame period of pipeline p: one frame fills the
+        pipeline, then reps + 1 frames; the period is the time between the
+        first and the last of their completions over reps (no fill or drain
+        counted)."""
+        p.frame()
+        recs = []
+        for _ in range(reps + 1):
+            img = p.frame()
+            recs.append(p.rec)
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            img = fn()
-        torch.cuda.synchronize()
-        return img, (time.perf_counter() - t) / reps
+        return img, recs[0].elapsed_time(recs[-1]) / 1e3 / reps
 
     den_inputs = [(spp, ph) for ph in (1 << 16, 1 << 18, 1 << 20) for spp in (1, 2, 4)]
     plain_photons = (1 << 16, 1 << 18, 1 << 20, 1 << 22, 1 << 24)
@@ -413,8 +463,8 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
         # the fastest (the images are the same under every schedule)
         for spp, ph in den_inputs:
             img, best = None, None
-            for name, renders, blocks in DEN_SCHEDULES:
-                im, t = timed(Pipeline(bvh, cam, wl, md, spp, ph, True, renders, blocks).frame, 4)
+            for name, renders, blocks, unet_on in DEN_SCHEDULES:
+                im, t = timed(Pipeline(bvh, cam, wl, md, spp, ph, True, renders, blocks, unet_on), 6)
                 img = im if img is None else img
                 if best is None or t < best[1]:
                     best = (name, t)
@@ -425,8 +475,8 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
             for spp in plain_spp:
                 reps = 2 if spp <= 16 else 1
                 img, best = None, None
-                for name, renders, blocks in PLAIN_SCHEDULES:
-                    im, t = timed(Pipeline(bvh, cam, wl, md, spp, ph, False, renders, blocks).frame,
+                for name, renders, blocks, unet_on in PLAIN_SCHEDULES:
+                    im, t = timed(Pipeline(bvh, cam, wl, md, spp, ph, False, renders, blocks, unet_on),
                                   max(reps, renders))
                     img = im if img is None else img
                     if best is None or t < best[1]:
@@ -435,6 +485,7 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
                 row["plain_ms"][(spp, ph)] = best[1] * 1e3
                 row["plain_sched"][(spp, ph)] = best[0]
         scenes.append(row)
+        progress(f"denoise protocol: held-out scene {j + 1}/{n_scenes} done")
         del bvh, ref
         torch.cuda.empty_cache()
 
@@ -493,8 +544,12 @@ def denoise_heldout(ctx, n_scenes=8, spp_ref=1024):
         res["fps_ratio_cheapest_input"] = round(pbest["ms"] / dbest["ms"], 2)
     ctx.set_option(sc._sc.SC_OPT_TRACE_BLOCKS, 8)   # the library's default, for the workloads after this one
     net.close()
+    net_main.close()
+    net_main2.close()
+    net_main3.close()
     ctx_gt.close()
     ctx2.close()
+    ctx3.close()
     return res
 
 
@@ -833,6 +888,7 @@ def main():
         "paper": "no published renderer numbers (the paper renders with a game engine's hardware ray tracing on "
                  "2x GTX 1080 Ti and quotes no frame rates)",
     }
+    progress(f"headline workload done: {line['ms_per_step']} ms per step")
     if not args.no_medium and args.workload == "large":
         c2 = sg.config2()
         med = scene_step(ctx, c2, max(args.steps, 20), args.warmup, "medium")
@@ -844,18 +900,22 @@ def main():
             "roofline_other_traversal_kernels": med["rooflines"][1:]}
     if not args.no_glass_variants:
         line["glass_variants"] = glass_variants(ctx)
+        progress("glass variants done")
     if not args.no_pmap:
         line["general_photon_map"] = general_photon_map(ctx)
+        progress("general photon map done")
     if not args.no_unet:
         line["unet_1080p"] = unet_1080p(ctx)
     if not args.no_train:
         line["unet_train_step"] = unet_train_step(ctx)
     if not args.no_gt:
         line["ground_truth_1080p"] = ground_truth_1080p(ctx)
+    progress("U-Net and ground-truth kernels done")
     if not args.no_denoise:
         line["denoise_1080p"] = denoise_heldout(ctx)
     if not args.no_batch:
         line["batch_64"] = batch_compare(ctx)
+        progress("64-scene batch done")
     if not args.no_cpu_baseline:
         if args.workload == "large":
             line["cpu_baseline"] = cpu_baseline(cfg, big["rays_per_step"], secs / args.steps)
