@@ -112,6 +112,48 @@ def test_any_hit_exact(ctx):
     assert np.array_equal(occ, ref)
 
 
+@pytest.mark.parametrize("offset", [(0.0, 0.0, 0.0), (3000.0, -2000.0, 500.0), (-40000.0, 25000.0, 0.0)])
+def test_hits_far_from_the_origin(ctx, offset):
+    """A triangle soup placed far from the world origin, rays starting on
+    its triangles (as secondary rays do) or within a millimetre of them.
+    The box test crosses a plane at p * inv + c with c = -o * inv, whose
+    rounding grows with |o| while the distances stay small; its per-ray
+    margins must keep every box that holds a hit, so closest hits
+    (triangle, t, barycentrics) and occlusion equal the oracle's bit for
+    bit.  The oracle's own traversal shares none of that arithmetic."""
+    rng = np.random.default_rng(17)
+    off = np.array(offset)
+    b = sg.SceneBuilder()
+    C = rng.uniform(-1, 1, size=(300, 3))
+    V = np.repeat(C, 3, axis=0) + rng.normal(scale=0.05, size=(900, 3)) + off
+    b.add(sg.Mesh(V, np.arange(900).reshape(300, 3), np.tile([0, 0, 1.0], (900, 1))),
+          dict(type=sg.MAT_DIFFUSE, rho_a=0.5))
+    scene = b.build(None)
+    V = scene.V.astype(np.float64)
+    I = scene.I
+    k = rng.integers(0, len(I), size=3000)
+    w = rng.dirichlet([1.0, 1.0, 1.0], size=3000)
+    P = w[:, :1] * V[I[k, 0]] + w[:, 1:2] * V[I[k, 1]] + w[:, 2:] * V[I[k, 2]]
+    O = np.concatenate([P, P + rng.normal(scale=1e-3, size=P.shape)]).astype(np.float32)
+    D = rng.normal(size=O.shape)
+    D = (D / np.linalg.norm(D, axis=1, keepdims=True)).astype(np.float32)
+    osc = oracle.OracleScene(scene)
+    to, po, uo, vo = oracle.closest(osc, O, D)
+    bvh = ctx.build_bvh(scene)
+    t, p, u, v = [x.cpu().numpy() for x in ctx.trace_rays(bvh, _t(O), _t(D))]
+    assert np.array_equal(p.view(np.uint32), po)
+    assert np.array_equal(_bits(t), _bits(to))
+    assert np.array_equal(_bits(u), _bits(uo))
+    assert np.array_equal(_bits(v), _bits(vo))
+    hit = po != 0xFFFFFFFF
+    assert hit.sum() > len(O) // 4   # most rays meet another triangle
+    tmax = rng.uniform(0.01, 2.0, size=len(O)).astype(np.float32)
+    excl = np.where(rng.uniform(size=len(O)) < 0.5, po, 0xFFFFFFFF).astype(np.uint32)
+    ref = oracle.any_hit(osc, O, D, tmax, excl)
+    occ = ctx.occluded(bvh, _t(O), _t(D), _t(tmax), _t(excl.view(np.int32))).cpu().numpy().astype(bool)
+    assert np.array_equal(occ, ref)
+
+
 def _oracle_aov(scene, cam, wl, spp=1, depth=1, seed=1, cmap=None, pixels=None):
     return oracle.render(oracle.OracleScene(scene), cam, spp, depth, wl, seed, caustic_map=cmap, pixels=pixels,
                          want_tie=True)
