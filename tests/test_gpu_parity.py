@@ -284,6 +284,32 @@ def test_determinism(ctx):
     assert np.array_equal(_bits(g1["rgb"].cpu().numpy()), _bits(g2["rgb"].cpu().numpy()))
 
 
+def test_empty_inputs(ctx):
+    """Zero rays through each ray entry point return at once with nothing
+    written; a pass of zero photons leaves an all-zero map and counts; a
+    render of zero samples per pixel is refused (documented EINVAL)."""
+    import paper_2107_11008_amd as sc
+    c = sg.config1()
+    scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
+    bvh = ctx.build_bvh(scene)
+    O = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    D = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    t, p, u, v = ctx.trace_rays(bvh, O, D)
+    assert t.numel() == 0 and p.numel() == 0 and u.numel() == 0 and v.numel() == 0
+    occ = ctx.occluded(bvh, O, D, torch.empty(0, dtype=torch.float32, device="cuda"))
+    assert occ.numel() == 0
+    t0 = torch.full((4,), 7.0, dtype=torch.float32, device="cuda")
+    p0 = torch.full((4,), 5, dtype=torch.int32, device="cuda")
+    ctx.trace_rays_noalloc(bvh, O, D, t0, p0)
+    assert torch.all(t0 == 7.0) and torch.all(p0 == 5)   # nothing written
+    m = torch.full((scene.receiver.hc, scene.receiver.wc, wl.channels), 3.0, dtype=torch.float32, device="cuda")
+    r = ctx.trace_photons(bvh, 0, c["max_depth"], wl, 1, counts=True, out=m)
+    assert torch.count_nonzero(r["map"]).item() == 0
+    assert torch.count_nonzero(r["count"]).item() == 0
+    with pytest.raises(sc.ScError):
+        ctx.render(bvh, cam, 0, c["max_depth"], wl, 1)
+
+
 def test_single_triangle_and_degenerate(ctx):
     """One triangle, plus degenerate and non-finite triangles that never hit."""
     b = sg.SceneBuilder()
