@@ -273,6 +273,23 @@ def test_radiance_c2_small_spectral(ctx, spp, cap):
     _cmp_aov(g, o)
 
 
+@pytest.mark.parametrize("w,h", [(1, 1), (37, 23), (65, 3)])
+def test_radiance_ragged_image_sizes(ctx, w, h):
+    """Images whose pixel counts fill no wave or block evenly (one pixel;
+    37 x 23; a 65-pixel-wide strip): with the oracle's caustic map on both
+    sides the image and every ground-truth buffer are bit-exact."""
+    c = sg.config2(seed=2001, tri_scale=0.03, w=w, h=h)
+    scene, wl, cam = c["scene"], c["wavelengths"], c["camera"]
+    osc = oracle.OracleScene(scene)
+    om, _, _, _ = oracle.trace_photons(osc, 1 << 14, c["max_depth"], wl, c["photon_seed"])
+    o = oracle.render(osc, cam, 2, c["max_depth"], wl, c["render_seed"], caustic_map=om)
+    bvh = ctx.build_bvh(scene)
+    g = ctx.render(bvh, cam, 2, c["max_depth"], wl, c["render_seed"], caustic_map=_t(om))
+    assert g["rgb"].shape == (h, w, 3)
+    assert np.array_equal(_bits(g["rgb"].cpu().numpy()), _bits(o["rgb"]))
+    _cmp_aov(g, o)
+
+
 def test_determinism(ctx):
     c = sg.config1()
     bvh = ctx.build_bvh(c["scene"])
