@@ -322,7 +322,10 @@ __device__ __forceinline__ HitRec load_hit(const PathState& P, uint32_t pid) {
     return HitRec{P.t[pid], P.u[pid], P.v[pid], P.prim[pid]};
 }
 
-__global__ void k_raygen(CamInfo ci, WaveDev wl, PathState P, uint32_t n, uint32_t* queue, uint32_t* counts) {
+// `extra`: further entries another kernel appends to the same queue before
+// the first closest-hit launch (the ground truth's pixel-centre rays).
+__global__ void k_raygen(CamInfo ci, WaveDev wl, PathState P, uint32_t n, uint32_t* queue, uint32_t* counts,
+                         uint32_t extra) {
     for (uint32_t pid = blockIdx.x * blockDim.x + threadIdx.x; pid < n; pid += gridDim.x * blockDim.x) {
         uint32_t pix, sample, slot;
         pid_decode(ci, pid, pix, sample, slot);
@@ -335,13 +338,15 @@ __global__ void k_raygen(CamInfo ci, WaveDev wl, PathState P, uint32_t n, uint32
         P.med[pid] = c.med;
         queue[pid] = pid;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) counts[QC_CUR] = n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) counts[QC_CUR] = n + extra;
 }
 
 // Sort hits by material: emitters and misses end here, dielectric and
-// diffuse hits go to their own queues.
+// diffuse hits go to their own queues.  Queue entries from path_end on are
+// not camera paths (the ground truth's rays traced in the same launch) and
+// are left alone.
 __global__ void k_classify(DevScene S, PathState P, const uint32_t* __restrict__ queue, uint32_t* counts,
-                           uint32_t* q_diffuse, uint32_t* q_dielectric, uint32_t cap) {
+                           uint32_t* q_diffuse, uint32_t* q_dielectric, uint32_t path_end) {
     const uint32_t n = counts[QC_CUR];
     const uint32_t per = push_items(n), span = blockDim.x * per;
     for (uint32_t base = blockIdx.x * span; base < n; base += gridDim.x * span) {
@@ -350,6 +355,7 @@ __global__ void k_classify(DevScene S, PathState P, const uint32_t* __restrict__
             const uint32_t i = base + k * blockDim.x + threadIdx.x;
             if (i >= n) break;
             const uint32_t pid = queue[i];
+            if (pid >= path_end) continue;
             const uint32_t prim = P.prim[pid];
             if (prim == 0xffffffffu) continue;
             const uint32_t type = S.mat[S.tri_obj[prim]].type;
@@ -458,13 +464,16 @@ __global__ void k_film_scale(float* rgb, uint32_t n, float inv_spp) {
 }
 
 // ------------------------------------------------------------------ ground truth
-__global__ void k_aov_raygen(sc_camera cam, RaySoA R) {
+// Pixel-centre rays of the ground truth; with `queue`, entry pix of it is
+// set to id0 + pix (the rays then join a closest-hit launch's queue).
+__global__ void k_aov_raygen(sc_camera cam, RaySoA R, uint32_t* queue, uint32_t id0) {
     const uint32_t hw = cam.w * cam.h;
     for (uint32_t pix = blockIdx.x * blockDim.x + threadIdx.x; pix < hw; pix += gridDim.x * blockDim.x) {
         F3 o, d;
         camera_ray(cam, pix % cam.w, pix / cam.w, 0.5f, 0.5f, o, d);
         R.ox[pix] = o.x; R.oy[pix] = o.y; R.oz[pix] = o.z;
         R.dx[pix] = d.x; R.dy[pix] = d.y; R.dz[pix] = d.z;
+        if (queue) queue[pix] = id0 + pix;
     }
 }
 
@@ -1332,24 +1341,32 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
     if (chunk < 1) chunk = 1;
     if (chunk > spp) chunk = spp;
     const size_t n_max = std::max(chunk * per_sample, hw);
-    if (n_max > 0xffffffffull) return set_error(SC_EUNSUPPORTED, "image too large for one wavefront chunk");
-    SC_TRY(ensure_path(c, n_max));
-    SC_TRY(ensure_queues(c, n_max));
-    PathState P = carve_path(c->path.p, n_max);
-    Queues q = carve_queues(c->queues.p, n_max);
+    const bool want_aov = out.obj || out.trans || out.tri || out.depth || out.depthn || out.normal || out.normal_cam ||
+                          out.albedo;
+    // With an image too, the ground truth's pixel-centre rays are traced in
+    // the first bounce's closest-hit launch (path slots n_max .. n_max + hw)
+    // instead of a launch of their own, whose ramp and tail cost more than
+    // its 1 ray per pixel.
+    const bool merge_aov = want_aov && out.rgb;
+    const size_t n_cap = n_max + (merge_aov ? hw : 0);
+    if (n_cap > 0xffffffffull) return set_error(SC_EUNSUPPORTED, "image too large for one wavefront chunk");
+    SC_TRY(ensure_path(c, n_cap));
+    SC_TRY(ensure_queues(c, n_cap));
+    PathState P = carve_path(c->path.p, n_cap);
+    Queues q = carve_queues(c->queues.p, n_cap);
     const uint32_t frame_words = (max_depth + 2) * QC_FRAME;
     SC_TRY(c->qcounts.ensure(4 * (size_t)frame_words));
     q.counts = c->qcounts.as<uint32_t>();
     reset_work(c);
     const uint32_t staged = c->staged_depth && c->staged_depth < max_depth ? c->staged_depth : max_depth;
 
-    const bool want_aov = out.obj || out.trans || out.tri || out.depth || out.depthn || out.normal || out.normal_cam ||
-                          out.albedo;
     const RaySoA R{P.ox, P.oy, P.oz, P.dx, P.dy, P.dz};
     const HitSoA H{P.t, P.prim, P.u, P.v};
+    const RaySoA Ra{P.ox + n_max, P.oy + n_max, P.oz + n_max, P.dx + n_max, P.dy + n_max, P.dz + n_max};
+    const HitSoA Ha{P.t + n_max, P.prim + n_max, P.u + n_max, P.v + n_max};
     const uint32_t bs = 256;
-    if (want_aov) {
-        hipLaunchKernelGGL(k_aov_raygen, dim3(grid_for(hw, bs)), dim3(bs), 0, st, cam, R);
+    if (want_aov && !merge_aov) {
+        hipLaunchKernelGGL(k_aov_raygen, dim3(grid_for(hw, bs)), dim3(bs), 0, st, cam, R, nullptr, 0u);
         launch_closest(c, S, R, H, nullptr, nullptr, (uint32_t)hw, hw);
         hipLaunchKernelGGL(k_aov_write, dim3(grid_for(hw, bs)), dim3(bs), 0, st, S, cam, R, H, out);
     }
@@ -1361,14 +1378,23 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
             const uint32_t n = (uint32_t)(ns * per_sample);
             CamInfo ci{cam, seed, s0, (uint32_t)hw, K, max_depth};
             hipLaunchKernelGGL(k_zero_u32, dim3(32), dim3(256), 0, st, q.counts, frame_words);
-            hipLaunchKernelGGL(k_raygen, dim3(grid_for(n, bs)), dim3(bs), 0, st, ci, wd, P, n, q.cur, q.counts);
+            const bool aov_here = merge_aov && s0 == 0;   // the ground truth joins the first bounce
+            const uint32_t extra = aov_here ? (uint32_t)hw : 0u;
+            hipLaunchKernelGGL(k_raygen, dim3(grid_for(n, bs)), dim3(bs), 0, st, ci, wd, P, n, q.cur, q.counts,
+                               extra);
+            if (aov_here)
+                hipLaunchKernelGGL(k_aov_raygen, dim3(grid_for(hw, bs)), dim3(bs), 0, st, cam, Ra, q.cur + n,
+                                   (uint32_t)n_max);
             uint32_t* cur = q.cur;
             uint32_t* nxt = q.next;
             for (uint32_t depth = 1; depth <= staged; ++depth) {
                 uint32_t* fc = q.counts + (size_t)(depth - 1) * QC_FRAME;
-                launch_closest(c, S, R, H, cur, fc + QC_CUR, 0u, n);
-                hipLaunchKernelGGL(k_classify, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, P, cur, fc, q.diffuse,
-                                   q.dielectric, n);
+                const uint32_t n_here = depth == 1 ? n + extra : n;
+                launch_closest(c, S, R, H, cur, fc + QC_CUR, 0u, n_here);
+                if (depth == 1 && aov_here)
+                    hipLaunchKernelGGL(k_aov_write, dim3(grid_for(hw, bs)), dim3(bs), 0, st, S, cam, Ra, Ha, out);
+                hipLaunchKernelGGL(k_classify, dim3(grid_for(n_here, bs)), dim3(bs), 0, st, S, P, cur, fc, q.diffuse,
+                                   q.dielectric, (uint32_t)n_max);
                 hipLaunchKernelGGL(k_shade_dielectric, dim3(grid_for(n, bs)), dim3(bs), 0, st, S, ci, P, depth,
                                    q.dielectric, fc, nxt);
                 // the diffuse stage is the first reader of the caustic map;
