@@ -800,7 +800,7 @@ def main():
     ap.add_argument("--no-denoise", action="store_true")
     ap.add_argument("--staged-depth", type=int, default=None,
                     help="bounces run as one launch per stage before per-lane path finishing "
-                         "(library default if omitted; 0 = all bounces staged)")
+                         "(library default if omitted; 0 = none, max depth or more = all bounces staged)")
     ap.add_argument("--photon-staged-depth", type=int, default=None,
                     help="the same for photon paths (library default if omitted)")
     ap.add_argument("--queue-cap", type=int, default=None, help="camera paths per wavefront chunk")

@@ -238,13 +238,15 @@ typedef struct {
                                * finishing) with HIP events */
 #define SC_OPT_QUEUE_CAP 3    /* camera paths per wavefront chunk (1024..2^30, default 1<<27) */
 #define SC_OPT_STAGED_DEPTH 4 /* camera-path bounces traced as one launch per stage before the
-                               * remaining paths are each finished by one lane (default 2; 0 =
-                               * every bounce staged); any value gives the same output bit for bit */
+                               * remaining paths are each finished by one lane (default 2; 0 = none,
+                               * every path finished by one lane from its camera ray; a value of
+                               * max_depth or more = every bounce staged); any value gives the same
+                               * output bit for bit */
 #define SC_OPT_CONV_BIG_TILE 5 /* U-Net 3x3 convolutions use 12-row pixel tiles when a layer has at
                                 * least this many of them (default 2048; 0 = always), 8-row tiles
                                 * otherwise; any value gives the same output bit for bit */
-#define SC_OPT_PHOTON_STAGED_DEPTH 6 /* the same switch for photon paths (default 1: after the
-                                      * first bounce every photon is finished by one lane) */
+#define SC_OPT_PHOTON_STAGED_DEPTH 6 /* the same switch for photon paths (default 0: every photon
+                                      * is finished by one lane from its emission) */
 #define SC_OPT_PHOTON_CAP 7   /* photons per photon-pass chunk (1024..2^28, default 1<<24) */
 #define SC_OPT_BVH_BUILDER 8  /* tree of later sc_build_bvh / sc_bvh_rebuild calls: 0 = binary radix
                                * tree over 36-bit Morton codes (Karras, HPG 2012), 1 = parallel

@@ -94,7 +94,7 @@ struct Ctx {
     // 148.1 / 151.1 / 153.6 ms at 2 / 3 / 4; plain 64-spp frame 118.6 /
     // 113.1 / 115.2 / 118.2 ms; medium step 10.8 / 11.0 / 11.3 ms at 2 / 3 / 4)
     uint32_t staged_depth = 2;
-    uint32_t photon_staged_depth = 1;   // the same for photon paths
+    uint32_t photon_staged_depth = 0;   // the same for photon paths (none: every photon finished per lane)
     uint64_t conv_big_tile = 2048;   // 16-row U-Net convolution tiles needed before they are used
     // photons per photon-pass chunk (2^24 photons of the large scene in one
     // chunk: 34.8 / 29.8 / 27.5 ms per pass at 2^22 / 2^23 / 2^24; ~1.5 GB)

@@ -1347,7 +1347,9 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
     // the first bounce's closest-hit launch (path slots n_max .. n_max + hw)
     // instead of a launch of their own, whose ramp and tail cost more than
     // its 1 ray per pixel.
-    const bool merge_aov = want_aov && out.rgb;
+    // bounces traced as one launch per stage (0: none, every path finished per lane)
+    const uint32_t staged = std::min(c->staged_depth, max_depth);
+    const bool merge_aov = want_aov && out.rgb && staged >= 1;
     const size_t n_cap = n_max + (merge_aov ? hw : 0);
     if (n_cap > 0xffffffffull) return set_error(SC_EUNSUPPORTED, "image too large for one wavefront chunk");
     SC_TRY(ensure_path(c, n_cap));
@@ -1358,7 +1360,6 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
     SC_TRY(c->qcounts.ensure(4 * (size_t)frame_words));
     q.counts = c->qcounts.as<uint32_t>();
     reset_work(c);
-    const uint32_t staged = c->staged_depth && c->staged_depth < max_depth ? c->staged_depth : max_depth;
 
     const RaySoA R{P.ox, P.oy, P.oz, P.dx, P.dy, P.dz};
     const HitSoA H{P.t, P.prim, P.u, P.v};
@@ -1410,6 +1411,8 @@ sc_status render(Ctx* c, Bvh* b, const sc_camera& cam, uint32_t spp, uint32_t ma
                 std::swap(cur, nxt);
             }
             if (staged < max_depth) {
+                // with no staged bounce the finishing kernel is the map's first reader
+                if (map_ready && s0 == 0 && staged == 0) SC_HIP(hipStreamWaitEvent(st, map_ready, 0));
                 auto kfin = pm.on ? (c->count_visits ? k_finish_camera_pm<true> : k_finish_camera_pm<false>)
                                   : (c->count_visits ? k_finish_camera<false, true> : k_finish_camera<false, false>);
                 uint32_t* work = next_work_slot(c);
@@ -1509,8 +1512,7 @@ sc_status trace_photons(Ctx* c, Bvh* b, uint64_t N, uint32_t max_depth, const sc
                                c->counters.as<DevCounters>());
             uint32_t* cur = q.cur;
             uint32_t* nxt = q.next;
-            const uint32_t psd = c->photon_staged_depth;
-            const uint32_t staged = psd && psd < max_depth ? psd : max_depth;
+            const uint32_t staged = std::min(c->photon_staged_depth, max_depth);   // 0: none
             for (uint32_t depth = 1; depth <= staged; ++depth) {
                 uint32_t* fc = q.counts + (size_t)(depth - 1) * QC_FRAME;
                 launch_closest(c, S, R, H, cur, fc + QC_CUR, 0u, n);

@@ -10,8 +10,10 @@ import scenegen as sg
 
 pytestmark = pytest.mark.gpu
 
-# (camera, photon) switch depths; the first is the reference
-DEPTHS = ((0, 0), (1, 1), (2, 5), (3, 2), (5, 1), (1, 3))
+# (camera, photon) switch depths, the number of staged bounces (0: none, every
+# path finished per lane; max depth or more: all staged); the first, every
+# bounce staged, is the reference
+DEPTHS = ((99, 99), (0, 0), (1, 1), (2, 5), (3, 2), (5, 1), (1, 3), (0, 2), (2, 0))
 
 
 @pytest.fixture(scope="module")
@@ -35,7 +37,7 @@ def _run(ctx, cfg, staged, spp):
                 ph["count"].cpu().numpy().copy(), ph["stats"])
     finally:
         ctx.set_option(sc._sc.SC_OPT_STAGED_DEPTH, 2)      # the library's defaults
-        ctx.set_option(sc._sc.SC_OPT_PHOTON_STAGED_DEPTH, 1)
+        ctx.set_option(sc._sc.SC_OPT_PHOTON_STAGED_DEPTH, 0)
 
 
 @pytest.mark.parametrize("which", ["c1", "c2s", "glass"])
@@ -70,13 +72,15 @@ def test_bad_staged_depth_rejected(ctx):
             ctx.set_option(opt, -1)
 
 
-def test_finishing_counters(ctx):
+@pytest.mark.parametrize("psd", [1, 0])
+def test_finishing_counters(ctx, psd):
     """The counters behind the photon finishing kernel's roofline: with
     profiling and visit counting on, one timed launch per photon pass; it
-    takes over the photons still alive after the staged bounce and traces at
-    least one segment each; every photon segment is counted once, by the
-    staged kernel or by the finishing kernel (equal to the pass's segment
-    statistic); counting does not change the map."""
+    takes over the photons still alive after the staged bounce (every
+    photon when no bounce is staged) and traces at least one segment each;
+    every photon segment is counted once, by the staged kernel or by the
+    finishing kernel (equal to the pass's segment statistic); counting does
+    not change the map."""
     import paper_2107_11008_amd as sc
     c = sg.config2(tri_scale=0.05, w=32, h=24)
     md, wl = c["max_depth"], c["wavelengths"]
@@ -86,15 +90,20 @@ def test_finishing_counters(ctx):
     ctx.reset_counters()
     ctx.set_option(sc._sc.SC_OPT_PROFILE, 1)
     ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 1)
+    ctx.set_option(sc._sc.SC_OPT_PHOTON_STAGED_DEPTH, psd)
     try:
         r = ctx.trace_photons(bvh, n, md, wl, c["photon_seed"], stats=True)
         k = ctx.counters()
     finally:
         ctx.set_option(sc._sc.SC_OPT_PROFILE, 0)
         ctx.set_option(sc._sc.SC_OPT_COUNT_VISITS, 0)
+        ctx.set_option(sc._sc.SC_OPT_PHOTON_STAGED_DEPTH, 0)
     assert r["map"].cpu().numpy().tobytes() == plain.tobytes()
     assert k["finish_launches"] == 1 and k["finish_ms"] > 0.0
-    assert 0 < k["finish_paths"] < n
+    if psd:
+        assert 0 < k["finish_paths"] < n
+    else:
+        assert k["finish_paths"] == n and k["closest_rays_timed"] == 0
     assert k["finish_rays"] >= k["finish_paths"]
     assert k["closest_rays_timed"] + k["finish_rays"] == k["rays_closest"] == r["stats"]["segments"]
     assert k["finish_node_visits"] >= k["finish_rays"] and k["finish_tri_tests"] > 0
@@ -109,11 +118,11 @@ def test_trace_blocks_do_not_change_outputs(ctx):
     for bit."""
     import paper_2107_11008_amd as sc
     cfg = sg.config2(tri_scale=0.05, w=64, h=64)
-    base = _run(ctx, cfg, (2, 1), 4)
+    base = _run(ctx, cfg, (2, 0), 4)
     try:
         for tb in (3, 5, 16):
             ctx.set_option(sc._sc.SC_OPT_TRACE_BLOCKS, tb)
-            other = _run(ctx, cfg, (2, 1), 4)
+            other = _run(ctx, cfg, (2, 0), 4)
             for k in base[0]:
                 assert base[0][k].tobytes() == other[0][k].tobytes(), (tb, k)
             assert base[1].tobytes() == other[1].tobytes(), tb
